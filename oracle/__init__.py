@@ -1,0 +1,288 @@
+"""CPU oracle for nested-CSG Monte Carlo geometry tracking.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark may import this package; the product library never does.
+It shares no code with the HIP path: ``oracle.c`` is compiled here with gcc
+(no FMA contraction) and loaded through ctypes.
+
+Functions follow the paper's tracking operations (Table 1) and algorithms
+(Alg. 2 history loop, Alg. 3/4 CSG find_cell / cross_surface, Alg. 7/8
+multi-universe descent); see the header of ``oracle.c``.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+MAXL = 8
+
+END_NONE, END_ESCAPE, END_CAP, END_LOST, END_SEGCAP = 0, 1, 2, 3, 4
+COUNTERS = ("escaped", "capped", "lost", "segcap", "rec_overflow", "segments", "rejected", "spare")
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (strict IEEE double: no FMA
+    contraction, no fast-math)."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-msse2", "-mfpmath=sse",
+           "-fPIC", "-shared", "-Wall", "-Wno-unused-function", "-o", tmp, SRC, "-lm", "-lpthread"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class _Flat(C.Structure):
+    _fields_ = [
+        ("n_surfaces", C.c_uint32), ("n_cells", C.c_uint32), ("n_universes", C.c_uint32),
+        ("n_materials", C.c_uint32), ("n_hs", C.c_uint32), ("root", C.c_uint32),
+        ("surf_type", C.c_void_p), ("surf_coef", C.c_void_p), ("cell_hs_off", C.c_void_p),
+        ("hs", C.c_void_p), ("cell_fill", C.c_void_p), ("cell_trans", C.c_void_p),
+        ("univ_cell_off", C.c_void_p), ("sigma_t", C.c_void_p),
+        ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3),
+    ]
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("seed", C.c_uint64), ("first_particle", C.c_uint64), ("n_particles", C.c_uint64),
+        ("geometry_id", C.c_uint32), ("max_collisions", C.c_uint32), ("source", C.c_uint32),
+        ("ray_n1", C.c_uint32), ("max_segments", C.c_uint32), ("record_first_k", C.c_uint32),
+        ("record_cap", C.c_uint32), ("pad", C.c_uint32),
+    ]
+
+
+class _Out(C.Structure):
+    _fields_ = [
+        ("tally_fx", C.c_void_p), ("tally", C.c_void_p), ("tally_fxd", C.c_void_p),
+        ("seg_count", C.c_void_p), ("seq_hash", C.c_void_p), ("end_code", C.c_void_p),
+        ("rec", C.c_void_p), ("counters", C.c_void_p),
+    ]
+
+
+class _Trace(C.Structure):
+    _fields_ = [
+        ("cap", C.c_uint32), ("n", C.c_uint32), ("n_flights", C.c_uint32), ("pad", C.c_uint32),
+        ("seg_len", C.c_void_p), ("seg_sigma", C.c_void_p), ("seg_pos", C.c_void_p),
+        ("seg_inst", C.c_void_p), ("seg_kind", C.c_void_p), ("flight_tau", C.c_void_p),
+        ("birth_pos", C.c_double * 3), ("birth_dir", C.c_double * 3),
+        ("end_code", C.c_uint8), ("pad2", C.c_uint8 * 7),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        vp, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
+        L.or_geometry_create.argtypes = [C.POINTER(_Flat), C.POINTER(vp), C.c_char_p, C.c_int]
+        L.or_geometry_destroy.argtypes = [vp]
+        L.or_geometry_n_instances.argtypes = [vp]
+        L.or_geometry_n_instances.restype = u64
+        L.or_geometry_max_depth.argtypes = [vp]
+        L.or_geometry_max_depth.restype = u32
+        L.or_track.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), C.c_int]
+        L.or_trace_particle.argtypes = [vp, C.POINTER(_Params), u64, C.POINTER(_Trace)]
+        L.or_sample_births.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, vp]
+        L.or_find_cell.argtypes = [vp, vp, u64, vp, vp]
+        L.or_distance_to_surface.argtypes = [vp, vp, vp, u64, vp, vp, vp]
+        L.or_neighbours.argtypes = [vp, u32, vp, u32]
+        L.or_philox4x32_10.argtypes = [vp, vp, vp]
+        L.or_u01.argtypes = [u64]
+        L.or_u01.restype = C.c_double
+        L.or_mc_log.argtypes = [C.c_double]
+        L.or_mc_log.restype = C.c_double
+        L.or_mc_log_batch.argtypes = [vp, u64, vp]
+        L.or_fx_quantise.argtypes = [vp, u64, vp]
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+class OracleGeometry:
+    """The oracle's own copy of a flattened geometry (validated, with
+    per-surface neighbour lists and leaf-instance offsets)."""
+
+    def __init__(self, g):
+        L = lib()
+        self._keep = [np.ascontiguousarray(g.surf_type, np.uint8), np.ascontiguousarray(g.surf_coef, np.float64),
+                      np.ascontiguousarray(g.cell_hs_off, np.uint32), np.ascontiguousarray(g.hs, np.int32),
+                      np.ascontiguousarray(g.cell_fill, np.int32), np.ascontiguousarray(g.cell_trans, np.float64),
+                      np.ascontiguousarray(g.univ_cell_off, np.uint32), np.ascontiguousarray(g.sigma_t, np.float64)]
+        st, sc, ho, hs, cf, ct, uo, sg = self._keep
+        f = _Flat(n_surfaces=st.shape[0], n_cells=cf.shape[0], n_universes=uo.shape[0] - 1,
+                  n_materials=sg.shape[0], n_hs=hs.shape[0], root=int(g.root),
+                  surf_type=_p(st), surf_coef=_p(sc), cell_hs_off=_p(ho), hs=_p(hs), cell_fill=_p(cf),
+                  cell_trans=_p(ct), univ_cell_off=_p(uo), sigma_t=_p(sg))
+        f.domain_lo[:] = [float(v) for v in g.domain_lo]
+        f.domain_hi[:] = [float(v) for v in g.domain_hi]
+        h = C.c_void_p()
+        err = C.create_string_buffer(512)
+        rc = L.or_geometry_create(C.byref(f), C.byref(h), err, 512)
+        if rc != 0:
+            raise ValueError("oracle rejected geometry: " + err.value.decode())
+        self.h = h
+        self._keep = None
+        self.n_instances = int(L.or_geometry_n_instances(h))
+        self.max_depth = int(L.or_geometry_max_depth(h))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.or_geometry_destroy(self.h)
+            self.h = None
+
+    def neighbours(self, s: int) -> np.ndarray:
+        buf = np.zeros(1 << 16, np.uint32)
+        n = lib().or_neighbours(self.h, s, _p(buf), buf.shape[0])
+        return buf[:n].copy()
+
+    def find_cell(self, pos: np.ndarray):
+        pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+        n = pos.shape[0]
+        inst = np.empty(n, np.int64)
+        cells = np.empty((n, MAXL), np.int32)
+        lib().or_find_cell(self.h, _p(pos), n, _p(inst), _p(cells))
+        return inst, cells
+
+    def distance_to_surface(self, pos: np.ndarray, dirs: np.ndarray):
+        pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+        dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+        n = pos.shape[0]
+        d = np.empty(n, np.float64)
+        lev = np.empty(n, np.int32)
+        srf = np.empty(n, np.int32)
+        lib().or_distance_to_surface(self.h, _p(pos), _p(dirs), n, _p(d), _p(lev), _p(srf))
+        return d, lev, srf
+
+
+@dataclass
+class TrackParams:
+    seed: int
+    n_particles: int
+    first_particle: int = 0
+    geometry_id: int = 0
+    max_collisions: int = 20
+    source: int = 0
+    ray_n1: int = 0
+    max_segments: int = 100_000
+    record_first_k: int = 0
+    record_cap: int = 0
+
+    def c(self) -> _Params:
+        return _Params(seed=self.seed, first_particle=self.first_particle, n_particles=self.n_particles,
+                       geometry_id=self.geometry_id, max_collisions=self.max_collisions, source=self.source,
+                       ray_n1=self.ray_n1, max_segments=self.max_segments, record_first_k=self.record_first_k,
+                       record_cap=self.record_cap, pad=0)
+
+
+@dataclass
+class TrackResult:
+    tally: Optional[np.ndarray]       # Neumaier FP64 sum per leaf instance
+    tally_fx: Optional[np.ndarray]    # [n_inst, 2] u64 (lo, hi) fixed point, quantum 2^-96
+    tally_fxd: Optional[np.ndarray]   # fixed point rounded to double
+    seg_count: np.ndarray
+    seq_hash: np.ndarray
+    end_code: np.ndarray
+    rec: Optional[np.ndarray]         # [record_first_k, record_cap] i32, -1 padded
+    counters: dict
+
+
+def track(geom: OracleGeometry, p: TrackParams, n_threads: int = 0, tallies: bool = True) -> TrackResult:
+    if n_threads <= 0:
+        n_threads = min(16, os.cpu_count() or 1)
+    n = p.n_particles
+    ni = geom.n_instances
+    tally = np.zeros(ni, np.float64) if tallies else None
+    tfx = np.zeros((ni, 2), np.uint64) if tallies else None
+    tfxd = np.zeros(ni, np.float64) if tallies else None
+    seg = np.zeros(n, np.uint32)
+    hsh = np.zeros(n, np.uint64)
+    end = np.zeros(n, np.uint8)
+    rec = np.full((p.record_first_k, p.record_cap), -1, np.int32) if p.record_first_k else None
+    cnt = np.zeros(8, np.uint64)
+    out = _Out(tally_fx=_p(tfx), tally=_p(tally), tally_fxd=_p(tfxd), seg_count=_p(seg), seq_hash=_p(hsh),
+               end_code=_p(end), rec=_p(rec), counters=_p(cnt))
+    prm = p.c()
+    rc = lib().or_track(geom.h, C.byref(prm), C.byref(out), int(n_threads))
+    if rc != 0:
+        raise RuntimeError("or_track failed (%d)" % rc)
+    return TrackResult(tally, tfx, tfxd, seg, hsh, end, rec, {k: int(v) for k, v in zip(COUNTERS, cnt)})
+
+
+@dataclass
+class Trace:
+    seg_len: np.ndarray
+    seg_sigma: np.ndarray
+    seg_pos: np.ndarray
+    seg_inst: np.ndarray
+    seg_kind: np.ndarray
+    flight_tau: np.ndarray
+    birth_pos: np.ndarray
+    birth_dir: np.ndarray
+    end_code: int
+
+
+def trace_particle(geom: OracleGeometry, p: TrackParams, local: int, cap: int = 100_000) -> Trace:
+    a = dict(seg_len=np.zeros(cap), seg_sigma=np.zeros(cap), seg_pos=np.zeros((cap, 3)),
+             seg_inst=np.zeros(cap, np.int64), seg_kind=np.zeros(cap, np.uint8), flight_tau=np.zeros(cap))
+    t = _Trace(cap=cap, **{k: _p(v) for k, v in a.items()})
+    prm = p.c()
+    lib().or_trace_particle(geom.h, C.byref(prm), local, C.byref(t))
+    n, nf = t.n, t.n_flights
+    return Trace(a["seg_len"][:n], a["seg_sigma"][:n], a["seg_pos"][:n], a["seg_inst"][:n], a["seg_kind"][:n],
+                 a["flight_tau"][:nf], np.array(t.birth_pos[:]), np.array(t.birth_dir[:]), int(t.end_code))
+
+
+def sample_births(geom: OracleGeometry, p: TrackParams):
+    n = p.n_particles
+    pos = np.zeros((n, 3))
+    d = np.zeros((n, 3))
+    tau = np.zeros(n)
+    inst = np.zeros(n, np.int64)
+    prm = p.c()
+    lib().or_sample_births(geom.h, C.byref(prm), _p(pos), _p(d), _p(tau), _p(inst))
+    return pos, d, tau, inst
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, np.uint32)
+    k = np.asarray(key, np.uint32)
+    o = np.zeros(4, np.uint32)
+    lib().or_philox4x32_10(_p(c), _p(k), _p(o))
+    return o
+
+
+def u01(w: int) -> float:
+    return float(lib().or_u01(int(w)))
+
+
+def mc_log(x) -> np.ndarray:
+    x = np.ascontiguousarray(x, np.float64).ravel()
+    out = np.empty_like(x)
+    lib().or_mc_log_batch(_p(x), x.shape[0], _p(out))
+    return out
+
+
+def fx_quantise(lengths) -> np.ndarray:
+    lengths = np.ascontiguousarray(lengths, np.float64).ravel()
+    out = np.zeros((lengths.shape[0], 2), np.uint64)
+    lib().or_fx_quantise(_p(lengths), lengths.shape[0], _p(out))
+    return out

@@ -1,0 +1,319 @@
+"""Seeded synthetic inputs: flattened nested-CSG geometries.
+
+This module only *describes* geometries (surface coefficients, cell half-space
+lists, fills, translations, per-material attenuation coefficients).  It holds
+none of the tracking arithmetic: no containment test, distance, sampling or
+tally code lives here.  Both the CPU oracle (tests) and the HIP library take
+the same :class:`FlatGeometry` arrays as input.
+
+Geometry model (paper, Introduction and Fig. 2/3 discussion; Section
+"Tracking algorithms"):
+
+* a *surface* is a plane, a z-cylinder or a sphere; its positive side is
+  ``f(p) > 0`` (outside of a cylinder/sphere is positive);
+* a *cell* is an intersection of signed half-spaces, filled either with a
+  material or with a daughter *universe* placed with a translation;
+* a *universe* is a contiguous range of cells; arrays are modelled as
+  pseudo-array CSG universes (one explicit cell per lattice element, Section
+  "Single tracker (ST) method").
+
+Encodings (identical to ``include/gt.h``):
+
+* ``surf_type``: 0 PX, 1 PY, 2 PZ (coef[0] = d), 3 P (a, b, c, d),
+  4 CZ (x0, y0, r^2), 5 SPH (x0, y0, z0, r^2); 8 coefficient slots/surface.
+* ``hs``: +(s+1) for the positive side of surface s, -(s+1) for the negative.
+* ``cell_fill``: >= 0 material id, < 0 daughter universe -(u+1).
+* ``lattice_hint``: 8 doubles per universe
+  ``[kind, nx, ny, x0, y0, px, py, 0]``; kind 1 = square pseudo-lattice whose
+  local cell ``j*nx + i`` spans ``[x0 + i*px, x0 + (i+1)*px]`` (edge cells may
+  be unbounded outward).  Optional, advisory: it never changes a result.
+
+Workload recipes follow the paper's shapes: 17x17 rectilinear assemblies of
+pins split axially (Section "NuScale SMR"), 9-ring hexagonal assemblies of
+217 pins (Section "Empire microreactor").
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+PX, PY, PZ, P, CZ, SPH = 0, 1, 2, 3, 4, 5
+N_COEF = 8
+HINT_NONE, HINT_SQUARE = 0, 1
+
+
+@dataclasses.dataclass
+class FlatGeometry:
+    surf_type: np.ndarray        # u8  [n_surfaces]
+    surf_coef: np.ndarray        # f64 [n_surfaces, 8]
+    cell_hs_off: np.ndarray      # u32 [n_cells + 1]
+    hs: np.ndarray               # i32 [n_halfspaces]
+    cell_fill: np.ndarray        # i32 [n_cells]
+    cell_trans: np.ndarray       # f64 [n_cells, 3]
+    univ_cell_off: np.ndarray    # u32 [n_universes + 1]
+    root: int
+    lattice_hint: np.ndarray     # f64 [n_universes, 8]
+    sigma_t: np.ndarray          # f64 [n_materials]
+    domain_lo: np.ndarray        # f64 [3]
+    domain_hi: np.ndarray        # f64 [3]
+    name: str = ""
+
+    @property
+    def n_surfaces(self) -> int:
+        return int(self.surf_type.shape[0])
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cell_fill.shape[0])
+
+    @property
+    def n_universes(self) -> int:
+        return int(self.univ_cell_off.shape[0] - 1)
+
+    @property
+    def n_materials(self) -> int:
+        return int(self.sigma_t.shape[0])
+
+    def universe_cells(self, u: int) -> range:
+        return range(int(self.univ_cell_off[u]), int(self.univ_cell_off[u + 1]))
+
+    def cell_halfspaces(self, c: int) -> np.ndarray:
+        return self.hs[self.cell_hs_off[c]:self.cell_hs_off[c + 1]]
+
+
+class GeomBuilder:
+    """Accumulates surfaces and universes; universes are appended whole so
+    that each universe's cells stay contiguous."""
+
+    def __init__(self) -> None:
+        self.stype: List[int] = []
+        self.scoef: List[List[float]] = []
+        self.cells: List[Tuple[List[int], int, Tuple[float, float, float]]] = []
+        self.uoff: List[int] = [0]
+        self.hints: List[List[float]] = []
+
+    def surface(self, stype: int, *coef: float) -> int:
+        c = [float(v) for v in coef] + [0.0] * (N_COEF - len(coef))
+        self.stype.append(stype)
+        self.scoef.append(c)
+        return len(self.stype) - 1
+
+    def universe(self, cells: Sequence[Tuple[List[int], int, Tuple[float, float, float]]],
+                 hint: Optional[List[float]] = None) -> int:
+        """cells: list of (halfspaces, fill, translation).  Returns the id."""
+        for c in cells:
+            self.cells.append((list(c[0]), int(c[1]), tuple(float(v) for v in c[2])))
+        self.uoff.append(len(self.cells))
+        self.hints.append(list(hint) if hint is not None else [0.0] * 8)
+        return len(self.uoff) - 2
+
+    def build(self, root: int, sigma_t: Sequence[float], lo, hi, name="") -> FlatGeometry:
+        hs_off = [0]
+        hs: List[int] = []
+        for h, _, _ in self.cells:
+            hs.extend(h)
+            hs_off.append(len(hs))
+        return FlatGeometry(
+            surf_type=np.asarray(self.stype, dtype=np.uint8),
+            surf_coef=np.asarray(self.scoef, dtype=np.float64).reshape(-1, N_COEF),
+            cell_hs_off=np.asarray(hs_off, dtype=np.uint32),
+            hs=np.asarray(hs, dtype=np.int32),
+            cell_fill=np.asarray([c[1] for c in self.cells], dtype=np.int32),
+            cell_trans=np.asarray([c[2] for c in self.cells], dtype=np.float64).reshape(-1, 3),
+            univ_cell_off=np.asarray(self.uoff, dtype=np.uint32),
+            root=int(root),
+            lattice_hint=np.asarray(self.hints, dtype=np.float64).reshape(-1, 8),
+            sigma_t=np.asarray(sigma_t, dtype=np.float64),
+            domain_lo=np.asarray(lo, dtype=np.float64),
+            domain_hi=np.asarray(hi, dtype=np.float64),
+            name=name,
+        )
+
+
+def pos(s: int) -> int:
+    return s + 1
+
+
+def neg(s: int) -> int:
+    return -(s + 1)
+
+
+def fill_universe(u: int) -> int:
+    return -(u + 1)
+
+
+# --------------------------------------------------------------------------
+# building blocks
+# --------------------------------------------------------------------------
+
+def _pin_universe(b: GeomBuilder, radii: Sequence[float], mat0: int,
+                  zplanes: Sequence[float] = ()) -> int:
+    """Concentric z-cylinders centred on the local origin; the outermost
+    region (moderator) and the outer axial slabs are unbounded, so the pin
+    universe tiles space and never repeats a parent's boundary surface."""
+    cyl = [b.surface(CZ, 0.0, 0.0, r * r) for r in radii]
+    zs = [b.surface(PZ, z) for z in zplanes]
+    nr = len(radii) + 1
+    cells = []
+    for k in range(len(zs) + 1):
+        slab = []
+        if k > 0:
+            slab.append(pos(zs[k - 1]))
+        if k < len(zs):
+            slab.append(neg(zs[k]))
+        for r in range(nr):
+            h = []
+            if r > 0:
+                h.append(pos(cyl[r - 1]))
+            if r < nr - 1:
+                h.append(neg(cyl[r]))
+            cells.append((h + slab, mat0 + r, (0.0, 0.0, 0.0)))
+    return b.universe(cells)
+
+
+def _square_lattice(b: GeomBuilder, n: int, pitch: float, fills: np.ndarray,
+                    bounded_outer: bool, zbounds: Optional[Tuple[float, float]] = None) -> int:
+    """n x n pseudo-array universe centred at the origin.  Cell (i, j) is
+    local cell j*n + i and is filled with universe fills[j, i] translated to
+    its centre.  With bounded_outer=False the edge cells are unbounded
+    outward (an infinite daughter); otherwise all n+1 planes per axis exist."""
+    x0 = -0.5 * n * pitch
+    edges = [x0 + k * pitch for k in range(n + 1)]
+    lo_k = 0 if bounded_outer else 1
+    hi_k = n if bounded_outer else n - 1
+    sx = {k: b.surface(PX, edges[k]) for k in range(lo_k, hi_k + 1)}
+    sy = {k: b.surface(PY, edges[k]) for k in range(lo_k, hi_k + 1)}
+    zs = None
+    if zbounds is not None:
+        zs = (b.surface(PZ, zbounds[0]), b.surface(PZ, zbounds[1]))
+    cells = []
+    for j in range(n):
+        for i in range(n):
+            h = []
+            if i in sx:
+                h.append(pos(sx[i]))
+            if i + 1 in sx:
+                h.append(neg(sx[i + 1]))
+            if j in sy:
+                h.append(pos(sy[j]))
+            if j + 1 in sy:
+                h.append(neg(sy[j + 1]))
+            if zs is not None:
+                h += [pos(zs[0]), neg(zs[1])]
+            cx = x0 + (i + 0.5) * pitch
+            cy = x0 + (j + 0.5) * pitch
+            cells.append((h, fill_universe(int(fills[j, i])), (cx, cy, 0.0)))
+    hint = [HINT_SQUARE, n, n, x0, x0, pitch, pitch, 0.0]
+    return b.universe(cells, hint)
+
+
+def _sigmas(rng: np.random.Generator, n: int) -> np.ndarray:
+    return rng.uniform(0.3, 1.0, size=n)
+
+
+PIN_RADII = (0.40, 0.45, 0.50)
+SQ_PITCH = 1.25
+
+
+# --------------------------------------------------------------------------
+# workload configurations
+# --------------------------------------------------------------------------
+
+def config1(seed: int = 1001) -> FlatGeometry:
+    """3x3 square lattice, pitch 1.25, one pin universe of 3 concentric
+    z-cylinders r = 0.40/0.45/0.50 (4 materials); root cells bounded by 6
+    planes; domain [-1.875, 1.875]^3, vacuum outside."""
+    rng = np.random.default_rng(seed)
+    b = GeomBuilder()
+    h = 1.875
+    # root first so that it is universe 0; its fills are patched below
+    root_slot = len(b.uoff) - 1
+    pin_placeholder = 1
+    root = _square_lattice(b, 3, SQ_PITCH, np.full((3, 3), pin_placeholder), True, (-h, h))
+    pin = _pin_universe(b, PIN_RADII, 0)
+    assert root == root_slot and pin == pin_placeholder
+    return b.build(root, _sigmas(rng, 4), (-h, -h, -h), (h, h, h), "cfg1_3x3")
+
+
+def _axial_planes(n_interior: int, zlo: float, zhi: float) -> List[float]:
+    return [zlo + k * (zhi - zlo) / (n_interior + 1) for k in range(1, n_interior + 1)]
+
+
+def config2(seed: int = 1002) -> FlatGeometry:
+    """17x17 square lattice of pins at the root, pitch 1.25, |z| <= 100;
+    3 pin types in a seeded layout; each pin has 10 interior z-planes
+    (11 slabs x 4 radial regions = 44 cells); 12 materials."""
+    rng = np.random.default_rng(seed)
+    n = 17
+    layout = rng.integers(0, 3, size=(n, n))
+    sig = _sigmas(rng, 12)
+    b = GeomBuilder()
+    root = _square_lattice(b, n, SQ_PITCH, layout + 1, True, (-100.0, 100.0))
+    zpl = _axial_planes(10, -100.0, 100.0)
+    pins = [_pin_universe(b, PIN_RADII, 4 * t, zpl) for t in range(3)]
+    assert root == 0 and pins == [1, 2, 3]
+    h = 0.5 * n * SQ_PITCH
+    return b.build(root, sig, (-h, -h, -100.0), (h, h, 100.0), "cfg2_17x17")
+
+
+def config3(seed: int = 1003) -> FlatGeometry:
+    """Root cell (inside CZ r=140, |z| <= 100) filled with a 15x15 core
+    lattice (pitch 21.25) of 5 seeded assembly types, each a 17x17 lattice
+    of 3 pin types (pins as config 2).  Core and assembly lattices are
+    infinite daughters (edge cells unbounded outward)."""
+    rng = np.random.default_rng(seed)
+    n_core, n_asm = 15, 17
+    core_layout = rng.integers(0, 5, size=(n_core, n_core))
+    asm_layouts = [rng.integers(0, 3, size=(n_asm, n_asm)) for _ in range(5)]
+    sig = _sigmas(rng, 12)
+    b = GeomBuilder()
+    # universe ids: 0 root, 1 core, 2..6 assemblies, 7..9 pins
+    rcyl = b.surface(CZ, 0.0, 0.0, 140.0 * 140.0)
+    zlo = b.surface(PZ, -100.0)
+    zhi = b.surface(PZ, 100.0)
+    root = b.universe([([neg(rcyl), pos(zlo), neg(zhi)], fill_universe(1), (0.0, 0.0, 0.0))])
+    core = _square_lattice(b, n_core, n_asm * SQ_PITCH, core_layout + 2, False)
+    asms = [_square_lattice(b, n_asm, SQ_PITCH, asm_layouts[a] + 7, False) for a in range(5)]
+    zpl = _axial_planes(10, -100.0, 100.0)
+    pins = [_pin_universe(b, PIN_RADII, 4 * t, zpl) for t in range(3)]
+    assert (root, core, asms, pins) == (0, 1, [2, 3, 4, 5, 6], [7, 8, 9])
+    return b.build(root, sig, (-140.0, -140.0, -100.0), (140.0, 140.0, 100.0), "cfg3_core15x15")
+
+
+def sphere(radius: float = 1.0, sigma: float = 1.0) -> FlatGeometry:
+    """A single sphere of one material (for first-flight escape checks)."""
+    b = GeomBuilder()
+    s = b.surface(SPH, 0.0, 0.0, 0.0, radius * radius)
+    root = b.universe([([neg(s)], 0, (0.0, 0.0, 0.0))])
+    r = radius
+    return b.build(root, [sigma], (-r, -r, -r), (r, r, r), "sphere")
+
+
+def box(half: Tuple[float, float, float] = (1.0, 1.0, 1.0), sigma: float = 1.0) -> FlatGeometry:
+    """A single rectangular cell of one material."""
+    b = GeomBuilder()
+    hx, hy, hz = half
+    s = [b.surface(PX, -hx), b.surface(PX, hx), b.surface(PY, -hy), b.surface(PY, hy),
+         b.surface(PZ, -hz), b.surface(PZ, hz)]
+    root = b.universe([([pos(s[0]), neg(s[1]), pos(s[2]), neg(s[3]), pos(s[4]), neg(s[5])],
+                        0, (0.0, 0.0, 0.0))])
+    return b.build(root, [sigma], (-hx, -hy, -hz), (hx, hy, hz), "box")
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3}
+
+# particle counts of the workload table, and the seeds: geometry 1000+i,
+# particles 2000+i.
+CONFIG_PARTICLES = {1: 10_000, 2: 1_000_000, 3: 10_000_000, 4: 10_000_000}
+
+
+def make_config(i: int) -> FlatGeometry:
+    return CONFIGS[i](1000 + i)
+
+
+def particle_seed(i: int) -> int:
+    return 2000 + i

@@ -1,0 +1,178 @@
+"""Pins for the oracle's random-number layer (counter-based Philox4x32-10,
+the (0,1) uniform map, the project's series logarithm) and the birth
+sampling of the toy transport (Alg. 2: position, isotropic direction,
+exponential optical depth).  None of these compare the oracle with itself:
+they use published known-answer vectors, an independent library
+implementation, libm, and distributional closed forms."""
+
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_13849_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _kat():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                v = [int(x, 16) for x in line.split()]
+                rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+def test_philox_published_kat():
+    rows = _kat()
+    assert len(rows) == 3
+    for ctr, key, want in rows:
+        assert list(oracle.philox4x32_10(ctr, key)) == want
+
+
+ROCRAND_PROBE = r"""
+#include <rocrand/rocrand_philox4x32_10.h>
+#include <cstdio>
+#include <cstdlib>
+struct X : rocrand_device::philox4x32_10_engine { using rocrand_device::philox4x32_10_engine::ten_rounds; };
+int main(int argc, char** argv) {
+  X e; unsigned s = (unsigned)atoi(argv[1]);
+  for (int i = 0; i < 64; i++) {
+    unsigned v[6]; for (int k = 0; k < 6; k++) { s = s * 1664525u + 1013904223u; v[k] = s; }
+    uint4 o = e.ten_rounds(uint4{v[0], v[1], v[2], v[3]}, uint2{v[4], v[5]});
+    printf("%u %u %u %u %u %u %u %u %u %u\n", v[0],v[1],v[2],v[3],v[4],v[5],o.x,o.y,o.z,o.w);
+  }
+}
+"""
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None and not os.path.exists("/opt/rocm/bin/hipcc"),
+                    reason="hipcc not available")
+def test_philox_matches_rocrand_library():
+    """rocRAND's Philox4x32-10 (compiled here as host code) is an independent
+    implementation of the same published generator."""
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "p.cpp")
+        exe = os.path.join(d, "p")
+        open(src, "w").write(ROCRAND_PROBE)
+        subprocess.run([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O1", src, "-o", exe],
+                       check=True, capture_output=True)
+        out = subprocess.run([exe, "12345"], check=True, capture_output=True, text=True).stdout
+    n = 0
+    for line in out.strip().splitlines():
+        v = [int(x) for x in line.split()]
+        assert list(oracle.philox4x32_10(v[0:4], v[4:6])) == v[6:10]
+        n += 1
+    assert n == 64
+
+
+def test_u01_exact_and_open_interval():
+    assert oracle.u01(0) == 2.0 ** -53
+    assert oracle.u01(2 ** 64 - 1) == 1.0 - 2.0 ** -53
+    assert oracle.u01(1 << 63) == 0.5 + 2.0 ** -53
+    for w in (0x123456789ABCDEF0, 0xFFF, 0x1000):
+        assert oracle.u01(w) == ((w >> 12) + 0.5) / 2.0 ** 52  # exact: both sides representable
+
+
+def _ulp_diff(a, b):
+    ia = a.view(np.int64)
+    ib = b.view(np.int64)
+    return np.abs(ia - ib)
+
+
+def test_mc_log_within_2ulp_of_libm():
+    rng = np.random.default_rng(7)
+    x = np.concatenate([rng.random(400_000), np.exp(-rng.uniform(0, 37, 200_000)),
+                        1.0 - rng.random(100_000) * 1e-6, rng.uniform(0.70, 1.42, 200_000)])
+    x = x[(x > 0) & (x <= 1.0)]
+    got = oracle.mc_log(x)
+    want = np.log(x)
+    # ulps measured in the scale of the result
+    d = _ulp_diff(got, want)
+    assert d.max() <= 2, d.max()
+    assert oracle.mc_log([1.0])[0] == 0.0
+
+
+def test_mc_log_monotone_and_powers_of_two():
+    rng = np.random.default_rng(8)
+    x = np.sort(rng.random(200_000))
+    # neighbours one ulp apart around the mantissa split point sqrt(2)/2
+    s = math.sqrt(0.5)
+    around = np.array([np.nextafter(s, 0), s, np.nextafter(s, 1), np.nextafter(np.nextafter(s, 1), 1)])
+    for xs in (x, np.sort(np.concatenate([around, around / 2, around / 4]))):
+        y = oracle.mc_log(xs)
+        assert np.all(np.diff(y) >= 0)
+    k = np.arange(-53, 1)
+    y = oracle.mc_log(2.0 ** k)
+    assert np.all(np.abs(y - k * math.log(2.0)) <= 2 * np.spacing(np.abs(k * math.log(2.0)) + 1e-300))
+
+
+def test_uniform_moments_and_chi2():
+    """u01 of the Philox words of many particles: mean, variance and a
+    64-bin chi-square within generous bounds."""
+    g = synth.box((1.0, 1.0, 1.0))
+    og = oracle.OracleGeometry(g)
+    p = oracle.TrackParams(seed=99, n_particles=200_000, geometry_id=3)
+    pos, d, tau, inst = oracle.sample_births(og, p)
+    x = (pos[:, 0] + 1.0) / 2.0   # first uniform of each particle (box accepts everything)
+    assert abs(x.mean() - 0.5) < 5 * math.sqrt(1 / 12 / x.size)
+    assert abs(x.var() - 1 / 12) < 0.003
+    h, _ = np.histogram(x, bins=64, range=(0, 1))
+    e = x.size / 64
+    chi2 = ((h - e) ** 2 / e).sum()
+    assert chi2 < 63 + 6 * math.sqrt(2 * 63)
+
+
+def test_direction_isotropic_unit_vectors():
+    g = synth.box((1.0, 1.0, 1.0))
+    og = oracle.OracleGeometry(g)
+    p = oracle.TrackParams(seed=5, n_particles=200_000, geometry_id=1)
+    _, d, _, _ = oracle.sample_births(og, p)
+    norm = np.sqrt((d * d).sum(1))
+    assert np.max(np.abs(norm - 1.0)) <= 4 * np.finfo(float).eps
+    n = d.shape[0]
+    se = math.sqrt(1 / 3 / n)
+    for k in range(3):
+        assert abs(d[:, k].mean()) < 5 * se
+        assert abs((d[:, k] ** 2).mean() - 1 / 3) < 5 * math.sqrt(4 / 45 / n)
+    # w is uniform on [-1, 1] for an isotropic direction
+    h, _ = np.histogram(d[:, 2], bins=32, range=(-1, 1))
+    e = n / 32
+    assert ((h - e) ** 2 / e).sum() < 31 + 6 * math.sqrt(62)
+
+
+def test_tau_is_exponential():
+    g = synth.box((1.0, 1.0, 1.0))
+    og = oracle.OracleGeometry(g)
+    p = oracle.TrackParams(seed=11, n_particles=200_000, geometry_id=2)
+    _, _, tau, _ = oracle.sample_births(og, p)
+    n = tau.size
+    assert tau.min() > 0
+    assert abs(tau.mean() - 1.0) < 5 / math.sqrt(n)
+    assert abs(tau.var() - 1.0) < 5 * math.sqrt(8 / n)
+    # P(tau > t) = exp(-t)
+    for t in (0.1, 1.0, 3.0):
+        assert abs((tau > t).mean() - math.exp(-t)) < 5 * math.sqrt(math.exp(-t) / n)
+
+
+def test_birth_position_uniform_and_rejection():
+    """cfg3's root is a cylinder r=140 in a 280x280 box: the accepted births
+    are uniform inside it (radial CDF r^2/R^2)."""
+    g = synth.make_config(3)
+    og = oracle.OracleGeometry(g)
+    p = oracle.TrackParams(seed=2003, n_particles=20_000, geometry_id=3)
+    pos, _, _, inst = oracle.sample_births(og, p)
+    assert np.all(inst >= 0)
+    r2 = (pos[:, 0] ** 2 + pos[:, 1] ** 2) / 140.0 ** 2
+    assert r2.max() <= 1.0
+    for q in (0.25, 0.5, 0.75):
+        assert abs((r2 <= q).mean() - q) < 5 * math.sqrt(q * (1 - q) / r2.size)
+    assert abs(pos[:, 2].mean()) < 5 * 200 / math.sqrt(12 * r2.size)
