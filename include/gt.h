@@ -1,0 +1,222 @@
+/*
+ * gt.h -- C ABI of the MI355X nested-CSG geometry tracker (libgt.so).
+ *
+ * The library tracks toy-transport Monte Carlo particle histories through
+ * nested constructive-solid-geometry universes and pseudo-array lattices
+ * with one CSG tracker accelerated by per-universe bounding-volume
+ * hierarchies: the "single tracker" method of Biondo et al. (Section
+ * "Single tracker (ST) method"), using the tracking operations of Table 1
+ * (find_cell, distance_to_surface, move_within_cell, cross_surface,
+ * change_direction) inside the history loop of Alg. 2.
+ *
+ * Conventions for every entry point:
+ *   - return 0 on success or a negative GT_E* code; gt_last_error() then
+ *     returns a thread-local message naming the offending argument, cell or
+ *     surface.  No C++ exception crosses this boundary.
+ *   - "host" pointers are read during the call and never retained; "device"
+ *     pointers are HIP device memory owned by the caller (for example torch
+ *     tensors' data pointers) and are accessed asynchronously on `stream`
+ *     (a hipStream_t; NULL is the null stream).  Device results are valid
+ *     once the stream has been synchronised by the caller.
+ *   - Problems found while tracking (a particle leaving through a gap, a
+ *     record buffer too short) are reported through per-particle end codes
+ *     and the counters array, not through the return value.
+ *   - All arithmetic that decides a cell is IEEE double without fused
+ *     multiply-add; single precision is only used to skip candidates whose
+ *     conservatively widened bounding box cannot contain the point, so
+ *     results do not depend on the precision mode.
+ */
+#ifndef GT_H
+#define GT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define GT_OK 0
+#define GT_EINVAL (-1)     /* bad argument (null pointer, size, flag)         */
+#define GT_EGEOM (-2)      /* geometry failed validation                      */
+#define GT_ENOMEM (-3)     /* host or device allocation failed               */
+#define GT_EHIP (-4)       /* a HIP runtime call failed (message has details) */
+#define GT_ECAPACITY (-5)  /* a size exceeds a documented limit               */
+
+/* ---- limits ------------------------------------------------------------ */
+#define GT_MAX_LEVELS 6          /* nesting depth (root = level 0)            */
+#define GT_MAX_INSTANCES 0xFFFFFFF0u
+
+/* ---- surface types (Introduction, CSG construction): positive side is
+ *      f(p) > 0, a point with f(p) <= 0 is on the negative side.  Coefficient
+ *      slots, 8 doubles per surface:
+ *        PX/PY/PZ : d            f = x - d (resp. y, z)
+ *        P        : a b c d      f = ((a x + b y) + c z) - d
+ *        CZ       : x0 y0 r2     f = ((x-x0)^2 + (y-y0)^2) - r2
+ *        SPH      : x0 y0 z0 r2  f = (((x-x0)^2 + (y-y0)^2) + (z-z0)^2) - r2  */
+#define GT_SURF_PX 0
+#define GT_SURF_PY 1
+#define GT_SURF_PZ 2
+#define GT_SURF_P 3
+#define GT_SURF_CZ 4
+#define GT_SURF_SPH 5
+
+/* ---- per-particle end codes ------------------------------------------- */
+#define GT_END_NONE 0
+#define GT_END_ESCAPE 1   /* crossed out of every root cell (vacuum)         */
+#define GT_END_CAP 2      /* reached max_collisions                           */
+#define GT_END_LOST 3     /* no cell found below the root after a crossing    */
+#define GT_END_SEGCAP 4   /* reached max_segments                             */
+
+/* ---- counters (uint64 each, device array of 8) -------------------------- */
+#define GT_CNT_ESCAPED 0
+#define GT_CNT_CAPPED 1
+#define GT_CNT_LOST 2
+#define GT_CNT_SEGCAP 3
+#define GT_CNT_REC_OVERFLOW 4   /* recorded particles with more segments than record_cap */
+#define GT_CNT_SEGMENTS 5       /* total segments (move_within_cell calls)               */
+#define GT_CNT_REJECTED 6       /* birth positions rejected (outside every root cell)     */
+
+/* ---- precision modes ---------------------------------------------------- */
+#define GT_PREC_FP64 0    /* double-precision bounding boxes, no lattice guess          */
+#define GT_PREC_MIXED 1   /* single-precision widened boxes + lattice index guess, every
+                             decision still taken in double precision                   */
+
+/* ---- flags --------------------------------------------------------------- */
+#define GT_FLAG_ACCUMULATE 1u   /* add to tally_fx instead of zeroing it first */
+
+typedef struct gt_geometry gt_geometry;   /* opaque; owns its device tables */
+
+/* Flattened geometry, all arrays host memory, copied by gt_geometry_create.
+ * A cell is the intersection of its half-spaces (Introduction, CSG cells);
+ * a universe is a contiguous range of cells; a cell is filled with a
+ * material or with a daughter universe placed with a translation t, the
+ * daughter's local coordinates being p - t (Section "Multi-universe CPU
+ * tracking", Alg. 7/8).  Arrays are modelled as pseudo-array universes
+ * (Section "Single tracker (ST) method").
+ * Requirements (checked; violations return GT_EGEOM):
+ *   - hs entries are +(s+1) (positive side of surface s) or -(s+1); a
+ *     surface appears at most once per cell and belongs to one universe;
+ *   - univ_cell_off is non-decreasing with non-empty ranges covering all
+ *     cells; the fill graph from `root` is acyclic and at most
+ *     GT_MAX_LEVELS deep; materials index sigma_t (> 0, finite);
+ *   - every root cell lies inside [domain_lo, domain_hi] (the sampling box).
+ * Modelling assumption (not checked): two cells of one universe never
+ * both contain a point, i.e. they are separated by a shared surface with
+ * opposite senses, by parallel planes of one family, or by concentric
+ * cylinders/spheres; a daughter universe never repeats a surface of its
+ * parent cell.  Then every search order finds the same cell.
+ * lattice_hint: optional (NULL), 8 doubles per universe
+ *   [kind, nx, ny, x0, y0, px, py, 0]; kind 1 = square pseudo-array whose
+ *   local cell j*nx+i spans [x0+i px, x0+(i+1) px] x [y0+j py, ...].  Used
+ *   only as a first guess that is verified in double precision. */
+typedef struct {
+    uint32_t n_surfaces, n_cells, n_universes, n_materials, n_halfspaces, root;
+    const uint8_t *surf_type;      /* [n_surfaces]                 */
+    const double *surf_coef;       /* [n_surfaces * 8]             */
+    const uint32_t *cell_hs_off;   /* [n_cells + 1]                */
+    const int32_t *hs;             /* [n_halfspaces]               */
+    const int32_t *cell_fill;      /* [n_cells]: >=0 material, <0 -(universe+1) */
+    const double *cell_trans;      /* [n_cells * 3]                */
+    const uint32_t *univ_cell_off; /* [n_universes + 1]            */
+    const double *lattice_hint;    /* [n_universes * 8] or NULL    */
+    const double *sigma_t;         /* [n_materials], 1/cm          */
+    double domain_lo[3], domain_hi[3];
+} gt_flat_geometry;
+
+/* Validate, preprocess (leaf-instance numbering, cell bounding boxes, one
+ * SAH-built bounding-volume hierarchy per universe -- the paper's
+ * acceleration structure of Section "Single tracker (ST) method" with the
+ * three-candidates-per-axis surface-area heuristic -- and lattice guesses),
+ * then upload once to the current HIP device.  *out receives the handle. */
+int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out);
+
+/* Number of leaf instances (the length of the tally arrays), nesting depth
+ * and bytes of device memory held.  Any output pointer may be NULL. */
+int gt_geometry_info(const gt_geometry *g, uint64_t *n_instances, uint32_t *max_depth,
+                     uint64_t *device_bytes);
+
+void gt_geometry_destroy(gt_geometry *g);
+
+/* Parameters of one batch of histories (host struct). */
+typedef struct {
+    uint64_t seed;            /* Philox4x32-10 key                                   */
+    uint64_t first_particle;  /* global id of the first particle                     */
+    uint64_t n_particles;
+    uint32_t geometry_id;     /* fourth Philox counter word                          */
+    uint32_t max_collisions;  /* a history ends at this many collisions (>= 1)       */
+    uint32_t source;          /* 0 uniform volume source, isotropic;
+                                 1 parallel rays along +x from the x = lo face on a
+                                 ray_n1 x ceil(n/ray_n1) grid, no collisions         */
+    uint32_t ray_n1;
+    uint32_t max_segments;    /* a history ends after this many segments (>= 1)      */
+    uint32_t precision;       /* GT_PREC_*                                           */
+    uint32_t record_first_k;  /* particles [0, k) of the batch record their sequence */
+    uint32_t record_cap;      /* entries recorded per particle                       */
+    uint32_t flags;           /* GT_FLAG_*                                           */
+    uint32_t block_size;      /* threads per workgroup (64..1024, multiple of 64;
+                                 0 = library default)                                */
+} gt_track_params;
+
+/* Outputs, all device memory owned by the caller.
+ *   tally_fx  [2 * n_instances] uint64: per leaf instance, the (low, high)
+ *             words of a 128-bit fixed-point sum of segment lengths in units
+ *             of 2^-96 cm (each length truncated to that quantum; the total
+ *             is independent of summation order).  Required.
+ *   tally     [n_instances] double or NULL: tally_fx converted to cm.
+ *   seg_count [n_particles] uint32, seq_hash [n_particles] uint64,
+ *   end_code  [n_particles] uint8, each may be NULL.  seq_hash is the 64-bit
+ *             FNV-1a style fold h = (h ^ (inst+1)) * 0x100000001b3 over the
+ *             leaf instance of every segment from 0xcbf29ce484222325, then
+ *             h ^= end_code.
+ *   rec       [record_first_k * record_cap] int32 or NULL: leaf instance of
+ *             each segment of the recorded particles, -1 padded.
+ *   counters  [8] uint64, required; zeroed by the call (GT_CNT_*). */
+typedef struct {
+    uint64_t *tally_fx;
+    double *tally;
+    uint32_t *seg_count;
+    uint64_t *seq_hash;
+    uint8_t *end_code;
+    int32_t *rec;
+    uint64_t *counters;
+} gt_track_out;
+
+/* Sample and track a batch of histories (Alg. 2 reduced to a toy
+ * transport: uniform birth position rejected until a root cell contains
+ * it, isotropic direction (Marsaglia 1972), exponential optical depth from
+ * a counter-based Philox4x32-10 stream keyed by (seed, particle id,
+ * geometry id); per segment distance_to_surface over every level, a
+ * boundary crossing when it is strictly shorter than tau/Sigma of the leaf
+ * material, else a collision with isotropic redirection; vacuum boundary).
+ * Asynchronous on `stream`; allocates nothing. */
+int gt_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream);
+
+/* Table 1 find_cell for a batch of global positions (device pos[3n]):
+ * inst[n] receives the leaf instance or -1, cells[n * GT_MAX_LEVELS] (may be
+ * NULL) the cell id per level, -1 padded.  precision selects the candidate
+ * search (GT_PREC_*); results do not depend on it. */
+int gt_find_cell(const gt_geometry *g, const double *pos, uint64_t n, int64_t *inst, int32_t *cells,
+                 uint32_t precision, void *stream);
+
+/* Table 1 distance_to_surface for a batch (device pos[3n], dir[3n]); each
+ * point is first located with find_cell and is not on a surface.  dist[n]
+ * receives the distance (+inf if none, NaN if the point is in no cell),
+ * level[n]/surf[n] the level and surface id hit (-1 if none). */
+int gt_distance_to_surface(const gt_geometry *g, const double *pos, const double *dir, uint64_t n,
+                           double *dist, int32_t *level, int32_t *surf, void *stream);
+
+/* Floating-point contract check: for device arrays a[n], b[n] (b > 0)
+ * writes a/b, sqrt(b) and the library's logarithm of b (the series used for
+ * the exponential flight sampling) computed on the device, so a caller can
+ * compare them bit for bit with a host implementation. */
+int gt_fp64_check(const double *a, const double *b, uint64_t n, double *quot, double *root, double *logb,
+                  void *stream);
+
+/* Thread-local description of the last failure in this thread. */
+const char *gt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GT_H */

@@ -1,0 +1,597 @@
+// Host side of libgt: validation of a flattened geometry, preprocessing into
+// device tables, one upload, and the extern "C" entry points.
+//
+// Preprocessing steps:
+//   1. validation (ranges, surface ownership, acyclic fills, depth);
+//   2. leaf-instance numbering: a material cell counts one instance, a
+//      filled cell the instances of its daughter (per-instance cell tallies,
+//      Section "Empire microreactor" tallies every pin sub-cell instance);
+//   3. reachable extent of every universe, propagated from the root's
+//      sampling box through each filled cell's box minus its translation;
+//   4. an axis-aligned box per cell: the universe extent clipped by the
+//      cell's axis planes, the boxes of its inside-of-cylinder/sphere
+//      half-spaces, and the polygon cut out by its vertical general planes
+//      (exact convex clipping, where the paper truncates the universe box by
+//      each surface's bounding planes), then widened outward by a margin far
+//      larger than any rounding in the point evaluation;
+//   5. per universe a bounding-volume hierarchy over those boxes, split with
+//      the surface-area heuristic over three equally spaced candidate planes
+//      per axis (Section "Single tracker (ST) method"); children may
+//      overlap and every cell appears once;
+//   6. single-precision copies of all boxes rounded outward (lower bounds
+//      down, upper bounds up), so a point rounded to nearest can never be
+//      rejected by a box that contains it in double precision.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gt_internal.h"
+
+namespace gt {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+namespace {
+
+struct Box {
+    double lo[3], hi[3];
+    static Box empty() {
+        Box b;
+        for (int k = 0; k < 3; k++) { b.lo[k] = INFINITY; b.hi[k] = -INFINITY; }
+        return b;
+    }
+    bool is_empty() const { return lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2]; }
+    void grow(const Box &o) {
+        for (int k = 0; k < 3; k++) { lo[k] = std::min(lo[k], o.lo[k]); hi[k] = std::max(hi[k], o.hi[k]); }
+    }
+    void widen(double d) {
+        for (int k = 0; k < 3; k++) { lo[k] -= d; hi[k] += d; }
+    }
+    double area() const {
+        double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+        return 2.0 * (dx * dy + dy * dz + dz * dx);
+    }
+};
+
+struct HalfPlane { double a, b, d; bool pos; };
+
+// Sutherland-Hodgman clip of a convex polygon by a closed half-plane.
+static void clip_polygon(std::vector<double> &px, std::vector<double> &py, const HalfPlane &h) {
+    std::vector<double> ox, oy;
+    size_t n = px.size();
+    auto val = [&](size_t i) {
+        double f = (h.a * px[i] + h.b * py[i]) - h.d;
+        return h.pos ? f : -f;   // keep val >= 0
+    };
+    for (size_t i = 0; i < n; i++) {
+        size_t j = (i + 1) % n;
+        double vi = val(i), vj = val(j);
+        if (vi >= 0) { ox.push_back(px[i]); oy.push_back(py[i]); }
+        if ((vi >= 0) != (vj >= 0)) {
+            double t = vi / (vi - vj);
+            ox.push_back(px[i] + t * (px[j] - px[i]));
+            oy.push_back(py[i] + t * (py[j] - py[i]));
+        }
+    }
+    px.swap(ox);
+    py.swap(oy);
+}
+
+static float round_down(double v) {
+    float f = (float)v;
+    if ((double)f > v) f = std::nextafter(f, -INFINITY);
+    return f;
+}
+
+static float round_up(double v) {
+    float f = (float)v;
+    if ((double)f < v) f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+struct Builder {
+    const gt_flat_geometry *f;
+    std::vector<uint32_t> cell_univ;
+    std::vector<uint64_t> ninst, inst_off;
+    std::vector<uint32_t> depth;
+    std::vector<Box> ext, cbox;
+    std::vector<uint8_t> reached;
+    std::vector<uint32_t> topo;
+    double delta = 0;
+    // outputs
+    std::vector<Node32> n32;
+    std::vector<Node64> n64;
+    std::vector<uint32_t> leaf;
+    std::vector<Univ> univ;
+
+    uint32_t surf_of(int32_t h) const { return (uint32_t)(h < 0 ? -(int64_t)h : h) - 1; }
+
+    int validate() {
+        const gt_flat_geometry &F = *f;
+        if (F.n_universes == 0 || F.n_cells == 0) { set_error("geometry has no universes or cells"); return GT_EGEOM; }
+        if (!F.surf_type && F.n_surfaces) return set_error("surf_type is NULL"), GT_EINVAL;
+        if (!F.surf_coef && F.n_surfaces) return set_error("surf_coef is NULL"), GT_EINVAL;
+        if (!F.cell_hs_off || !F.cell_fill || !F.cell_trans || !F.univ_cell_off || !F.sigma_t ||
+            (!F.hs && F.n_halfspaces))
+            return set_error("a required geometry array is NULL"), GT_EINVAL;
+        if (F.root >= F.n_universes) return set_error("root universe %u out of range", F.root), GT_EGEOM;
+        if (F.n_surfaces >= (1u << 28)) return set_error("too many surfaces (%u)", F.n_surfaces), GT_ECAPACITY;
+        for (uint32_t s = 0; s < F.n_surfaces; s++) {
+            if (F.surf_type[s] > ST_SPH) return set_error("surface %u: unknown type %u", s, F.surf_type[s]), GT_EGEOM;
+            for (int k = 0; k < 8; k++)
+                if (!std::isfinite(F.surf_coef[8 * (size_t)s + k]))
+                    return set_error("surface %u: non-finite coefficient", s), GT_EGEOM;
+            if (F.surf_type[s] == ST_CZ && !(F.surf_coef[8 * (size_t)s + 2] > 0))
+                return set_error("surface %u: cylinder r^2 must be > 0", s), GT_EGEOM;
+            if (F.surf_type[s] == ST_SPH && !(F.surf_coef[8 * (size_t)s + 3] > 0))
+                return set_error("surface %u: sphere r^2 must be > 0", s), GT_EGEOM;
+        }
+        for (uint32_t m = 0; m < F.n_materials; m++)
+            if (!(F.sigma_t[m] > 0) || !std::isfinite(F.sigma_t[m]))
+                return set_error("material %u: sigma_t must be finite and > 0", m), GT_EGEOM;
+        for (int k = 0; k < 3; k++)
+            if (!(F.domain_lo[k] < F.domain_hi[k]) || !std::isfinite(F.domain_lo[k]) || !std::isfinite(F.domain_hi[k]))
+                return set_error("domain box empty or infinite on axis %d", k), GT_EGEOM;
+        if (F.univ_cell_off[0] != 0 || F.univ_cell_off[F.n_universes] != F.n_cells)
+            return set_error("univ_cell_off must start at 0 and end at n_cells"), GT_EGEOM;
+        if (F.cell_hs_off[0] != 0 || F.cell_hs_off[F.n_cells] != F.n_halfspaces)
+            return set_error("cell_hs_off must start at 0 and end at n_halfspaces"), GT_EGEOM;
+        cell_univ.assign(F.n_cells, 0);
+        for (uint32_t u = 0; u < F.n_universes; u++) {
+            if (F.univ_cell_off[u + 1] <= F.univ_cell_off[u]) return set_error("universe %u has no cells", u), GT_EGEOM;
+            for (uint32_t c = F.univ_cell_off[u]; c < F.univ_cell_off[u + 1]; c++) cell_univ[c] = u;
+        }
+        std::vector<int64_t> owner(F.n_surfaces, -1);
+        for (uint32_t c = 0; c < F.n_cells; c++) {
+            if (F.cell_hs_off[c + 1] < F.cell_hs_off[c]) return set_error("cell %u: decreasing cell_hs_off", c), GT_EGEOM;
+            if (F.cell_hs_off[c + 1] - F.cell_hs_off[c] > 0xFFFFu) return set_error("cell %u: too many half-spaces", c), GT_ECAPACITY;
+            for (uint32_t k = F.cell_hs_off[c]; k < F.cell_hs_off[c + 1]; k++) {
+                int32_t h = F.hs[k];
+                if (h == 0 || (uint32_t)(h < 0 ? -(int64_t)h : h) > F.n_surfaces)
+                    return set_error("cell %u: half-space %d names no surface", c, h), GT_EGEOM;
+                uint32_t s = surf_of(h);
+                for (uint32_t k2 = F.cell_hs_off[c]; k2 < k; k2++)
+                    if (surf_of(F.hs[k2]) == s) return set_error("cell %u: surface %u appears twice", c, s), GT_EGEOM;
+                if (owner[s] >= 0 && owner[s] != (int64_t)cell_univ[c])
+                    return set_error("surface %u is used by universes %lld and %u", s, (long long)owner[s], cell_univ[c]), GT_EGEOM;
+                owner[s] = cell_univ[c];
+            }
+            int32_t fl = F.cell_fill[c];
+            if (fl >= 0 && (uint32_t)fl >= F.n_materials) return set_error("cell %u: material %d out of range", c, fl), GT_EGEOM;
+            if (fl < 0 && (uint64_t)(-(int64_t)fl - 1) >= F.n_universes)
+                return set_error("cell %u: daughter universe %lld out of range", c, (long long)(-(int64_t)fl - 1)), GT_EGEOM;
+            for (int k = 0; k < 3; k++)
+                if (!std::isfinite(F.cell_trans[3 * (size_t)c + k])) return set_error("cell %u: non-finite translation", c), GT_EGEOM;
+        }
+        // instances, depth and a parents-first order of the universes reachable from the root
+        ninst.assign(F.n_universes, 0);
+        inst_off.assign(F.n_cells, 0);
+        depth.assign(F.n_universes, 0);
+        std::vector<uint8_t> state(F.n_universes, 0);
+        std::vector<uint32_t> post;
+        int rc = visit(F.root, state, post);
+        if (rc) return rc;
+        topo.assign(post.rbegin(), post.rend());
+        if (depth[F.root] > GT_MAX_LEVELS)
+            return set_error("nesting depth %u exceeds %d", depth[F.root], GT_MAX_LEVELS), GT_ECAPACITY;
+        if (ninst[F.root] > GT_MAX_INSTANCES)
+            return set_error("%llu leaf instances exceed the limit", (unsigned long long)ninst[F.root]), GT_ECAPACITY;
+        if (F.lattice_hint) {
+            for (uint32_t u = 0; u < F.n_universes; u++) {
+                const double *h = F.lattice_hint + 8 * (size_t)u;
+                if (h[0] == 0) continue;
+                if (h[0] != 1) return set_error("universe %u: unknown lattice hint kind %g", u, h[0]), GT_EGEOM;
+                uint32_t nc = F.univ_cell_off[u + 1] - F.univ_cell_off[u];
+                if (!(h[1] >= 1 && h[2] >= 1 && h[1] * h[2] == (double)nc && h[5] > 0 && h[6] > 0 &&
+                      std::isfinite(h[3]) && std::isfinite(h[4]) && std::isfinite(h[5]) && std::isfinite(h[6])))
+                    return set_error("universe %u: lattice hint does not match its %u cells", u, nc), GT_EGEOM;
+            }
+        }
+        return GT_OK;
+    }
+
+    int visit(uint32_t u, std::vector<uint8_t> &state, std::vector<uint32_t> &post) {
+        if (state[u] == 2) return GT_OK;
+        if (state[u] == 1) return set_error("fill graph has a cycle through universe %u", u), GT_EGEOM;
+        state[u] = 1;
+        uint64_t n = 0;
+        uint32_t d = 1;
+        for (uint32_t c = f->univ_cell_off[u]; c < f->univ_cell_off[u + 1]; c++) {
+            inst_off[c] = n;
+            int32_t fl = f->cell_fill[c];
+            if (fl >= 0) { n += 1; continue; }
+            uint32_t du = (uint32_t)(-(int64_t)fl - 1);
+            int rc = visit(du, state, post);
+            if (rc) return rc;
+            n += ninst[du];
+            d = std::max(d, depth[du] + 1);
+            if (n > (uint64_t)GT_MAX_INSTANCES) return set_error("too many leaf instances"), GT_ECAPACITY;
+        }
+        ninst[u] = n;
+        depth[u] = d;
+        state[u] = 2;
+        post.push_back(u);
+        return GT_OK;
+    }
+
+    Box clip_cell(uint32_t c, const Box &start) const {
+        Box b = start;
+        std::vector<HalfPlane> planes;
+        for (uint32_t k = f->cell_hs_off[c]; k < f->cell_hs_off[c + 1]; k++) {
+            int32_t h = f->hs[k];
+            uint32_t s = surf_of(h);
+            bool pos = h > 0;
+            const double *q = f->surf_coef + 8 * (size_t)s;
+            switch (f->surf_type[s]) {
+            case ST_PX: case ST_PY: case ST_PZ: {
+                int ax = f->surf_type[s];
+                if (pos) b.lo[ax] = std::max(b.lo[ax], q[0]);
+                else b.hi[ax] = std::min(b.hi[ax], q[0]);
+                break;
+            }
+            case ST_CZ:
+                if (!pos) {
+                    double r = std::sqrt(q[2]);
+                    b.lo[0] = std::max(b.lo[0], q[0] - r); b.hi[0] = std::min(b.hi[0], q[0] + r);
+                    b.lo[1] = std::max(b.lo[1], q[1] - r); b.hi[1] = std::min(b.hi[1], q[1] + r);
+                }
+                break;
+            case ST_SPH:
+                if (!pos) {
+                    double r = std::sqrt(q[3]);
+                    for (int k2 = 0; k2 < 3; k2++) {
+                        b.lo[k2] = std::max(b.lo[k2], q[k2] - r);
+                        b.hi[k2] = std::min(b.hi[k2], q[k2] + r);
+                    }
+                }
+                break;
+            case ST_P:
+                if (q[2] == 0.0 && (q[0] != 0.0 || q[1] != 0.0)) planes.push_back({q[0], q[1], q[3], pos});
+                break;   // planes that are not vertical only make the box conservative
+            }
+        }
+        if (b.is_empty()) return Box::empty();
+        if (!planes.empty()) {
+            std::vector<double> px = {b.lo[0], b.hi[0], b.hi[0], b.lo[0]};
+            std::vector<double> py = {b.lo[1], b.lo[1], b.hi[1], b.hi[1]};
+            for (const HalfPlane &h : planes) {
+                clip_polygon(px, py, h);
+                if (px.empty()) return Box::empty();
+            }
+            double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+            for (size_t i = 0; i < px.size(); i++) {
+                x0 = std::min(x0, px[i]); x1 = std::max(x1, px[i]);
+                y0 = std::min(y0, py[i]); y1 = std::max(y1, py[i]);
+            }
+            b.lo[0] = std::max(b.lo[0], x0); b.hi[0] = std::min(b.hi[0], x1);
+            b.lo[1] = std::max(b.lo[1], y0); b.hi[1] = std::min(b.hi[1], y1);
+            if (b.is_empty()) return Box::empty();
+        }
+        b.widen(delta);
+        return b;
+    }
+
+    int boxes() {
+        const gt_flat_geometry &F = *f;
+        double scale = 1.0;
+        for (int k = 0; k < 3; k++) scale = std::max({scale, std::fabs(F.domain_lo[k]), std::fabs(F.domain_hi[k])});
+        delta = std::ldexp(scale, -26);
+        ext.assign(F.n_universes, Box::empty());
+        cbox.assign(F.n_cells, Box::empty());
+        reached.assign(F.n_universes, 0);
+        // root: every root cell must lie inside the sampling box
+        Box dom;
+        for (int k = 0; k < 3; k++) { dom.lo[k] = F.domain_lo[k]; dom.hi[k] = F.domain_hi[k]; }
+        Box big = dom;
+        for (int k = 0; k < 3; k++) { double w = dom.hi[k] - dom.lo[k]; big.lo[k] -= w; big.hi[k] += w; }
+        for (uint32_t c = F.univ_cell_off[F.root]; c < F.univ_cell_off[F.root + 1]; c++) {
+            Box b = clip_cell(c, big);
+            if (b.is_empty()) continue;
+            for (int k = 0; k < 3; k++)
+                if (b.lo[k] < dom.lo[k] - 2 * delta || b.hi[k] > dom.hi[k] + 2 * delta)
+                    return set_error("root cell %u is not bounded inside the domain box (axis %d)", c, k), GT_EGEOM;
+        }
+        Box root_ext = dom;
+        root_ext.widen(delta);
+        ext[F.root] = root_ext;
+        reached[F.root] = 1;
+        for (uint32_t u : topo) {
+            if (!reached[u]) continue;
+            for (uint32_t c = F.univ_cell_off[u]; c < F.univ_cell_off[u + 1]; c++) {
+                Box b = clip_cell(c, ext[u]);
+                cbox[c] = b;
+                if (b.is_empty() || F.cell_fill[c] >= 0) continue;
+                uint32_t du = (uint32_t)(-(int64_t)F.cell_fill[c] - 1);
+                Box local = b;
+                for (int k = 0; k < 3; k++) {
+                    local.lo[k] -= F.cell_trans[3 * (size_t)c + k];
+                    local.hi[k] += -F.cell_trans[3 * (size_t)c + k];
+                }
+                local.widen(delta);
+                ext[du].grow(local);
+                reached[du] = 1;
+            }
+        }
+        return GT_OK;
+    }
+
+    struct Item { uint32_t cell; Box b; double c[3]; };
+
+    uint32_t build_node(std::vector<Item> &it, size_t b0, size_t b1) {
+        uint32_t idx = (uint32_t)n64.size();
+        n64.emplace_back();
+        Box bb = Box::empty();
+        for (size_t i = b0; i < b1; i++) bb.grow(it[i].b);
+        size_t n = b1 - b0;
+        uint32_t leafv = kLeafNone;
+        if (n <= kLeafMax) {
+            leafv = ((uint32_t)leaf.size() << 4) | (uint32_t)(n - 1);
+            for (size_t i = b0; i < b1; i++) leaf.push_back(it[i].cell);
+        } else {
+            // surface-area heuristic, three equally spaced candidates per axis
+            double best = INFINITY;
+            int bax = -1;
+            double bplane = 0;
+            for (int ax = 0; ax < 3; ax++) {
+                double cmin = INFINITY, cmax = -INFINITY;
+                for (size_t i = b0; i < b1; i++) { cmin = std::min(cmin, it[i].c[ax]); cmax = std::max(cmax, it[i].c[ax]); }
+                if (!(cmax > cmin)) continue;
+                for (int k = 1; k <= 3; k++) {
+                    double plane = cmin + (cmax - cmin) * (double)k / 4.0;
+                    Box L = Box::empty(), R = Box::empty();
+                    size_t nl = 0;
+                    for (size_t i = b0; i < b1; i++) {
+                        if (it[i].c[ax] < plane) { L.grow(it[i].b); nl++; }
+                        else R.grow(it[i].b);
+                    }
+                    if (nl == 0 || nl == n) continue;
+                    double cost = (double)nl * L.area() + (double)(n - nl) * R.area();
+                    if (cost < best) { best = cost; bax = ax; bplane = plane; }
+                }
+            }
+            size_t mid;
+            if (bax >= 0) {
+                auto m = std::stable_partition(it.begin() + b0, it.begin() + b1,
+                                               [&](const Item &x) { return x.c[bax] < bplane; });
+                mid = (size_t)(m - it.begin());
+            } else {   // all centres coincide: split the list in two
+                mid = b0 + n / 2;
+            }
+            build_node(it, b0, mid);
+            build_node(it, mid, b1);
+        }
+        Node64 &nd = n64[idx];
+        for (int k = 0; k < 3; k++) { nd.lo[k] = bb.lo[k]; nd.hi[k] = bb.hi[k]; }
+        nd.leaf = leafv;
+        nd.escape = (uint32_t)n64.size();
+        nd.pad[0] = nd.pad[1] = 0;
+        return idx;
+    }
+
+    int hierarchies() {
+        const gt_flat_geometry &F = *f;
+        univ.assign(F.n_universes, Univ{});
+        for (uint32_t u = 0; u < F.n_universes; u++) {
+            Univ &U = univ[u];
+            U.cell0 = F.univ_cell_off[u];
+            U.ncell = F.univ_cell_off[u + 1] - F.univ_cell_off[u];
+            U.node0 = (uint32_t)n64.size();
+            U.nnode = 0;
+            U.hint = kHintNone;
+            if (F.lattice_hint && F.lattice_hint[8 * (size_t)u] == 1) {
+                const double *h = F.lattice_hint + 8 * (size_t)u;
+                U.hint = kHintSquare;
+                U.nx = (int32_t)h[1];
+                U.ny = (int32_t)h[2];
+                U.x0 = (float)h[3];
+                U.y0 = (float)h[4];
+                U.inv_px = (float)(1.0 / h[5]);
+                U.inv_py = (float)(1.0 / h[6]);
+            }
+            if (!reached[u]) continue;
+            std::vector<Item> items;
+            for (uint32_t c = U.cell0; c < U.cell0 + U.ncell; c++) {
+                if (cbox[c].is_empty()) continue;
+                Item x;
+                x.cell = c;
+                x.b = cbox[c];
+                for (int k = 0; k < 3; k++) x.c[k] = 0.5 * (x.b.lo[k] + x.b.hi[k]);
+                items.push_back(x);
+            }
+            if (items.empty()) continue;
+            build_node(items, 0, items.size());
+            U.nnode = (uint32_t)n64.size() - U.node0;
+        }
+        if (leaf.size() >= (1u << 28)) return set_error("too many leaf entries"), GT_ECAPACITY;
+        n32.resize(n64.size());
+        for (size_t i = 0; i < n64.size(); i++) {
+            for (int k = 0; k < 3; k++) { n32[i].lo[k] = round_down(n64[i].lo[k]); n32[i].hi[k] = round_up(n64[i].hi[k]); }
+            n32[i].escape = n64[i].escape;
+            n32[i].leaf = n64[i].leaf;
+        }
+        return GT_OK;
+    }
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+}  // namespace gt
+
+using namespace gt;
+
+extern "C" const char *gt_last_error(void) { return g_err; }
+
+extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) {
+    if (!f || !out) return set_error("gt_geometry_create: null argument"), GT_EINVAL;
+    *out = nullptr;
+    try {
+        Builder B;
+        B.f = f;
+        int rc = B.validate();
+        if (rc) return rc;
+        rc = B.boxes();
+        if (rc) return rc;
+        rc = B.hierarchies();
+        if (rc) return rc;
+        const gt_flat_geometry &F = *f;
+        // host images of every table
+        std::vector<double> coef(4 * (size_t)F.n_surfaces, 0.0);
+        for (uint32_t s = 0; s < F.n_surfaces; s++) {
+            const double *q = F.surf_coef + 8 * (size_t)s;
+            double *o = &coef[4 * (size_t)s];
+            switch (F.surf_type[s]) {
+            case ST_PX: case ST_PY: case ST_PZ: o[0] = q[0]; break;
+            case ST_P: o[0] = q[0]; o[1] = q[1]; o[2] = q[2]; o[3] = q[3]; break;
+            case ST_CZ: o[0] = q[0]; o[1] = q[1]; o[2] = q[2]; break;
+            default: o[0] = q[0]; o[1] = q[1]; o[2] = q[2]; o[3] = q[3]; break;
+            }
+        }
+        std::vector<uint32_t> hs(F.n_halfspaces);
+        for (uint32_t k = 0; k < F.n_halfspaces; k++) {
+            uint32_t s = B.surf_of(F.hs[k]);
+            hs[k] = hs_pack(s, F.hs[k] > 0, F.surf_type[s]);
+        }
+        std::vector<Cell> cell(F.n_cells);
+        std::vector<double> trans(4 * (size_t)F.n_cells, 0.0);
+        std::vector<float> cb(8 * (size_t)F.n_cells, 0.0f);
+        for (uint32_t c = 0; c < F.n_cells; c++) {
+            cell[c].hs_off = F.cell_hs_off[c];
+            cell[c].hs_n = F.cell_hs_off[c + 1] - F.cell_hs_off[c];
+            cell[c].fill = F.cell_fill[c];
+            cell[c].inst_off = (uint32_t)B.inst_off[c];
+            for (int k = 0; k < 3; k++) trans[4 * (size_t)c + k] = F.cell_trans[3 * (size_t)c + k];
+            const Box &b = B.cbox[c];
+            for (int k = 0; k < 3; k++) {
+                cb[8 * (size_t)c + k] = b.is_empty() ? INFINITY : round_down(b.lo[k]);
+                cb[8 * (size_t)c + 4 + k] = b.is_empty() ? -INFINITY : round_up(b.hi[k]);
+            }
+        }
+        // one blob
+        size_t off[10], sz[10];
+        sz[0] = coef.size() * 8;
+        sz[1] = hs.size() * 4;
+        sz[2] = cell.size() * sizeof(Cell);
+        sz[3] = trans.size() * 8;
+        sz[4] = B.univ.size() * sizeof(Univ);
+        sz[5] = B.n32.size() * sizeof(Node32);
+        sz[6] = B.n64.size() * sizeof(Node64);
+        sz[7] = B.leaf.size() * 4;
+        sz[8] = cb.size() * 4;
+        sz[9] = (size_t)F.n_materials * 8;
+        size_t total = 0;
+        for (int i = 0; i < 10; i++) { off[i] = total; total = align_up(total + std::max(sz[i], (size_t)1)); }
+        std::vector<unsigned char> img(total, 0);
+        const void *src[10] = {coef.data(), hs.data(), cell.data(), trans.data(), B.univ.data(),
+                               B.n32.data(), B.n64.data(), B.leaf.data(), cb.data(), F.sigma_t};
+        for (int i = 0; i < 10; i++)
+            if (sz[i]) std::memcpy(img.data() + off[i], src[i], sz[i]);
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return set_error("hipGetDevice failed"), GT_EHIP;
+        void *blob = nullptr;
+        hipError_t e = hipMalloc(&blob, total);
+        if (e != hipSuccess) return set_error("hipMalloc(%zu): %s", total, hipGetErrorString(e)), GT_ENOMEM;
+        e = hipMemcpy(blob, img.data(), total, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(blob);
+            return set_error("hipMemcpy: %s", hipGetErrorString(e)), GT_EHIP;
+        }
+        gt_geometry *g = new gt_geometry;
+        unsigned char *base = (unsigned char *)blob;
+        g->dev.coef = (const double *)(base + off[0]);
+        g->dev.hs = (const uint32_t *)(base + off[1]);
+        g->dev.cell = (const Cell *)(base + off[2]);
+        g->dev.trans = (const double *)(base + off[3]);
+        g->dev.univ = (const Univ *)(base + off[4]);
+        g->dev.node32 = (const Node32 *)(base + off[5]);
+        g->dev.node64 = (const Node64 *)(base + off[6]);
+        g->dev.leaf = (const uint32_t *)(base + off[7]);
+        g->dev.cbox = (const float *)(base + off[8]);
+        g->dev.sigma = (const double *)(base + off[9]);
+        g->dev.root = F.root;
+        g->dev.n_inst = (uint32_t)B.ninst[F.root];
+        g->dev.max_depth = B.depth[F.root];
+        g->dev.n_cells = F.n_cells;
+        for (int k = 0; k < 3; k++) { g->dev.lo[k] = F.domain_lo[k]; g->dev.hi[k] = F.domain_hi[k]; }
+        g->blob = blob;
+        g->blob_bytes = total;
+        g->n_inst = B.ninst[F.root];
+        g->max_depth = B.depth[F.root];
+        g->device = dev;
+        *out = g;
+        return GT_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error("host allocation failed"), GT_ENOMEM;
+    } catch (...) {
+        return set_error("unexpected exception in gt_geometry_create"), GT_EINVAL;
+    }
+}
+
+extern "C" int gt_geometry_info(const gt_geometry *g, uint64_t *n_instances, uint32_t *max_depth,
+                                uint64_t *device_bytes) {
+    if (!g) return set_error("gt_geometry_info: null geometry"), GT_EINVAL;
+    if (n_instances) *n_instances = g->n_inst;
+    if (max_depth) *max_depth = g->max_depth;
+    if (device_bytes) *device_bytes = g->blob_bytes;
+    return GT_OK;
+}
+
+extern "C" void gt_geometry_destroy(gt_geometry *g) {
+    if (!g) return;
+    int cur = 0;
+    bool switched = hipGetDevice(&cur) == hipSuccess && cur != g->device && hipSetDevice(g->device) == hipSuccess;
+    (void)hipFree(g->blob);
+    if (switched) (void)hipSetDevice(cur);
+    delete g;
+}
+
+extern "C" int gt_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream) {
+    if (!g || !p || !o) return set_error("gt_track: null argument"), GT_EINVAL;
+    if (!o->tally_fx || !o->counters) return set_error("gt_track: tally_fx and counters are required"), GT_EINVAL;
+    if (p->max_collisions < 1) return set_error("gt_track: max_collisions must be >= 1"), GT_EINVAL;
+    if (p->max_segments < 1) return set_error("gt_track: max_segments must be >= 1"), GT_EINVAL;
+    if (p->precision > GT_PREC_MIXED) return set_error("gt_track: unknown precision %u", p->precision), GT_EINVAL;
+    if (p->source > 1) return set_error("gt_track: unknown source %u", p->source), GT_EINVAL;
+    if (p->source == 1 && p->ray_n1 < 1) return set_error("gt_track: ray source needs ray_n1 >= 1"), GT_EINVAL;
+    if (p->record_first_k && (!o->rec || p->record_cap < 1))
+        return set_error("gt_track: recording needs rec and record_cap >= 1"), GT_EINVAL;
+    if (p->flags & ~GT_FLAG_ACCUMULATE) return set_error("gt_track: unknown flags 0x%x", p->flags), GT_EINVAL;
+    if (p->block_size && (p->block_size % 64 || p->block_size > 1024))
+        return set_error("gt_track: block_size must be a multiple of 64 up to 1024"), GT_EINVAL;
+    if (p->first_particle + p->n_particles < p->first_particle)
+        return set_error("gt_track: particle id range overflows"), GT_EINVAL;
+    if ((uint64_t)p->record_first_k * p->record_cap > (1ull << 40))
+        return set_error("gt_track: record buffer too large"), GT_ECAPACITY;
+    return launch_track(g, p, o, stream);
+}
+
+extern "C" int gt_find_cell(const gt_geometry *g, const double *pos, uint64_t n, int64_t *inst, int32_t *cells,
+                            uint32_t precision, void *stream) {
+    if (!g || (n && (!pos || !inst))) return set_error("gt_find_cell: null argument"), GT_EINVAL;
+    if (precision > GT_PREC_MIXED) return set_error("gt_find_cell: unknown precision %u", precision), GT_EINVAL;
+    return launch_find_cell(g, pos, n, inst, cells, precision, stream);
+}
+
+extern "C" int gt_distance_to_surface(const gt_geometry *g, const double *pos, const double *dir, uint64_t n,
+                                      double *dist, int32_t *level, int32_t *surf, void *stream) {
+    if (!g || (n && (!pos || !dir || !dist || !level || !surf)))
+        return set_error("gt_distance_to_surface: null argument"), GT_EINVAL;
+    return launch_distance(g, pos, dir, n, dist, level, surf, stream);
+}
+
+extern "C" int gt_fp64_check(const double *a, const double *b, uint64_t n, double *quot, double *root, double *logb,
+                             void *stream) {
+    if (n && (!a || !b || !quot || !root || !logb)) return set_error("gt_fp64_check: null argument"), GT_EINVAL;
+    return launch_fp64_check(a, b, n, quot, root, logb, stream);
+}

@@ -1,0 +1,111 @@
+// Internal layout of the device geometry tables and kernel launch records.
+// Shared by the host preprocessor (gt_geometry.cpp) and the HIP kernels
+// (gt_track.hip); not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gt.h"
+
+namespace gt {
+
+enum SurfType : uint32_t { ST_PX = 0, ST_PY = 1, ST_PZ = 2, ST_P = 3, ST_CZ = 4, ST_SPH = 5 };
+
+// packed half-space: surface id << 4 | positive-side bit << 3 | surface type
+__host__ __device__ inline uint32_t hs_pack(uint32_t s, bool pos, uint32_t type) {
+    return (s << 4) | ((pos ? 1u : 0u) << 3) | type;
+}
+
+constexpr uint32_t kLeafNone = 0xFFFFFFFFu;
+constexpr uint32_t kLeafMax = 4;       // cells per BVH leaf
+constexpr uint32_t kHintNone = 0, kHintSquare = 1;
+
+// 16 bytes per cell
+struct alignas(16) Cell {
+    uint32_t hs_off;    // first packed half-space
+    uint32_t hs_n;      // number of half-spaces
+    int32_t fill;       // >= 0 material, < 0 daughter universe -(u+1)
+    uint32_t inst_off;  // leaf-instance offset of this cell within its universe
+};
+
+// 48 bytes per universe
+struct alignas(16) Univ {
+    uint32_t cell0, ncell;   // cell range
+    uint32_t node0, nnode;   // BVH nodes in depth-first order; nnode == 0: no cell reachable
+    int32_t hint, nx, ny, pad;
+    float x0, y0, inv_px, inv_py;   // lattice guess (single precision, advisory)
+};
+
+// BVH node with single-precision, outward-rounded bounds (32 bytes).  Nodes
+// are stored depth-first; an internal node's first child follows it, and
+// `escape` is the next node to visit when the point is outside the node
+// (or after a leaf has been searched).  leaf == kLeafNone for internal
+// nodes, else first << 4 | (count - 1) into the leaf-cell array.
+struct alignas(32) Node32 {
+    float lo[3];
+    uint32_t escape;
+    float hi[3];
+    uint32_t leaf;
+};
+
+// The same hierarchy with double-precision widened bounds (64 bytes).
+struct alignas(64) Node64 {
+    double lo[3];
+    uint32_t escape, leaf;
+    double hi[3];
+    uint32_t pad[2];
+};
+
+// Device view of one geometry (passed by value to kernels).
+struct Dev {
+    const double *coef;     // 4 per surface (see gt.h, first four slots)
+    const uint32_t *hs;     // packed half-spaces
+    const Cell *cell;
+    const double *trans;    // 4 per cell: x, y, z, 0
+    const Univ *univ;
+    const Node32 *node32;
+    const Node64 *node64;
+    const uint32_t *leaf;   // leaf cell ids
+    const float *cbox;      // 8 per cell: lo xyz, 0, hi xyz, 0 (single precision, outward)
+    const double *sigma;
+    uint32_t root, n_inst, max_depth, n_cells;
+    double lo[3], hi[3];
+};
+
+struct KParams {
+    uint64_t seed, first, n;
+    uint32_t geom_id, max_coll, source, ray_n1, max_segs, rec_k, rec_cap, pad;
+};
+
+struct KOut {
+    uint64_t *tally_fx;
+    uint32_t *seg_count;
+    uint64_t *seq_hash;
+    uint8_t *end_code;
+    int32_t *rec;
+    uint64_t *counters;
+};
+
+}  // namespace gt
+
+// host-side geometry object behind the opaque ABI handle
+struct gt_geometry {
+    gt::Dev dev;
+    void *blob;          // one device allocation holding every table
+    uint64_t blob_bytes;
+    uint64_t n_inst;
+    uint32_t max_depth;
+    int device;
+};
+
+namespace gt {
+void set_error(const char *fmt, ...);
+int launch_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream);
+int launch_find_cell(const gt_geometry *g, const double *pos, uint64_t n, int64_t *inst, int32_t *cells,
+                     uint32_t precision, void *stream);
+int launch_distance(const gt_geometry *g, const double *pos, const double *dir, uint64_t n, double *dist,
+                    int32_t *level, int32_t *surf, void *stream);
+int launch_fp64_check(const double *a, const double *b, uint64_t n, double *q, double *r, double *l,
+                      void *stream);
+}  // namespace gt

@@ -1,0 +1,237 @@
+"""Python binding of libgt.so (the C ABI declared in include/gt.h).
+
+Argument marshalling only: every step of the tracking runs in the HIP
+kernels of the library.  PyTorch supplies device memory and the stream.
+There is no fallback: if the library is not built, or there is no GPU, the
+calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgt.so")
+
+GT_OK, GT_EINVAL, GT_EGEOM, GT_ENOMEM, GT_EHIP, GT_ECAPACITY = 0, -1, -2, -3, -4, -5
+MAX_LEVELS = 6
+PREC_FP64, PREC_MIXED = 0, 1
+FLAG_ACCUMULATE = 1
+END_NONE, END_ESCAPE, END_CAP, END_LOST, END_SEGCAP = 0, 1, 2, 3, 4
+COUNTERS = ("escaped", "capped", "lost", "segcap", "rec_overflow", "segments", "rejected", "spare")
+
+
+class GtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("libgt error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Flat(C.Structure):
+    _fields_ = [
+        ("n_surfaces", C.c_uint32), ("n_cells", C.c_uint32), ("n_universes", C.c_uint32),
+        ("n_materials", C.c_uint32), ("n_halfspaces", C.c_uint32), ("root", C.c_uint32),
+        ("surf_type", C.c_void_p), ("surf_coef", C.c_void_p), ("cell_hs_off", C.c_void_p),
+        ("hs", C.c_void_p), ("cell_fill", C.c_void_p), ("cell_trans", C.c_void_p),
+        ("univ_cell_off", C.c_void_p), ("lattice_hint", C.c_void_p), ("sigma_t", C.c_void_p),
+        ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3),
+    ]
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("seed", C.c_uint64), ("first_particle", C.c_uint64), ("n_particles", C.c_uint64),
+        ("geometry_id", C.c_uint32), ("max_collisions", C.c_uint32), ("source", C.c_uint32),
+        ("ray_n1", C.c_uint32), ("max_segments", C.c_uint32), ("precision", C.c_uint32),
+        ("record_first_k", C.c_uint32), ("record_cap", C.c_uint32), ("flags", C.c_uint32),
+        ("block_size", C.c_uint32),
+    ]
+
+
+class _Out(C.Structure):
+    _fields_ = [
+        ("tally_fx", C.c_void_p), ("tally", C.c_void_p), ("seg_count", C.c_void_p),
+        ("seq_hash", C.c_void_p), ("end_code", C.c_void_p), ("rec", C.c_void_p), ("counters", C.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libgt.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgt.so is not built (run paper_2406_13849_amd/build.py or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, u64, u32, i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int
+        L.gt_geometry_create.argtypes = [C.POINTER(_Flat), C.POINTER(vp)]
+        L.gt_geometry_create.restype = i32
+        L.gt_geometry_info.argtypes = [vp, C.POINTER(u64), C.POINTER(u32), C.POINTER(u64)]
+        L.gt_geometry_info.restype = i32
+        L.gt_geometry_destroy.argtypes = [vp]
+        L.gt_geometry_destroy.restype = None
+        L.gt_track.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), vp]
+        L.gt_track.restype = i32
+        L.gt_find_cell.argtypes = [vp, vp, u64, vp, vp, u32, vp]
+        L.gt_find_cell.restype = i32
+        L.gt_distance_to_surface.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp]
+        L.gt_distance_to_surface.restype = i32
+        L.gt_fp64_check.argtypes = [vp, vp, u64, vp, vp, vp, vp]
+        L.gt_fp64_check.restype = i32
+        L.gt_last_error.argtypes = []
+        L.gt_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != GT_OK:
+        raise GtError(rc, (lib().gt_last_error() or b"").decode())
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def flat_struct(g, keep: list) -> _Flat:
+    """Marshal a FlatGeometry (numpy arrays) into the ABI struct; `keep`
+    holds the contiguous arrays alive for the duration of the call."""
+    arrs = [np.ascontiguousarray(g.surf_type, np.uint8), np.ascontiguousarray(g.surf_coef, np.float64),
+            np.ascontiguousarray(g.cell_hs_off, np.uint32), np.ascontiguousarray(g.hs, np.int32),
+            np.ascontiguousarray(g.cell_fill, np.int32), np.ascontiguousarray(g.cell_trans, np.float64),
+            np.ascontiguousarray(g.univ_cell_off, np.uint32),
+            None if g.lattice_hint is None else np.ascontiguousarray(g.lattice_hint, np.float64),
+            np.ascontiguousarray(g.sigma_t, np.float64)]
+    keep.extend(arrs)
+    st, sc, ho, hs, cf, ct, uo, lh, sg = arrs
+
+    def p(a):
+        return None if a is None or a.size == 0 else a.ctypes.data
+
+    f = _Flat(n_surfaces=st.shape[0], n_cells=cf.shape[0], n_universes=uo.shape[0] - 1, n_materials=sg.shape[0],
+              n_halfspaces=hs.shape[0], root=int(g.root), surf_type=p(st), surf_coef=p(sc), cell_hs_off=p(ho),
+              hs=p(hs), cell_fill=p(cf), cell_trans=p(ct), univ_cell_off=p(uo), lattice_hint=p(lh), sigma_t=p(sg))
+    f.domain_lo[:] = [float(v) for v in g.domain_lo]
+    f.domain_hi[:] = [float(v) for v in g.domain_hi]
+    return f
+
+
+class Geometry:
+    """A flattened geometry uploaded to the current HIP device."""
+
+    def __init__(self, g):
+        keep: list = []
+        f = flat_struct(g, keep)
+        h = C.c_void_p()
+        _check(lib().gt_geometry_create(C.byref(f), C.byref(h)))
+        self.h = h
+        ni, md, nb = C.c_uint64(), C.c_uint32(), C.c_uint64()
+        _check(lib().gt_geometry_info(h, C.byref(ni), C.byref(md), C.byref(nb)))
+        self.n_instances = int(ni.value)
+        self.max_depth = int(md.value)
+        self.device_bytes = int(nb.value)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.gt_geometry_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+@dataclass
+class TrackOutputs:
+    """Device tensors written by gt_track (int64 tensors hold uint64 bits)."""
+    tally_fx: "object"    # int64 [n_inst, 2]
+    tally: "object"       # float64 [n_inst]
+    seg_count: "object"   # int32 [n]
+    seq_hash: "object"    # int64 [n]
+    end_code: "object"    # uint8 [n]
+    rec: "object"         # int32 [k, cap] or None
+    counters: "object"    # int64 [8]
+
+    def counters_dict(self) -> dict:
+        c = self.counters.cpu().numpy().view(np.uint64)
+        return {k: int(v) for k, v in zip(COUNTERS, c)}
+
+
+def alloc_outputs(geom: Geometry, n: int, record_first_k: int = 0, record_cap: int = 0, device="cuda",
+                  per_particle: bool = True) -> TrackOutputs:
+    import torch
+    ni = geom.n_instances
+    return TrackOutputs(
+        tally_fx=torch.zeros((ni, 2), dtype=torch.int64, device=device),
+        tally=torch.zeros(ni, dtype=torch.float64, device=device),
+        seg_count=torch.zeros(n, dtype=torch.int32, device=device) if per_particle else None,
+        seq_hash=torch.zeros(n, dtype=torch.int64, device=device) if per_particle else None,
+        end_code=torch.zeros(n, dtype=torch.uint8, device=device) if per_particle else None,
+        rec=torch.full((record_first_k, record_cap), -1, dtype=torch.int32, device=device)
+        if record_first_k else None,
+        counters=torch.zeros(8, dtype=torch.int64, device=device),
+    )
+
+
+def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 0, geometry_id: int = 0,
+          max_collisions: int = 20, source: int = 0, ray_n1: int = 0, max_segments: int = 100_000,
+          precision: int = PREC_MIXED, record_first_k: int = 0, record_cap: int = 0, accumulate: bool = False,
+          block_size: int = 0, out: Optional[TrackOutputs] = None, stream=None) -> TrackOutputs:
+    """gt_track: sample and track n_particles histories (asynchronous)."""
+    if out is None:
+        out = alloc_outputs(geom, n_particles, record_first_k, record_cap)
+    prm = _Params(seed=seed, first_particle=first_particle, n_particles=n_particles, geometry_id=geometry_id,
+                  max_collisions=max_collisions, source=source, ray_n1=ray_n1, max_segments=max_segments,
+                  precision=precision, record_first_k=record_first_k, record_cap=record_cap,
+                  flags=FLAG_ACCUMULATE if accumulate else 0, block_size=block_size)
+    o = _Out(tally_fx=_ptr(out.tally_fx), tally=_ptr(out.tally), seg_count=_ptr(out.seg_count),
+             seq_hash=_ptr(out.seq_hash), end_code=_ptr(out.end_code), rec=_ptr(out.rec),
+             counters=_ptr(out.counters))
+    _check(lib().gt_track(geom.h, C.byref(prm), C.byref(o), _stream(stream)))
+    return out
+
+
+def find_cell(geom: Geometry, pos, precision: int = PREC_MIXED, stream=None):
+    """gt_find_cell on a device tensor pos [n, 3] float64."""
+    import torch
+    n = pos.shape[0]
+    inst = torch.empty(n, dtype=torch.int64, device=pos.device)
+    cells = torch.empty((n, MAX_LEVELS), dtype=torch.int32, device=pos.device)
+    _check(lib().gt_find_cell(geom.h, _ptr(pos), n, _ptr(inst), _ptr(cells), precision, _stream(stream)))
+    return inst, cells
+
+
+def distance_to_surface(geom: Geometry, pos, dirs, stream=None):
+    """gt_distance_to_surface on device tensors pos, dirs [n, 3] float64."""
+    import torch
+    n = pos.shape[0]
+    dist = torch.empty(n, dtype=torch.float64, device=pos.device)
+    lev = torch.empty(n, dtype=torch.int32, device=pos.device)
+    srf = torch.empty(n, dtype=torch.int32, device=pos.device)
+    _check(lib().gt_distance_to_surface(geom.h, _ptr(pos), _ptr(dirs), n, _ptr(dist), _ptr(lev), _ptr(srf),
+                                        _stream(stream)))
+    return dist, lev, srf
+
+
+def fp64_check(a, b, stream=None):
+    """gt_fp64_check: device a/b, sqrt(b) and the library logarithm of b."""
+    import torch
+    n = a.shape[0]
+    q = torch.empty_like(a)
+    r = torch.empty_like(a)
+    lg = torch.empty_like(a)
+    _check(lib().gt_fp64_check(_ptr(a), _ptr(b), n, _ptr(q), _ptr(r), _ptr(lg), _stream(stream)))
+    return q, r, lg

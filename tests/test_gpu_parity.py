@@ -1,0 +1,235 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bar: per-particle segment counts, sequence hashes, end codes and recorded
+cell sequences identical; fixed-point tallies bit-identical; finalized
+tallies within 1e-12 relative of the oracle's Neumaier sums (exactly 0 where
+the oracle's is 0); counters identical.  Both precision modes.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_13849_amd import gt, synth
+
+pytestmark = pytest.mark.gpu
+
+NT = min(16, os.cpu_count() or 1)
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    gt.lib()
+    yield
+
+
+def _np(t):
+    return None if t is None else t.cpu().numpy()
+
+
+def gpu_track(geom, **kw):
+    import torch
+    out = gt.track(geom, **kw)
+    torch.cuda.synchronize()
+    return dict(tally_fx=_np(out.tally_fx).view(np.uint64), tally=_np(out.tally),
+                seg_count=_np(out.seg_count).view(np.uint32), seq_hash=_np(out.seq_hash).view(np.uint64),
+                end_code=_np(out.end_code), rec=_np(out.rec), counters=out.counters_dict())
+
+
+def assert_parity(g, o, check_tally=True, where=""):
+    first_bad = np.nonzero((g["seq_hash"] != o.seq_hash) | (g["seg_count"] != o.seg_count) |
+                           (g["end_code"] != o.end_code))[0]
+    assert first_bad.size == 0, "%s: %d particles differ, first %s" % (where, first_bad.size, first_bad[:5])
+    if o.rec is not None:
+        assert np.array_equal(g["rec"], o.rec), where
+    for k in ("escaped", "capped", "lost", "segcap", "rec_overflow", "segments", "rejected"):
+        assert g["counters"][k] == o.counters[k], (where, k, g["counters"][k], o.counters[k])
+    if check_tally:
+        assert np.array_equal(g["tally_fx"], o.tally_fx), where
+        zero = o.tally == 0
+        assert np.all(g["tally"][zero] == 0), where
+        rel = np.abs(g["tally"][~zero] - o.tally[~zero]) / np.abs(o.tally[~zero])
+        assert rel.size == 0 or rel.max() <= TOL, (where, rel.max())
+        assert np.array_equal(g["tally"], o.tally_fxd), where
+
+
+_geoms = {}
+
+
+def geoms(cfg):
+    if cfg not in _geoms:
+        fg = synth.make_config(cfg) if isinstance(cfg, int) else getattr(synth, cfg)()
+        _geoms[cfg] = (fg, gt.Geometry(fg), oracle.OracleGeometry(fg))
+    return _geoms[cfg]
+
+
+# ---------------------------------------------------------------- FP contract
+def test_fp64_division_sqrt_log_bit_exact():
+    import torch
+    rng = np.random.default_rng(0)
+    a = np.concatenate([rng.normal(size=200_000) * 10.0 ** rng.integers(-30, 30, 200_000),
+                        [1.0, -1.0, 3.0, 1e-310, 5e-324, 1e300]])
+    b = np.concatenate([np.abs(rng.normal(size=200_000)) * 10.0 ** rng.integers(-30, 30, 200_000),
+                        [3.0, 7.0, 1e-300, 2.0, 1e-320, 3e-10]])
+    u = rng.random(200_000)
+    q, r, lg = gt.fp64_check(torch.tensor(a, device="cuda"), torch.tensor(b, device="cuda"))
+    qq, rr, _ = (x.cpu().numpy() for x in (q, r, lg))
+    assert np.array_equal(qq.view(np.int64), (a / b).view(np.int64))
+    assert np.array_equal(rr.view(np.int64), np.sqrt(b).view(np.int64))
+    _, _, lg = gt.fp64_check(torch.tensor(u, device="cuda"), torch.tensor(u, device="cuda"))
+    assert np.array_equal(lg.cpu().numpy().view(np.int64), oracle.mc_log(u).view(np.int64))
+
+
+# ---------------------------------------------------------------- Table 1 ops
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+@pytest.mark.parametrize("prec", [gt.PREC_FP64, gt.PREC_MIXED])
+def test_find_cell_parity(cfg, prec):
+    import torch
+    fg, G, O = geoms(cfg)
+    rng = np.random.default_rng(10 + cfg)
+    lo, hi = fg.domain_lo, fg.domain_hi
+    w = hi - lo
+    pts = rng.uniform(lo - 0.02 * w, hi + 0.02 * w, size=(50_000, 3))
+    inst, cells = gt.find_cell(G, torch.tensor(pts, device="cuda"), prec)
+    oi, oc = O.find_cell(pts)
+    assert np.array_equal(inst.cpu().numpy(), oi)
+    assert np.array_equal(cells.cpu().numpy(), oc[:, :gt.MAX_LEVELS])
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_distance_parity(cfg):
+    import torch
+    fg, G, O = geoms(cfg)
+    rng = np.random.default_rng(20 + cfg)
+    pts = rng.uniform(fg.domain_lo, fg.domain_hi, size=(50_000, 3))
+    d = rng.normal(size=(50_000, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    dist, lev, srf = gt.distance_to_surface(G, torch.tensor(pts, device="cuda"), torch.tensor(d, device="cuda"))
+    od, ol, os_ = O.distance_to_surface(pts, d)
+    gd = dist.cpu().numpy()
+    assert np.array_equal(np.isnan(gd), np.isnan(od))
+    ok = ~np.isnan(od)
+    assert np.array_equal(gd[ok].view(np.int64), od[ok].view(np.int64))
+    assert np.array_equal(lev.cpu().numpy(), ol)
+    assert np.array_equal(srf.cpu().numpy(), os_)
+
+
+# ---------------------------------------------------------------- histories
+CASES = [
+    ("sphere", dict(seed=31, n_particles=20_000, geometry_id=9, max_collisions=3), 20_000, 64),
+    ("box", dict(seed=32, n_particles=20_000, geometry_id=8), 2000, 64),
+    (1, dict(seed=2001, n_particles=10_000, geometry_id=1), 10_000, 128),
+    (2, dict(seed=2002, n_particles=20_000, geometry_id=2), 2000, 512),
+    (3, dict(seed=2003, n_particles=4000, geometry_id=3), 1000, 1024),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[str(c[0]) for c in CASES])
+@pytest.mark.parametrize("prec", [gt.PREC_FP64, gt.PREC_MIXED])
+def test_track_parity(case, prec):
+    cfg, kw, k, cap = case
+    fg, G, O = geoms(cfg)
+    print("track parity", cfg, kw, "precision", prec, flush=True)
+    g = gpu_track(G, precision=prec, record_first_k=k, record_cap=cap, **kw)
+    o = oracle.track(O, oracle.TrackParams(record_first_k=k, record_cap=cap, **kw), n_threads=NT)
+    assert_parity(g, o, where="cfg %s prec %d" % (cfg, prec))
+
+
+@pytest.mark.parametrize("cfg,n1,n2", [(1, 3000, 1), (2, 1700, 22)])
+def test_ray_mode_parity(cfg, n1, n2):
+    fg, G, O = geoms(cfg)
+    kw = dict(seed=0, n_particles=n1 * n2, source=1, ray_n1=n1, max_collisions=1)
+    for prec in (gt.PREC_FP64, gt.PREC_MIXED):
+        g = gpu_track(G, precision=prec, **kw)
+        o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT)
+        assert_parity(g, o, where="rays cfg %d" % cfg)
+        assert g["counters"]["escaped"] == n1 * n2
+
+
+def test_edge_cases():
+    fg, G, O = geoms(2)
+    base = dict(seed=7, n_particles=3000, geometry_id=2)
+    for extra in (dict(max_segments=5), dict(max_collisions=1), dict(first_particle=123_456_789_012),
+                  dict(n_particles=1), dict(n_particles=65), dict(max_segments=1)):
+        kw = dict(base, **extra)
+        for prec in (gt.PREC_FP64, gt.PREC_MIXED):
+            g = gpu_track(G, precision=prec, record_first_k=70, record_cap=4, **kw)
+            o = oracle.track(O, oracle.TrackParams(record_first_k=70, record_cap=4, **kw), n_threads=NT)
+            assert_parity(g, o, where=str(extra))
+    # empty batch: tallies and counters zeroed, nothing else written
+    g = gpu_track(G, precision=gt.PREC_MIXED, seed=1, n_particles=0)
+    assert not g["tally_fx"].any() and sum(g["counters"].values()) == 0
+
+
+@pytest.mark.parametrize("block", [64, 128, 192])
+def test_block_sizes_do_not_change_results(block):
+    fg, G, O = geoms(2)
+    kw = dict(seed=2002, n_particles=5000, geometry_id=2)
+    g = gpu_track(G, precision=gt.PREC_MIXED, block_size=block, **kw)
+    o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT)
+    assert_parity(g, o, where="block %d" % block)
+
+
+def test_accumulate_two_halves():
+    import torch
+    fg, G, O = geoms(1)
+    out = gt.alloc_outputs(G, 4000)
+    gt.track(G, seed=9, n_particles=4000, geometry_id=1, out=out)
+    out2 = gt.alloc_outputs(G, 6000)
+    out2.tally_fx.copy_(out.tally_fx)
+    gt.track(G, seed=9, n_particles=6000, first_particle=4000, geometry_id=1, accumulate=True, out=out2)
+    torch.cuda.synchronize()
+    o = oracle.track(O, oracle.TrackParams(seed=9, n_particles=10_000, geometry_id=1), n_threads=NT)
+    assert np.array_equal(out2.tally_fx.cpu().numpy().view(np.uint64), o.tally_fx)
+    assert np.array_equal(out2.tally.cpu().numpy(), o.tally_fxd)
+
+
+def test_invalid_track_arguments():
+    fg, G, O = geoms(1)
+    with pytest.raises(gt.GtError) as e:
+        gt.track(G, seed=1, n_particles=10, max_collisions=0)
+    assert e.value.code == gt.GT_EINVAL
+    with pytest.raises(gt.GtError):
+        gt.track(G, seed=1, n_particles=10, precision=7)
+    with pytest.raises(gt.GtError):
+        gt.track(G, seed=1, n_particles=10, block_size=100)
+    with pytest.raises(gt.GtError):
+        gt.track(G, seed=1, n_particles=10, source=1, ray_n1=0)
+
+
+# ---------------------------------------------------------------- full size
+def test_full_size_cfg2_all_particles():
+    """The benchmark workload (17x17 two-level lattice, 1e6 histories, mixed
+    precision, default launch): every particle and every tally."""
+    fg, G, O = geoms(2)
+    kw = dict(seed=synth.particle_seed(2), n_particles=1_000_000, geometry_id=2)
+    print("cfg2 full size", flush=True)
+    g = gpu_track(G, precision=gt.PREC_MIXED, record_first_k=1000, record_cap=256, **kw)
+    o = oracle.track(O, oracle.TrackParams(record_first_k=1000, record_cap=256, **kw), n_threads=NT)
+    assert_parity(g, o, where="cfg2 full")
+
+
+def test_full_size_cfg3_sampled():
+    """Three-level core (2.86M tallies), 1e7 histories on the GPU; a random
+    sample of particles is re-run one by one in the oracle; counters add up."""
+    fg, G, O = geoms(3)
+    n = 10_000_000
+    print("cfg3 full size", flush=True)
+    g = gpu_track(G, precision=gt.PREC_MIXED, seed=synth.particle_seed(3), n_particles=n, geometry_id=3)
+    c = g["counters"]
+    assert c["escaped"] + c["capped"] + c["lost"] + c["segcap"] == n
+    assert c["segments"] == int(g["seg_count"].astype(np.int64).sum())
+    assert np.all(g["tally"] >= 0)
+    rng = np.random.default_rng(3)
+    ids = np.sort(rng.choice(n, size=300, replace=False))
+    for i in ids:
+        o = oracle.track(O, oracle.TrackParams(seed=synth.particle_seed(3), n_particles=1, first_particle=int(i),
+                                               geometry_id=3), n_threads=1, tallies=False)
+        assert g["seq_hash"][i] == o.seq_hash[0] and g["seg_count"][i] == o.seg_count[0], i
+        assert g["end_code"][i] == o.end_code[0]
