@@ -6,7 +6,9 @@ pin types, 12 materials, 12,716 leaf-instance tallies) with 1e6 toy-transport
 histories (uniform volume source, isotropic, at most 20 collisions), i.e.
 the second workload configuration.  Both precision modes are timed; `value`
 is the mixed-precision tracker (single-precision pruning, double-precision
-decisions), `fp64` the all-double tracker.  Inputs (the geometry tables) are
+decisions), `fp64` the all-double tracker on the same persistent schedule,
+`plain_fp64_lane_per_history` the plain all-double tracker with one history
+per lane (the baseline the mixed tracker must beat).  Inputs (the geometry tables) are
 resident in HBM before the timed region; a step is one gt_track call: zero
 the tallies, sample and track every history, write per-particle outputs,
 finalize the tallies.
@@ -42,13 +44,15 @@ def parse():
     ap.add_argument("--particles", type=int, default=1_000_000)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["mixed", "fp64"], default=None, help="time one mode only (profiling)")
+    ap.add_argument("--only", choices=["mixed", "fp64", "plain_fp64"], default=None,
+                    help="time one mode only (profiling)")
     return ap.parse_args()
 
 
-def timed(gt, G, out, args, prec):
+def timed(gt, G, out, args, prec, lane=False):
     import torch
-    kw = dict(seed=2002, n_particles=args.particles, geometry_id=2, precision=prec, block_size=args.block, out=out)
+    kw = dict(seed=2002, n_particles=args.particles, geometry_id=2, precision=prec, block_size=args.block, out=out,
+              lane_per_history=lane)
     for _ in range(args.warmup):
         gt.track(G, **kw)
     torch.cuda.synchronize()
@@ -86,9 +90,11 @@ def cpu_baseline(fg, gpu_out, n):
     nz = o.tally != 0
     g_t = gpu_out.tally.cpu().numpy()
     rel = float(np.max(np.abs(g_t[nz] - o.tally[nz]) / o.tally[nz])) if nz.any() else 0.0
+    # algorithmic double-precision operations per segment (work meter over a sample)
+    ops, segs = oracle.count_work(og, oracle.TrackParams(seed=2002, n_particles=min(n, 20_000), geometry_id=2))
     return dict(value=o.counters["segments"] / dt, unit="segments/s", cores=cores, kind="oracle",
                 sample="the whole workload (%d histories, %d segments), %.1f s" % (n, o.counters["segments"], dt),
-                parity=parity, max_tally_rel_err=rel)
+                parity=parity, max_tally_rel_err=rel, ops_per_segment=ops / segs)
 
 
 def main():
@@ -105,11 +111,11 @@ def main():
     n = args.particles
     out = gt.alloc_outputs(G, n)
     res = {}
-    modes = [("fp64", gt.PREC_FP64), ("mixed", gt.PREC_MIXED)]
+    modes = [("plain_fp64", gt.PREC_FP64, True), ("fp64", gt.PREC_FP64, False), ("mixed", gt.PREC_MIXED, False)]
     if args.only:
         modes = [m for m in modes if m[0] == args.only]
-    for name, prec in modes:
-        res[name] = timed(gt, G, out, args, prec)
+    for name, prec, lane in modes:
+        res[name] = timed(gt, G, out, args, prec, lane)
         print("# %s: %.3f ms/step, %d segments/step" % (name, sum(res[name]["ms"]) / args.steps,
                                                         res[name]["segments"]), file=sys.stderr, flush=True)
     head = res["mixed"] if "mixed" in res else res["fp64"]
@@ -132,16 +138,25 @@ def main():
                    "histories": n, "segments_per_step": head["segments"],
                    "precision": "mixed" if "mixed" in res else "fp64", "parallelism": "none (1 GPU)"},
     }
-    if "fp64" in res and "mixed" in res:
-        f = res["fp64"]
-        fms = sum(f["ms"]) / len(f["ms"])
-        line["fp64"] = {"value": f["segments"] / (fms * 1e-3), "ms_per_step": fms}
+    for name, label in (("fp64", "fp64"), ("plain_fp64", "plain_fp64_lane_per_history")):
+        if name in res:
+            f = res[name]
+            fms = sum(f["ms"]) / len(f["ms"])
+            line[label] = {"value": f["segments"] / (fms * 1e-3), "ms_per_step": fms}
+    if "mixed" in res and "fp64" in res:
         line["mixed_over_fp64"] = line["value"] / line["fp64"]["value"]
+    if "mixed" in res and "plain_fp64" in res:
+        line["mixed_over_plain_fp64"] = line["value"] / line["plain_fp64_lane_per_history"]["value"]
     if not args.no_cpu_baseline:
         cb = cpu_baseline(fg, out, n)
         line["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         line["parity"] = {"sequences_and_fixed_point_tallies_identical": cb["parity"],
                           "max_tally_rel_err": cb["max_tally_rel_err"]}
+        achieved = cb["ops_per_segment"] * seg_s
+        line["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
+                            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS, "traffic": None,
+                            "ops_per_segment": cb["ops_per_segment"],
+                            "kernel": "k_track_persistent (mixed precision)"}
     print(json.dumps(line), flush=True)
 
 

@@ -68,7 +68,8 @@ extern "C" {
 #define GT_END_LOST 3     /* no cell found below the root after a crossing    */
 #define GT_END_SEGCAP 4   /* reached max_segments                             */
 
-/* ---- counters (uint64 each, device array of 8) -------------------------- */
+/* ---- counters (uint64 each, device array of 8; counters[7] is the work-queue
+ *      position used by the persistent schedule) ---------------------------- */
 #define GT_CNT_ESCAPED 0
 #define GT_CNT_CAPPED 1
 #define GT_CNT_LOST 2
@@ -83,7 +84,10 @@ extern "C" {
                              decision still taken in double precision                   */
 
 /* ---- flags --------------------------------------------------------------- */
-#define GT_FLAG_ACCUMULATE 1u   /* add to tally_fx instead of zeroing it first */
+#define GT_FLAG_ACCUMULATE 1u          /* add to tally_fx instead of zeroing it first         */
+#define GT_FLAG_LANE_PER_HISTORY 2u    /* one history per lane, one launch slot per history
+                                          (the plain schedule) instead of the persistent,
+                                          refilling schedule                                */
 
 typedef struct gt_geometry gt_geometry;   /* opaque; owns its device tables */
 
@@ -154,8 +158,9 @@ typedef struct {
     uint32_t record_first_k;  /* particles [0, k) of the batch record their sequence */
     uint32_t record_cap;      /* entries recorded per particle                       */
     uint32_t flags;           /* GT_FLAG_*                                           */
-    uint32_t block_size;      /* threads per workgroup (64..1024, multiple of 64;
-                                 0 = library default)                                */
+    uint32_t block_size;      /* threads per workgroup, a multiple of 64: up to 1024
+                                 (persistent schedule, default 1024) or up to 256
+                                 (GT_FLAG_LANE_PER_HISTORY, default 256); 0 = default */
 } gt_track_params;
 
 /* Outputs, all device memory owned by the caller.

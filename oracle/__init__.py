@@ -109,6 +109,7 @@ def lib():
         L.or_mc_log.restype = C.c_double
         L.or_mc_log_batch.argtypes = [vp, u64, vp]
         L.or_fx_quantise.argtypes = [vp, u64, vp]
+        L.or_count_work.argtypes = [vp, C.POINTER(_Params), vp]
         _lib = L
     return _lib
 
@@ -279,6 +280,16 @@ def mc_log(x) -> np.ndarray:
     out = np.empty_like(x)
     lib().or_mc_log_batch(_p(x), x.shape[0], _p(out))
     return out
+
+
+def count_work(geom: OracleGeometry, p: TrackParams):
+    """Double-precision operations the method requires over the histories of
+    p (every distance evaluation, move, sample and one containment test per
+    located cell; not a linear scan's extra candidates) and the segments."""
+    out = np.zeros(2, np.uint64)
+    prm = p.c()
+    lib().or_count_work(geom.h, C.byref(prm), _p(out))
+    return int(out[0]), int(out[1])
 
 
 def fx_quantise(lengths) -> np.ndarray:

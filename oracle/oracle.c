@@ -49,6 +49,14 @@ enum { S_PX = 0, S_PY = 1, S_PZ = 2, S_P = 3, S_CZ = 4, S_SPH = 5 };
 enum { END_NONE = 0, END_ESCAPE = 1, END_CAP = 2, END_LOST = 3, END_SEGCAP = 4 };
 enum { C_ESCAPED = 0, C_CAPPED, C_LOST, C_SEGCAP, C_RECOVF, C_SEGMENTS, C_REJECTED, C_NC };
 
+/* Work meter (off unless or_count_work runs): counts the double-precision
+ * arithmetic operations (+ - * / sqrt; comparisons and sign flips excluded)
+ * that the method itself requires -- every distance evaluation of every
+ * level, the moves, the sampling, and one containment test of each cell
+ * that is located -- but not the extra candidates a linear scan tries. */
+static __thread uint64_t *meter;
+#define METER(n) do { if (meter) *meter += (uint64_t)(n); } while (0)
+
 /* ------------------------------------------------------------------ */
 /* input contract                                                      */
 /* ------------------------------------------------------------------ */
@@ -277,10 +285,27 @@ static int cell_contains(const or_geom *g, uint32_t c, const double p[3], int64_
     return 1;
 }
 
+static uint64_t surf_value_ops(int type) {
+    switch (type) {
+    case S_PX: case S_PY: case S_PZ: return 1;
+    case S_P: case S_CZ: return 6;
+    default: return 9;
+    }
+}
+
+/* operations of one containment test of cell c (forced surface free) */
+static void meter_verify(const or_geom *g, int64_t c, int64_t force_s) {
+    if (!meter || c < 0) return;
+    for (uint32_t k = g->hs_off[c]; k < g->hs_off[c + 1]; k++) {
+        int64_t s = abs(g->hs[k]) - 1;
+        if (s != force_s) *meter += surf_value_ops(g->stype[s]);
+    }
+}
+
 /* Alg. 3: first cell of universe u containing p, or -1. */
 static int64_t find_cell_in(const or_geom *g, uint32_t u, const double p[3]) {
     for (uint32_t c = g->uoff[u]; c < g->uoff[u + 1]; c++)
-        if (cell_contains(g, c, p, -1, 0)) return c;
+        if (cell_contains(g, c, p, -1, 0)) { meter_verify(g, c, -1); return c; }
     return -1;
 }
 
@@ -313,6 +338,7 @@ static int descend(const or_geom *g, ptl *t, int level, double q[3]) {
         uint32_t du = (uint32_t)(-g->fill[t->cell[L]] - 1);
         const double *tr = g->trans + 3 * (size_t)t->cell[L];
         q[0] = q[0] - tr[0]; q[1] = q[1] - tr[1]; q[2] = q[2] - tr[2];
+        METER(3);
         int64_t c = find_cell_in(g, du, q);
         if (c < 0) { t->depth = L + 1; return -1; }
         t->cell[++L] = c;
@@ -348,11 +374,12 @@ static double hs_distance(const or_geom *g, uint32_t s, int pos, const double q[
         case S_PX: den = u[0]; break;
         case S_PY: den = u[1]; break;
         case S_PZ: den = u[2]; break;
-        default:   den = (c[0] * u[0] + c[1] * u[1]) + c[2] * u[2]; break;
+        default:   den = (c[0] * u[0] + c[1] * u[1]) + c[2] * u[2]; METER(5); break;
         }
         if (den == 0.0) return INFINITY;
         if (!((!pos && den > 0.0) || (pos && den < 0.0))) return INFINITY;
         t = (-surf_f(g, s, q)) / den;
+        METER(surf_value_ops(type) + 1);
     } else {
         double a, b, dx = q[0] - c[0], dy = q[1] - c[1];
         if (type == S_CZ) {
@@ -363,15 +390,18 @@ static double hs_distance(const or_geom *g, uint32_t s, int pos, const double q[
             a = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
             b = (dx * u[0] + dy * u[1]) + dz * u[2];
         }
+        METER(type == S_CZ ? 8 : 13);
         if (a == 0.0) return INFINITY;
         if (on) {
-            if (!pos && b < 0.0) t = (-2.0 * b) / a;
+            if (!pos && b < 0.0) { t = (-2.0 * b) / a; METER(2); }
             else return INFINITY;
         } else {
             double cc = surf_f(g, s, q);
             double disc = b * b - a * cc;
+            METER(type == S_CZ ? 7 : 9);
             if (!(disc > 0.0)) return INFINITY;
             double qq = sqrt(disc);
+            METER(3);
             if (!pos) {
                 t = (b <= 0.0) ? (qq - b) / a : (-cc) / (b + qq);
             } else {
@@ -393,6 +423,7 @@ static double distance_to_surface(const or_geom *g, const ptl *t, int *out_level
     double q[3];
     for (int L = 0; L < t->depth; L++) {
         local_pos(g, t, L, q);
+        if (L > 0) METER(3);
         int64_t c = t->cell[L];
         for (uint32_t k = g->hs_off[c]; k < g->hs_off[c + 1]; k++) {
             int32_t h = g->hs[k];
@@ -416,6 +447,7 @@ static double distance_to_surface(const or_geom *g, const ptl *t, int *out_level
 static int cross_surface(const or_geom *g, ptl *t, int level, int64_t surf) {
     double q[3];
     local_pos(g, t, level, q);
+    METER(3 * level);
     int64_t old = t->cell[level];
     int old_pos = -1;
     for (uint32_t k = g->hs_off[old]; k < g->hs_off[old + 1]; k++)
@@ -435,6 +467,7 @@ static int cross_surface(const or_geom *g, ptl *t, int level, int64_t surf) {
         }
     }
     if (found < 0) return level == 0 ? END_ESCAPE : END_LOST;
+    meter_verify(g, found, surf);
     t->cell[level] = found;
     if (descend(g, t, level, q)) return END_LOST;
     t->on_level = level;
@@ -475,6 +508,7 @@ static uint64_t rng_word(uint64_t seed, uint32_t geom_id, uint64_t pid, uint32_t
 
 /* uniform double in (0,1): the top 52 bits plus one half, times 2^-52 */
 double or_u01(uint64_t w) {
+    METER(2);
     return ((double)(w >> 12) + 0.5) * 0x1p-52;
 }
 
@@ -499,6 +533,7 @@ double or_mc_log(double x) {
     if (m >= sqrt2) { m = m * 0.5; e = e + 1; }
     double s = (m - 1.0) / (m + 1.0);
     double z = s * s;
+    METER(4 + 22 + 2 + 4);
     double poly = LOGC[11];
     for (int k = 10; k >= 0; k--) poly = poly * z + LOGC[k];
     double logm = (s + s) * poly;
@@ -525,8 +560,10 @@ static void sample_direction(const or_params *pr, ptl *t) {
         v1 = 2.0 * next_u01(pr, t) - 1.0;
         v2 = 2.0 * next_u01(pr, t) - 1.0;
         s = v1 * v1 + v2 * v2;
+        METER(7);
         if (s < 1.0 && s != 0.0) break;
     }
+    METER(8);
     double r = sqrt(1.0 - s);
     t->u[0] = (2.0 * v1) * r;
     t->u[1] = (2.0 * v2) * r;
@@ -567,6 +604,7 @@ static int birth(const or_geom *g, const or_params *pr, ptl *t, uint64_t local, 
     int64_t c = -1;
     for (int a = 0; a < OR_MAX_BIRTH_ATTEMPTS && c < 0; a++) {
         for (int k = 0; k < 3; k++) t->p[k] = g->lo[k] + (g->hi[k] - g->lo[k]) * next_u01(pr, t);
+        METER(9);
         c = find_cell_in(g, g->root, t->p);
         if (c < 0) (*rejected)++;
     }
@@ -647,12 +685,13 @@ static void run_history(const or_geom *g, const or_params *pr, uint64_t local, t
         double dist = distance_to_surface(g, &t, &bl, &bs);
         double sig = g->sigma[leaf_material(g, &t)];
         double sc = (pr->source == 1) ? INFINITY : t.tau / sig;
+        METER(pr->source == 1 ? 0 : 1);
         uint64_t inst = leaf_inst(g, &t);
         int boundary = dist < sc;
         double l;
         if (boundary) {
             l = dist;
-            if (pr->source != 1) t.tau = t.tau - sig * dist;
+            if (pr->source != 1) { t.tau = t.tau - sig * dist; METER(2); }
         } else {
             if (sc == INFINITY) { end = END_LOST; break; }
             l = sc;
@@ -660,6 +699,7 @@ static void run_history(const or_geom *g, const or_params *pr, uint64_t local, t
         /* move_within_cell */
         double m0 = l * t.u[0], m1 = l * t.u[1], m2 = l * t.u[2];
         t.p[0] = t.p[0] + m0; t.p[1] = t.p[1] + m1; t.p[2] = t.p[2] + m2;
+        METER(6);
         /* tally and sequence */
         if (acc) {
             neumaier_add(&acc->sum[inst], &acc->comp[inst], l);
@@ -788,6 +828,22 @@ int or_track(const or_geom *g, const or_params *pr, const or_out *out, int n_thr
     free(jobs);
     free(th);
     return err ? -3 : 0;
+}
+
+/* Work meter over particles [first, first+n) of pr: out[0] = double
+ * operations the method requires (see `meter`), out[1] = segments. */
+int or_count_work(const or_geom *g, const or_params *pr, uint64_t *out) {
+    uint64_t ops = 0, segs = 0, rej = 0;
+    meter = &ops;
+    for (uint64_t i = 0; i < pr->n_particles; i++) {
+        hist_result r;
+        run_history(g, pr, i, NULL, NULL, NULL, &r, &rej);
+        segs += r.segs;
+    }
+    meter = NULL;
+    out[0] = ops;
+    out[1] = segs;
+    return 0;
 }
 
 /* one history with every segment recorded (for invariant checks) */

@@ -566,7 +566,8 @@ extern "C" int gt_track(const gt_geometry *g, const gt_track_params *p, const gt
     if (p->source == 1 && p->ray_n1 < 1) return set_error("gt_track: ray source needs ray_n1 >= 1"), GT_EINVAL;
     if (p->record_first_k && (!o->rec || p->record_cap < 1))
         return set_error("gt_track: recording needs rec and record_cap >= 1"), GT_EINVAL;
-    if (p->flags & ~GT_FLAG_ACCUMULATE) return set_error("gt_track: unknown flags 0x%x", p->flags), GT_EINVAL;
+    if (p->flags & ~(GT_FLAG_ACCUMULATE | GT_FLAG_LANE_PER_HISTORY))
+        return set_error("gt_track: unknown flags 0x%x", p->flags), GT_EINVAL;
     if (p->block_size && (p->block_size % 64 || p->block_size > 1024))
         return set_error("gt_track: block_size must be a multiple of 64 up to 1024"), GT_EINVAL;
     if (p->first_particle + p->n_particles < p->first_particle)

@@ -239,11 +239,12 @@ __device__ int32_t search(const Dev &g, uint32_t u, double x, double y, double z
 }
 
 // ------------------------------------------------------------------ particle
-constexpr int kBlock = 256;   // lanes per workgroup (the launch bound)
+constexpr int kBlock = 256;       // lanes per workgroup of the one-history-per-lane kernels
+constexpr int kBlockP = 1024;     // lanes per workgroup of the persistent tracker (launch bound)
 
 // Per-lane state.  The cell of every level lives in LDS, one column per
-// lane (cell[L * kBlock]), so that level loops index it dynamically without
-// spilling and without unrolling the per-level search code.
+// lane (cell[L * blockDim.x]), so that level loops index it dynamically
+// without spilling and without unrolling the per-level search code.
 struct Particle {
     double x, y, z, u, v, w, tau;
     uint32_t *cell;
@@ -252,7 +253,7 @@ struct Particle {
     uint32_t on_surf;
 };
 
-__device__ __forceinline__ uint32_t &lvl(const Particle &P, int L) { return P.cell[L * kBlock]; }
+__device__ __forceinline__ uint32_t &lvl(const Particle &P, int L) { return P.cell[L * (int)blockDim.x]; }
 
 // Descend from level L0 (cell set, (qx,qy,qz) its local position): while
 // the cell is filled, find the daughter's cell at p - t (Alg. 7).
@@ -541,6 +542,263 @@ __device__ __forceinline__ void add_counts(const Counts &c, uint64_t *counters) 
     if (threadIdx.x < 7 && sh[threadIdx.x]) atomicAdd((unsigned long long *)&counters[threadIdx.x], sh[threadIdx.x]);
 }
 
+
+// ------------------------------------------------------------------ persistent tracker
+// Each lane runs a small state machine; a wave loops until the shared
+// particle pool is drained and all of its lanes are idle.  Finished lanes
+// are refilled at once from a wave-local pool of particle ids (ballot +
+// per-lane rank, one global atomic per 64 ids), so a wave no longer waits
+// for its longest history.  The candidate search, the sampling and the
+// segment step each have a single call site, so lanes that are at different
+// steps of their histories share one instruction stream per step.
+enum Mode : int { M_IDLE = 0, M_POS = 1, M_SEARCH = 2, M_SAMPLE = 3, M_TRACK = 4 };
+
+constexpr uint32_t kChunk = 64;
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g, KParams p, KOut o) {
+    __shared__ uint32_t cells[GT_MAX_LEVELS * kBlockP];
+    unsigned long long *queue = (unsigned long long *)&o.counters[7];
+    Counts cnt = {0, 0, 0, 0, 0, 0, 0};
+    Particle P;
+    P.cell = cells + threadIdx.x;
+    Stream rng;
+    rng.key = p.seed;
+    rng.gid = p.geom_id;
+    int mode = M_IDLE;
+    uint64_t local = 0;
+    // history state
+    uint64_t h = 0;
+    uint32_t segs = 0, ncoll = 0, attempts = 0;
+    bool recovf = false, birth = false;
+    TallyAcc acc;
+    acc.inst = kNone;
+    acc.lo = acc.hi = 0;
+    // pending search: universe su at local point (qx,qy,qz) for level sL
+    int sL = 0;
+    uint32_t su = 0, sforce = kNone;
+    bool sfpos = false;
+    int32_t sexcl = -1;
+    double qx = 0, qy = 0, qz = 0;
+    float gx = 0, gy = 0;
+    // wave-uniform pool of particle ids
+    uint64_t pool_next = 0, pool_end = 0;
+    bool drained = false;
+    int end = GT_END_NONE;
+
+    for (;;) {
+        // ---- refill idle lanes
+        if (!drained) {
+            uint64_t idle = __ballot(mode == M_IDLE);
+            while (idle) {
+                if (pool_next == pool_end) {
+                    const int leader = __ffsll((unsigned long long)idle) - 1;
+                    unsigned long long base = 0;
+                    if ((int)__lane_id() == leader) base = atomicAdd(queue, (unsigned long long)kChunk);
+                    base = __shfl(base, leader);
+                    if (base >= p.n) { drained = true; break; }
+                    pool_next = base;
+                    pool_end = min((uint64_t)base + kChunk, p.n);
+                }
+                const uint64_t avail = pool_end - pool_next;
+                const uint32_t r = lane_rank(idle);
+                if (mode == M_IDLE && r < avail) {
+                    local = pool_next + r;
+                    rng.pid = p.first + local;
+                    rng.k = 0;
+                    h = kFnvOffset;
+                    segs = ncoll = attempts = 0;
+                    recovf = false;
+                    birth = true;
+                    P.on_level = -1;
+                    P.on_surf = kNone;
+                    P.depth = 1;
+                    end = GT_END_NONE;
+                    mode = M_POS;
+                }
+                const uint64_t nidle = (uint64_t)__popcll(idle);
+                pool_next += nidle < avail ? nidle : avail;
+                idle = __ballot(mode == M_IDLE);
+            }
+        }
+        if (__ballot(mode != M_IDLE) == 0) break;
+
+        // ---- birth position (uniform in the box, retried until a root cell has it)
+        if (mode == M_POS) {
+            if (p.source == 1) {
+                const uint64_t n1 = p.ray_n1;
+                const uint64_t n2 = (p.n + n1 - 1) / n1;
+                const uint64_t j = rng.pid % n1, k = rng.pid / n1;
+                const double hy = (g.hi[1] - g.lo[1]) / (double)n1;
+                const double hz = (g.hi[2] - g.lo[2]) / (double)n2;
+                P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * 0x1p-30;
+                P.y = g.lo[1] + ((double)j + 0.5) * hy;
+                P.z = g.lo[2] + ((double)k + 0.5) * hz;
+                P.u = 1.0;
+                P.v = 0.0;
+                P.w = 0.0;
+                P.tau = 0.0;
+                mode = M_SEARCH;
+            } else if (attempts >= (uint32_t)kMaxBirthAttempts) {
+                end = GT_END_LOST;
+            } else {
+                P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * rng.u01();
+                P.y = g.lo[1] + (g.hi[1] - g.lo[1]) * rng.u01();
+                P.z = g.lo[2] + (g.hi[2] - g.lo[2]) * rng.u01();
+                attempts++;
+                mode = M_SEARCH;
+            }
+            sL = 0;
+            su = g.root;
+            sforce = kNone;
+            sexcl = -1;
+            qx = P.x;
+            qy = P.y;
+            qz = P.z;
+            gx = (float)qx;
+            gy = (float)qy;
+        }
+
+        // ---- one level of find_cell / cross_surface
+        if (mode == M_SEARCH) {
+            const int32_t c = search<PREC>(g, su, qx, qy, qz, sforce, sfpos, sexcl, gx, gy);
+            if (c < 0) {
+                if (birth) {
+                    if (sL == 0 && p.source != 1) { cnt.rejected++; mode = M_POS; }
+                    else end = GT_END_LOST;
+                } else {
+                    end = (sforce != kNone && sL == 0) ? GT_END_ESCAPE : GT_END_LOST;
+                }
+            } else {
+                lvl(P, sL) = (uint32_t)c;
+                const int32_t fill = g.cell[c].fill;
+                if (fill < 0) {
+                    const double *t = g.trans + 4 * (size_t)c;
+                    qx = qx - t[0];
+                    qy = qy - t[1];
+                    qz = qz - t[2];
+                    gx = (float)qx;
+                    gy = (float)qy;
+                    su = (uint32_t)(-fill - 1);
+                    sL++;
+                    sforce = kNone;
+                    sexcl = -1;
+                } else {
+                    P.depth = sL + 1;
+                    if (birth) {
+                        birth = false;
+                        mode = p.source == 1 ? M_TRACK : M_SAMPLE;
+                    } else {
+                        if (segs >= p.max_segs) end = GT_END_SEGCAP;
+                        mode = M_TRACK;
+                    }
+                }
+            }
+        }
+
+        // ---- change_direction and a new optical depth
+        if (mode == M_SAMPLE && end == GT_END_NONE) {
+            sample_direction(rng, P.u, P.v, P.w);
+            P.tau = -series_log(rng.u01());
+            mode = M_TRACK;
+        }
+
+        // ---- one segment: distance_to_surface, move, tally, then crossing or collision
+        if (mode == M_TRACK && end == GT_END_NONE) {
+            int bl;
+            uint32_t bs;
+            bool bpos;
+            const double dist = distance_all(g, P, bl, bs, bpos);
+            const uint32_t lc = lvl(P, P.depth - 1);
+            const double sig = g.sigma[g.cell[lc].fill];
+            const double sc = (p.source == 1) ? dinf() : P.tau / sig;
+            const uint32_t inst = leaf_instance(g, P);
+            const bool boundary = dist < sc;
+            if (!boundary && sc == dinf()) {
+                end = GT_END_LOST;
+            } else {
+                double l;
+                if (boundary) {
+                    l = dist;
+                    if (p.source != 1) P.tau = P.tau - sig * dist;
+                } else {
+                    l = sc;
+                }
+                const double m0 = l * P.u, m1 = l * P.v, m2 = l * P.w;
+                P.x = P.x + m0;
+                P.y = P.y + m1;
+                P.z = P.z + m2;
+                tally_add(o.tally_fx, acc, inst, l);
+                h = (h ^ ((uint64_t)inst + 1)) * kFnvPrime;
+                if (local < p.rec_k) {
+                    if (segs < p.rec_cap) o.rec[local * (uint64_t)p.rec_cap + segs] = (int32_t)inst;
+                    else recovf = true;
+                }
+                segs++;
+                if (boundary) {
+                    // set up cross_surface at level bl on surface bs (Alg. 8)
+                    qx = P.x;
+                    qy = P.y;
+                    qz = P.z;
+                    su = g.root;
+                    for (int L = 0; L < bl; L++) {
+                        const uint32_t c = lvl(P, L);
+                        const double *t = g.trans + 4 * (size_t)c;
+                        qx = qx - t[0];
+                        qy = qy - t[1];
+                        qz = qz - t[2];
+                        su = (uint32_t)(-g.cell[c].fill - 1);
+                    }
+                    sL = bl;
+                    sforce = bs;
+                    sfpos = !bpos;
+                    sexcl = (int32_t)lvl(P, bl);
+                    gx = (float)qx;
+                    gy = (float)qy;
+                    if (PREC == GT_PREC_MIXED) {
+                        const Univ U = g.univ[su];
+                        if (U.hint == (int32_t)kHintSquare) {
+                            gx += (float)P.u * 1e-3f / U.inv_px;
+                            gy += (float)P.v * 1e-3f / U.inv_py;
+                        }
+                    }
+                    P.on_level = bl;
+                    P.on_surf = bs;
+                    mode = M_SEARCH;
+                } else {
+                    P.on_level = -1;
+                    P.on_surf = kNone;
+                    ncoll++;
+                    if (ncoll >= p.max_coll) end = GT_END_CAP;
+                    else if (segs >= p.max_segs) end = GT_END_SEGCAP;
+                    else mode = M_SAMPLE;
+                }
+            }
+        }
+
+        // ---- history finished: outputs, then the lane is free
+        if (mode != M_IDLE && end != GT_END_NONE) {
+            tally_flush(o.tally_fx, acc);
+            h ^= (uint64_t)end;
+            if (o.seg_count) o.seg_count[local] = segs;
+            if (o.seq_hash) o.seq_hash[local] = h;
+            if (o.end_code) o.end_code[local] = (uint8_t)end;
+            cnt.segments += segs;
+            cnt.escaped += end == GT_END_ESCAPE;
+            cnt.capped += end == GT_END_CAP;
+            cnt.lost += end == GT_END_LOST;
+            cnt.segcap += end == GT_END_SEGCAP;
+            cnt.recovf += recovf;
+            mode = M_IDLE;
+        }
+    }
+    add_counts(cnt, o.counters);
+}
+
 template <int PREC>
 __global__ void __launch_bounds__(kBlock) k_track(Dev g, KParams p, KOut o) {
     __shared__ uint32_t cells[GT_MAX_LEVELS * kBlock];
@@ -651,6 +909,35 @@ inline unsigned fill_grid(uint64_t n) {
     return (unsigned)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
+// Workgroups that fit on the device at once (all compute units, the
+// occupancy the kernel's resources allow), cached per device and block size.
+int persistent_grid(const void *kernel, unsigned block, int device, int *blocks) {
+    static int cache_dev[64], cache_block[64], cache_n[64];
+    static const void *cache_k[64];
+    static int used = 0;
+    for (int i = 0; i < used; i++)
+        if (cache_k[i] == kernel && cache_dev[i] == device && cache_block[i] == (int)block) {
+            *blocks = cache_n[i];
+            return GT_OK;
+        }
+    int cus = 0, per = 0;
+    int rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
+    if (rc) return rc;
+    rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, (int)block, 0),
+                   "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    if (rc) return rc;
+    if (per < 1) per = 1;
+    *blocks = cus * per;
+    if (used < 64) {
+        cache_k[used] = kernel;
+        cache_dev[used] = device;
+        cache_block[used] = (int)block;
+        cache_n[used] = *blocks;
+        used++;
+    }
+    return GT_OK;
+}
+
 template <int PREC>
 int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, hipStream_t st) {
     KParams kp;
@@ -672,7 +959,6 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
     ko.end_code = o->end_code;
     ko.rec = o->rec;
     ko.counters = o->counters;
-    const unsigned block = p->block_size ? p->block_size : kBlock;
     if (!(p->flags & GT_FLAG_ACCUMULATE))
         hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(2 * g->n_inst)), dim3(256), 0, st, o->tally_fx, 2 * g->n_inst,
                            (uint64_t)0);
@@ -681,7 +967,20 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
         const uint64_t nrec = (uint64_t)kp.rec_k * kp.rec_cap;
         hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(nrec)), dim3(256), 0, st, o->rec, nrec, (int32_t)-1);
     }
-    if (kp.n) hipLaunchKernelGGL((k_track<PREC>), dim3(grid_for(kp.n, block)), dim3(block), 0, st, g->dev, kp, ko);
+    if (kp.n) {
+        if (p->flags & GT_FLAG_LANE_PER_HISTORY) {
+            const unsigned block = p->block_size ? p->block_size : kBlock;
+            hipLaunchKernelGGL((k_track<PREC>), dim3(grid_for(kp.n, block)), dim3(block), 0, st, g->dev, kp, ko);
+        } else {
+            const unsigned block = p->block_size ? p->block_size : kBlockP;
+            int blocks = 0;
+            int rc = persistent_grid((const void *)k_track_persistent<PREC>, block, g->device, &blocks);
+            if (rc) return rc;
+            const uint64_t need = (kp.n + block - 1) / block;
+            if ((uint64_t)blocks > need) blocks = (int)need;
+            hipLaunchKernelGGL((k_track_persistent<PREC>), dim3(blocks), dim3(block), 0, st, g->dev, kp, ko);
+        }
+    }
     if (o->tally)
         hipLaunchKernelGGL(k_finalize, dim3(fill_grid(g->n_inst)), dim3(256), 0, st, o->tally_fx, o->tally, g->n_inst);
     return hip_check(hipGetLastError(), "gt_track launch");
@@ -691,7 +990,8 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
 
 int launch_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    if (p->block_size > (uint32_t)kBlock) return set_error("gt_track: block_size must be at most %d", kBlock), GT_EINVAL;
+    if ((p->flags & GT_FLAG_LANE_PER_HISTORY) && p->block_size > (uint32_t)kBlock)
+        return set_error("gt_track: block_size must be at most %d with GT_FLAG_LANE_PER_HISTORY", kBlock), GT_EINVAL;
     if (p->n_particles > (uint64_t)0x7FFFFFFF * 64ull) return set_error("gt_track: too many particles"), GT_ECAPACITY;
     return p->precision == GT_PREC_MIXED ? launch_track_t<GT_PREC_MIXED>(g, p, o, st)
                                          : launch_track_t<GT_PREC_FP64>(g, p, o, st);

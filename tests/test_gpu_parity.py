@@ -132,11 +132,12 @@ CASES = [
 
 @pytest.mark.parametrize("case", CASES, ids=[str(c[0]) for c in CASES])
 @pytest.mark.parametrize("prec", [gt.PREC_FP64, gt.PREC_MIXED])
-def test_track_parity(case, prec):
+@pytest.mark.parametrize("lane", [False, True], ids=["persistent", "lane"])
+def test_track_parity(case, prec, lane):
     cfg, kw, k, cap = case
     fg, G, O = geoms(cfg)
-    print("track parity", cfg, kw, "precision", prec, flush=True)
-    g = gpu_track(G, precision=prec, record_first_k=k, record_cap=cap, **kw)
+    print("track parity", cfg, kw, "precision", prec, "lane per history", lane, flush=True)
+    g = gpu_track(G, precision=prec, record_first_k=k, record_cap=cap, lane_per_history=lane, **kw)
     o = oracle.track(O, oracle.TrackParams(record_first_k=k, record_cap=cap, **kw), n_threads=NT)
     assert_parity(g, o, where="cfg %s prec %d" % (cfg, prec))
 
@@ -167,11 +168,12 @@ def test_edge_cases():
     assert not g["tally_fx"].any() and sum(g["counters"].values()) == 0
 
 
-@pytest.mark.parametrize("block", [64, 128, 192])
-def test_block_sizes_do_not_change_results(block):
+@pytest.mark.parametrize("block,lane", [(64, True), (128, True), (192, True), (64, False), (256, False),
+                                        (512, False), (1024, False)])
+def test_block_sizes_do_not_change_results(block, lane):
     fg, G, O = geoms(2)
     kw = dict(seed=2002, n_particles=5000, geometry_id=2)
-    g = gpu_track(G, precision=gt.PREC_MIXED, block_size=block, **kw)
+    g = gpu_track(G, precision=gt.PREC_MIXED, block_size=block, lane_per_history=lane, **kw)
     o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT)
     assert_parity(g, o, where="block %d" % block)
 
@@ -199,6 +201,8 @@ def test_invalid_track_arguments():
         gt.track(G, seed=1, n_particles=10, precision=7)
     with pytest.raises(gt.GtError):
         gt.track(G, seed=1, n_particles=10, block_size=100)
+    with pytest.raises(gt.GtError):
+        gt.track(G, seed=1, n_particles=10, block_size=512, lane_per_history=True)
     with pytest.raises(gt.GtError):
         gt.track(G, seed=1, n_particles=10, source=1, ray_n1=0)
 

@@ -202,3 +202,13 @@ def test_segment_cap_and_collision_cap():
     p = oracle.TrackParams(seed=3, n_particles=500, geometry_id=2, max_collisions=3)
     r = oracle.track(og, p, n_threads=2)
     assert set(np.unique(r.end_code)) <= {oracle.END_ESCAPE, oracle.END_CAP}
+
+
+def test_work_meter_hand_count():
+    """Rays along +x through a single box: locating the birth cell tests 6
+    axis half-spaces (6 ops), the one segment evaluates the +x plane (2 ops:
+    subtract, divide; the -x plane is receding and y/z planes are parallel)
+    and moves (6 ops): 14 operations per history, one segment each."""
+    og = oracle.OracleGeometry(synth.box((1.0, 2.0, 3.0)))
+    ops, segs = oracle.count_work(og, oracle.TrackParams(seed=0, n_particles=100, source=1, ray_n1=10))
+    assert segs == 100 and ops == 1400
