@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--particles", type=int, default=1_000_000)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead of tracking, run a plain device copy of this many bytes --steps times "
+                         "(reference kernel for scaling HBM counters)")
     ap.add_argument("--only", choices=["mixed", "fp64", "plain_fp64"], default=None,
                     help="time one mode only (profiling)")
     return ap.parse_args()
@@ -105,6 +108,15 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    if args.copy_bytes:
+        a = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_bytes, "steps": args.steps}))
+        return
     from paper_2406_13849_amd import gt, synth
     fg = synth.make_config(2)
     G = gt.Geometry(fg)

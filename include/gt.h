@@ -88,6 +88,8 @@ extern "C" {
 #define GT_FLAG_LANE_PER_HISTORY 2u    /* one history per lane, one launch slot per history
                                           (the plain schedule) instead of the persistent,
                                           refilling schedule                                */
+#define GT_FLAG_NO_STAGING 4u          /* persistent schedule: read the geometry tables from
+                                          global memory even when they fit in LDS           */
 
 typedef struct gt_geometry gt_geometry;   /* opaque; owns its device tables */
 

@@ -319,7 +319,7 @@ typedef struct {
     int on_level;          /* -1: not on a surface */
     int64_t on_surf;
     uint64_t pid;
-    uint32_t draw;         /* index of the next 64-bit random word */
+    uint32_t draw;         /* index of the next random-number block */
 } ptl;
 
 static void local_pos(const or_geom *g, const ptl *t, int level, double q[3]) {
@@ -495,21 +495,30 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-/* 64-bit word number k of particle pid: block k/2 of the stream keyed by the
- * seed with counter (block, pid lo, pid hi, geometry id); even k takes
- * output words 0,1 and odd k words 2,3 (low half first). */
-static uint64_t rng_word(uint64_t seed, uint32_t geom_id, uint64_t pid, uint32_t k) {
-    uint32_t ctr[4] = { k >> 1, (uint32_t)pid, (uint32_t)(pid >> 32), geom_id };
+/* Random numbers.  Every sampling event of a particle takes one whole
+ * Philox4x32-10 block: counter (b, pid lo, pid hi, geometry id) under the
+ * key = seed, b being the particle's block index (0, 1, 2, ... in order of
+ * use).  The block's 128 bits (word 0 least significant) are cut into three
+ * 42-bit fields f0 = bits [0,42), f1 = [42,84), f2 = [84,126), each mapped
+ * to the uniform (f + 1/2) 2^-42 in (0,1).  A birth-position attempt uses
+ * f0, f1, f2 for x, y, z; a direction attempt uses f0, f1 for Marsaglia's
+ * pair and, once accepted, f2 for the optical depth of the next flight. */
+static void rng_fields(uint64_t seed, uint32_t geom_id, uint64_t pid, uint32_t b, uint64_t f[3]) {
+    uint32_t ctr[4] = { b, (uint32_t)pid, (uint32_t)(pid >> 32), geom_id };
     uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
     uint32_t o[4];
     or_philox4x32_10(ctr, key, o);
-    return (k & 1) ? ((uint64_t)o[3] << 32 | o[2]) : ((uint64_t)o[1] << 32 | o[0]);
+    uint64_t w0 = (uint64_t)o[1] << 32 | o[0], w1 = (uint64_t)o[3] << 32 | o[2];
+    const uint64_t m42 = (1ull << 42) - 1;
+    f[0] = w0 & m42;
+    f[1] = (w0 >> 42) | ((w1 & ((1ull << 20) - 1)) << 22);
+    f[2] = (w1 >> 20) & m42;
 }
 
-/* uniform double in (0,1): the top 52 bits plus one half, times 2^-52 */
-double or_u01(uint64_t w) {
+/* uniform double in (0,1) from a 42-bit field: (f + 1/2) 2^-42, exact */
+double or_u01(uint64_t f) {
     METER(2);
-    return ((double)(w >> 12) + 0.5) * 0x1p-52;
+    return ((double)f + 0.5) * 0x1p-42;
 }
 
 /* natural log of a positive normal double, from the series
@@ -549,16 +558,19 @@ void or_mc_log_batch(const double *x, uint64_t n, double *out) {
     for (uint64_t i = 0; i < n; i++) out[i] = or_mc_log(x[i]);
 }
 
-static double next_u01(const or_params *pr, ptl *t) {
-    return or_u01(rng_word(pr->seed, pr->geometry_id, t->pid, t->draw++));
+static void next_block(const or_params *pr, ptl *t, uint64_t f[3]) {
+    rng_fields(pr->seed, pr->geometry_id, t->pid, t->draw++, f);
 }
 
-/* isotropic direction, Marsaglia (1972) */
-static void sample_direction(const or_params *pr, ptl *t) {
+/* change_direction (Table 1) to an isotropic direction, Marsaglia (1972),
+ * and a new exponential(1) optical depth tau = -log U for the next flight */
+static void sample_flight(const or_params *pr, ptl *t) {
     double v1, v2, s;
+    uint64_t f[3];
     for (;;) {
-        v1 = 2.0 * next_u01(pr, t) - 1.0;
-        v2 = 2.0 * next_u01(pr, t) - 1.0;
+        next_block(pr, t, f);
+        v1 = 2.0 * or_u01(f[0]) - 1.0;
+        v2 = 2.0 * or_u01(f[1]) - 1.0;
         s = v1 * v1 + v2 * v2;
         METER(7);
         if (s < 1.0 && s != 0.0) break;
@@ -568,11 +580,7 @@ static void sample_direction(const or_params *pr, ptl *t) {
     t->u[0] = (2.0 * v1) * r;
     t->u[1] = (2.0 * v2) * r;
     t->u[2] = 1.0 - 2.0 * s;
-}
-
-/* number of mean free paths to the next collision, exponential(1) */
-static void sample_tau(const or_params *pr, ptl *t) {
-    t->tau = -or_mc_log(next_u01(pr, t));
+    t->tau = -or_mc_log(or_u01(f[2]));
 }
 
 /* Birth (Alg. 2 sampling lines): uniform position in the domain box,
@@ -603,7 +611,9 @@ static int birth(const or_geom *g, const or_params *pr, ptl *t, uint64_t local, 
     }
     int64_t c = -1;
     for (int a = 0; a < OR_MAX_BIRTH_ATTEMPTS && c < 0; a++) {
-        for (int k = 0; k < 3; k++) t->p[k] = g->lo[k] + (g->hi[k] - g->lo[k]) * next_u01(pr, t);
+        uint64_t f[3];
+        next_block(pr, t, f);
+        for (int k = 0; k < 3; k++) t->p[k] = g->lo[k] + (g->hi[k] - g->lo[k]) * or_u01(f[k]);
         METER(9);
         c = find_cell_in(g, g->root, t->p);
         if (c < 0) (*rejected)++;
@@ -612,8 +622,7 @@ static int birth(const or_geom *g, const or_params *pr, ptl *t, uint64_t local, 
     t->cell[0] = c;
     q[0] = t->p[0]; q[1] = t->p[1]; q[2] = t->p[2];
     int rc = descend(g, t, 0, q) ? END_LOST : END_NONE;
-    sample_direction(pr, t);
-    sample_tau(pr, t);
+    sample_flight(pr, t);
     return rc;
 }
 
@@ -726,8 +735,7 @@ static void run_history(const or_geom *g, const or_params *pr, uint64_t local, t
             if (ncoll >= pr->max_collisions) {
                 end = END_CAP;
             } else {
-                sample_direction(pr, &t);
-                sample_tau(pr, &t);
+                sample_flight(pr, &t);
                 if (tr && tr->n_flights < tr->cap) tr->flight_tau[tr->n_flights++] = t.tau;
             }
         }

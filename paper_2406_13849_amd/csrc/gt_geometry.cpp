@@ -458,17 +458,28 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
             default: o[0] = q[0]; o[1] = q[1]; o[2] = q[2]; o[3] = q[3]; break;
             }
         }
+        // each cell's half-spaces planes first, then quadrics (the order never
+        // changes a result: containment is a conjunction and distance ties
+        // break on surface id)
         std::vector<uint32_t> hs(F.n_halfspaces);
-        for (uint32_t k = 0; k < F.n_halfspaces; k++) {
-            uint32_t s = B.surf_of(F.hs[k]);
-            hs[k] = hs_pack(s, F.hs[k] > 0, F.surf_type[s]);
-        }
         std::vector<Cell> cell(F.n_cells);
+        for (uint32_t c = 0; c < F.n_cells; c++) {
+            uint32_t k0 = F.cell_hs_off[c], k1 = F.cell_hs_off[c + 1], o = k0, npl = 0;
+            for (int quad = 0; quad < 2; quad++)
+                for (uint32_t k = k0; k < k1; k++) {
+                    uint32_t s = B.surf_of(F.hs[k]);
+                    bool is_quad = F.surf_type[s] >= ST_CZ;
+                    if (is_quad != (quad == 1)) continue;
+                    hs[o++] = hs_pack(s, F.hs[k] > 0, F.surf_type[s]);
+                    npl += !is_quad;
+                }
+            cell[c].n_pl = (uint16_t)npl;
+        }
         std::vector<double> trans(4 * (size_t)F.n_cells, 0.0);
         std::vector<float> cb(8 * (size_t)F.n_cells, 0.0f);
         for (uint32_t c = 0; c < F.n_cells; c++) {
             cell[c].hs_off = F.cell_hs_off[c];
-            cell[c].hs_n = F.cell_hs_off[c + 1] - F.cell_hs_off[c];
+            cell[c].n_hs = (uint16_t)(F.cell_hs_off[c + 1] - F.cell_hs_off[c]);
             cell[c].fill = F.cell_fill[c];
             cell[c].inst_off = (uint32_t)B.inst_off[c];
             for (int k = 0; k < 3; k++) trans[4 * (size_t)c + k] = F.cell_trans[3 * (size_t)c + k];
@@ -507,6 +518,13 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
             (void)hipFree(blob);
             return set_error("hipMemcpy: %s", hipGetErrorString(e)), GT_EHIP;
         }
+        void *ws = nullptr;
+        const size_t ws_bytes = (size_t)8 * 4 * 8 * (size_t)std::max<uint64_t>(B.ninst[F.root], 1);
+        e = hipMalloc(&ws, ws_bytes);
+        if (e != hipSuccess) {
+            (void)hipFree(blob);
+            return set_error("hipMalloc(%zu) for the tally workspace: %s", ws_bytes, hipGetErrorString(e)), GT_ENOMEM;
+        }
         gt_geometry *g = new gt_geometry;
         unsigned char *base = (unsigned char *)blob;
         g->dev.coef = (const double *)(base + off[0]);
@@ -524,8 +542,30 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         g->dev.max_depth = B.depth[F.root];
         g->dev.n_cells = F.n_cells;
         for (int k = 0; k < 3; k++) { g->dev.lo[k] = F.domain_lo[k]; g->dev.hi[k] = F.domain_hi[k]; }
+        // LDS staging plans: the tables each precision mode reads, packed
+        for (int prec = 0; prec < 2; prec++) {
+            StagePlan &P = g->stage[prec];
+            std::memset(&P, 0, sizeof P);
+            uint32_t *slot[10] = {&P.coef, &P.hs, &P.cell, &P.trans, &P.univ, &P.node32, &P.node64, &P.leaf, &P.cbox,
+                                  &P.sigma};
+            uint64_t at = 0;
+            for (int i = 0; i < 10; i++) {
+                bool need = prec == GT_PREC_MIXED ? (i != 6) : (i != 5 && i != 8);
+                *slot[i] = 0xFFFFFFFFu;
+                if (!need) continue;
+                const uint64_t b = (std::max<size_t>(sz[i], 16) + 15) & ~(uint64_t)15;
+                P.src[P.n] = (uint32_t)off[i];
+                P.dst[P.n] = (uint32_t)at;
+                P.bytes[P.n] = (uint32_t)b;
+                *slot[i] = (uint32_t)at;
+                P.n++;
+                at += b;
+            }
+            P.total = at > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)at;
+        }
         g->blob = blob;
-        g->blob_bytes = total;
+        g->blob_bytes = total + ws_bytes;
+        g->tally_ws = (uint64_t *)ws;
         g->n_inst = B.ninst[F.root];
         g->max_depth = B.depth[F.root];
         g->device = dev;
@@ -552,6 +592,7 @@ extern "C" void gt_geometry_destroy(gt_geometry *g) {
     int cur = 0;
     bool switched = hipGetDevice(&cur) == hipSuccess && cur != g->device && hipSetDevice(g->device) == hipSuccess;
     (void)hipFree(g->blob);
+    (void)hipFree(g->tally_ws);
     if (switched) (void)hipSetDevice(cur);
     delete g;
 }
@@ -566,7 +607,7 @@ extern "C" int gt_track(const gt_geometry *g, const gt_track_params *p, const gt
     if (p->source == 1 && p->ray_n1 < 1) return set_error("gt_track: ray source needs ray_n1 >= 1"), GT_EINVAL;
     if (p->record_first_k && (!o->rec || p->record_cap < 1))
         return set_error("gt_track: recording needs rec and record_cap >= 1"), GT_EINVAL;
-    if (p->flags & ~(GT_FLAG_ACCUMULATE | GT_FLAG_LANE_PER_HISTORY))
+    if (p->flags & ~(GT_FLAG_ACCUMULATE | GT_FLAG_LANE_PER_HISTORY | GT_FLAG_NO_STAGING))
         return set_error("gt_track: unknown flags 0x%x", p->flags), GT_EINVAL;
     if (p->block_size && (p->block_size % 64 || p->block_size > 1024))
         return set_error("gt_track: block_size must be a multiple of 64 up to 1024"), GT_EINVAL;

@@ -21,10 +21,11 @@ constexpr uint32_t kLeafNone = 0xFFFFFFFFu;
 constexpr uint32_t kLeafMax = 4;       // cells per BVH leaf
 constexpr uint32_t kHintNone = 0, kHintSquare = 1;
 
-// 16 bytes per cell
+// 16 bytes per cell; its half-spaces are stored planes first, then quadrics
 struct alignas(16) Cell {
     uint32_t hs_off;    // first packed half-space
-    uint32_t hs_n;      // number of half-spaces
+    uint16_t n_pl;      // number of plane half-spaces (stored first)
+    uint16_t n_hs;      // number of half-spaces
     int32_t fill;       // >= 0 material, < 0 daughter universe -(u+1)
     uint32_t inst_off;  // leaf-instance offset of this cell within its universe
 };
@@ -73,13 +74,23 @@ struct Dev {
     double lo[3], hi[3];
 };
 
+// Copy of a geometry's hot tables into LDS: sections of the device blob
+// (byte offsets, 16-byte multiples) and where each lands in LDS.
+struct StagePlan {
+    uint32_t n;             // number of sections
+    uint32_t total;         // LDS bytes
+    uint32_t src[10], dst[10], bytes[10];
+    // LDS byte offsets of each table (kNotStaged when absent)
+    uint32_t coef, hs, cell, trans, univ, node32, node64, leaf, cbox, sigma;
+};
+
 struct KParams {
     uint64_t seed, first, n;
     uint32_t geom_id, max_coll, source, ray_n1, max_segs, rec_k, rec_cap, pad;
 };
 
 struct KOut {
-    uint64_t *tally_fx;
+    uint64_t *tally_ws;     // per-XCD replicas of per-instance limb counters
     uint32_t *seg_count;
     uint64_t *seq_hash;
     uint8_t *end_code;
@@ -92,8 +103,10 @@ struct KOut {
 // host-side geometry object behind the opaque ABI handle
 struct gt_geometry {
     gt::Dev dev;
+    gt::StagePlan stage[2];   // per precision mode (GT_PREC_FP64, GT_PREC_MIXED)
     void *blob;          // one device allocation holding every table
     uint64_t blob_bytes;
+    uint64_t *tally_ws;  // tally workspace: 8 replicas x n_inst x 4 limb counters
     uint64_t n_inst;
     uint32_t max_depth;
     int device;

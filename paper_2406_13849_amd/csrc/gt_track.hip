@@ -2,18 +2,23 @@
 // through nested CSG universes with one CSG tracker and per-universe
 // bounding-volume hierarchies (Section "Single tracker (ST) method").
 //
-// One lane carries one history at a time; its whole state (position,
-// direction, optical depth, the cell at every level, random-stream
-// position, tally accumulator) lives in registers.  Geometry tables are
-// read-only and shared by all lanes.
+// Two schedules share every device function:
+//   - k_track_persistent (default): one workgroup per compute unit; each
+//     wave loops until the particle pool is drained, refilling finished
+//     lanes from a wave-local pool of particle ids, and every lane runs a
+//     small state machine whose steps (draw random numbers, search one
+//     level, one segment) each have a single call site;
+//   - k_track (GT_FLAG_LANE_PER_HISTORY): one history per lane.
+// A particle's state lives in registers; the cell of each level lives in
+// LDS (one column per lane) so level loops index it without spilling.
 //
 // Floating point: compiled with -ffp-contract=off and no fast-math, so every
 // double operation below is one IEEE operation in the order written; the
-// results of find_cell / distance_to_surface / cross_surface are therefore
-// the ones a plain double-precision implementation of the same definitions
-// computes.  Single precision only appears in the optional candidate
-// pruning (widened, outward-rounded boxes and a lattice-index guess), which
-// can skip a cell only when that cell cannot contain the point.
+// results of find_cell / distance_to_surface / cross_surface are the ones a
+// plain double-precision implementation of the same definitions computes.
+// Single precision only appears in the optional candidate pruning (widened,
+// outward-rounded boxes and a lattice-index guess), which can skip a cell
+// only when that cell cannot contain the point.
 #pragma clang fp contract(off)
 
 #include "gt_internal.h"
@@ -25,6 +30,11 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kMaxBirthAttempts = 1000;
 constexpr uint64_t kFnvOffset = 0xcbf29ce484222325ull;
 constexpr uint64_t kFnvPrime = 0x100000001b3ull;
+constexpr int kBlock = 256;     // lanes per workgroup of the one-history-per-lane kernels
+constexpr int kBlockP = 1024;   // lanes per workgroup of the persistent tracker (launch bound)
+// LDS left for staged geometry tables next to the persistent tracker's
+// per-lane level arrays (160 KiB per compute unit on gfx950)
+constexpr unsigned kStageBudget = 160 * 1024 - GT_MAX_LEVELS * kBlockP * 4 - 1024;
 
 __device__ __forceinline__ double dinf() { return __builtin_huge_val(); }
 
@@ -36,9 +46,9 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
                                               uint32_t k1, uint32_t &o0, uint32_t &o1, uint32_t &o2, uint32_t &o3) {
 #pragma unroll
     for (int r = 0; r < 10; r++) {
-        uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-        uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -46,42 +56,37 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     o0 = c0; o1 = c1; o2 = c2; o3 = c3;
 }
 
-// Stream of 64-bit words of one particle: word k is half (k & 1) of block
-// k >> 1 under counter (block, id lo, id hi, geometry id), low half first.
-struct Stream {
-    uint64_t key, pid, stash;
-    uint32_t gid, k;
-
-    __device__ __forceinline__ uint64_t word() {
-        uint64_t w;
-        if (k & 1u) {
-            w = stash;
-        } else {
-            uint32_t o0, o1, o2, o3;
-            philox4x32_10(k >> 1, (uint32_t)pid, (uint32_t)(pid >> 32), gid, (uint32_t)key, (uint32_t)(key >> 32),
-                          o0, o1, o2, o3);
-            w = ((uint64_t)o1 << 32) | o0;
-            stash = ((uint64_t)o3 << 32) | o2;
-        }
-        k++;
-        return w;
-    }
-    // uniform on (0,1): top 52 bits plus one half, times 2^-52 (exact)
-    __device__ __forceinline__ double u01() { return ((double)(word() >> 12) + 0.5) * 0x1p-52; }
-};
+// One sampling event = one Philox block at counter (b, id lo, id hi,
+// geometry id): its 128 bits (word 0 least significant) give three 42-bit
+// fields (bits [0,42), [42,84), [84,126)), each mapped exactly to the
+// uniform (f + 1/2) 2^-42 in (0,1).
+__device__ __forceinline__ void draw_block(uint64_t key, uint32_t gid, uint64_t pid, uint32_t b, double &u0,
+                                           double &u1, double &u2) {
+    uint32_t o0, o1, o2, o3;
+    philox4x32_10(b, (uint32_t)pid, (uint32_t)(pid >> 32), gid, (uint32_t)key, (uint32_t)(key >> 32), o0, o1, o2,
+                  o3);
+    const uint64_t w0 = ((uint64_t)o1 << 32) | o0, w1 = ((uint64_t)o3 << 32) | o2;
+    const uint64_t m42 = (1ull << 42) - 1;
+    const uint64_t f0 = w0 & m42;
+    const uint64_t f1 = (w0 >> 42) | ((w1 & ((1ull << 20) - 1)) << 22);
+    const uint64_t f2 = (w1 >> 20) & m42;
+    u0 = ((double)f0 + 0.5) * 0x1p-42;
+    u1 = ((double)f1 + 0.5) * 0x1p-42;
+    u2 = ((double)f2 + 0.5) * 0x1p-42;
+}
 
 // Natural logarithm from log m = 2 atanh(s), s = (m-1)/(m+1), m in
 // [sqrt(1/2), sqrt(2)), twelve odd-power terms with coefficients 1/(2k+1)
 // (each the correctly rounded quotient), and e*ln2 split in a 32-bit head
 // (exact products) and a tail.  Used for the exponential optical depth.
 __device__ __forceinline__ double series_log(double x) {
-    uint64_t bits = (uint64_t)__double_as_longlong(x);
+    const uint64_t bits = (uint64_t)__double_as_longlong(x);
     int e = (int)((bits >> 52) & 0x7ffu) - 1023;
     double m = __longlong_as_double((long long)((bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
     const double sqrt2 = __longlong_as_double(0x3FF6A09E667F3BCDll);
     if (m >= sqrt2) { m = m * 0.5; e = e + 1; }
-    double s = (m - 1.0) / (m + 1.0);
-    double z = s * s;
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
     double poly = 1.0 / 23.0;
     poly = poly * z + 1.0 / 21.0;
     poly = poly * z + 1.0 / 19.0;
@@ -94,30 +99,44 @@ __device__ __forceinline__ double series_log(double x) {
     poly = poly * z + 1.0 / 5.0;
     poly = poly * z + 1.0 / 3.0;
     poly = poly * z + 1.0;
-    double logm = (s + s) * poly;
+    const double logm = (s + s) * poly;
     const double ln2_hi = __longlong_as_double(0x3FE62E42FEE00000ll);
     const double ln2_lo = __longlong_as_double(0x3DEA39EF35793C76ll);
-    double de = (double)e;
+    const double de = (double)e;
     return de * ln2_hi + (de * ln2_lo + logm);
 }
 
+// Marsaglia (1972) isotropic direction from one block's first two fields;
+// false when the pair is rejected.
+__device__ __forceinline__ bool direction_from(double u0, double u1, double &u, double &v, double &w) {
+    const double v1 = 2.0 * u0 - 1.0;
+    const double v2 = 2.0 * u1 - 1.0;
+    const double s = v1 * v1 + v2 * v2;
+    if (!(s < 1.0 && s != 0.0)) return false;
+    const double r = sqrt(1.0 - s);
+    u = (2.0 * v1) * r;
+    v = (2.0 * v2) * r;
+    w = 1.0 - 2.0 * s;
+    return true;
+}
+
 // ------------------------------------------------------------------ surfaces
-// f(p); the positive side is f > 0 (outside of cylinders and spheres)
-__device__ __forceinline__ double surf_value(uint32_t type, const double *c, double x, double y, double z) {
+// Half-spaces of a cell are stored planes first (types PX, PY, PZ, P), then
+// quadrics (CZ, SPH), so each loop below runs one surface family.
+__device__ __forceinline__ double plane_value(uint32_t type, const double *c, double x, double y, double z) {
     switch (type) {
     case ST_PX: return x - c[0];
     case ST_PY: return y - c[0];
     case ST_PZ: return z - c[0];
-    case ST_P: return ((c[0] * x + c[1] * y) + c[2] * z) - c[3];
-    case ST_CZ: {
-        double dx = x - c[0], dy = y - c[1];
-        return (dx * dx + dy * dy) - c[2];
+    default: return ((c[0] * x + c[1] * y) + c[2] * z) - c[3];
     }
-    default: {
-        double dx = x - c[0], dy = y - c[1], dz = z - c[2];
-        return ((dx * dx + dy * dy) + dz * dz) - c[3];
-    }
-    }
+}
+
+__device__ __forceinline__ double quad_value(uint32_t type, const double *c, double x, double y, double z) {
+    const double dx = x - c[0], dy = y - c[1];
+    if (type == ST_CZ) return (dx * dx + dy * dy) - c[2];
+    const double dz = z - c[2];
+    return ((dx * dx + dy * dy) + dz * dz) - c[3];
 }
 
 // Cell containment: the point is on the required side of every half-space;
@@ -125,60 +144,68 @@ __device__ __forceinline__ double surf_value(uint32_t type, const double *c, dou
 __device__ __forceinline__ bool contains(const Dev &g, uint32_t c, double x, double y, double z, uint32_t force_s,
                                          bool force_pos) {
     const Cell cc = g.cell[c];
-    for (uint32_t k = 0; k < cc.hs_n; k++) {
-        uint32_t h = g.hs[cc.hs_off + k];
-        uint32_t s = h >> 4;
-        bool want = (h >> 3) & 1u;
-        bool pos = (s == force_s) ? force_pos : (surf_value(h & 7u, g.coef + 4 * (size_t)s, x, y, z) > 0.0);
-        if (pos != want) return false;
+    const uint32_t *hs = g.hs + cc.hs_off;
+    for (uint32_t k = 0; k < cc.n_pl; k++) {
+        const uint32_t h = hs[k];
+        const uint32_t s = h >> 4;
+        const bool pos = (s == force_s) ? force_pos : (plane_value(h & 7u, g.coef + 4 * (size_t)s, x, y, z) > 0.0);
+        if (pos != (bool)((h >> 3) & 1u)) return false;
+    }
+    for (uint32_t k = cc.n_pl; k < cc.n_hs; k++) {
+        const uint32_t h = hs[k];
+        const uint32_t s = h >> 4;
+        const bool pos = (s == force_s) ? force_pos : (quad_value(h & 7u, g.coef + 4 * (size_t)s, x, y, z) > 0.0);
+        if (pos != (bool)((h >> 3) & 1u)) return false;
     }
     return true;
 }
 
-// Distance along (u,v,w) from q to the point where the sense of surface s
-// leaves the cell's required side `pos`; +inf if it does not.  `on` marks the
-// surface the particle has just crossed (Table 1 distance_to_surface).
-__device__ __forceinline__ double hs_distance(uint32_t type, const double *c, bool pos, double qx, double qy,
-                                              double qz, double u, double v, double w, bool on) {
-    double t;
-    if (type <= ST_P) {
-        if (on) return dinf();
-        double den;
-        switch (type) {
-        case ST_PX: den = u; break;
-        case ST_PY: den = v; break;
-        case ST_PZ: den = w; break;
-        default: den = (c[0] * u + c[1] * v) + c[2] * w; break;
-        }
-        if (den == 0.0) return dinf();
-        if (!((!pos && den > 0.0) || (pos && den < 0.0))) return dinf();
-        t = (-surf_value(type, c, qx, qy, qz)) / den;
+// Distance along (u,v,w) from q to the point where a plane's sense leaves
+// the cell's required side `pos`; +inf if it does not (Table 1).
+__device__ __forceinline__ double plane_distance(uint32_t type, const double *c, bool pos, double qx, double qy,
+                                                 double qz, double u, double v, double w) {
+    double den;
+    switch (type) {
+    case ST_PX: den = u; break;
+    case ST_PY: den = v; break;
+    case ST_PZ: den = w; break;
+    default: den = (c[0] * u + c[1] * v) + c[2] * w; break;
+    }
+    if (den == 0.0) return dinf();
+    if (!((!pos && den > 0.0) || (pos && den < 0.0))) return dinf();
+    const double t = (-plane_value(type, c, qx, qy, qz)) / den;
+    return (t > 0.0) ? t : 0.0;
+}
+
+// The same for a cylinder or sphere: textbook cancellation-free roots;
+// `on` marks the surface just crossed (only the far root can be hit).
+__device__ __forceinline__ double quad_distance(uint32_t type, const double *c, bool pos, double qx, double qy,
+                                                double qz, double u, double v, double w, bool on) {
+    double a, b;
+    const double dx = qx - c[0], dy = qy - c[1];
+    if (type == ST_CZ) {
+        a = u * u + v * v;
+        b = dx * u + dy * v;
     } else {
-        double a, b;
-        double dx = qx - c[0], dy = qy - c[1];
-        if (type == ST_CZ) {
-            a = u * u + v * v;
-            b = dx * u + dy * v;
+        const double dz = qz - c[2];
+        a = (u * u + v * v) + w * w;
+        b = (dx * u + dy * v) + dz * w;
+    }
+    if (a == 0.0) return dinf();
+    double t;
+    if (on) {
+        if (!(!pos && b < 0.0)) return dinf();
+        t = (-2.0 * b) / a;
+    } else {
+        const double cc = quad_value(type, c, qx, qy, qz);
+        const double disc = b * b - a * cc;
+        if (!(disc > 0.0)) return dinf();
+        const double q = sqrt(disc);
+        if (!pos) {
+            t = (b <= 0.0) ? (q - b) / a : (-cc) / (b + q);
         } else {
-            double dz = qz - c[2];
-            a = (u * u + v * v) + w * w;
-            b = (dx * u + dy * v) + dz * w;
-        }
-        if (a == 0.0) return dinf();
-        if (on) {
-            if (!pos && b < 0.0) t = (-2.0 * b) / a;
-            else return dinf();
-        } else {
-            double cc = surf_value(type, c, qx, qy, qz);
-            double disc = b * b - a * cc;
-            if (!(disc > 0.0)) return dinf();
-            double q = sqrt(disc);
-            if (!pos) {
-                t = (b <= 0.0) ? (q - b) / a : (-cc) / (b + q);
-            } else {
-                if (b < 0.0) t = cc / (q - b);
-                else return dinf();
-            }
+            if (!(b < 0.0)) return dinf();
+            t = cc / (q - b);
         }
     }
     return (t > 0.0) ? t : 0.0;
@@ -200,7 +227,7 @@ __device__ int32_t search(const Dev &g, uint32_t u, double x, double y, double z
         int j = (int)floorf((gy - U.y0) * U.inv_py);
         i = min(max(i, 0), U.nx - 1);
         j = min(max(j, 0), U.ny - 1);
-        int32_t c = (int32_t)U.cell0 + j * U.nx + i;
+        const int32_t c = (int32_t)U.cell0 + j * U.nx + i;
         if (c != exclude && contains(g, (uint32_t)c, x, y, z, force_s, force_pos)) return c;
     }
     uint32_t n = U.node0;
@@ -225,7 +252,7 @@ __device__ int32_t search(const Dev &g, uint32_t u, double x, double y, double z
         if (lf == kLeafNone) { n++; continue; }
         const uint32_t first = lf >> 4, cnt = (lf & 15u) + 1;
         for (uint32_t k = 0; k < cnt; k++) {
-            uint32_t c = g.leaf[first + k];
+            const uint32_t c = g.leaf[first + k];
             if ((int32_t)c == exclude) continue;
             if (PREC == GT_PREC_MIXED) {
                 const float *b = g.cbox + 8 * (size_t)c;
@@ -239,15 +266,9 @@ __device__ int32_t search(const Dev &g, uint32_t u, double x, double y, double z
 }
 
 // ------------------------------------------------------------------ particle
-constexpr int kBlock = 256;       // lanes per workgroup of the one-history-per-lane kernels
-constexpr int kBlockP = 1024;     // lanes per workgroup of the persistent tracker (launch bound)
-
-// Per-lane state.  The cell of every level lives in LDS, one column per
-// lane (cell[L * blockDim.x]), so that level loops index it dynamically
-// without spilling and without unrolling the per-level search code.
 struct Particle {
     double x, y, z, u, v, w, tau;
-    uint32_t *cell;
+    uint32_t *cell;     // LDS column: cell of level L at cell[L * blockDim.x]
     int depth;
     int on_level;
     uint32_t on_surf;
@@ -300,12 +321,26 @@ __device__ __forceinline__ double distance_all(const Dev &g, const Particle &P, 
             qz = qz - t[2];
         }
         const Cell cc = g.cell[c];
-        for (uint32_t k = 0; k < cc.hs_n; k++) {
-            const uint32_t h = g.hs[cc.hs_off + k];
+        const uint32_t *hs = g.hs + cc.hs_off;
+        for (uint32_t k = 0; k < cc.n_pl; k++) {
+            const uint32_t h = hs[k];
+            const uint32_t s = h >> 4;
+            const bool pos = (h >> 3) & 1u;
+            if (P.on_level == L && P.on_surf == s) continue;   // a plane just crossed is not hit again
+            const double d = plane_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w);
+            if (d < bt || (d == bt && d != dinf() && L == bl && s < bs)) {
+                bt = d;
+                bl = L;
+                bs = s;
+                bpos = pos;
+            }
+        }
+        for (uint32_t k = cc.n_pl; k < cc.n_hs; k++) {
+            const uint32_t h = hs[k];
             const uint32_t s = h >> 4;
             const bool pos = (h >> 3) & 1u;
             const bool on = (P.on_level == L) && (P.on_surf == s);
-            const double d = hs_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w, on);
+            const double d = quad_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w, on);
             if (d < bt || (d == bt && d != dinf() && L == bl && s < bs)) {
                 bt = d;
                 bl = L;
@@ -317,9 +352,9 @@ __device__ __forceinline__ double distance_all(const Dev &g, const Particle &P, 
     return bt;
 }
 
-// cross_surface at level L* on surface s* (Alg. 8): the cell of that level's
-// universe on the other side (the old cell's sense on s* flipped), then
-// descent below it.  Returns an end code (GT_END_NONE if tracking goes on).
+// cross_surface at level L* on surface s* (Alg. 8) for the one-history-
+// per-lane schedule: the cell of that level's universe on the other side
+// (the old cell's sense on s* flipped), then descent below it.
 template <int PREC>
 __device__ __forceinline__ int cross(const Dev &g, Particle &P, int Ls, uint32_t ss, bool old_pos) {
     double qx = P.x, qy = P.y, qz = P.z;
@@ -351,44 +386,48 @@ __device__ __forceinline__ int cross(const Dev &g, Particle &P, int Ls, uint32_t
     return GT_END_NONE;
 }
 
-__device__ __forceinline__ void sample_direction(Stream &rng, double &u, double &v, double &w) {
-    double v1, v2, s;
-    for (;;) {
-        v1 = 2.0 * rng.u01() - 1.0;
-        v2 = 2.0 * rng.u01() - 1.0;
-        s = v1 * v1 + v2 * v2;
-        if (s < 1.0 && s != 0.0) break;
-    }
-    const double r = sqrt(1.0 - s);
-    u = (2.0 * v1) * r;
-    v = (2.0 * v2) * r;
-    w = 1.0 - 2.0 * s;
+// ------------------------------------------------------------------ tallies
+// Segment lengths are summed as 128-bit integers in units of 2^-96 cm.  In
+// the kernel a contribution is split into four 32-bit limbs, each added to
+// its own 64-bit counter with an atomic whose result is not used, so no
+// carry has to travel back to the lane; the counters are exact for up to
+// 2^32 contributions per instance and launch.  Each XCD adds into its own
+// replica of the counters, so the atomics stay in that XCD's L2; the
+// finalize kernel folds replicas and limbs into the 128-bit total.
+constexpr int kReplicas = 8;
+
+__device__ __forceinline__ uint32_t xcc_id() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kReplicas - 1);   // HW_REG_XCC_ID[3:0]
 }
 
-// 128-bit fixed-point accumulator of segment lengths, quantum 2^-96 cm
 struct TallyAcc {
     uint32_t inst;
-    uint64_t lo, hi;
+    uint64_t lo, hi;   // 128-bit register accumulator for consecutive segments in one instance
 };
 
-__device__ __forceinline__ void tally_flush(uint64_t *tfx, TallyAcc &a) {
+__device__ __forceinline__ void add_limb(uint64_t *p, uint64_t v) {
+    if (v) __hip_atomic_fetch_add((unsigned long long *)p, (unsigned long long)v, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void tally_flush(uint64_t *rep, TallyAcc &a) {
     if (a.inst == kNone) return;
-    unsigned long long *p = (unsigned long long *)(tfx + 2 * (size_t)a.inst);
-    const unsigned long long old = atomicAdd(p, (unsigned long long)a.lo);
-    const uint64_t carry = (old + a.lo < old) ? 1u : 0u;
-    const uint64_t h = a.hi + carry;
-    if (h) atomicAdd(p + 1, (unsigned long long)h);
+    uint64_t *p = rep + 4 * (size_t)a.inst;
+    add_limb(p + 0, a.lo & 0xFFFFFFFFull);
+    add_limb(p + 1, a.lo >> 32);
+    add_limb(p + 2, a.hi & 0xFFFFFFFFull);
+    add_limb(p + 3, a.hi >> 32);
     a.inst = kNone;
 }
 
-__device__ __forceinline__ void tally_add(uint64_t *tfx, TallyAcc &a, uint32_t inst, double l) {
+__device__ __forceinline__ void tally_add(uint64_t *rep, TallyAcc &a, uint32_t inst, double l) {
     const double v = l * 0x1p32;
     const double fl = floor(v);
     const double fr = v - fl;
     const uint64_t hi = (uint64_t)fl;
     const uint64_t lo = (uint64_t)(fr * 0x1p64);
     if (inst != a.inst) {
-        tally_flush(tfx, a);
+        tally_flush(rep, a);
         a.inst = inst;
         a.lo = lo;
         a.hi = hi;
@@ -404,27 +443,49 @@ struct Counts {
     uint64_t segments;
 };
 
-// One history: Alg. 2 with the toy transport.
+__device__ __forceinline__ void count_end(Counts &cnt, int end, uint32_t segs, bool recovf) {
+    cnt.segments += segs;
+    cnt.escaped += end == GT_END_ESCAPE;
+    cnt.capped += end == GT_END_CAP;
+    cnt.lost += end == GT_END_LOST;
+    cnt.segcap += end == GT_END_SEGCAP;
+    cnt.recovf += recovf;
+}
+
+__device__ __forceinline__ void add_counts(const Counts &c, uint64_t *counters) {
+    __shared__ unsigned long long sh[7];
+    if (threadIdx.x < 7) sh[threadIdx.x] = 0;
+    __syncthreads();
+    if (c.escaped) atomicAdd(&sh[GT_CNT_ESCAPED], (unsigned long long)c.escaped);
+    if (c.capped) atomicAdd(&sh[GT_CNT_CAPPED], (unsigned long long)c.capped);
+    if (c.lost) atomicAdd(&sh[GT_CNT_LOST], (unsigned long long)c.lost);
+    if (c.segcap) atomicAdd(&sh[GT_CNT_SEGCAP], (unsigned long long)c.segcap);
+    if (c.recovf) atomicAdd(&sh[GT_CNT_REC_OVERFLOW], (unsigned long long)c.recovf);
+    if (c.segments) atomicAdd(&sh[GT_CNT_SEGMENTS], (unsigned long long)c.segments);
+    if (c.rejected) atomicAdd(&sh[GT_CNT_REJECTED], (unsigned long long)c.rejected);
+    __syncthreads();
+    if (threadIdx.x < 7 && sh[threadIdx.x]) atomicAdd((unsigned long long *)&counters[threadIdx.x], sh[threadIdx.x]);
+}
+
+// ------------------------------------------------------------------ plain schedule
+// One history per lane: Alg. 2 with the toy transport, straight-line.
 template <int PREC>
-__device__ void run_history(const Dev &g, const KParams &p, const KOut &o, uint64_t local, uint32_t *cells,
-                            Counts &cnt) {
+__device__ void run_history(const Dev &g, const KParams &p, const KOut &o, uint64_t *rep, uint64_t local,
+                            uint32_t *cells, Counts &cnt) {
     Particle P;
     P.cell = cells;
-    Stream rng;
-    rng.key = p.seed;
-    rng.pid = p.first + local;
-    rng.gid = p.geom_id;
-    rng.k = 0;
-    rng.stash = 0;
+    const uint64_t pid = p.first + local;
+    uint32_t blk = 0;
     P.on_level = -1;
     P.on_surf = kNone;
     P.depth = 1;
     int end = GT_END_NONE;
+    double u0, u1, u2;
     // ---- birth
     if (p.source == 1) {
         const uint64_t n1 = p.ray_n1;
         const uint64_t n2 = (p.n + n1 - 1) / n1;
-        const uint64_t j = rng.pid % n1, k = rng.pid / n1;
+        const uint64_t j = pid % n1, k = pid / n1;
         const double hy = (g.hi[1] - g.lo[1]) / (double)n1;
         const double hz = (g.hi[2] - g.lo[2]) / (double)n2;
         P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * 0x1p-30;
@@ -444,9 +505,10 @@ __device__ void run_history(const Dev &g, const KParams &p, const KOut &o, uint6
     } else {
         int32_t c = -1;
         for (int a = 0; a < kMaxBirthAttempts && c < 0; a++) {
-            P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * rng.u01();
-            P.y = g.lo[1] + (g.hi[1] - g.lo[1]) * rng.u01();
-            P.z = g.lo[2] + (g.hi[2] - g.lo[2]) * rng.u01();
+            draw_block(p.seed, p.geom_id, pid, blk++, u0, u1, u2);
+            P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * u0;
+            P.y = g.lo[1] + (g.hi[1] - g.lo[1]) * u1;
+            P.z = g.lo[2] + (g.hi[2] - g.lo[2]) * u2;
             c = search<PREC>(g, g.root, P.x, P.y, P.z, kNone, false, -1, (float)P.x, (float)P.y);
             if (c < 0) cnt.rejected++;
         }
@@ -455,8 +517,9 @@ __device__ void run_history(const Dev &g, const KParams &p, const KOut &o, uint6
         } else {
             lvl(P, 0) = (uint32_t)c;
             if (!descend<PREC>(g, P, 0, P.x, P.y, P.z)) end = GT_END_LOST;
-            sample_direction(rng, P.u, P.v, P.w);
-            P.tau = -series_log(rng.u01());
+            do draw_block(p.seed, p.geom_id, pid, blk++, u0, u1, u2);
+            while (!direction_from(u0, u1, P.u, P.v, P.w));
+            P.tau = -series_log(u2);
         }
     }
     // ---- segments
@@ -492,7 +555,7 @@ __device__ void run_history(const Dev &g, const KParams &p, const KOut &o, uint6
         P.y = P.y + m1;
         P.z = P.z + m2;
         // tally and sequence
-        tally_add(o.tally_fx, acc, inst, l);
+        tally_add(rep, acc, inst, l);
         h = (h ^ ((uint64_t)inst + 1)) * kFnvPrime;
         if (recorded) {
             if (segs < p.rec_cap) rec[segs] = (int32_t)inst;
@@ -508,50 +571,42 @@ __device__ void run_history(const Dev &g, const KParams &p, const KOut &o, uint6
             if (ncoll >= p.max_coll) {
                 end = GT_END_CAP;
             } else {
-                sample_direction(rng, P.u, P.v, P.w);
-                P.tau = -series_log(rng.u01());
+                do draw_block(p.seed, p.geom_id, pid, blk++, u0, u1, u2);
+                while (!direction_from(u0, u1, P.u, P.v, P.w));
+                P.tau = -series_log(u2);
             }
         }
         if (end == GT_END_NONE && segs >= p.max_segs) end = GT_END_SEGCAP;
     }
-    tally_flush(o.tally_fx, acc);
+    tally_flush(rep, acc);
     h ^= (uint64_t)end;
     if (o.seg_count) o.seg_count[local] = segs;
     if (o.seq_hash) o.seq_hash[local] = h;
     if (o.end_code) o.end_code[local] = (uint8_t)end;
-    cnt.segments += segs;
-    cnt.escaped += end == GT_END_ESCAPE;
-    cnt.capped += end == GT_END_CAP;
-    cnt.lost += end == GT_END_LOST;
-    cnt.segcap += end == GT_END_SEGCAP;
-    cnt.recovf += recovf;
+    count_end(cnt, end, segs, recovf);
 }
 
-__device__ __forceinline__ void add_counts(const Counts &c, uint64_t *counters) {
-    __shared__ unsigned long long sh[7];
-    if (threadIdx.x < 7) sh[threadIdx.x] = 0;
-    __syncthreads();
-    if (c.escaped) atomicAdd(&sh[GT_CNT_ESCAPED], (unsigned long long)c.escaped);
-    if (c.capped) atomicAdd(&sh[GT_CNT_CAPPED], (unsigned long long)c.capped);
-    if (c.lost) atomicAdd(&sh[GT_CNT_LOST], (unsigned long long)c.lost);
-    if (c.segcap) atomicAdd(&sh[GT_CNT_SEGCAP], (unsigned long long)c.segcap);
-    if (c.recovf) atomicAdd(&sh[GT_CNT_REC_OVERFLOW], (unsigned long long)c.recovf);
-    if (c.segments) atomicAdd(&sh[GT_CNT_SEGMENTS], (unsigned long long)c.segments);
-    if (c.rejected) atomicAdd(&sh[GT_CNT_REJECTED], (unsigned long long)c.rejected);
-    __syncthreads();
-    if (threadIdx.x < 7 && sh[threadIdx.x]) atomicAdd((unsigned long long *)&counters[threadIdx.x], sh[threadIdx.x]);
+template <int PREC>
+__global__ void __launch_bounds__(kBlock) k_track(Dev g, KParams p, KOut o) {
+    __shared__ uint32_t cells[GT_MAX_LEVELS * kBlock];
+    uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
+    Counts cnt = {0, 0, 0, 0, 0, 0, 0};
+    const uint64_t local = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (local < p.n) run_history<PREC>(g, p, o, rep, local, cells + threadIdx.x, cnt);
+    add_counts(cnt, o.counters);
 }
 
-
-// ------------------------------------------------------------------ persistent tracker
-// Each lane runs a small state machine; a wave loops until the shared
-// particle pool is drained and all of its lanes are idle.  Finished lanes
-// are refilled at once from a wave-local pool of particle ids (ballot +
+// ------------------------------------------------------------------ persistent schedule
+// Each lane runs a state machine; a wave loops until the shared particle
+// pool is drained and all of its lanes are idle.  Finished lanes are
+// refilled at once from a wave-local pool of particle ids (ballot +
 // per-lane rank, one global atomic per 64 ids), so a wave no longer waits
-// for its longest history.  The candidate search, the sampling and the
-// segment step each have a single call site, so lanes that are at different
-// steps of their histories share one instruction stream per step.
-enum Mode : int { M_IDLE = 0, M_POS = 1, M_SEARCH = 2, M_SAMPLE = 3, M_TRACK = 4 };
+// for its longest history.  Per loop trip every lane takes at most one of
+// each step -- draw one random block (a birth position or a direction
+// attempt with its optical depth), search one level, one segment -- and
+// each step has one call site, so lanes at different points of their
+// histories share one instruction stream per step.
+enum Mode : int { M_IDLE = 0, M_POS = 1, M_DIR = 2, M_SEARCH = 3, M_TRACK = 4 };
 
 constexpr uint32_t kChunk = 64;
 
@@ -559,18 +614,52 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Copy the plan's sections of the device blob into LDS and point a Dev at
+// the copies (all lanes of the workgroup take part).  Every table the
+// precision mode reads is in the plan, so every pointer below is an LDS one.
 template <int PREC>
-__global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g, KParams p, KOut o) {
+__device__ __forceinline__ Dev stage_tables(const Dev &g, const StagePlan &sp, const unsigned char *blob,
+                                            unsigned char *lds) {
+    for (uint32_t k = 0; k < sp.n; k++) {
+        const uint4 *src = (const uint4 *)(blob + sp.src[k]);
+        uint4 *dst = (uint4 *)(lds + sp.dst[k]);
+        for (uint32_t i = threadIdx.x; i < sp.bytes[k] / 16; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+    Dev d = g;
+    d.coef = (const double *)(lds + sp.coef);
+    d.hs = (const uint32_t *)(lds + sp.hs);
+    d.cell = (const Cell *)(lds + sp.cell);
+    d.trans = (const double *)(lds + sp.trans);
+    d.univ = (const Univ *)(lds + sp.univ);
+    d.leaf = (const uint32_t *)(lds + sp.leaf);
+    if (PREC == GT_PREC_MIXED) {
+        d.node32 = (const Node32 *)(lds + sp.node32);
+        d.cbox = (const float *)(lds + sp.cbox);
+    } else {
+        d.node64 = (const Node64 *)(lds + sp.node64);
+    }
+    d.sigma = (const double *)(lds + sp.sigma);
+    return d;
+}
+
+template <int PREC, bool STAGED>
+__global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p, KOut o, StagePlan sp) {
     __shared__ uint32_t cells[GT_MAX_LEVELS * kBlockP];
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_tables[];
+    const Dev g = STAGED ? stage_tables<PREC>(g0, sp, (const unsigned char *)g0.coef, lds_tables) : g0;
     unsigned long long *queue = (unsigned long long *)&o.counters[7];
+    uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     Particle P;
     P.cell = cells + threadIdx.x;
-    Stream rng;
-    rng.key = p.seed;
-    rng.gid = p.geom_id;
+    P.x = P.y = P.z = P.u = P.v = P.w = P.tau = 0.0;
+    P.depth = 1;
+    P.on_level = -1;
+    P.on_surf = kNone;
     int mode = M_IDLE;
-    uint64_t local = 0;
+    uint64_t local = 0, pid = 0;
+    uint32_t blk = 0;
     // history state
     uint64_t h = 0;
     uint32_t segs = 0, ncoll = 0, attempts = 0;
@@ -608,8 +697,8 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g, KParams p, 
                 const uint32_t r = lane_rank(idle);
                 if (mode == M_IDLE && r < avail) {
                     local = pool_next + r;
-                    rng.pid = p.first + local;
-                    rng.k = 0;
+                    pid = p.first + local;
+                    blk = 0;
                     h = kFnvOffset;
                     segs = ncoll = attempts = 0;
                     recovf = false;
@@ -627,12 +716,12 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g, KParams p, 
         }
         if (__ballot(mode != M_IDLE) == 0) break;
 
-        // ---- birth position (uniform in the box, retried until a root cell has it)
-        if (mode == M_POS) {
-            if (p.source == 1) {
+        // ---- draw: a birth-position attempt, or a direction attempt and its optical depth
+        if (mode == M_POS || mode == M_DIR) {
+            if (mode == M_POS && p.source == 1) {
                 const uint64_t n1 = p.ray_n1;
                 const uint64_t n2 = (p.n + n1 - 1) / n1;
-                const uint64_t j = rng.pid % n1, k = rng.pid / n1;
+                const uint64_t j = pid % n1, k = pid / n1;
                 const double hy = (g.hi[1] - g.lo[1]) / (double)n1;
                 const double hz = (g.hi[2] - g.lo[2]) / (double)n2;
                 P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * 0x1p-30;
@@ -642,25 +731,33 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g, KParams p, 
                 P.v = 0.0;
                 P.w = 0.0;
                 P.tau = 0.0;
-                mode = M_SEARCH;
-            } else if (attempts >= (uint32_t)kMaxBirthAttempts) {
+            } else if (mode == M_POS && attempts >= (uint32_t)kMaxBirthAttempts) {
                 end = GT_END_LOST;
             } else {
-                P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * rng.u01();
-                P.y = g.lo[1] + (g.hi[1] - g.lo[1]) * rng.u01();
-                P.z = g.lo[2] + (g.hi[2] - g.lo[2]) * rng.u01();
-                attempts++;
+                double u0, u1, u2;
+                draw_block(p.seed, p.geom_id, pid, blk++, u0, u1, u2);
+                if (mode == M_POS) {
+                    P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * u0;
+                    P.y = g.lo[1] + (g.hi[1] - g.lo[1]) * u1;
+                    P.z = g.lo[2] + (g.hi[2] - g.lo[2]) * u2;
+                    attempts++;
+                } else if (direction_from(u0, u1, P.u, P.v, P.w)) {
+                    P.tau = -series_log(u2);
+                    mode = M_TRACK;
+                }
+            }
+            if (mode == M_POS && end == GT_END_NONE) {
+                sL = 0;
+                su = g.root;
+                sforce = kNone;
+                sexcl = -1;
+                qx = P.x;
+                qy = P.y;
+                qz = P.z;
+                gx = (float)qx;
+                gy = (float)qy;
                 mode = M_SEARCH;
             }
-            sL = 0;
-            su = g.root;
-            sforce = kNone;
-            sexcl = -1;
-            qx = P.x;
-            qy = P.y;
-            qz = P.z;
-            gx = (float)qx;
-            gy = (float)qy;
         }
 
         // ---- one level of find_cell / cross_surface
@@ -691,20 +788,13 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g, KParams p, 
                     P.depth = sL + 1;
                     if (birth) {
                         birth = false;
-                        mode = p.source == 1 ? M_TRACK : M_SAMPLE;
+                        mode = p.source == 1 ? M_TRACK : M_DIR;
                     } else {
                         if (segs >= p.max_segs) end = GT_END_SEGCAP;
                         mode = M_TRACK;
                     }
                 }
             }
-        }
-
-        // ---- change_direction and a new optical depth
-        if (mode == M_SAMPLE && end == GT_END_NONE) {
-            sample_direction(rng, P.u, P.v, P.w);
-            P.tau = -series_log(rng.u01());
-            mode = M_TRACK;
         }
 
         // ---- one segment: distance_to_surface, move, tally, then crossing or collision
@@ -732,7 +822,7 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g, KParams p, 
                 P.x = P.x + m0;
                 P.y = P.y + m1;
                 P.z = P.z + m2;
-                tally_add(o.tally_fx, acc, inst, l);
+                tally_add(rep, acc, inst, l);
                 h = (h ^ ((uint64_t)inst + 1)) * kFnvPrime;
                 if (local < p.rec_k) {
                     if (segs < p.rec_cap) o.rec[local * (uint64_t)p.rec_cap + segs] = (int32_t)inst;
@@ -775,39 +865,26 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g, KParams p, 
                     ncoll++;
                     if (ncoll >= p.max_coll) end = GT_END_CAP;
                     else if (segs >= p.max_segs) end = GT_END_SEGCAP;
-                    else mode = M_SAMPLE;
+                    else mode = M_DIR;
                 }
             }
         }
 
         // ---- history finished: outputs, then the lane is free
         if (mode != M_IDLE && end != GT_END_NONE) {
-            tally_flush(o.tally_fx, acc);
+            tally_flush(rep, acc);
             h ^= (uint64_t)end;
             if (o.seg_count) o.seg_count[local] = segs;
             if (o.seq_hash) o.seq_hash[local] = h;
             if (o.end_code) o.end_code[local] = (uint8_t)end;
-            cnt.segments += segs;
-            cnt.escaped += end == GT_END_ESCAPE;
-            cnt.capped += end == GT_END_CAP;
-            cnt.lost += end == GT_END_LOST;
-            cnt.segcap += end == GT_END_SEGCAP;
-            cnt.recovf += recovf;
+            count_end(cnt, end, segs, recovf);
             mode = M_IDLE;
         }
     }
     add_counts(cnt, o.counters);
 }
 
-template <int PREC>
-__global__ void __launch_bounds__(kBlock) k_track(Dev g, KParams p, KOut o) {
-    __shared__ uint32_t cells[GT_MAX_LEVELS * kBlock];
-    Counts cnt = {0, 0, 0, 0, 0, 0, 0};
-    const uint64_t local = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (local < p.n) run_history<PREC>(g, p, o, local, cells + threadIdx.x, cnt);
-    add_counts(cnt, o.counters);
-}
-
+// ------------------------------------------------------------------ small kernels
 __global__ void k_fill_u64(uint64_t *a, uint64_t n, uint64_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         a[i] = v;
@@ -818,10 +895,33 @@ __global__ void k_fill_i32(int32_t *a, uint64_t n, int32_t v) {
         a[i] = v;
 }
 
-// fixed point (units of 2^-96 cm) to double: high word * 2^-32 + low * 2^-96
-__global__ void k_finalize(const uint64_t *tfx, double *tally, uint64_t n) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        tally[i] = (double)tfx[2 * i + 1] * 0x1p-32 + (double)tfx[2 * i] * 0x1p-96;
+// Fold the replicas' limb counters into the 128-bit fixed-point total (plus
+// the previous total when accumulating), then convert it to cm:
+// high word * 2^-32 + low word * 2^-96.
+__global__ void k_finalize(const uint64_t *ws, uint64_t *tfx, double *tally, uint64_t n, int accumulate) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t lo = accumulate ? tfx[2 * i] : 0, hi = accumulate ? tfx[2 * i + 1] : 0;
+        for (int r = 0; r < kReplicas; r++) {
+            const uint64_t *L = ws + ((size_t)r * n + i) * 4;
+            for (int k = 0; k < 4; k++) {
+                // add L[k] * 2^(32 k) to (hi, lo) modulo 2^128
+                const uint64_t v = L[k];
+                uint64_t add_lo, add_hi;
+                switch (k) {
+                case 0: add_lo = v; add_hi = 0; break;
+                case 1: add_lo = v << 32; add_hi = v >> 32; break;
+                case 2: add_lo = 0; add_hi = v; break;
+                default: add_lo = 0; add_hi = v << 32; break;
+                }
+                const uint64_t nlo = lo + add_lo;
+                hi += add_hi + (nlo < lo ? 1u : 0u);
+                lo = nlo;
+            }
+        }
+        tfx[2 * i] = lo;
+        tfx[2 * i + 1] = hi;
+        if (tally) tally[i] = (double)hi * 0x1p-32 + (double)lo * 0x1p-96;
+    }
 }
 
 template <int PREC>
@@ -893,6 +993,7 @@ __global__ void k_fp64_check(const double *a, const double *b, uint64_t n, doubl
     l[i] = series_log(b[i]);
 }
 
+// ------------------------------------------------------------------ launchers
 inline int hip_check(hipError_t e, const char *what) {
     if (e == hipSuccess) return GT_OK;
     set_error("%s: %s", what, hipGetErrorString(e));
@@ -910,20 +1011,22 @@ inline unsigned fill_grid(uint64_t n) {
 }
 
 // Workgroups that fit on the device at once (all compute units, the
-// occupancy the kernel's resources allow), cached per device and block size.
-int persistent_grid(const void *kernel, unsigned block, int device, int *blocks) {
+// occupancy the kernel's resources allow), cached per device, kernel, block
+// size and dynamic LDS size.
+int persistent_grid(const void *kernel, unsigned block, unsigned dyn, int device, int *blocks) {
     static int cache_dev[64], cache_block[64], cache_n[64];
+    static unsigned cache_dyn[64];
     static const void *cache_k[64];
     static int used = 0;
     for (int i = 0; i < used; i++)
-        if (cache_k[i] == kernel && cache_dev[i] == device && cache_block[i] == (int)block) {
+        if (cache_k[i] == kernel && cache_dev[i] == device && cache_block[i] == (int)block && cache_dyn[i] == dyn) {
             *blocks = cache_n[i];
             return GT_OK;
         }
     int cus = 0, per = 0;
     int rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
     if (rc) return rc;
-    rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, (int)block, 0),
+    rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, (int)block, dyn),
                    "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (rc) return rc;
     if (per < 1) per = 1;
@@ -932,9 +1035,23 @@ int persistent_grid(const void *kernel, unsigned block, int device, int *blocks)
         cache_k[used] = kernel;
         cache_dev[used] = device;
         cache_block[used] = (int)block;
+        cache_dyn[used] = dyn;
         cache_n[used] = *blocks;
         used++;
     }
+    return GT_OK;
+}
+
+// Let a kernel use up to `bytes` of dynamic LDS (once per kernel).
+int allow_dynamic_lds(const void *kernel, unsigned bytes) {
+    static const void *done[16];
+    static int used = 0;
+    for (int i = 0; i < used; i++)
+        if (done[i] == kernel) return GT_OK;
+    int rc = hip_check(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes),
+                       "hipFuncSetAttribute");
+    if (rc) return rc;
+    if (used < 16) done[used++] = kernel;
     return GT_OK;
 }
 
@@ -953,15 +1070,14 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
     kp.rec_cap = p->record_cap;
     kp.pad = 0;
     KOut ko;
-    ko.tally_fx = o->tally_fx;
+    ko.tally_ws = g->tally_ws;
     ko.seg_count = o->seg_count;
     ko.seq_hash = o->seq_hash;
     ko.end_code = o->end_code;
     ko.rec = o->rec;
     ko.counters = o->counters;
-    if (!(p->flags & GT_FLAG_ACCUMULATE))
-        hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(2 * g->n_inst)), dim3(256), 0, st, o->tally_fx, 2 * g->n_inst,
-                           (uint64_t)0);
+    const uint64_t nws = (uint64_t)kReplicas * 4 * g->n_inst;
+    hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(nws)), dim3(256), 0, st, g->tally_ws, nws, (uint64_t)0);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, o->counters, (uint64_t)8, (uint64_t)0);
     if (kp.rec_k) {
         const uint64_t nrec = (uint64_t)kp.rec_k * kp.rec_cap;
@@ -973,16 +1089,29 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
             hipLaunchKernelGGL((k_track<PREC>), dim3(grid_for(kp.n, block)), dim3(block), 0, st, g->dev, kp, ko);
         } else {
             const unsigned block = p->block_size ? p->block_size : kBlockP;
+            const StagePlan &sp = g->stage[PREC];
+            const bool staged = !(p->flags & GT_FLAG_NO_STAGING) && sp.total <= kStageBudget;
+            const void *kern = staged ? (const void *)k_track_persistent<PREC, true>
+                                      : (const void *)k_track_persistent<PREC, false>;
+            const unsigned dyn = staged ? sp.total : 0;
+            int rc = GT_OK;
+            if (staged) rc = allow_dynamic_lds(kern, kStageBudget);
+            if (rc) return rc;
             int blocks = 0;
-            int rc = persistent_grid((const void *)k_track_persistent<PREC>, block, g->device, &blocks);
+            rc = persistent_grid(kern, block, dyn, g->device, &blocks);
             if (rc) return rc;
             const uint64_t need = (kp.n + block - 1) / block;
             if ((uint64_t)blocks > need) blocks = (int)need;
-            hipLaunchKernelGGL((k_track_persistent<PREC>), dim3(blocks), dim3(block), 0, st, g->dev, kp, ko);
+            if (staged)
+                hipLaunchKernelGGL((k_track_persistent<PREC, true>), dim3(blocks), dim3(block), dyn, st, g->dev, kp, ko,
+                                   sp);
+            else
+                hipLaunchKernelGGL((k_track_persistent<PREC, false>), dim3(blocks), dim3(block), 0, st, g->dev, kp, ko,
+                                   sp);
         }
     }
-    if (o->tally)
-        hipLaunchKernelGGL(k_finalize, dim3(fill_grid(g->n_inst)), dim3(256), 0, st, o->tally_fx, o->tally, g->n_inst);
+    hipLaunchKernelGGL(k_finalize, dim3(fill_grid(g->n_inst)), dim3(256), 0, st, (const uint64_t *)g->tally_ws,
+                       o->tally_fx, o->tally, g->n_inst, (int)((p->flags & GT_FLAG_ACCUMULATE) != 0));
     return hip_check(hipGetLastError(), "gt_track launch");
 }
 

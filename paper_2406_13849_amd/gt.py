@@ -23,6 +23,7 @@ MAX_LEVELS = 6
 PREC_FP64, PREC_MIXED = 0, 1
 FLAG_ACCUMULATE = 1
 FLAG_LANE_PER_HISTORY = 2
+FLAG_NO_STAGING = 4
 END_NONE, END_ESCAPE, END_CAP, END_LOST, END_SEGCAP = 0, 1, 2, 3, 4
 COUNTERS = ("escaped", "capped", "lost", "segcap", "rec_overflow", "segments", "rejected", "spare")
 
@@ -190,17 +191,19 @@ def alloc_outputs(geom: Geometry, n: int, record_first_k: int = 0, record_cap: i
 def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 0, geometry_id: int = 0,
           max_collisions: int = 20, source: int = 0, ray_n1: int = 0, max_segments: int = 100_000,
           precision: int = PREC_MIXED, record_first_k: int = 0, record_cap: int = 0, accumulate: bool = False,
-          lane_per_history: bool = False, block_size: int = 0, out: Optional[TrackOutputs] = None,
-          stream=None) -> TrackOutputs:
+          lane_per_history: bool = False, staging: bool = True, block_size: int = 0,
+          out: Optional[TrackOutputs] = None, stream=None) -> TrackOutputs:
     """gt_track: sample and track n_particles histories (asynchronous).
     lane_per_history selects the plain one-history-per-lane schedule instead
-    of the persistent refilling one."""
+    of the persistent refilling one; staging=False keeps the geometry tables
+    in global memory even when they fit in LDS."""
     if out is None:
         out = alloc_outputs(geom, n_particles, record_first_k, record_cap)
     prm = _Params(seed=seed, first_particle=first_particle, n_particles=n_particles, geometry_id=geometry_id,
                   max_collisions=max_collisions, source=source, ray_n1=ray_n1, max_segments=max_segments,
                   precision=precision, record_first_k=record_first_k, record_cap=record_cap,
-                  flags=(FLAG_ACCUMULATE if accumulate else 0) | (FLAG_LANE_PER_HISTORY if lane_per_history else 0),
+                  flags=(FLAG_ACCUMULATE if accumulate else 0) | (FLAG_LANE_PER_HISTORY if lane_per_history else 0)
+                  | (0 if staging else FLAG_NO_STAGING),
                   block_size=block_size)
     o = _Out(tally_fx=_ptr(out.tally_fx), tally=_ptr(out.tally), seg_count=_ptr(out.seg_count),
              seq_hash=_ptr(out.seq_hash), end_code=_ptr(out.end_code), rec=_ptr(out.rec),

@@ -142,6 +142,19 @@ def test_track_parity(case, prec, lane):
     assert_parity(g, o, where="cfg %s prec %d" % (cfg, prec))
 
 
+@pytest.mark.parametrize("cfg", ["sphere", 1, 2, 3])
+@pytest.mark.parametrize("prec", [gt.PREC_FP64, gt.PREC_MIXED])
+def test_global_tables_match_staged(cfg, prec):
+    """The persistent tracker reading the geometry from global memory gives
+    the oracle's results too (cfg3 is always read from global memory: its
+    tables exceed the LDS budget)."""
+    fg, G, O = geoms(cfg)
+    kw = dict(seed=4242, n_particles=6000, geometry_id=5)
+    g = gpu_track(G, precision=prec, staging=False, record_first_k=100, record_cap=64, **kw)
+    o = oracle.track(O, oracle.TrackParams(record_first_k=100, record_cap=64, **kw), n_threads=NT)
+    assert_parity(g, o, where="global tables cfg %s" % cfg)
+
+
 @pytest.mark.parametrize("cfg,n1,n2", [(1, 3000, 1), (2, 1700, 22)])
 def test_ray_mode_parity(cfg, n1, n2):
     fg, G, O = geoms(cfg)

@@ -75,11 +75,12 @@ def test_philox_matches_rocrand_library():
 
 
 def test_u01_exact_and_open_interval():
-    assert oracle.u01(0) == 2.0 ** -53
-    assert oracle.u01(2 ** 64 - 1) == 1.0 - 2.0 ** -53
-    assert oracle.u01(1 << 63) == 0.5 + 2.0 ** -53
-    for w in (0x123456789ABCDEF0, 0xFFF, 0x1000):
-        assert oracle.u01(w) == ((w >> 12) + 0.5) / 2.0 ** 52  # exact: both sides representable
+    """42-bit fields map to (f + 1/2) 2^-42: exact, never 0 or 1."""
+    assert oracle.u01(0) == 2.0 ** -43
+    assert oracle.u01(2 ** 42 - 1) == 1.0 - 2.0 ** -43
+    assert oracle.u01(1 << 41) == 0.5 + 2.0 ** -43
+    for f in (0x123456789AB, 0xFFF, 0x1000):
+        assert oracle.u01(f) == (f + 0.5) / 2.0 ** 42  # exact: both sides representable
 
 
 def _ulp_diff(a, b):
@@ -116,19 +117,24 @@ def test_mc_log_monotone_and_powers_of_two():
 
 
 def test_uniform_moments_and_chi2():
-    """u01 of the Philox words of many particles: mean, variance and a
-    64-bin chi-square within generous bounds."""
+    """The three 42-bit fields of the first Philox block of many particles
+    (the birth position in a box that accepts everything): mean, variance,
+    a 64-bin chi-square, and no correlation between the fields."""
     g = synth.box((1.0, 1.0, 1.0))
     og = oracle.OracleGeometry(g)
     p = oracle.TrackParams(seed=99, n_particles=200_000, geometry_id=3)
     pos, d, tau, inst = oracle.sample_births(og, p)
-    x = (pos[:, 0] + 1.0) / 2.0   # first uniform of each particle (box accepts everything)
-    assert abs(x.mean() - 0.5) < 5 * math.sqrt(1 / 12 / x.size)
-    assert abs(x.var() - 1 / 12) < 0.003
-    h, _ = np.histogram(x, bins=64, range=(0, 1))
-    e = x.size / 64
-    chi2 = ((h - e) ** 2 / e).sum()
-    assert chi2 < 63 + 6 * math.sqrt(2 * 63)
+    u = (pos + 1.0) / 2.0   # the three fields of each particle's first block
+    for k in range(3):
+        x = u[:, k]
+        assert abs(x.mean() - 0.5) < 5 * math.sqrt(1 / 12 / x.size)
+        assert abs(x.var() - 1 / 12) < 0.003
+        h, _ = np.histogram(x, bins=64, range=(0, 1))
+        e = x.size / 64
+        chi2 = ((h - e) ** 2 / e).sum()
+        assert chi2 < 63 + 6 * math.sqrt(2 * 63)
+    c = np.corrcoef(u.T)
+    assert np.all(np.abs(c[np.triu_indices(3, 1)]) < 5 / math.sqrt(u.shape[0]))
 
 
 def test_direction_isotropic_unit_vectors():
@@ -176,3 +182,23 @@ def test_birth_position_uniform_and_rejection():
     for q in (0.25, 0.5, 0.75):
         assert abs((r2 <= q).mean() - q) < 5 * math.sqrt(q * (1 - q) / r2.size)
     assert abs(pos[:, 2].mean()) < 5 * 200 / math.sqrt(12 * r2.size)
+
+
+def test_block_field_layout_matches_philox():
+    """A birth position in the box [-1,1]^3 (which accepts every point) is
+    x = -1 + 2 (f0 + 1/2) 2^-42 etc., so the fields can be recovered exactly
+    and compared with the bits of Philox4x32-10 at counter (0, pid lo,
+    pid hi, geometry id) under the seed as key."""
+    g = synth.box((1.0, 1.0, 1.0))
+    og = oracle.OracleGeometry(g)
+    seed, gid = 0x0123456789ABCDEF, 77
+    p = oracle.TrackParams(seed=seed, n_particles=50, first_particle=(5 << 32) + 3, geometry_id=gid)
+    pos, _, _, _ = oracle.sample_births(og, p)
+    for i in range(50):
+        pid = (5 << 32) + 3 + i
+        o = oracle.philox4x32_10([0, pid & 0xFFFFFFFF, pid >> 32, gid], [seed & 0xFFFFFFFF, seed >> 32])
+        bits = int(o[0]) | int(o[1]) << 32 | int(o[2]) << 64 | int(o[3]) << 96
+        fields = [(bits >> (42 * k)) & ((1 << 42) - 1) for k in range(3)]
+        for k in range(3):
+            f = (pos[i, k] + 1.0) / 2.0 * 2.0 ** 42 - 0.5
+            assert f == fields[k]
