@@ -489,24 +489,66 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
                 cb[8 * (size_t)c + 4 + k] = b.is_empty() ? -INFINITY : round_up(b.hi[k]);
             }
         }
+        // crossing candidates per half-space entry (device order): cells of the
+        // same universe that use the surface with the other sense and whose
+        // widened boxes overlap this cell's box, largest overlap first
+        std::vector<std::vector<std::pair<uint32_t, bool>>> users(F.n_surfaces);
+        for (uint32_t c = 0; c < F.n_cells; c++)
+            for (uint32_t k = F.cell_hs_off[c]; k < F.cell_hs_off[c + 1]; k++)
+                users[B.surf_of(F.hs[k])].push_back({c, F.hs[k] > 0});
+        std::vector<uint32_t> adj_off(F.n_halfspaces + 1, 0), adj;
+        for (uint32_t c = 0; c < F.n_cells; c++) {
+            const Box &bc = B.cbox[c];
+            for (uint32_t k = F.cell_hs_off[c]; k < F.cell_hs_off[c + 1]; k++) {
+                adj_off[k] = (uint32_t)adj.size();
+                if (bc.is_empty()) continue;
+                const uint32_t s = hs[k] >> 4;
+                const bool pos = (hs[k] >> 3) & 1u;
+                std::vector<std::pair<double, uint32_t>> cand;
+                for (const auto &us : users[s]) {
+                    if (us.first == c || us.second == pos) continue;
+                    const Box &bd = B.cbox[us.first];
+                    if (bd.is_empty()) continue;
+                    double v = 1.0;
+                    for (int ax = 0; ax < 3; ax++) {
+                        const double w = std::min(bc.hi[ax], bd.hi[ax]) - std::max(bc.lo[ax], bd.lo[ax]);
+                        v = w < 0 ? -1.0 : v * w;
+                        if (v < 0) break;
+                    }
+                    if (v >= 0) cand.push_back({v, us.first});
+                }
+                std::stable_sort(cand.begin(), cand.end(),
+                                 [](const std::pair<double, uint32_t> &x, const std::pair<double, uint32_t> &y) {
+                                     return x.first > y.first;
+                                 });
+                for (size_t i = 0; i < cand.size() && i < 16; i++) adj.push_back(cand[i].second);
+            }
+        }
+        adj_off[F.n_halfspaces] = (uint32_t)adj.size();
+        std::vector<uint32_t> cell_local(F.n_cells);
+        for (uint32_t c = 0; c < F.n_cells; c++) cell_local[c] = c - F.univ_cell_off[B.cell_univ[c]];
         // one blob
-        size_t off[10], sz[10];
-        sz[0] = coef.size() * 8;
-        sz[1] = hs.size() * 4;
-        sz[2] = cell.size() * sizeof(Cell);
-        sz[3] = trans.size() * 8;
-        sz[4] = B.univ.size() * sizeof(Univ);
-        sz[5] = B.n32.size() * sizeof(Node32);
-        sz[6] = B.n64.size() * sizeof(Node64);
-        sz[7] = B.leaf.size() * 4;
-        sz[8] = cb.size() * 4;
-        sz[9] = (size_t)F.n_materials * 8;
+        size_t off[SEC_COUNT], sz[SEC_COUNT];
+        sz[SEC_COEF] = coef.size() * 8;
+        sz[SEC_HS] = hs.size() * 4;
+        sz[SEC_CELL] = cell.size() * sizeof(Cell);
+        sz[SEC_TRANS] = trans.size() * 8;
+        sz[SEC_UNIV] = B.univ.size() * sizeof(Univ);
+        sz[SEC_NODE32] = B.n32.size() * sizeof(Node32);
+        sz[SEC_NODE64] = B.n64.size() * sizeof(Node64);
+        sz[SEC_LEAF] = B.leaf.size() * 4;
+        sz[SEC_CBOX] = cb.size() * 4;
+        sz[SEC_SIGMA] = (size_t)F.n_materials * 8;
+        sz[SEC_ADJOFF] = adj_off.size() * 4;
+        sz[SEC_ADJ] = adj.size() * 4;
+        sz[SEC_LOCAL] = cell_local.size() * 4;
         size_t total = 0;
-        for (int i = 0; i < 10; i++) { off[i] = total; total = align_up(total + std::max(sz[i], (size_t)1)); }
+        for (int i = 0; i < SEC_COUNT; i++) { off[i] = total; total = align_up(total + std::max(sz[i], (size_t)16)); }
         std::vector<unsigned char> img(total, 0);
-        const void *src[10] = {coef.data(), hs.data(), cell.data(), trans.data(), B.univ.data(),
-                               B.n32.data(), B.n64.data(), B.leaf.data(), cb.data(), F.sigma_t};
-        for (int i = 0; i < 10; i++)
+        const void *src[SEC_COUNT] = {coef.data(), hs.data(), cell.data(), trans.data(), B.univ.data(),
+                                      B.n32.data(), B.n64.data(), B.leaf.data(), cb.data(), F.sigma_t,
+                                      adj_off.data(), adj.data(), cell_local.data()};
+        for (int i = 0; i < SEC_COUNT; i++)
             if (sz[i]) std::memcpy(img.data() + off[i], src[i], sz[i]);
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess) return set_error("hipGetDevice failed"), GT_EHIP;
@@ -527,16 +569,19 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         }
         gt_geometry *g = new gt_geometry;
         unsigned char *base = (unsigned char *)blob;
-        g->dev.coef = (const double *)(base + off[0]);
-        g->dev.hs = (const uint32_t *)(base + off[1]);
-        g->dev.cell = (const Cell *)(base + off[2]);
-        g->dev.trans = (const double *)(base + off[3]);
-        g->dev.univ = (const Univ *)(base + off[4]);
-        g->dev.node32 = (const Node32 *)(base + off[5]);
-        g->dev.node64 = (const Node64 *)(base + off[6]);
-        g->dev.leaf = (const uint32_t *)(base + off[7]);
-        g->dev.cbox = (const float *)(base + off[8]);
-        g->dev.sigma = (const double *)(base + off[9]);
+        g->dev.coef = (const double *)(base + off[SEC_COEF]);
+        g->dev.hs = (const uint32_t *)(base + off[SEC_HS]);
+        g->dev.cell = (const Cell *)(base + off[SEC_CELL]);
+        g->dev.trans = (const double *)(base + off[SEC_TRANS]);
+        g->dev.univ = (const Univ *)(base + off[SEC_UNIV]);
+        g->dev.node32 = (const Node32 *)(base + off[SEC_NODE32]);
+        g->dev.node64 = (const Node64 *)(base + off[SEC_NODE64]);
+        g->dev.leaf = (const uint32_t *)(base + off[SEC_LEAF]);
+        g->dev.cbox = (const float *)(base + off[SEC_CBOX]);
+        g->dev.sigma = (const double *)(base + off[SEC_SIGMA]);
+        g->dev.adj_off = (const uint32_t *)(base + off[SEC_ADJOFF]);
+        g->dev.adj = (const uint32_t *)(base + off[SEC_ADJ]);
+        g->dev.cell_local = (const uint32_t *)(base + off[SEC_LOCAL]);
         g->dev.root = F.root;
         g->dev.n_inst = (uint32_t)B.ninst[F.root];
         g->dev.max_depth = B.depth[F.root];
@@ -546,18 +591,16 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         for (int prec = 0; prec < 2; prec++) {
             StagePlan &P = g->stage[prec];
             std::memset(&P, 0, sizeof P);
-            uint32_t *slot[10] = {&P.coef, &P.hs, &P.cell, &P.trans, &P.univ, &P.node32, &P.node64, &P.leaf, &P.cbox,
-                                  &P.sigma};
             uint64_t at = 0;
-            for (int i = 0; i < 10; i++) {
-                bool need = prec == GT_PREC_MIXED ? (i != 6) : (i != 5 && i != 8);
-                *slot[i] = 0xFFFFFFFFu;
+            for (int i = 0; i < SEC_COUNT; i++) {
+                const bool need = prec == GT_PREC_MIXED ? (i != SEC_NODE64) : (i != SEC_NODE32 && i != SEC_CBOX);
+                P.at[i] = 0xFFFFFFFFu;
                 if (!need) continue;
                 const uint64_t b = (std::max<size_t>(sz[i], 16) + 15) & ~(uint64_t)15;
                 P.src[P.n] = (uint32_t)off[i];
                 P.dst[P.n] = (uint32_t)at;
                 P.bytes[P.n] = (uint32_t)b;
-                *slot[i] = (uint32_t)at;
+                P.at[i] = (uint32_t)at;
                 P.n++;
                 at += b;
             }

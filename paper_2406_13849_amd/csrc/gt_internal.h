@@ -70,18 +70,25 @@ struct Dev {
     const uint32_t *leaf;   // leaf cell ids
     const float *cbox;      // 8 per cell: lo xyz, 0, hi xyz, 0 (single precision, outward)
     const double *sigma;
+    const uint32_t *adj_off;    // per half-space entry: first candidate in adj (n_hs + 1 entries)
+    const uint32_t *adj;        // crossing candidates: cells using the surface with the other sense
+                                // whose widened boxes touch the cell's box, largest overlap first
+    const uint32_t *cell_local; // index of each cell within its universe
     uint32_t root, n_inst, max_depth, n_cells;
     double lo[3], hi[3];
 };
 
+// Blob sections (all 256-byte aligned in one device allocation)
+enum Section { SEC_COEF, SEC_HS, SEC_CELL, SEC_TRANS, SEC_UNIV, SEC_NODE32, SEC_NODE64, SEC_LEAF, SEC_CBOX,
+               SEC_SIGMA, SEC_ADJOFF, SEC_ADJ, SEC_LOCAL, SEC_COUNT };
+
 // Copy of a geometry's hot tables into LDS: sections of the device blob
 // (byte offsets, 16-byte multiples) and where each lands in LDS.
 struct StagePlan {
-    uint32_t n;             // number of sections
-    uint32_t total;         // LDS bytes
-    uint32_t src[10], dst[10], bytes[10];
-    // LDS byte offsets of each table (kNotStaged when absent)
-    uint32_t coef, hs, cell, trans, univ, node32, node64, leaf, cbox, sigma;
+    uint32_t n;                 // number of sections copied
+    uint32_t total;             // LDS bytes
+    uint32_t src[SEC_COUNT], dst[SEC_COUNT], bytes[SEC_COUNT];
+    uint32_t at[SEC_COUNT];     // LDS byte offset of each section (0xFFFFFFFF when not copied)
 };
 
 struct KParams {

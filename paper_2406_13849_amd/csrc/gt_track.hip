@@ -306,11 +306,13 @@ __device__ __forceinline__ uint32_t leaf_instance(const Dev &g, const Particle &
 
 // distance_to_surface over every level; ties resolve to the smallest
 // (distance, level, surface id), i.e. the top-most level on the surface.
-__device__ __forceinline__ double distance_all(const Dev &g, const Particle &P, int &bl, uint32_t &bs, bool &bpos) {
+__device__ __forceinline__ double distance_all(const Dev &g, const Particle &P, int &bl, uint32_t &bs, bool &bpos,
+                                               uint32_t &bk) {
     double bt = dinf();
     bl = GT_MAX_LEVELS;
     bs = kNone;
     bpos = false;
+    bk = 0;
     double qx = P.x, qy = P.y, qz = P.z;
     for (int L = 0; L < P.depth; L++) {
         const uint32_t c = lvl(P, L);
@@ -333,6 +335,7 @@ __device__ __forceinline__ double distance_all(const Dev &g, const Particle &P, 
                 bl = L;
                 bs = s;
                 bpos = pos;
+                bk = cc.hs_off + k;
             }
         }
         for (uint32_t k = cc.n_pl; k < cc.n_hs; k++) {
@@ -346,6 +349,7 @@ __device__ __forceinline__ double distance_all(const Dev &g, const Particle &P, 
                 bl = L;
                 bs = s;
                 bpos = pos;
+                bk = cc.hs_off + k;
             }
         }
     }
@@ -533,9 +537,9 @@ __device__ void run_history(const Dev &g, const KParams &p, const KOut &o, uint6
     acc.lo = acc.hi = 0;
     while (end == GT_END_NONE) {
         int bl;
-        uint32_t bs;
+        uint32_t bs, bk;
         bool bpos;
-        const double dist = distance_all(g, P, bl, bs, bpos);
+        const double dist = distance_all(g, P, bl, bs, bpos, bk);
         const uint32_t lc = lvl(P, P.depth - 1);
         const double sig = g.sigma[g.cell[lc].fill];
         const double sc = (p.source == 1) ? dinf() : P.tau / sig;
@@ -627,19 +631,22 @@ __device__ __forceinline__ Dev stage_tables(const Dev &g, const StagePlan &sp, c
     }
     __syncthreads();
     Dev d = g;
-    d.coef = (const double *)(lds + sp.coef);
-    d.hs = (const uint32_t *)(lds + sp.hs);
-    d.cell = (const Cell *)(lds + sp.cell);
-    d.trans = (const double *)(lds + sp.trans);
-    d.univ = (const Univ *)(lds + sp.univ);
-    d.leaf = (const uint32_t *)(lds + sp.leaf);
+    d.coef = (const double *)(lds + sp.at[SEC_COEF]);
+    d.hs = (const uint32_t *)(lds + sp.at[SEC_HS]);
+    d.cell = (const Cell *)(lds + sp.at[SEC_CELL]);
+    d.trans = (const double *)(lds + sp.at[SEC_TRANS]);
+    d.univ = (const Univ *)(lds + sp.at[SEC_UNIV]);
+    d.leaf = (const uint32_t *)(lds + sp.at[SEC_LEAF]);
     if (PREC == GT_PREC_MIXED) {
-        d.node32 = (const Node32 *)(lds + sp.node32);
-        d.cbox = (const float *)(lds + sp.cbox);
+        d.node32 = (const Node32 *)(lds + sp.at[SEC_NODE32]);
+        d.cbox = (const float *)(lds + sp.at[SEC_CBOX]);
     } else {
-        d.node64 = (const Node64 *)(lds + sp.node64);
+        d.node64 = (const Node64 *)(lds + sp.at[SEC_NODE64]);
     }
-    d.sigma = (const double *)(lds + sp.sigma);
+    d.sigma = (const double *)(lds + sp.at[SEC_SIGMA]);
+    d.adj_off = (const uint32_t *)(lds + sp.at[SEC_ADJOFF]);
+    d.adj = (const uint32_t *)(lds + sp.at[SEC_ADJ]);
+    d.cell_local = (const uint32_t *)(lds + sp.at[SEC_LOCAL]);
     return d;
 }
 
@@ -653,6 +660,7 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p,
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     Particle P;
     P.cell = cells + threadIdx.x;
+    for (int L = 0; L < GT_MAX_LEVELS; L++) lvl(P, L) = 0;   // hints below read earlier levels
     P.x = P.y = P.z = P.u = P.v = P.w = P.tau = 0.0;
     P.depth = 1;
     P.on_level = -1;
@@ -669,7 +677,7 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p,
     acc.lo = acc.hi = 0;
     // pending search: universe su at local point (qx,qy,qz) for level sL
     int sL = 0;
-    uint32_t su = 0, sforce = kNone;
+    uint32_t su = 0, sforce = kNone, sk = 0;
     bool sfpos = false;
     int32_t sexcl = -1;
     double qx = 0, qy = 0, qz = 0;
@@ -762,7 +770,26 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p,
 
         // ---- one level of find_cell / cross_surface
         if (mode == M_SEARCH) {
-            const int32_t c = search<PREC>(g, su, qx, qy, qz, sforce, sfpos, sexcl, gx, gy);
+            // quick candidates first: after a crossing, the cells listed for the
+            // crossed half-space; in a descent, the cell with the same index in
+            // the new universe as the lane had at this level before
+            uint32_t k0, k1, hint = 0;
+            if (sforce != kNone) {
+                k0 = g.adj_off[sk];
+                k1 = g.adj_off[sk + 1];
+            } else {
+                const Univ U = g.univ[su];
+                const uint32_t loc = g.cell_local[lvl(P, sL)];
+                hint = U.cell0 + loc;
+                k0 = 0;
+                k1 = loc < U.ncell ? 1u : 0u;
+            }
+            int32_t c = -1;
+            for (uint32_t k = k0; k < k1; k++) {
+                const uint32_t d = sforce != kNone ? g.adj[k] : hint;
+                if (contains(g, d, qx, qy, qz, sforce, sfpos)) { c = (int32_t)d; break; }
+            }
+            if (c < 0) c = search<PREC>(g, su, qx, qy, qz, sforce, sfpos, sexcl, gx, gy);
             if (c < 0) {
                 if (birth) {
                     if (sL == 0 && p.source != 1) { cnt.rejected++; mode = M_POS; }
@@ -800,9 +827,9 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p,
         // ---- one segment: distance_to_surface, move, tally, then crossing or collision
         if (mode == M_TRACK && end == GT_END_NONE) {
             int bl;
-            uint32_t bs;
+            uint32_t bs, bk;
             bool bpos;
-            const double dist = distance_all(g, P, bl, bs, bpos);
+            const double dist = distance_all(g, P, bl, bs, bpos, bk);
             const uint32_t lc = lvl(P, P.depth - 1);
             const double sig = g.sigma[g.cell[lc].fill];
             const double sc = (p.source == 1) ? dinf() : P.tau / sig;
@@ -846,6 +873,7 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p,
                     sL = bl;
                     sforce = bs;
                     sfpos = !bpos;
+                    sk = bk;
                     sexcl = (int32_t)lvl(P, bl);
                     gx = (float)qx;
                     gy = (float)qy;
@@ -977,9 +1005,9 @@ __global__ void __launch_bounds__(kBlock) k_distance(Dev g, const double *pos, c
         return;
     }
     int bl;
-    uint32_t bs;
+    uint32_t bs, bk;
     bool bpos;
-    const double d = distance_all(g, P, bl, bs, bpos);
+    const double d = distance_all(g, P, bl, bs, bpos, bk);
     dist[i] = d;
     level[i] = d == dinf() ? -1 : bl;
     surf[i] = d == dinf() ? -1 : (int32_t)bs;

@@ -284,6 +284,157 @@ def config3(seed: int = 1003) -> FlatGeometry:
     return b.build(root, sig, (-140.0, -140.0, -100.0), (140.0, 140.0, 100.0), "cfg3_core15x15")
 
 
+# --------------------------------------------------------------------------
+# hexagonal pseudo-arrays from planes only (Section "Empire microreactor":
+# hexagonal assemblies tracked without hexagon-specific routines)
+# --------------------------------------------------------------------------
+
+def hex_ring_cells(rings: int) -> List[Tuple[int, int]]:
+    """Axial coordinates (i, j) of a hexagonal arrangement of `rings` rings
+    (1 + 3 r (r-1) cells), ordered ring by ring.  Hex distance
+    max(|i|, |j|, |i + j|)."""
+    out = []
+    for r in range(rings):
+        ring = [(i, j) for i in range(-r, r + 1) for j in range(-r, r + 1)
+                if max(abs(i), abs(j), abs(i + j)) == r]
+        ring.sort(key=lambda ij: (math.atan2(*_axial_dir(ij)), ij))
+        out.extend(ring)
+    return out
+
+
+def _axial_dir(ij):
+    i, j = ij
+    # direction of i*a1 + j*a2 with a1 at 30 deg, a2 at 90 deg (for ordering only)
+    return (i * 0.5 + j, i * math.sqrt(3) / 2)
+
+
+class HexFamilies:
+    """Three families of parallel planes (normals n_k at angles phi_k, all
+    planes of a family share bitwise-identical normal coefficients) spaced
+    by half a pitch.  A hexagonal cell of flat-to-flat width `pitch` centred
+    on the lattice point i*a1 + j*a2 (a1 = pitch * n_0, a2 = pitch * n_1) is
+    the slab between planes m_k - 1 and m_k + 1 (in units of pitch/2) of each
+    family, with m_0 = 2i + j, m_1 = i + 2j, m_2 = -i + j."""
+
+    def __init__(self, b: "GeomBuilder", pitch: float, phi0_deg: float):
+        self.b = b
+        self.pitch = pitch
+        angs = [math.radians(phi0_deg + 60.0 * k) for k in range(3)]
+        self.n = [(math.cos(a), math.sin(a)) for a in angs]
+        self.planes: dict = {}
+
+    def plane(self, k: int, m: int) -> int:
+        key = (k, m)
+        if key not in self.planes:
+            a, bb = self.n[k]
+            self.planes[key] = self.b.surface(P, a, bb, 0.0, m * (self.pitch / 2.0))
+        return self.planes[key]
+
+    def cell(self, i: int, j: int) -> List[int]:
+        ms = (2 * i + j, i + 2 * j, -i + j)
+        h = []
+        for k, m in enumerate(ms):
+            h += [pos(self.plane(k, m - 1)), neg(self.plane(k, m + 1))]
+        return h
+
+    def centre(self, i: int, j: int) -> Tuple[float, float]:
+        (a0, b0), (a1, b1) = self.n[0], self.n[1]
+        return (self.pitch * (i * a0 + j * a1), self.pitch * (i * b0 + j * b1))
+
+    def vertices(self, i: int, j: int) -> List[Tuple[float, float]]:
+        cx, cy = self.centre(i, j)
+        rc = self.pitch / math.sqrt(3.0)
+        # vertices lie halfway between the face normals
+        phi = math.atan2(self.n[0][1], self.n[0][0])
+        return [(cx + rc * math.cos(phi + math.radians(30 + 60 * k)), cy + rc * math.sin(phi + math.radians(30 + 60 * k)))
+                for k in range(6)]
+
+
+HEX_PIN_PITCH = 1.3
+HEX_PIN_RADII = (0.4, 0.5)
+HEX_GAP = 0.05
+
+
+def config4(seed: int = 1004, core_rings: int = 7, asm_rings: int = 9, rim_rings: int = 2) -> FlatGeometry:
+    """7-ring core of hexagonal assemblies, each a 9-ring (217-pin) hexagonal
+    lattice of pins (two z-cylinders r = 0.4/0.5, pitch 1.3), built from
+    planes only and tracked through the generic hierarchy (no lattice hint).
+
+    Pins are flat-top hexagons (plane families at 30/90/150 degrees);
+    assemblies are pointy-top hexagons (families at 0/60/120 degrees) of
+    flat-to-flat 26 p / sqrt(3) + 2 g, so no pin plane is ever parallel to an
+    assembly boundary.  Each assembly universe adds `rim_rings` rings of
+    moderator hexagons around its pins; they cover the whole assembly
+    hexagon (the only region its parent can reach).  Three pin types
+    (fuel-, moderator-, heat-pipe-like: 3 materials each) and three seeded
+    assembly layouts; the root is the core pseudo-array of hexagonal prisms
+    with |z| <= 100 and vacuum outside its jagged union."""
+    rng = np.random.default_rng(seed)
+    p = HEX_PIN_PITCH
+    # circumscribing pointy-top hexagon of the pin union, plus the gap on each side
+    F = 2.0 * ((asm_rings - 1) * p * math.sqrt(3) / 2.0 + p / math.sqrt(3)) + 2 * HEX_GAP
+    n_pin_types, n_asm_types = 3, 3
+    sig = _sigmas(rng, 3 * n_pin_types + 1)
+    mod_mat = 3 * n_pin_types
+    pins_in = hex_ring_cells(asm_rings)
+    rim = hex_ring_cells(asm_rings + rim_rings)[len(pins_in):]
+    layouts = [rng.choice(n_pin_types, size=len(pins_in), p=[0.5, 0.3, 0.2]) for _ in range(n_asm_types)]
+    core = hex_ring_cells(core_rings)
+    core_types = rng.integers(0, n_asm_types, size=len(core))
+    b = GeomBuilder()
+    # universe ids: 0 root (core), 1..3 assemblies, 4..6 pins
+    fam_core = HexFamilies(b, F, 0.0)
+    zlo = b.surface(PZ, -100.0)
+    zhi = b.surface(PZ, 100.0)
+    cells = []
+    for (i, j), t in zip(core, core_types):
+        cx, cy = fam_core.centre(i, j)
+        cells.append((fam_core.cell(i, j) + [pos(zlo), neg(zhi)], fill_universe(1 + int(t)), (cx, cy, 0.0)))
+    root = b.universe(cells)
+    asms = []
+    for a in range(n_asm_types):
+        fam = HexFamilies(b, p, 30.0)
+        cells = []
+        for (i, j), t in zip(pins_in, layouts[a]):
+            cx, cy = fam.centre(i, j)
+            cells.append((fam.cell(i, j), fill_universe(4 + int(t)), (cx, cy, 0.0)))
+        for (i, j) in rim:
+            cells.append((fam.cell(i, j), mod_mat, (0.0, 0.0, 0.0)))
+        asms.append(b.universe(cells))
+    pins = [_pin_universe(b, HEX_PIN_RADII, 3 * t) for t in range(n_pin_types)]
+    assert root == 0 and asms == [1, 2, 3] and pins == [4, 5, 6]
+    xs, ys = [], []
+    for (i, j) in core:
+        for vx, vy in fam_core.vertices(i, j):
+            xs.append(vx)
+            ys.append(vy)
+    m = 1e-9 * max(max(map(abs, xs)), max(map(abs, ys)))
+    lo = (min(xs) - m, min(ys) - m, -100.0)
+    hi = (max(xs) + m, max(ys) + m, 100.0)
+    return b.build(root, sig, lo, hi, "cfg4_hex7x9")
+
+
+def hex_pin_box(half: float = 6.0, rings: int = 8, seed: int = 1104) -> FlatGeometry:
+    """A box |x|,|y| <= half, |z| <= 100 filled with a flat-top hexagonal
+    lattice of identical pins (pitch 1.3, cylinders 0.4/0.5) large enough to
+    cover the box; used to check hexagonal pin volumes with stratified rays."""
+    rng = np.random.default_rng(seed)
+    b = GeomBuilder()
+    s = [b.surface(PX, -half), b.surface(PX, half), b.surface(PY, -half), b.surface(PY, half),
+         b.surface(PZ, -100.0), b.surface(PZ, 100.0)]
+    root = b.universe([([pos(s[0]), neg(s[1]), pos(s[2]), neg(s[3]), pos(s[4]), neg(s[5])],
+                        fill_universe(1), (0.0, 0.0, 0.0))])
+    fam = HexFamilies(b, HEX_PIN_PITCH, 30.0)
+    cells = []
+    for (i, j) in hex_ring_cells(rings):
+        cx, cy = fam.centre(i, j)
+        cells.append((fam.cell(i, j), fill_universe(2), (cx, cy, 0.0)))
+    lat = b.universe(cells)
+    pin = _pin_universe(b, HEX_PIN_RADII, 0)
+    assert (root, lat, pin) == (0, 1, 2)
+    return b.build(root, _sigmas(rng, 3), (-half, -half, -100.0), (half, half, 100.0), "hex_pin_box")
+
+
 def sphere(radius: float = 1.0, sigma: float = 1.0) -> FlatGeometry:
     """A single sphere of one material (for first-flight escape checks)."""
     b = GeomBuilder()
@@ -304,7 +455,7 @@ def box(half: Tuple[float, float, float] = (1.0, 1.0, 1.0), sigma: float = 1.0) 
     return b.build(root, [sigma], (-hx, -hy, -hz), (hx, hy, hz), "box")
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3}
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
 
 # particle counts of the workload table, and the seeds: geometry 1000+i,
 # particles 2000+i.

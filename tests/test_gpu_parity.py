@@ -87,7 +87,7 @@ def test_fp64_division_sqrt_log_bit_exact():
 
 
 # ---------------------------------------------------------------- Table 1 ops
-@pytest.mark.parametrize("cfg", [1, 2, 3])
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
 @pytest.mark.parametrize("prec", [gt.PREC_FP64, gt.PREC_MIXED])
 def test_find_cell_parity(cfg, prec):
     import torch
@@ -102,7 +102,7 @@ def test_find_cell_parity(cfg, prec):
     assert np.array_equal(cells.cpu().numpy(), oc[:, :gt.MAX_LEVELS])
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3])
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
 def test_distance_parity(cfg):
     import torch
     fg, G, O = geoms(cfg)
@@ -127,6 +127,8 @@ CASES = [
     (1, dict(seed=2001, n_particles=10_000, geometry_id=1), 10_000, 128),
     (2, dict(seed=2002, n_particles=20_000, geometry_id=2), 2000, 512),
     (3, dict(seed=2003, n_particles=4000, geometry_id=3), 1000, 1024),
+    (4, dict(seed=2004, n_particles=4000, geometry_id=4), 1000, 1024),
+    ("hex_pin_box", dict(seed=2104, n_particles=4000, geometry_id=11), 500, 256),
 ]
 
 
@@ -142,7 +144,7 @@ def test_track_parity(case, prec, lane):
     assert_parity(g, o, where="cfg %s prec %d" % (cfg, prec))
 
 
-@pytest.mark.parametrize("cfg", ["sphere", 1, 2, 3])
+@pytest.mark.parametrize("cfg", ["sphere", 1, 2, 3, 4])
 @pytest.mark.parametrize("prec", [gt.PREC_FP64, gt.PREC_MIXED])
 def test_global_tables_match_staged(cfg, prec):
     """The persistent tracker reading the geometry from global memory gives
@@ -155,14 +157,14 @@ def test_global_tables_match_staged(cfg, prec):
     assert_parity(g, o, where="global tables cfg %s" % cfg)
 
 
-@pytest.mark.parametrize("cfg,n1,n2", [(1, 3000, 1), (2, 1700, 22)])
+@pytest.mark.parametrize("cfg,n1,n2", [(1, 3000, 1), (2, 1700, 22), ("hex_pin_box", 2400, 1)])
 def test_ray_mode_parity(cfg, n1, n2):
     fg, G, O = geoms(cfg)
     kw = dict(seed=0, n_particles=n1 * n2, source=1, ray_n1=n1, max_collisions=1)
     for prec in (gt.PREC_FP64, gt.PREC_MIXED):
         g = gpu_track(G, precision=prec, **kw)
         o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT)
-        assert_parity(g, o, where="rays cfg %d" % cfg)
+        assert_parity(g, o, where="rays cfg %s" % cfg)
         assert g["counters"]["escaped"] == n1 * n2
 
 
@@ -232,13 +234,15 @@ def test_full_size_cfg2_all_particles():
     assert_parity(g, o, where="cfg2 full")
 
 
-def test_full_size_cfg3_sampled():
-    """Three-level core (2.86M tallies), 1e7 histories on the GPU; a random
-    sample of particles is re-run one by one in the oracle; counters add up."""
-    fg, G, O = geoms(3)
+@pytest.mark.parametrize("cfg", [3, 4])
+def test_full_size_sampled(cfg):
+    """Three-level square core (2.86M tallies) and hexagonal core (97k
+    tallies), 1e7 histories on the GPU; a random sample of particles is re-run
+    one by one in the oracle; counters add up."""
+    fg, G, O = geoms(cfg)
     n = 10_000_000
-    print("cfg3 full size", flush=True)
-    g = gpu_track(G, precision=gt.PREC_MIXED, seed=synth.particle_seed(3), n_particles=n, geometry_id=3)
+    print("cfg%d full size" % cfg, flush=True)
+    g = gpu_track(G, precision=gt.PREC_MIXED, seed=synth.particle_seed(cfg), n_particles=n, geometry_id=cfg)
     c = g["counters"]
     assert c["escaped"] + c["capped"] + c["lost"] + c["segcap"] == n
     assert c["segments"] == int(g["seg_count"].astype(np.int64).sum())
@@ -246,7 +250,7 @@ def test_full_size_cfg3_sampled():
     rng = np.random.default_rng(3)
     ids = np.sort(rng.choice(n, size=300, replace=False))
     for i in ids:
-        o = oracle.track(O, oracle.TrackParams(seed=synth.particle_seed(3), n_particles=1, first_particle=int(i),
-                                               geometry_id=3), n_threads=1, tallies=False)
+        o = oracle.track(O, oracle.TrackParams(seed=synth.particle_seed(cfg), n_particles=1, first_particle=int(i),
+                                               geometry_id=cfg), n_threads=1, tallies=False)
         assert g["seq_hash"][i] == o.seq_hash[0] and g["seg_count"][i] == o.seg_count[0], i
         assert g["end_code"][i] == o.end_code[0]

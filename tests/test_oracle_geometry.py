@@ -227,3 +227,91 @@ def test_pseudo_array_plane_neighbour_counts(cfg, n):
             nb = og.neighbours(s)
             assert len(nb) == 2 * (11 if cfg == 2 else 1)
             assert np.all(np.diff(nb) > 0)
+
+
+# ---------------------------------------------------------------- hexagonal pseudo-arrays
+def _hex_round(fi, fj):
+    """Nearest hexagonal lattice point of fractional axial coordinates
+    (cube-coordinate rounding)."""
+    x, z = fi, fj
+    y = -x - z
+    rx, ry, rz = round(x), round(y), round(z)
+    dx, dy, dz = abs(rx - x), abs(ry - y), abs(rz - z)
+    if dx > dy and dx > dz:
+        rx = -ry - rz
+    elif dy > dz:
+        ry = -rx - rz
+    else:
+        rz = -rx - ry
+    return int(rx), int(rz)
+
+
+def test_hex_ring_counts():
+    """n rings hold 3 n (n - 1) + 1 cells: 9 rings = 217 pins, 7 rings = 127
+    assemblies (the Empire assemblies' 217 pins)."""
+    assert len(synth.hex_ring_cells(9)) == 217
+    assert len(synth.hex_ring_cells(7)) == 127
+    g = synth.make_config(4)
+    assert g.univ_cell_off[1] - g.univ_cell_off[0] == 127
+    assert g.univ_cell_off[2] - g.univ_cell_off[1] == len(synth.hex_ring_cells(11))
+
+
+def test_find_cell_hex_matches_axial_rounding():
+    """cfg4: the assembly and the pin found for a point are the nearest
+    lattice points in the core's and the assembly's axial coordinates; the
+    radial zone follows from the distance to the pin centre."""
+    g = synth.make_config(4)
+    og = oracle.OracleGeometry(g)
+    rng = np.random.default_rng(9)
+    pts = rng.uniform(g.domain_lo, g.domain_hi, size=(20000, 3))
+    inst, cells = og.find_cell(pts)
+    p = synth.HEX_PIN_PITCH
+    F = 2.0 * (8 * p * math.sqrt(3) / 2.0 + p / math.sqrt(3)) + 2 * synth.HEX_GAP
+    core = synth.hex_ring_cells(7)
+    pins = synth.hex_ring_cells(9)
+    rim = synth.hex_ring_cells(11)
+    checked = 0
+    for n, (x, y, z) in enumerate(pts):
+        # core: a1 = F (1, 0), a2 = F (1/2, sqrt3/2)
+        fj = y / (F * math.sqrt(3) / 2)
+        fi = x / F - fj / 2
+        I, J = _hex_round(fi, fj)
+        if (I, J) not in core:
+            continue
+        cx, cy = F * (I + J / 2), F * J * math.sqrt(3) / 2
+        lx, ly = x - cx, y - cy
+        # distance to the assembly hexagon's edges (pointy-top: normals at 0, 60, 120 deg)
+        edge = min(F / 2 - abs(lx * math.cos(a) + ly * math.sin(a)) for a in (0, math.pi / 3, 2 * math.pi / 3))
+        # pins: a1 = p (cos30, sin30), a2 = p (0, 1)
+        fi2 = lx / (p * math.sqrt(3) / 2)
+        fj2 = ly / p - fi2 / 2
+        i, j = _hex_round(fi2, fj2)
+        px, py = p * i * math.sqrt(3) / 2, p * (i / 2 + j)
+        r = math.hypot(lx - px, ly - py)
+        pedge = min(p / 2 - abs((lx - px) * math.cos(a) + (ly - py) * math.sin(a))
+                    for a in (math.pi / 6, math.pi / 2, 5 * math.pi / 6))
+        if edge < 1e-7 or pedge < 1e-7 or min(abs(r - 0.4), abs(r - 0.5)) < 1e-7:
+            continue
+        assert cells[n, 0] == core.index((I, J)), n
+        k = rim.index((i, j))
+        assert cells[n, 1] == g.univ_cell_off[1 + (g.cell_fill[cells[n, 0]] * -1 - 2)] + k, n
+        if (i, j) in pins:
+            assert cells[n, 2] - g.univ_cell_off[g.cell_fill[cells[n, 1]] * -1 - 1] == (0 if r < 0.4 else (1 if r < 0.5 else 2))
+        checked += 1
+    assert checked > 10000
+
+
+def test_hex_cells_never_overlap():
+    g = synth.make_config(4)
+    rng = np.random.default_rng(10)
+    pts = rng.uniform(-14, 14, size=(4000, 3))
+    for u in (1, 2, 3):
+        counts = np.zeros(len(pts), int)
+        for c in g.universe_cells(u):
+            ok = np.ones(len(pts), bool)
+            for h in g.cell_halfspaces(c):
+                s = abs(int(h)) - 1
+                a, b, _, d = g.surf_coef[s][:4]
+                ok &= ((a * pts[:, 0] + b * pts[:, 1]) - d > 0) == (h > 0)
+            counts += ok
+        assert counts.max() <= 1

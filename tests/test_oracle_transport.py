@@ -212,3 +212,25 @@ def test_work_meter_hand_count():
     og = oracle.OracleGeometry(synth.box((1.0, 2.0, 3.0)))
     ops, segs = oracle.count_work(og, oracle.TrackParams(seed=0, n_particles=100, source=1, ray_n1=10))
     assert segs == 100 and ops == 1400
+
+
+def test_ray_volumes_hex_pins():
+    """Hexagonal pins (three plane families, flat-to-flat 1.3) filling a box:
+    for every pin whose hexagon lies inside the box, stratified rays give
+    fuel and clad volumes pi r^2 * 200 and moderator ((sqrt3/2) p^2 -
+    pi 0.5^2) * 200."""
+    g = synth.hex_pin_box(6.0)
+    og = oracle.OracleGeometry(g)
+    vol, _ = _ray_volumes(g, og, 24000, 1)
+    p, H = synth.HEX_PIN_PITCH, 200.0
+    want = np.array([math.pi * 0.16, math.pi * (0.25 - 0.16), math.sqrt(3) / 2 * p * p - math.pi * 0.25]) * H
+    ring = synth.hex_ring_cells(8)
+    inside = 0
+    for k, (i, j) in enumerate(ring):
+        cx, cy = p * i * math.sqrt(3) / 2, p * (i / 2 + j)
+        rc = p / math.sqrt(3)
+        if abs(cx) + rc < 6.0 and abs(cy) + p / 2 < 6.0:
+            assert np.allclose(vol[3 * k:3 * k + 3], want, rtol=2e-4), (k, vol[3 * k:3 * k + 3], want)
+            inside += 1
+    assert inside >= 40
+    assert abs(vol.sum() - 12.0 * 12.0 * H) < 1e-6 * 12.0 * 12.0 * H
