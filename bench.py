@@ -43,33 +43,111 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--particles", type=int, default=1_000_000)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--refill", type=int, default=0, help="refill_min of the persistent schedule (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of tracking, run a plain device copy of this many bytes --steps times "
                          "(reference kernel for scaling HBM counters)")
-    ap.add_argument("--only", choices=["mixed", "fp64", "plain_fp64"], default=None,
+    ap.add_argument("--only", choices=["mixed", "fp64", "plain_fp64", "batch"], default=None,
                     help="time one mode only (profiling)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-geometry batched workload")
     return ap.parse_args()
 
 
-def timed(gt, G, out, args, prec, lane=False):
+class HipEvents:
+    """hipEvent_t pairs from the HIP runtime, handed to the library's timing
+    hook so that only the tracking kernel launch is bracketed (the zeroing and
+    finalize kernels of a step are outside)."""
+
+    def __init__(self):
+        import ctypes as C
+        self.C = C
+        self.hip = C.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [C.c_void_p]
+
+    def pair(self):
+        a, b = self.C.c_void_p(), self.C.c_void_p()
+        if self.hip.hipEventCreate(self.C.byref(a)) or self.hip.hipEventCreate(self.C.byref(b)):
+            raise RuntimeError("hipEventCreate failed")
+        return a.value, b.value
+
+    def elapsed_ms(self, a, b):
+        ms = self.C.c_float()
+        if self.hip.hipEventElapsedTime(self.C.byref(ms), a, b):
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+    def destroy(self, a, b):
+        self.hip.hipEventDestroy(a)
+        self.hip.hipEventDestroy(b)
+
+
+def run_timed(gt, step, args, hev):
+    """Warm up, then time args.steps calls of step(): torch events around
+    each whole step on the launch stream, HIP events (through the library's
+    hook) around its tracking kernels."""
     import torch
-    kw = dict(seed=2002, n_particles=args.particles, geometry_id=2, precision=prec, block_size=args.block, out=out,
-              lane_per_history=lane)
     for _ in range(args.warmup):
-        gt.track(G, **kw)
+        step()
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    kev = [hev.pair() for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for a, b in ev:
+    for (a, b), (ka, kb) in zip(ev, kev):
+        gt.set_kernel_events(ka, kb)
         a.record()
-        gt.track(G, **kw)
+        step()
         b.record()
+    gt.set_kernel_events(None, None)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = [a.elapsed_time(b) for a, b in ev]
-    segs = out.counters_dict()["segments"]
-    return dict(ms=ms, wall=wall, segments=segs)
+    kms = [hev.elapsed_ms(ka, kb) for ka, kb in kev]
+    for ka, kb in kev:
+        hev.destroy(ka, kb)
+    return dict(ms=ms, kernel_ms=kms, wall=wall)
+
+
+def timed(gt, G, out, args, prec, hev, lane=False):
+    kw = dict(seed=2002, n_particles=args.particles, geometry_id=2, precision=prec, block_size=args.block, out=out,
+              lane_per_history=lane, refill_min=0 if lane else args.refill)
+    r = run_timed(gt, lambda: gt.track(G, **kw), args, hev)
+    r["segments"] = out.counters_dict()["segments"]
+    return r
+
+
+def batched(gt, synth, args, hev):
+    """The 64-geometry workload: one batched mixed-precision launch against
+    64 sequential gt_track launches (all-double, and mixed)."""
+    items, geoms = [], []
+    for j in range(synth.BATCH_SIZE):
+        fg, n = synth.batch_item(j)
+        G = gt.Geometry(fg)
+        geoms.append((G, n, j))
+        items.append(gt.batch_item(G, synth.batch_particle_seed(j), n, geometry_id=synth.batch_geometry_id(j),
+                                   precision=gt.PREC_MIXED))
+    b = gt.Batch(items, block_size=args.block, refill_min=args.refill)
+    res = {"batched_mixed": run_timed(gt, b.launch, args, hev)}
+    segs = sum(it.out.counters_dict()["segments"] for it in items)
+    for name, prec in (("sequential_fp64", gt.PREC_FP64), ("sequential_mixed", gt.PREC_MIXED)):
+        def step(prec=prec):
+            for (G, n, j), it in zip(geoms, items):
+                gt.track(G, seed=synth.batch_particle_seed(j), n_particles=n, geometry_id=synth.batch_geometry_id(j),
+                         precision=prec, block_size=args.block, refill_min=args.refill, out=it.out)
+        res[name] = run_timed(gt, step, args, hev)
+        if sum(it.out.counters_dict()["segments"] for it in items) != segs:
+            raise RuntimeError("batched and sequential segment counts differ")
+    b.close()
+    out = {"workload": "64 seeded square/hexagonal geometries, 1-3 levels, %d histories" %
+           sum(n for _, n, _ in geoms), "segments_per_step": segs}
+    for k, r in res.items():
+        ms = sum(r["ms"]) / len(r["ms"])
+        out[k] = {"value": segs / (ms * 1e-3), "ms_per_step": ms}
+    out["batched_over_sequential_fp64"] = out["batched_mixed"]["value"] / out["sequential_fp64"]["value"]
+    out["batched_over_sequential_mixed"] = out["batched_mixed"]["value"] / out["sequential_mixed"]["value"]
+    return out
 
 
 def cpu_baseline(fg, gpu_out, n):
@@ -93,11 +171,51 @@ def cpu_baseline(fg, gpu_out, n):
     nz = o.tally != 0
     g_t = gpu_out.tally.cpu().numpy()
     rel = float(np.max(np.abs(g_t[nz] - o.tally[nz]) / o.tally[nz])) if nz.any() else 0.0
+    # one core on a 10^4-history slice
+    t0 = time.perf_counter()
+    o1 = oracle.track(og, oracle.TrackParams(seed=2002, n_particles=min(n, 10_000), geometry_id=2), n_threads=1)
+    per_core = o1.counters["segments"] / (time.perf_counter() - t0)
     # algorithmic double-precision operations per segment (work meter over a sample)
     ops, segs = oracle.count_work(og, oracle.TrackParams(seed=2002, n_particles=min(n, 20_000), geometry_id=2))
     return dict(value=o.counters["segments"] / dt, unit="segments/s", cores=cores, kind="oracle",
                 sample="the whole workload (%d histories, %d segments), %.1f s" % (n, o.counters["segments"], dt),
-                parity=parity, max_tally_rel_err=rel, ops_per_segment=ops / segs)
+                parity=parity, max_tally_rel_err=rel, ops_per_segment=ops / segs, per_core=per_core)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_track_persistent_17x17_1e6.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2406_13849_amd", "csrc", f)
+                  for f in ("gt_track.hip", "gt_internal.h", "gt_geometry.cpp")]
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch():
+    """HBM bytes per tracking launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by the
+    factor a plain device copy of known size gives), or None when the kernel
+    sources have changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    try:
+        if kv["kernel_source_sha256"] != kernel_source_digest():
+            return None
+        return (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+                + float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])) * 1024.0
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -126,13 +244,22 @@ def main():
     modes = [("plain_fp64", gt.PREC_FP64, True), ("fp64", gt.PREC_FP64, False), ("mixed", gt.PREC_MIXED, False)]
     if args.only:
         modes = [m for m in modes if m[0] == args.only]
+    hev = HipEvents()
     for name, prec, lane in modes:
-        res[name] = timed(gt, G, out, args, prec, lane)
+        res[name] = timed(gt, G, out, args, prec, hev, lane)
         print("# %s: %.3f ms/step, %d segments/step" % (name, sum(res[name]["ms"]) / args.steps,
                                                         res[name]["segments"]), file=sys.stderr, flush=True)
+    bat = None
+    if (args.only in (None, "batch")) and not args.no_batch:
+        bat = batched(gt, synth, args, hev)
+        print("# batch: %s" % json.dumps(bat), file=sys.stderr, flush=True)
+    if not res:
+        print(json.dumps({"batched": bat}), flush=True)
+        return
     head = res["mixed"] if "mixed" in res else res["fp64"]
     ms_step = sum(head["ms"]) / len(head["ms"])
     seg_s = head["segments"] / (ms_step * 1e-3)
+    kernel_ms = sum(head["kernel_ms"]) / len(head["kernel_ms"])
     line = {
         "metric": "track segments/sec on 1 MI355X (mixed vs FP64), exact cell sequences",
         "value": seg_s,
@@ -159,16 +286,21 @@ def main():
         line["mixed_over_fp64"] = line["value"] / line["fp64"]["value"]
     if "mixed" in res and "plain_fp64" in res:
         line["mixed_over_plain_fp64"] = line["value"] / line["plain_fp64_lane_per_history"]["value"]
+    if bat is not None:
+        line["batched"] = bat
     if not args.no_cpu_baseline:
         cb = cpu_baseline(fg, out, n)
         line["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         line["parity"] = {"sequences_and_fixed_point_tallies_identical": cb["parity"],
                           "max_tally_rel_err": cb["max_tally_rel_err"]}
-        achieved = cb["ops_per_segment"] * seg_s
+        line["cpu_baseline"]["per_core_value"] = cb["per_core"]
+        line["cpu_baseline"]["gpu_in_core_equivalents"] = seg_s / cb["per_core"]
+        achieved = cb["ops_per_segment"] * head["segments"] / (kernel_ms * 1e-3)
         line["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
-                            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS, "traffic": None,
-                            "ops_per_segment": cb["ops_per_segment"],
-                            "kernel": "k_track_persistent (mixed precision)"}
+                            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS,
+                            "traffic": traffic_per_launch(),
+                            "ops_per_segment": cb["ops_per_segment"], "kernel_ms": kernel_ms,
+                            "kernel": "k_track_persistent<mixed, staged>"}
     print(json.dumps(line), flush=True)
 
 

@@ -163,6 +163,9 @@ typedef struct {
     uint32_t block_size;      /* threads per workgroup, a multiple of 64: up to 1024
                                  (persistent schedule, default 1024) or up to 256
                                  (GT_FLAG_LANE_PER_HISTORY, default 256); 0 = default */
+    uint32_t refill_min;      /* persistent schedule: a wave starts new histories once at
+                                 least this many of its lanes are idle (1..64; 0 = 8)   */
+    uint32_t reserved;        /* must be 0                                           */
 } gt_track_params;
 
 /* Outputs, all device memory owned by the caller.
@@ -198,6 +201,54 @@ typedef struct {
  * material, else a collision with isotropic redirection; vacuum boundary).
  * Asynchronous on `stream`; allocates nothing. */
 int gt_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream);
+
+/* ---- many geometries in one launch -------------------------------------- */
+typedef struct gt_batch gt_batch;   /* opaque: device descriptors of a batch */
+
+typedef struct {
+    const gt_geometry *geometry;    /* each geometry at most once per batch    */
+    gt_track_params params;         /* as for gt_track; one precision for all;
+                                       GT_FLAG_LANE_PER_HISTORY not allowed    */
+    gt_track_out out;               /* as for gt_track                         */
+} gt_batch_item;
+
+typedef struct {
+    uint32_t block_size;   /* threads per workgroup, multiple of 64 up to 1024; 0 = 1024      */
+    uint32_t refill_min;   /* as gt_track_params.refill_min; 0 = 8                             */
+    uint64_t chunk;        /* histories per work item taken from the device queue; 0 = 16384  */
+} gt_tuning;
+
+/* Validate a batch and upload its descriptors: per item the geometry
+ * tables, parameters and output pointers; a work list of (item, particle
+ * range) chunks, largest items first.  The histories are exactly those each
+ * item's gt_track call would track, with identical outputs. */
+int gt_batch_create(const gt_batch_item *items, uint32_t n_items, const gt_tuning *tuning, gt_batch **out);
+/* Errors: GT_EINVAL for an empty batch, a rejected item (the message names
+ * it), mixed precisions, GT_FLAG_LANE_PER_HISTORY, a geometry used twice or
+ * on another device than the current one; GT_ECAPACITY above 16384 items;
+ * GT_ENOMEM when the descriptors cannot be allocated.  The batch keeps the
+ * geometry tables' and output buffers' addresses: they must outlive it.
+ * Work-queue position counters[7] stays 0 for batch items. */
+
+/* Track every item of the batch with one persistent launch (a second launch
+ * of the same kernel covers items whose tables exceed the LDS budget), plus
+ * one fill and one finalize launch.  Only kernel launches are issued, so the
+ * call can be captured into a HIP graph and replayed. */
+int gt_batch_launch(gt_batch *b, void *stream);
+
+void gt_batch_destroy(gt_batch *b);
+
+/* Timing hook (for benchmarks and profilers; the paper times the tracking
+ * kernels alone).  With two hipEvent_t handles set, every later gt_track and
+ * gt_batch_launch on the calling thread records start_event on its stream
+ * right before its tracking kernel launch(es) and stop_event right after, so
+ * the elapsed time between them excludes the zeroing and finalize kernels.
+ * The events stay the caller's; gt_set_kernel_events(NULL, NULL) turns the
+ * hook off.  GT_EINVAL if exactly one handle is NULL. */
+int gt_set_kernel_events(void *start_event, void *stop_event);
+
+/* One-shot form: create, launch, wait for the stream, destroy. */
+int gt_track_batch(const gt_batch_item *items, uint32_t n_items, const gt_tuning *tuning, void *stream);
 
 /* Table 1 find_cell for a batch of global positions (device pos[3n]):
  * inst[n] receives the leaf instance or -1, cells[n * GT_MAX_LEVELS] (may be

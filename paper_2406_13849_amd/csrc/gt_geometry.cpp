@@ -640,7 +640,7 @@ extern "C" void gt_geometry_destroy(gt_geometry *g) {
     delete g;
 }
 
-extern "C" int gt_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream) {
+int gt::check_track_args(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o) {
     if (!g || !p || !o) return set_error("gt_track: null argument"), GT_EINVAL;
     if (!o->tally_fx || !o->counters) return set_error("gt_track: tally_fx and counters are required"), GT_EINVAL;
     if (p->max_collisions < 1) return set_error("gt_track: max_collisions must be >= 1"), GT_EINVAL;
@@ -654,11 +654,171 @@ extern "C" int gt_track(const gt_geometry *g, const gt_track_params *p, const gt
         return set_error("gt_track: unknown flags 0x%x", p->flags), GT_EINVAL;
     if (p->block_size && (p->block_size % 64 || p->block_size > 1024))
         return set_error("gt_track: block_size must be a multiple of 64 up to 1024"), GT_EINVAL;
+    if (p->refill_min > 64) return set_error("gt_track: refill_min must be at most 64"), GT_EINVAL;
+    if (p->reserved) return set_error("gt_track: reserved must be 0"), GT_EINVAL;
     if (p->first_particle + p->n_particles < p->first_particle)
         return set_error("gt_track: particle id range overflows"), GT_EINVAL;
     if ((uint64_t)p->record_first_k * p->record_cap > (1ull << 40))
         return set_error("gt_track: record buffer too large"), GT_ECAPACITY;
+    return GT_OK;
+}
+
+extern "C" int gt_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream) {
+    int rc = check_track_args(g, p, o);
+    if (rc) return rc;
     return launch_track(g, p, o, stream);
+}
+
+extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, const gt_tuning *tuning, gt_batch **out) {
+    if (!out || (n_items && !items)) return set_error("gt_batch_create: null argument"), GT_EINVAL;
+    *out = nullptr;
+    if (n_items == 0) return set_error("gt_batch_create: empty batch"), GT_EINVAL;
+    if (n_items > 16384) return set_error("gt_batch_create: at most 16384 items"), GT_ECAPACITY;
+    const uint32_t block = tuning && tuning->block_size ? tuning->block_size : 1024;
+    const uint32_t refill = tuning && tuning->refill_min ? tuning->refill_min : 0;
+    const uint64_t chunk = tuning && tuning->chunk ? tuning->chunk : 16384;
+    if (block % 64 || block > 1024) return set_error("gt_batch_create: block_size must be a multiple of 64 up to 1024"), GT_EINVAL;
+    if (refill > 64) return set_error("gt_batch_create: refill_min must be at most 64"), GT_EINVAL;
+    try {
+        const uint32_t prec = items[0].params.precision;
+        const int dev = items[0].geometry ? items[0].geometry->device : 0;
+        std::vector<BatchItem> bi(n_items);
+        std::vector<FillRange> fills;
+        std::vector<FinalizeItem> fin(n_items);
+        std::vector<std::pair<double, uint32_t>> order;
+        std::vector<uint8_t> staged(n_items);
+        uint32_t lds = 0;
+        uint64_t max_inst = 1, max_fill = 2;
+        for (uint32_t i = 0; i < n_items; i++) {
+            const gt_batch_item &it = items[i];
+            int rc = check_track_args(it.geometry, &it.params, &it.out);
+            if (rc) return set_error("gt_batch_create: item %u: %s", i, gt_last_error()), rc;
+            if (it.params.precision != prec) return set_error("gt_batch_create: item %u: precision differs", i), GT_EINVAL;
+            if (it.params.flags & GT_FLAG_LANE_PER_HISTORY)
+                return set_error("gt_batch_create: item %u: GT_FLAG_LANE_PER_HISTORY is not available in batches", i), GT_EINVAL;
+            if (it.geometry->device != dev) return set_error("gt_batch_create: item %u: geometry on another device", i), GT_EINVAL;
+            for (uint32_t j = 0; j < i; j++)
+                if (items[j].geometry == it.geometry)
+                    return set_error("gt_batch_create: items %u and %u share a geometry", j, i), GT_EINVAL;
+            const gt_geometry *g = it.geometry;
+            BatchItem &b = bi[i];
+            b.dev = g->dev;
+            b.plan = g->stage[prec];
+            gt_track_params p = it.params;
+            p.refill_min = refill ? refill : p.refill_min;
+            fill_kparams(&p, g, b.p, b.o, &it.out);
+            staged[i] = !(it.params.flags & GT_FLAG_NO_STAGING) && b.plan.total <= stage_budget();
+            if (staged[i]) lds = std::max(lds, b.plan.total);
+            fills.push_back({g->tally_ws, (uint64_t)8 * 4 * g->n_inst, 0, 8, 0});
+            fills.push_back({it.out.counters, 8, 0, 8, 0});
+            if (b.p.rec_k) fills.push_back({it.out.rec, (uint64_t)b.p.rec_k * b.p.rec_cap, (uint64_t)(uint32_t)-1, 4, 0});
+            fin[i] = {g->tally_ws, it.out.tally_fx, it.out.tally, g->n_inst,
+                      (uint32_t)((it.params.flags & GT_FLAG_ACCUMULATE) != 0), 0};
+            max_inst = std::max(max_inst, g->n_inst);
+            order.push_back({(double)it.params.n_particles * (double)g->max_depth, i});
+        }
+        // chunks: staged items first, each group largest cost first
+        std::stable_sort(order.begin(), order.end(),
+                         [](const std::pair<double, uint32_t> &a, const std::pair<double, uint32_t> &b) {
+                             return a.first > b.first;
+                         });
+        std::vector<BatchChunk> chunks;
+        uint32_t n_staged = 0;
+        for (int pass = 0; pass < 2; pass++) {
+            for (const auto &o : order) {
+                const uint32_t i = o.second;
+                if ((staged[i] != 0) != (pass == 0)) continue;
+                const uint64_t n = items[i].params.n_particles;
+                for (uint64_t f = 0; f < n; f += chunk) chunks.push_back({i, 0, f, std::min(chunk, n - f)});
+            }
+            if (pass == 0) n_staged = (uint32_t)chunks.size();
+        }
+        if (chunks.size() > 0xFFFFFFF0u) return set_error("gt_batch_create: too many chunks"), GT_ECAPACITY;
+        // one device allocation: items, chunks, fills, finalize items, two queue counters
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        const size_t o_items = 0;
+        const size_t o_chunks = al(o_items + bi.size() * sizeof(BatchItem));
+        const size_t o_queue = al(o_chunks + std::max<size_t>(chunks.size(), 1) * sizeof(BatchChunk));
+        const size_t o_fill = al(o_queue + 2 * sizeof(unsigned long long));
+        const size_t o_fin = al(o_fill + (fills.size() + 1) * sizeof(FillRange));
+        const size_t total = al(o_fin + fin.size() * sizeof(FinalizeItem));
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) return set_error("hipGetDevice failed"), GT_EHIP;
+        if (cur != dev) return set_error("gt_batch_create: current device is not the geometries' device"), GT_EINVAL;
+        void *dm = nullptr;
+        hipError_t e = hipMalloc(&dm, total);
+        if (e != hipSuccess) return set_error("hipMalloc(%zu): %s", total, hipGetErrorString(e)), GT_ENOMEM;
+        unsigned char *base = (unsigned char *)dm;
+        fills.push_back({base + o_queue, 2, 0, 8, 0});
+        for (const FillRange &f : fills) max_fill = std::max(max_fill, f.count);
+        std::vector<unsigned char> img(total, 0);
+        std::memcpy(img.data() + o_items, bi.data(), bi.size() * sizeof(BatchItem));
+        if (!chunks.empty()) std::memcpy(img.data() + o_chunks, chunks.data(), chunks.size() * sizeof(BatchChunk));
+        std::memcpy(img.data() + o_fill, fills.data(), fills.size() * sizeof(FillRange));
+        std::memcpy(img.data() + o_fin, fin.data(), fin.size() * sizeof(FinalizeItem));
+        e = hipMemcpy(dm, img.data(), total, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(dm);
+            return set_error("hipMemcpy: %s", hipGetErrorString(e)), GT_EHIP;
+        }
+        gt_batch *b = new gt_batch;
+        b->device = dev;
+        b->precision = prec;
+        b->n_items = n_items;
+        b->block = block;
+        b->refill_min = refill;
+        b->dmem = dm;
+        b->d_items = (BatchItem *)(base + o_items);
+        b->d_chunks = (BatchChunk *)(base + o_chunks);
+        b->n_staged = n_staged;
+        b->n_global = (uint32_t)chunks.size() - n_staged;
+        b->d_fill = (FillRange *)(base + o_fill);
+        b->n_fill = (uint32_t)fills.size();
+        b->max_fill = max_fill;
+        b->d_fin = (FinalizeItem *)(base + o_fin);
+        b->max_inst = max_inst;
+        b->d_queue = (unsigned long long *)(base + o_queue);
+        b->lds_bytes = lds;
+        *out = b;
+        return GT_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error("host allocation failed"), GT_ENOMEM;
+    } catch (...) {
+        return set_error("unexpected exception in gt_batch_create"), GT_EINVAL;
+    }
+}
+
+extern "C" int gt_set_kernel_events(void *start_event, void *stop_event) {
+    if ((start_event == nullptr) != (stop_event == nullptr))
+        return set_error("gt_set_kernel_events: give both events or neither"), GT_EINVAL;
+    set_kernel_events(start_event, stop_event);
+    return GT_OK;
+}
+
+extern "C" int gt_batch_launch(gt_batch *b, void *stream) {
+    if (!b) return set_error("gt_batch_launch: null batch"), GT_EINVAL;
+    return launch_batch(b, stream);
+}
+
+extern "C" void gt_batch_destroy(gt_batch *b) {
+    if (!b) return;
+    int cur = 0;
+    bool switched = hipGetDevice(&cur) == hipSuccess && cur != b->device && hipSetDevice(b->device) == hipSuccess;
+    (void)hipFree(b->dmem);
+    if (switched) (void)hipSetDevice(cur);
+    delete b;
+}
+
+extern "C" int gt_track_batch(const gt_batch_item *items, uint32_t n_items, const gt_tuning *tuning, void *stream) {
+    gt_batch *b = nullptr;
+    int rc = gt_batch_create(items, n_items, tuning, &b);
+    if (rc) return rc;
+    rc = gt_batch_launch(b, stream);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    gt_batch_destroy(b);
+    if (rc) return rc;
+    if (e != hipSuccess) return set_error("hipStreamSynchronize: %s", hipGetErrorString(e)), GT_EHIP;
+    return GT_OK;
 }
 
 extern "C" int gt_find_cell(const gt_geometry *g, const double *pos, uint64_t n, int64_t *inst, int32_t *cells,

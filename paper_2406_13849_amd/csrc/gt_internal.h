@@ -93,7 +93,7 @@ struct StagePlan {
 
 struct KParams {
     uint64_t seed, first, n;
-    uint32_t geom_id, max_coll, source, ray_n1, max_segs, rec_k, rec_cap, pad;
+    uint32_t geom_id, max_coll, source, ray_n1, max_segs, rec_k, rec_cap, refill_min;
 };
 
 struct KOut {
@@ -103,6 +103,34 @@ struct KOut {
     uint8_t *end_code;
     int32_t *rec;
     uint64_t *counters;
+};
+
+// One item of a batched launch (device copy).
+struct BatchItem {
+    Dev dev;
+    StagePlan plan;
+    KParams p;
+    KOut o;
+};
+
+// A range of particle indices of one batch item.
+struct BatchChunk {
+    uint32_t item, pad;
+    uint64_t first, count;
+};
+
+struct FillRange {
+    void *ptr;
+    uint64_t count, value;
+    uint32_t bytes, pad;
+};
+
+struct FinalizeItem {
+    const uint64_t *ws;
+    uint64_t *tfx;
+    double *tally;
+    uint64_t n_inst;
+    uint32_t accumulate, pad;
 };
 
 }  // namespace gt
@@ -119,8 +147,30 @@ struct gt_geometry {
     int device;
 };
 
+// host-side batch object behind the opaque ABI handle
+struct gt_batch {
+    int device;
+    uint32_t precision, n_items, block, refill_min;
+    void *dmem;                         // one allocation for everything below
+    gt::BatchItem *d_items;
+    gt::BatchChunk *d_chunks;           // staged items' chunks, then the others'
+    uint32_t n_staged, n_global;
+    gt::FillRange *d_fill;
+    uint32_t n_fill;
+    uint64_t max_fill;
+    gt::FinalizeItem *d_fin;
+    uint64_t max_inst;
+    unsigned long long *d_queue;        // two counters (staged and global launch)
+    uint32_t lds_bytes;                 // dynamic LDS of the staged launch
+};
+
 namespace gt {
 void set_error(const char *fmt, ...);
+int check_track_args(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o);
+void fill_kparams(const gt_track_params *p, const gt_geometry *g, KParams &kp, KOut &ko, const gt_track_out *o);
+unsigned stage_budget();
+void set_kernel_events(void *start, void *stop);
+int launch_batch(gt_batch *b, void *stream);
 int launch_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream);
 int launch_find_cell(const gt_geometry *g, const double *pos, uint64_t n, int64_t *inst, int32_t *cells,
                      uint32_t precision, void *stream);

@@ -21,6 +21,8 @@
 // only when that cell cannot contain the point.
 #pragma clang fp contract(off)
 
+#include <algorithm>
+
 #include "gt_internal.h"
 
 namespace gt {
@@ -356,6 +358,77 @@ __device__ __forceinline__ double distance_all(const Dev &g, const Particle &P, 
     return bt;
 }
 
+// distance_to_surface as above, also returning what the segment step needs
+// without reading the levels' cells again: the leaf instance and material,
+// and the universe of the level that holds the nearest surface.
+struct Nearest {
+    double t;
+    int level;
+    uint32_t surf, entry, univ, inst;
+    int32_t leaf_fill;
+    bool pos;
+};
+
+__device__ __forceinline__ void nearest_surface(const Dev &g, const Particle &P, Nearest &r) {
+    r.t = dinf();
+    r.level = GT_MAX_LEVELS;
+    r.surf = kNone;
+    r.entry = 0;
+    r.pos = false;
+    r.univ = g.root;
+    r.inst = 0;
+    double qx = P.x, qy = P.y, qz = P.z;
+    uint32_t univ = g.root;
+    int32_t fill = 0;
+    for (int L = 0; L < P.depth; L++) {
+        const uint32_t c = lvl(P, L);
+        if (L > 0) {
+            const double *t = g.trans + 4 * (size_t)lvl(P, L - 1);
+            qx = qx - t[0];
+            qy = qy - t[1];
+            qz = qz - t[2];
+            univ = (uint32_t)(-fill - 1);
+        }
+        const Cell cc = g.cell[c];
+        fill = cc.fill;
+        r.inst += cc.inst_off;
+        const uint32_t *hs = g.hs + cc.hs_off;
+        bool better = false;
+        for (uint32_t k = 0; k < cc.n_pl; k++) {
+            const uint32_t h = hs[k];
+            const uint32_t s = h >> 4;
+            const bool pos = (h >> 3) & 1u;
+            if (P.on_level == L && P.on_surf == s) continue;   // a plane just crossed is not hit again
+            const double d = plane_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w);
+            if (d < r.t || (d == r.t && d != dinf() && L == r.level && s < r.surf)) {
+                r.t = d;
+                r.level = L;
+                r.surf = s;
+                r.pos = pos;
+                r.entry = cc.hs_off + k;
+                better = true;
+            }
+        }
+        for (uint32_t k = cc.n_pl; k < cc.n_hs; k++) {
+            const uint32_t h = hs[k];
+            const uint32_t s = h >> 4;
+            const bool pos = (h >> 3) & 1u;
+            const bool on = (P.on_level == L) && (P.on_surf == s);
+            const double d = quad_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w, on);
+            if (d < r.t || (d == r.t && d != dinf() && L == r.level && s < r.surf)) {
+                r.t = d;
+                r.level = L;
+                r.surf = s;
+                r.pos = pos;
+                r.entry = cc.hs_off + k;
+                better = true;
+            }
+        }
+        if (better) r.univ = univ;
+    }
+    r.leaf_fill = fill;
+}
+
 // cross_surface at level L* on surface s* (Alg. 8) for the one-history-
 // per-lane schedule: the cell of that level's universe on the other side
 // (the old cell's sense on s* flipped), then descent below it.
@@ -613,6 +686,10 @@ __global__ void __launch_bounds__(kBlock) k_track(Dev g, KParams p, KOut o) {
 enum Mode : int { M_IDLE = 0, M_POS = 1, M_DIR = 2, M_SEARCH = 3, M_TRACK = 4 };
 
 constexpr uint32_t kChunk = 64;
+// A wave refills its idle lanes once at least this many are idle, so that
+// new histories start together and their first searches (which rarely have
+// a good candidate) run once for several lanes.
+constexpr uint32_t kRefillMin = 8;
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -650,16 +727,30 @@ __device__ __forceinline__ Dev stage_tables(const Dev &g, const StagePlan &sp, c
     return d;
 }
 
-template <int PREC, bool STAGED>
-__global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p, KOut o, StagePlan sp) {
-    __shared__ uint32_t cells[GT_MAX_LEVELS * kBlockP];
-    extern __shared__ __attribute__((aligned(16))) unsigned char lds_tables[];
-    const Dev g = STAGED ? stage_tables<PREC>(g0, sp, (const unsigned char *)g0.coef, lds_tables) : g0;
-    unsigned long long *queue = (unsigned long long *)&o.counters[7];
-    uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
-    Counts cnt = {0, 0, 0, 0, 0, 0, 0};
+// Particle-id sources for the state machine below: a global counter over
+// [0, end) for one geometry, or a workgroup (LDS) counter over one chunk of
+// a batch item.  take() is called by one lane and returns the first of k ids.
+struct GlobalQueue {
+    unsigned long long *ctr;
+    uint64_t end;
+    __device__ __forceinline__ uint64_t take(uint64_t k) const { return atomicAdd(ctr, (unsigned long long)k); }
+};
+
+struct ChunkQueue {
+    unsigned long long *ctr;   // LDS
+    uint64_t first, end;
+    __device__ __forceinline__ uint64_t take(uint64_t k) const {
+        return first + atomicAdd(ctr, (unsigned long long)k);
+    }
+};
+
+// The persistent history loop of one lane (see above); returns when its
+// wave has drained the queue and every lane of the wave is idle.
+template <int PREC, typename Queue>
+__device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const KOut &o, uint64_t *rep,
+                                           uint32_t *cells, const Queue &queue, Counts &cnt) {
     Particle P;
-    P.cell = cells + threadIdx.x;
+    P.cell = cells;
     for (int L = 0; L < GT_MAX_LEVELS; L++) lvl(P, L) = 0;   // hints below read earlier levels
     P.x = P.y = P.z = P.u = P.v = P.w = P.tau = 0.0;
     P.depth = 1;
@@ -691,15 +782,16 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p,
         // ---- refill idle lanes
         if (!drained) {
             uint64_t idle = __ballot(mode == M_IDLE);
+            if ((uint32_t)__popcll(idle) < p.refill_min) idle = 0;
             while (idle) {
                 if (pool_next == pool_end) {
                     const int leader = __ffsll((unsigned long long)idle) - 1;
                     unsigned long long base = 0;
-                    if ((int)__lane_id() == leader) base = atomicAdd(queue, (unsigned long long)kChunk);
+                    if ((int)__lane_id() == leader) base = queue.take(kChunk);
                     base = __shfl(base, leader);
-                    if (base >= p.n) { drained = true; break; }
+                    if (base >= queue.end) { drained = true; break; }
                     pool_next = base;
-                    pool_end = min((uint64_t)base + kChunk, p.n);
+                    pool_end = min((uint64_t)base + kChunk, queue.end);
                 }
                 const uint64_t avail = pool_end - pool_next;
                 const uint32_t r = lane_rank(idle);
@@ -826,22 +918,19 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p,
 
         // ---- one segment: distance_to_surface, move, tally, then crossing or collision
         if (mode == M_TRACK && end == GT_END_NONE) {
-            int bl;
-            uint32_t bs, bk;
-            bool bpos;
-            const double dist = distance_all(g, P, bl, bs, bpos, bk);
-            const uint32_t lc = lvl(P, P.depth - 1);
-            const double sig = g.sigma[g.cell[lc].fill];
+            Nearest nr;
+            nearest_surface(g, P, nr);
+            const double sig = g.sigma[nr.leaf_fill];
             const double sc = (p.source == 1) ? dinf() : P.tau / sig;
-            const uint32_t inst = leaf_instance(g, P);
-            const bool boundary = dist < sc;
+            const uint32_t inst = nr.inst;
+            const bool boundary = nr.t < sc;
             if (!boundary && sc == dinf()) {
                 end = GT_END_LOST;
             } else {
                 double l;
                 if (boundary) {
-                    l = dist;
-                    if (p.source != 1) P.tau = P.tau - sig * dist;
+                    l = nr.t;
+                    if (p.source != 1) P.tau = P.tau - sig * nr.t;
                 } else {
                     l = sc;
                 }
@@ -857,24 +946,23 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p,
                 }
                 segs++;
                 if (boundary) {
-                    // set up cross_surface at level bl on surface bs (Alg. 8)
+                    // set up cross_surface at level nr.level on surface nr.surf (Alg. 8):
+                    // the local position there, from the moved global position
                     qx = P.x;
                     qy = P.y;
                     qz = P.z;
-                    su = g.root;
-                    for (int L = 0; L < bl; L++) {
-                        const uint32_t c = lvl(P, L);
-                        const double *t = g.trans + 4 * (size_t)c;
+                    for (int L = 0; L < nr.level; L++) {
+                        const double *t = g.trans + 4 * (size_t)lvl(P, L);
                         qx = qx - t[0];
                         qy = qy - t[1];
                         qz = qz - t[2];
-                        su = (uint32_t)(-g.cell[c].fill - 1);
                     }
-                    sL = bl;
-                    sforce = bs;
-                    sfpos = !bpos;
-                    sk = bk;
-                    sexcl = (int32_t)lvl(P, bl);
+                    su = nr.univ;
+                    sL = nr.level;
+                    sforce = nr.surf;
+                    sfpos = !nr.pos;
+                    sk = nr.entry;
+                    sexcl = (int32_t)lvl(P, nr.level);
                     gx = (float)qx;
                     gy = (float)qy;
                     if (PREC == GT_PREC_MIXED) {
@@ -884,8 +972,8 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p,
                             gy += (float)P.v * 1e-3f / U.inv_py;
                         }
                     }
-                    P.on_level = bl;
-                    P.on_surf = bs;
+                    P.on_level = nr.level;
+                    P.on_surf = nr.surf;
                     mode = M_SEARCH;
                 } else {
                     P.on_level = -1;
@@ -909,7 +997,59 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p,
             mode = M_IDLE;
         }
     }
+}
+
+template <int PREC, bool STAGED>
+__global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p, KOut o, StagePlan sp) {
+    __shared__ uint32_t cells[GT_MAX_LEVELS * kBlockP];
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_tables[];
+    const Dev g = STAGED ? stage_tables<PREC>(g0, sp, (const unsigned char *)g0.coef, lds_tables) : g0;
+    uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
+    Counts cnt = {0, 0, 0, 0, 0, 0, 0};
+    const GlobalQueue q = {(unsigned long long *)&o.counters[7], p.n};
+    track_pool<PREC>(g, p, o, rep, cells + threadIdx.x, q, cnt);
     add_counts(cnt, o.counters);
+}
+
+// Many geometries in one persistent launch: each workgroup takes chunks
+// (item, range of particle indices) from a device queue, copies the item's
+// tables into LDS when the item changes (STAGED), and runs the lanes' state
+// machine over the chunk with a workgroup-local id counter.
+template <int PREC, bool STAGED>
+__global__ void __launch_bounds__(kBlockP) k_track_batch(const BatchItem *items, const BatchChunk *chunks,
+                                                         uint32_t n_chunks, unsigned long long *queue) {
+    __shared__ uint32_t cells[GT_MAX_LEVELS * kBlockP];
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_tables[];
+    __shared__ uint32_t s_chunk;
+    __shared__ unsigned long long s_pool;
+    int cur = -1;
+    Dev g;
+    KParams p;
+    KOut o;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_chunk = (uint32_t)atomicAdd(queue, 1ull);
+            s_pool = 0;
+        }
+        __syncthreads();
+        const uint32_t c = s_chunk;
+        if (c >= n_chunks) break;
+        const BatchChunk ch = chunks[c];
+        if ((int)ch.item != cur) {
+            const BatchItem &it = items[ch.item];
+            p = it.p;
+            o = it.o;
+            g = it.dev;
+            if (STAGED) g = stage_tables<PREC>(it.dev, it.plan, (const unsigned char *)it.dev.coef, lds_tables);
+            cur = (int)ch.item;
+        }
+        uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
+        Counts cnt = {0, 0, 0, 0, 0, 0, 0};
+        const ChunkQueue q = {&s_pool, ch.first, ch.first + ch.count};
+        track_pool<PREC>(g, p, o, rep, cells + threadIdx.x, q, cnt);
+        add_counts(cnt, o.counters);
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -923,33 +1063,53 @@ __global__ void k_fill_i32(int32_t *a, uint64_t n, int32_t v) {
         a[i] = v;
 }
 
-// Fold the replicas' limb counters into the 128-bit fixed-point total (plus
-// the previous total when accumulating), then convert it to cm:
-// high word * 2^-32 + low word * 2^-96.
-__global__ void k_finalize(const uint64_t *ws, uint64_t *tfx, double *tally, uint64_t n, int accumulate) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t lo = accumulate ? tfx[2 * i] : 0, hi = accumulate ? tfx[2 * i + 1] : 0;
-        for (int r = 0; r < kReplicas; r++) {
-            const uint64_t *L = ws + ((size_t)r * n + i) * 4;
-            for (int k = 0; k < 4; k++) {
-                // add L[k] * 2^(32 k) to (hi, lo) modulo 2^128
-                const uint64_t v = L[k];
-                uint64_t add_lo, add_hi;
-                switch (k) {
-                case 0: add_lo = v; add_hi = 0; break;
-                case 1: add_lo = v << 32; add_hi = v >> 32; break;
-                case 2: add_lo = 0; add_hi = v; break;
-                default: add_lo = 0; add_hi = v << 32; break;
-                }
-                const uint64_t nlo = lo + add_lo;
-                hi += add_hi + (nlo < lo ? 1u : 0u);
-                lo = nlo;
+// Fold the replicas' limb counters of instance i into the 128-bit
+// fixed-point total (plus the previous total when accumulating), then convert
+// it to cm: high word * 2^-32 + low word * 2^-96.
+__device__ __forceinline__ void fold_tally(const uint64_t *ws, uint64_t *tfx, double *tally, uint64_t n, uint64_t i,
+                                           bool accumulate) {
+    uint64_t lo = accumulate ? tfx[2 * i] : 0, hi = accumulate ? tfx[2 * i + 1] : 0;
+    for (int r = 0; r < kReplicas; r++) {
+        const uint64_t *L = ws + ((size_t)r * n + i) * 4;
+        for (int k = 0; k < 4; k++) {
+            // add L[k] * 2^(32 k) to (hi, lo) modulo 2^128
+            const uint64_t v = L[k];
+            uint64_t add_lo, add_hi;
+            switch (k) {
+            case 0: add_lo = v; add_hi = 0; break;
+            case 1: add_lo = v << 32; add_hi = v >> 32; break;
+            case 2: add_lo = 0; add_hi = v; break;
+            default: add_lo = 0; add_hi = v << 32; break;
             }
+            const uint64_t nlo = lo + add_lo;
+            hi += add_hi + (nlo < lo ? 1u : 0u);
+            lo = nlo;
         }
-        tfx[2 * i] = lo;
-        tfx[2 * i + 1] = hi;
-        if (tally) tally[i] = (double)hi * 0x1p-32 + (double)lo * 0x1p-96;
     }
+    tfx[2 * i] = lo;
+    tfx[2 * i + 1] = hi;
+    if (tally) tally[i] = (double)hi * 0x1p-32 + (double)lo * 0x1p-96;
+}
+
+__global__ void k_finalize(const uint64_t *ws, uint64_t *tfx, double *tally, uint64_t n, int accumulate) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        fold_tally(ws, tfx, tally, n, i, accumulate != 0);
+}
+
+// One launch zeroing every range of a batch: blockIdx.y selects the range.
+__global__ void k_fill_ranges(const FillRange *r) {
+    const FillRange f = r[blockIdx.y];
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < f.count; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (f.bytes == 8) ((uint64_t *)f.ptr)[i] = f.value;
+        else ((uint32_t *)f.ptr)[i] = (uint32_t)f.value;
+    }
+}
+
+// k_finalize for every item of a batch: blockIdx.y selects the item.
+__global__ void k_finalize_batch(const FinalizeItem *fi) {
+    const FinalizeItem f = fi[blockIdx.y];
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < f.n_inst; i += (uint64_t)gridDim.x * blockDim.x)
+        fold_tally(f.ws, f.tfx, f.tally, f.n_inst, i, f.accumulate != 0);
 }
 
 template <int PREC>
@@ -1083,27 +1243,19 @@ int allow_dynamic_lds(const void *kernel, unsigned bytes) {
     return GT_OK;
 }
 
+// Events recorded around the tracking kernels of this thread's next launches
+// (set by gt_set_kernel_events; both null = off).
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+
+inline void mark(hipEvent_t e, hipStream_t st) {
+    if (e) (void)hipEventRecord(e, st);
+}
+
 template <int PREC>
 int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, hipStream_t st) {
     KParams kp;
-    kp.seed = p->seed;
-    kp.first = p->first_particle;
-    kp.n = p->n_particles;
-    kp.geom_id = p->geometry_id;
-    kp.max_coll = p->max_collisions;
-    kp.source = p->source;
-    kp.ray_n1 = p->ray_n1;
-    kp.max_segs = p->max_segments;
-    kp.rec_k = (uint32_t)((uint64_t)p->record_first_k < p->n_particles ? p->record_first_k : p->n_particles);
-    kp.rec_cap = p->record_cap;
-    kp.pad = 0;
     KOut ko;
-    ko.tally_ws = g->tally_ws;
-    ko.seg_count = o->seg_count;
-    ko.seq_hash = o->seq_hash;
-    ko.end_code = o->end_code;
-    ko.rec = o->rec;
-    ko.counters = o->counters;
+    fill_kparams(p, g, kp, ko, o);
     const uint64_t nws = (uint64_t)kReplicas * 4 * g->n_inst;
     hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(nws)), dim3(256), 0, st, g->tally_ws, nws, (uint64_t)0);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, o->counters, (uint64_t)8, (uint64_t)0);
@@ -1111,6 +1263,7 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
         const uint64_t nrec = (uint64_t)kp.rec_k * kp.rec_cap;
         hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(nrec)), dim3(256), 0, st, o->rec, nrec, (int32_t)-1);
     }
+    mark(t_ev_start, st);
     if (kp.n) {
         if (p->flags & GT_FLAG_LANE_PER_HISTORY) {
             const unsigned block = p->block_size ? p->block_size : kBlock;
@@ -1138,12 +1291,77 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
                                    sp);
         }
     }
+    mark(t_ev_stop, st);
     hipLaunchKernelGGL(k_finalize, dim3(fill_grid(g->n_inst)), dim3(256), 0, st, (const uint64_t *)g->tally_ws,
                        o->tally_fx, o->tally, g->n_inst, (int)((p->flags & GT_FLAG_ACCUMULATE) != 0));
     return hip_check(hipGetLastError(), "gt_track launch");
 }
 
+template <int PREC>
+int launch_batch_t(gt_batch *b, hipStream_t st) {
+    const uint64_t fx = std::min<uint64_t>((b->max_fill + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_fill_ranges, dim3((unsigned)std::max<uint64_t>(fx, 1), b->n_fill), dim3(256), 0, st, b->d_fill);
+    mark(t_ev_start, st);
+    for (int pass = 0; pass < 2; pass++) {
+        const uint32_t n = pass == 0 ? b->n_staged : b->n_global;
+        if (!n) continue;
+        const void *kern = pass == 0 ? (const void *)k_track_batch<PREC, true> : (const void *)k_track_batch<PREC, false>;
+        const unsigned dyn = pass == 0 ? b->lds_bytes : 0;
+        int rc = GT_OK;
+        if (pass == 0) rc = allow_dynamic_lds(kern, kStageBudget);
+        if (rc) return rc;
+        int blocks = 0;
+        rc = persistent_grid(kern, b->block, dyn, b->device, &blocks);
+        if (rc) return rc;
+        if ((uint32_t)blocks > n) blocks = (int)n;
+        const BatchChunk *ch = b->d_chunks + (pass == 0 ? 0 : b->n_staged);
+        if (pass == 0)
+            hipLaunchKernelGGL((k_track_batch<PREC, true>), dim3(blocks), dim3(b->block), dyn, st, b->d_items, ch, n,
+                               b->d_queue);
+        else
+            hipLaunchKernelGGL((k_track_batch<PREC, false>), dim3(blocks), dim3(b->block), 0, st, b->d_items, ch, n,
+                               b->d_queue + 1);
+    }
+    mark(t_ev_stop, st);
+    const uint64_t bx = std::min<uint64_t>((b->max_inst + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_finalize_batch, dim3((unsigned)std::max<uint64_t>(bx, 1), b->n_items), dim3(256), 0, st, b->d_fin);
+    return hip_check(hipGetLastError(), "gt_batch_launch");
+}
+
 }  // namespace
+
+void fill_kparams(const gt_track_params *p, const gt_geometry *g, KParams &kp, KOut &ko, const gt_track_out *o) {
+    kp.seed = p->seed;
+    kp.first = p->first_particle;
+    kp.n = p->n_particles;
+    kp.geom_id = p->geometry_id;
+    kp.max_coll = p->max_collisions;
+    kp.source = p->source;
+    kp.ray_n1 = p->ray_n1;
+    kp.max_segs = p->max_segments;
+    kp.rec_k = (uint32_t)((uint64_t)p->record_first_k < p->n_particles ? p->record_first_k : p->n_particles);
+    kp.rec_cap = p->record_cap;
+    kp.refill_min = p->refill_min ? p->refill_min : kRefillMin;
+    ko.tally_ws = g->tally_ws;
+    ko.seg_count = o->seg_count;
+    ko.seq_hash = o->seq_hash;
+    ko.end_code = o->end_code;
+    ko.rec = o->rec;
+    ko.counters = o->counters;
+}
+
+unsigned stage_budget() { return kStageBudget; }
+
+void set_kernel_events(void *start, void *stop) {
+    t_ev_start = (hipEvent_t)start;
+    t_ev_stop = (hipEvent_t)stop;
+}
+
+int launch_batch(gt_batch *b, void *stream) {
+    if (b->block > (uint32_t)kBlockP) return set_error("gt_batch_launch: block_size too large"), GT_EINVAL;
+    return b->precision == GT_PREC_MIXED ? launch_batch_t<GT_PREC_MIXED>(b, (hipStream_t)stream)
+                                         : launch_batch_t<GT_PREC_FP64>(b, (hipStream_t)stream);
+}
 
 int launch_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream) {
     hipStream_t st = (hipStream_t)stream;

@@ -51,7 +51,7 @@ class _Params(C.Structure):
         ("geometry_id", C.c_uint32), ("max_collisions", C.c_uint32), ("source", C.c_uint32),
         ("ray_n1", C.c_uint32), ("max_segments", C.c_uint32), ("precision", C.c_uint32),
         ("record_first_k", C.c_uint32), ("record_cap", C.c_uint32), ("flags", C.c_uint32),
-        ("block_size", C.c_uint32),
+        ("block_size", C.c_uint32), ("refill_min", C.c_uint32), ("reserved", C.c_uint32),
     ]
 
 
@@ -60,6 +60,14 @@ class _Out(C.Structure):
         ("tally_fx", C.c_void_p), ("tally", C.c_void_p), ("seg_count", C.c_void_p),
         ("seq_hash", C.c_void_p), ("end_code", C.c_void_p), ("rec", C.c_void_p), ("counters", C.c_void_p),
     ]
+
+
+class _BatchItem(C.Structure):
+    _fields_ = [("geometry", C.c_void_p), ("params", _Params), ("out", _Out)]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("block_size", C.c_uint32), ("refill_min", C.c_uint32), ("chunk", C.c_uint64)]
 
 
 _lib = None
@@ -81,6 +89,16 @@ def lib():
         L.gt_geometry_destroy.restype = None
         L.gt_track.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), vp]
         L.gt_track.restype = i32
+        L.gt_batch_create.argtypes = [C.POINTER(_BatchItem), u32, C.POINTER(_Tuning), C.POINTER(vp)]
+        L.gt_batch_create.restype = i32
+        L.gt_batch_launch.argtypes = [vp, vp]
+        L.gt_batch_launch.restype = i32
+        L.gt_batch_destroy.argtypes = [vp]
+        L.gt_batch_destroy.restype = None
+        L.gt_track_batch.argtypes = [C.POINTER(_BatchItem), u32, C.POINTER(_Tuning), vp]
+        L.gt_track_batch.restype = i32
+        L.gt_set_kernel_events.argtypes = [vp, vp]
+        L.gt_set_kernel_events.restype = i32
         L.gt_find_cell.argtypes = [vp, vp, u64, vp, vp, u32, vp]
         L.gt_find_cell.restype = i32
         L.gt_distance_to_surface.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp]
@@ -191,7 +209,7 @@ def alloc_outputs(geom: Geometry, n: int, record_first_k: int = 0, record_cap: i
 def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 0, geometry_id: int = 0,
           max_collisions: int = 20, source: int = 0, ray_n1: int = 0, max_segments: int = 100_000,
           precision: int = PREC_MIXED, record_first_k: int = 0, record_cap: int = 0, accumulate: bool = False,
-          lane_per_history: bool = False, staging: bool = True, block_size: int = 0,
+          lane_per_history: bool = False, staging: bool = True, block_size: int = 0, refill_min: int = 0,
           out: Optional[TrackOutputs] = None, stream=None) -> TrackOutputs:
     """gt_track: sample and track n_particles histories (asynchronous).
     lane_per_history selects the plain one-history-per-lane schedule instead
@@ -199,17 +217,96 @@ def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 
     in global memory even when they fit in LDS."""
     if out is None:
         out = alloc_outputs(geom, n_particles, record_first_k, record_cap)
-    prm = _Params(seed=seed, first_particle=first_particle, n_particles=n_particles, geometry_id=geometry_id,
-                  max_collisions=max_collisions, source=source, ray_n1=ray_n1, max_segments=max_segments,
-                  precision=precision, record_first_k=record_first_k, record_cap=record_cap,
-                  flags=(FLAG_ACCUMULATE if accumulate else 0) | (FLAG_LANE_PER_HISTORY if lane_per_history else 0)
-                  | (0 if staging else FLAG_NO_STAGING),
-                  block_size=block_size)
-    o = _Out(tally_fx=_ptr(out.tally_fx), tally=_ptr(out.tally), seg_count=_ptr(out.seg_count),
-             seq_hash=_ptr(out.seq_hash), end_code=_ptr(out.end_code), rec=_ptr(out.rec),
-             counters=_ptr(out.counters))
+    prm = _params(seed, n_particles, first_particle, geometry_id, max_collisions, source, ray_n1, max_segments,
+                  precision, record_first_k, record_cap, accumulate, lane_per_history, staging, block_size,
+                  refill_min)
+    o = _out_struct(out)
     _check(lib().gt_track(geom.h, C.byref(prm), C.byref(o), _stream(stream)))
     return out
+
+
+def _params(seed, n_particles, first_particle=0, geometry_id=0, max_collisions=20, source=0, ray_n1=0,
+            max_segments=100_000, precision=PREC_MIXED, record_first_k=0, record_cap=0, accumulate=False,
+            lane_per_history=False, staging=True, block_size=0, refill_min=0) -> _Params:
+    return _Params(seed=seed, first_particle=first_particle, n_particles=n_particles, geometry_id=geometry_id,
+                   max_collisions=max_collisions, source=source, ray_n1=ray_n1, max_segments=max_segments,
+                   precision=precision, record_first_k=record_first_k, record_cap=record_cap,
+                   flags=(FLAG_ACCUMULATE if accumulate else 0) | (FLAG_LANE_PER_HISTORY if lane_per_history else 0)
+                   | (0 if staging else FLAG_NO_STAGING),
+                   block_size=block_size, refill_min=refill_min, reserved=0)
+
+
+def _out_struct(out: TrackOutputs) -> _Out:
+    return _Out(tally_fx=_ptr(out.tally_fx), tally=_ptr(out.tally), seg_count=_ptr(out.seg_count),
+                seq_hash=_ptr(out.seq_hash), end_code=_ptr(out.end_code), rec=_ptr(out.rec),
+                counters=_ptr(out.counters))
+
+
+@dataclass
+class BatchItem:
+    """One (geometry, histories) pair of a batch: the keyword arguments of
+    track() except the schedule options, plus the output tensors."""
+    geom: Geometry
+    seed: int
+    n_particles: int
+    out: TrackOutputs
+    kwargs: dict
+
+
+class Batch:
+    """gt_batch_create / gt_batch_launch / gt_batch_destroy: many geometries
+    tracked by one persistent launch.  The descriptors hold the geometries'
+    tables and the outputs' addresses, so both are kept alive here."""
+
+    def __init__(self, items, block_size: int = 0, refill_min: int = 0, chunk: int = 0):
+        self.items = list(items)
+        arr = (_BatchItem * max(len(self.items), 1))()
+        for i, it in enumerate(self.items):
+            arr[i].geometry = it.geom.h
+            arr[i].params = _params(it.seed, it.n_particles, **it.kwargs)
+            arr[i].out = _out_struct(it.out)
+        tun = _Tuning(block_size=block_size, refill_min=refill_min, chunk=chunk)
+        h = C.c_void_p()
+        _check(lib().gt_batch_create(arr, len(self.items), C.byref(tun), C.byref(h)))
+        self.h = h.value
+
+    def launch(self, stream=None):
+        if not self.h:
+            raise GtError(GT_EINVAL, "batch is closed")
+        _check(lib().gt_batch_launch(self.h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gt_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def batch_item(geom: Geometry, seed: int, n_particles: int, out: Optional[TrackOutputs] = None,
+               **kwargs) -> BatchItem:
+    """A batch item with freshly allocated outputs unless given."""
+    if out is None:
+        out = alloc_outputs(geom, n_particles, kwargs.get("record_first_k", 0), kwargs.get("record_cap", 0))
+    return BatchItem(geom, seed, n_particles, out, kwargs)
+
+
+def track_batch(items, block_size: int = 0, refill_min: int = 0, chunk: int = 0, stream=None):
+    """gt_track_batch: one-shot batch (waits for the stream)."""
+    arr = (_BatchItem * max(len(items), 1))()
+    for i, it in enumerate(items):
+        arr[i].geometry = it.geom.h
+        arr[i].params = _params(it.seed, it.n_particles, **it.kwargs)
+        arr[i].out = _out_struct(it.out)
+    tun = _Tuning(block_size=block_size, refill_min=refill_min, chunk=chunk)
+    _check(lib().gt_track_batch(arr, len(items), C.byref(tun), _stream(stream)))
+    return [it.out for it in items]
+
+
+def set_kernel_events(start: Optional[int], stop: Optional[int]):
+    """gt_set_kernel_events: raw hipEvent_t handles (ints) or None, None."""
+    _check(lib().gt_set_kernel_events(start, stop))
 
 
 def find_cell(geom: Geometry, pos, precision: int = PREC_MIXED, stream=None):

@@ -414,6 +414,153 @@ def config4(seed: int = 1004, core_rings: int = 7, asm_rings: int = 9, rim_rings
     return b.build(root, sig, lo, hi, "cfg4_hex7x9")
 
 
+# --------------------------------------------------------------------------
+# batched workload: many geometries of uneven size
+# --------------------------------------------------------------------------
+
+BATCH_HALF_HEIGHT = 10.0
+
+
+def _square_flat(b: GeomBuilder, n: int, pitch: float, types: np.ndarray, radii, zb) -> int:
+    """One universe holding an n x n lattice with every pin's cylinders
+    flattened into it: per slot a fuel cell (inside the inner cylinder), a
+    ring cell and a moderator cell bounded by the slot's planes.  The
+    lattice's outer planes and z planes bound every cell."""
+    x0 = -0.5 * n * pitch
+    sx = [b.surface(PX, x0 + k * pitch) for k in range(n + 1)]
+    sy = [b.surface(PY, x0 + k * pitch) for k in range(n + 1)]
+    z0, z1 = b.surface(PZ, -zb), b.surface(PZ, zb)
+    cells = []
+    for j in range(n):
+        for i in range(n):
+            cx, cy = x0 + (i + 0.5) * pitch, x0 + (j + 0.5) * pitch
+            cyl = [b.surface(CZ, cx, cy, r * r) for r in radii]
+            box = [pos(sx[i]), neg(sx[i + 1]), pos(sy[j]), neg(sy[j + 1]), pos(z0), neg(z1)]
+            m0 = 3 * int(types[j, i])
+            cells.append(([neg(cyl[0]), pos(z0), neg(z1)], m0, (0.0, 0.0, 0.0)))
+            cells.append(([pos(cyl[0]), neg(cyl[1]), pos(z0), neg(z1)], m0 + 1, (0.0, 0.0, 0.0)))
+            cells.append(([pos(cyl[1])] + box, m0 + 2, (0.0, 0.0, 0.0)))
+    return b.universe(cells)
+
+
+def _hex_flat(b: GeomBuilder, rings: int, pitch: float, types, radii, zb) -> Tuple[int, HexFamilies, list]:
+    fam = HexFamilies(b, pitch, 30.0)
+    z0, z1 = b.surface(PZ, -zb), b.surface(PZ, zb)
+    cells = []
+    slots = hex_ring_cells(rings)
+    for (i, j), t in zip(slots, types):
+        cx, cy = fam.centre(i, j)
+        cyl = [b.surface(CZ, cx, cy, r * r) for r in radii]
+        m0 = 3 * int(t)
+        cells.append(([neg(cyl[0]), pos(z0), neg(z1)], m0, (0.0, 0.0, 0.0)))
+        cells.append(([pos(cyl[0]), neg(cyl[1]), pos(z0), neg(z1)], m0 + 1, (0.0, 0.0, 0.0)))
+        cells.append(([pos(cyl[1])] + fam.cell(i, j) + [pos(z0), neg(z1)], m0 + 2, (0.0, 0.0, 0.0)))
+    return b.universe(cells), fam, slots
+
+
+def batch_item(j: int) -> Tuple[FlatGeometry, int]:
+    """Geometry j of the batched workload and its history count (seeds 5000+j
+    for the geometry, 6000+j for the particles).  Square (pitch 1.25) or
+    hexagonal (pitch 1.3) with equal probability; lattice dimension (square
+    side, or hexagonal rings) uniform in 3..33; nesting levels uniform in
+    1..3: 1 = one universe with every pin's cylinders flattened into it,
+    2 = a lattice of pin universes at the root, 3 = a small lattice (3x3 or
+    2 rings) of such lattices; pins have cylinders r = 0.4/0.5 and three
+    types; |z| <= 10; histories log-uniform in [1e4, 1e6]."""
+    rng = np.random.default_rng(5000 + j)
+    hexa = bool(rng.integers(0, 2))
+    dim = int(rng.integers(3, 34))
+    levels = int(rng.integers(1, 4))
+    n_hist = int(round(math.exp(rng.uniform(math.log(1e4), math.log(1e6)))))
+    radii = (0.4, 0.5)
+    zb = BATCH_HALF_HEIGHT
+    sig = _sigmas(rng, 9)
+    b = GeomBuilder()
+    if not hexa:
+        pitch = SQ_PITCH
+        if levels == 1:
+            types = rng.integers(0, 3, size=(dim, dim))
+            root = _square_flat(b, dim, pitch, types, radii, zb)
+            h = 0.5 * dim * pitch
+        elif levels == 2:
+            types = rng.integers(0, 3, size=(dim, dim))
+            root = _square_lattice(b, dim, pitch, types + 1, True, (-zb, zb))
+            pins = [_pin_universe(b, radii, 3 * t) for t in range(3)]
+            assert root == 0 and pins == [1, 2, 3]
+            h = 0.5 * dim * pitch
+        else:
+            n_core, n_asm_types = 3, 2
+            core_types = rng.integers(0, n_asm_types, size=(n_core, n_core))
+            apitch = dim * pitch
+            root = _square_lattice(b, n_core, apitch, core_types + 1, True, (-zb, zb))
+            asms = [_square_lattice(b, dim, pitch, rng.integers(0, 3, size=(dim, dim)) + 1 + n_asm_types, False)
+                    for _ in range(n_asm_types)]
+            pins = [_pin_universe(b, radii, 3 * t) for t in range(3)]
+            assert root == 0 and asms == [1, 2] and pins == [3, 4, 5]
+            h = 0.5 * n_core * apitch
+        g = b.build(root, sig, (-h, -h, -zb), (h, h, zb), "batch%02d_sq%d_L%d" % (j, dim, levels))
+        return g, n_hist
+    pitch = HEX_PIN_PITCH
+    if levels == 1:
+        types = rng.integers(0, 3, size=len(hex_ring_cells(dim)))
+        root, fam, slots = _hex_flat(b, dim, pitch, types, radii, zb)
+        verts = [v for (i, jj) in slots for v in fam.vertices(i, jj)]
+    elif levels == 2:
+        fam = HexFamilies(b, pitch, 30.0)
+        z0, z1 = b.surface(PZ, -zb), b.surface(PZ, zb)
+        slots = hex_ring_cells(dim)
+        types = rng.integers(0, 3, size=len(slots))
+        cells = []
+        for (i, jj), t in zip(slots, types):
+            cx, cy = fam.centre(i, jj)
+            cells.append((fam.cell(i, jj) + [pos(z0), neg(z1)], fill_universe(1 + int(t)), (cx, cy, 0.0)))
+        root = b.universe(cells)
+        pins = [_pin_universe(b, radii, 3 * t) for t in range(3)]
+        assert root == 0 and pins == [1, 2, 3]
+        verts = [v for (i, jj) in slots for v in fam.vertices(i, jj)]
+    else:
+        n_asm_types = 2
+        F = 2.0 * ((dim - 1) * pitch * math.sqrt(3) / 2.0 + pitch / math.sqrt(3)) + 2 * HEX_GAP
+        fam_core = HexFamilies(b, F, 0.0)
+        z0, z1 = b.surface(PZ, -zb), b.surface(PZ, zb)
+        core = hex_ring_cells(2)
+        core_types = rng.integers(0, n_asm_types, size=len(core))
+        cells = []
+        for (i, jj), t in zip(core, core_types):
+            cx, cy = fam_core.centre(i, jj)
+            cells.append((fam_core.cell(i, jj) + [pos(z0), neg(z1)], fill_universe(1 + int(t)), (cx, cy, 0.0)))
+        root = b.universe(cells)
+        pins_in = hex_ring_cells(dim)
+        rim = hex_ring_cells(dim + 2)[len(pins_in):]
+        asms = []
+        for a in range(n_asm_types):
+            fam = HexFamilies(b, pitch, 30.0)
+            types = rng.integers(0, 3, size=len(pins_in))
+            cells = []
+            for (i, jj), t in zip(pins_in, types):
+                cx, cy = fam.centre(i, jj)
+                cells.append((fam.cell(i, jj), fill_universe(1 + n_asm_types + int(t)), (cx, cy, 0.0)))
+            for (i, jj) in rim:
+                cells.append((fam.cell(i, jj), 2, (0.0, 0.0, 0.0)))
+            asms.append(b.universe(cells))
+        pins = [_pin_universe(b, radii, 3 * t) for t in range(3)]
+        assert root == 0 and asms == [1, 2] and pins == [3, 4, 5]
+        verts = [v for (i, jj) in core for v in fam_core.vertices(i, jj)]
+    xs, ys = [v[0] for v in verts], [v[1] for v in verts]
+    m = 1e-9 * max(max(map(abs, xs)), max(map(abs, ys)))
+    g = b.build(0, sig, (min(xs) - m, min(ys) - m, -zb), (max(xs) + m, max(ys) + m, zb),
+                "batch%02d_hex%d_L%d" % (j, dim, levels))
+    return g, n_hist
+
+
+BATCH_SIZE = 64
+
+
+def config5() -> List[Tuple[FlatGeometry, int]]:
+    """The batched workload: 64 geometries and their history counts."""
+    return [batch_item(j) for j in range(BATCH_SIZE)]
+
+
 def hex_pin_box(half: float = 6.0, rings: int = 8, seed: int = 1104) -> FlatGeometry:
     """A box |x|,|y| <= half, |z| <= 100 filled with a flat-top hexagonal
     lattice of identical pins (pitch 1.3, cylinders 0.4/0.5) large enough to
@@ -468,3 +615,13 @@ def make_config(i: int) -> FlatGeometry:
 
 def particle_seed(i: int) -> int:
     return 2000 + i
+
+
+def batch_particle_seed(j: int) -> int:
+    """Particle seed of item j of the batched workload."""
+    return 6000 + j
+
+
+def batch_geometry_id(j: int) -> int:
+    """Geometry id (the fourth Philox counter word) of batch item j."""
+    return 100 + j

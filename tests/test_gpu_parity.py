@@ -183,12 +183,12 @@ def test_edge_cases():
     assert not g["tally_fx"].any() and sum(g["counters"].values()) == 0
 
 
-@pytest.mark.parametrize("block,lane", [(64, True), (128, True), (192, True), (64, False), (256, False),
-                                        (512, False), (1024, False)])
-def test_block_sizes_do_not_change_results(block, lane):
+@pytest.mark.parametrize("block,lane,refill", [(64, True, 0), (128, True, 0), (192, True, 0), (64, False, 1),
+                                               (256, False, 64), (512, False, 3), (1024, False, 0)])
+def test_launch_shapes_do_not_change_results(block, lane, refill):
     fg, G, O = geoms(2)
     kw = dict(seed=2002, n_particles=5000, geometry_id=2)
-    g = gpu_track(G, precision=gt.PREC_MIXED, block_size=block, lane_per_history=lane, **kw)
+    g = gpu_track(G, precision=gt.PREC_MIXED, block_size=block, lane_per_history=lane, refill_min=refill, **kw)
     o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT)
     assert_parity(g, o, where="block %d" % block)
 
@@ -218,6 +218,8 @@ def test_invalid_track_arguments():
         gt.track(G, seed=1, n_particles=10, block_size=100)
     with pytest.raises(gt.GtError):
         gt.track(G, seed=1, n_particles=10, block_size=512, lane_per_history=True)
+    with pytest.raises(gt.GtError):
+        gt.track(G, seed=1, n_particles=10, refill_min=65)
     with pytest.raises(gt.GtError):
         gt.track(G, seed=1, n_particles=10, source=1, ray_n1=0)
 
@@ -254,3 +256,142 @@ def test_full_size_sampled(cfg):
                                                geometry_id=cfg), n_threads=1, tallies=False)
         assert g["seq_hash"][i] == o.seq_hash[0] and g["seg_count"][i] == o.seg_count[0], i
         assert g["end_code"][i] == o.end_code[0]
+
+
+# ---------------------------------------------------------------- batched launch
+_batch = {}
+
+
+def batch_geoms(j):
+    if j not in _batch:
+        fg, n = synth.batch_item(j)
+        _batch[j] = (fg, n, gt.Geometry(fg), oracle.OracleGeometry(fg))
+    return _batch[j]
+
+
+def _outs(out):
+    return dict(tally_fx=_np(out.tally_fx).view(np.uint64), tally=_np(out.tally),
+                seg_count=_np(out.seg_count).view(np.uint32), seq_hash=_np(out.seq_hash).view(np.uint64),
+                end_code=_np(out.end_code), rec=_np(out.rec), counters=out.counters_dict())
+
+
+# square and hexagonal items, 1-3 levels, flattened universes up to 8931 cells
+BATCH_SUBSET = [0, 2, 3, 5, 7, 10, 25, 41, 57, 63]
+
+
+@pytest.mark.parametrize("prec", [gt.PREC_FP64, gt.PREC_MIXED])
+def test_batch_matches_oracle(prec):
+    """One batched launch over ten geometries (half of them forced to read
+    their tables from global memory, so both launches of the batch run), with
+    small chunks so every item is split into several and ends ragged."""
+    import torch
+    items, want = [], []
+    for k, j in enumerate(BATCH_SUBSET):
+        fg, n, G, O = batch_geoms(j)
+        n = min(n, 1500 + 137 * k)
+        kw = dict(first_particle=0, geometry_id=synth.batch_geometry_id(j), record_first_k=40, record_cap=64,
+                  precision=prec, staging=(k % 2 == 0))
+        items.append(gt.batch_item(G, synth.batch_particle_seed(j), n, **kw))
+        want.append(oracle.track(O, oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=n,
+                                                       geometry_id=synth.batch_geometry_id(j),
+                                                       record_first_k=40, record_cap=64), n_threads=NT))
+    print("batch of", len(items), "precision", prec, flush=True)
+    gt.track_batch(items, chunk=333)
+    torch.cuda.synchronize()
+    for j, it, o in zip(BATCH_SUBSET, items, want):
+        assert_parity(_outs(it.out), o, where="batch item %d" % j)
+
+
+def test_batch_graph_replays_match_eager():
+    """gt_batch_launch captured into a HIP graph: every replay (with other
+    device work and host synchronisation in between) reproduces the eager
+    launch exactly, including the zeroing of tallies and counters."""
+    import torch
+    items = []
+    for j in (3, 10, 41):
+        fg, n, G, O = batch_geoms(j)
+        items.append(gt.batch_item(G, synth.batch_particle_seed(j), 3000, geometry_id=synth.batch_geometry_id(j),
+                                   record_first_k=20, record_cap=32))
+    b = gt.Batch(items, chunk=700)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.launch(s)
+    s.synchronize()
+    eager = [_outs(it.out) for it in items]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        b.launch(s)
+    for r in range(3):
+        for it in items:   # scribble over the outputs between replays
+            it.out.tally_fx.fill_(7)
+            it.out.counters.fill_(3)
+            it.out.seq_hash.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for j, it, e in zip((3, 10, 41), items, eager):
+            g = _outs(it.out)
+            for k in ("tally_fx", "tally", "seg_count", "seq_hash", "end_code", "rec"):
+                assert np.array_equal(g[k], e[k]), (r, j, k)
+            assert g["counters"] == e["counters"], (r, j)
+    del graph
+    b.close()
+
+
+def test_batch_invalid_arguments():
+    fg, n, G, O = batch_geoms(3)
+    fg2, n2, G2, O2 = batch_geoms(10)
+    ok = dict(geometry_id=1)
+    with pytest.raises(gt.GtError) as e:
+        gt.track_batch([])
+    assert e.value.code == gt.GT_EINVAL
+    with pytest.raises(gt.GtError):   # geometry used twice
+        gt.track_batch([gt.batch_item(G, 1, 10, **ok), gt.batch_item(G, 2, 10, **ok)])
+    with pytest.raises(gt.GtError):   # mixed precisions
+        gt.track_batch([gt.batch_item(G, 1, 10, precision=gt.PREC_FP64, **ok),
+                        gt.batch_item(G2, 2, 10, precision=gt.PREC_MIXED, **ok)])
+    with pytest.raises(gt.GtError):
+        gt.track_batch([gt.batch_item(G, 1, 10, lane_per_history=True, **ok)])
+    with pytest.raises(gt.GtError):
+        gt.track_batch([gt.batch_item(G, 1, 10, max_collisions=0)])
+    with pytest.raises(gt.GtError):
+        gt.track_batch([gt.batch_item(G, 1, 10, **ok)], block_size=100)
+    with pytest.raises(gt.GtError):
+        gt.track_batch([gt.batch_item(G, 1, 10, **ok)], refill_min=65)
+    # an item with no histories: tallies and counters zeroed
+    it = gt.batch_item(G, 1, 0, **ok)
+    it.out.tally_fx.fill_(5)
+    gt.track_batch([it, gt.batch_item(G2, 1, 100, **ok)])
+    g = _outs(it.out)
+    assert not g["tally_fx"].any() and sum(g["counters"].values()) == 0
+
+
+def test_batch_full_workload_sampled():
+    """The 64-geometry batched workload at full size (1.42e7 histories, mixed
+    precision, default tuning): counters add up per item, every item's
+    results equal its own gt_track launch, and sampled particles of every
+    item re-run one by one in the oracle."""
+    import torch
+    items = []
+    for j in range(synth.BATCH_SIZE):
+        fg, n, G, O = batch_geoms(j)
+        items.append(gt.batch_item(G, synth.batch_particle_seed(j), n, geometry_id=synth.batch_geometry_id(j)))
+    print("batch full workload", flush=True)
+    gt.track_batch(items)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    for j, it in enumerate(items):
+        fg, n, G, O = batch_geoms(j)
+        g = _outs(it.out)
+        c = g["counters"]
+        assert c["escaped"] + c["capped"] + c["lost"] + c["segcap"] == n, j
+        assert c["segments"] == int(g["seg_count"].astype(np.int64).sum()), j
+        single = gpu_track(G, precision=gt.PREC_MIXED, seed=synth.batch_particle_seed(j), n_particles=n,
+                           geometry_id=synth.batch_geometry_id(j))
+        for k in ("tally_fx", "seg_count", "seq_hash", "end_code"):
+            assert np.array_equal(g[k], single[k]), (j, k)
+        for i in np.sort(rng.choice(n, size=6, replace=False)):
+            o = oracle.track(O, oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=1,
+                                                   first_particle=int(i), geometry_id=synth.batch_geometry_id(j)),
+                             n_threads=1, tallies=False)
+            assert g["seq_hash"][i] == o.seq_hash[0] and g["seg_count"][i] == o.seg_count[0], (j, i)
