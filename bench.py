@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--only", choices=["mixed", "fp64", "plain_fp64", "batch"], default=None,
                     help="time one mode only (profiling)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-geometry batched workload")
+    ap.add_argument("--no-tail", action="store_true", help="switch off tail compaction (comparison)")
     return ap.parse_args()
 
 
@@ -112,7 +113,7 @@ def run_timed(gt, step, args, hev):
 
 def timed(gt, G, out, args, prec, hev, lane=False):
     kw = dict(seed=2002, n_particles=args.particles, geometry_id=2, precision=prec, block_size=args.block, out=out,
-              lane_per_history=lane, refill_min=0 if lane else args.refill)
+              lane_per_history=lane, refill_min=0 if lane else args.refill, tail_compaction=not args.no_tail)
     r = run_timed(gt, lambda: gt.track(G, **kw), args, hev)
     r["segments"] = out.counters_dict()["segments"]
     return r
@@ -127,7 +128,7 @@ def batched(gt, synth, args, hev):
         G = gt.Geometry(fg)
         geoms.append((G, n, j))
         items.append(gt.batch_item(G, synth.batch_particle_seed(j), n, geometry_id=synth.batch_geometry_id(j),
-                                   precision=gt.PREC_MIXED))
+                                   precision=gt.PREC_MIXED, tail_compaction=not args.no_tail))
     b = gt.Batch(items, block_size=args.block, refill_min=args.refill)
     res = {"batched_mixed": run_timed(gt, b.launch, args, hev)}
     segs = sum(it.out.counters_dict()["segments"] for it in items)
@@ -135,7 +136,8 @@ def batched(gt, synth, args, hev):
         def step(prec=prec):
             for (G, n, j), it in zip(geoms, items):
                 gt.track(G, seed=synth.batch_particle_seed(j), n_particles=n, geometry_id=synth.batch_geometry_id(j),
-                         precision=prec, block_size=args.block, refill_min=args.refill, out=it.out)
+                         precision=prec, block_size=args.block, refill_min=args.refill, out=it.out,
+                         tail_compaction=not args.no_tail)
         res[name] = run_timed(gt, step, args, hev)
         if sum(it.out.counters_dict()["segments"] for it in items) != segs:
             raise RuntimeError("batched and sequential segment counts differ")

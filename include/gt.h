@@ -90,6 +90,8 @@ extern "C" {
                                           refilling schedule                                */
 #define GT_FLAG_NO_STAGING 4u          /* persistent schedule: read the geometry tables from
                                           global memory even when they fit in LDS           */
+#define GT_FLAG_NO_TAIL_COMPACTION 8u  /* persistent schedule: once the queue is empty, do not
+                                          pack the remaining histories into fewer waves      */
 
 typedef struct gt_geometry gt_geometry;   /* opaque; owns its device tables */
 

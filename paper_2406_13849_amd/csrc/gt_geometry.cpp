@@ -544,7 +544,7 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         sz[SEC_LOCAL] = cell_local.size() * 4;
         size_t total = 0;
         for (int i = 0; i < SEC_COUNT; i++) { off[i] = total; total = align_up(total + std::max(sz[i], (size_t)16)); }
-        std::vector<unsigned char> img(total, 0);
+        std::vector<unsigned char> img(total + 2 * sizeof(GeomDesc) + 2 * sizeof(LaunchRec) + 1024, 0);
         const void *src[SEC_COUNT] = {coef.data(), hs.data(), cell.data(), trans.data(), B.univ.data(),
                                       B.n32.data(), B.n64.data(), B.leaf.data(), cb.data(), F.sigma_t,
                                       adj_off.data(), adj.data(), cell_local.data()};
@@ -552,10 +552,14 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
             if (sz[i]) std::memcpy(img.data() + off[i], src[i], sz[i]);
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess) return set_error("hipGetDevice failed"), GT_EHIP;
+        const size_t desc_at = total;
+        total = align_up(total + sizeof(GeomDesc));
+        const size_t launch_at = total;
+        total = align_up(total + sizeof(LaunchRec));
         void *blob = nullptr;
         hipError_t e = hipMalloc(&blob, total);
         if (e != hipSuccess) return set_error("hipMalloc(%zu): %s", total, hipGetErrorString(e)), GT_ENOMEM;
-        e = hipMemcpy(blob, img.data(), total, hipMemcpyHostToDevice);
+        e = hipMemcpy(blob, img.data(), desc_at, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             (void)hipFree(blob);
             return set_error("hipMemcpy: %s", hipGetErrorString(e)), GT_EHIP;
@@ -606,6 +610,19 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
             }
             P.total = at > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)at;
         }
+        GeomDesc desc;
+        desc.dev = g->dev;
+        desc.stage[0] = g->stage[0];
+        desc.stage[1] = g->stage[1];
+        e = hipMemcpy(base + desc_at, &desc, sizeof desc, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(blob);
+            (void)hipFree(ws);
+            delete g;
+            return set_error("hipMemcpy: %s", hipGetErrorString(e)), GT_EHIP;
+        }
+        g->desc = (const GeomDesc *)(base + desc_at);
+        g->launch = (LaunchRec *)(base + launch_at);
         g->blob = blob;
         g->blob_bytes = total + ws_bytes;
         g->tally_ws = (uint64_t *)ws;
@@ -650,7 +667,7 @@ int gt::check_track_args(const gt_geometry *g, const gt_track_params *p, const g
     if (p->source == 1 && p->ray_n1 < 1) return set_error("gt_track: ray source needs ray_n1 >= 1"), GT_EINVAL;
     if (p->record_first_k && (!o->rec || p->record_cap < 1))
         return set_error("gt_track: recording needs rec and record_cap >= 1"), GT_EINVAL;
-    if (p->flags & ~(GT_FLAG_ACCUMULATE | GT_FLAG_LANE_PER_HISTORY | GT_FLAG_NO_STAGING))
+    if (p->flags & ~(GT_FLAG_ACCUMULATE | GT_FLAG_LANE_PER_HISTORY | GT_FLAG_NO_STAGING | GT_FLAG_NO_TAIL_COMPACTION))
         return set_error("gt_track: unknown flags 0x%x", p->flags), GT_EINVAL;
     if (p->block_size && (p->block_size % 64 || p->block_size > 1024))
         return set_error("gt_track: block_size must be a multiple of 64 up to 1024"), GT_EINVAL;
@@ -751,7 +768,7 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
         unsigned char *base = (unsigned char *)dm;
         fills.push_back({base + o_queue, 2, 0, 8, 0});
         for (const FillRange &f : fills) max_fill = std::max(max_fill, f.count);
-        std::vector<unsigned char> img(total, 0);
+        std::vector<unsigned char> img(total + 2 * sizeof(GeomDesc) + 2 * sizeof(LaunchRec) + 1024, 0);
         std::memcpy(img.data() + o_items, bi.data(), bi.size() * sizeof(BatchItem));
         if (!chunks.empty()) std::memcpy(img.data() + o_chunks, chunks.data(), chunks.size() * sizeof(BatchChunk));
         std::memcpy(img.data() + o_fill, fills.data(), fills.size() * sizeof(FillRange));
@@ -779,6 +796,7 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
         b->max_inst = max_inst;
         b->d_queue = (unsigned long long *)(base + o_queue);
         b->lds_bytes = lds;
+        b->tail = !(items[0].params.flags & GT_FLAG_NO_TAIL_COMPACTION);
         *out = b;
         return GT_OK;
     } catch (const std::bad_alloc &) {

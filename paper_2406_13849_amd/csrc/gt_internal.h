@@ -105,6 +105,19 @@ struct KOut {
     uint64_t *counters;
 };
 
+// Device copy of a geometry's descriptor (read-only for every launch).
+struct GeomDesc {
+    Dev dev;
+    StagePlan stage[2];
+};
+
+// Parameters of one tracking launch, written to device memory by a small
+// kernel ahead of it (so the tracker reads them through a pointer).
+struct LaunchRec {
+    KParams p;
+    KOut o;
+};
+
 // One item of a batched launch (device copy).
 struct BatchItem {
     Dev dev;
@@ -139,6 +152,8 @@ struct FinalizeItem {
 struct gt_geometry {
     gt::Dev dev;
     gt::StagePlan stage[2];   // per precision mode (GT_PREC_FP64, GT_PREC_MIXED)
+    const gt::GeomDesc *desc; // device copy of dev and stage (in the blob)
+    gt::LaunchRec *launch;    // device slot for the current launch's parameters (in the blob)
     void *blob;          // one device allocation holding every table
     uint64_t blob_bytes;
     uint64_t *tally_ws;  // tally workspace: 8 replicas x n_inst x 4 limb counters
@@ -161,7 +176,8 @@ struct gt_batch {
     gt::FinalizeItem *d_fin;
     uint64_t max_inst;
     unsigned long long *d_queue;        // two counters (staged and global launch)
-    uint32_t lds_bytes;                 // dynamic LDS of the staged launch
+    uint32_t lds_bytes;                 // staged tables' LDS bytes (largest item)
+    bool tail;                          // tail compaction on
 };
 
 namespace gt {

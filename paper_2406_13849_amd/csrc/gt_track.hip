@@ -22,6 +22,7 @@
 #pragma clang fp contract(off)
 
 #include <algorithm>
+#include <mutex>
 
 #include "gt_internal.h"
 
@@ -695,18 +696,21 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Copy the plan's sections of the device blob into LDS and point a Dev at
-// the copies (all lanes of the workgroup take part).  Every table the
-// precision mode reads is in the plan, so every pointer below is an LDS one.
-template <int PREC>
-__device__ __forceinline__ Dev stage_tables(const Dev &g, const StagePlan &sp, const unsigned char *blob,
-                                            unsigned char *lds) {
+// Copy the plan's sections of the device blob into LDS (all lanes of the
+// workgroup take part).
+__device__ __forceinline__ void stage_copy(const StagePlan &sp, const unsigned char *blob, unsigned char *lds) {
     for (uint32_t k = 0; k < sp.n; k++) {
         const uint4 *src = (const uint4 *)(blob + sp.src[k]);
         uint4 *dst = (uint4 *)(lds + sp.dst[k]);
         for (uint32_t i = threadIdx.x; i < sp.bytes[k] / 16; i += blockDim.x) dst[i] = src[i];
     }
     __syncthreads();
+}
+
+// A Dev whose tables are the LDS copies: every table the precision mode
+// reads is in the plan, so every pointer below is an LDS one.
+template <int PREC>
+__device__ __forceinline__ Dev lds_view(const Dev &g, const StagePlan &sp, unsigned char *lds) {
     Dev d = g;
     d.coef = (const double *)(lds + sp.at[SEC_COEF]);
     d.hs = (const uint32_t *)(lds + sp.at[SEC_HS]);
@@ -744,11 +748,30 @@ struct ChunkQueue {
     }
 };
 
+// Tail compaction.  Once the queue is empty for every wave of the
+// workgroup, the histories still running are spread thinly over its waves.
+// Every `round` loop trips the waves meet at a barrier; when the live
+// histories fit in fewer waves (and in the LDS buffer), each is written to
+// the buffer at its rank and read back by the lane of that rank, so fewer,
+// fuller waves carry the tail while the emptied ones wait at the barrier.  A
+// history's state moves as a whole, so its results do not depend on the lane
+// that finishes it.
+constexpr int kTailFields = 16;   // 64-bit words per moved history
+constexpr uint32_t kTailRound = 8;
+
+struct TailCfg {
+    uint64_t *buf;   // LDS, kTailFields x cap words (field-major)
+    uint32_t *ctl;   // LDS: [0] waves whose queue is empty, [1 + w] live lanes of wave w
+    uint32_t cap;    // histories the buffer holds; 0 = no compaction
+    uint32_t round;  // loop trips between compactions
+};
+
 // The persistent history loop of one lane (see above); returns when its
-// wave has drained the queue and every lane of the wave is idle.
+// wave has drained the queue and every lane of the wave is idle (with tail
+// compaction: when no lane of the workgroup has a history left).
 template <int PREC, typename Queue>
 __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const KOut &o, uint64_t *rep,
-                                           uint32_t *cells, const Queue &queue, Counts &cnt) {
+                                           uint32_t *cells, const Queue &queue, Counts &cnt, const TailCfg &tc) {
     Particle P;
     P.cell = cells;
     for (int L = 0; L < GT_MAX_LEVELS; L++) lvl(P, L) = 0;   // hints below read earlier levels
@@ -757,7 +780,7 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
     P.on_level = -1;
     P.on_surf = kNone;
     int mode = M_IDLE;
-    uint64_t local = 0, pid = 0;
+    uint64_t local = 0;
     uint32_t blk = 0;
     // history state
     uint64_t h = 0;
@@ -766,19 +789,124 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
     TallyAcc acc;
     acc.inst = kNone;
     acc.lo = acc.hi = 0;
-    // pending search: universe su at local point (qx,qy,qz) for level sL
+    // pending search at level sL: after a crossing, surface sforce (sense
+    // sfpos forced) through half-space entry sk; kNone in a descent.  The
+    // local position and universe there follow from the position and the
+    // cells of the levels above, and are recomputed at each search step.
     int sL = 0;
-    uint32_t su = 0, sforce = kNone, sk = 0;
+    uint32_t sforce = kNone, sk = 0;
     bool sfpos = false;
-    int32_t sexcl = -1;
-    double qx = 0, qy = 0, qz = 0;
-    float gx = 0, gy = 0;
     // wave-uniform pool of particle ids
     uint64_t pool_next = 0, pool_end = 0;
     bool drained = false;
     int end = GT_END_NONE;
+    // tail compaction state (wave-uniform)
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64u), nwaves = blockDim.x / 64u;
+    bool counted = false, in_tail = false;
+    uint32_t titer = 0;
 
     for (;;) {
+        if (tc.cap) {
+            if (drained && !counted) {
+                counted = true;
+                if (__lane_id() == 0) atomicAdd(&tc.ctl[0], 1u);
+            }
+            if (drained && !in_tail)
+                in_tail = __builtin_amdgcn_readfirstlane(__atomic_load_n(&tc.ctl[0], __ATOMIC_RELAXED)) == nwaves;
+            if (in_tail) {
+                const uint64_t act = __ballot(mode != M_IDLE);
+                if (act == 0 || ++titer >= tc.round) {
+                    titer = 0;
+                    if (__lane_id() == 0) tc.ctl[1 + wave] = (uint32_t)__popcll(act);
+                    __syncthreads();
+                    // (the counts are workgroup-uniform: read them as scalars)
+                    uint32_t A = 0, busy = 0, before = 0;
+                    for (uint32_t w = 0; w < nwaves; w++) {
+                        const uint32_t a = __builtin_amdgcn_readfirstlane(tc.ctl[1 + w]);
+                        A += a;
+                        busy += a ? 1u : 0u;
+                        before += w < wave ? a : 0u;
+                    }
+                    // every wave has read this round's counts before any wave
+                    // can write the next round's
+                    __syncthreads();
+                    if (A == 0) break;
+                    // pack the A live histories into lanes 0..A-1 of the workgroup
+                    // when that frees a wave and the buffer holds them all
+                    if (A <= tc.cap && (A + 63u) / 64u < busy) {
+                        const uint32_t C = tc.cap;
+                        if (mode != M_IDLE) {
+                            tally_flush(rep, acc);
+                            uint64_t *b = tc.buf + before + lane_rank(act);
+                            b[0 * C] = __double_as_longlong(P.x);
+                            b[1 * C] = __double_as_longlong(P.y);
+                            b[2 * C] = __double_as_longlong(P.z);
+                            b[3 * C] = __double_as_longlong(P.u);
+                            b[4 * C] = __double_as_longlong(P.v);
+                            b[5 * C] = __double_as_longlong(P.w);
+                            b[6 * C] = __double_as_longlong(P.tau);
+                            b[7 * C] = local;
+                            b[8 * C] = h;
+                            b[9 * C] = (uint64_t)blk | (uint64_t)segs << 32;
+                            b[10 * C] = (uint64_t)ncoll | (uint64_t)attempts << 32;
+                            b[11 * C] = (uint64_t)sforce | (uint64_t)sk << 32;
+                            const uint32_t fl = (uint32_t)mode | (uint32_t)recovf << 3 | (uint32_t)birth << 4 |
+                                                (uint32_t)sfpos << 5 | (uint32_t)P.depth << 8 |
+                                                (uint32_t)(P.on_level + 1) << 12 | (uint32_t)sL << 16;
+                            b[12 * C] = (uint64_t)P.on_surf | (uint64_t)fl << 32;
+                            for (int L = 0; L < GT_MAX_LEVELS; L += 2)
+                                b[(13 + L / 2) * C] = (uint64_t)lvl(P, L) | (uint64_t)lvl(P, L + 1) << 32;
+                        }
+                        __syncthreads();
+                        if (threadIdx.x < A) {
+                            const uint64_t *b = tc.buf + threadIdx.x;
+                            P.x = __longlong_as_double(b[0 * C]);
+                            P.y = __longlong_as_double(b[1 * C]);
+                            P.z = __longlong_as_double(b[2 * C]);
+                            P.u = __longlong_as_double(b[3 * C]);
+                            P.v = __longlong_as_double(b[4 * C]);
+                            P.w = __longlong_as_double(b[5 * C]);
+                            P.tau = __longlong_as_double(b[6 * C]);
+                            local = b[7 * C];
+                            h = b[8 * C];
+                            blk = (uint32_t)b[9 * C];
+                            segs = (uint32_t)(b[9 * C] >> 32);
+                            ncoll = (uint32_t)b[10 * C];
+                            attempts = (uint32_t)(b[10 * C] >> 32);
+                            sforce = (uint32_t)b[11 * C];
+                            sk = (uint32_t)(b[11 * C] >> 32);
+                            P.on_surf = (uint32_t)b[12 * C];
+                            const uint32_t fl = (uint32_t)(b[12 * C] >> 32);
+                            mode = (int)(fl & 7u);
+                            recovf = (fl >> 3) & 1u;
+                            birth = (fl >> 4) & 1u;
+                            sfpos = (fl >> 5) & 1u;
+                            P.depth = (int)((fl >> 8) & 15u);
+                            P.on_level = (int)((fl >> 12) & 15u) - 1;
+                            sL = (int)((fl >> 16) & 15u);
+                            for (int L = 0; L < GT_MAX_LEVELS; L += 2) {
+                                const uint64_t v = b[(13 + L / 2) * C];
+                                lvl(P, L) = (uint32_t)v;
+                                lvl(P, L + 1) = (uint32_t)(v >> 32);
+                            }
+                        } else {
+                            // no history here any more (all of the old one is in the buffer)
+                            mode = M_IDLE;
+                            P.x = P.y = P.z = P.u = P.v = P.w = P.tau = 0.0;
+                            local = h = 0;
+                            blk = segs = ncoll = attempts = sk = 0;
+                            sforce = P.on_surf = kNone;
+                            recovf = birth = sfpos = false;
+                            P.depth = 1;
+                            P.on_level = -1;
+                            sL = 0;
+                        }
+                        end = GT_END_NONE;
+                    }
+                    continue;
+                }
+            }
+        }
         // ---- refill idle lanes
         if (!drained) {
             uint64_t idle = __ballot(mode == M_IDLE);
@@ -797,7 +925,6 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
                 const uint32_t r = lane_rank(idle);
                 if (mode == M_IDLE && r < avail) {
                     local = pool_next + r;
-                    pid = p.first + local;
                     blk = 0;
                     h = kFnvOffset;
                     segs = ncoll = attempts = 0;
@@ -814,13 +941,29 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
                 idle = __ballot(mode == M_IDLE);
             }
         }
-        if (__ballot(mode != M_IDLE) == 0) break;
+        if (__ballot(mode != M_IDLE) == 0) {
+            if (!tc.cap) break;
+            // the queue is empty for this wave: wait for the workgroup's tail
+            // (no lane holds a history: the state is dead)
+            P.x = P.y = P.z = P.u = P.v = P.w = P.tau = 0.0;
+            local = h = 0;
+            blk = segs = ncoll = attempts = sk = 0;
+            sforce = P.on_surf = kNone;
+            recovf = birth = sfpos = false;
+            P.depth = 1;
+            P.on_level = -1;
+            sL = 0;
+            end = GT_END_NONE;
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
 
         // ---- draw: a birth-position attempt, or a direction attempt and its optical depth
         if (mode == M_POS || mode == M_DIR) {
             if (mode == M_POS && p.source == 1) {
                 const uint64_t n1 = p.ray_n1;
                 const uint64_t n2 = (p.n + n1 - 1) / n1;
+                const uint64_t pid = p.first + local;
                 const uint64_t j = pid % n1, k = pid / n1;
                 const double hy = (g.hi[1] - g.lo[1]) / (double)n1;
                 const double hz = (g.hi[2] - g.lo[2]) / (double)n2;
@@ -835,7 +978,7 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
                 end = GT_END_LOST;
             } else {
                 double u0, u1, u2;
-                draw_block(p.seed, p.geom_id, pid, blk++, u0, u1, u2);
+                draw_block(p.seed, p.geom_id, p.first + local, blk++, u0, u1, u2);
                 if (mode == M_POS) {
                     P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * u0;
                     P.y = g.lo[1] + (g.hi[1] - g.lo[1]) * u1;
@@ -848,29 +991,43 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
             }
             if (mode == M_POS && end == GT_END_NONE) {
                 sL = 0;
-                su = g.root;
                 sforce = kNone;
-                sexcl = -1;
-                qx = P.x;
-                qy = P.y;
-                qz = P.z;
-                gx = (float)qx;
-                gy = (float)qy;
                 mode = M_SEARCH;
             }
         }
 
         // ---- one level of find_cell / cross_surface
         if (mode == M_SEARCH) {
+            // local position and universe at level sL (translations applied
+            // level by level from the global position, as in the descent)
+            double qx = P.x, qy = P.y, qz = P.z;
+            uint32_t su = g.root;
+            for (int L = 0; L < sL; L++) {
+                const uint32_t cl = lvl(P, L);
+                const double *t = g.trans + 4 * (size_t)cl;
+                qx = qx - t[0];
+                qy = qy - t[1];
+                qz = qz - t[2];
+                su = (uint32_t)(-g.cell[cl].fill - 1);
+            }
+            const Univ U = g.univ[su];
+            // guess point for a lattice index; after a crossing it is nudged
+            // along the flight so that it lands on the far side
+            float gx = (float)qx, gy = (float)qy;
+            if (PREC == GT_PREC_MIXED && sforce != kNone && U.hint == (int32_t)kHintSquare) {
+                gx += (float)P.u * 1e-3f / U.inv_px;
+                gy += (float)P.v * 1e-3f / U.inv_py;
+            }
             // quick candidates first: after a crossing, the cells listed for the
             // crossed half-space; in a descent, the cell with the same index in
             // the new universe as the lane had at this level before
             uint32_t k0, k1, hint = 0;
+            int32_t excl = -1;
             if (sforce != kNone) {
                 k0 = g.adj_off[sk];
                 k1 = g.adj_off[sk + 1];
+                excl = (int32_t)lvl(P, sL);   // the cell being left
             } else {
-                const Univ U = g.univ[su];
                 const uint32_t loc = g.cell_local[lvl(P, sL)];
                 hint = U.cell0 + loc;
                 k0 = 0;
@@ -881,7 +1038,7 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
                 const uint32_t d = sforce != kNone ? g.adj[k] : hint;
                 if (contains(g, d, qx, qy, qz, sforce, sfpos)) { c = (int32_t)d; break; }
             }
-            if (c < 0) c = search<PREC>(g, su, qx, qy, qz, sforce, sfpos, sexcl, gx, gy);
+            if (c < 0) c = search<PREC>(g, su, qx, qy, qz, sforce, sfpos, excl, gx, gy);
             if (c < 0) {
                 if (birth) {
                     if (sL == 0 && p.source != 1) { cnt.rejected++; mode = M_POS; }
@@ -891,18 +1048,9 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
                 }
             } else {
                 lvl(P, sL) = (uint32_t)c;
-                const int32_t fill = g.cell[c].fill;
-                if (fill < 0) {
-                    const double *t = g.trans + 4 * (size_t)c;
-                    qx = qx - t[0];
-                    qy = qy - t[1];
-                    qz = qz - t[2];
-                    gx = (float)qx;
-                    gy = (float)qy;
-                    su = (uint32_t)(-fill - 1);
+                if (g.cell[c].fill < 0) {
                     sL++;
                     sforce = kNone;
-                    sexcl = -1;
                 } else {
                     P.depth = sL + 1;
                     if (birth) {
@@ -946,32 +1094,12 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
                 }
                 segs++;
                 if (boundary) {
-                    // set up cross_surface at level nr.level on surface nr.surf (Alg. 8):
-                    // the local position there, from the moved global position
-                    qx = P.x;
-                    qy = P.y;
-                    qz = P.z;
-                    for (int L = 0; L < nr.level; L++) {
-                        const double *t = g.trans + 4 * (size_t)lvl(P, L);
-                        qx = qx - t[0];
-                        qy = qy - t[1];
-                        qz = qz - t[2];
-                    }
-                    su = nr.univ;
+                    // cross_surface at level nr.level on surface nr.surf (Alg. 8),
+                    // at the local position there of the moved global position
                     sL = nr.level;
                     sforce = nr.surf;
                     sfpos = !nr.pos;
                     sk = nr.entry;
-                    sexcl = (int32_t)lvl(P, nr.level);
-                    gx = (float)qx;
-                    gy = (float)qy;
-                    if (PREC == GT_PREC_MIXED) {
-                        const Univ U = g.univ[su];
-                        if (U.hint == (int32_t)kHintSquare) {
-                            gx += (float)P.u * 1e-3f / U.inv_px;
-                            gy += (float)P.v * 1e-3f / U.inv_py;
-                        }
-                    }
                     P.on_level = nr.level;
                     P.on_surf = nr.surf;
                     mode = M_SEARCH;
@@ -999,16 +1127,32 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
     }
 }
 
+// Dynamic LDS of the persistent kernels: the staged tables (STAGED), then
+// the tail buffer at byte offset tail_at.
 template <int PREC, bool STAGED>
-__global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p, KOut o, StagePlan sp) {
+__global__ void __launch_bounds__(kBlockP) k_track_persistent(const GeomDesc *__restrict__ gd,
+                                                              const LaunchRec *__restrict__ lr, uint32_t tail_at,
+                                                              uint32_t tail_cap, uint32_t tail_round) {
     __shared__ uint32_t cells[GT_MAX_LEVELS * kBlockP];
+    __shared__ uint32_t ctl[1 + kBlockP / 64];
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_tables[];
-    const Dev g = STAGED ? stage_tables<PREC>(g0, sp, (const unsigned char *)g0.coef, lds_tables) : g0;
+    if (threadIdx.x == 0) ctl[0] = 0;
+    if (STAGED) stage_copy(gd->stage[PREC], (const unsigned char *)gd->dev.coef, lds_tables);
+    else __syncthreads();
+    const Dev g = STAGED ? lds_view<PREC>(gd->dev, gd->stage[PREC], lds_tables) : gd->dev;
+    const KParams &p = lr->p;
+    const KOut &o = lr->o;
     uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     const GlobalQueue q = {(unsigned long long *)&o.counters[7], p.n};
-    track_pool<PREC>(g, p, o, rep, cells + threadIdx.x, q, cnt);
+    const TailCfg tc = {(uint64_t *)(lds_tables + tail_at), ctl, tail_cap, tail_round};
+    track_pool<PREC>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc);
     add_counts(cnt, o.counters);
+}
+
+// Store a launch's parameters for the tracker that follows on the stream.
+__global__ void k_put_launch(LaunchRec r, LaunchRec *dst) {
+    if (threadIdx.x == 0) *dst = r;
 }
 
 // Many geometries in one persistent launch: each workgroup takes chunks
@@ -1016,37 +1160,41 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(Dev g0, KParams p,
 // tables into LDS when the item changes (STAGED), and runs the lanes' state
 // machine over the chunk with a workgroup-local id counter.
 template <int PREC, bool STAGED>
-__global__ void __launch_bounds__(kBlockP) k_track_batch(const BatchItem *items, const BatchChunk *chunks,
-                                                         uint32_t n_chunks, unsigned long long *queue) {
+__global__ void __launch_bounds__(kBlockP) k_track_batch(const BatchItem *__restrict__ items,
+                                                         const BatchChunk *__restrict__ chunks,
+                                                         uint32_t n_chunks, unsigned long long *queue,
+                                                         uint32_t tail_at, uint32_t tail_cap, uint32_t tail_round) {
     __shared__ uint32_t cells[GT_MAX_LEVELS * kBlockP];
+    __shared__ uint32_t ctl[1 + kBlockP / 64];
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_tables[];
     __shared__ uint32_t s_chunk;
     __shared__ unsigned long long s_pool;
-    int cur = -1;
-    Dev g;
-    KParams p;
-    KOut o;
+    const TailCfg tc = {(uint64_t *)(lds_tables + tail_at), ctl, tail_cap, tail_round};
+    // the descriptors are read-only for the whole launch: their fields are
+    // read where needed (scalar loads the compiler may repeat) rather than
+    // carried from chunk to chunk in registers
+    uint32_t cur = 0xFFFFFFFFu;
     for (;;) {
         if (threadIdx.x == 0) {
             s_chunk = (uint32_t)atomicAdd(queue, 1ull);
             s_pool = 0;
+            ctl[0] = 0;
         }
         __syncthreads();
-        const uint32_t c = s_chunk;
+        const uint32_t c = __builtin_amdgcn_readfirstlane(s_chunk);
         if (c >= n_chunks) break;
-        const BatchChunk ch = chunks[c];
-        if ((int)ch.item != cur) {
-            const BatchItem &it = items[ch.item];
-            p = it.p;
-            o = it.o;
-            g = it.dev;
-            if (STAGED) g = stage_tables<PREC>(it.dev, it.plan, (const unsigned char *)it.dev.coef, lds_tables);
-            cur = (int)ch.item;
-        }
+        const uint32_t item = chunks[c].item;
+        const uint64_t first = chunks[c].first, count = chunks[c].count;
+        const BatchItem &it = items[item];
+        if (STAGED && item != cur) stage_copy(it.plan, (const unsigned char *)it.dev.coef, lds_tables);
+        cur = item;
+        const Dev g = STAGED ? lds_view<PREC>(it.dev, it.plan, lds_tables) : it.dev;
+        const KParams &p = it.p;
+        const KOut &o = it.o;
         uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
         Counts cnt = {0, 0, 0, 0, 0, 0, 0};
-        const ChunkQueue q = {&s_pool, ch.first, ch.first + ch.count};
-        track_pool<PREC>(g, p, o, rep, cells + threadIdx.x, q, cnt);
+        const ChunkQueue q = {&s_pool, first, first + count};
+        track_pool<PREC>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc);
         add_counts(cnt, o.counters);
         __syncthreads();
     }
@@ -1201,7 +1349,10 @@ inline unsigned fill_grid(uint64_t n) {
 // Workgroups that fit on the device at once (all compute units, the
 // occupancy the kernel's resources allow), cached per device, kernel, block
 // size and dynamic LDS size.
+std::mutex g_launch_mu;   // guards the launch-shape caches below
+
 int persistent_grid(const void *kernel, unsigned block, unsigned dyn, int device, int *blocks) {
+    std::lock_guard<std::mutex> lk(g_launch_mu);
     static int cache_dev[64], cache_block[64], cache_n[64];
     static unsigned cache_dyn[64];
     static const void *cache_k[64];
@@ -1232,6 +1383,7 @@ int persistent_grid(const void *kernel, unsigned block, unsigned dyn, int device
 
 // Let a kernel use up to `bytes` of dynamic LDS (once per kernel).
 int allow_dynamic_lds(const void *kernel, unsigned bytes) {
+    std::lock_guard<std::mutex> lk(g_launch_mu);
     static const void *done[16];
     static int used = 0;
     for (int i = 0; i < used; i++)
@@ -1242,6 +1394,56 @@ int allow_dynamic_lds(const void *kernel, unsigned bytes) {
     if (used < 16) done[used++] = kernel;
     return GT_OK;
 }
+
+// LDS of a persistent launch: the staged tables (if any), then the tail
+// buffer, as large as the workgroup's share of the compute unit's LDS allows
+// without lowering the number of resident workgroups.
+struct LdsPlan {
+    unsigned dyn, tail_at, tail_cap;
+    int blocks;
+};
+
+constexpr unsigned kLdsPerCU = 160 * 1024;
+
+int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail, int device, LdsPlan &lp) {
+    hipFuncAttributes fa;
+    int rc = hip_check(hipFuncGetAttributes(&fa, kern), "hipFuncGetAttributes");
+    if (rc) return rc;
+    const unsigned stat = (unsigned)fa.sharedSizeBytes;
+    if (stat + tables > kLdsPerCU) return set_error("staged tables exceed the LDS"), GT_ECAPACITY;
+    rc = allow_dynamic_lds(kern, kLdsPerCU - stat);
+    if (rc) return rc;
+    const unsigned base = (tables + 15u) & ~15u;
+    int blocks = 0;
+    rc = persistent_grid(kern, block, base, device, &blocks);
+    if (rc) return rc;
+    int cus = 0;
+    rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
+    if (rc) return rc;
+    const unsigned per = (unsigned)std::max(1, blocks / std::max(cus, 1));
+    unsigned cap = 0;
+    if (tail && block > 64) {
+        const long avail = (long)(kLdsPerCU / per) - (long)stat - (long)base - 512;
+        if (avail > 0) cap = std::min<unsigned>((unsigned)(avail / (kTailFields * 8)), block);
+        if (cap < 64) cap = 0;
+    }
+    unsigned dyn = base + cap * kTailFields * 8;
+    if (cap) {
+        int b2 = 0;
+        rc = persistent_grid(kern, block, dyn, device, &b2);
+        if (rc) return rc;
+        if (b2 < blocks) {   // the buffer would cost a resident workgroup: go without
+            cap = 0;
+            dyn = base;
+        }
+    }
+    lp.dyn = dyn;
+    lp.tail_at = base;
+    lp.tail_cap = cap;
+    lp.blocks = blocks;
+    return GT_OK;
+}
+
 
 // Events recorded around the tracking kernels of this thread's next launches
 // (set by gt_set_kernel_events; both null = off).
@@ -1274,21 +1476,23 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
             const bool staged = !(p->flags & GT_FLAG_NO_STAGING) && sp.total <= kStageBudget;
             const void *kern = staged ? (const void *)k_track_persistent<PREC, true>
                                       : (const void *)k_track_persistent<PREC, false>;
-            const unsigned dyn = staged ? sp.total : 0;
-            int rc = GT_OK;
-            if (staged) rc = allow_dynamic_lds(kern, kStageBudget);
+            LdsPlan lp;
+            int rc = plan_persistent(kern, block, staged ? sp.total : 0, !(p->flags & GT_FLAG_NO_TAIL_COMPACTION),
+                                     g->device, lp);
             if (rc) return rc;
-            int blocks = 0;
-            rc = persistent_grid(kern, block, dyn, g->device, &blocks);
-            if (rc) return rc;
+            int blocks = lp.blocks;
             const uint64_t need = (kp.n + block - 1) / block;
             if ((uint64_t)blocks > need) blocks = (int)need;
+            LaunchRec rec;
+            rec.p = kp;
+            rec.o = ko;
+            hipLaunchKernelGGL(k_put_launch, dim3(1), dim3(64), 0, st, rec, g->launch);
             if (staged)
-                hipLaunchKernelGGL((k_track_persistent<PREC, true>), dim3(blocks), dim3(block), dyn, st, g->dev, kp, ko,
-                                   sp);
+                hipLaunchKernelGGL((k_track_persistent<PREC, true>), dim3(blocks), dim3(block), lp.dyn, st, g->desc,
+                                   (const LaunchRec *)g->launch, lp.tail_at, lp.tail_cap, kTailRound);
             else
-                hipLaunchKernelGGL((k_track_persistent<PREC, false>), dim3(blocks), dim3(block), 0, st, g->dev, kp, ko,
-                                   sp);
+                hipLaunchKernelGGL((k_track_persistent<PREC, false>), dim3(blocks), dim3(block), lp.dyn, st, g->desc,
+                                   (const LaunchRec *)g->launch, lp.tail_at, lp.tail_cap, kTailRound);
         }
     }
     mark(t_ev_stop, st);
@@ -1306,21 +1510,18 @@ int launch_batch_t(gt_batch *b, hipStream_t st) {
         const uint32_t n = pass == 0 ? b->n_staged : b->n_global;
         if (!n) continue;
         const void *kern = pass == 0 ? (const void *)k_track_batch<PREC, true> : (const void *)k_track_batch<PREC, false>;
-        const unsigned dyn = pass == 0 ? b->lds_bytes : 0;
-        int rc = GT_OK;
-        if (pass == 0) rc = allow_dynamic_lds(kern, kStageBudget);
+        LdsPlan lp;
+        int rc = plan_persistent(kern, b->block, pass == 0 ? b->lds_bytes : 0, b->tail, b->device, lp);
         if (rc) return rc;
-        int blocks = 0;
-        rc = persistent_grid(kern, b->block, dyn, b->device, &blocks);
-        if (rc) return rc;
+        int blocks = lp.blocks;
         if ((uint32_t)blocks > n) blocks = (int)n;
         const BatchChunk *ch = b->d_chunks + (pass == 0 ? 0 : b->n_staged);
         if (pass == 0)
-            hipLaunchKernelGGL((k_track_batch<PREC, true>), dim3(blocks), dim3(b->block), dyn, st, b->d_items, ch, n,
-                               b->d_queue);
+            hipLaunchKernelGGL((k_track_batch<PREC, true>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items, ch, n,
+                               b->d_queue, lp.tail_at, lp.tail_cap, kTailRound);
         else
-            hipLaunchKernelGGL((k_track_batch<PREC, false>), dim3(blocks), dim3(b->block), 0, st, b->d_items, ch, n,
-                               b->d_queue + 1);
+            hipLaunchKernelGGL((k_track_batch<PREC, false>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items, ch,
+                               n, b->d_queue + 1, lp.tail_at, lp.tail_cap, kTailRound);
     }
     mark(t_ev_stop, st);
     const uint64_t bx = std::min<uint64_t>((b->max_inst + 255) / 256, 1024);

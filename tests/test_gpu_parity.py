@@ -193,6 +193,18 @@ def test_launch_shapes_do_not_change_results(block, lane, refill):
     assert_parity(g, o, where="block %d" % block)
 
 
+@pytest.mark.parametrize("cfg", [1, 2, 4])
+@pytest.mark.parametrize("block", [128, 1024])
+def test_without_tail_compaction(cfg, block):
+    """Histories stay in their lanes after the queue drains: same results."""
+    fg, G, O = geoms(cfg)
+    kw = dict(seed=77, n_particles=7000, geometry_id=cfg)
+    g = gpu_track(G, precision=gt.PREC_MIXED, block_size=block, tail_compaction=False, record_first_k=50,
+                  record_cap=64, **kw)
+    o = oracle.track(O, oracle.TrackParams(record_first_k=50, record_cap=64, **kw), n_threads=NT)
+    assert_parity(g, o, where="no tail compaction cfg %s block %d" % (cfg, block))
+
+
 def test_accumulate_two_halves():
     import torch
     fg, G, O = geoms(1)
