@@ -52,6 +52,9 @@ def parse():
                     help="time one mode only (profiling)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-geometry batched workload")
     ap.add_argument("--no-tail", action="store_true", help="switch off tail compaction (comparison)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default launch shape instead of the one gt_autotune_track picks")
+    ap.add_argument("--tune-batch", action="store_true", help="autotune the batched launch shape first")
     return ap.parse_args()
 
 
@@ -114,8 +117,14 @@ def run_timed(gt, step, args, hev):
 def timed(gt, G, out, args, prec, hev, lane=False):
     kw = dict(seed=2002, n_particles=args.particles, geometry_id=2, precision=prec, block_size=args.block, out=out,
               lane_per_history=lane, refill_min=0 if lane else args.refill, tail_compaction=not args.no_tail)
+    shape = None
+    if not lane and not args.no_autotune and not args.block and not args.refill:
+        shape = gt.autotune_track(G, reps=2, **{k: v for k, v in kw.items() if k not in ("block_size", "refill_min")})
+        kw["block_size"], kw["refill_min"] = shape["block_size"], shape["refill_min"]
     r = run_timed(gt, lambda: gt.track(G, **kw), args, hev)
     r["segments"] = out.counters_dict()["segments"]
+    r["shape"] = {"block_size": kw["block_size"], "refill_min": kw["refill_min"],
+                  "autotuned": shape is not None}
     return r
 
 
@@ -129,7 +138,10 @@ def batched(gt, synth, args, hev):
         geoms.append((G, n, j))
         items.append(gt.batch_item(G, synth.batch_particle_seed(j), n, geometry_id=synth.batch_geometry_id(j),
                                    precision=gt.PREC_MIXED, tail_compaction=not args.no_tail))
-    b = gt.Batch(items, block_size=args.block, refill_min=args.refill)
+    tuned = None
+    if args.tune_batch:
+        tuned = gt.autotune_batch(items, reps=1)
+    b = gt.Batch(items, block_size=args.block, refill_min=args.refill, tuned=args.tune_batch)
     res = {"batched_mixed": run_timed(gt, b.launch, args, hev)}
     segs = sum(it.out.counters_dict()["segments"] for it in items)
     for name, prec in (("sequential_fp64", gt.PREC_FP64), ("sequential_mixed", gt.PREC_MIXED)):
@@ -143,7 +155,7 @@ def batched(gt, synth, args, hev):
             raise RuntimeError("batched and sequential segment counts differ")
     b.close()
     out = {"workload": "64 seeded square/hexagonal geometries, 1-3 levels, %d histories" %
-           sum(n for _, n, _ in geoms), "segments_per_step": segs}
+           sum(n for _, n, _ in geoms), "segments_per_step": segs, "batch_shape": tuned}
     for k, r in res.items():
         ms = sum(r["ms"]) / len(r["ms"])
         out[k] = {"value": segs / (ms * 1e-3), "ms_per_step": ms}
@@ -277,7 +289,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "17x17 square lattice of 3 axially split pin types (two levels), %d histories" % n,
                    "histories": n, "segments_per_step": head["segments"],
-                   "precision": "mixed" if "mixed" in res else "fp64", "parallelism": "none (1 GPU)"},
+                   "precision": "mixed" if "mixed" in res else "fp64", "parallelism": "none (1 GPU)",
+                   "launch_shape": head["shape"]},
     }
     for name, label in (("fp64", "fp64"), ("plain_fp64", "plain_fp64_lane_per_history")):
         if name in res:

@@ -218,7 +218,8 @@ typedef struct {
     uint32_t block_size;   /* threads per workgroup, multiple of 64 up to 1024; 0 = 1024      */
     uint32_t refill_min;   /* as gt_track_params.refill_min; 0 = 8                             */
     uint64_t chunk;        /* histories per work item taken from the device queue; 0 = 16384  */
-} gt_tuning;
+} gt_tuning;               /* a NULL gt_tuning* means: the shape gt_autotune_batch found for
+                              the same items in this process, else the defaults              */
 
 /* Validate a batch and upload its descriptors: per item the geometry
  * tables, parameters and output pointers; a work list of (item, particle
@@ -239,6 +240,32 @@ int gt_batch_create(const gt_batch_item *items, uint32_t n_items, const gt_tunin
 int gt_batch_launch(gt_batch *b, void *stream);
 
 void gt_batch_destroy(gt_batch *b);
+
+/* ---- launch-shape autotuning ---------------------------------------------
+ * Shapes change only the speed, never an output.  Both tuners synchronize
+ * the stream and overwrite the outputs they are given. */
+
+/* Time gt_track with every shape block_size in {256, 512, 1024} x refill_min
+ * in {1, 4, 8, 16} (one untimed and `reps` timed launches each) on the
+ * given parameters; *best gets the fastest (chunk = 0) and *best_ms its mean
+ * launch time (may be NULL).  The outputs end as those of one gt_track call
+ * with the winning shape.  The winner is cached in the process under
+ * (geometry, precision, staging and tail flags, histories rounded up to a
+ * power of two): see gt_tuning_lookup.  Errors as gt_track, and GT_EINVAL
+ * for GT_FLAG_LANE_PER_HISTORY (nothing to tune). */
+int gt_autotune_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, uint32_t reps,
+                      void *stream, gt_tuning *best, float *best_ms);
+
+/* The cached shape for these parameters: 1 and *out filled if
+ * gt_autotune_track has tuned such a launch in this process, else 0. */
+int gt_tuning_lookup(const gt_geometry *g, const gt_track_params *p, gt_tuning *out);
+
+/* Time gt_batch_launch for block_size in {512, 1024} x refill_min in
+ * {1, 4, 8, 16} x chunk in {4096, 16384, 65536}; *best gets the fastest.  The
+ * winner is cached in the process for this list of (geometry, histories,
+ * precision): gt_batch_create and gt_track_batch given a NULL tuning use it. */
+int gt_autotune_batch(const gt_batch_item *items, uint32_t n_items, uint32_t reps, void *stream, gt_tuning *best,
+                      float *best_ms);
 
 /* Timing hook (for benchmarks and profilers; the paper times the tracking
  * kernels alone).  With two hipEvent_t handles set, every later gt_track and

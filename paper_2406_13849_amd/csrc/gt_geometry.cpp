@@ -458,22 +458,49 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
             default: o[0] = q[0]; o[1] = q[1]; o[2] = q[2]; o[3] = q[3]; break;
             }
         }
-        // each cell's half-spaces planes first, then quadrics (the order never
-        // changes a result: containment is a conjunction and distance ties
-        // break on surface id)
+        // each cell's half-spaces: slab pairs, the other planes, then quadrics
+        // (the order never changes a result: containment is a conjunction and
+        // distance ties break on surface id)
         std::vector<uint32_t> hs(F.n_halfspaces);
         std::vector<Cell> cell(F.n_cells);
+        auto same_family = [&](uint32_t a, uint32_t b) {
+            if (F.surf_type[a] != F.surf_type[b]) return false;
+            if (F.surf_type[a] != ST_P) return true;   // one axis
+            return std::memcmp(F.surf_coef + 8 * (size_t)a, F.surf_coef + 8 * (size_t)b, 3 * sizeof(double)) == 0;
+        };
         for (uint32_t c = 0; c < F.n_cells; c++) {
-            uint32_t k0 = F.cell_hs_off[c], k1 = F.cell_hs_off[c + 1], o = k0, npl = 0;
-            for (int quad = 0; quad < 2; quad++)
-                for (uint32_t k = k0; k < k1; k++) {
-                    uint32_t s = B.surf_of(F.hs[k]);
-                    bool is_quad = F.surf_type[s] >= ST_CZ;
-                    if (is_quad != (quad == 1)) continue;
-                    hs[o++] = hs_pack(s, F.hs[k] > 0, F.surf_type[s]);
-                    npl += !is_quad;
+            const uint32_t k0 = F.cell_hs_off[c], k1 = F.cell_hs_off[c + 1];
+            std::vector<uint32_t> planes, quads;
+            for (uint32_t k = k0; k < k1; k++)
+                (F.surf_type[B.surf_of(F.hs[k])] >= ST_CZ ? quads : planes).push_back(k);
+            if (planes.size() > kPlaneCountMask) return set_error("cell %u: too many plane half-spaces", c), GT_ECAPACITY;
+            // a family with exactly one negative and one positive half-space forms a pair
+            std::vector<uint32_t> order, rest;
+            std::vector<bool> used(planes.size(), false);
+            uint32_t npair = 0;
+            for (size_t i = 0; i < planes.size(); i++) {
+                if (used[i]) continue;
+                std::vector<size_t> fam = {i};
+                for (size_t j = i + 1; j < planes.size(); j++)
+                    if (!used[j] && same_family(B.surf_of(F.hs[planes[i]]), B.surf_of(F.hs[planes[j]]))) fam.push_back(j);
+                for (size_t j : fam) used[j] = true;
+                if (fam.size() == 2 && (F.hs[planes[fam[0]]] > 0) != (F.hs[planes[fam[1]]] > 0) && npair < kMaxPairs) {
+                    const bool first_neg = F.hs[planes[fam[0]]] < 0;
+                    order.push_back(planes[first_neg ? fam[0] : fam[1]]);
+                    order.push_back(planes[first_neg ? fam[1] : fam[0]]);
+                    npair++;
+                } else {
+                    for (size_t j : fam) rest.push_back(planes[j]);
                 }
-            cell[c].n_pl = (uint16_t)npl;
+            }
+            order.insert(order.end(), rest.begin(), rest.end());
+            order.insert(order.end(), quads.begin(), quads.end());
+            uint32_t o = k0;
+            for (uint32_t k : order) {
+                const uint32_t s = B.surf_of(F.hs[k]);
+                hs[o++] = hs_pack(s, F.hs[k] > 0, F.surf_type[s]);
+            }
+            cell[c].n_pl = (uint16_t)(planes.size() | (size_t)npair << 12);
         }
         std::vector<double> trans(4 * (size_t)F.n_cells, 0.0);
         std::vector<float> cb(8 * (size_t)F.n_cells, 0.0f);
@@ -691,6 +718,8 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
     *out = nullptr;
     if (n_items == 0) return set_error("gt_batch_create: empty batch"), GT_EINVAL;
     if (n_items > 16384) return set_error("gt_batch_create: at most 16384 items"), GT_ECAPACITY;
+    gt_tuning cached;
+    if (!tuning && cached_batch_tuning(items, n_items, &cached)) tuning = &cached;
     const uint32_t block = tuning && tuning->block_size ? tuning->block_size : 1024;
     const uint32_t refill = tuning && tuning->refill_min ? tuning->refill_min : 0;
     const uint64_t chunk = tuning && tuning->chunk ? tuning->chunk : 16384;

@@ -21,10 +21,18 @@ constexpr uint32_t kLeafNone = 0xFFFFFFFFu;
 constexpr uint32_t kLeafMax = 4;       // cells per BVH leaf
 constexpr uint32_t kHintNone = 0, kHintSquare = 1;
 
+// A cell's plane half-spaces start with slab pairs: two planes of one family
+// (the same axis, or bitwise-identical normal coefficients) bounding the
+// cell from both sides, the negative-side one first.  Along any direction at
+// most one plane of a pair can be reached, chosen by the sign of the shared
+// denominator, so a pair costs one distance evaluation.
+constexpr uint32_t kPlaneCountMask = 0xFFFu, kMaxPairs = 15;
+
 // 16 bytes per cell; its half-spaces are stored planes first, then quadrics
 struct alignas(16) Cell {
     uint32_t hs_off;    // first packed half-space
-    uint16_t n_pl;      // number of plane half-spaces (stored first)
+    uint16_t n_pl;      // plane half-spaces (stored first): low 12 bits their number, high 4 bits
+                        // the number of slab pairs at their front (see kPlaneCountMask)
     uint16_t n_hs;      // number of half-spaces
     int32_t fill;       // >= 0 material, < 0 daughter universe -(u+1)
     uint32_t inst_off;  // leaf-instance offset of this cell within its universe
@@ -186,6 +194,7 @@ int check_track_args(const gt_geometry *g, const gt_track_params *p, const gt_tr
 void fill_kparams(const gt_track_params *p, const gt_geometry *g, KParams &kp, KOut &ko, const gt_track_out *o);
 unsigned stage_budget();
 void set_kernel_events(void *start, void *stop);
+bool cached_batch_tuning(const gt_batch_item *items, uint32_t n_items, gt_tuning *out);
 int launch_batch(gt_batch *b, void *stream);
 int launch_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream);
 int launch_find_cell(const gt_geometry *g, const double *pos, uint64_t n, int64_t *inst, int32_t *cells,

@@ -148,13 +148,14 @@ __device__ __forceinline__ bool contains(const Dev &g, uint32_t c, double x, dou
                                          bool force_pos) {
     const Cell cc = g.cell[c];
     const uint32_t *hs = g.hs + cc.hs_off;
-    for (uint32_t k = 0; k < cc.n_pl; k++) {
+    const uint32_t npl = cc.n_pl & kPlaneCountMask;
+    for (uint32_t k = 0; k < npl; k++) {
         const uint32_t h = hs[k];
         const uint32_t s = h >> 4;
         const bool pos = (s == force_s) ? force_pos : (plane_value(h & 7u, g.coef + 4 * (size_t)s, x, y, z) > 0.0);
         if (pos != (bool)((h >> 3) & 1u)) return false;
     }
-    for (uint32_t k = cc.n_pl; k < cc.n_hs; k++) {
+    for (uint32_t k = npl; k < cc.n_hs; k++) {
         const uint32_t h = hs[k];
         const uint32_t s = h >> 4;
         const bool pos = (s == force_s) ? force_pos : (quad_value(h & 7u, g.coef + 4 * (size_t)s, x, y, z) > 0.0);
@@ -165,15 +166,18 @@ __device__ __forceinline__ bool contains(const Dev &g, uint32_t c, double x, dou
 
 // Distance along (u,v,w) from q to the point where a plane's sense leaves
 // the cell's required side `pos`; +inf if it does not (Table 1).
+__device__ __forceinline__ double plane_den(uint32_t type, const double *c, double u, double v, double w) {
+    switch (type) {
+    case ST_PX: return u;
+    case ST_PY: return v;
+    case ST_PZ: return w;
+    default: return (c[0] * u + c[1] * v) + c[2] * w;
+    }
+}
+
 __device__ __forceinline__ double plane_distance(uint32_t type, const double *c, bool pos, double qx, double qy,
                                                  double qz, double u, double v, double w) {
-    double den;
-    switch (type) {
-    case ST_PX: den = u; break;
-    case ST_PY: den = v; break;
-    case ST_PZ: den = w; break;
-    default: den = (c[0] * u + c[1] * v) + c[2] * w; break;
-    }
+    const double den = plane_den(type, c, u, v, w);
     if (den == 0.0) return dinf();
     if (!((!pos && den > 0.0) || (pos && den < 0.0))) return dinf();
     const double t = (-plane_value(type, c, qx, qy, qz)) / den;
@@ -327,7 +331,8 @@ __device__ __forceinline__ double distance_all(const Dev &g, const Particle &P, 
         }
         const Cell cc = g.cell[c];
         const uint32_t *hs = g.hs + cc.hs_off;
-        for (uint32_t k = 0; k < cc.n_pl; k++) {
+        const uint32_t npl = cc.n_pl & kPlaneCountMask;
+        for (uint32_t k = 0; k < npl; k++) {
             const uint32_t h = hs[k];
             const uint32_t s = h >> 4;
             const bool pos = (h >> 3) & 1u;
@@ -341,7 +346,7 @@ __device__ __forceinline__ double distance_all(const Dev &g, const Particle &P, 
                 bk = cc.hs_off + k;
             }
         }
-        for (uint32_t k = cc.n_pl; k < cc.n_hs; k++) {
+        for (uint32_t k = npl; k < cc.n_hs; k++) {
             const uint32_t h = hs[k];
             const uint32_t s = h >> 4;
             const bool pos = (h >> 3) & 1u;
@@ -394,8 +399,31 @@ __device__ __forceinline__ void nearest_surface(const Dev &g, const Particle &P,
         fill = cc.fill;
         r.inst += cc.inst_off;
         const uint32_t *hs = g.hs + cc.hs_off;
+        const uint32_t npl = cc.n_pl & kPlaneCountMask, npair2 = 2u * (cc.n_pl >> 12);
         bool better = false;
-        for (uint32_t k = 0; k < cc.n_pl; k++) {
+        for (uint32_t k = 0; k < npair2; k += 2) {
+            // a slab pair: the shared denominator picks the one plane that can be
+            // reached (the negative-side one when it is positive); the other
+            // would give no hit
+            const uint32_t h0 = hs[k];
+            const double den = plane_den(h0 & 7u, g.coef + 4 * (size_t)(h0 >> 4), P.u, P.v, P.w);
+            if (den == 0.0) continue;
+            const uint32_t kk = den > 0.0 ? k : k + 1;
+            const uint32_t h = den > 0.0 ? h0 : hs[k + 1];
+            const uint32_t s = h >> 4;
+            if (P.on_level == L && P.on_surf == s) continue;   // a plane just crossed is not hit again
+            const double t = (-plane_value(h & 7u, g.coef + 4 * (size_t)s, qx, qy, qz)) / den;
+            const double d = (t > 0.0) ? t : 0.0;
+            if (d < r.t || (d == r.t && d != dinf() && L == r.level && s < r.surf)) {
+                r.t = d;
+                r.level = L;
+                r.surf = s;
+                r.pos = den < 0.0;
+                r.entry = cc.hs_off + kk;
+                better = true;
+            }
+        }
+        for (uint32_t k = npair2; k < npl; k++) {
             const uint32_t h = hs[k];
             const uint32_t s = h >> 4;
             const bool pos = (h >> 3) & 1u;
@@ -410,7 +438,7 @@ __device__ __forceinline__ void nearest_surface(const Dev &g, const Particle &P,
                 better = true;
             }
         }
-        for (uint32_t k = cc.n_pl; k < cc.n_hs; k++) {
+        for (uint32_t k = npl; k < cc.n_hs; k++) {
             const uint32_t h = hs[k];
             const uint32_t s = h >> 4;
             const bool pos = (h >> 3) & 1u;

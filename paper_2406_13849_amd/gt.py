@@ -98,6 +98,14 @@ def lib():
         L.gt_batch_destroy.restype = None
         L.gt_track_batch.argtypes = [C.POINTER(_BatchItem), u32, C.POINTER(_Tuning), vp]
         L.gt_track_batch.restype = i32
+        L.gt_autotune_track.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), u32, vp, C.POINTER(_Tuning),
+                                        C.POINTER(C.c_float)]
+        L.gt_autotune_track.restype = i32
+        L.gt_tuning_lookup.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Tuning)]
+        L.gt_tuning_lookup.restype = i32
+        L.gt_autotune_batch.argtypes = [C.POINTER(_BatchItem), u32, u32, vp, C.POINTER(_Tuning),
+                                        C.POINTER(C.c_float)]
+        L.gt_autotune_batch.restype = i32
         L.gt_set_kernel_events.argtypes = [vp, vp]
         L.gt_set_kernel_events.restype = i32
         L.gt_find_cell.argtypes = [vp, vp, u64, vp, vp, u32, vp]
@@ -260,16 +268,14 @@ class Batch:
     tracked by one persistent launch.  The descriptors hold the geometries'
     tables and the outputs' addresses, so both are kept alive here."""
 
-    def __init__(self, items, block_size: int = 0, refill_min: int = 0, chunk: int = 0):
+    def __init__(self, items, block_size: int = 0, refill_min: int = 0, chunk: int = 0, tuned: bool = False):
+        """tuned=True passes no tuning: the shape gt_autotune_batch found for
+        these items (else the defaults)."""
         self.items = list(items)
-        arr = (_BatchItem * max(len(self.items), 1))()
-        for i, it in enumerate(self.items):
-            arr[i].geometry = it.geom.h
-            arr[i].params = _params(it.seed, it.n_particles, **it.kwargs)
-            arr[i].out = _out_struct(it.out)
-        tun = _Tuning(block_size=block_size, refill_min=refill_min, chunk=chunk)
+        arr = _batch_array(self.items)
+        tun = None if tuned else C.byref(_Tuning(block_size=block_size, refill_min=refill_min, chunk=chunk))
         h = C.c_void_p()
-        _check(lib().gt_batch_create(arr, len(self.items), C.byref(tun), C.byref(h)))
+        _check(lib().gt_batch_create(arr, len(self.items), tun, C.byref(h)))
         self.h = h.value
 
     def launch(self, stream=None):
@@ -294,16 +300,57 @@ def batch_item(geom: Geometry, seed: int, n_particles: int, out: Optional[TrackO
     return BatchItem(geom, seed, n_particles, out, kwargs)
 
 
-def track_batch(items, block_size: int = 0, refill_min: int = 0, chunk: int = 0, stream=None):
+def track_batch(items, block_size: int = 0, refill_min: int = 0, chunk: int = 0, tuned: bool = False,
+                stream=None):
     """gt_track_batch: one-shot batch (waits for the stream)."""
+    arr = _batch_array(items)
+    tun = None if tuned else C.byref(_Tuning(block_size=block_size, refill_min=refill_min, chunk=chunk))
+    _check(lib().gt_track_batch(arr, len(items), tun, _stream(stream)))
+    return [it.out for it in items]
+
+
+def autotune_track(geom: Geometry, seed: int, n_particles: int, out: Optional[TrackOutputs] = None, reps: int = 3,
+                   stream=None, **kwargs) -> dict:
+    """gt_autotune_track: the fastest (block_size, refill_min) for these
+    parameters (the outputs are overwritten and end as those of one launch
+    with that shape); also cached in the library for gt_tuning_lookup."""
+    if out is None:
+        out = alloc_outputs(geom, n_particles, kwargs.get("record_first_k", 0), kwargs.get("record_cap", 0))
+    prm = _params(seed, n_particles, **kwargs)
+    best = _Tuning()
+    ms = C.c_float()
+    _check(lib().gt_autotune_track(geom.h, C.byref(prm), C.byref(_out_struct(out)), reps, _stream(stream),
+                                   C.byref(best), C.byref(ms)))
+    return dict(block_size=best.block_size, refill_min=best.refill_min, ms=ms.value)
+
+
+def tuning_lookup(geom: Geometry, seed: int, n_particles: int, **kwargs) -> Optional[dict]:
+    """gt_tuning_lookup: the cached shape for such a launch, or None."""
+    best = _Tuning()
+    prm = _params(seed, n_particles, **kwargs)
+    rc = lib().gt_tuning_lookup(geom.h, C.byref(prm), C.byref(best))
+    if rc < 0:
+        _check(rc)
+    return dict(block_size=best.block_size, refill_min=best.refill_min) if rc == 1 else None
+
+
+def _batch_array(items):
     arr = (_BatchItem * max(len(items), 1))()
     for i, it in enumerate(items):
         arr[i].geometry = it.geom.h
         arr[i].params = _params(it.seed, it.n_particles, **it.kwargs)
         arr[i].out = _out_struct(it.out)
-    tun = _Tuning(block_size=block_size, refill_min=refill_min, chunk=chunk)
-    _check(lib().gt_track_batch(arr, len(items), C.byref(tun), _stream(stream)))
-    return [it.out for it in items]
+    return arr
+
+
+def autotune_batch(items, reps: int = 1, stream=None) -> dict:
+    """gt_autotune_batch: the fastest (block_size, refill_min, chunk) for this
+    list of items; Batch(items) and track_batch(items) then use it."""
+    best = _Tuning()
+    ms = C.c_float()
+    _check(lib().gt_autotune_batch(_batch_array(items), len(items), reps, _stream(stream), C.byref(best),
+                                   C.byref(ms)))
+    return dict(block_size=best.block_size, refill_min=best.refill_min, chunk=best.chunk, ms=ms.value)
 
 
 def set_kernel_events(start: Optional[int], stop: Optional[int]):

@@ -407,3 +407,36 @@ def test_batch_full_workload_sampled():
                                                    first_particle=int(i), geometry_id=synth.batch_geometry_id(j)),
                              n_threads=1, tallies=False)
             assert g["seq_hash"][i] == o.seq_hash[0] and g["seg_count"][i] == o.seg_count[0], (j, i)
+
+
+# ---------------------------------------------------------------- autotuning
+def test_autotune_track_keeps_results():
+    """The tuner's launches leave the outputs of the caller's parameters, and
+    the winning shape is one of the candidates and is cached."""
+    fg, G, O = geoms(2)
+    kw = dict(seed=515, n_particles=6000, geometry_id=2, record_first_k=30, record_cap=64)
+    out = gt.alloc_outputs(G, 6000, 30, 64)
+    shape = gt.autotune_track(G, out=out, reps=1, precision=gt.PREC_MIXED, **kw)
+    assert shape["block_size"] in (256, 512, 1024) and shape["refill_min"] in (1, 4, 8, 16)
+    assert gt.tuning_lookup(G, precision=gt.PREC_MIXED, **kw) == {k: shape[k] for k in ("block_size", "refill_min")}
+    import torch
+    torch.cuda.synchronize()
+    o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT)
+    assert_parity(_outs(out), o, where="after autotune")
+
+
+def test_autotune_batch_then_tuned_batch():
+    import torch
+    items, want = [], []
+    for j in (3, 41, 57):
+        fg, n, G, O = batch_geoms(j)
+        kw = dict(geometry_id=synth.batch_geometry_id(j))
+        items.append(gt.batch_item(G, synth.batch_particle_seed(j), 2500, **kw))
+        want.append(oracle.track(O, oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=2500, **kw),
+                                 n_threads=NT))
+    shape = gt.autotune_batch(items, reps=1)
+    assert shape["block_size"] in (512, 1024) and shape["chunk"] in (4096, 16384, 65536)
+    gt.track_batch(items, tuned=True)
+    torch.cuda.synchronize()
+    for it, o in zip(items, want):
+        assert_parity(_outs(it.out), o, where="tuned batch")
