@@ -163,8 +163,10 @@ typedef struct {
     uint32_t record_cap;      /* entries recorded per particle                       */
     uint32_t flags;           /* GT_FLAG_*                                           */
     uint32_t block_size;      /* threads per workgroup, a multiple of 64: up to 1024
-                                 (persistent schedule, default 1024) or up to 256
-                                 (GT_FLAG_LANE_PER_HISTORY, default 256); 0 = default */
+                                 (persistent schedule, default 1024; 640 selects a
+                                 build for two workgroups of 10 waves per compute
+                                 unit) or up to 256 (GT_FLAG_LANE_PER_HISTORY,
+                                 default 256); 0 = default                          */
     uint32_t refill_min;      /* persistent schedule: a wave starts new histories once at
                                  least this many of its lanes are idle (1..64; 0 = 8)   */
     uint32_t reserved;        /* must be 0                                           */
@@ -245,7 +247,7 @@ void gt_batch_destroy(gt_batch *b);
  * Shapes change only the speed, never an output.  Both tuners synchronize
  * the stream and overwrite the outputs they are given. */
 
-/* Time gt_track with every shape block_size in {256, 512, 1024} x refill_min
+/* Time gt_track with every shape block_size in {256, 512, 640, 1024} x refill_min
  * in {1, 4, 8, 16} (one untimed and `reps` timed launches each) on the
  * given parameters; *best gets the fastest (chunk = 0) and *best_ms its mean
  * launch time (may be NULL).  The outputs end as those of one gt_track call
@@ -260,7 +262,7 @@ int gt_autotune_track(const gt_geometry *g, const gt_track_params *p, const gt_t
  * gt_autotune_track has tuned such a launch in this process, else 0. */
 int gt_tuning_lookup(const gt_geometry *g, const gt_track_params *p, gt_tuning *out);
 
-/* Time gt_batch_launch for block_size in {512, 1024} x refill_min in
+/* Time gt_batch_launch for block_size in {512, 640, 1024} x refill_min in
  * {1, 4, 8, 16} x chunk in {4096, 16384, 65536}; *best gets the fastest.  The
  * winner is cached in the process for this list of (geometry, histories,
  * precision): gt_batch_create and gt_track_batch given a NULL tuning use it. */

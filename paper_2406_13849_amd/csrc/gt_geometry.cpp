@@ -618,16 +618,25 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         g->dev.max_depth = B.depth[F.root];
         g->dev.n_cells = F.n_cells;
         for (int k = 0; k < 3; k++) { g->dev.lo[k] = F.domain_lo[k]; g->dev.hi[k] = F.domain_hi[k]; }
-        // LDS staging plans: the tables each precision mode reads, packed
+        // LDS staging plans: the tables each precision mode reads, in order of
+        // use per segment (cells, half-spaces, surfaces, ... first; the
+        // hierarchy, used only when the quick candidates miss, last), as many
+        // as fit in the LDS budget; the others stay in global memory
+        static const int kStageOrder[SEC_COUNT] = {SEC_CELL,  SEC_HS,  SEC_COEF,   SEC_UNIV,   SEC_TRANS,
+                                                   SEC_SIGMA, SEC_ADJOFF, SEC_ADJ, SEC_LOCAL, SEC_NODE32,
+                                                   SEC_NODE64, SEC_LEAF, SEC_CBOX};
+        const uint64_t budget = stage_budget();
         for (int prec = 0; prec < 2; prec++) {
             StagePlan &P = g->stage[prec];
             std::memset(&P, 0, sizeof P);
+            for (int i = 0; i < SEC_COUNT; i++) P.at[i] = 0xFFFFFFFFu;
             uint64_t at = 0;
-            for (int i = 0; i < SEC_COUNT; i++) {
+            for (int oi = 0; oi < SEC_COUNT; oi++) {
+                const int i = kStageOrder[oi];
                 const bool need = prec == GT_PREC_MIXED ? (i != SEC_NODE64) : (i != SEC_NODE32 && i != SEC_CBOX);
-                P.at[i] = 0xFFFFFFFFu;
                 if (!need) continue;
                 const uint64_t b = (std::max<size_t>(sz[i], 16) + 15) & ~(uint64_t)15;
+                if (at + b > budget) continue;
                 P.src[P.n] = (uint32_t)off[i];
                 P.dst[P.n] = (uint32_t)at;
                 P.bytes[P.n] = (uint32_t)b;
@@ -753,7 +762,7 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
             gt_track_params p = it.params;
             p.refill_min = refill ? refill : p.refill_min;
             fill_kparams(&p, g, b.p, b.o, &it.out);
-            staged[i] = !(it.params.flags & GT_FLAG_NO_STAGING) && b.plan.total <= stage_budget();
+            staged[i] = !(it.params.flags & GT_FLAG_NO_STAGING) && b.plan.n > 0;
             if (staged[i]) lds = std::max(lds, b.plan.total);
             fills.push_back({g->tally_ws, (uint64_t)8 * 4 * g->n_inst, 0, 8, 0});
             fills.push_back({it.out.counters, 8, 0, 8, 0});

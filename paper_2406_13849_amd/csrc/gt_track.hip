@@ -735,27 +735,30 @@ __device__ __forceinline__ void stage_copy(const StagePlan &sp, const unsigned c
     __syncthreads();
 }
 
-// A Dev whose tables are the LDS copies: every table the precision mode
-// reads is in the plan, so every pointer below is an LDS one.
+// A Dev whose staged tables are the LDS copies (the others stay in global
+// memory).
 template <int PREC>
 __device__ __forceinline__ Dev lds_view(const Dev &g, const StagePlan &sp, unsigned char *lds) {
     Dev d = g;
-    d.coef = (const double *)(lds + sp.at[SEC_COEF]);
-    d.hs = (const uint32_t *)(lds + sp.at[SEC_HS]);
-    d.cell = (const Cell *)(lds + sp.at[SEC_CELL]);
-    d.trans = (const double *)(lds + sp.at[SEC_TRANS]);
-    d.univ = (const Univ *)(lds + sp.at[SEC_UNIV]);
-    d.leaf = (const uint32_t *)(lds + sp.at[SEC_LEAF]);
+    auto at = [&](int sec, const void *dflt) -> const void * {
+        return sp.at[sec] != 0xFFFFFFFFu ? (const void *)(lds + sp.at[sec]) : dflt;
+    };
+    d.coef = (const double *)at(SEC_COEF, g.coef);
+    d.hs = (const uint32_t *)at(SEC_HS, g.hs);
+    d.cell = (const Cell *)at(SEC_CELL, g.cell);
+    d.trans = (const double *)at(SEC_TRANS, g.trans);
+    d.univ = (const Univ *)at(SEC_UNIV, g.univ);
+    d.leaf = (const uint32_t *)at(SEC_LEAF, g.leaf);
     if (PREC == GT_PREC_MIXED) {
-        d.node32 = (const Node32 *)(lds + sp.at[SEC_NODE32]);
-        d.cbox = (const float *)(lds + sp.at[SEC_CBOX]);
+        d.node32 = (const Node32 *)at(SEC_NODE32, g.node32);
+        d.cbox = (const float *)at(SEC_CBOX, g.cbox);
     } else {
-        d.node64 = (const Node64 *)(lds + sp.at[SEC_NODE64]);
+        d.node64 = (const Node64 *)at(SEC_NODE64, g.node64);
     }
-    d.sigma = (const double *)(lds + sp.at[SEC_SIGMA]);
-    d.adj_off = (const uint32_t *)(lds + sp.at[SEC_ADJOFF]);
-    d.adj = (const uint32_t *)(lds + sp.at[SEC_ADJ]);
-    d.cell_local = (const uint32_t *)(lds + sp.at[SEC_LOCAL]);
+    d.sigma = (const double *)at(SEC_SIGMA, g.sigma);
+    d.adj_off = (const uint32_t *)at(SEC_ADJOFF, g.adj_off);
+    d.adj = (const uint32_t *)at(SEC_ADJ, g.adj);
+    d.cell_local = (const uint32_t *)at(SEC_LOCAL, g.cell_local);
     return d;
 }
 
@@ -1157,13 +1160,19 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
 
 // Dynamic LDS of the persistent kernels: the staged tables (STAGED), then
 // the tail buffer at byte offset tail_at.
-template <int PREC, bool STAGED>
-__global__ void __launch_bounds__(kBlockP) k_track_persistent(const GeomDesc *__restrict__ gd,
-                                                              const LaunchRec *__restrict__ lr, uint32_t tail_at,
-                                                              uint32_t tail_cap, uint32_t tail_round) {
-    __shared__ uint32_t cells[GT_MAX_LEVELS * kBlockP];
+// W = waves per SIMD the register budget is cut for: 4 (up to 1024 lanes
+// per workgroup, 128 registers) or 5 (640 lanes, two workgroups per compute
+// unit, 96 registers).
+template <int PREC, bool STAGED, int W>
+__global__ void __launch_bounds__(W == 5 ? 640 : kBlockP) __attribute__((amdgpu_waves_per_eu(W)))
+k_track_persistent(const GeomDesc *__restrict__ gd,
+                                                              const LaunchRec *__restrict__ lr, uint32_t tables_at,
+                                                              uint32_t tail_at, uint32_t tail_cap,
+                                                              uint32_t tail_round) {
     __shared__ uint32_t ctl[1 + kBlockP / 64];
-    extern __shared__ __attribute__((aligned(16))) unsigned char lds_tables[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_dyn[];
+    uint32_t *cells = (uint32_t *)lds_dyn;   // the cell of each level, one column per lane
+    unsigned char *lds_tables = lds_dyn + tables_at;
     if (threadIdx.x == 0) ctl[0] = 0;
     if (STAGED) stage_copy(gd->stage[PREC], (const unsigned char *)gd->dev.coef, lds_tables);
     else __syncthreads();
@@ -1173,7 +1182,7 @@ __global__ void __launch_bounds__(kBlockP) k_track_persistent(const GeomDesc *__
     uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     const GlobalQueue q = {(unsigned long long *)&o.counters[7], p.n};
-    const TailCfg tc = {(uint64_t *)(lds_tables + tail_at), ctl, tail_cap, tail_round};
+    const TailCfg tc = {(uint64_t *)(lds_dyn + tail_at), ctl, tail_cap, tail_round};
     track_pool<PREC>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc);
     add_counts(cnt, o.counters);
 }
@@ -1187,17 +1196,20 @@ __global__ void k_put_launch(LaunchRec r, LaunchRec *dst) {
 // (item, range of particle indices) from a device queue, copies the item's
 // tables into LDS when the item changes (STAGED), and runs the lanes' state
 // machine over the chunk with a workgroup-local id counter.
-template <int PREC, bool STAGED>
-__global__ void __launch_bounds__(kBlockP) k_track_batch(const BatchItem *__restrict__ items,
+template <int PREC, bool STAGED, int W>
+__global__ void __launch_bounds__(W == 5 ? 640 : kBlockP) __attribute__((amdgpu_waves_per_eu(W)))
+k_track_batch(const BatchItem *__restrict__ items,
                                                          const BatchChunk *__restrict__ chunks,
                                                          uint32_t n_chunks, unsigned long long *queue,
-                                                         uint32_t tail_at, uint32_t tail_cap, uint32_t tail_round) {
-    __shared__ uint32_t cells[GT_MAX_LEVELS * kBlockP];
+                                                         uint32_t tables_at, uint32_t tail_at, uint32_t tail_cap,
+                                                         uint32_t tail_round) {
     __shared__ uint32_t ctl[1 + kBlockP / 64];
-    extern __shared__ __attribute__((aligned(16))) unsigned char lds_tables[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_dyn[];
     __shared__ uint32_t s_chunk;
     __shared__ unsigned long long s_pool;
-    const TailCfg tc = {(uint64_t *)(lds_tables + tail_at), ctl, tail_cap, tail_round};
+    uint32_t *cells = (uint32_t *)lds_dyn;   // the cell of each level, one column per lane
+    unsigned char *lds_tables = lds_dyn + tables_at;
+    const TailCfg tc = {(uint64_t *)(lds_dyn + tail_at), ctl, tail_cap, tail_round};
     // the descriptors are read-only for the whole launch: their fields are
     // read where needed (scalar loads the compiler may repeat) rather than
     // carried from chunk to chunk in registers
@@ -1427,7 +1439,7 @@ int allow_dynamic_lds(const void *kernel, unsigned bytes) {
 // buffer, as large as the workgroup's share of the compute unit's LDS allows
 // without lowering the number of resident workgroups.
 struct LdsPlan {
-    unsigned dyn, tail_at, tail_cap;
+    unsigned dyn, tables_at, tail_at, tail_cap;
     int blocks;
 };
 
@@ -1438,10 +1450,13 @@ int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail
     int rc = hip_check(hipFuncGetAttributes(&fa, kern), "hipFuncGetAttributes");
     if (rc) return rc;
     const unsigned stat = (unsigned)fa.sharedSizeBytes;
-    if (stat + tables > kLdsPerCU) return set_error("staged tables exceed the LDS"), GT_ECAPACITY;
+    if (stat + GT_MAX_LEVELS * 4u * block + tables + 32u > kLdsPerCU)
+        return set_error("staged tables exceed the LDS"), GT_ECAPACITY;
     rc = allow_dynamic_lds(kern, kLdsPerCU - stat);
     if (rc) return rc;
-    const unsigned base = (tables + 15u) & ~15u;
+    // dynamic LDS: level columns, staged tables, tail buffer
+    const unsigned tables_at = (GT_MAX_LEVELS * 4u * block + 15u) & ~15u;
+    const unsigned base = tables_at + ((tables + 15u) & ~15u);
     int blocks = 0;
     rc = persistent_grid(kern, block, base, device, &blocks);
     if (rc) return rc;
@@ -1466,6 +1481,7 @@ int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail
         }
     }
     lp.dyn = dyn;
+    lp.tables_at = tables_at;
     lp.tail_at = base;
     lp.tail_cap = cap;
     lp.blocks = blocks;
@@ -1501,9 +1517,12 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
         } else {
             const unsigned block = p->block_size ? p->block_size : kBlockP;
             const StagePlan &sp = g->stage[PREC];
-            const bool staged = !(p->flags & GT_FLAG_NO_STAGING) && sp.total <= kStageBudget;
-            const void *kern = staged ? (const void *)k_track_persistent<PREC, true>
-                                      : (const void *)k_track_persistent<PREC, false>;
+            const bool staged = !(p->flags & GT_FLAG_NO_STAGING) && sp.n > 0;
+            const bool w5 = block == 640;
+            const void *kern = staged ? (w5 ? (const void *)k_track_persistent<PREC, true, 5>
+                                            : (const void *)k_track_persistent<PREC, true, 4>)
+                                      : (w5 ? (const void *)k_track_persistent<PREC, false, 5>
+                                            : (const void *)k_track_persistent<PREC, false, 4>);
             LdsPlan lp;
             int rc = plan_persistent(kern, block, staged ? sp.total : 0, !(p->flags & GT_FLAG_NO_TAIL_COMPACTION),
                                      g->device, lp);
@@ -1515,12 +1534,19 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
             rec.p = kp;
             rec.o = ko;
             hipLaunchKernelGGL(k_put_launch, dim3(1), dim3(64), 0, st, rec, g->launch);
-            if (staged)
-                hipLaunchKernelGGL((k_track_persistent<PREC, true>), dim3(blocks), dim3(block), lp.dyn, st, g->desc,
-                                   (const LaunchRec *)g->launch, lp.tail_at, lp.tail_cap, kTailRound);
+            const LaunchRec *lr = g->launch;
+            if (staged && w5)
+                hipLaunchKernelGGL((k_track_persistent<PREC, true, 5>), dim3(blocks), dim3(block), lp.dyn, st, g->desc,
+                                   lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
+            else if (staged)
+                hipLaunchKernelGGL((k_track_persistent<PREC, true, 4>), dim3(blocks), dim3(block), lp.dyn, st, g->desc,
+                                   lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
+            else if (w5)
+                hipLaunchKernelGGL((k_track_persistent<PREC, false, 5>), dim3(blocks), dim3(block), lp.dyn, st,
+                                   g->desc, lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
             else
-                hipLaunchKernelGGL((k_track_persistent<PREC, false>), dim3(blocks), dim3(block), lp.dyn, st, g->desc,
-                                   (const LaunchRec *)g->launch, lp.tail_at, lp.tail_cap, kTailRound);
+                hipLaunchKernelGGL((k_track_persistent<PREC, false, 4>), dim3(blocks), dim3(block), lp.dyn, st,
+                                   g->desc, lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
         }
     }
     mark(t_ev_stop, st);
@@ -1537,19 +1563,30 @@ int launch_batch_t(gt_batch *b, hipStream_t st) {
     for (int pass = 0; pass < 2; pass++) {
         const uint32_t n = pass == 0 ? b->n_staged : b->n_global;
         if (!n) continue;
-        const void *kern = pass == 0 ? (const void *)k_track_batch<PREC, true> : (const void *)k_track_batch<PREC, false>;
+        const bool w5 = b->block == 640;
+        const void *kern = pass == 0 ? (w5 ? (const void *)k_track_batch<PREC, true, 5>
+                                           : (const void *)k_track_batch<PREC, true, 4>)
+                                     : (w5 ? (const void *)k_track_batch<PREC, false, 5>
+                                           : (const void *)k_track_batch<PREC, false, 4>);
         LdsPlan lp;
         int rc = plan_persistent(kern, b->block, pass == 0 ? b->lds_bytes : 0, b->tail, b->device, lp);
         if (rc) return rc;
         int blocks = lp.blocks;
         if ((uint32_t)blocks > n) blocks = (int)n;
         const BatchChunk *ch = b->d_chunks + (pass == 0 ? 0 : b->n_staged);
-        if (pass == 0)
-            hipLaunchKernelGGL((k_track_batch<PREC, true>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items, ch, n,
-                               b->d_queue, lp.tail_at, lp.tail_cap, kTailRound);
+        unsigned long long *q = b->d_queue + pass;
+        if (pass == 0 && w5)
+            hipLaunchKernelGGL((k_track_batch<PREC, true, 5>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items, ch,
+                               n, q, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
+        else if (pass == 0)
+            hipLaunchKernelGGL((k_track_batch<PREC, true, 4>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items, ch,
+                               n, q, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
+        else if (w5)
+            hipLaunchKernelGGL((k_track_batch<PREC, false, 5>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items,
+                               ch, n, q, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
         else
-            hipLaunchKernelGGL((k_track_batch<PREC, false>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items, ch,
-                               n, b->d_queue + 1, lp.tail_at, lp.tail_cap, kTailRound);
+            hipLaunchKernelGGL((k_track_batch<PREC, false, 4>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items,
+                               ch, n, q, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
     }
     mark(t_ev_stop, st);
     const uint64_t bx = std::min<uint64_t>((b->max_inst + 255) / 256, 1024);

@@ -148,8 +148,9 @@ def test_track_parity(case, prec, lane):
 @pytest.mark.parametrize("prec", [gt.PREC_FP64, gt.PREC_MIXED])
 def test_global_tables_match_staged(cfg, prec):
     """The persistent tracker reading the geometry from global memory gives
-    the oracle's results too (cfg3 is always read from global memory: its
-    tables exceed the LDS budget)."""
+    the oracle's results too (the default copies to LDS the tables that fit,
+    in order of use: all of them for cfg1, cfg2 and the sphere, part of them
+    for the three-level and hexagonal cores)."""
     fg, G, O = geoms(cfg)
     kw = dict(seed=4242, n_particles=6000, geometry_id=5)
     g = gpu_track(G, precision=prec, staging=False, record_first_k=100, record_cap=64, **kw)
@@ -184,7 +185,7 @@ def test_edge_cases():
 
 
 @pytest.mark.parametrize("block,lane,refill", [(64, True, 0), (128, True, 0), (192, True, 0), (64, False, 1),
-                                               (256, False, 64), (512, False, 3), (1024, False, 0)])
+                                               (256, False, 64), (512, False, 3), (640, False, 8), (1024, False, 0)])
 def test_launch_shapes_do_not_change_results(block, lane, refill):
     fg, G, O = geoms(2)
     kw = dict(seed=2002, n_particles=5000, geometry_id=2)
@@ -194,7 +195,7 @@ def test_launch_shapes_do_not_change_results(block, lane, refill):
 
 
 @pytest.mark.parametrize("cfg", [1, 2, 4])
-@pytest.mark.parametrize("block", [128, 1024])
+@pytest.mark.parametrize("block", [128, 640, 1024])
 def test_without_tail_compaction(cfg, block):
     """Histories stay in their lanes after the queue drains: same results."""
     fg, G, O = geoms(cfg)
