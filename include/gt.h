@@ -144,6 +144,13 @@ int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out);
 int gt_geometry_info(const gt_geometry *g, uint64_t *n_instances, uint32_t *max_depth,
                      uint64_t *device_bytes);
 
+/* How the persistent trackers hold this geometry's tables for a precision
+ * mode: *kind 0 = all in global memory, 1 = the per-segment tables (cells,
+ * half-spaces, surfaces, universes, materials) copied to LDS, 2 = those and
+ * the crossing tables (translations, candidate lists), 3 = every table; and
+ * the LDS bytes copied per workgroup.  Either output may be NULL. */
+int gt_geometry_staging(const gt_geometry *g, uint32_t precision, uint32_t *kind, uint32_t *lds_bytes);
+
 void gt_geometry_destroy(gt_geometry *g);
 
 /* Parameters of one batch of histories (host struct). */

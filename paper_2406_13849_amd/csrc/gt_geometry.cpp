@@ -571,7 +571,7 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         sz[SEC_LOCAL] = cell_local.size() * 4;
         size_t total = 0;
         for (int i = 0; i < SEC_COUNT; i++) { off[i] = total; total = align_up(total + std::max(sz[i], (size_t)16)); }
-        std::vector<unsigned char> img(total + 2 * sizeof(GeomDesc) + 2 * sizeof(LaunchRec) + 1024, 0);
+        std::vector<unsigned char> img(total, 0);
         const void *src[SEC_COUNT] = {coef.data(), hs.data(), cell.data(), trans.data(), B.univ.data(),
                                       B.n32.data(), B.n64.data(), B.leaf.data(), cb.data(), F.sigma_t,
                                       adj_off.data(), adj.data(), cell_local.data()};
@@ -618,33 +618,50 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         g->dev.max_depth = B.depth[F.root];
         g->dev.n_cells = F.n_cells;
         for (int k = 0; k < 3; k++) { g->dev.lo[k] = F.domain_lo[k]; g->dev.hi[k] = F.domain_hi[k]; }
-        // LDS staging plans: the tables each precision mode reads, in order of
-        // use per segment (cells, half-spaces, surfaces, ... first; the
-        // hierarchy, used only when the quick candidates miss, last), as many
-        // as fit in the LDS budget; the others stay in global memory
-        static const int kStageOrder[SEC_COUNT] = {SEC_CELL,  SEC_HS,  SEC_COEF,   SEC_UNIV,   SEC_TRANS,
-                                                   SEC_SIGMA, SEC_ADJOFF, SEC_ADJ, SEC_LOCAL, SEC_NODE32,
-                                                   SEC_NODE64, SEC_LEAF, SEC_CBOX};
+        // LDS staging plans per precision mode: the per-segment tables (cells,
+        // half-spaces, surfaces, universes, materials, local indices) if they
+        // fit, then the crossing tables (translations, candidate lists) if
+        // those fit too, then as many hierarchy tables as fit; whatever is not
+        // copied is read from global memory
+        static const int kTierA[] = {SEC_CELL, SEC_HS, SEC_COEF, SEC_UNIV, SEC_SIGMA, SEC_LOCAL};
+        static const int kTierB[] = {SEC_TRANS, SEC_ADJOFF, SEC_ADJ};
         const uint64_t budget = stage_budget();
         for (int prec = 0; prec < 2; prec++) {
             StagePlan &P = g->stage[prec];
             std::memset(&P, 0, sizeof P);
             for (int i = 0; i < SEC_COUNT; i++) P.at[i] = 0xFFFFFFFFu;
             uint64_t at = 0;
-            for (int oi = 0; oi < SEC_COUNT; oi++) {
-                const int i = kStageOrder[oi];
-                const bool need = prec == GT_PREC_MIXED ? (i != SEC_NODE64) : (i != SEC_NODE32 && i != SEC_CBOX);
-                if (!need) continue;
-                const uint64_t b = (std::max<size_t>(sz[i], 16) + 15) & ~(uint64_t)15;
-                if (at + b > budget) continue;
+            auto bytes = [&](int i) { return (std::max<size_t>(sz[i], 16) + 15) & ~(uint64_t)15; };
+            auto add = [&](int i) {
                 P.src[P.n] = (uint32_t)off[i];
                 P.dst[P.n] = (uint32_t)at;
-                P.bytes[P.n] = (uint32_t)b;
+                P.bytes[P.n] = (uint32_t)bytes(i);
                 P.at[i] = (uint32_t)at;
                 P.n++;
-                at += b;
+                at += bytes(i);
+            };
+            uint64_t need_a = 0, need_b = 0;
+            for (int i : kTierA) need_a += bytes(i);
+            for (int i : kTierB) need_b += bytes(i);
+            if (need_a <= budget) {
+                for (int i : kTierA) add(i);
+                P.kind = 1;
+                if (need_a + need_b <= budget) {
+                    for (int i : kTierB) add(i);
+                    P.kind = 2;
+                    const int cold[] = {prec == GT_PREC_MIXED ? SEC_NODE32 : SEC_NODE64, SEC_LEAF,
+                                        prec == GT_PREC_MIXED ? SEC_CBOX : -1};
+                    uint64_t need_c = 0;
+                    for (int i : cold)
+                        if (i >= 0) need_c += bytes(i);
+                    if (need_a + need_b + need_c <= budget) {
+                        for (int i : cold)
+                            if (i >= 0) add(i);
+                        P.kind = 3;
+                    }
+                }
             }
-            P.total = at > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)at;
+            P.total = (uint32_t)at;
         }
         GeomDesc desc;
         desc.dev = g->dev;
@@ -680,6 +697,14 @@ extern "C" int gt_geometry_info(const gt_geometry *g, uint64_t *n_instances, uin
     if (n_instances) *n_instances = g->n_inst;
     if (max_depth) *max_depth = g->max_depth;
     if (device_bytes) *device_bytes = g->blob_bytes;
+    return GT_OK;
+}
+
+extern "C" int gt_geometry_staging(const gt_geometry *g, uint32_t precision, uint32_t *kind, uint32_t *lds_bytes) {
+    if (!g) return set_error("gt_geometry_staging: null geometry"), GT_EINVAL;
+    if (precision > GT_PREC_MIXED) return set_error("gt_geometry_staging: unknown precision %u", precision), GT_EINVAL;
+    if (kind) *kind = g->stage[precision].kind;
+    if (lds_bytes) *lds_bytes = g->stage[precision].total;
     return GT_OK;
 }
 
@@ -741,8 +766,8 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
         std::vector<FillRange> fills;
         std::vector<FinalizeItem> fin(n_items);
         std::vector<std::pair<double, uint32_t>> order;
-        std::vector<uint8_t> staged(n_items);
-        uint32_t lds = 0;
+        std::vector<uint8_t> kind(n_items);
+        uint32_t lds[4] = {0, 0, 0, 0};
         uint64_t max_inst = 1, max_fill = 2;
         for (uint32_t i = 0; i < n_items; i++) {
             const gt_batch_item &it = items[i];
@@ -762,8 +787,8 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
             gt_track_params p = it.params;
             p.refill_min = refill ? refill : p.refill_min;
             fill_kparams(&p, g, b.p, b.o, &it.out);
-            staged[i] = !(it.params.flags & GT_FLAG_NO_STAGING) && b.plan.n > 0;
-            if (staged[i]) lds = std::max(lds, b.plan.total);
+            kind[i] = (it.params.flags & GT_FLAG_NO_STAGING) ? 0 : (uint8_t)b.plan.kind;
+            lds[kind[i]] = std::max(lds[kind[i]], kind[i] ? b.plan.total : 0u);
             fills.push_back({g->tally_ws, (uint64_t)8 * 4 * g->n_inst, 0, 8, 0});
             fills.push_back({it.out.counters, 8, 0, 8, 0});
             if (b.p.rec_k) fills.push_back({it.out.rec, (uint64_t)b.p.rec_k * b.p.rec_cap, (uint64_t)(uint32_t)-1, 4, 0});
@@ -772,29 +797,30 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
             max_inst = std::max(max_inst, g->n_inst);
             order.push_back({(double)it.params.n_particles * (double)g->max_depth, i});
         }
-        // chunks: staged items first, each group largest cost first
+        // chunks grouped by staging kind (3, 2, 1, 0), each group largest cost first
         std::stable_sort(order.begin(), order.end(),
                          [](const std::pair<double, uint32_t> &a, const std::pair<double, uint32_t> &b) {
                              return a.first > b.first;
                          });
         std::vector<BatchChunk> chunks;
-        uint32_t n_staged = 0;
-        for (int pass = 0; pass < 2; pass++) {
+        uint32_t n_kind[4] = {0, 0, 0, 0};
+        for (int k = 3; k >= 0; k--) {
+            const size_t before = chunks.size();
             for (const auto &o : order) {
                 const uint32_t i = o.second;
-                if ((staged[i] != 0) != (pass == 0)) continue;
+                if (kind[i] != k) continue;
                 const uint64_t n = items[i].params.n_particles;
                 for (uint64_t f = 0; f < n; f += chunk) chunks.push_back({i, 0, f, std::min(chunk, n - f)});
             }
-            if (pass == 0) n_staged = (uint32_t)chunks.size();
+            n_kind[k] = (uint32_t)(chunks.size() - before);
         }
         if (chunks.size() > 0xFFFFFFF0u) return set_error("gt_batch_create: too many chunks"), GT_ECAPACITY;
-        // one device allocation: items, chunks, fills, finalize items, two queue counters
+        // one device allocation: items, chunks, fills, finalize items, four queue counters
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
         const size_t o_items = 0;
         const size_t o_chunks = al(o_items + bi.size() * sizeof(BatchItem));
         const size_t o_queue = al(o_chunks + std::max<size_t>(chunks.size(), 1) * sizeof(BatchChunk));
-        const size_t o_fill = al(o_queue + 2 * sizeof(unsigned long long));
+        const size_t o_fill = al(o_queue + 4 * sizeof(unsigned long long));
         const size_t o_fin = al(o_fill + (fills.size() + 1) * sizeof(FillRange));
         const size_t total = al(o_fin + fin.size() * sizeof(FinalizeItem));
         int cur = 0;
@@ -804,9 +830,9 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
         hipError_t e = hipMalloc(&dm, total);
         if (e != hipSuccess) return set_error("hipMalloc(%zu): %s", total, hipGetErrorString(e)), GT_ENOMEM;
         unsigned char *base = (unsigned char *)dm;
-        fills.push_back({base + o_queue, 2, 0, 8, 0});
+        fills.push_back({base + o_queue, 4, 0, 8, 0});
         for (const FillRange &f : fills) max_fill = std::max(max_fill, f.count);
-        std::vector<unsigned char> img(total + 2 * sizeof(GeomDesc) + 2 * sizeof(LaunchRec) + 1024, 0);
+        std::vector<unsigned char> img(total, 0);
         std::memcpy(img.data() + o_items, bi.data(), bi.size() * sizeof(BatchItem));
         if (!chunks.empty()) std::memcpy(img.data() + o_chunks, chunks.data(), chunks.size() * sizeof(BatchChunk));
         std::memcpy(img.data() + o_fill, fills.data(), fills.size() * sizeof(FillRange));
@@ -825,15 +851,14 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
         b->dmem = dm;
         b->d_items = (BatchItem *)(base + o_items);
         b->d_chunks = (BatchChunk *)(base + o_chunks);
-        b->n_staged = n_staged;
-        b->n_global = (uint32_t)chunks.size() - n_staged;
+        for (int k = 0; k < 4; k++) b->n_kind[k] = n_kind[k];
         b->d_fill = (FillRange *)(base + o_fill);
         b->n_fill = (uint32_t)fills.size();
         b->max_fill = max_fill;
         b->d_fin = (FinalizeItem *)(base + o_fin);
         b->max_inst = max_inst;
         b->d_queue = (unsigned long long *)(base + o_queue);
-        b->lds_bytes = lds;
+        for (int k = 0; k < 4; k++) b->lds_bytes[k] = lds[k];
         b->tail = !(items[0].params.flags & GT_FLAG_NO_TAIL_COMPACTION);
         *out = b;
         return GT_OK;

@@ -97,6 +97,10 @@ struct StagePlan {
     uint32_t total;             // LDS bytes
     uint32_t src[SEC_COUNT], dst[SEC_COUNT], bytes[SEC_COUNT];
     uint32_t at[SEC_COUNT];     // LDS byte offset of each section (0xFFFFFFFF when not copied)
+    uint32_t kind;              // 0: nothing copied; 1: the per-segment tables (cells, half-spaces,
+                                // surfaces, universes, materials, local indices); 2: those and
+                                // the crossing tables (translations, candidate lists); 3: every
+                                // table the precision mode reads
 };
 
 struct KParams {
@@ -176,15 +180,15 @@ struct gt_batch {
     uint32_t precision, n_items, block, refill_min;
     void *dmem;                         // one allocation for everything below
     gt::BatchItem *d_items;
-    gt::BatchChunk *d_chunks;           // staged items' chunks, then the others'
-    uint32_t n_staged, n_global;
+    gt::BatchChunk *d_chunks;           // chunks by staging kind: kind 3, then 2, 1, 0
+    uint32_t n_kind[4];
     gt::FillRange *d_fill;
     uint32_t n_fill;
     uint64_t max_fill;
     gt::FinalizeItem *d_fin;
     uint64_t max_inst;
-    unsigned long long *d_queue;        // two counters (staged and global launch)
-    uint32_t lds_bytes;                 // staged tables' LDS bytes (largest item)
+    unsigned long long *d_queue;        // one counter per staging kind
+    uint32_t lds_bytes[4];              // staged tables' LDS bytes per kind (largest item)
     bool tail;                          // tail compaction on
 };
 

@@ -41,6 +41,84 @@ constexpr unsigned kStageBudget = 160 * 1024 - GT_MAX_LEVELS * kBlockP * 4 - 102
 
 __device__ __forceinline__ double dinf() { return __builtin_huge_val(); }
 
+// ------------------------------------------------------------------ table views
+// The kernels read the geometry tables through pointers whose address space
+// is part of their type, so the compiler emits LDS reads (32-bit addresses)
+// for tables staged in LDS and global loads for the others, instead of flat
+// loads that must serve both.  A view DevT<A, B, C> holds the per-segment
+// tables (cells, half-spaces, surfaces, universes, materials, local indices)
+// in address space A, the crossing tables (translations, candidate lists) in
+// B and the hierarchy (nodes, leaves, cell boxes) in C; 3 = LDS, 1 = global.
+template <int AS, typename T> using cptr = const __attribute__((address_space(AS))) T *;
+
+template <int A, int B, int C>
+struct DevT {
+    cptr<A, double> coef;
+    cptr<A, uint32_t> hs;
+    cptr<A, Cell> cell;
+    cptr<A, Univ> univ;
+    cptr<A, double> sigma;
+    cptr<A, uint32_t> cell_local;
+    cptr<B, double> trans;
+    cptr<B, uint32_t> adj_off;
+    cptr<B, uint32_t> adj;
+    cptr<C, Node32> node32;
+    cptr<C, Node64> node64;
+    cptr<C, uint32_t> leaf;
+    cptr<C, float> cbox;
+    uint32_t root, n_inst, max_depth, n_cells;
+    double lo[3], hi[3];
+};
+
+typedef DevT<1, 1, 1> DevGlobal;   // every table in global memory
+typedef DevT<3, 1, 1> DevSplit;    // per-segment tables in LDS
+typedef DevT<3, 3, 1> DevLds;      // per-segment and crossing tables in LDS
+typedef DevT<3, 3, 3> DevAll;      // every table in LDS
+
+// Store to global memory (the output arrays) through a typed pointer.
+template <typename T, typename V>
+__device__ __forceinline__ void gstore(T *base, uint64_t i, V v) {
+    ((__attribute__((address_space(1))) T *)base)[i] = (T)v;
+}
+
+// A whole record through a typed pointer (the copy goes through a generic
+// pointer cast from the typed one, which keeps the address space).
+template <typename T, typename P>
+__device__ __forceinline__ T ldv(P p) {
+    return *(const T *)p;
+}
+
+template <int A, int B, int C>
+__device__ __forceinline__ void view_scalars(DevT<A, B, C> &d, const Dev &g) {
+    d.root = g.root;
+    d.n_inst = g.n_inst;
+    d.max_depth = g.max_depth;
+    d.n_cells = g.n_cells;
+    for (int k = 0; k < 3; k++) {
+        d.lo[k] = g.lo[k];
+        d.hi[k] = g.hi[k];
+    }
+}
+
+__device__ __forceinline__ DevGlobal global_view(const Dev &g) {
+    DevGlobal d;
+    d.coef = (cptr<1, double>)g.coef;
+    d.hs = (cptr<1, uint32_t>)g.hs;
+    d.cell = (cptr<1, Cell>)g.cell;
+    d.univ = (cptr<1, Univ>)g.univ;
+    d.sigma = (cptr<1, double>)g.sigma;
+    d.cell_local = (cptr<1, uint32_t>)g.cell_local;
+    d.trans = (cptr<1, double>)g.trans;
+    d.adj_off = (cptr<1, uint32_t>)g.adj_off;
+    d.adj = (cptr<1, uint32_t>)g.adj;
+    d.node32 = (cptr<1, Node32>)g.node32;
+    d.node64 = (cptr<1, Node64>)g.node64;
+    d.leaf = (cptr<1, uint32_t>)g.leaf;
+    d.cbox = (cptr<1, float>)g.cbox;
+    view_scalars(d, g);
+    return d;
+}
+
 // ------------------------------------------------------------------ RNG
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies with the published multipliers, the key bumped by the
@@ -126,7 +204,8 @@ __device__ __forceinline__ bool direction_from(double u0, double u1, double &u, 
 // ------------------------------------------------------------------ surfaces
 // Half-spaces of a cell are stored planes first (types PX, PY, PZ, P), then
 // quadrics (CZ, SPH), so each loop below runs one surface family.
-__device__ __forceinline__ double plane_value(uint32_t type, const double *c, double x, double y, double z) {
+template <typename CP>
+__device__ __forceinline__ double plane_value(uint32_t type, CP c, double x, double y, double z) {
     switch (type) {
     case ST_PX: return x - c[0];
     case ST_PY: return y - c[0];
@@ -135,7 +214,8 @@ __device__ __forceinline__ double plane_value(uint32_t type, const double *c, do
     }
 }
 
-__device__ __forceinline__ double quad_value(uint32_t type, const double *c, double x, double y, double z) {
+template <typename CP>
+__device__ __forceinline__ double quad_value(uint32_t type, CP c, double x, double y, double z) {
     const double dx = x - c[0], dy = y - c[1];
     if (type == ST_CZ) return (dx * dx + dy * dy) - c[2];
     const double dz = z - c[2];
@@ -144,10 +224,11 @@ __device__ __forceinline__ double quad_value(uint32_t type, const double *c, dou
 
 // Cell containment: the point is on the required side of every half-space;
 // on surface force_s the logical sense force_pos is used instead.
-__device__ __forceinline__ bool contains(const Dev &g, uint32_t c, double x, double y, double z, uint32_t force_s,
+template <typename G>
+__device__ __forceinline__ bool contains(const G &g, uint32_t c, double x, double y, double z, uint32_t force_s,
                                          bool force_pos) {
-    const Cell cc = g.cell[c];
-    const uint32_t *hs = g.hs + cc.hs_off;
+    const Cell cc = ldv<Cell>(g.cell + c);
+    const auto hs = g.hs + cc.hs_off;
     const uint32_t npl = cc.n_pl & kPlaneCountMask;
     for (uint32_t k = 0; k < npl; k++) {
         const uint32_t h = hs[k];
@@ -166,7 +247,8 @@ __device__ __forceinline__ bool contains(const Dev &g, uint32_t c, double x, dou
 
 // Distance along (u,v,w) from q to the point where a plane's sense leaves
 // the cell's required side `pos`; +inf if it does not (Table 1).
-__device__ __forceinline__ double plane_den(uint32_t type, const double *c, double u, double v, double w) {
+template <typename CP>
+__device__ __forceinline__ double plane_den(uint32_t type, CP c, double u, double v, double w) {
     switch (type) {
     case ST_PX: return u;
     case ST_PY: return v;
@@ -175,7 +257,8 @@ __device__ __forceinline__ double plane_den(uint32_t type, const double *c, doub
     }
 }
 
-__device__ __forceinline__ double plane_distance(uint32_t type, const double *c, bool pos, double qx, double qy,
+template <typename CP>
+__device__ __forceinline__ double plane_distance(uint32_t type, CP c, bool pos, double qx, double qy,
                                                  double qz, double u, double v, double w) {
     const double den = plane_den(type, c, u, v, w);
     if (den == 0.0) return dinf();
@@ -186,7 +269,8 @@ __device__ __forceinline__ double plane_distance(uint32_t type, const double *c,
 
 // The same for a cylinder or sphere: textbook cancellation-free roots;
 // `on` marks the surface just crossed (only the far root can be hit).
-__device__ __forceinline__ double quad_distance(uint32_t type, const double *c, bool pos, double qx, double qy,
+template <typename CP>
+__device__ __forceinline__ double quad_distance(uint32_t type, CP c, bool pos, double qx, double qy,
                                                 double qz, double u, double v, double w, bool on) {
     double a, b;
     const double dx = qx - c[0], dy = qy - c[1];
@@ -225,10 +309,10 @@ __device__ __forceinline__ double quad_distance(uint32_t type, const double *c, 
 // walks the single-precision hierarchy; double precision walks the
 // double-precision hierarchy.  Whichever cell is returned passed the double
 // containment test, which at most one cell of a universe passes.
-template <int PREC>
-__device__ int32_t search(const Dev &g, uint32_t u, double x, double y, double z, uint32_t force_s, bool force_pos,
+template <int PREC, typename G>
+__device__ int32_t search(const G &g, uint32_t u, double x, double y, double z, uint32_t force_s, bool force_pos,
                           int32_t exclude, float gx, float gy) {
-    const Univ U = g.univ[u];
+    const Univ U = ldv<Univ>(g.univ + u);
     if (PREC == GT_PREC_MIXED && U.hint == (int32_t)kHintSquare) {
         int i = (int)floorf((gx - U.x0) * U.inv_px);
         int j = (int)floorf((gy - U.y0) * U.inv_py);
@@ -244,13 +328,13 @@ __device__ int32_t search(const Dev &g, uint32_t u, double x, double y, double z
         bool in;
         uint32_t esc, lf;
         if (PREC == GT_PREC_MIXED) {
-            const Node32 nd = g.node32[n];
+            const Node32 nd = ldv<Node32>(g.node32 + n);
             in = fx >= nd.lo[0] && fx <= nd.hi[0] && fy >= nd.lo[1] && fy <= nd.hi[1] && fz >= nd.lo[2] &&
                  fz <= nd.hi[2];
             esc = nd.escape;
             lf = nd.leaf;
         } else {
-            const Node64 nd = g.node64[n];
+            const Node64 nd = ldv<Node64>(g.node64 + n);
             in = x >= nd.lo[0] && x <= nd.hi[0] && y >= nd.lo[1] && y <= nd.hi[1] && z >= nd.lo[2] && z <= nd.hi[2];
             esc = nd.escape;
             lf = nd.leaf;
@@ -262,7 +346,7 @@ __device__ int32_t search(const Dev &g, uint32_t u, double x, double y, double z
             const uint32_t c = g.leaf[first + k];
             if ((int32_t)c == exclude) continue;
             if (PREC == GT_PREC_MIXED) {
-                const float *b = g.cbox + 8 * (size_t)c;
+                const auto b = g.cbox + 8 * (size_t)c;
                 if (!(fx >= b[0] && fx <= b[4] && fy >= b[1] && fy <= b[5] && fz >= b[2] && fz <= b[6])) continue;
             }
             if (contains(g, c, x, y, z, force_s, force_pos)) return (int32_t)c;
@@ -285,14 +369,14 @@ __device__ __forceinline__ uint32_t &lvl(const Particle &P, int L) { return P.ce
 
 // Descend from level L0 (cell set, (qx,qy,qz) its local position): while
 // the cell is filled, find the daughter's cell at p - t (Alg. 7).
-template <int PREC>
-__device__ __forceinline__ bool descend(const Dev &g, Particle &P, int L0, double qx, double qy, double qz) {
+template <int PREC, typename G>
+__device__ __forceinline__ bool descend(const G &g, Particle &P, int L0, double qx, double qy, double qz) {
     int L = L0;
     for (;;) {
         const uint32_t c = lvl(P, L);
         const int32_t fill = g.cell[c].fill;
         if (fill >= 0) break;
-        const double *t = g.trans + 4 * (size_t)c;
+        const auto t = g.trans + 4 * (size_t)c;
         qx = qx - t[0];
         qy = qy - t[1];
         qz = qz - t[2];
@@ -305,7 +389,8 @@ __device__ __forceinline__ bool descend(const Dev &g, Particle &P, int L0, doubl
     return true;
 }
 
-__device__ __forceinline__ uint32_t leaf_instance(const Dev &g, const Particle &P) {
+template <typename G>
+__device__ __forceinline__ uint32_t leaf_instance(const G &g, const Particle &P) {
     uint32_t i = 0;
     for (int L = 0; L < P.depth; L++) i += g.cell[lvl(P, L)].inst_off;
     return i;
@@ -313,7 +398,8 @@ __device__ __forceinline__ uint32_t leaf_instance(const Dev &g, const Particle &
 
 // distance_to_surface over every level; ties resolve to the smallest
 // (distance, level, surface id), i.e. the top-most level on the surface.
-__device__ __forceinline__ double distance_all(const Dev &g, const Particle &P, int &bl, uint32_t &bs, bool &bpos,
+template <typename G>
+__device__ __forceinline__ double distance_all(const G &g, const Particle &P, int &bl, uint32_t &bs, bool &bpos,
                                                uint32_t &bk) {
     double bt = dinf();
     bl = GT_MAX_LEVELS;
@@ -324,13 +410,13 @@ __device__ __forceinline__ double distance_all(const Dev &g, const Particle &P, 
     for (int L = 0; L < P.depth; L++) {
         const uint32_t c = lvl(P, L);
         if (L > 0) {
-            const double *t = g.trans + 4 * (size_t)lvl(P, L - 1);
+            const auto t = g.trans + 4 * (size_t)lvl(P, L - 1);
             qx = qx - t[0];
             qy = qy - t[1];
             qz = qz - t[2];
         }
-        const Cell cc = g.cell[c];
-        const uint32_t *hs = g.hs + cc.hs_off;
+        const Cell cc = ldv<Cell>(g.cell + c);
+        const auto hs = g.hs + cc.hs_off;
         const uint32_t npl = cc.n_pl & kPlaneCountMask;
         for (uint32_t k = 0; k < npl; k++) {
             const uint32_t h = hs[k];
@@ -375,7 +461,8 @@ struct Nearest {
     bool pos;
 };
 
-__device__ __forceinline__ void nearest_surface(const Dev &g, const Particle &P, Nearest &r) {
+template <typename G>
+__device__ __forceinline__ void nearest_surface(const G &g, const Particle &P, Nearest &r) {
     r.t = dinf();
     r.level = GT_MAX_LEVELS;
     r.surf = kNone;
@@ -389,16 +476,16 @@ __device__ __forceinline__ void nearest_surface(const Dev &g, const Particle &P,
     for (int L = 0; L < P.depth; L++) {
         const uint32_t c = lvl(P, L);
         if (L > 0) {
-            const double *t = g.trans + 4 * (size_t)lvl(P, L - 1);
+            const auto t = g.trans + 4 * (size_t)lvl(P, L - 1);
             qx = qx - t[0];
             qy = qy - t[1];
             qz = qz - t[2];
             univ = (uint32_t)(-fill - 1);
         }
-        const Cell cc = g.cell[c];
+        const Cell cc = ldv<Cell>(g.cell + c);
         fill = cc.fill;
         r.inst += cc.inst_off;
-        const uint32_t *hs = g.hs + cc.hs_off;
+        const auto hs = g.hs + cc.hs_off;
         const uint32_t npl = cc.n_pl & kPlaneCountMask, npair2 = 2u * (cc.n_pl >> 12);
         bool better = false;
         for (uint32_t k = 0; k < npair2; k += 2) {
@@ -461,13 +548,13 @@ __device__ __forceinline__ void nearest_surface(const Dev &g, const Particle &P,
 // cross_surface at level L* on surface s* (Alg. 8) for the one-history-
 // per-lane schedule: the cell of that level's universe on the other side
 // (the old cell's sense on s* flipped), then descent below it.
-template <int PREC>
-__device__ __forceinline__ int cross(const Dev &g, Particle &P, int Ls, uint32_t ss, bool old_pos) {
+template <int PREC, typename G>
+__device__ __forceinline__ int cross(const G &g, Particle &P, int Ls, uint32_t ss, bool old_pos) {
     double qx = P.x, qy = P.y, qz = P.z;
     uint32_t univ = g.root;
     for (int L = 0; L < Ls; L++) {
         const uint32_t c = lvl(P, L);
-        const double *t = g.trans + 4 * (size_t)c;
+        const auto t = g.trans + 4 * (size_t)c;
         qx = qx - t[0];
         qy = qy - t[1];
         qz = qz - t[2];
@@ -477,7 +564,7 @@ __device__ __forceinline__ int cross(const Dev &g, Particle &P, int Ls, uint32_t
     // guess point nudged along the flight so that a lattice guess lands on the far side
     float gx = (float)qx, gy = (float)qy;
     if (PREC == GT_PREC_MIXED) {
-        const Univ U = g.univ[univ];
+        const Univ U = ldv<Univ>(g.univ + univ);
         if (U.hint == (int32_t)kHintSquare) {
             gx += (float)P.u * 1e-3f / U.inv_px;
             gy += (float)P.v * 1e-3f / U.inv_py;
@@ -512,7 +599,8 @@ struct TallyAcc {
 };
 
 __device__ __forceinline__ void add_limb(uint64_t *p, uint64_t v) {
-    if (v) __hip_atomic_fetch_add((unsigned long long *)p, (unsigned long long)v, __ATOMIC_RELAXED,
+    if (v) __hip_atomic_fetch_add((__attribute__((address_space(1))) unsigned long long *)p, (unsigned long long)v,
+                                  __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
@@ -575,8 +663,8 @@ __device__ __forceinline__ void add_counts(const Counts &c, uint64_t *counters) 
 
 // ------------------------------------------------------------------ plain schedule
 // One history per lane: Alg. 2 with the toy transport, straight-line.
-template <int PREC>
-__device__ void run_history(const Dev &g, const KParams &p, const KOut &o, uint64_t *rep, uint64_t local,
+template <int PREC, typename G>
+__device__ void run_history(const G &g, const KParams &p, const KOut &o, uint64_t *rep, uint64_t local,
                             uint32_t *cells, Counts &cnt) {
     Particle P;
     P.cell = cells;
@@ -686,15 +774,16 @@ __device__ void run_history(const Dev &g, const KParams &p, const KOut &o, uint6
     }
     tally_flush(rep, acc);
     h ^= (uint64_t)end;
-    if (o.seg_count) o.seg_count[local] = segs;
-    if (o.seq_hash) o.seq_hash[local] = h;
-    if (o.end_code) o.end_code[local] = (uint8_t)end;
+    if (o.seg_count) gstore(o.seg_count, local, segs);
+    if (o.seq_hash) gstore(o.seq_hash, local, h);
+    if (o.end_code) gstore(o.end_code, local, end);
     count_end(cnt, end, segs, recovf);
 }
 
 template <int PREC>
-__global__ void __launch_bounds__(kBlock) k_track(Dev g, KParams p, KOut o) {
+__global__ void __launch_bounds__(kBlock) k_track(Dev g0, KParams p, KOut o) {
     __shared__ uint32_t cells[GT_MAX_LEVELS * kBlock];
+    const DevGlobal g = global_view(g0);
     uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     const uint64_t local = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -735,31 +824,62 @@ __device__ __forceinline__ void stage_copy(const StagePlan &sp, const unsigned c
     __syncthreads();
 }
 
-// A Dev whose staged tables are the LDS copies (the others stay in global
-// memory).
-template <int PREC>
-__device__ __forceinline__ Dev lds_view(const Dev &g, const StagePlan &sp, unsigned char *lds) {
-    Dev d = g;
-    auto at = [&](int sec, const void *dflt) -> const void * {
-        return sp.at[sec] != 0xFFFFFFFFu ? (const void *)(lds + sp.at[sec]) : dflt;
-    };
-    d.coef = (const double *)at(SEC_COEF, g.coef);
-    d.hs = (const uint32_t *)at(SEC_HS, g.hs);
-    d.cell = (const Cell *)at(SEC_CELL, g.cell);
-    d.trans = (const double *)at(SEC_TRANS, g.trans);
-    d.univ = (const Univ *)at(SEC_UNIV, g.univ);
-    d.leaf = (const uint32_t *)at(SEC_LEAF, g.leaf);
-    if (PREC == GT_PREC_MIXED) {
-        d.node32 = (const Node32 *)at(SEC_NODE32, g.node32);
-        d.cbox = (const float *)at(SEC_CBOX, g.cbox);
+// Staging kinds of a plan: nothing in LDS, the per-segment tables only, the
+// per-segment and crossing tables, or every table.
+enum StageKind : uint32_t { SK_NONE = 0, SK_SPLIT = 1, SK_LDS = 2, SK_ALL = 3 };
+
+template <int KIND> struct ViewOf;
+template <> struct ViewOf<SK_NONE> { typedef DevGlobal type; };
+template <> struct ViewOf<SK_SPLIT> { typedef DevSplit type; };
+template <> struct ViewOf<SK_LDS> { typedef DevLds type; };
+template <> struct ViewOf<SK_ALL> { typedef DevAll type; };
+
+// The view of a geometry for a kernel of staging kind KIND: staged tables at
+// their LDS copies (`lds`, a workgroup-shared address), the others global.
+template <int KIND>
+__device__ __forceinline__ typename ViewOf<KIND>::type make_view(const Dev &g, const StagePlan &sp,
+                                                                 unsigned char *lds) {
+    typedef typename ViewOf<KIND>::type V;
+    if constexpr (KIND == SK_NONE) {
+        return global_view(g);
     } else {
-        d.node64 = (const Node64 *)at(SEC_NODE64, g.node64);
+        V d;
+        auto lp = [&](int sec) { return lds + sp.at[sec]; };
+        d.coef = (cptr<3, double>)lp(SEC_COEF);
+        d.hs = (cptr<3, uint32_t>)lp(SEC_HS);
+        d.cell = (cptr<3, Cell>)lp(SEC_CELL);
+        d.univ = (cptr<3, Univ>)lp(SEC_UNIV);
+        d.sigma = (cptr<3, double>)lp(SEC_SIGMA);
+        d.cell_local = (cptr<3, uint32_t>)lp(SEC_LOCAL);
+        if constexpr (KIND == SK_SPLIT) {
+            d.trans = (cptr<1, double>)g.trans;
+            d.adj_off = (cptr<1, uint32_t>)g.adj_off;
+            d.adj = (cptr<1, uint32_t>)g.adj;
+            d.node32 = (cptr<1, Node32>)g.node32;
+            d.node64 = (cptr<1, Node64>)g.node64;
+            d.leaf = (cptr<1, uint32_t>)g.leaf;
+            d.cbox = (cptr<1, float>)g.cbox;
+        } else {
+            d.trans = (cptr<3, double>)lp(SEC_TRANS);
+            d.adj_off = (cptr<3, uint32_t>)lp(SEC_ADJOFF);
+            d.adj = (cptr<3, uint32_t>)lp(SEC_ADJ);
+            if constexpr (KIND == SK_LDS) {
+                d.node32 = (cptr<1, Node32>)g.node32;
+                d.node64 = (cptr<1, Node64>)g.node64;
+                d.leaf = (cptr<1, uint32_t>)g.leaf;
+                d.cbox = (cptr<1, float>)g.cbox;
+            } else {
+                // only the precision mode's own hierarchy is staged; the other
+                // pointer is never read
+                d.node32 = (cptr<3, Node32>)lp(SEC_NODE32);
+                d.node64 = (cptr<3, Node64>)lp(SEC_NODE64);
+                d.leaf = (cptr<3, uint32_t>)lp(SEC_LEAF);
+                d.cbox = (cptr<3, float>)lp(SEC_CBOX);
+            }
+        }
+        view_scalars(d, g);
+        return d;
     }
-    d.sigma = (const double *)at(SEC_SIGMA, g.sigma);
-    d.adj_off = (const uint32_t *)at(SEC_ADJOFF, g.adj_off);
-    d.adj = (const uint32_t *)at(SEC_ADJ, g.adj);
-    d.cell_local = (const uint32_t *)at(SEC_LOCAL, g.cell_local);
-    return d;
 }
 
 // Particle-id sources for the state machine below: a global counter over
@@ -800,8 +920,8 @@ struct TailCfg {
 // The persistent history loop of one lane (see above); returns when its
 // wave has drained the queue and every lane of the wave is idle (with tail
 // compaction: when no lane of the workgroup has a history left).
-template <int PREC, typename Queue>
-__device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const KOut &o, uint64_t *rep,
+template <int PREC, typename G, typename Queue>
+__device__ __forceinline__ void track_pool(const G &g, const KParams &p, const KOut &o, uint64_t *rep,
                                            uint32_t *cells, const Queue &queue, Counts &cnt, const TailCfg &tc) {
     Particle P;
     P.cell = cells;
@@ -1035,13 +1155,13 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
             uint32_t su = g.root;
             for (int L = 0; L < sL; L++) {
                 const uint32_t cl = lvl(P, L);
-                const double *t = g.trans + 4 * (size_t)cl;
+                const auto t = g.trans + 4 * (size_t)cl;
                 qx = qx - t[0];
                 qy = qy - t[1];
                 qz = qz - t[2];
                 su = (uint32_t)(-g.cell[cl].fill - 1);
             }
-            const Univ U = g.univ[su];
+            const Univ U = ldv<Univ>(g.univ + su);
             // guess point for a lattice index; after a crossing it is nudged
             // along the flight so that it lands on the far side
             float gx = (float)qx, gy = (float)qy;
@@ -1120,7 +1240,7 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
                 tally_add(rep, acc, inst, l);
                 h = (h ^ ((uint64_t)inst + 1)) * kFnvPrime;
                 if (local < p.rec_k) {
-                    if (segs < p.rec_cap) o.rec[local * (uint64_t)p.rec_cap + segs] = (int32_t)inst;
+                    if (segs < p.rec_cap) gstore(o.rec, local * (uint64_t)p.rec_cap + segs, inst);
                     else recovf = true;
                 }
                 segs++;
@@ -1149,34 +1269,33 @@ __device__ __forceinline__ void track_pool(const Dev &g, const KParams &p, const
         if (mode != M_IDLE && end != GT_END_NONE) {
             tally_flush(rep, acc);
             h ^= (uint64_t)end;
-            if (o.seg_count) o.seg_count[local] = segs;
-            if (o.seq_hash) o.seq_hash[local] = h;
-            if (o.end_code) o.end_code[local] = (uint8_t)end;
+            if (o.seg_count) gstore(o.seg_count, local, segs);
+            if (o.seq_hash) gstore(o.seq_hash, local, h);
+            if (o.end_code) gstore(o.end_code, local, end);
             count_end(cnt, end, segs, recovf);
             mode = M_IDLE;
         }
     }
 }
 
-// Dynamic LDS of the persistent kernels: the staged tables (STAGED), then
-// the tail buffer at byte offset tail_at.
-// W = waves per SIMD the register budget is cut for: 4 (up to 1024 lanes
-// per workgroup, 128 registers) or 5 (640 lanes, two workgroups per compute
-// unit, 96 registers).
-template <int PREC, bool STAGED, int W>
+// Dynamic LDS of the persistent kernels: the level columns, the staged
+// tables at byte offset tables_at, then the tail buffer at tail_at.
+// KIND = staging kind of the geometry's plan (see make_view); W = waves per
+// SIMD the register budget is cut for: 4 (up to 1024 lanes per workgroup,
+// 128 registers) or 5 (640 lanes, two workgroups per compute unit, 96
+// registers).
+template <int PREC, int KIND, int W>
 __global__ void __launch_bounds__(W == 5 ? 640 : kBlockP) __attribute__((amdgpu_waves_per_eu(W)))
-k_track_persistent(const GeomDesc *__restrict__ gd,
-                                                              const LaunchRec *__restrict__ lr, uint32_t tables_at,
-                                                              uint32_t tail_at, uint32_t tail_cap,
-                                                              uint32_t tail_round) {
+k_track_persistent(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict__ lr, uint32_t tables_at,
+                   uint32_t tail_at, uint32_t tail_cap, uint32_t tail_round) {
     __shared__ uint32_t ctl[1 + kBlockP / 64];
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_dyn[];
     uint32_t *cells = (uint32_t *)lds_dyn;   // the cell of each level, one column per lane
     unsigned char *lds_tables = lds_dyn + tables_at;
     if (threadIdx.x == 0) ctl[0] = 0;
-    if (STAGED) stage_copy(gd->stage[PREC], (const unsigned char *)gd->dev.coef, lds_tables);
+    if (KIND != SK_NONE) stage_copy(gd->stage[PREC], (const unsigned char *)gd->dev.coef, lds_tables);
     else __syncthreads();
-    const Dev g = STAGED ? lds_view<PREC>(gd->dev, gd->stage[PREC], lds_tables) : gd->dev;
+    const auto g = make_view<KIND>(gd->dev, gd->stage[PREC], lds_tables);
     const KParams &p = lr->p;
     const KOut &o = lr->o;
     uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
@@ -1194,9 +1313,9 @@ __global__ void k_put_launch(LaunchRec r, LaunchRec *dst) {
 
 // Many geometries in one persistent launch: each workgroup takes chunks
 // (item, range of particle indices) from a device queue, copies the item's
-// tables into LDS when the item changes (STAGED), and runs the lanes' state
+// tables into LDS when the item changes (KIND), and runs the lanes' state
 // machine over the chunk with a workgroup-local id counter.
-template <int PREC, bool STAGED, int W>
+template <int PREC, int KIND, int W>
 __global__ void __launch_bounds__(W == 5 ? 640 : kBlockP) __attribute__((amdgpu_waves_per_eu(W)))
 k_track_batch(const BatchItem *__restrict__ items,
                                                          const BatchChunk *__restrict__ chunks,
@@ -1226,9 +1345,9 @@ k_track_batch(const BatchItem *__restrict__ items,
         const uint32_t item = chunks[c].item;
         const uint64_t first = chunks[c].first, count = chunks[c].count;
         const BatchItem &it = items[item];
-        if (STAGED && item != cur) stage_copy(it.plan, (const unsigned char *)it.dev.coef, lds_tables);
+        if (KIND != SK_NONE && item != cur) stage_copy(it.plan, (const unsigned char *)it.dev.coef, lds_tables);
         cur = item;
-        const Dev g = STAGED ? lds_view<PREC>(it.dev, it.plan, lds_tables) : it.dev;
+        const auto g = make_view<KIND>(it.dev, it.plan, lds_tables);
         const KParams &p = it.p;
         const KOut &o = it.o;
         uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
@@ -1301,9 +1420,10 @@ __global__ void k_finalize_batch(const FinalizeItem *fi) {
 }
 
 template <int PREC>
-__global__ void __launch_bounds__(kBlock) k_find_cell(Dev g, const double *pos, uint64_t n, int64_t *inst,
+__global__ void __launch_bounds__(kBlock) k_find_cell(Dev g0, const double *pos, uint64_t n, int64_t *inst,
                                                       int32_t *cells) {
     __shared__ uint32_t lc[GT_MAX_LEVELS * kBlock];
+    const DevGlobal g = global_view(g0);
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     Particle P;
@@ -1324,9 +1444,10 @@ __global__ void __launch_bounds__(kBlock) k_find_cell(Dev g, const double *pos, 
             cells[i * GT_MAX_LEVELS + L] = (c >= 0 && L < P.depth) ? (int32_t)lvl(P, L) : -1;
 }
 
-__global__ void __launch_bounds__(kBlock) k_distance(Dev g, const double *pos, const double *dir, uint64_t n,
+__global__ void __launch_bounds__(kBlock) k_distance(Dev g0, const double *pos, const double *dir, uint64_t n,
                                                      double *dist, int32_t *level, int32_t *surf) {
     __shared__ uint32_t lc[GT_MAX_LEVELS * kBlock];
+    const DevGlobal g = global_view(g0);
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     Particle P;
@@ -1497,6 +1618,63 @@ inline void mark(hipEvent_t e, hipStream_t st) {
     if (e) (void)hipEventRecord(e, st);
 }
 
+// One persistent tracker launch for a geometry of staging kind KIND.
+template <int PREC, int KIND, int W>
+int launch_persistent_k(const gt_geometry *g, uint64_t n, unsigned block, bool tail, hipStream_t st) {
+    const void *kern = (const void *)k_track_persistent<PREC, KIND, W>;
+    LdsPlan lp;
+    int rc = plan_persistent(kern, block, KIND == SK_NONE ? 0 : g->stage[PREC].total, tail, g->device, lp);
+    if (rc) return rc;
+    int blocks = lp.blocks;
+    const uint64_t need = (n + block - 1) / block;
+    if ((uint64_t)blocks > need) blocks = (int)need;
+    hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W>), dim3(blocks), dim3(block), lp.dyn, st, g->desc,
+                       (const LaunchRec *)g->launch, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
+    return GT_OK;
+}
+
+template <int PREC, int W>
+int launch_persistent(const gt_geometry *g, int kind, uint64_t n, unsigned block, bool tail, hipStream_t st) {
+    switch (kind) {
+    case SK_ALL: return launch_persistent_k<PREC, SK_ALL, W>(g, n, block, tail, st);
+    case SK_LDS: return launch_persistent_k<PREC, SK_LDS, W>(g, n, block, tail, st);
+    case SK_SPLIT: return launch_persistent_k<PREC, SK_SPLIT, W>(g, n, block, tail, st);
+    default: return launch_persistent_k<PREC, SK_NONE, W>(g, n, block, tail, st);
+    }
+}
+
+// The chunks of one staging kind of a batch, in one launch.
+template <int PREC, int KIND, int W>
+int launch_batch_k(gt_batch *b, const BatchChunk *ch, uint32_t n, unsigned long long *q, hipStream_t st) {
+    const void *kern = (const void *)k_track_batch<PREC, KIND, W>;
+    LdsPlan lp;
+    int rc = plan_persistent(kern, b->block, b->lds_bytes[KIND], b->tail, b->device, lp);
+    if (rc) return rc;
+    int blocks = lp.blocks;
+    if ((uint32_t)blocks > n) blocks = (int)n;
+    hipLaunchKernelGGL((k_track_batch<PREC, KIND, W>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items, ch, n, q,
+                       lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
+    return GT_OK;
+}
+
+template <int PREC, int W>
+int launch_batch_kinds(gt_batch *b, hipStream_t st) {
+    uint32_t first = 0;
+    for (int kind = SK_ALL; kind >= SK_NONE; kind--) {
+        const uint32_t n = b->n_kind[kind];
+        const BatchChunk *ch = b->d_chunks + first;
+        unsigned long long *q = b->d_queue + kind;
+        first += n;
+        if (!n) continue;
+        int rc = kind == SK_ALL     ? launch_batch_k<PREC, SK_ALL, W>(b, ch, n, q, st)
+                 : kind == SK_LDS   ? launch_batch_k<PREC, SK_LDS, W>(b, ch, n, q, st)
+                 : kind == SK_SPLIT ? launch_batch_k<PREC, SK_SPLIT, W>(b, ch, n, q, st)
+                                    : launch_batch_k<PREC, SK_NONE, W>(b, ch, n, q, st);
+        if (rc) return rc;
+    }
+    return GT_OK;
+}
+
 template <int PREC>
 int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, hipStream_t st) {
     KParams kp;
@@ -1517,36 +1695,15 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
         } else {
             const unsigned block = p->block_size ? p->block_size : kBlockP;
             const StagePlan &sp = g->stage[PREC];
-            const bool staged = !(p->flags & GT_FLAG_NO_STAGING) && sp.n > 0;
-            const bool w5 = block == 640;
-            const void *kern = staged ? (w5 ? (const void *)k_track_persistent<PREC, true, 5>
-                                            : (const void *)k_track_persistent<PREC, true, 4>)
-                                      : (w5 ? (const void *)k_track_persistent<PREC, false, 5>
-                                            : (const void *)k_track_persistent<PREC, false, 4>);
-            LdsPlan lp;
-            int rc = plan_persistent(kern, block, staged ? sp.total : 0, !(p->flags & GT_FLAG_NO_TAIL_COMPACTION),
-                                     g->device, lp);
-            if (rc) return rc;
-            int blocks = lp.blocks;
-            const uint64_t need = (kp.n + block - 1) / block;
-            if ((uint64_t)blocks > need) blocks = (int)need;
+            const int kind = (p->flags & GT_FLAG_NO_STAGING) ? SK_NONE : (int)sp.kind;
             LaunchRec rec;
             rec.p = kp;
             rec.o = ko;
             hipLaunchKernelGGL(k_put_launch, dim3(1), dim3(64), 0, st, rec, g->launch);
-            const LaunchRec *lr = g->launch;
-            if (staged && w5)
-                hipLaunchKernelGGL((k_track_persistent<PREC, true, 5>), dim3(blocks), dim3(block), lp.dyn, st, g->desc,
-                                   lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
-            else if (staged)
-                hipLaunchKernelGGL((k_track_persistent<PREC, true, 4>), dim3(blocks), dim3(block), lp.dyn, st, g->desc,
-                                   lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
-            else if (w5)
-                hipLaunchKernelGGL((k_track_persistent<PREC, false, 5>), dim3(blocks), dim3(block), lp.dyn, st,
-                                   g->desc, lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
-            else
-                hipLaunchKernelGGL((k_track_persistent<PREC, false, 4>), dim3(blocks), dim3(block), lp.dyn, st,
-                                   g->desc, lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
+            const bool tail = !(p->flags & GT_FLAG_NO_TAIL_COMPACTION);
+            int rc = block == 640 ? launch_persistent<PREC, 5>(g, kind, kp.n, block, tail, st)
+                                  : launch_persistent<PREC, 4>(g, kind, kp.n, block, tail, st);
+            if (rc) return rc;
         }
     }
     mark(t_ev_stop, st);
@@ -1560,34 +1717,8 @@ int launch_batch_t(gt_batch *b, hipStream_t st) {
     const uint64_t fx = std::min<uint64_t>((b->max_fill + 255) / 256, 2048);
     hipLaunchKernelGGL(k_fill_ranges, dim3((unsigned)std::max<uint64_t>(fx, 1), b->n_fill), dim3(256), 0, st, b->d_fill);
     mark(t_ev_start, st);
-    for (int pass = 0; pass < 2; pass++) {
-        const uint32_t n = pass == 0 ? b->n_staged : b->n_global;
-        if (!n) continue;
-        const bool w5 = b->block == 640;
-        const void *kern = pass == 0 ? (w5 ? (const void *)k_track_batch<PREC, true, 5>
-                                           : (const void *)k_track_batch<PREC, true, 4>)
-                                     : (w5 ? (const void *)k_track_batch<PREC, false, 5>
-                                           : (const void *)k_track_batch<PREC, false, 4>);
-        LdsPlan lp;
-        int rc = plan_persistent(kern, b->block, pass == 0 ? b->lds_bytes : 0, b->tail, b->device, lp);
-        if (rc) return rc;
-        int blocks = lp.blocks;
-        if ((uint32_t)blocks > n) blocks = (int)n;
-        const BatchChunk *ch = b->d_chunks + (pass == 0 ? 0 : b->n_staged);
-        unsigned long long *q = b->d_queue + pass;
-        if (pass == 0 && w5)
-            hipLaunchKernelGGL((k_track_batch<PREC, true, 5>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items, ch,
-                               n, q, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
-        else if (pass == 0)
-            hipLaunchKernelGGL((k_track_batch<PREC, true, 4>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items, ch,
-                               n, q, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
-        else if (w5)
-            hipLaunchKernelGGL((k_track_batch<PREC, false, 5>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items,
-                               ch, n, q, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
-        else
-            hipLaunchKernelGGL((k_track_batch<PREC, false, 4>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items,
-                               ch, n, q, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
-    }
+    int rc = b->block == 640 ? launch_batch_kinds<PREC, 5>(b, st) : launch_batch_kinds<PREC, 4>(b, st);
+    if (rc) return rc;
     mark(t_ev_stop, st);
     const uint64_t bx = std::min<uint64_t>((b->max_inst + 255) / 256, 1024);
     hipLaunchKernelGGL(k_finalize_batch, dim3((unsigned)std::max<uint64_t>(bx, 1), b->n_items), dim3(256), 0, st, b->d_fin);

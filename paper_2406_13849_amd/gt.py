@@ -86,6 +86,8 @@ def lib():
         L.gt_geometry_create.restype = i32
         L.gt_geometry_info.argtypes = [vp, C.POINTER(u64), C.POINTER(u32), C.POINTER(u64)]
         L.gt_geometry_info.restype = i32
+        L.gt_geometry_staging.argtypes = [vp, u32, C.POINTER(u32), C.POINTER(u32)]
+        L.gt_geometry_staging.restype = i32
         L.gt_geometry_destroy.argtypes = [vp]
         L.gt_geometry_destroy.restype = None
         L.gt_track.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), vp]
@@ -173,6 +175,13 @@ class Geometry:
         self.n_instances = int(ni.value)
         self.max_depth = int(md.value)
         self.device_bytes = int(nb.value)
+
+    def staging(self, precision: int = PREC_MIXED):
+        """gt_geometry_staging: (kind, LDS bytes) of the persistent trackers'
+        copy of the tables (kind 0 none, 1 per-segment, 2 + crossing, 3 all)."""
+        k, b = C.c_uint32(), C.c_uint32()
+        _check(lib().gt_geometry_staging(self.h, precision, C.byref(k), C.byref(b)))
+        return int(k.value), int(b.value)
 
     def close(self):
         if getattr(self, "h", None) is not None and _lib is not None:

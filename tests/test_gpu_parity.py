@@ -315,6 +315,35 @@ def test_batch_matches_oracle(prec):
         assert_parity(_outs(it.out), o, where="batch item %d" % j)
 
 
+def test_every_staging_kind_is_tracked_exactly():
+    """Each way of holding the tables (all global, per-segment tables in LDS,
+    those plus the crossing tables, everything in LDS) on a geometry that
+    gets it, against the oracle."""
+    import torch
+    seen = {}
+    for cfg in (1, 2, 3, 4):
+        fg, G, O = geoms(cfg)
+        seen.setdefault(G.staging(gt.PREC_MIXED)[0], ("cfg", cfg))
+    for j in range(synth.BATCH_SIZE):
+        if len(seen) == 4:
+            break
+        fg, n, G, O = batch_geoms(j)
+        seen.setdefault(G.staging(gt.PREC_MIXED)[0], ("batch", j))
+    print("staging kinds", seen, flush=True)
+    assert set(seen) == {0, 1, 2, 3}
+    for kind, (what, k) in sorted(seen.items()):
+        if what == "cfg":
+            fg, G, O = geoms(k)
+            kw = dict(seed=99, n_particles=3000, geometry_id=k)
+        else:
+            fg, n, G, O = batch_geoms(k)
+            kw = dict(seed=synth.batch_particle_seed(k), n_particles=3000, geometry_id=synth.batch_geometry_id(k))
+        for prec in (gt.PREC_FP64, gt.PREC_MIXED):
+            g = gpu_track(G, precision=prec, record_first_k=40, record_cap=64, **kw)
+            o = oracle.track(O, oracle.TrackParams(record_first_k=40, record_cap=64, **kw), n_threads=NT)
+            assert_parity(g, o, where="staging kind %d (%s %s) prec %d" % (kind, what, k, prec))
+
+
 def test_batch_graph_replays_match_eager():
     """gt_batch_launch captured into a HIP graph: every replay (with other
     device work and host synchronisation in between) reproduces the eager
