@@ -52,8 +52,9 @@ def parse():
                     help="time one mode only (profiling)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-geometry batched workload")
     ap.add_argument("--no-tail", action="store_true", help="switch off tail compaction (comparison)")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="time the default launch shape instead of the one gt_autotune_track picks")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the launch shape gt_autotune_track picks instead of the library default")
+    ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)   # the default
     ap.add_argument("--tune-batch", action="store_true", help="autotune the batched launch shape first")
     return ap.parse_args()
 
@@ -118,7 +119,7 @@ def timed(gt, G, out, args, prec, hev, lane=False):
     kw = dict(seed=2002, n_particles=args.particles, geometry_id=2, precision=prec, block_size=args.block, out=out,
               lane_per_history=lane, refill_min=0 if lane else args.refill, tail_compaction=not args.no_tail)
     shape = None
-    if not lane and not args.no_autotune and not args.block and not args.refill:
+    if not lane and args.autotune and not args.block and not args.refill:
         shape = gt.autotune_track(G, reps=2, **{k: v for k, v in kw.items() if k not in ("block_size", "refill_min")})
         kw["block_size"], kw["refill_min"] = shape["block_size"], shape["refill_min"]
     r = run_timed(gt, lambda: gt.track(G, **kw), args, hev)

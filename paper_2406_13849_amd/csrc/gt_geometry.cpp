@@ -851,6 +851,7 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
         b->dmem = dm;
         b->d_items = (BatchItem *)(base + o_items);
         b->d_chunks = (BatchChunk *)(base + o_chunks);
+        b->n_chunks = (uint32_t)chunks.size();
         for (int k = 0; k < 4; k++) b->n_kind[k] = n_kind[k];
         b->d_fill = (FillRange *)(base + o_fill);
         b->n_fill = (uint32_t)fills.size();

@@ -181,6 +181,7 @@ struct gt_batch {
     void *dmem;                         // one allocation for everything below
     gt::BatchItem *d_items;
     gt::BatchChunk *d_chunks;           // chunks by staging kind: kind 3, then 2, 1, 0
+    uint32_t n_chunks;
     uint32_t n_kind[4];
     gt::FillRange *d_fill;
     uint32_t n_fill;

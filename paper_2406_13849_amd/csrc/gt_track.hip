@@ -826,7 +826,8 @@ __device__ __forceinline__ void stage_copy(const StagePlan &sp, const unsigned c
 
 // Staging kinds of a plan: nothing in LDS, the per-segment tables only, the
 // per-segment and crossing tables, or every table.
-enum StageKind : uint32_t { SK_NONE = 0, SK_SPLIT = 1, SK_LDS = 2, SK_ALL = 3 };
+// (signed, so that loops counting down over the kinds end)
+enum StageKind : int { SK_NONE = 0, SK_SPLIT = 1, SK_LDS = 2, SK_ALL = 3 };
 
 template <int KIND> struct ViewOf;
 template <> struct ViewOf<SK_NONE> { typedef DevGlobal type; };
@@ -1660,7 +1661,7 @@ int launch_batch_k(gt_batch *b, const BatchChunk *ch, uint32_t n, unsigned long 
 template <int PREC, int W>
 int launch_batch_kinds(gt_batch *b, hipStream_t st) {
     uint32_t first = 0;
-    for (int kind = SK_ALL; kind >= SK_NONE; kind--) {
+    for (int kind = 3; kind >= 0; kind--) {   // chunk groups in the order gt_batch_create wrote them
         const uint32_t n = b->n_kind[kind];
         const BatchChunk *ch = b->d_chunks + first;
         unsigned long long *q = b->d_queue + kind;
@@ -1672,6 +1673,7 @@ int launch_batch_kinds(gt_batch *b, hipStream_t st) {
                                     : launch_batch_k<PREC, SK_NONE, W>(b, ch, n, q, st);
         if (rc) return rc;
     }
+    if (first != b->n_chunks) return set_error("gt_batch_launch: inconsistent chunk groups"), GT_EINVAL;
     return GT_OK;
 }
 
