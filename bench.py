@@ -199,7 +199,7 @@ def cpu_baseline(fg, gpu_out, n):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_track_persistent_17x17_1e6.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2406_13849_amd", "csrc", f)
-                  for f in ("gt_track.hip", "gt_internal.h", "gt_geometry.cpp")]
+                  for f in ("gt_device.h", "gt_track.hip", "gt_internal.h", "gt_geometry.cpp")]
 
 
 def kernel_source_digest():

@@ -718,6 +718,28 @@ extern "C" void gt_geometry_destroy(gt_geometry *g) {
     delete g;
 }
 
+void gt::fill_kparams(const gt_track_params *p, const gt_geometry *g, KParams &kp, KOut &ko, const gt_track_out *o) {
+    kp.seed = p->seed;
+    kp.first = p->first_particle;
+    kp.n = p->n_particles;
+    kp.geom_id = p->geometry_id;
+    kp.max_coll = p->max_collisions;
+    kp.source = p->source;
+    kp.ray_n1 = p->ray_n1;
+    kp.max_segs = p->max_segments;
+    kp.rec_k = (uint32_t)((uint64_t)p->record_first_k < p->n_particles ? p->record_first_k : p->n_particles);
+    kp.rec_cap = p->record_cap;
+    kp.refill_min = p->refill_min ? p->refill_min : kRefillMin;
+    ko.tally_ws = g->tally_ws;
+    ko.seg_count = o->seg_count;
+    ko.seq_hash = o->seq_hash;
+    ko.end_code = o->end_code;
+    ko.rec = o->rec;
+    ko.counters = o->counters;
+}
+
+unsigned gt::stage_budget() { return kStageBudget; }
+
 int gt::check_track_args(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o) {
     if (!g || !p || !o) return set_error("gt_track: null argument"), GT_EINVAL;
     if (!o->tally_fx || !o->counters) return set_error("gt_track: tally_fx and counters are required"), GT_EINVAL;

@@ -17,6 +17,15 @@ __host__ __device__ inline uint32_t hs_pack(uint32_t s, bool pos, uint32_t type)
     return (s << 4) | ((pos ? 1u : 0u) << 3) | type;
 }
 
+constexpr int kBlockP = 1024;   // lanes per workgroup of the persistent trackers (launch bound)
+// LDS left for staged geometry tables next to the persistent trackers'
+// per-lane level columns (160 KiB per compute unit on gfx950)
+constexpr unsigned kStageBudget = 160 * 1024 - GT_MAX_LEVELS * kBlockP * 4 - 1024;
+// A wave refills its idle lanes once at least this many are idle, so that
+// new histories start together and their first searches (which rarely have
+// a good candidate) run once for several lanes.
+constexpr uint32_t kRefillMin = 8;
+
 constexpr uint32_t kLeafNone = 0xFFFFFFFFu;
 constexpr uint32_t kLeafMax = 4;       // cells per BVH leaf
 constexpr uint32_t kHintNone = 0, kHintSquare = 1;

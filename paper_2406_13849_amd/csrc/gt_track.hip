@@ -12,639 +12,17 @@
 // A particle's state lives in registers; the cell of each level lives in
 // LDS (one column per lane) so level loops index it without spilling.
 //
-// Floating point: compiled with -ffp-contract=off and no fast-math, so every
-// double operation below is one IEEE operation in the order written; the
-// results of find_cell / distance_to_surface / cross_surface are the ones a
-// plain double-precision implementation of the same definitions computes.
-// Single precision only appears in the optional candidate pruning (widened,
-// outward-rounded boxes and a lattice-index guess), which can skip a cell
-// only when that cell cannot contain the point.
+// The device functions are in gt_device.h; this file holds the kernels and
+// their host-side launchers.
 #pragma clang fp contract(off)
 
 #include <algorithm>
 #include <mutex>
 
-#include "gt_internal.h"
+#include "gt_device.h"
 
 namespace gt {
 namespace {
-
-constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr int kMaxBirthAttempts = 1000;
-constexpr uint64_t kFnvOffset = 0xcbf29ce484222325ull;
-constexpr uint64_t kFnvPrime = 0x100000001b3ull;
-constexpr int kBlock = 256;     // lanes per workgroup of the one-history-per-lane kernels
-constexpr int kBlockP = 1024;   // lanes per workgroup of the persistent tracker (launch bound)
-// LDS left for staged geometry tables next to the persistent tracker's
-// per-lane level arrays (160 KiB per compute unit on gfx950)
-constexpr unsigned kStageBudget = 160 * 1024 - GT_MAX_LEVELS * kBlockP * 4 - 1024;
-
-__device__ __forceinline__ double dinf() { return __builtin_huge_val(); }
-
-// ------------------------------------------------------------------ table views
-// The kernels read the geometry tables through pointers whose address space
-// is part of their type, so the compiler emits LDS reads (32-bit addresses)
-// for tables staged in LDS and global loads for the others, instead of flat
-// loads that must serve both.  A view DevT<A, B, C> holds the per-segment
-// tables (cells, half-spaces, surfaces, universes, materials, local indices)
-// in address space A, the crossing tables (translations, candidate lists) in
-// B and the hierarchy (nodes, leaves, cell boxes) in C; 3 = LDS, 1 = global.
-template <int AS, typename T> using cptr = const __attribute__((address_space(AS))) T *;
-
-template <int A, int B, int C>
-struct DevT {
-    cptr<A, double> coef;
-    cptr<A, uint32_t> hs;
-    cptr<A, Cell> cell;
-    cptr<A, Univ> univ;
-    cptr<A, double> sigma;
-    cptr<A, uint32_t> cell_local;
-    cptr<B, double> trans;
-    cptr<B, uint32_t> adj_off;
-    cptr<B, uint32_t> adj;
-    cptr<C, Node32> node32;
-    cptr<C, Node64> node64;
-    cptr<C, uint32_t> leaf;
-    cptr<C, float> cbox;
-    uint32_t root, n_inst, max_depth, n_cells;
-    double lo[3], hi[3];
-};
-
-typedef DevT<1, 1, 1> DevGlobal;   // every table in global memory
-typedef DevT<3, 1, 1> DevSplit;    // per-segment tables in LDS
-typedef DevT<3, 3, 1> DevLds;      // per-segment and crossing tables in LDS
-typedef DevT<3, 3, 3> DevAll;      // every table in LDS
-
-// Store to global memory (the output arrays) through a typed pointer.
-template <typename T, typename V>
-__device__ __forceinline__ void gstore(T *base, uint64_t i, V v) {
-    ((__attribute__((address_space(1))) T *)base)[i] = (T)v;
-}
-
-// A whole record through a typed pointer (the copy goes through a generic
-// pointer cast from the typed one, which keeps the address space).
-template <typename T, typename P>
-__device__ __forceinline__ T ldv(P p) {
-    return *(const T *)p;
-}
-
-template <int A, int B, int C>
-__device__ __forceinline__ void view_scalars(DevT<A, B, C> &d, const Dev &g) {
-    d.root = g.root;
-    d.n_inst = g.n_inst;
-    d.max_depth = g.max_depth;
-    d.n_cells = g.n_cells;
-    for (int k = 0; k < 3; k++) {
-        d.lo[k] = g.lo[k];
-        d.hi[k] = g.hi[k];
-    }
-}
-
-__device__ __forceinline__ DevGlobal global_view(const Dev &g) {
-    DevGlobal d;
-    d.coef = (cptr<1, double>)g.coef;
-    d.hs = (cptr<1, uint32_t>)g.hs;
-    d.cell = (cptr<1, Cell>)g.cell;
-    d.univ = (cptr<1, Univ>)g.univ;
-    d.sigma = (cptr<1, double>)g.sigma;
-    d.cell_local = (cptr<1, uint32_t>)g.cell_local;
-    d.trans = (cptr<1, double>)g.trans;
-    d.adj_off = (cptr<1, uint32_t>)g.adj_off;
-    d.adj = (cptr<1, uint32_t>)g.adj;
-    d.node32 = (cptr<1, Node32>)g.node32;
-    d.node64 = (cptr<1, Node64>)g.node64;
-    d.leaf = (cptr<1, uint32_t>)g.leaf;
-    d.cbox = (cptr<1, float>)g.cbox;
-    view_scalars(d, g);
-    return d;
-}
-
-// ------------------------------------------------------------------ RNG
-// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
-// 32x32->64 multiplies with the published multipliers, the key bumped by the
-// published Weyl constants between rounds.
-__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                              uint32_t k1, uint32_t &o0, uint32_t &o1, uint32_t &o2, uint32_t &o3) {
-#pragma unroll
-    for (int r = 0; r < 10; r++) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    o0 = c0; o1 = c1; o2 = c2; o3 = c3;
-}
-
-// One sampling event = one Philox block at counter (b, id lo, id hi,
-// geometry id): its 128 bits (word 0 least significant) give three 42-bit
-// fields (bits [0,42), [42,84), [84,126)), each mapped exactly to the
-// uniform (f + 1/2) 2^-42 in (0,1).
-__device__ __forceinline__ void draw_block(uint64_t key, uint32_t gid, uint64_t pid, uint32_t b, double &u0,
-                                           double &u1, double &u2) {
-    uint32_t o0, o1, o2, o3;
-    philox4x32_10(b, (uint32_t)pid, (uint32_t)(pid >> 32), gid, (uint32_t)key, (uint32_t)(key >> 32), o0, o1, o2,
-                  o3);
-    const uint64_t w0 = ((uint64_t)o1 << 32) | o0, w1 = ((uint64_t)o3 << 32) | o2;
-    const uint64_t m42 = (1ull << 42) - 1;
-    const uint64_t f0 = w0 & m42;
-    const uint64_t f1 = (w0 >> 42) | ((w1 & ((1ull << 20) - 1)) << 22);
-    const uint64_t f2 = (w1 >> 20) & m42;
-    u0 = ((double)f0 + 0.5) * 0x1p-42;
-    u1 = ((double)f1 + 0.5) * 0x1p-42;
-    u2 = ((double)f2 + 0.5) * 0x1p-42;
-}
-
-// Natural logarithm from log m = 2 atanh(s), s = (m-1)/(m+1), m in
-// [sqrt(1/2), sqrt(2)), twelve odd-power terms with coefficients 1/(2k+1)
-// (each the correctly rounded quotient), and e*ln2 split in a 32-bit head
-// (exact products) and a tail.  Used for the exponential optical depth.
-__device__ __forceinline__ double series_log(double x) {
-    const uint64_t bits = (uint64_t)__double_as_longlong(x);
-    int e = (int)((bits >> 52) & 0x7ffu) - 1023;
-    double m = __longlong_as_double((long long)((bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
-    const double sqrt2 = __longlong_as_double(0x3FF6A09E667F3BCDll);
-    if (m >= sqrt2) { m = m * 0.5; e = e + 1; }
-    const double s = (m - 1.0) / (m + 1.0);
-    const double z = s * s;
-    double poly = 1.0 / 23.0;
-    poly = poly * z + 1.0 / 21.0;
-    poly = poly * z + 1.0 / 19.0;
-    poly = poly * z + 1.0 / 17.0;
-    poly = poly * z + 1.0 / 15.0;
-    poly = poly * z + 1.0 / 13.0;
-    poly = poly * z + 1.0 / 11.0;
-    poly = poly * z + 1.0 / 9.0;
-    poly = poly * z + 1.0 / 7.0;
-    poly = poly * z + 1.0 / 5.0;
-    poly = poly * z + 1.0 / 3.0;
-    poly = poly * z + 1.0;
-    const double logm = (s + s) * poly;
-    const double ln2_hi = __longlong_as_double(0x3FE62E42FEE00000ll);
-    const double ln2_lo = __longlong_as_double(0x3DEA39EF35793C76ll);
-    const double de = (double)e;
-    return de * ln2_hi + (de * ln2_lo + logm);
-}
-
-// Marsaglia (1972) isotropic direction from one block's first two fields;
-// false when the pair is rejected.
-__device__ __forceinline__ bool direction_from(double u0, double u1, double &u, double &v, double &w) {
-    const double v1 = 2.0 * u0 - 1.0;
-    const double v2 = 2.0 * u1 - 1.0;
-    const double s = v1 * v1 + v2 * v2;
-    if (!(s < 1.0 && s != 0.0)) return false;
-    const double r = sqrt(1.0 - s);
-    u = (2.0 * v1) * r;
-    v = (2.0 * v2) * r;
-    w = 1.0 - 2.0 * s;
-    return true;
-}
-
-// ------------------------------------------------------------------ surfaces
-// Half-spaces of a cell are stored planes first (types PX, PY, PZ, P), then
-// quadrics (CZ, SPH), so each loop below runs one surface family.
-template <typename CP>
-__device__ __forceinline__ double plane_value(uint32_t type, CP c, double x, double y, double z) {
-    switch (type) {
-    case ST_PX: return x - c[0];
-    case ST_PY: return y - c[0];
-    case ST_PZ: return z - c[0];
-    default: return ((c[0] * x + c[1] * y) + c[2] * z) - c[3];
-    }
-}
-
-template <typename CP>
-__device__ __forceinline__ double quad_value(uint32_t type, CP c, double x, double y, double z) {
-    const double dx = x - c[0], dy = y - c[1];
-    if (type == ST_CZ) return (dx * dx + dy * dy) - c[2];
-    const double dz = z - c[2];
-    return ((dx * dx + dy * dy) + dz * dz) - c[3];
-}
-
-// Cell containment: the point is on the required side of every half-space;
-// on surface force_s the logical sense force_pos is used instead.
-template <typename G>
-__device__ __forceinline__ bool contains(const G &g, uint32_t c, double x, double y, double z, uint32_t force_s,
-                                         bool force_pos) {
-    const Cell cc = ldv<Cell>(g.cell + c);
-    const auto hs = g.hs + cc.hs_off;
-    const uint32_t npl = cc.n_pl & kPlaneCountMask;
-    for (uint32_t k = 0; k < npl; k++) {
-        const uint32_t h = hs[k];
-        const uint32_t s = h >> 4;
-        const bool pos = (s == force_s) ? force_pos : (plane_value(h & 7u, g.coef + 4 * (size_t)s, x, y, z) > 0.0);
-        if (pos != (bool)((h >> 3) & 1u)) return false;
-    }
-    for (uint32_t k = npl; k < cc.n_hs; k++) {
-        const uint32_t h = hs[k];
-        const uint32_t s = h >> 4;
-        const bool pos = (s == force_s) ? force_pos : (quad_value(h & 7u, g.coef + 4 * (size_t)s, x, y, z) > 0.0);
-        if (pos != (bool)((h >> 3) & 1u)) return false;
-    }
-    return true;
-}
-
-// Distance along (u,v,w) from q to the point where a plane's sense leaves
-// the cell's required side `pos`; +inf if it does not (Table 1).
-template <typename CP>
-__device__ __forceinline__ double plane_den(uint32_t type, CP c, double u, double v, double w) {
-    switch (type) {
-    case ST_PX: return u;
-    case ST_PY: return v;
-    case ST_PZ: return w;
-    default: return (c[0] * u + c[1] * v) + c[2] * w;
-    }
-}
-
-template <typename CP>
-__device__ __forceinline__ double plane_distance(uint32_t type, CP c, bool pos, double qx, double qy,
-                                                 double qz, double u, double v, double w) {
-    const double den = plane_den(type, c, u, v, w);
-    if (den == 0.0) return dinf();
-    if (!((!pos && den > 0.0) || (pos && den < 0.0))) return dinf();
-    const double t = (-plane_value(type, c, qx, qy, qz)) / den;
-    return (t > 0.0) ? t : 0.0;
-}
-
-// The same for a cylinder or sphere: textbook cancellation-free roots;
-// `on` marks the surface just crossed (only the far root can be hit).
-template <typename CP>
-__device__ __forceinline__ double quad_distance(uint32_t type, CP c, bool pos, double qx, double qy,
-                                                double qz, double u, double v, double w, bool on) {
-    double a, b;
-    const double dx = qx - c[0], dy = qy - c[1];
-    if (type == ST_CZ) {
-        a = u * u + v * v;
-        b = dx * u + dy * v;
-    } else {
-        const double dz = qz - c[2];
-        a = (u * u + v * v) + w * w;
-        b = (dx * u + dy * v) + dz * w;
-    }
-    if (a == 0.0) return dinf();
-    double t;
-    if (on) {
-        if (!(!pos && b < 0.0)) return dinf();
-        t = (-2.0 * b) / a;
-    } else {
-        const double cc = quad_value(type, c, qx, qy, qz);
-        const double disc = b * b - a * cc;
-        if (!(disc > 0.0)) return dinf();
-        const double q = sqrt(disc);
-        if (!pos) {
-            t = (b <= 0.0) ? (q - b) / a : (-cc) / (b + q);
-        } else {
-            if (!(b < 0.0)) return dinf();
-            t = cc / (q - b);
-        }
-    }
-    return (t > 0.0) ? t : 0.0;
-}
-
-// ------------------------------------------------------------------ search
-// The cell of universe u containing (x,y,z) -- Table 1 find_cell when
-// force_s == kNone, the cross_surface candidate test otherwise -- or -1.
-// Mixed precision first tries the lattice-index guess at (gx, gy), then
-// walks the single-precision hierarchy; double precision walks the
-// double-precision hierarchy.  Whichever cell is returned passed the double
-// containment test, which at most one cell of a universe passes.
-template <int PREC, typename G>
-__device__ int32_t search(const G &g, uint32_t u, double x, double y, double z, uint32_t force_s, bool force_pos,
-                          int32_t exclude, float gx, float gy) {
-    const Univ U = ldv<Univ>(g.univ + u);
-    if (PREC == GT_PREC_MIXED && U.hint == (int32_t)kHintSquare) {
-        int i = (int)floorf((gx - U.x0) * U.inv_px);
-        int j = (int)floorf((gy - U.y0) * U.inv_py);
-        i = min(max(i, 0), U.nx - 1);
-        j = min(max(j, 0), U.ny - 1);
-        const int32_t c = (int32_t)U.cell0 + j * U.nx + i;
-        if (c != exclude && contains(g, (uint32_t)c, x, y, z, force_s, force_pos)) return c;
-    }
-    uint32_t n = U.node0;
-    const uint32_t end = U.node0 + U.nnode;
-    const float fx = (float)x, fy = (float)y, fz = (float)z;
-    while (n < end) {
-        bool in;
-        uint32_t esc, lf;
-        if (PREC == GT_PREC_MIXED) {
-            const Node32 nd = ldv<Node32>(g.node32 + n);
-            in = fx >= nd.lo[0] && fx <= nd.hi[0] && fy >= nd.lo[1] && fy <= nd.hi[1] && fz >= nd.lo[2] &&
-                 fz <= nd.hi[2];
-            esc = nd.escape;
-            lf = nd.leaf;
-        } else {
-            const Node64 nd = ldv<Node64>(g.node64 + n);
-            in = x >= nd.lo[0] && x <= nd.hi[0] && y >= nd.lo[1] && y <= nd.hi[1] && z >= nd.lo[2] && z <= nd.hi[2];
-            esc = nd.escape;
-            lf = nd.leaf;
-        }
-        if (!in) { n = esc; continue; }
-        if (lf == kLeafNone) { n++; continue; }
-        const uint32_t first = lf >> 4, cnt = (lf & 15u) + 1;
-        for (uint32_t k = 0; k < cnt; k++) {
-            const uint32_t c = g.leaf[first + k];
-            if ((int32_t)c == exclude) continue;
-            if (PREC == GT_PREC_MIXED) {
-                const auto b = g.cbox + 8 * (size_t)c;
-                if (!(fx >= b[0] && fx <= b[4] && fy >= b[1] && fy <= b[5] && fz >= b[2] && fz <= b[6])) continue;
-            }
-            if (contains(g, c, x, y, z, force_s, force_pos)) return (int32_t)c;
-        }
-        n = esc;
-    }
-    return -1;
-}
-
-// ------------------------------------------------------------------ particle
-struct Particle {
-    double x, y, z, u, v, w, tau;
-    uint32_t *cell;     // LDS column: cell of level L at cell[L * blockDim.x]
-    int depth;
-    int on_level;
-    uint32_t on_surf;
-};
-
-__device__ __forceinline__ uint32_t &lvl(const Particle &P, int L) { return P.cell[L * (int)blockDim.x]; }
-
-// Descend from level L0 (cell set, (qx,qy,qz) its local position): while
-// the cell is filled, find the daughter's cell at p - t (Alg. 7).
-template <int PREC, typename G>
-__device__ __forceinline__ bool descend(const G &g, Particle &P, int L0, double qx, double qy, double qz) {
-    int L = L0;
-    for (;;) {
-        const uint32_t c = lvl(P, L);
-        const int32_t fill = g.cell[c].fill;
-        if (fill >= 0) break;
-        const auto t = g.trans + 4 * (size_t)c;
-        qx = qx - t[0];
-        qy = qy - t[1];
-        qz = qz - t[2];
-        const int32_t d = search<PREC>(g, (uint32_t)(-fill - 1), qx, qy, qz, kNone, false, -1, (float)qx, (float)qy);
-        if (d < 0) { P.depth = L + 1; return false; }
-        L++;
-        lvl(P, L) = (uint32_t)d;
-    }
-    P.depth = L + 1;
-    return true;
-}
-
-template <typename G>
-__device__ __forceinline__ uint32_t leaf_instance(const G &g, const Particle &P) {
-    uint32_t i = 0;
-    for (int L = 0; L < P.depth; L++) i += g.cell[lvl(P, L)].inst_off;
-    return i;
-}
-
-// distance_to_surface over every level; ties resolve to the smallest
-// (distance, level, surface id), i.e. the top-most level on the surface.
-template <typename G>
-__device__ __forceinline__ double distance_all(const G &g, const Particle &P, int &bl, uint32_t &bs, bool &bpos,
-                                               uint32_t &bk) {
-    double bt = dinf();
-    bl = GT_MAX_LEVELS;
-    bs = kNone;
-    bpos = false;
-    bk = 0;
-    double qx = P.x, qy = P.y, qz = P.z;
-    for (int L = 0; L < P.depth; L++) {
-        const uint32_t c = lvl(P, L);
-        if (L > 0) {
-            const auto t = g.trans + 4 * (size_t)lvl(P, L - 1);
-            qx = qx - t[0];
-            qy = qy - t[1];
-            qz = qz - t[2];
-        }
-        const Cell cc = ldv<Cell>(g.cell + c);
-        const auto hs = g.hs + cc.hs_off;
-        const uint32_t npl = cc.n_pl & kPlaneCountMask;
-        for (uint32_t k = 0; k < npl; k++) {
-            const uint32_t h = hs[k];
-            const uint32_t s = h >> 4;
-            const bool pos = (h >> 3) & 1u;
-            if (P.on_level == L && P.on_surf == s) continue;   // a plane just crossed is not hit again
-            const double d = plane_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w);
-            if (d < bt || (d == bt && d != dinf() && L == bl && s < bs)) {
-                bt = d;
-                bl = L;
-                bs = s;
-                bpos = pos;
-                bk = cc.hs_off + k;
-            }
-        }
-        for (uint32_t k = npl; k < cc.n_hs; k++) {
-            const uint32_t h = hs[k];
-            const uint32_t s = h >> 4;
-            const bool pos = (h >> 3) & 1u;
-            const bool on = (P.on_level == L) && (P.on_surf == s);
-            const double d = quad_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w, on);
-            if (d < bt || (d == bt && d != dinf() && L == bl && s < bs)) {
-                bt = d;
-                bl = L;
-                bs = s;
-                bpos = pos;
-                bk = cc.hs_off + k;
-            }
-        }
-    }
-    return bt;
-}
-
-// distance_to_surface as above, also returning what the segment step needs
-// without reading the levels' cells again: the leaf instance and material,
-// and the universe of the level that holds the nearest surface.
-struct Nearest {
-    double t;
-    int level;
-    uint32_t surf, entry, univ, inst;
-    int32_t leaf_fill;
-    bool pos;
-};
-
-template <typename G>
-__device__ __forceinline__ void nearest_surface(const G &g, const Particle &P, Nearest &r) {
-    r.t = dinf();
-    r.level = GT_MAX_LEVELS;
-    r.surf = kNone;
-    r.entry = 0;
-    r.pos = false;
-    r.univ = g.root;
-    r.inst = 0;
-    double qx = P.x, qy = P.y, qz = P.z;
-    uint32_t univ = g.root;
-    int32_t fill = 0;
-    for (int L = 0; L < P.depth; L++) {
-        const uint32_t c = lvl(P, L);
-        if (L > 0) {
-            const auto t = g.trans + 4 * (size_t)lvl(P, L - 1);
-            qx = qx - t[0];
-            qy = qy - t[1];
-            qz = qz - t[2];
-            univ = (uint32_t)(-fill - 1);
-        }
-        const Cell cc = ldv<Cell>(g.cell + c);
-        fill = cc.fill;
-        r.inst += cc.inst_off;
-        const auto hs = g.hs + cc.hs_off;
-        const uint32_t npl = cc.n_pl & kPlaneCountMask, npair2 = 2u * (cc.n_pl >> 12);
-        bool better = false;
-        for (uint32_t k = 0; k < npair2; k += 2) {
-            // a slab pair: the shared denominator picks the one plane that can be
-            // reached (the negative-side one when it is positive); the other
-            // would give no hit
-            const uint32_t h0 = hs[k];
-            const double den = plane_den(h0 & 7u, g.coef + 4 * (size_t)(h0 >> 4), P.u, P.v, P.w);
-            if (den == 0.0) continue;
-            const uint32_t kk = den > 0.0 ? k : k + 1;
-            const uint32_t h = den > 0.0 ? h0 : hs[k + 1];
-            const uint32_t s = h >> 4;
-            if (P.on_level == L && P.on_surf == s) continue;   // a plane just crossed is not hit again
-            const double t = (-plane_value(h & 7u, g.coef + 4 * (size_t)s, qx, qy, qz)) / den;
-            const double d = (t > 0.0) ? t : 0.0;
-            if (d < r.t || (d == r.t && d != dinf() && L == r.level && s < r.surf)) {
-                r.t = d;
-                r.level = L;
-                r.surf = s;
-                r.pos = den < 0.0;
-                r.entry = cc.hs_off + kk;
-                better = true;
-            }
-        }
-        for (uint32_t k = npair2; k < npl; k++) {
-            const uint32_t h = hs[k];
-            const uint32_t s = h >> 4;
-            const bool pos = (h >> 3) & 1u;
-            if (P.on_level == L && P.on_surf == s) continue;   // a plane just crossed is not hit again
-            const double d = plane_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w);
-            if (d < r.t || (d == r.t && d != dinf() && L == r.level && s < r.surf)) {
-                r.t = d;
-                r.level = L;
-                r.surf = s;
-                r.pos = pos;
-                r.entry = cc.hs_off + k;
-                better = true;
-            }
-        }
-        for (uint32_t k = npl; k < cc.n_hs; k++) {
-            const uint32_t h = hs[k];
-            const uint32_t s = h >> 4;
-            const bool pos = (h >> 3) & 1u;
-            const bool on = (P.on_level == L) && (P.on_surf == s);
-            const double d = quad_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w, on);
-            if (d < r.t || (d == r.t && d != dinf() && L == r.level && s < r.surf)) {
-                r.t = d;
-                r.level = L;
-                r.surf = s;
-                r.pos = pos;
-                r.entry = cc.hs_off + k;
-                better = true;
-            }
-        }
-        if (better) r.univ = univ;
-    }
-    r.leaf_fill = fill;
-}
-
-// cross_surface at level L* on surface s* (Alg. 8) for the one-history-
-// per-lane schedule: the cell of that level's universe on the other side
-// (the old cell's sense on s* flipped), then descent below it.
-template <int PREC, typename G>
-__device__ __forceinline__ int cross(const G &g, Particle &P, int Ls, uint32_t ss, bool old_pos) {
-    double qx = P.x, qy = P.y, qz = P.z;
-    uint32_t univ = g.root;
-    for (int L = 0; L < Ls; L++) {
-        const uint32_t c = lvl(P, L);
-        const auto t = g.trans + 4 * (size_t)c;
-        qx = qx - t[0];
-        qy = qy - t[1];
-        qz = qz - t[2];
-        univ = (uint32_t)(-g.cell[c].fill - 1);
-    }
-    const uint32_t old = lvl(P, Ls);
-    // guess point nudged along the flight so that a lattice guess lands on the far side
-    float gx = (float)qx, gy = (float)qy;
-    if (PREC == GT_PREC_MIXED) {
-        const Univ U = ldv<Univ>(g.univ + univ);
-        if (U.hint == (int32_t)kHintSquare) {
-            gx += (float)P.u * 1e-3f / U.inv_px;
-            gy += (float)P.v * 1e-3f / U.inv_py;
-        }
-    }
-    const int32_t c = search<PREC>(g, univ, qx, qy, qz, ss, !old_pos, (int32_t)old, gx, gy);
-    if (c < 0) return Ls == 0 ? GT_END_ESCAPE : GT_END_LOST;
-    lvl(P, Ls) = (uint32_t)c;
-    if (!descend<PREC>(g, P, Ls, qx, qy, qz)) return GT_END_LOST;
-    P.on_level = Ls;
-    P.on_surf = ss;
-    return GT_END_NONE;
-}
-
-// ------------------------------------------------------------------ tallies
-// Segment lengths are summed as 128-bit integers in units of 2^-96 cm.  In
-// the kernel a contribution is split into four 32-bit limbs, each added to
-// its own 64-bit counter with an atomic whose result is not used, so no
-// carry has to travel back to the lane; the counters are exact for up to
-// 2^32 contributions per instance and launch.  Each XCD adds into its own
-// replica of the counters, so the atomics stay in that XCD's L2; the
-// finalize kernel folds replicas and limbs into the 128-bit total.
-constexpr int kReplicas = 8;
-
-__device__ __forceinline__ uint32_t xcc_id() {
-    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kReplicas - 1);   // HW_REG_XCC_ID[3:0]
-}
-
-struct TallyAcc {
-    uint32_t inst;
-    uint64_t lo, hi;   // 128-bit register accumulator for consecutive segments in one instance
-};
-
-__device__ __forceinline__ void add_limb(uint64_t *p, uint64_t v) {
-    if (v) __hip_atomic_fetch_add((__attribute__((address_space(1))) unsigned long long *)p, (unsigned long long)v,
-                                  __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-__device__ __forceinline__ void tally_flush(uint64_t *rep, TallyAcc &a) {
-    if (a.inst == kNone) return;
-    uint64_t *p = rep + 4 * (size_t)a.inst;
-    add_limb(p + 0, a.lo & 0xFFFFFFFFull);
-    add_limb(p + 1, a.lo >> 32);
-    add_limb(p + 2, a.hi & 0xFFFFFFFFull);
-    add_limb(p + 3, a.hi >> 32);
-    a.inst = kNone;
-}
-
-__device__ __forceinline__ void tally_add(uint64_t *rep, TallyAcc &a, uint32_t inst, double l) {
-    const double v = l * 0x1p32;
-    const double fl = floor(v);
-    const double fr = v - fl;
-    const uint64_t hi = (uint64_t)fl;
-    const uint64_t lo = (uint64_t)(fr * 0x1p64);
-    if (inst != a.inst) {
-        tally_flush(rep, a);
-        a.inst = inst;
-        a.lo = lo;
-        a.hi = hi;
-    } else {
-        const uint64_t nlo = a.lo + lo;
-        a.hi += hi + ((nlo < a.lo) ? 1u : 0u);
-        a.lo = nlo;
-    }
-}
-
-struct Counts {
-    uint32_t escaped, capped, lost, segcap, recovf, rejected;
-    uint64_t segments;
-};
-
-__device__ __forceinline__ void count_end(Counts &cnt, int end, uint32_t segs, bool recovf) {
-    cnt.segments += segs;
-    cnt.escaped += end == GT_END_ESCAPE;
-    cnt.capped += end == GT_END_CAP;
-    cnt.lost += end == GT_END_LOST;
-    cnt.segcap += end == GT_END_SEGCAP;
-    cnt.recovf += recovf;
-}
 
 __device__ __forceinline__ void add_counts(const Counts &c, uint64_t *counters) {
     __shared__ unsigned long long sh[7];
@@ -661,125 +39,6 @@ __device__ __forceinline__ void add_counts(const Counts &c, uint64_t *counters) 
     if (threadIdx.x < 7 && sh[threadIdx.x]) atomicAdd((unsigned long long *)&counters[threadIdx.x], sh[threadIdx.x]);
 }
 
-// ------------------------------------------------------------------ plain schedule
-// One history per lane: Alg. 2 with the toy transport, straight-line.
-template <int PREC, typename G>
-__device__ void run_history(const G &g, const KParams &p, const KOut &o, uint64_t *rep, uint64_t local,
-                            uint32_t *cells, Counts &cnt) {
-    Particle P;
-    P.cell = cells;
-    const uint64_t pid = p.first + local;
-    uint32_t blk = 0;
-    P.on_level = -1;
-    P.on_surf = kNone;
-    P.depth = 1;
-    int end = GT_END_NONE;
-    double u0, u1, u2;
-    // ---- birth
-    if (p.source == 1) {
-        const uint64_t n1 = p.ray_n1;
-        const uint64_t n2 = (p.n + n1 - 1) / n1;
-        const uint64_t j = pid % n1, k = pid / n1;
-        const double hy = (g.hi[1] - g.lo[1]) / (double)n1;
-        const double hz = (g.hi[2] - g.lo[2]) / (double)n2;
-        P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * 0x1p-30;
-        P.y = g.lo[1] + ((double)j + 0.5) * hy;
-        P.z = g.lo[2] + ((double)k + 0.5) * hz;
-        P.u = 1.0;
-        P.v = 0.0;
-        P.w = 0.0;
-        P.tau = 0.0;
-        const int32_t c = search<PREC>(g, g.root, P.x, P.y, P.z, kNone, false, -1, (float)P.x, (float)P.y);
-        if (c < 0) {
-            end = GT_END_LOST;
-        } else {
-            lvl(P, 0) = (uint32_t)c;
-            if (!descend<PREC>(g, P, 0, P.x, P.y, P.z)) end = GT_END_LOST;
-        }
-    } else {
-        int32_t c = -1;
-        for (int a = 0; a < kMaxBirthAttempts && c < 0; a++) {
-            draw_block(p.seed, p.geom_id, pid, blk++, u0, u1, u2);
-            P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * u0;
-            P.y = g.lo[1] + (g.hi[1] - g.lo[1]) * u1;
-            P.z = g.lo[2] + (g.hi[2] - g.lo[2]) * u2;
-            c = search<PREC>(g, g.root, P.x, P.y, P.z, kNone, false, -1, (float)P.x, (float)P.y);
-            if (c < 0) cnt.rejected++;
-        }
-        if (c < 0) {
-            end = GT_END_LOST;
-        } else {
-            lvl(P, 0) = (uint32_t)c;
-            if (!descend<PREC>(g, P, 0, P.x, P.y, P.z)) end = GT_END_LOST;
-            do draw_block(p.seed, p.geom_id, pid, blk++, u0, u1, u2);
-            while (!direction_from(u0, u1, P.u, P.v, P.w));
-            P.tau = -series_log(u2);
-        }
-    }
-    // ---- segments
-    uint64_t h = kFnvOffset;
-    uint32_t segs = 0, ncoll = 0;
-    bool recovf = false;
-    const bool recorded = local < p.rec_k;
-    int32_t *rec = recorded ? o.rec + local * (uint64_t)p.rec_cap : nullptr;
-    TallyAcc acc;
-    acc.inst = kNone;
-    acc.lo = acc.hi = 0;
-    while (end == GT_END_NONE) {
-        int bl;
-        uint32_t bs, bk;
-        bool bpos;
-        const double dist = distance_all(g, P, bl, bs, bpos, bk);
-        const uint32_t lc = lvl(P, P.depth - 1);
-        const double sig = g.sigma[g.cell[lc].fill];
-        const double sc = (p.source == 1) ? dinf() : P.tau / sig;
-        const uint32_t inst = leaf_instance(g, P);
-        const bool boundary = dist < sc;
-        double l;
-        if (boundary) {
-            l = dist;
-            if (p.source != 1) P.tau = P.tau - sig * dist;
-        } else {
-            if (sc == dinf()) { end = GT_END_LOST; break; }
-            l = sc;
-        }
-        // move_within_cell
-        const double m0 = l * P.u, m1 = l * P.v, m2 = l * P.w;
-        P.x = P.x + m0;
-        P.y = P.y + m1;
-        P.z = P.z + m2;
-        // tally and sequence
-        tally_add(rep, acc, inst, l);
-        h = (h ^ ((uint64_t)inst + 1)) * kFnvPrime;
-        if (recorded) {
-            if (segs < p.rec_cap) rec[segs] = (int32_t)inst;
-            else recovf = true;
-        }
-        segs++;
-        if (boundary) {
-            end = cross<PREC>(g, P, bl, bs, bpos);
-        } else {
-            P.on_level = -1;
-            P.on_surf = kNone;
-            ncoll++;
-            if (ncoll >= p.max_coll) {
-                end = GT_END_CAP;
-            } else {
-                do draw_block(p.seed, p.geom_id, pid, blk++, u0, u1, u2);
-                while (!direction_from(u0, u1, P.u, P.v, P.w));
-                P.tau = -series_log(u2);
-            }
-        }
-        if (end == GT_END_NONE && segs >= p.max_segs) end = GT_END_SEGCAP;
-    }
-    tally_flush(rep, acc);
-    h ^= (uint64_t)end;
-    if (o.seg_count) gstore(o.seg_count, local, segs);
-    if (o.seq_hash) gstore(o.seq_hash, local, h);
-    if (o.end_code) gstore(o.end_code, local, end);
-    count_end(cnt, end, segs, recovf);
-}
-
 template <int PREC>
 __global__ void __launch_bounds__(kBlock) k_track(Dev g0, KParams p, KOut o) {
     __shared__ uint32_t cells[GT_MAX_LEVELS * kBlock];
@@ -791,496 +50,6 @@ __global__ void __launch_bounds__(kBlock) k_track(Dev g0, KParams p, KOut o) {
     add_counts(cnt, o.counters);
 }
 
-// ------------------------------------------------------------------ persistent schedule
-// Each lane runs a state machine; a wave loops until the shared particle
-// pool is drained and all of its lanes are idle.  Finished lanes are
-// refilled at once from a wave-local pool of particle ids (ballot +
-// per-lane rank, one global atomic per 64 ids), so a wave no longer waits
-// for its longest history.  Per loop trip every lane takes at most one of
-// each step -- draw one random block (a birth position or a direction
-// attempt with its optical depth), search one level, one segment -- and
-// each step has one call site, so lanes at different points of their
-// histories share one instruction stream per step.
-enum Mode : int { M_IDLE = 0, M_POS = 1, M_DIR = 2, M_SEARCH = 3, M_TRACK = 4 };
-
-constexpr uint32_t kChunk = 64;
-// A wave refills its idle lanes once at least this many are idle, so that
-// new histories start together and their first searches (which rarely have
-// a good candidate) run once for several lanes.
-constexpr uint32_t kRefillMin = 8;
-
-__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-// Copy the plan's sections of the device blob into LDS (all lanes of the
-// workgroup take part).
-__device__ __forceinline__ void stage_copy(const StagePlan &sp, const unsigned char *blob, unsigned char *lds) {
-    for (uint32_t k = 0; k < sp.n; k++) {
-        const uint4 *src = (const uint4 *)(blob + sp.src[k]);
-        uint4 *dst = (uint4 *)(lds + sp.dst[k]);
-        for (uint32_t i = threadIdx.x; i < sp.bytes[k] / 16; i += blockDim.x) dst[i] = src[i];
-    }
-    __syncthreads();
-}
-
-// Staging kinds of a plan: nothing in LDS, the per-segment tables only, the
-// per-segment and crossing tables, or every table.
-// (signed, so that loops counting down over the kinds end)
-enum StageKind : int { SK_NONE = 0, SK_SPLIT = 1, SK_LDS = 2, SK_ALL = 3 };
-
-template <int KIND> struct ViewOf;
-template <> struct ViewOf<SK_NONE> { typedef DevGlobal type; };
-template <> struct ViewOf<SK_SPLIT> { typedef DevSplit type; };
-template <> struct ViewOf<SK_LDS> { typedef DevLds type; };
-template <> struct ViewOf<SK_ALL> { typedef DevAll type; };
-
-// The view of a geometry for a kernel of staging kind KIND: staged tables at
-// their LDS copies (`lds`, a workgroup-shared address), the others global.
-template <int KIND>
-__device__ __forceinline__ typename ViewOf<KIND>::type make_view(const Dev &g, const StagePlan &sp,
-                                                                 unsigned char *lds) {
-    typedef typename ViewOf<KIND>::type V;
-    if constexpr (KIND == SK_NONE) {
-        return global_view(g);
-    } else {
-        V d;
-        auto lp = [&](int sec) { return lds + sp.at[sec]; };
-        d.coef = (cptr<3, double>)lp(SEC_COEF);
-        d.hs = (cptr<3, uint32_t>)lp(SEC_HS);
-        d.cell = (cptr<3, Cell>)lp(SEC_CELL);
-        d.univ = (cptr<3, Univ>)lp(SEC_UNIV);
-        d.sigma = (cptr<3, double>)lp(SEC_SIGMA);
-        d.cell_local = (cptr<3, uint32_t>)lp(SEC_LOCAL);
-        if constexpr (KIND == SK_SPLIT) {
-            d.trans = (cptr<1, double>)g.trans;
-            d.adj_off = (cptr<1, uint32_t>)g.adj_off;
-            d.adj = (cptr<1, uint32_t>)g.adj;
-            d.node32 = (cptr<1, Node32>)g.node32;
-            d.node64 = (cptr<1, Node64>)g.node64;
-            d.leaf = (cptr<1, uint32_t>)g.leaf;
-            d.cbox = (cptr<1, float>)g.cbox;
-        } else {
-            d.trans = (cptr<3, double>)lp(SEC_TRANS);
-            d.adj_off = (cptr<3, uint32_t>)lp(SEC_ADJOFF);
-            d.adj = (cptr<3, uint32_t>)lp(SEC_ADJ);
-            if constexpr (KIND == SK_LDS) {
-                d.node32 = (cptr<1, Node32>)g.node32;
-                d.node64 = (cptr<1, Node64>)g.node64;
-                d.leaf = (cptr<1, uint32_t>)g.leaf;
-                d.cbox = (cptr<1, float>)g.cbox;
-            } else {
-                // only the precision mode's own hierarchy is staged; the other
-                // pointer is never read
-                d.node32 = (cptr<3, Node32>)lp(SEC_NODE32);
-                d.node64 = (cptr<3, Node64>)lp(SEC_NODE64);
-                d.leaf = (cptr<3, uint32_t>)lp(SEC_LEAF);
-                d.cbox = (cptr<3, float>)lp(SEC_CBOX);
-            }
-        }
-        view_scalars(d, g);
-        return d;
-    }
-}
-
-// Particle-id sources for the state machine below: a global counter over
-// [0, end) for one geometry, or a workgroup (LDS) counter over one chunk of
-// a batch item.  take() is called by one lane and returns the first of k ids.
-struct GlobalQueue {
-    unsigned long long *ctr;
-    uint64_t end;
-    __device__ __forceinline__ uint64_t take(uint64_t k) const { return atomicAdd(ctr, (unsigned long long)k); }
-};
-
-struct ChunkQueue {
-    unsigned long long *ctr;   // LDS
-    uint64_t first, end;
-    __device__ __forceinline__ uint64_t take(uint64_t k) const {
-        return first + atomicAdd(ctr, (unsigned long long)k);
-    }
-};
-
-// Tail compaction.  Once the queue is empty for every wave of the
-// workgroup, the histories still running are spread thinly over its waves.
-// Every `round` loop trips the waves meet at a barrier; when the live
-// histories fit in fewer waves (and in the LDS buffer), each is written to
-// the buffer at its rank and read back by the lane of that rank, so fewer,
-// fuller waves carry the tail while the emptied ones wait at the barrier.  A
-// history's state moves as a whole, so its results do not depend on the lane
-// that finishes it.
-constexpr int kTailFields = 16;   // 64-bit words per moved history
-constexpr uint32_t kTailRound = 8;
-
-struct TailCfg {
-    uint64_t *buf;   // LDS, kTailFields x cap words (field-major)
-    uint32_t *ctl;   // LDS: [0] waves whose queue is empty, [1 + w] live lanes of wave w
-    uint32_t cap;    // histories the buffer holds; 0 = no compaction
-    uint32_t round;  // loop trips between compactions
-};
-
-// The persistent history loop of one lane (see above); returns when its
-// wave has drained the queue and every lane of the wave is idle (with tail
-// compaction: when no lane of the workgroup has a history left).
-template <int PREC, typename G, typename Queue>
-__device__ __forceinline__ void track_pool(const G &g, const KParams &p, const KOut &o, uint64_t *rep,
-                                           uint32_t *cells, const Queue &queue, Counts &cnt, const TailCfg &tc) {
-    Particle P;
-    P.cell = cells;
-    for (int L = 0; L < GT_MAX_LEVELS; L++) lvl(P, L) = 0;   // hints below read earlier levels
-    P.x = P.y = P.z = P.u = P.v = P.w = P.tau = 0.0;
-    P.depth = 1;
-    P.on_level = -1;
-    P.on_surf = kNone;
-    int mode = M_IDLE;
-    uint64_t local = 0;
-    uint32_t blk = 0;
-    // history state
-    uint64_t h = 0;
-    uint32_t segs = 0, ncoll = 0, attempts = 0;
-    bool recovf = false, birth = false;
-    TallyAcc acc;
-    acc.inst = kNone;
-    acc.lo = acc.hi = 0;
-    // pending search at level sL: after a crossing, surface sforce (sense
-    // sfpos forced) through half-space entry sk; kNone in a descent.  The
-    // local position and universe there follow from the position and the
-    // cells of the levels above, and are recomputed at each search step.
-    int sL = 0;
-    uint32_t sforce = kNone, sk = 0;
-    bool sfpos = false;
-    // wave-uniform pool of particle ids
-    uint64_t pool_next = 0, pool_end = 0;
-    bool drained = false;
-    int end = GT_END_NONE;
-    // tail compaction state (wave-uniform)
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64u), nwaves = blockDim.x / 64u;
-    bool counted = false, in_tail = false;
-    uint32_t titer = 0;
-
-    for (;;) {
-        if (tc.cap) {
-            if (drained && !counted) {
-                counted = true;
-                if (__lane_id() == 0) atomicAdd(&tc.ctl[0], 1u);
-            }
-            if (drained && !in_tail)
-                in_tail = __builtin_amdgcn_readfirstlane(__atomic_load_n(&tc.ctl[0], __ATOMIC_RELAXED)) == nwaves;
-            if (in_tail) {
-                const uint64_t act = __ballot(mode != M_IDLE);
-                if (act == 0 || ++titer >= tc.round) {
-                    titer = 0;
-                    if (__lane_id() == 0) tc.ctl[1 + wave] = (uint32_t)__popcll(act);
-                    __syncthreads();
-                    // (the counts are workgroup-uniform: read them as scalars)
-                    uint32_t A = 0, busy = 0, before = 0;
-                    for (uint32_t w = 0; w < nwaves; w++) {
-                        const uint32_t a = __builtin_amdgcn_readfirstlane(tc.ctl[1 + w]);
-                        A += a;
-                        busy += a ? 1u : 0u;
-                        before += w < wave ? a : 0u;
-                    }
-                    // every wave has read this round's counts before any wave
-                    // can write the next round's
-                    __syncthreads();
-                    if (A == 0) break;
-                    // pack the A live histories into lanes 0..A-1 of the workgroup
-                    // when that frees a wave and the buffer holds them all
-                    if (A <= tc.cap && (A + 63u) / 64u < busy) {
-                        const uint32_t C = tc.cap;
-                        if (mode != M_IDLE) {
-                            tally_flush(rep, acc);
-                            uint64_t *b = tc.buf + before + lane_rank(act);
-                            b[0 * C] = __double_as_longlong(P.x);
-                            b[1 * C] = __double_as_longlong(P.y);
-                            b[2 * C] = __double_as_longlong(P.z);
-                            b[3 * C] = __double_as_longlong(P.u);
-                            b[4 * C] = __double_as_longlong(P.v);
-                            b[5 * C] = __double_as_longlong(P.w);
-                            b[6 * C] = __double_as_longlong(P.tau);
-                            b[7 * C] = local;
-                            b[8 * C] = h;
-                            b[9 * C] = (uint64_t)blk | (uint64_t)segs << 32;
-                            b[10 * C] = (uint64_t)ncoll | (uint64_t)attempts << 32;
-                            b[11 * C] = (uint64_t)sforce | (uint64_t)sk << 32;
-                            const uint32_t fl = (uint32_t)mode | (uint32_t)recovf << 3 | (uint32_t)birth << 4 |
-                                                (uint32_t)sfpos << 5 | (uint32_t)P.depth << 8 |
-                                                (uint32_t)(P.on_level + 1) << 12 | (uint32_t)sL << 16;
-                            b[12 * C] = (uint64_t)P.on_surf | (uint64_t)fl << 32;
-                            for (int L = 0; L < GT_MAX_LEVELS; L += 2)
-                                b[(13 + L / 2) * C] = (uint64_t)lvl(P, L) | (uint64_t)lvl(P, L + 1) << 32;
-                        }
-                        __syncthreads();
-                        if (threadIdx.x < A) {
-                            const uint64_t *b = tc.buf + threadIdx.x;
-                            P.x = __longlong_as_double(b[0 * C]);
-                            P.y = __longlong_as_double(b[1 * C]);
-                            P.z = __longlong_as_double(b[2 * C]);
-                            P.u = __longlong_as_double(b[3 * C]);
-                            P.v = __longlong_as_double(b[4 * C]);
-                            P.w = __longlong_as_double(b[5 * C]);
-                            P.tau = __longlong_as_double(b[6 * C]);
-                            local = b[7 * C];
-                            h = b[8 * C];
-                            blk = (uint32_t)b[9 * C];
-                            segs = (uint32_t)(b[9 * C] >> 32);
-                            ncoll = (uint32_t)b[10 * C];
-                            attempts = (uint32_t)(b[10 * C] >> 32);
-                            sforce = (uint32_t)b[11 * C];
-                            sk = (uint32_t)(b[11 * C] >> 32);
-                            P.on_surf = (uint32_t)b[12 * C];
-                            const uint32_t fl = (uint32_t)(b[12 * C] >> 32);
-                            mode = (int)(fl & 7u);
-                            recovf = (fl >> 3) & 1u;
-                            birth = (fl >> 4) & 1u;
-                            sfpos = (fl >> 5) & 1u;
-                            P.depth = (int)((fl >> 8) & 15u);
-                            P.on_level = (int)((fl >> 12) & 15u) - 1;
-                            sL = (int)((fl >> 16) & 15u);
-                            for (int L = 0; L < GT_MAX_LEVELS; L += 2) {
-                                const uint64_t v = b[(13 + L / 2) * C];
-                                lvl(P, L) = (uint32_t)v;
-                                lvl(P, L + 1) = (uint32_t)(v >> 32);
-                            }
-                        } else {
-                            // no history here any more (all of the old one is in the buffer)
-                            mode = M_IDLE;
-                            P.x = P.y = P.z = P.u = P.v = P.w = P.tau = 0.0;
-                            local = h = 0;
-                            blk = segs = ncoll = attempts = sk = 0;
-                            sforce = P.on_surf = kNone;
-                            recovf = birth = sfpos = false;
-                            P.depth = 1;
-                            P.on_level = -1;
-                            sL = 0;
-                        }
-                        end = GT_END_NONE;
-                    }
-                    continue;
-                }
-            }
-        }
-        // ---- refill idle lanes
-        if (!drained) {
-            uint64_t idle = __ballot(mode == M_IDLE);
-            if ((uint32_t)__popcll(idle) < p.refill_min) idle = 0;
-            while (idle) {
-                if (pool_next == pool_end) {
-                    const int leader = __ffsll((unsigned long long)idle) - 1;
-                    unsigned long long base = 0;
-                    if ((int)__lane_id() == leader) base = queue.take(kChunk);
-                    base = __shfl(base, leader);
-                    if (base >= queue.end) { drained = true; break; }
-                    pool_next = base;
-                    pool_end = min((uint64_t)base + kChunk, queue.end);
-                }
-                const uint64_t avail = pool_end - pool_next;
-                const uint32_t r = lane_rank(idle);
-                if (mode == M_IDLE && r < avail) {
-                    local = pool_next + r;
-                    blk = 0;
-                    h = kFnvOffset;
-                    segs = ncoll = attempts = 0;
-                    recovf = false;
-                    birth = true;
-                    P.on_level = -1;
-                    P.on_surf = kNone;
-                    P.depth = 1;
-                    end = GT_END_NONE;
-                    mode = M_POS;
-                }
-                const uint64_t nidle = (uint64_t)__popcll(idle);
-                pool_next += nidle < avail ? nidle : avail;
-                idle = __ballot(mode == M_IDLE);
-            }
-        }
-        if (__ballot(mode != M_IDLE) == 0) {
-            if (!tc.cap) break;
-            // the queue is empty for this wave: wait for the workgroup's tail
-            // (no lane holds a history: the state is dead)
-            P.x = P.y = P.z = P.u = P.v = P.w = P.tau = 0.0;
-            local = h = 0;
-            blk = segs = ncoll = attempts = sk = 0;
-            sforce = P.on_surf = kNone;
-            recovf = birth = sfpos = false;
-            P.depth = 1;
-            P.on_level = -1;
-            sL = 0;
-            end = GT_END_NONE;
-            __builtin_amdgcn_s_sleep(2);
-            continue;
-        }
-
-        // ---- draw: a birth-position attempt, or a direction attempt and its optical depth
-        if (mode == M_POS || mode == M_DIR) {
-            if (mode == M_POS && p.source == 1) {
-                const uint64_t n1 = p.ray_n1;
-                const uint64_t n2 = (p.n + n1 - 1) / n1;
-                const uint64_t pid = p.first + local;
-                const uint64_t j = pid % n1, k = pid / n1;
-                const double hy = (g.hi[1] - g.lo[1]) / (double)n1;
-                const double hz = (g.hi[2] - g.lo[2]) / (double)n2;
-                P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * 0x1p-30;
-                P.y = g.lo[1] + ((double)j + 0.5) * hy;
-                P.z = g.lo[2] + ((double)k + 0.5) * hz;
-                P.u = 1.0;
-                P.v = 0.0;
-                P.w = 0.0;
-                P.tau = 0.0;
-            } else if (mode == M_POS && attempts >= (uint32_t)kMaxBirthAttempts) {
-                end = GT_END_LOST;
-            } else {
-                double u0, u1, u2;
-                draw_block(p.seed, p.geom_id, p.first + local, blk++, u0, u1, u2);
-                if (mode == M_POS) {
-                    P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * u0;
-                    P.y = g.lo[1] + (g.hi[1] - g.lo[1]) * u1;
-                    P.z = g.lo[2] + (g.hi[2] - g.lo[2]) * u2;
-                    attempts++;
-                } else if (direction_from(u0, u1, P.u, P.v, P.w)) {
-                    P.tau = -series_log(u2);
-                    mode = M_TRACK;
-                }
-            }
-            if (mode == M_POS && end == GT_END_NONE) {
-                sL = 0;
-                sforce = kNone;
-                mode = M_SEARCH;
-            }
-        }
-
-        // ---- one level of find_cell / cross_surface
-        if (mode == M_SEARCH) {
-            // local position and universe at level sL (translations applied
-            // level by level from the global position, as in the descent)
-            double qx = P.x, qy = P.y, qz = P.z;
-            uint32_t su = g.root;
-            for (int L = 0; L < sL; L++) {
-                const uint32_t cl = lvl(P, L);
-                const auto t = g.trans + 4 * (size_t)cl;
-                qx = qx - t[0];
-                qy = qy - t[1];
-                qz = qz - t[2];
-                su = (uint32_t)(-g.cell[cl].fill - 1);
-            }
-            const Univ U = ldv<Univ>(g.univ + su);
-            // guess point for a lattice index; after a crossing it is nudged
-            // along the flight so that it lands on the far side
-            float gx = (float)qx, gy = (float)qy;
-            if (PREC == GT_PREC_MIXED && sforce != kNone && U.hint == (int32_t)kHintSquare) {
-                gx += (float)P.u * 1e-3f / U.inv_px;
-                gy += (float)P.v * 1e-3f / U.inv_py;
-            }
-            // quick candidates first: after a crossing, the cells listed for the
-            // crossed half-space; in a descent, the cell with the same index in
-            // the new universe as the lane had at this level before
-            uint32_t k0, k1, hint = 0;
-            int32_t excl = -1;
-            if (sforce != kNone) {
-                k0 = g.adj_off[sk];
-                k1 = g.adj_off[sk + 1];
-                excl = (int32_t)lvl(P, sL);   // the cell being left
-            } else {
-                const uint32_t loc = g.cell_local[lvl(P, sL)];
-                hint = U.cell0 + loc;
-                k0 = 0;
-                k1 = loc < U.ncell ? 1u : 0u;
-            }
-            int32_t c = -1;
-            for (uint32_t k = k0; k < k1; k++) {
-                const uint32_t d = sforce != kNone ? g.adj[k] : hint;
-                if (contains(g, d, qx, qy, qz, sforce, sfpos)) { c = (int32_t)d; break; }
-            }
-            if (c < 0) c = search<PREC>(g, su, qx, qy, qz, sforce, sfpos, excl, gx, gy);
-            if (c < 0) {
-                if (birth) {
-                    if (sL == 0 && p.source != 1) { cnt.rejected++; mode = M_POS; }
-                    else end = GT_END_LOST;
-                } else {
-                    end = (sforce != kNone && sL == 0) ? GT_END_ESCAPE : GT_END_LOST;
-                }
-            } else {
-                lvl(P, sL) = (uint32_t)c;
-                if (g.cell[c].fill < 0) {
-                    sL++;
-                    sforce = kNone;
-                } else {
-                    P.depth = sL + 1;
-                    if (birth) {
-                        birth = false;
-                        mode = p.source == 1 ? M_TRACK : M_DIR;
-                    } else {
-                        if (segs >= p.max_segs) end = GT_END_SEGCAP;
-                        mode = M_TRACK;
-                    }
-                }
-            }
-        }
-
-        // ---- one segment: distance_to_surface, move, tally, then crossing or collision
-        if (mode == M_TRACK && end == GT_END_NONE) {
-            Nearest nr;
-            nearest_surface(g, P, nr);
-            const double sig = g.sigma[nr.leaf_fill];
-            const double sc = (p.source == 1) ? dinf() : P.tau / sig;
-            const uint32_t inst = nr.inst;
-            const bool boundary = nr.t < sc;
-            if (!boundary && sc == dinf()) {
-                end = GT_END_LOST;
-            } else {
-                double l;
-                if (boundary) {
-                    l = nr.t;
-                    if (p.source != 1) P.tau = P.tau - sig * nr.t;
-                } else {
-                    l = sc;
-                }
-                const double m0 = l * P.u, m1 = l * P.v, m2 = l * P.w;
-                P.x = P.x + m0;
-                P.y = P.y + m1;
-                P.z = P.z + m2;
-                tally_add(rep, acc, inst, l);
-                h = (h ^ ((uint64_t)inst + 1)) * kFnvPrime;
-                if (local < p.rec_k) {
-                    if (segs < p.rec_cap) gstore(o.rec, local * (uint64_t)p.rec_cap + segs, inst);
-                    else recovf = true;
-                }
-                segs++;
-                if (boundary) {
-                    // cross_surface at level nr.level on surface nr.surf (Alg. 8),
-                    // at the local position there of the moved global position
-                    sL = nr.level;
-                    sforce = nr.surf;
-                    sfpos = !nr.pos;
-                    sk = nr.entry;
-                    P.on_level = nr.level;
-                    P.on_surf = nr.surf;
-                    mode = M_SEARCH;
-                } else {
-                    P.on_level = -1;
-                    P.on_surf = kNone;
-                    ncoll++;
-                    if (ncoll >= p.max_coll) end = GT_END_CAP;
-                    else if (segs >= p.max_segs) end = GT_END_SEGCAP;
-                    else mode = M_DIR;
-                }
-            }
-        }
-
-        // ---- history finished: outputs, then the lane is free
-        if (mode != M_IDLE && end != GT_END_NONE) {
-            tally_flush(rep, acc);
-            h ^= (uint64_t)end;
-            if (o.seg_count) gstore(o.seg_count, local, segs);
-            if (o.seq_hash) gstore(o.seq_hash, local, h);
-            if (o.end_code) gstore(o.end_code, local, end);
-            count_end(cnt, end, segs, recovf);
-            mode = M_IDLE;
-        }
-    }
-}
-
-// Dynamic LDS of the persistent kernels: the level columns, the staged
-// tables at byte offset tables_at, then the tail buffer at tail_at.
 // KIND = staging kind of the geometry's plan (see make_view); W = waves per
 // SIMD the register budget is cut for: 4 (up to 1024 lanes per workgroup,
 // 128 registers) or 5 (640 lanes, two workgroups per compute unit, 96
@@ -1369,34 +138,6 @@ __global__ void k_fill_u64(uint64_t *a, uint64_t n, uint64_t v) {
 __global__ void k_fill_i32(int32_t *a, uint64_t n, int32_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         a[i] = v;
-}
-
-// Fold the replicas' limb counters of instance i into the 128-bit
-// fixed-point total (plus the previous total when accumulating), then convert
-// it to cm: high word * 2^-32 + low word * 2^-96.
-__device__ __forceinline__ void fold_tally(const uint64_t *ws, uint64_t *tfx, double *tally, uint64_t n, uint64_t i,
-                                           bool accumulate) {
-    uint64_t lo = accumulate ? tfx[2 * i] : 0, hi = accumulate ? tfx[2 * i + 1] : 0;
-    for (int r = 0; r < kReplicas; r++) {
-        const uint64_t *L = ws + ((size_t)r * n + i) * 4;
-        for (int k = 0; k < 4; k++) {
-            // add L[k] * 2^(32 k) to (hi, lo) modulo 2^128
-            const uint64_t v = L[k];
-            uint64_t add_lo, add_hi;
-            switch (k) {
-            case 0: add_lo = v; add_hi = 0; break;
-            case 1: add_lo = v << 32; add_hi = v >> 32; break;
-            case 2: add_lo = 0; add_hi = v; break;
-            default: add_lo = 0; add_hi = v << 32; break;
-            }
-            const uint64_t nlo = lo + add_lo;
-            hi += add_hi + (nlo < lo ? 1u : 0u);
-            lo = nlo;
-        }
-    }
-    tfx[2 * i] = lo;
-    tfx[2 * i + 1] = hi;
-    if (tally) tally[i] = (double)hi * 0x1p-32 + (double)lo * 0x1p-96;
 }
 
 __global__ void k_finalize(const uint64_t *ws, uint64_t *tfx, double *tally, uint64_t n, int accumulate) {
@@ -1729,27 +470,6 @@ int launch_batch_t(gt_batch *b, hipStream_t st) {
 
 }  // namespace
 
-void fill_kparams(const gt_track_params *p, const gt_geometry *g, KParams &kp, KOut &ko, const gt_track_out *o) {
-    kp.seed = p->seed;
-    kp.first = p->first_particle;
-    kp.n = p->n_particles;
-    kp.geom_id = p->geometry_id;
-    kp.max_coll = p->max_collisions;
-    kp.source = p->source;
-    kp.ray_n1 = p->ray_n1;
-    kp.max_segs = p->max_segments;
-    kp.rec_k = (uint32_t)((uint64_t)p->record_first_k < p->n_particles ? p->record_first_k : p->n_particles);
-    kp.rec_cap = p->record_cap;
-    kp.refill_min = p->refill_min ? p->refill_min : kRefillMin;
-    ko.tally_ws = g->tally_ws;
-    ko.seg_count = o->seg_count;
-    ko.seq_hash = o->seq_hash;
-    ko.end_code = o->end_code;
-    ko.rec = o->rec;
-    ko.counters = o->counters;
-}
-
-unsigned stage_budget() { return kStageBudget; }
 
 void set_kernel_events(void *start, void *stop) {
     t_ev_start = (hipEvent_t)start;

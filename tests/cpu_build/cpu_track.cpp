@@ -1,0 +1,132 @@
+// CPU build of the tracker's per-lane state machine (test infrastructure):
+// gt_device.h compiled for the host with one-lane wave stand-ins, driven
+// the way the persistent and batched kernels drive it, on geometries made
+// by the real host preprocessor.  Tables are read in place (staging kind 0)
+// or from a copy in an emulated LDS buffer made from the staging plan.
+#include <vector>
+
+#include "gt_internal.h"
+#include "shim.h"
+#include "gt_device.h"
+
+namespace gt {
+namespace {
+
+constexpr size_t kLdsEmuBytes = 160 * 1024;
+thread_local unsigned char g_lds[kLdsEmuBytes];
+
+template <int PREC, int KIND, typename Queue>
+void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut &o, const Queue &q, uint64_t *counts) {
+    static thread_local uint32_t cells[GT_MAX_LEVELS];
+    static thread_local uint32_t ctl[1 + kBlockP / 64];
+    blockDim.x = 1;
+    threadIdx.x = 0;
+    if (KIND != SK_NONE) stage_copy(sp, (const unsigned char *)dev.coef, g_lds);
+    const auto v = make_view<KIND>(dev, sp, g_lds);
+    KParams p = p0;
+    p.refill_min = 1;   // a one-lane wave refills as soon as its lane is idle
+    Counts cnt = {0, 0, 0, 0, 0, 0, 0};
+    const TailCfg tc = {nullptr, ctl, 0, kTailRound};
+    track_pool<PREC>(v, p, o, o.tally_ws, cells, q, cnt, tc);
+    counts[GT_CNT_ESCAPED] += cnt.escaped;
+    counts[GT_CNT_CAPPED] += cnt.capped;
+    counts[GT_CNT_LOST] += cnt.lost;
+    counts[GT_CNT_SEGCAP] += cnt.segcap;
+    counts[GT_CNT_REC_OVERFLOW] += cnt.recovf;
+    counts[GT_CNT_SEGMENTS] += cnt.segments;
+    counts[GT_CNT_REJECTED] += cnt.rejected;
+}
+
+template <int PREC, typename Queue>
+int run_kind(int kind, const Dev &dev, const StagePlan &sp, const KParams &p, const KOut &o, const Queue &q,
+             uint64_t *counts) {
+    if (kind != SK_NONE && sp.total > sizeof(g_lds)) return GT_ECAPACITY;
+    switch (kind) {
+    case SK_ALL: run_lane<PREC, SK_ALL>(dev, sp, p, o, q, counts); break;
+    case SK_LDS: run_lane<PREC, SK_LDS>(dev, sp, p, o, q, counts); break;
+    case SK_SPLIT: run_lane<PREC, SK_SPLIT>(dev, sp, p, o, q, counts); break;
+    default: run_lane<PREC, SK_NONE>(dev, sp, p, o, q, counts); break;
+    }
+    return GT_OK;
+}
+
+void fold_all(const uint64_t *ws, uint64_t *tfx, double *tally, uint64_t n, bool acc) {
+    for (uint64_t i = 0; i < n; i++) fold_tally(ws, tfx, tally, n, i, acc);
+}
+
+}  // namespace
+}  // namespace gt
+
+using namespace gt;
+
+// gt_track on the CPU: the histories of `p` through one lane with the
+// geometry's tables held the way staging kind `kind` holds them (0..3; the
+// geometry's own kind or 0).  Outputs as gt_track's, in host memory.
+extern "C" int cpu_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, int kind) {
+    int rc = check_track_args(g, p, o);
+    if (rc) return rc;
+    const StagePlan &sp = g->stage[p->precision];
+    if (kind != SK_NONE && kind != (int)sp.kind) return set_error("cpu_track: the geometry has another staging kind"), GT_EINVAL;
+    KParams kp;
+    KOut ko;
+    fill_kparams(p, g, kp, ko, o);
+    std::memset(g->tally_ws, 0, (size_t)8 * 4 * 8 * g->n_inst);
+    std::memset(o->counters, 0, 8 * sizeof(uint64_t));
+    if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
+    unsigned long long ctr = 0;
+    const GlobalQueue q = {&ctr, kp.n};
+    rc = p->precision == GT_PREC_MIXED ? run_kind<GT_PREC_MIXED>(kind, g->dev, sp, kp, ko, q, o->counters)
+                                       : run_kind<GT_PREC_FP64>(kind, g->dev, sp, kp, ko, q, o->counters);
+    if (rc) return rc;
+    fold_all(g->tally_ws, o->tally_fx, o->tally, g->n_inst, (p->flags & GT_FLAG_ACCUMULATE) != 0);
+    return GT_OK;
+}
+
+// gt_track_batch on the CPU: gt_batch_create's descriptors (in host memory)
+// executed the way gt_batch_launch executes them -- the fill list, then the
+// chunk groups by staging kind (3, 2, 1, 0) each chunk through one lane with
+// its item's tables, then the finalize list.  *n_chunks gets the number of
+// chunks run.
+extern "C" int cpu_track_batch(const gt_batch_item *items, uint32_t n_items, const gt_tuning *tuning,
+                               uint32_t *n_chunks) {
+    gt_batch *b = nullptr;
+    int rc = gt_batch_create(items, n_items, tuning, &b);
+    if (rc) return rc;
+    for (uint32_t f = 0; f < b->n_fill; f++) {
+        const FillRange &r = b->d_fill[f];
+        for (uint64_t i = 0; i < r.count; i++) {
+            if (r.bytes == 8) ((uint64_t *)r.ptr)[i] = r.value;
+            else ((uint32_t *)r.ptr)[i] = (uint32_t)r.value;
+        }
+    }
+    uint32_t first = 0, ran = 0;
+    for (int kind = 3; kind >= 0 && !rc; kind--) {
+        for (uint32_t c = first; c < first + b->n_kind[kind] && !rc; c++) {
+            const BatchChunk &ch = b->d_chunks[c];
+            if (ch.item >= b->n_items) {
+                set_error("cpu_track_batch: chunk %u names item %u", c, ch.item);
+                rc = GT_EINVAL;
+                break;
+            }
+            const BatchItem &it = b->d_items[ch.item];
+            unsigned long long pool = 0;
+            const ChunkQueue q = {&pool, ch.first, ch.first + ch.count};
+            rc = b->precision == GT_PREC_MIXED ? run_kind<GT_PREC_MIXED>(kind, it.dev, it.plan, it.p, it.o, q, it.o.counters)
+                                               : run_kind<GT_PREC_FP64>(kind, it.dev, it.plan, it.p, it.o, q, it.o.counters);
+            ran++;
+        }
+        first += b->n_kind[kind];
+    }
+    if (!rc && (first != b->n_chunks || ran != b->n_chunks)) {
+        set_error("cpu_track_batch: chunk groups do not cover the chunks");
+        rc = GT_EINVAL;
+    }
+    if (!rc)
+        for (uint32_t i = 0; i < b->n_items; i++) {
+            const FinalizeItem &f = b->d_fin[i];
+            fold_all(f.ws, f.tfx, f.tally, f.n_inst, f.accumulate != 0);
+        }
+    if (n_chunks) *n_chunks = ran;
+    gt_batch_destroy(b);
+    return rc;
+}

@@ -1,0 +1,205 @@
+"""The tracker's device functions compiled for the host (one-lane waves;
+tests/cpu_build) against the oracle, bit for bit, on a CPU.  This covers the
+per-lane logic of the HIP path -- birth sampling, searches with candidate
+lists, hints and hierarchies, slab pairs, distances, crossings, tallies,
+recording -- for every table staging kind, and the batched launch's
+descriptors (fills, chunk groups, finalize), without a GPU.  The wave-level
+scheduling (refill, tail compaction) is covered by the GPU tests.  A second
+run under AddressSanitizer checks that no table or output is read or written
+out of bounds."""
+
+import ctypes as C
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_13849_amd import gt, synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "cpu_build"))
+import build as cpu_build  # noqa: E402
+
+
+class HostLib:
+    """The CPU build loaded with the binding's structures (a second ctypes
+    handle; the GPU library is not touched)."""
+
+    def __init__(self, path):
+        L = C.CDLL(path)
+        vp = C.c_void_p
+        L.gt_geometry_create.argtypes = [C.POINTER(gt._Flat), C.POINTER(vp)]
+        L.gt_geometry_info.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)]
+        L.gt_geometry_staging.argtypes = [vp, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+        L.gt_geometry_destroy.argtypes = [vp]
+        L.gt_geometry_destroy.restype = None
+        L.gt_last_error.restype = C.c_char_p
+        L.cpu_track.argtypes = [vp, C.POINTER(gt._Params), C.POINTER(gt._Out), C.c_int]
+        L.cpu_track_batch.argtypes = [C.POINTER(gt._BatchItem), C.c_uint32, C.POINTER(gt._Tuning),
+                                      C.POINTER(C.c_uint32)]
+        self.L = L
+
+    def check(self, rc):
+        if rc != 0:
+            raise gt.GtError(rc, (self.L.gt_last_error() or b"").decode())
+
+    def geometry(self, fg):
+        keep = []
+        f = gt.flat_struct(fg, keep)
+        h = C.c_void_p()
+        self.check(self.L.gt_geometry_create(C.byref(f), C.byref(h)))
+        ni, md, nb = C.c_uint64(), C.c_uint32(), C.c_uint64()
+        self.check(self.L.gt_geometry_info(h, C.byref(ni), C.byref(md), C.byref(nb)))
+        return h.value, int(ni.value)
+
+    def staging(self, h, prec):
+        k, b = C.c_uint32(), C.c_uint32()
+        self.check(self.L.gt_geometry_staging(h, prec, C.byref(k), C.byref(b)))
+        return int(k.value)
+
+
+class Outs:
+    def __init__(self, n_inst, n, k, cap):
+        self.a = dict(tally_fx=np.zeros((n_inst, 2), np.uint64), tally=np.zeros(n_inst),
+                      seg_count=np.zeros(n, np.uint32), seq_hash=np.zeros(n, np.uint64),
+                      end_code=np.zeros(n, np.uint8), rec=np.full((max(k, 1), max(cap, 1)), -1, np.int32),
+                      counters=np.zeros(8, np.uint64))
+
+    def struct(self):
+        a = self.a
+        return gt._Out(tally_fx=a["tally_fx"].ctypes.data, tally=a["tally"].ctypes.data,
+                       seg_count=a["seg_count"].ctypes.data, seq_hash=a["seq_hash"].ctypes.data,
+                       end_code=a["end_code"].ctypes.data, rec=a["rec"].ctypes.data,
+                       counters=a["counters"].ctypes.data)
+
+
+def same(a, o, k):
+    assert np.array_equal(a["seq_hash"], o.seq_hash)
+    assert np.array_equal(a["seg_count"], o.seg_count)
+    assert np.array_equal(a["end_code"], o.end_code)
+    assert np.array_equal(a["tally_fx"], o.tally_fx)
+    assert np.array_equal(a["tally"], o.tally_fxd)
+    if k:
+        assert np.array_equal(a["rec"], o.rec)
+    names = ("escaped", "capped", "lost", "segcap", "rec_overflow", "segments", "rejected")
+    assert {n: int(v) for n, v in zip(names, a["counters"])} == {n: o.counters[n] for n in names}
+
+
+@pytest.fixture(scope="module")
+def host():
+    try:
+        return HostLib(cpu_build.build())
+    except RuntimeError as e:
+        pytest.skip(str(e))
+
+
+GEOMS = [("cfg", 1), ("cfg", 2), ("cfg", 4), ("fn", "sphere"), ("batch", 3), ("batch", 5), ("batch", 41),
+         ("batch", 57), ("batch", 2), ("batch", 63)]
+
+
+def make(what, k):
+    if what == "cfg":
+        return synth.make_config(k), dict(seed=synth.particle_seed(k), geometry_id=k)
+    if what == "fn":
+        return getattr(synth, k)(), dict(seed=77, geometry_id=9)
+    fg, _ = synth.batch_item(k)
+    return fg, dict(seed=synth.batch_particle_seed(k), geometry_id=synth.batch_geometry_id(k))
+
+
+@pytest.mark.parametrize("what,k", GEOMS, ids=["%s%s" % g for g in GEOMS])
+def test_cpu_build_matches_oracle(host, what, k):
+    """Every staging kind the geometry can be held in (its own and all
+    global), both precisions, 400 histories with recorded sequences."""
+    fg, kw = make(what, k)
+    h, ni = host.geometry(fg)
+    n, rk, cap = 400, 30, 48
+    o = oracle.track(oracle.OracleGeometry(fg), oracle.TrackParams(n_particles=n, record_first_k=rk,
+                                                                    record_cap=cap, **kw), n_threads=4)
+    for prec in (gt.PREC_FP64, gt.PREC_MIXED):
+        for kind in sorted({0, host.staging(h, prec)}):
+            out = Outs(ni, n, rk, cap)
+            prm = gt._params(kw["seed"], n, geometry_id=kw["geometry_id"], precision=prec, record_first_k=rk,
+                             record_cap=cap)
+            host.check(host.L.cpu_track(h, C.byref(prm), C.byref(out.struct()), kind))
+            same(out.a, o, rk)
+    host.L.gt_geometry_destroy(h)
+
+
+def test_cpu_build_covers_every_staging_kind(host):
+    kinds = set()
+    for what, k in GEOMS:
+        fg, _ = make(what, k)
+        h, _ = host.geometry(fg)
+        kinds.add(host.staging(h, gt.PREC_MIXED))
+        host.L.gt_geometry_destroy(h)
+    assert kinds == {0, 1, 2, 3}
+
+
+def batch_run(host, items_spec, prec, chunk):
+    arr = (gt._BatchItem * len(items_spec))()
+    outs, want, hs = [], [], []
+    for i, (j, n, staging) in enumerate(items_spec):
+        fg, kw = make("batch", j)
+        h, ni = host.geometry(fg)
+        hs.append(h)
+        out = Outs(ni, n, 20, 32)
+        outs.append(out)
+        arr[i].geometry = h
+        arr[i].params = gt._params(kw["seed"], n, geometry_id=kw["geometry_id"], precision=prec, record_first_k=20,
+                                   record_cap=32, staging=staging)
+        arr[i].out = out.struct()
+        want.append(oracle.track(oracle.OracleGeometry(fg), oracle.TrackParams(n_particles=n, record_first_k=20,
+                                                                                 record_cap=32, **kw), n_threads=4))
+    ran = C.c_uint32()
+    host.check(host.L.cpu_track_batch(arr, len(items_spec), C.byref(gt._Tuning(0, 0, chunk)), C.byref(ran)))
+    for out, o in zip(outs, want):
+        same(out.a, o, 20)
+    for h in hs:
+        host.L.gt_geometry_destroy(h)
+    return ran.value
+
+
+@pytest.mark.parametrize("prec", [gt.PREC_FP64, gt.PREC_MIXED])
+def test_cpu_batch_descriptors(host, prec):
+    """A batch of items of every staging kind (and some forced global), with
+    small ragged chunks: the chunk groups by staging kind cover every chunk
+    exactly once, and every item's outputs equal the oracle's."""
+    spec = [(57, 700, True), (3, 500, True), (5, 450, True), (2, 380, True), (41, 333, False), (63, 300, True)]
+    ran = batch_run(host, spec, prec, 97)
+    assert ran == sum((n + 96) // 97 for _, n, _ in spec)
+
+
+def test_cpu_build_under_address_sanitizer():
+    """The same per-lane logic and batch planner with AddressSanitizer, in a
+    child process (the sanitizer runtime must be loaded first)."""
+    try:
+        lib = cpu_build.build(asan=True)
+    except RuntimeError as e:
+        pytest.skip(str(e))
+    rt = cpu_build.asan_runtime()
+    if rt is None:
+        pytest.skip("no AddressSanitizer runtime")
+    code = r"""
+import sys, ctypes as C
+sys.path.insert(0, %r); sys.path.insert(0, %r)
+import test_cpu_build as t
+host = t.HostLib(%r)
+for what, k in [("cfg", 2), ("batch", 3), ("batch", 5), ("batch", 2)]:
+    fg, kw = t.make(what, k)
+    h, ni = host.geometry(fg)
+    for prec in (0, 1):
+        for kind in sorted({0, host.staging(h, prec)}):
+            out = t.Outs(ni, 200, 10, 16)
+            prm = t.gt._params(kw["seed"], 200, geometry_id=kw["geometry_id"], precision=prec, record_first_k=10,
+                               record_cap=16)
+            host.check(host.L.cpu_track(h, C.byref(prm), C.byref(out.struct()), kind))
+    host.L.gt_geometry_destroy(h)
+t.batch_run(host, [(57, 300, True), (5, 200, True), (41, 150, False)], 1, 64)
+print("asan clean")
+""" % (os.path.dirname(HERE), HERE, lib)
+    env = dict(os.environ, LD_PRELOAD=rt, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0 and "asan clean" in r.stdout, (r.stdout[-2000:] + r.stderr[-4000:])
