@@ -765,12 +765,16 @@ __device__ void run_history(const G &g, const KParams &p, const KOut &o, uint64_
 // per-lane rank, one global atomic per 64 ids), so a wave no longer waits
 // for its longest history.  Per loop trip every lane takes at most one of
 // each step -- draw one random block (a birth position or a direction
-// attempt with its optical depth), search one level, one segment -- and
-// each step has one call site, so lanes at different points of their
-// histories share one instruction stream per step.
+// attempt with its optical depth), search up to kSearchLevels levels, one
+// segment -- and each step has one call site, so lanes at different points
+// of their histories share one instruction stream per step.
 enum Mode : int { M_IDLE = 0, M_POS = 1, M_DIR = 2, M_SEARCH = 3, M_TRACK = 4 };
 
 constexpr uint32_t kChunk = 64;
+// Search levels a lane may take per loop trip: two lets a crossing of a
+// lattice cell and the descent into the pin below it finish in one trip, so
+// the lane still tracks a segment in that trip.
+constexpr int kSearchLevels = 2;
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -1111,8 +1115,8 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
             }
         }
 
-        // ---- one level of find_cell / cross_surface
-        if (mode == M_SEARCH) {
+        // ---- up to kSearchLevels levels of find_cell / cross_surface
+        for (int sn = 0; sn < kSearchLevels && mode == M_SEARCH && end == GT_END_NONE; sn++) {
             // local position and universe at level sL (translations applied
             // level by level from the global position, as in the descent)
             double qx = P.x, qy = P.y, qz = P.z;
