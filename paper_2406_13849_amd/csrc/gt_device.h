@@ -261,37 +261,38 @@ __device__ __forceinline__ double plane_distance(uint32_t type, CP c, bool pos, 
 
 // The same for a cylinder or sphere: textbook cancellation-free roots;
 // `on` marks the surface just crossed (only the far root can be hit).
+// Written without branches: every case's operands are formed, and the one
+// division takes those of the case that applies, so the quotient is the one
+// the case-by-case formula gives (lanes of a wave often take different cases).
 template <typename CP>
 __device__ __forceinline__ double quad_distance(uint32_t type, CP c, bool pos, double qx, double qy,
                                                 double qz, double u, double v, double w, bool on) {
-    double a, b;
-    const double dx = qx - c[0], dy = qy - c[1];
-    if (type == ST_CZ) {
-        a = u * u + v * v;
-        b = dx * u + dy * v;
-    } else {
-        const double dz = qz - c[2];
-        a = (u * u + v * v) + w * w;
-        b = (dx * u + dy * v) + dz * w;
-    }
-    if (a == 0.0) return dinf();
-    double t;
+    const bool cyl = type == ST_CZ;
+    const double c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
+    const double dx = qx - c0, dy = qy - c1, dz = qz - c2;
+    const double a2 = u * u + v * v, b2 = dx * u + dy * v, r2 = dx * dx + dy * dy;
+    const double a = cyl ? a2 : a2 + w * w;
+    const double b = cyl ? b2 : b2 + dz * w;
+    const double cc = cyl ? r2 - c2 : (r2 + dz * dz) - c3;
+    const double disc = b * b - a * cc;
+    const double q = sqrt(disc > 0.0 ? disc : 0.0);
+    double num, den;
+    bool hit;
     if (on) {
-        if (!(!pos && b < 0.0)) return dinf();
-        t = (-2.0 * b) / a;
+        hit = !pos && b < 0.0;
+        num = -2.0 * b;
+        den = a;
+    } else if (!pos) {
+        hit = disc > 0.0;
+        num = (b <= 0.0) ? q - b : -cc;
+        den = (b <= 0.0) ? a : b + q;
     } else {
-        const double cc = quad_value(type, c, qx, qy, qz);
-        const double disc = b * b - a * cc;
-        if (!(disc > 0.0)) return dinf();
-        const double q = sqrt(disc);
-        if (!pos) {
-            t = (b <= 0.0) ? (q - b) / a : (-cc) / (b + q);
-        } else {
-            if (!(b < 0.0)) return dinf();
-            t = cc / (q - b);
-        }
+        hit = disc > 0.0 && b < 0.0;
+        num = cc;
+        den = q - b;
     }
-    return (t > 0.0) ? t : 0.0;
+    const double t = num / den;
+    return (hit && a != 0.0) ? ((t > 0.0) ? t : 0.0) : dinf();
 }
 
 // ------------------------------------------------------------------ search
@@ -483,16 +484,16 @@ __device__ __forceinline__ void nearest_surface(const G &g, const Particle &P, N
         for (uint32_t k = 0; k < npair2; k += 2) {
             // a slab pair: the shared denominator picks the one plane that can be
             // reached (the negative-side one when it is positive); the other
-            // would give no hit
-            const uint32_t h0 = hs[k];
+            // would give no hit.  No branches: a plane that cannot be hit, or was
+            // just crossed, gets +inf.
+            const uint32_t h0 = hs[k], h1 = hs[k + 1];
             const double den = plane_den(h0 & 7u, g.coef + 4 * (size_t)(h0 >> 4), P.u, P.v, P.w);
-            if (den == 0.0) continue;
             const uint32_t kk = den > 0.0 ? k : k + 1;
-            const uint32_t h = den > 0.0 ? h0 : hs[k + 1];
+            const uint32_t h = den > 0.0 ? h0 : h1;
             const uint32_t s = h >> 4;
-            if (P.on_level == L && P.on_surf == s) continue;   // a plane just crossed is not hit again
             const double t = (-plane_value(h & 7u, g.coef + 4 * (size_t)s, qx, qy, qz)) / den;
-            const double d = (t > 0.0) ? t : 0.0;
+            const bool skip = den == 0.0 || (P.on_level == L && P.on_surf == s);
+            const double d = skip ? dinf() : ((t > 0.0) ? t : 0.0);
             if (d < r.t || (d == r.t && d != dinf() && L == r.level && s < r.surf)) {
                 r.t = d;
                 r.level = L;
