@@ -237,7 +237,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the tracker has no multi-GPU path "
-              "(histories shard by particle-id range; see the design notes)", file=sys.stderr)
+              "(histories would shard across GPUs by particle-id range; only the one-GPU path is built)", file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)

@@ -92,6 +92,9 @@ extern "C" {
                                           global memory even when they fit in LDS           */
 #define GT_FLAG_NO_TAIL_COMPACTION 8u  /* persistent schedule: once the queue is empty, do not
                                           pack the remaining histories into fewer waves      */
+#define GT_FLAG_NO_TALLY_CACHE 16u     /* persistent schedule: flush a lane's tally partial sum
+                                          at every change of instance instead of keeping up
+                                          to three more in an LDS cache (speed only)         */
 
 typedef struct gt_geometry gt_geometry;   /* opaque; owns its device tables */
 

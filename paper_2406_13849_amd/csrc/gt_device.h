@@ -625,6 +625,69 @@ __device__ __forceinline__ void tally_add(uint64_t *rep, TallyAcc &a, uint32_t i
     }
 }
 
+// A lane's recent-instance cache in LDS for the persistent schedule.  The
+// counters' atomics are carried out beyond the L2, and at two or more per
+// contribution their stream limits the tracker; a particle often returns to
+// an instance it left a few segments earlier, so each lane keeps up to k
+// more 128-bit partial sums (besides the one in registers) and flushes one
+// only when it is evicted (round robin) or at the end.  Sums are integers,
+// so grouping contributions differently leaves the totals unchanged.
+struct TallyCache {
+    uint64_t *lo, *hi;   // LDS: entry e of this lane at [e * stride]
+    uint32_t *tag;       // instance of each entry, kNone when empty
+    uint32_t k, stride;
+};
+
+constexpr uint32_t kTallyCacheMax = 3;     // entries per lane at most
+constexpr uint32_t kTallyCacheEntry = 20;  // LDS bytes per entry: two 64-bit words and a tag
+
+// The cache of k entries per lane at byte offset `at` of the dynamic LDS:
+// all low words, then all high words, then all tags, lane-interleaved.
+__device__ __forceinline__ TallyCache tally_cache(unsigned char *lds, uint32_t at, uint32_t k) {
+    uint64_t *lo = (uint64_t *)(lds + at);
+    const size_t n = (size_t)k * blockDim.x;
+    return TallyCache{lo + threadIdx.x, lo + n + threadIdx.x, (uint32_t *)(lo + 2 * n) + threadIdx.x, k, blockDim.x};
+}
+
+__device__ __forceinline__ void tally_add_cached(uint64_t *rep, TallyAcc &a, const TallyCache &c, uint32_t &rr,
+                                                 uint32_t inst, double l) {
+    const double v = l * 0x1p32;
+    const double fl = floor(v);
+    const double fr = v - fl;
+    uint64_t hi = (uint64_t)fl;
+    uint64_t lo = (uint64_t)(fr * 0x1p64);
+    if (inst != a.inst) {
+        uint32_t j = kNone;
+        for (uint32_t e = 0; e < c.k; e++)
+            if (c.tag[e * c.stride] == inst) j = e;
+        const uint32_t slot = j != kNone ? j : rr;
+        const size_t at = (size_t)slot * c.stride;
+        TallyAcc old;
+        old.inst = c.tag[at];
+        old.lo = c.lo[at];
+        old.hi = c.hi[at];
+        c.tag[at] = a.inst;
+        c.lo[at] = a.lo;
+        c.hi[at] = a.hi;
+        if (j != kNone) {
+            // a hit: continue that partial sum in registers
+            const uint64_t nlo = old.lo + lo;
+            hi = old.hi + hi + ((nlo < old.lo) ? 1u : 0u);
+            lo = nlo;
+        } else {
+            rr = rr + 1 == c.k ? 0u : rr + 1;
+            tally_flush(rep, old);
+        }
+        a.inst = inst;
+        a.lo = lo;
+        a.hi = hi;
+    } else {
+        const uint64_t nlo = a.lo + lo;
+        a.hi += hi + ((nlo < a.lo) ? 1u : 0u);
+        a.lo = nlo;
+    }
+}
+
 struct Counts {
     uint32_t escaped, capped, lost, segcap, recovf, rejected;
     uint64_t segments;
@@ -891,7 +954,8 @@ struct TailCfg {
 // compaction: when no lane of the workgroup has a history left).
 template <int PREC, typename G, typename Queue>
 __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const KOut &o, uint64_t *rep,
-                                           uint32_t *cells, const Queue &queue, Counts &cnt, const TailCfg &tc) {
+                                           uint32_t *cells, const Queue &queue, Counts &cnt, const TailCfg &tc,
+                                           const TallyCache &tcache) {
     Particle P;
     P.cell = cells;
     for (int L = 0; L < GT_MAX_LEVELS; L++) lvl(P, L) = 0;   // hints below read earlier levels
@@ -909,6 +973,8 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
     TallyAcc acc;
     acc.inst = kNone;
     acc.lo = acc.hi = 0;
+    uint32_t rr = 0;   // next tally-cache entry to evict
+    for (uint32_t e = 0; e < tcache.k; e++) tcache.tag[e * tcache.stride] = kNone;
     // pending search at level sL: after a crossing, surface sforce (sense
     // sfpos forced) through half-space entry sk; kNone in a descent.  The
     // local position and universe there follow from the position and the
@@ -956,7 +1022,7 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
                     if (A <= tc.cap && (A + 63u) / 64u < busy) {
                         const uint32_t C = tc.cap;
                         if (mode != M_IDLE) {
-                            tally_flush(rep, acc);
+                            // (the tally accumulator and cache stay with the lane)
                             uint64_t *b = tc.buf + before + lane_rank(act);
                             b[0 * C] = __double_as_longlong(P.x);
                             b[1 * C] = __double_as_longlong(P.y);
@@ -1206,7 +1272,8 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
                 P.x = P.x + m0;
                 P.y = P.y + m1;
                 P.z = P.z + m2;
-                tally_add(rep, acc, inst, l);
+                if (tcache.k) tally_add_cached(rep, acc, tcache, rr, inst, l);
+                else tally_add(rep, acc, inst, l);
                 h = (h ^ ((uint64_t)inst + 1)) * kFnvPrime;
                 if (local < p.rec_k) {
                     if (segs < p.rec_cap) gstore(o.rec, local * (uint64_t)p.rec_cap + segs, inst);
@@ -1236,7 +1303,6 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
 
         // ---- history finished: outputs, then the lane is free
         if (mode != M_IDLE && end != GT_END_NONE) {
-            tally_flush(rep, acc);
             h ^= (uint64_t)end;
             if (o.seg_count) gstore(o.seg_count, local, segs);
             if (o.seq_hash) gstore(o.seq_hash, local, h);
@@ -1244,6 +1310,15 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
             count_end(cnt, end, segs, recovf);
             mode = M_IDLE;
         }
+    }
+    // the lane's partial tally sums
+    tally_flush(rep, acc);
+    for (uint32_t e = 0; e < tcache.k; e++) {
+        TallyAcc c;
+        c.inst = tcache.tag[e * tcache.stride];
+        c.lo = tcache.lo[e * tcache.stride];
+        c.hi = tcache.hi[e * tcache.stride];
+        tally_flush(rep, c);
     }
 }
 

@@ -200,6 +200,7 @@ struct gt_batch {
     unsigned long long *d_queue;        // one counter per staging kind
     uint32_t lds_bytes[4];              // staged tables' LDS bytes per kind (largest item)
     bool tail;                          // tail compaction on
+    bool cache;                         // per-lane tally cache on
 };
 
 namespace gt {

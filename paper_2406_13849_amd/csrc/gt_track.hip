@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(kBlock) k_track(Dev g0, KParams p, KOut o) {
 template <int PREC, int KIND, int W>
 __global__ void __launch_bounds__(W == 5 ? 640 : kBlockP) __attribute__((amdgpu_waves_per_eu(W)))
 k_track_persistent(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict__ lr, uint32_t tables_at,
-                   uint32_t tail_at, uint32_t tail_cap, uint32_t tail_round) {
+                   uint32_t tail_at, uint32_t tail_cap, uint32_t tail_round, uint32_t cache_at, uint32_t cache_k) {
     __shared__ uint32_t ctl[1 + kBlockP / 64];
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_dyn[];
     uint32_t *cells = (uint32_t *)lds_dyn;   // the cell of each level, one column per lane
@@ -72,7 +72,8 @@ k_track_persistent(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict_
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     const GlobalQueue q = {(unsigned long long *)&o.counters[7], p.n};
     const TailCfg tc = {(uint64_t *)(lds_dyn + tail_at), ctl, tail_cap, tail_round};
-    track_pool<PREC>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc);
+    const TallyCache tcache = tally_cache(lds_dyn, cache_at, cache_k);
+    track_pool<PREC>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc, tcache);
     add_counts(cnt, o.counters);
 }
 
@@ -91,7 +92,7 @@ k_track_batch(const BatchItem *__restrict__ items,
                                                          const BatchChunk *__restrict__ chunks,
                                                          uint32_t n_chunks, unsigned long long *queue,
                                                          uint32_t tables_at, uint32_t tail_at, uint32_t tail_cap,
-                                                         uint32_t tail_round) {
+                                                         uint32_t tail_round, uint32_t cache_at, uint32_t cache_k) {
     __shared__ uint32_t ctl[1 + kBlockP / 64];
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_dyn[];
     __shared__ uint32_t s_chunk;
@@ -99,6 +100,7 @@ k_track_batch(const BatchItem *__restrict__ items,
     uint32_t *cells = (uint32_t *)lds_dyn;   // the cell of each level, one column per lane
     unsigned char *lds_tables = lds_dyn + tables_at;
     const TailCfg tc = {(uint64_t *)(lds_dyn + tail_at), ctl, tail_cap, tail_round};
+    const TallyCache tcache = tally_cache(lds_dyn, cache_at, cache_k);
     // the descriptors are read-only for the whole launch: their fields are
     // read where needed (scalar loads the compiler may repeat) rather than
     // carried from chunk to chunk in registers
@@ -123,7 +125,7 @@ k_track_batch(const BatchItem *__restrict__ items,
         uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
         Counts cnt = {0, 0, 0, 0, 0, 0, 0};
         const ChunkQueue q = {&s_pool, first, first + count};
-        track_pool<PREC>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc);
+        track_pool<PREC>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc, tcache);
         add_counts(cnt, o.counters);
         __syncthreads();
     }
@@ -302,13 +304,14 @@ int allow_dynamic_lds(const void *kernel, unsigned bytes) {
 // buffer, as large as the workgroup's share of the compute unit's LDS allows
 // without lowering the number of resident workgroups.
 struct LdsPlan {
-    unsigned dyn, tables_at, tail_at, tail_cap;
+    unsigned dyn, tables_at, tail_at, tail_cap, cache_at, cache_k;
     int blocks;
 };
 
 constexpr unsigned kLdsPerCU = 160 * 1024;
 
-int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail, int device, LdsPlan &lp) {
+int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail, bool cache, int device,
+                    LdsPlan &lp) {
     hipFuncAttributes fa;
     int rc = hip_check(hipFuncGetAttributes(&fa, kern), "hipFuncGetAttributes");
     if (rc) return rc;
@@ -317,7 +320,7 @@ int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail
         return set_error("staged tables exceed the LDS"), GT_ECAPACITY;
     rc = allow_dynamic_lds(kern, kLdsPerCU - stat);
     if (rc) return rc;
-    // dynamic LDS: level columns, staged tables, tail buffer
+    // dynamic LDS: level columns, staged tables, tally cache, tail buffer
     const unsigned tables_at = (GT_MAX_LEVELS * 4u * block + 15u) & ~15u;
     const unsigned base = tables_at + ((tables + 15u) & ~15u);
     int blocks = 0;
@@ -327,25 +330,34 @@ int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail
     rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
     if (rc) return rc;
     const unsigned per = (unsigned)std::max(1, blocks / std::max(cus, 1));
+    // what is left of the workgroup's share of the compute unit's LDS (the
+    // share that keeps `per` workgroups resident)
+    long avail = (long)(kLdsPerCU / per) - (long)stat - (long)base - 512;
+    unsigned ck = 0;
+    if (cache && avail > 0) ck = std::min<unsigned>(kTallyCacheMax, (unsigned)(avail / (kTallyCacheEntry * block)));
+    const unsigned cache_bytes = (ck * kTallyCacheEntry * block + 15u) & ~15u;
+    avail -= (long)cache_bytes;
+    const unsigned tail_at = base + cache_bytes;
     unsigned cap = 0;
     if (tail && block > 64) {
-        const long avail = (long)(kLdsPerCU / per) - (long)stat - (long)base - 512;
         if (avail > 0) cap = std::min<unsigned>((unsigned)(avail / (kTailFields * 8)), block);
         if (cap < 64) cap = 0;
     }
-    unsigned dyn = base + cap * kTailFields * 8;
-    if (cap) {
+    unsigned dyn = tail_at + cap * kTailFields * 8;
+    if (dyn != base) {
         int b2 = 0;
         rc = persistent_grid(kern, block, dyn, device, &b2);
         if (rc) return rc;
-        if (b2 < blocks) {   // the buffer would cost a resident workgroup: go without
-            cap = 0;
+        if (b2 < blocks) {   // cache and buffer would cost a resident workgroup: go without
+            ck = cap = 0;
             dyn = base;
         }
     }
     lp.dyn = dyn;
     lp.tables_at = tables_at;
-    lp.tail_at = base;
+    lp.cache_at = base;
+    lp.cache_k = ck;
+    lp.tail_at = ck ? tail_at : base;
     lp.tail_cap = cap;
     lp.blocks = blocks;
     return GT_OK;
@@ -362,26 +374,28 @@ inline void mark(hipEvent_t e, hipStream_t st) {
 
 // One persistent tracker launch for a geometry of staging kind KIND.
 template <int PREC, int KIND, int W>
-int launch_persistent_k(const gt_geometry *g, uint64_t n, unsigned block, bool tail, hipStream_t st) {
+int launch_persistent_k(const gt_geometry *g, uint64_t n, unsigned block, bool tail, bool cache, hipStream_t st) {
     const void *kern = (const void *)k_track_persistent<PREC, KIND, W>;
     LdsPlan lp;
-    int rc = plan_persistent(kern, block, KIND == SK_NONE ? 0 : g->stage[PREC].total, tail, g->device, lp);
+    int rc = plan_persistent(kern, block, KIND == SK_NONE ? 0 : g->stage[PREC].total, tail, cache, g->device, lp);
     if (rc) return rc;
     int blocks = lp.blocks;
     const uint64_t need = (n + block - 1) / block;
     if ((uint64_t)blocks > need) blocks = (int)need;
     hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W>), dim3(blocks), dim3(block), lp.dyn, st, g->desc,
-                       (const LaunchRec *)g->launch, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
+                       (const LaunchRec *)g->launch, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.cache_at,
+                       lp.cache_k);
     return GT_OK;
 }
 
 template <int PREC, int W>
-int launch_persistent(const gt_geometry *g, int kind, uint64_t n, unsigned block, bool tail, hipStream_t st) {
+int launch_persistent(const gt_geometry *g, int kind, uint64_t n, unsigned block, bool tail, bool cache,
+                      hipStream_t st) {
     switch (kind) {
-    case SK_ALL: return launch_persistent_k<PREC, SK_ALL, W>(g, n, block, tail, st);
-    case SK_LDS: return launch_persistent_k<PREC, SK_LDS, W>(g, n, block, tail, st);
-    case SK_SPLIT: return launch_persistent_k<PREC, SK_SPLIT, W>(g, n, block, tail, st);
-    default: return launch_persistent_k<PREC, SK_NONE, W>(g, n, block, tail, st);
+    case SK_ALL: return launch_persistent_k<PREC, SK_ALL, W>(g, n, block, tail, cache, st);
+    case SK_LDS: return launch_persistent_k<PREC, SK_LDS, W>(g, n, block, tail, cache, st);
+    case SK_SPLIT: return launch_persistent_k<PREC, SK_SPLIT, W>(g, n, block, tail, cache, st);
+    default: return launch_persistent_k<PREC, SK_NONE, W>(g, n, block, tail, cache, st);
     }
 }
 
@@ -390,12 +404,12 @@ template <int PREC, int KIND, int W>
 int launch_batch_k(gt_batch *b, const BatchChunk *ch, uint32_t n, unsigned long long *q, hipStream_t st) {
     const void *kern = (const void *)k_track_batch<PREC, KIND, W>;
     LdsPlan lp;
-    int rc = plan_persistent(kern, b->block, b->lds_bytes[KIND], b->tail, b->device, lp);
+    int rc = plan_persistent(kern, b->block, b->lds_bytes[KIND], b->tail, b->cache, b->device, lp);
     if (rc) return rc;
     int blocks = lp.blocks;
     if ((uint32_t)blocks > n) blocks = (int)n;
     hipLaunchKernelGGL((k_track_batch<PREC, KIND, W>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items, ch, n, q,
-                       lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound);
+                       lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.cache_at, lp.cache_k);
     return GT_OK;
 }
 
@@ -444,8 +458,9 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
             rec.o = ko;
             hipLaunchKernelGGL(k_put_launch, dim3(1), dim3(64), 0, st, rec, g->launch);
             const bool tail = !(p->flags & GT_FLAG_NO_TAIL_COMPACTION);
-            int rc = block == 640 ? launch_persistent<PREC, 5>(g, kind, kp.n, block, tail, st)
-                                  : launch_persistent<PREC, 4>(g, kind, kp.n, block, tail, st);
+            const bool cache = !(p->flags & GT_FLAG_NO_TALLY_CACHE);
+            int rc = block == 640 ? launch_persistent<PREC, 5>(g, kind, kp.n, block, tail, cache, st)
+                                  : launch_persistent<PREC, 4>(g, kind, kp.n, block, tail, cache, st);
             if (rc) return rc;
         }
     }

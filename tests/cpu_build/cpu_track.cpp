@@ -14,11 +14,14 @@ namespace {
 
 constexpr size_t kLdsEmuBytes = 160 * 1024;
 thread_local unsigned char g_lds[kLdsEmuBytes];
+thread_local uint32_t g_cache_k = kTallyCacheMax;   // tally-cache entries of the lane (0 = off)
 
 template <int PREC, int KIND, typename Queue>
 void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut &o, const Queue &q, uint64_t *counts) {
     static thread_local uint32_t cells[GT_MAX_LEVELS];
     static thread_local uint32_t ctl[1 + kBlockP / 64];
+    static thread_local uint64_t c_lo[kTallyCacheMax], c_hi[kTallyCacheMax];
+    static thread_local uint32_t c_tag[kTallyCacheMax];
     blockDim.x = 1;
     threadIdx.x = 0;
     if (KIND != SK_NONE) stage_copy(sp, (const unsigned char *)dev.coef, g_lds);
@@ -27,7 +30,8 @@ void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut
     p.refill_min = 1;   // a one-lane wave refills as soon as its lane is idle
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     const TailCfg tc = {nullptr, ctl, 0, kTailRound};
-    track_pool<PREC>(v, p, o, o.tally_ws, cells, q, cnt, tc);
+    const TallyCache tcache = {c_lo, c_hi, c_tag, g_cache_k, 1};
+    track_pool<PREC>(v, p, o, o.tally_ws, cells, q, cnt, tc, tcache);
     counts[GT_CNT_ESCAPED] += cnt.escaped;
     counts[GT_CNT_CAPPED] += cnt.capped;
     counts[GT_CNT_LOST] += cnt.lost;
@@ -70,6 +74,7 @@ extern "C" int cpu_track(const gt_geometry *g, const gt_track_params *p, const g
     KParams kp;
     KOut ko;
     fill_kparams(p, g, kp, ko, o);
+    g_cache_k = (p->flags & GT_FLAG_NO_TALLY_CACHE) ? 0 : kTallyCacheMax;
     std::memset(g->tally_ws, 0, (size_t)8 * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
@@ -99,6 +104,7 @@ extern "C" int cpu_track_batch(const gt_batch_item *items, uint32_t n_items, con
             else ((uint32_t *)r.ptr)[i] = (uint32_t)r.value;
         }
     }
+    g_cache_k = b->cache ? kTallyCacheMax : 0;
     uint32_t first = 0, ran = 0;
     for (int kind = 3; kind >= 0 && !rc; kind--) {
         for (uint32_t c = first; c < first + b->n_kind[kind] && !rc; c++) {

@@ -112,7 +112,8 @@ def make(what, k):
 @pytest.mark.parametrize("what,k", GEOMS, ids=["%s%s" % g for g in GEOMS])
 def test_cpu_build_matches_oracle(host, what, k):
     """Every staging kind the geometry can be held in (its own and all
-    global), both precisions, 400 histories with recorded sequences."""
+    global), both precisions, with and without the lane's tally cache, 400
+    histories with recorded sequences."""
     fg, kw = make(what, k)
     h, ni = host.geometry(fg)
     n, rk, cap = 400, 30, 48
@@ -120,11 +121,12 @@ def test_cpu_build_matches_oracle(host, what, k):
                                                                     record_cap=cap, **kw), n_threads=4)
     for prec in (gt.PREC_FP64, gt.PREC_MIXED):
         for kind in sorted({0, host.staging(h, prec)}):
-            out = Outs(ni, n, rk, cap)
-            prm = gt._params(kw["seed"], n, geometry_id=kw["geometry_id"], precision=prec, record_first_k=rk,
-                             record_cap=cap)
-            host.check(host.L.cpu_track(h, C.byref(prm), C.byref(out.struct()), kind))
-            same(out.a, o, rk)
+            for cache in ((True, False) if kind else (True,)):
+                out = Outs(ni, n, rk, cap)
+                prm = gt._params(kw["seed"], n, geometry_id=kw["geometry_id"], precision=prec, record_first_k=rk,
+                                 record_cap=cap, tally_cache=cache)
+                host.check(host.L.cpu_track(h, C.byref(prm), C.byref(out.struct()), kind))
+                same(out.a, o, rk)
     host.L.gt_geometry_destroy(h)
 
 

@@ -206,6 +206,19 @@ def test_without_tail_compaction(cfg, block):
     assert_parity(g, o, where="no tail compaction cfg %s block %d" % (cfg, block))
 
 
+@pytest.mark.parametrize("cfg", [2, 3])
+@pytest.mark.parametrize("block,cache", [(1024, False), (640, False), (640, True), (256, True)])
+def test_tally_cache_on_and_off(cfg, block, cache):
+    """Tallies do not depend on whether lanes keep partial sums in their LDS
+    cache (nor on how many entries the launch shape leaves room for)."""
+    fg, G, O = geoms(cfg)
+    kw = dict(seed=78, n_particles=9000, geometry_id=cfg)
+    g = gpu_track(G, precision=gt.PREC_MIXED, block_size=block, tally_cache=cache, record_first_k=20,
+                  record_cap=64, **kw)
+    o = oracle.track(O, oracle.TrackParams(record_first_k=20, record_cap=64, **kw), n_threads=NT)
+    assert_parity(g, o, where="tally cache %s cfg %s block %d" % (cache, cfg, block))
+
+
 def test_accumulate_two_halves():
     import torch
     fg, G, O = geoms(1)
