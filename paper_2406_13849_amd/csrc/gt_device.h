@@ -218,8 +218,9 @@ __device__ __forceinline__ double quad_value(uint32_t type, CP c, double x, doub
 // on surface force_s the logical sense force_pos is used instead.
 template <typename G>
 __device__ __forceinline__ bool contains(const G &g, uint32_t c, double x, double y, double z, uint32_t force_s,
-                                         bool force_pos) {
+                                         bool force_pos, int32_t &fill) {
     const Cell cc = ldv<Cell>(g.cell + c);
+    fill = cc.fill;
     const auto hs = g.hs + cc.hs_off;
     const uint32_t npl = cc.n_pl & kPlaneCountMask;
     for (uint32_t k = 0; k < npl; k++) {
@@ -235,6 +236,13 @@ __device__ __forceinline__ bool contains(const G &g, uint32_t c, double x, doubl
         if (pos != (bool)((h >> 3) & 1u)) return false;
     }
     return true;
+}
+
+template <typename G>
+__device__ __forceinline__ bool contains(const G &g, uint32_t c, double x, double y, double z, uint32_t force_s,
+                                         bool force_pos) {
+    int32_t fill;
+    return contains(g, c, x, y, z, force_s, force_pos, fill);
 }
 
 // Distance along (u,v,w) from q to the point where a plane's sense leaves
@@ -298,21 +306,25 @@ __device__ __forceinline__ double quad_distance(uint32_t type, CP c, bool pos, d
 // ------------------------------------------------------------------ search
 // The cell of universe u containing (x,y,z) -- Table 1 find_cell when
 // force_s == kNone, the cross_surface candidate test otherwise -- or -1.
-// Mixed precision first tries the lattice-index guess at (gx, gy), then
-// walks the single-precision hierarchy; double precision walks the
-// double-precision hierarchy.  Whichever cell is returned passed the double
-// containment test, which at most one cell of a universe passes.
+// Mixed precision first tries the lattice-index guess, then walks the
+// single-precision hierarchy; double precision walks the double-precision
+// hierarchy.  The guess is taken at (x + nu * pitch, y + nv * pitch) in
+// single precision: after a crossing (nu, nv) is a small step along the
+// flight, so that the guess lands on the far side.  Whichever cell is
+// returned passed the double containment test, which at most one cell of a
+// universe passes.  The cell's fill is returned in *fill.
 template <int PREC, typename G>
 __device__ int32_t search(const G &g, uint32_t u, double x, double y, double z, uint32_t force_s, bool force_pos,
-                          int32_t exclude, float gx, float gy) {
+                          int32_t exclude, float nu, float nv, int32_t &fill) {
     const Univ U = ldv<Univ>(g.univ + u);
     if (PREC == GT_PREC_MIXED && U.hint == (int32_t)kHintSquare) {
+        const float gx = (float)x + nu / U.inv_px, gy = (float)y + nv / U.inv_py;
         int i = (int)floorf((gx - U.x0) * U.inv_px);
         int j = (int)floorf((gy - U.y0) * U.inv_py);
         i = min(max(i, 0), U.nx - 1);
         j = min(max(j, 0), U.ny - 1);
         const int32_t c = (int32_t)U.cell0 + j * U.nx + i;
-        if (c != exclude && contains(g, (uint32_t)c, x, y, z, force_s, force_pos)) return c;
+        if (c != exclude && contains(g, (uint32_t)c, x, y, z, force_s, force_pos, fill)) return c;
     }
     uint32_t n = U.node0;
     const uint32_t end = U.node0 + U.nnode;
@@ -342,7 +354,7 @@ __device__ int32_t search(const G &g, uint32_t u, double x, double y, double z, 
                 const auto b = g.cbox + 8 * (size_t)c;
                 if (!(fx >= b[0] && fx <= b[4] && fy >= b[1] && fy <= b[5] && fz >= b[2] && fz <= b[6])) continue;
             }
-            if (contains(g, c, x, y, z, force_s, force_pos)) return (int32_t)c;
+            if (contains(g, c, x, y, z, force_s, force_pos, fill)) return (int32_t)c;
         }
         n = esc;
     }
@@ -373,7 +385,8 @@ __device__ __forceinline__ bool descend(const G &g, Particle &P, int L0, double 
         qx = qx - t[0];
         qy = qy - t[1];
         qz = qz - t[2];
-        const int32_t d = search<PREC>(g, (uint32_t)(-fill - 1), qx, qy, qz, kNone, false, -1, (float)qx, (float)qy);
+        int32_t dfill;
+        const int32_t d = search<PREC>(g, (uint32_t)(-fill - 1), qx, qy, qz, kNone, false, -1, 0.0f, 0.0f, dfill);
         if (d < 0) { P.depth = L + 1; return false; }
         L++;
         lvl(P, L) = (uint32_t)d;
@@ -554,16 +567,9 @@ __device__ __forceinline__ int cross(const G &g, Particle &P, int Ls, uint32_t s
         univ = (uint32_t)(-g.cell[c].fill - 1);
     }
     const uint32_t old = lvl(P, Ls);
-    // guess point nudged along the flight so that a lattice guess lands on the far side
-    float gx = (float)qx, gy = (float)qy;
-    if (PREC == GT_PREC_MIXED) {
-        const Univ U = ldv<Univ>(g.univ + univ);
-        if (U.hint == (int32_t)kHintSquare) {
-            gx += (float)P.u * 1e-3f / U.inv_px;
-            gy += (float)P.v * 1e-3f / U.inv_py;
-        }
-    }
-    const int32_t c = search<PREC>(g, univ, qx, qy, qz, ss, !old_pos, (int32_t)old, gx, gy);
+    int32_t cfill;
+    const int32_t c = search<PREC>(g, univ, qx, qy, qz, ss, !old_pos, (int32_t)old, (float)P.u * 1e-3f,
+                                   (float)P.v * 1e-3f, cfill);
     if (c < 0) return Ls == 0 ? GT_END_ESCAPE : GT_END_LOST;
     lvl(P, Ls) = (uint32_t)c;
     if (!descend<PREC>(g, P, Ls, qx, qy, qz)) return GT_END_LOST;
@@ -731,7 +737,8 @@ __device__ void run_history(const G &g, const KParams &p, const KOut &o, uint64_
         P.v = 0.0;
         P.w = 0.0;
         P.tau = 0.0;
-        const int32_t c = search<PREC>(g, g.root, P.x, P.y, P.z, kNone, false, -1, (float)P.x, (float)P.y);
+        int32_t rfill;
+        const int32_t c = search<PREC>(g, g.root, P.x, P.y, P.z, kNone, false, -1, 0.0f, 0.0f, rfill);
         if (c < 0) {
             end = GT_END_LOST;
         } else {
@@ -739,13 +746,13 @@ __device__ void run_history(const G &g, const KParams &p, const KOut &o, uint64_
             if (!descend<PREC>(g, P, 0, P.x, P.y, P.z)) end = GT_END_LOST;
         }
     } else {
-        int32_t c = -1;
+        int32_t c = -1, rfill;
         for (int a = 0; a < kMaxBirthAttempts && c < 0; a++) {
             draw_block(p.seed, p.geom_id, pid, blk++, u0, u1, u2);
             P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * u0;
             P.y = g.lo[1] + (g.hi[1] - g.lo[1]) * u1;
             P.z = g.lo[2] + (g.hi[2] - g.lo[2]) * u2;
-            c = search<PREC>(g, g.root, P.x, P.y, P.z, kNone, false, -1, (float)P.x, (float)P.y);
+            c = search<PREC>(g, g.root, P.x, P.y, P.z, kNone, false, -1, 0.0f, 0.0f, rfill);
             if (c < 0) cnt.rejected++;
         }
         if (c < 0) {
@@ -1196,14 +1203,6 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
                 qz = qz - t[2];
                 su = (uint32_t)(-g.cell[cl].fill - 1);
             }
-            const Univ U = ldv<Univ>(g.univ + su);
-            // guess point for a lattice index; after a crossing it is nudged
-            // along the flight so that it lands on the far side
-            float gx = (float)qx, gy = (float)qy;
-            if (PREC == GT_PREC_MIXED && sforce != kNone && U.hint == (int32_t)kHintSquare) {
-                gx += (float)P.u * 1e-3f / U.inv_px;
-                gy += (float)P.v * 1e-3f / U.inv_py;
-            }
             // quick candidates first: after a crossing, the cells listed for the
             // crossed half-space; in a descent, the cell with the same index in
             // the new universe as the lane had at this level before
@@ -1215,16 +1214,23 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
                 excl = (int32_t)lvl(P, sL);   // the cell being left
             } else {
                 const uint32_t loc = g.cell_local[lvl(P, sL)];
+                const Univ U = ldv<Univ>(g.univ + su);
                 hint = U.cell0 + loc;
                 k0 = 0;
                 k1 = loc < U.ncell ? 1u : 0u;
             }
-            int32_t c = -1;
+            int32_t c = -1, fill = 0;
             for (uint32_t k = k0; k < k1; k++) {
                 const uint32_t d = sforce != kNone ? g.adj[k] : hint;
-                if (contains(g, d, qx, qy, qz, sforce, sfpos)) { c = (int32_t)d; break; }
+                if (contains(g, d, qx, qy, qz, sforce, sfpos, fill)) { c = (int32_t)d; break; }
             }
-            if (c < 0) c = search<PREC>(g, su, qx, qy, qz, sforce, sfpos, excl, gx, gy);
+            // the full search; after a crossing its lattice guess is taken a
+            // little along the flight, so that it lands on the far side
+            if (c < 0) {
+                const float nu = sforce != kNone ? (float)P.u * 1e-3f : 0.0f;
+                const float nv = sforce != kNone ? (float)P.v * 1e-3f : 0.0f;
+                c = search<PREC>(g, su, qx, qy, qz, sforce, sfpos, excl, nu, nv, fill);
+            }
             if (c < 0) {
                 if (birth) {
                     if (sL == 0 && p.source != 1) { cnt.rejected++; mode = M_POS; }
@@ -1234,7 +1240,7 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
                 }
             } else {
                 lvl(P, sL) = (uint32_t)c;
-                if (g.cell[c].fill < 0) {
+                if (fill < 0) {
                     sL++;
                     sforce = kNone;
                 } else {

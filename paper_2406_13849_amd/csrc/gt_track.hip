@@ -177,7 +177,8 @@ __global__ void __launch_bounds__(kBlock) k_find_cell(Dev g0, const double *pos,
     P.z = pos[3 * i + 2];
     P.depth = 0;
     bool ok = false;
-    const int32_t c = search<PREC>(g, g.root, P.x, P.y, P.z, kNone, false, -1, (float)P.x, (float)P.y);
+    int32_t fill;
+    const int32_t c = search<PREC>(g, g.root, P.x, P.y, P.z, kNone, false, -1, 0.0f, 0.0f, fill);
     if (c >= 0) {
         lvl(P, 0) = (uint32_t)c;
         ok = descend<PREC>(g, P, 0, P.x, P.y, P.z);
@@ -205,7 +206,8 @@ __global__ void __launch_bounds__(kBlock) k_distance(Dev g0, const double *pos, 
     P.on_level = -1;
     P.on_surf = kNone;
     P.depth = 0;
-    const int32_t c = search<GT_PREC_FP64>(g, g.root, P.x, P.y, P.z, kNone, false, -1, 0.f, 0.f);
+    int32_t fill;
+    const int32_t c = search<GT_PREC_FP64>(g, g.root, P.x, P.y, P.z, kNone, false, -1, 0.0f, 0.0f, fill);
     bool ok = false;
     if (c >= 0) {
         lvl(P, 0) = (uint32_t)c;
