@@ -885,6 +885,7 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
         for (int k = 0; k < 4; k++) b->lds_bytes[k] = lds[k];
         b->tail = !(items[0].params.flags & GT_FLAG_NO_TAIL_COMPACTION);
         b->cache = !(items[0].params.flags & GT_FLAG_NO_TALLY_CACHE);
+        b->side = nullptr;
         *out = b;
         return GT_OK;
     } catch (const std::bad_alloc &) {
@@ -910,6 +911,7 @@ extern "C" void gt_batch_destroy(gt_batch *b) {
     if (!b) return;
     int cur = 0;
     bool switched = hipGetDevice(&cur) == hipSuccess && cur != b->device && hipSetDevice(b->device) == hipSuccess;
+    release_batch_streams(b);
     (void)hipFree(b->dmem);
     if (switched) (void)hipSetDevice(cur);
     delete b;

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <new>
 
 #include "gt_device.h"
 
@@ -415,20 +416,79 @@ int launch_batch_k(gt_batch *b, const BatchChunk *ch, uint32_t n, unsigned long 
     return GT_OK;
 }
 
+// Helper streams of a batch: the launches of different staging kinds share
+// no data (each item's chunks, queue counter and outputs belong to one kind),
+// so they run on streams forked from and joined back into the caller's; the
+// workgroups of a later launch then start on compute units that an earlier
+// launch's tail has left (default priority throughout).
+struct BatchStreams {
+    hipStream_t s[3];
+    hipEvent_t fork, join[3];
+};
+
+int batch_streams(gt_batch *b, BatchStreams *&bs) {
+    bs = (BatchStreams *)b->side;
+    if (bs) return GT_OK;
+    BatchStreams *n = new (std::nothrow) BatchStreams;
+    if (!n) return set_error("host allocation failed"), GT_ENOMEM;
+    int streams = 0, joins = 0;
+    bool fork = false;
+    hipError_t e = hipEventCreateWithFlags(&n->fork, hipEventDisableTiming);
+    fork = e == hipSuccess;
+    for (int i = 0; i < 3 && e == hipSuccess; i++) {
+        e = hipStreamCreateWithFlags(&n->s[i], hipStreamNonBlocking);
+        if (e == hipSuccess) streams++;
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&n->join[i], hipEventDisableTiming);
+        if (e == hipSuccess) joins++;
+    }
+    if (e != hipSuccess) {
+        for (int i = 0; i < streams; i++) (void)hipStreamDestroy(n->s[i]);
+        for (int i = 0; i < joins; i++) (void)hipEventDestroy(n->join[i]);
+        if (fork) (void)hipEventDestroy(n->fork);
+        delete n;
+        return set_error("gt_batch_launch: helper streams: %s", hipGetErrorString(e)), GT_EHIP;
+    }
+    b->side = bs = n;
+    return GT_OK;
+}
+
 template <int PREC, int W>
 int launch_batch_kinds(gt_batch *b, hipStream_t st) {
+    int kinds = 0;
+    for (int kind = 0; kind < 4; kind++) kinds += b->n_kind[kind] ? 1 : 0;
+    BatchStreams *bs = nullptr;
+    if (kinds > 1) {
+        int rc = batch_streams(b, bs);
+        if (rc) return rc;
+        rc = hip_check(hipEventRecord(bs->fork, st), "hipEventRecord");
+        if (rc) return rc;
+    }
     uint32_t first = 0;
+    int lane = 0;
     for (int kind = 3; kind >= 0; kind--) {   // chunk groups in the order gt_batch_create wrote them
         const uint32_t n = b->n_kind[kind];
         const BatchChunk *ch = b->d_chunks + first;
         unsigned long long *q = b->d_queue + kind;
         first += n;
         if (!n) continue;
-        int rc = kind == SK_ALL     ? launch_batch_k<PREC, SK_ALL, W>(b, ch, n, q, st)
-                 : kind == SK_LDS   ? launch_batch_k<PREC, SK_LDS, W>(b, ch, n, q, st)
-                 : kind == SK_SPLIT ? launch_batch_k<PREC, SK_SPLIT, W>(b, ch, n, q, st)
-                                    : launch_batch_k<PREC, SK_NONE, W>(b, ch, n, q, st);
+        hipStream_t s = st;
+        if (lane > 0) {
+            s = bs->s[lane - 1];
+            int rc = hip_check(hipStreamWaitEvent(s, bs->fork, 0), "hipStreamWaitEvent");
+            if (rc) return rc;
+        }
+        int rc = kind == SK_ALL     ? launch_batch_k<PREC, SK_ALL, W>(b, ch, n, q, s)
+                 : kind == SK_LDS   ? launch_batch_k<PREC, SK_LDS, W>(b, ch, n, q, s)
+                 : kind == SK_SPLIT ? launch_batch_k<PREC, SK_SPLIT, W>(b, ch, n, q, s)
+                                    : launch_batch_k<PREC, SK_NONE, W>(b, ch, n, q, s);
         if (rc) return rc;
+        if (lane > 0) {
+            rc = hip_check(hipEventRecord(bs->join[lane - 1], s), "hipEventRecord");
+            if (rc) return rc;
+            rc = hip_check(hipStreamWaitEvent(st, bs->join[lane - 1], 0), "hipStreamWaitEvent");
+            if (rc) return rc;
+        }
+        lane++;
     }
     if (first != b->n_chunks) return set_error("gt_batch_launch: inconsistent chunk groups"), GT_EINVAL;
     return GT_OK;
@@ -491,6 +551,18 @@ int launch_batch_t(gt_batch *b, hipStream_t st) {
 void set_kernel_events(void *start, void *stop) {
     t_ev_start = (hipEvent_t)start;
     t_ev_stop = (hipEvent_t)stop;
+}
+
+void release_batch_streams(gt_batch *b) {
+    BatchStreams *bs = (BatchStreams *)b->side;
+    if (!bs) return;
+    for (int i = 0; i < 3; i++) {
+        (void)hipStreamDestroy(bs->s[i]);
+        (void)hipEventDestroy(bs->join[i]);
+    }
+    (void)hipEventDestroy(bs->fork);
+    delete bs;
+    b->side = nullptr;
 }
 
 int launch_batch(gt_batch *b, void *stream) {
