@@ -245,10 +245,15 @@ int gt_batch_create(const gt_batch_item *items, uint32_t n_items, const gt_tunin
  * geometry tables' and output buffers' addresses: they must outlive it.
  * Work-queue position counters[7] stays 0 for batch items. */
 
-/* Track every item of the batch with one persistent launch (a second launch
- * of the same kernel covers items whose tables exceed the LDS budget), plus
- * one fill and one finalize launch.  Only kernel launches are issued, so the
- * call can be captured into a HIP graph and replayed. */
+/* Track every item of the batch: one fill launch, then one persistent launch
+ * per staging kind present (items whose tables fit the LDS in full, in part,
+ * or not at all), then one finalize launch.  The kind launches run on helper
+ * streams that the batch owns (made by gt_batch_create when it has several
+ * kinds, default priority), forked from `stream` and joined back into it with
+ * events before the finalize launch, so later kinds start on compute units
+ * that earlier ones have finished with.  Only kernel launches and event
+ * records/waits are issued, so the call can be captured into a HIP graph and
+ * replayed. */
 int gt_batch_launch(gt_batch *b, void *stream);
 
 void gt_batch_destroy(gt_batch *b);

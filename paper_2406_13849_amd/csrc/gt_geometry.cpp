@@ -886,6 +886,11 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
         b->tail = !(items[0].params.flags & GT_FLAG_NO_TAIL_COMPACTION);
         b->cache = !(items[0].params.flags & GT_FLAG_NO_TALLY_CACHE);
         b->side = nullptr;
+        const int rcs = prepare_batch_streams(b);
+        if (rcs) {
+            gt_batch_destroy(b);
+            return rcs;
+        }
         *out = b;
         return GT_OK;
     } catch (const std::bad_alloc &) {

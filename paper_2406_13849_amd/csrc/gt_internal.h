@@ -202,7 +202,7 @@ struct gt_batch {
     bool tail;                          // tail compaction on
     bool cache;                         // per-lane tally cache on
     void *side;                         // helper streams and events for the staging-kind launches
-                                        // (made at the first launch that needs them)
+                                        // (made by gt_batch_create when there are several kinds)
 };
 
 namespace gt {
@@ -213,6 +213,7 @@ unsigned stage_budget();
 void set_kernel_events(void *start, void *stop);
 bool cached_batch_tuning(const gt_batch_item *items, uint32_t n_items, gt_tuning *out);
 int launch_batch(gt_batch *b, void *stream);
+int prepare_batch_streams(gt_batch *b);
 void release_batch_streams(gt_batch *b);
 int launch_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream);
 int launch_find_cell(const gt_geometry *g, const double *pos, uint64_t n, int64_t *inst, int32_t *cells,

@@ -553,6 +553,13 @@ void set_kernel_events(void *start, void *stop) {
     t_ev_stop = (hipEvent_t)stop;
 }
 
+int prepare_batch_streams(gt_batch *b) {
+    int kinds = 0;
+    for (int kind = 0; kind < 4; kind++) kinds += b->n_kind[kind] ? 1 : 0;
+    BatchStreams *bs = nullptr;
+    return kinds > 1 ? batch_streams(b, bs) : GT_OK;
+}
+
 void release_batch_streams(gt_batch *b) {
     BatchStreams *bs = (BatchStreams *)b->side;
     if (!bs) return;
