@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--only", choices=["mixed", "fp64", "plain_fp64", "batch"], default=None,
                     help="time one mode only (profiling)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-geometry batched workload")
-    ap.add_argument("--no-tail", action="store_true", help="switch off tail compaction (comparison)")
+    ap.add_argument("--tail", action="store_true", help="switch on tail compaction (comparison)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the launch shape gt_autotune_track picks instead of the library default")
     ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)   # the default
@@ -117,7 +117,7 @@ def run_timed(gt, step, args, hev):
 
 def timed(gt, G, out, args, prec, hev, lane=False):
     kw = dict(seed=2002, n_particles=args.particles, geometry_id=2, precision=prec, block_size=args.block, out=out,
-              lane_per_history=lane, refill_min=0 if lane else args.refill, tail_compaction=not args.no_tail)
+              lane_per_history=lane, refill_min=0 if lane else args.refill, tail_compaction=args.tail)
     shape = None
     if not lane and args.autotune and not args.block and not args.refill:
         shape = gt.autotune_track(G, reps=2, **{k: v for k, v in kw.items() if k not in ("block_size", "refill_min")})
@@ -138,7 +138,7 @@ def batched(gt, synth, args, hev):
         G = gt.Geometry(fg)
         geoms.append((G, n, j))
         items.append(gt.batch_item(G, synth.batch_particle_seed(j), n, geometry_id=synth.batch_geometry_id(j),
-                                   precision=gt.PREC_MIXED, tail_compaction=not args.no_tail))
+                                   precision=gt.PREC_MIXED, tail_compaction=args.tail))
     tuned = None
     if args.tune_batch:
         tuned = gt.autotune_batch(items, reps=1)
@@ -150,7 +150,7 @@ def batched(gt, synth, args, hev):
             for (G, n, j), it in zip(geoms, items):
                 gt.track(G, seed=synth.batch_particle_seed(j), n_particles=n, geometry_id=synth.batch_geometry_id(j),
                          precision=prec, block_size=args.block, refill_min=args.refill, out=it.out,
-                         tail_compaction=not args.no_tail)
+                         tail_compaction=args.tail)
         res[name] = run_timed(gt, step, args, hev)
         if sum(it.out.counters_dict()["segments"] for it in items) != segs:
             raise RuntimeError("batched and sequential segment counts differ")

@@ -90,8 +90,10 @@ extern "C" {
                                           refilling schedule                                */
 #define GT_FLAG_NO_STAGING 4u          /* persistent schedule: read the geometry tables from
                                           global memory even when they fit in LDS           */
-#define GT_FLAG_NO_TAIL_COMPACTION 8u  /* persistent schedule: once the queue is empty, do not
-                                          pack the remaining histories into fewer waves      */
+#define GT_FLAG_TAIL_COMPACTION 8u     /* persistent schedule: once the queue is empty, pack the
+                                          remaining histories of a workgroup into fewer waves
+                                          (off by default: idle waves then wait instead of
+                                          ending, which costs more than it saves here)       */
 #define GT_FLAG_NO_TALLY_CACHE 16u     /* persistent schedule: flush a lane's tally partial sum
                                           at every change of instance instead of keeping up
                                           to three more in an LDS cache (speed only)         */

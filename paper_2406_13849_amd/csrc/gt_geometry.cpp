@@ -750,7 +750,7 @@ int gt::check_track_args(const gt_geometry *g, const gt_track_params *p, const g
     if (p->source == 1 && p->ray_n1 < 1) return set_error("gt_track: ray source needs ray_n1 >= 1"), GT_EINVAL;
     if (p->record_first_k && (!o->rec || p->record_cap < 1))
         return set_error("gt_track: recording needs rec and record_cap >= 1"), GT_EINVAL;
-    if (p->flags & ~(GT_FLAG_ACCUMULATE | GT_FLAG_LANE_PER_HISTORY | GT_FLAG_NO_STAGING | GT_FLAG_NO_TAIL_COMPACTION |
+    if (p->flags & ~(GT_FLAG_ACCUMULATE | GT_FLAG_LANE_PER_HISTORY | GT_FLAG_NO_STAGING | GT_FLAG_TAIL_COMPACTION |
                      GT_FLAG_NO_TALLY_CACHE))
         return set_error("gt_track: unknown flags 0x%x", p->flags), GT_EINVAL;
     if (p->block_size && (p->block_size % 64 || p->block_size > 1024))
@@ -883,7 +883,7 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
         b->max_inst = max_inst;
         b->d_queue = (unsigned long long *)(base + o_queue);
         for (int k = 0; k < 4; k++) b->lds_bytes[k] = lds[k];
-        b->tail = !(items[0].params.flags & GT_FLAG_NO_TAIL_COMPACTION);
+        b->tail = (items[0].params.flags & GT_FLAG_TAIL_COMPACTION) != 0;
         b->cache = !(items[0].params.flags & GT_FLAG_NO_TALLY_CACHE);
         b->side = nullptr;
         const int rcs = prepare_batch_streams(b);

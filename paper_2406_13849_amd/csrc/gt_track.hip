@@ -519,7 +519,7 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
             rec.p = kp;
             rec.o = ko;
             hipLaunchKernelGGL(k_put_launch, dim3(1), dim3(64), 0, st, rec, g->launch);
-            const bool tail = !(p->flags & GT_FLAG_NO_TAIL_COMPACTION);
+            const bool tail = (p->flags & GT_FLAG_TAIL_COMPACTION) != 0;
             const bool cache = !(p->flags & GT_FLAG_NO_TALLY_CACHE);
             int rc = block == 640 ? launch_persistent<PREC, 5>(g, kind, kp.n, block, tail, cache, st)
                                   : launch_persistent<PREC, 4>(g, kind, kp.n, block, tail, cache, st);

@@ -32,7 +32,7 @@ unsigned log2_ceil(uint64_t n) {
 uint64_t track_key(const gt_geometry *g, const gt_track_params *p) {
     uint64_t h = mix(0, (uint64_t)(uintptr_t)g);
     h = mix(h, p->precision);
-    h = mix(h, p->flags & (GT_FLAG_NO_STAGING | GT_FLAG_NO_TAIL_COMPACTION));
+    h = mix(h, p->flags & (GT_FLAG_NO_STAGING | GT_FLAG_TAIL_COMPACTION));
     return mix(h, log2_ceil(p->n_particles));
 }
 

@@ -24,7 +24,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 FLAG_ACCUMULATE = 1
 FLAG_LANE_PER_HISTORY = 2
 FLAG_NO_STAGING = 4
-FLAG_NO_TAIL_COMPACTION = 8
+FLAG_TAIL_COMPACTION = 8
 FLAG_NO_TALLY_CACHE = 16
 END_NONE, END_ESCAPE, END_CAP, END_LOST, END_SEGCAP = 0, 1, 2, 3, 4
 COUNTERS = ("escaped", "capped", "lost", "segcap", "rec_overflow", "segments", "rejected", "spare")
@@ -229,13 +229,13 @@ def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 
           max_collisions: int = 20, source: int = 0, ray_n1: int = 0, max_segments: int = 100_000,
           precision: int = PREC_MIXED, record_first_k: int = 0, record_cap: int = 0, accumulate: bool = False,
           lane_per_history: bool = False, staging: bool = True, block_size: int = 0, refill_min: int = 0,
-          tail_compaction: bool = True, tally_cache: bool = True, out: Optional[TrackOutputs] = None,
+          tail_compaction: bool = False, tally_cache: bool = True, out: Optional[TrackOutputs] = None,
           stream=None) -> TrackOutputs:
     """gt_track: sample and track n_particles histories (asynchronous).
     lane_per_history selects the plain one-history-per-lane schedule instead
     of the persistent refilling one; staging=False keeps the geometry tables
-    in global memory even when they fit in LDS; tail_compaction=False keeps
-    each history in its lane after the queue has drained; tally_cache=False
+    in global memory even when they fit in LDS; tail_compaction=True packs
+    the histories left after the queue has drained into fewer waves; tally_cache=False
     flushes a lane's tally sum at every change of instance."""
     if out is None:
         out = alloc_outputs(geom, n_particles, record_first_k, record_cap)
@@ -249,13 +249,13 @@ def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 
 
 def _params(seed, n_particles, first_particle=0, geometry_id=0, max_collisions=20, source=0, ray_n1=0,
             max_segments=100_000, precision=PREC_MIXED, record_first_k=0, record_cap=0, accumulate=False,
-            lane_per_history=False, staging=True, block_size=0, refill_min=0, tail_compaction=True,
+            lane_per_history=False, staging=True, block_size=0, refill_min=0, tail_compaction=False,
             tally_cache=True) -> _Params:
     return _Params(seed=seed, first_particle=first_particle, n_particles=n_particles, geometry_id=geometry_id,
                    max_collisions=max_collisions, source=source, ray_n1=ray_n1, max_segments=max_segments,
                    precision=precision, record_first_k=record_first_k, record_cap=record_cap,
                    flags=(FLAG_ACCUMULATE if accumulate else 0) | (FLAG_LANE_PER_HISTORY if lane_per_history else 0)
-                   | (0 if staging else FLAG_NO_STAGING) | (0 if tail_compaction else FLAG_NO_TAIL_COMPACTION)
+                   | (0 if staging else FLAG_NO_STAGING) | (FLAG_TAIL_COMPACTION if tail_compaction else 0)
                    | (0 if tally_cache else FLAG_NO_TALLY_CACHE),
                    block_size=block_size, refill_min=refill_min, reserved=0)
 

@@ -196,14 +196,14 @@ def test_launch_shapes_do_not_change_results(block, lane, refill):
 
 @pytest.mark.parametrize("cfg", [1, 2, 4])
 @pytest.mark.parametrize("block", [128, 640, 1024])
-def test_without_tail_compaction(cfg, block):
-    """Histories stay in their lanes after the queue drains: same results."""
+def test_with_tail_compaction(cfg, block):
+    """Histories packed into fewer waves after the queue drains: same results."""
     fg, G, O = geoms(cfg)
     kw = dict(seed=77, n_particles=7000, geometry_id=cfg)
-    g = gpu_track(G, precision=gt.PREC_MIXED, block_size=block, tail_compaction=False, record_first_k=50,
+    g = gpu_track(G, precision=gt.PREC_MIXED, block_size=block, tail_compaction=True, record_first_k=50,
                   record_cap=64, **kw)
     o = oracle.track(O, oracle.TrackParams(record_first_k=50, record_cap=64, **kw), n_threads=NT)
-    assert_parity(g, o, where="no tail compaction cfg %s block %d" % (cfg, block))
+    assert_parity(g, o, where="tail compaction cfg %s block %d" % (cfg, block))
 
 
 @pytest.mark.parametrize("cfg", [2, 3])
@@ -305,18 +305,19 @@ def _outs(out):
 BATCH_SUBSET = [0, 2, 3, 5, 7, 10, 25, 41, 57, 63]
 
 
-@pytest.mark.parametrize("prec", [gt.PREC_FP64, gt.PREC_MIXED])
-def test_batch_matches_oracle(prec):
+@pytest.mark.parametrize("prec,tail", [(gt.PREC_FP64, False), (gt.PREC_MIXED, False), (gt.PREC_MIXED, True)])
+def test_batch_matches_oracle(prec, tail):
     """One batched launch over ten geometries (half of them forced to read
-    their tables from global memory, so both launches of the batch run), with
-    small chunks so every item is split into several and ends ragged."""
+    their tables from global memory, so several staging-kind launches run on
+    forked streams), with small chunks so every item is split into several
+    and ends ragged; with and without tail compaction."""
     import torch
     items, want = [], []
     for k, j in enumerate(BATCH_SUBSET):
         fg, n, G, O = batch_geoms(j)
         n = min(n, 1500 + 137 * k)
         kw = dict(first_particle=0, geometry_id=synth.batch_geometry_id(j), record_first_k=40, record_cap=64,
-                  precision=prec, staging=(k % 2 == 0))
+                  precision=prec, staging=(k % 2 == 0), tail_compaction=tail)
         items.append(gt.batch_item(G, synth.batch_particle_seed(j), n, **kw))
         want.append(oracle.track(O, oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=n,
                                                        geometry_id=synth.batch_geometry_id(j),
