@@ -518,7 +518,11 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         }
         // crossing candidates per half-space entry (device order): cells of the
         // same universe that use the surface with the other sense and whose
-        // widened boxes overlap this cell's box, largest overlap first
+        // widened boxes overlap this cell's box; first those that share the
+        // most of this cell's other half-spaces (the cell straight across a
+        // face usually keeps the bounds along the face: the y planes across an
+        // x plane, the cylinders across an axial plane), then the largest
+        // box overlap
         std::vector<std::vector<std::pair<uint32_t, bool>>> users(F.n_surfaces);
         for (uint32_t c = 0; c < F.n_cells; c++)
             for (uint32_t k = F.cell_hs_off[c]; k < F.cell_hs_off[c + 1]; k++)
@@ -531,7 +535,12 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
                 if (bc.is_empty()) continue;
                 const uint32_t s = hs[k] >> 4;
                 const bool pos = (hs[k] >> 3) & 1u;
-                std::vector<std::pair<double, uint32_t>> cand;
+                struct Cand {
+                    int shared;
+                    double v;
+                    uint32_t cell;
+                };
+                std::vector<Cand> cand;
                 for (const auto &us : users[s]) {
                     if (us.first == c || us.second == pos) continue;
                     const Box &bd = B.cbox[us.first];
@@ -542,13 +551,17 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
                         v = w < 0 ? -1.0 : v * w;
                         if (v < 0) break;
                     }
-                    if (v >= 0) cand.push_back({v, us.first});
+                    if (v < 0) continue;
+                    int shared = 0;
+                    for (uint32_t a = F.cell_hs_off[us.first]; a < F.cell_hs_off[us.first + 1]; a++)
+                        for (uint32_t q = F.cell_hs_off[c]; q < F.cell_hs_off[c + 1]; q++)
+                            if (q != k && F.hs[q] == F.hs[a]) shared++;
+                    cand.push_back({shared, v, us.first});
                 }
-                std::stable_sort(cand.begin(), cand.end(),
-                                 [](const std::pair<double, uint32_t> &x, const std::pair<double, uint32_t> &y) {
-                                     return x.first > y.first;
-                                 });
-                for (size_t i = 0; i < cand.size() && i < 16; i++) adj.push_back(cand[i].second);
+                std::stable_sort(cand.begin(), cand.end(), [](const Cand &x, const Cand &y) {
+                    return x.shared != y.shared ? x.shared > y.shared : x.v > y.v;
+                });
+                for (size_t i = 0; i < cand.size() && i < 16; i++) adj.push_back(cand[i].cell);
             }
         }
         adj_off[F.n_halfspaces] = (uint32_t)adj.size();
