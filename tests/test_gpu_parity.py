@@ -484,3 +484,56 @@ def test_autotune_batch_then_tuned_batch():
     torch.cuda.synchronize()
     for it, o in zip(items, want):
         assert_parity(_outs(it.out), o, where="tuned batch")
+
+
+def test_batch_of_one_staging_kind_matches_oracle():
+    """Every item forced to read its tables from global memory: one kind,
+    one launch on the caller's stream (no helper streams)."""
+    import torch
+    items, want = [], []
+    for k, j in enumerate(BATCH_SUBSET[:4]):
+        fg, n, G, O = batch_geoms(j)
+        n = min(n, 2000 + 211 * k)
+        items.append(gt.batch_item(G, synth.batch_particle_seed(j), n, geometry_id=synth.batch_geometry_id(j),
+                                   record_first_k=16, record_cap=64, staging=False))
+        want.append(oracle.track(O, oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=n,
+                                                       geometry_id=synth.batch_geometry_id(j),
+                                                       record_first_k=16, record_cap=64), n_threads=NT))
+    gt.track_batch(items, chunk=500)
+    torch.cuda.synchronize()
+    for j, it, o in zip(BATCH_SUBSET, items, want):
+        assert_parity(_outs(it.out), o, where="one-kind batch item %d" % j)
+
+
+def test_kernel_event_hook():
+    """gt_set_kernel_events brackets only the tracking kernel of a call: its
+    time is positive and within the whole call's; with the hook off the
+    events are left alone; one event alone is rejected."""
+    import ctypes as C
+    import torch
+    hip = C.CDLL("libamdhip64.so")
+    hip.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+    hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+    hip.hipEventDestroy.argtypes = [C.c_void_p]
+    a, b = C.c_void_p(), C.c_void_p()
+    assert hip.hipEventCreate(C.byref(a)) == 0 and hip.hipEventCreate(C.byref(b)) == 0
+    fg, G, O = geoms(2)
+    out = gt.alloc_outputs(G, 200_000)
+    try:
+        gt.set_kernel_events(a.value, b.value)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        gt.track(G, seed=5, n_particles=200_000, geometry_id=2, out=out)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = C.c_float()
+        assert hip.hipEventElapsedTime(C.byref(ms), a, b) == 0
+        assert 0.0 < ms.value <= t0.elapsed_time(t1) * 1.05 + 0.05
+    finally:
+        gt.set_kernel_events(None, None)
+    with pytest.raises(gt.GtError):
+        gt.set_kernel_events(a.value, None)
+    gt.track(G, seed=5, n_particles=1000, geometry_id=2, out=gt.alloc_outputs(G, 1000))
+    torch.cuda.synchronize()
+    hip.hipEventDestroy(a)
+    hip.hipEventDestroy(b)
