@@ -48,9 +48,10 @@ def parse():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of tracking, run a plain device copy of this many bytes --steps times "
                          "(reference kernel for scaling HBM counters)")
-    ap.add_argument("--only", choices=["mixed", "fp64", "plain_fp64", "batch"], default=None,
+    ap.add_argument("--only", choices=["mixed", "fp64", "plain_fp64", "event", "batch"], default=None,
                     help="time one mode only (profiling)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-geometry batched workload")
+    ap.add_argument("--no-event", action="store_true", help="skip the event-based schedule leg")
     ap.add_argument("--tail", action="store_true", help="switch on tail compaction (comparison)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the launch shape gt_autotune_track picks instead of the library default")
@@ -126,6 +127,20 @@ def timed(gt, G, out, args, prec, hev, lane=False):
     r["segments"] = out.counters_dict()["segments"]
     r["shape"] = {"block_size": kw["block_size"], "refill_min": kw["refill_min"],
                   "autotuned": shape is not None}
+    return r
+
+
+def timed_event(gt, G, args, hev):
+    """The event-based schedule on the same workload (mixed precision): one
+    kernel per tracking operation per iteration over a particle bank in
+    device memory (its own outputs and bank)."""
+    import torch
+    n = args.particles
+    out = gt.alloc_outputs(G, n)
+    bank = torch.empty(gt.event_bank_bytes(n), dtype=torch.uint8, device="cuda")
+    r = run_timed(gt, lambda: gt.track_event(G, seed=2002, n_particles=n, geometry_id=2, precision=gt.PREC_MIXED,
+                                             out=out, bank=bank), args, hev)
+    r["segments"] = out.counters_dict()["segments"]
     return r
 
 
@@ -264,12 +279,16 @@ def main():
         res[name] = timed(gt, G, out, args, prec, hev, lane)
         print("# %s: %.3f ms/step, %d segments/step" % (name, sum(res[name]["ms"]) / args.steps,
                                                         res[name]["segments"]), file=sys.stderr, flush=True)
+    if args.only in (None, "event") and not args.no_event:
+        res["event"] = timed_event(gt, G, args, hev)
+        print("# event: %.3f ms/step, %d segments/step" % (sum(res["event"]["ms"]) / args.steps,
+                                                           res["event"]["segments"]), file=sys.stderr, flush=True)
     bat = None
     if (args.only in (None, "batch")) and not args.no_batch:
         bat = batched(gt, synth, args, hev)
         print("# batch: %s" % json.dumps(bat), file=sys.stderr, flush=True)
-    if not res:
-        print(json.dumps({"batched": bat}), flush=True)
+    if not any(k in res for k in ("mixed", "fp64")):
+        print(json.dumps({"batched": bat, "event": res.get("event")}, default=str), flush=True)
         return
     head = res["mixed"] if "mixed" in res else res["fp64"]
     ms_step = sum(head["ms"]) / len(head["ms"])
@@ -293,7 +312,8 @@ def main():
                    "precision": "mixed" if "mixed" in res else "fp64", "parallelism": "none (1 GPU)",
                    "launch_shape": head["shape"]},
     }
-    for name, label in (("fp64", "fp64"), ("plain_fp64", "plain_fp64_lane_per_history")):
+    for name, label in (("fp64", "fp64"), ("plain_fp64", "plain_fp64_lane_per_history"),
+                        ("event", "event_based_mixed")):
         if name in res:
             f = res[name]
             fms = sum(f["ms"]) / len(f["ms"])
@@ -302,6 +322,8 @@ def main():
         line["mixed_over_fp64"] = line["value"] / line["fp64"]["value"]
     if "mixed" in res and "plain_fp64" in res:
         line["mixed_over_plain_fp64"] = line["value"] / line["plain_fp64_lane_per_history"]["value"]
+    if "mixed" in res and "event" in res:
+        line["persistent_over_event_based"] = line["value"] / line["event_based_mixed"]["value"]
     if bat is not None:
         line["batched"] = bat
     if not args.no_cpu_baseline:

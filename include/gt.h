@@ -218,6 +218,25 @@ typedef struct {
  * Asynchronous on `stream`; allocates nothing. */
 int gt_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream);
 
+/* ---- event-based schedule (for comparison) ------------------------------
+ * The histories and outputs of gt_track, computed the way an event-based GPU
+ * tracker is organised (Section "GPU-based implementation in Shift"): the
+ * particle state lives in a bank in device memory and every iteration runs
+ * one kernel per tracking operation over the whole bank -- distance to
+ * surface, then move / tally / collision, then cross surface -- until no
+ * history is left.  Each history takes the same steps in the same order as in
+ * gt_track, so every output is identical.
+ *   bank:  caller-owned device memory of at least gt_event_bank_bytes(n)
+ *          bytes, 256-byte aligned, contents overwritten (may be NULL when
+ *          n_particles is 0);
+ *   flags: GT_FLAG_ACCUMULATE only; block_size and refill_min must be 0.
+ * The host reads the number of live histories back every 8 iterations, so the
+ * call waits for `stream` and cannot be captured into a graph.  Errors as
+ * gt_track, and GT_EINVAL for a missing, short or misaligned bank. */
+uint64_t gt_event_bank_bytes(uint64_t n_particles);   /* 0 above the particle limit */
+int gt_track_event(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *bank,
+                   uint64_t bank_bytes, void *stream);
+
 /* ---- many geometries in one launch -------------------------------------- */
 typedef struct gt_batch gt_batch;   /* opaque: device descriptors of a batch */
 

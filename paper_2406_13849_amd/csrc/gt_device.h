@@ -584,8 +584,10 @@ __device__ __forceinline__ int cross(const G &g, Particle &P, int Ls, uint32_t s
 // its own 64-bit counter with an atomic whose result is not used, so no
 // carry has to travel back to the lane; the counters are exact for up to
 // 2^32 contributions per instance and launch.  Each XCD adds into its own
-// replica of the counters, so the atomics stay in that XCD's L2; the
-// finalize kernel folds replicas and limbs into the 128-bit total.
+// replica of the counters (on device memory of the default type the L2
+// forwards these atomics to the memory side; the replicas keep the XCDs off
+// each other's addresses); the finalize kernel folds replicas and limbs into
+// the 128-bit total.
 constexpr int kReplicas = 8;
 
 __device__ __forceinline__ uint32_t xcc_id() {

@@ -783,6 +783,49 @@ extern "C" int gt_track(const gt_geometry *g, const gt_track_params *p, const gt
     return launch_track(g, p, o, stream);
 }
 
+namespace gt {
+// The event bank's arrays, each 256-byte aligned from `base` (which may be
+// null to size it); returns the bytes used.
+uint64_t ev_layout(uint64_t n, unsigned char *base, EvBank *b) {
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        unsigned char *p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~(uint64_t)255;
+        return p;
+    };
+    EvBank e;
+    double **d[] = {&e.x, &e.y, &e.z, &e.u, &e.v, &e.w, &e.tau, &e.t, &e.sig};
+    for (double **q : d) *q = (double *)take(8 * n);
+    uint64_t **w[] = {&e.h, &e.acc_lo, &e.acc_hi};
+    for (uint64_t **q : w) *q = (uint64_t *)take(8 * n);
+    e.cell = (uint32_t *)take(4 * n * GT_MAX_LEVELS);
+    uint32_t **u[] = {&e.on_surf, &e.blk, &e.segs, &e.ncoll, &e.acc_inst, &e.surf, &e.inst, &e.st};
+    for (uint32_t **q : u) *q = (uint32_t *)take(4 * n);
+    e.alive = (unsigned long long *)take(16);
+    if (b) *b = e;
+    return off;
+}
+}  // namespace gt
+
+extern "C" uint64_t gt_event_bank_bytes(uint64_t n_particles) {
+    if (n_particles > (uint64_t)0x7FFFFFFF * 64ull) return 0;
+    return ev_layout(n_particles, nullptr, nullptr);
+}
+
+extern "C" int gt_track_event(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *bank,
+                              uint64_t bank_bytes, void *stream) {
+    int rc = check_track_args(g, p, o);
+    if (rc) return rc;
+    if (p->flags & ~GT_FLAG_ACCUMULATE)
+        return set_error("gt_track_event: only GT_FLAG_ACCUMULATE applies"), GT_EINVAL;
+    if (p->block_size || p->refill_min) return set_error("gt_track_event: no launch shape to set"), GT_EINVAL;
+    const uint64_t need = ev_layout(p->n_particles, nullptr, nullptr);
+    if (p->n_particles && (!bank || bank_bytes < need))
+        return set_error("gt_track_event: the bank needs %llu bytes", (unsigned long long)need), GT_EINVAL;
+    if (((uintptr_t)bank) & 255u) return set_error("gt_track_event: the bank must be 256-byte aligned"), GT_EINVAL;
+    return launch_event(g, p, o, bank, stream);
+}
+
 extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, const gt_tuning *tuning, gt_batch **out) {
     if (!out || (n_items && !items)) return set_error("gt_batch_create: null argument"), GT_EINVAL;
     *out = nullptr;

@@ -153,6 +153,20 @@ struct BatchChunk {
     uint64_t first, count;
 };
 
+// Particle bank of the event-based schedule: structure of arrays in device
+// memory, n entries each (the caller's buffer, laid out by ev_layout).
+struct EvBank {
+    double *x, *y, *z, *u, *v, *w, *tau;
+    double *t, *sig;                 // distance to the nearest surface and Sigma of the leaf, this segment
+    uint64_t *h, *acc_lo, *acc_hi;   // sequence hash; the history's open tally sum (128-bit)
+    uint32_t *cell;                  // GT_MAX_LEVELS x n, level-major
+    uint32_t *on_surf, *blk, *segs, *ncoll, *acc_inst, *surf, *inst;
+    uint32_t *st;                    // packed: depth | on_level + 1 << 4 | end << 8 | nearest level << 12 |
+                                     // nearest sense << 16 | crossing pending << 17 | record overflow << 18 |
+                                     // finished << 19
+    unsigned long long *alive;       // [2]: histories left after an iteration (alternating)
+};
+
 struct FillRange {
     void *ptr;
     uint64_t count, value;
@@ -222,4 +236,6 @@ int launch_distance(const gt_geometry *g, const double *pos, const double *dir, 
                     int32_t *level, int32_t *surf, void *stream);
 int launch_fp64_check(const double *a, const double *b, uint64_t n, double *q, double *r, double *l,
                       void *stream);
+uint64_t ev_layout(uint64_t n, unsigned char *base, EvBank *b);
+int launch_event(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *bank, void *stream);
 }  // namespace gt

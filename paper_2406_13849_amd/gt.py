@@ -93,6 +93,10 @@ def lib():
         L.gt_geometry_destroy.restype = None
         L.gt_track.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), vp]
         L.gt_track.restype = i32
+        L.gt_event_bank_bytes.argtypes = [u64]
+        L.gt_event_bank_bytes.restype = u64
+        L.gt_track_event.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), vp, u64, vp]
+        L.gt_track_event.restype = i32
         L.gt_batch_create.argtypes = [C.POINTER(_BatchItem), u32, C.POINTER(_Tuning), C.POINTER(vp)]
         L.gt_batch_create.restype = i32
         L.gt_batch_launch.argtypes = [vp, vp]
@@ -244,6 +248,30 @@ def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 
                   refill_min, tail_compaction, tally_cache)
     o = _out_struct(out)
     _check(lib().gt_track(geom.h, C.byref(prm), C.byref(o), _stream(stream)))
+    return out
+
+
+def event_bank_bytes(n_particles: int) -> int:
+    """gt_event_bank_bytes: device bytes of the event-based schedule's bank."""
+    return int(lib().gt_event_bank_bytes(n_particles))
+
+
+def track_event(geom: Geometry, seed: int, n_particles: int, *, bank=None, out: Optional[TrackOutputs] = None,
+                stream=None, **kwargs) -> TrackOutputs:
+    """gt_track_event: the same histories and outputs as track(), by the
+    event-based schedule (one kernel per operation per iteration over a
+    particle bank in device memory; waits for the stream).  kwargs as
+    track() (first_particle, geometry_id, max_collisions, source, ray_n1,
+    max_segments, precision, record_first_k, record_cap, accumulate)."""
+    import torch
+    if out is None:
+        out = alloc_outputs(geom, n_particles, kwargs.get("record_first_k", 0), kwargs.get("record_cap", 0))
+    need = event_bank_bytes(n_particles)
+    if bank is None:
+        bank = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+    prm = _params(seed, n_particles, **kwargs)
+    o = _out_struct(out)
+    _check(lib().gt_track_event(geom.h, C.byref(prm), C.byref(o), _ptr(bank), bank.numel(), _stream(stream)))
     return out
 
 

@@ -38,6 +38,9 @@ int launch_track(const gt_geometry *, const gt_track_params *, const gt_track_ou
     return set_error("host build: no kernels"), GT_EHIP;
 }
 int launch_batch(gt_batch *, void *) { return set_error("host build: no kernels"), GT_EHIP; }
+int launch_event(const gt_geometry *, const gt_track_params *, const gt_track_out *, void *, void *) {
+    return set_error("host build: no kernels"), GT_EHIP;
+}
 int prepare_batch_streams(gt_batch *) { return GT_OK; }
 void release_batch_streams(gt_batch *) {}
 int launch_find_cell(const gt_geometry *, const double *, uint64_t, int64_t *, int32_t *, uint32_t, void *) {

@@ -205,3 +205,17 @@ print("asan clean")
     env = dict(os.environ, LD_PRELOAD=rt, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0 and "asan clean" in r.stdout, (r.stdout[-2000:] + r.stderr[-4000:])
+
+
+def test_event_bank_layout(host):
+    """gt_event_bank_bytes: 256-byte multiples growing with the particle
+    count, 0 above the particle limit (host-only arithmetic)."""
+    f = host.L.gt_event_bank_bytes
+    f.argtypes = [C.c_uint64]
+    f.restype = C.c_uint64
+    prev = 0
+    for n in (0, 1, 255, 256, 1000, 10**6):
+        b = f(n)
+        assert b % 256 == 0 and b >= prev and b >= 152 * n
+        prev = b
+    assert f(0x7FFFFFFF * 64 + 1) == 0

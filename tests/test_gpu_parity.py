@@ -537,3 +537,62 @@ def test_kernel_event_hook():
     torch.cuda.synchronize()
     hip.hipEventDestroy(a)
     hip.hipEventDestroy(b)
+
+
+# ---------------------------------------------------------------- event-based schedule
+EVENT_CASES = [c for c in CASES if c[0] in ("sphere", 1, 2, 3, 4, "hex_pin_box")]
+
+
+@pytest.mark.parametrize("case", EVENT_CASES, ids=[str(c[0]) for c in EVENT_CASES])
+@pytest.mark.parametrize("prec", [gt.PREC_FP64, gt.PREC_MIXED])
+def test_event_based_parity(case, prec):
+    """The event-based schedule (one kernel per operation over a bank in
+    device memory) gives the oracle's histories and tallies."""
+    import torch
+    cfg, kw, k, cap = case
+    fg, G, O = geoms(cfg)
+    kw = dict(kw, n_particles=min(kw["n_particles"], 6000))
+    print("event parity", cfg, kw, "precision", prec, flush=True)
+    out = gt.track_event(G, precision=prec, record_first_k=min(k, 500), record_cap=cap, **kw)
+    torch.cuda.synchronize()
+    g = dict(tally_fx=_np(out.tally_fx).view(np.uint64), tally=_np(out.tally),
+             seg_count=_np(out.seg_count).view(np.uint32), seq_hash=_np(out.seq_hash).view(np.uint64),
+             end_code=_np(out.end_code), rec=_np(out.rec), counters=out.counters_dict())
+    o = oracle.track(O, oracle.TrackParams(record_first_k=min(k, 500), record_cap=cap, **kw), n_threads=NT)
+    assert_parity(g, o, where="event cfg %s prec %d" % (cfg, prec))
+
+
+def test_event_based_rays_and_caps():
+    """Ray source (no collisions), a segment cap and a collision cap."""
+    import torch
+    fg, G, O = geoms(2)
+    for kw in (dict(seed=0, n_particles=1700 * 3, source=1, ray_n1=1700, max_collisions=1),
+               dict(seed=8, n_particles=3000, geometry_id=2, max_segments=7),
+               dict(seed=9, n_particles=3000, geometry_id=2, max_collisions=1)):
+        out = gt.track_event(G, precision=gt.PREC_MIXED, **kw)
+        torch.cuda.synchronize()
+        g = dict(tally_fx=_np(out.tally_fx).view(np.uint64), tally=_np(out.tally),
+                 seg_count=_np(out.seg_count).view(np.uint32), seq_hash=_np(out.seq_hash).view(np.uint64),
+                 end_code=_np(out.end_code), rec=None, counters=out.counters_dict())
+        assert_parity(g, oracle.track(O, oracle.TrackParams(**kw), n_threads=NT), where="event %s" % kw)
+
+
+def test_event_based_invalid_arguments():
+    import torch
+    fg, G, O = geoms(1)
+    n = 1000
+    need = gt.event_bank_bytes(n)
+    assert need > 0 and need % 256 == 0 and gt.event_bank_bytes(2 * n) > need
+    short = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gt.GtError):
+        gt.track_event(G, seed=1, n_particles=n, bank=short)
+    big = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gt.GtError):
+        gt.track_event(G, seed=1, n_particles=n, bank=big[8:])
+    with pytest.raises(gt.GtError):
+        gt.track_event(G, seed=1, n_particles=n, lane_per_history=True)
+    with pytest.raises(gt.GtError):
+        gt.track_event(G, seed=1, n_particles=n, block_size=256)
+    out = gt.track_event(G, seed=1, n_particles=0)
+    torch.cuda.synchronize()
+    assert int(out.counters.sum().item()) == 0
