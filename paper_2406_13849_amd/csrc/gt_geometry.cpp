@@ -799,7 +799,7 @@ uint64_t ev_layout(uint64_t n, unsigned char *base, EvBank *b) {
     uint64_t **w[] = {&e.h, &e.acc_lo, &e.acc_hi};
     for (uint64_t **q : w) *q = (uint64_t *)take(8 * n);
     e.cell = (uint32_t *)take(4 * n * GT_MAX_LEVELS);
-    uint32_t **u[] = {&e.on_surf, &e.blk, &e.segs, &e.ncoll, &e.acc_inst, &e.surf, &e.inst, &e.st};
+    uint32_t **u[] = {&e.on_surf, &e.blk, &e.segs, &e.ncoll, &e.acc_inst, &e.surf, &e.inst, &e.entry, &e.st};
     for (uint32_t **q : u) *q = (uint32_t *)take(4 * n);
     e.alive = (unsigned long long *)take(16);
     if (b) *b = e;

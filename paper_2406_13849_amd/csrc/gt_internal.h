@@ -161,6 +161,7 @@ struct EvBank {
     uint64_t *h, *acc_lo, *acc_hi;   // sequence hash; the history's open tally sum (128-bit)
     uint32_t *cell;                  // GT_MAX_LEVELS x n, level-major
     uint32_t *on_surf, *blk, *segs, *ncoll, *acc_inst, *surf, *inst;
+    uint32_t *entry;                 // half-space entry of the nearest surface (its candidate list)
     uint32_t *st;                    // packed: depth | on_level + 1 << 4 | end << 8 | nearest level << 12 |
                                      // nearest sense << 16 | crossing pending << 17 | record overflow << 18 |
                                      // finished << 19

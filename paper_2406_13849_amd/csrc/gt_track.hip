@@ -52,12 +52,13 @@ __global__ void __launch_bounds__(kBlock) k_track(Dev g0, KParams p, KOut o) {
 }
 
 // ------------------------------------------------------------------ event-based schedule
-// The same histories as run_history, with the state in a bank in device
-// memory and one kernel per operation over the whole bank per iteration:
+// The same histories as gt_track, with the state in a bank in device memory
+// and one kernel per operation over the whole bank per iteration:
 // distance_to_surface, then move / tally / collision, then cross_surface
 // (the organisation of an event-based tracker; kept for comparison).  Each
-// kernel loads a history from the bank, takes its one step with the same
-// device functions and operation order as run_history, and stores it back.
+// kernel loads a history from the bank, takes its one step with the device
+// functions of the persistent schedule (slab pairs, candidate lists) in the
+// operation order of run_history, and stores it back.
 constexpr uint32_t kEvDone = 1u << 19, kEvPending = 1u << 17, kEvRecOvf = 1u << 18;
 
 __device__ __forceinline__ uint32_t ev_pack(int depth, int on_level, int end, int bl, bool bpos, bool pending,
@@ -77,12 +78,70 @@ __device__ __forceinline__ void ev_load(const EvBank &b, uint64_t n, uint64_t i,
     P.depth = (int)(st & 15u);
     P.on_level = (int)((st >> 4) & 15u) - 1;
     P.on_surf = b.on_surf[i];
-    for (int L = 0; L < P.depth; L++) lvl(P, L) = b.cell[(size_t)L * n + i];
+    // levels below the history's depth read as cell 0 (a descent's hint
+    // reads the previous cell of each level it enters)
+    for (int L = 0; L < GT_MAX_LEVELS; L++) lvl(P, L) = L < P.depth ? b.cell[(size_t)L * n + i] : 0u;
 }
 
 __device__ __forceinline__ void ev_store_geom(const EvBank &b, uint64_t n, uint64_t i, const Particle &P) {
     for (int L = 0; L < P.depth; L++) b.cell[(size_t)L * n + i] = lvl(P, L);
     b.on_surf[i] = P.on_surf;
+}
+
+// cross_surface as the persistent schedule takes it: the crossed
+// half-space's candidate list first, then the full search, then descent.
+template <int PREC, typename G>
+__device__ __forceinline__ int cross_listed(const G &g, Particle &P, int Ls, uint32_t ss, bool old_pos,
+                                            uint32_t entry) {
+    double qx = P.x, qy = P.y, qz = P.z;
+    uint32_t univ = g.root;
+    for (int L = 0; L < Ls; L++) {
+        const uint32_t c = lvl(P, L);
+        const auto t = g.trans + 4 * (size_t)c;
+        qx = qx - t[0];
+        qy = qy - t[1];
+        qz = qz - t[2];
+        univ = (uint32_t)(-g.cell[c].fill - 1);
+    }
+    const uint32_t old = lvl(P, Ls);
+    int32_t c = -1, fill = 0;
+    for (uint32_t k = g.adj_off[entry]; k < g.adj_off[entry + 1]; k++) {
+        const uint32_t d = g.adj[k];
+        if (contains(g, d, qx, qy, qz, ss, !old_pos, fill)) {
+            c = (int32_t)d;
+            break;
+        }
+    }
+    if (c < 0)
+        c = search<PREC>(g, univ, qx, qy, qz, ss, !old_pos, (int32_t)old, (float)P.u * 1e-3f, (float)P.v * 1e-3f,
+                         fill);
+    if (c < 0) return Ls == 0 ? GT_END_ESCAPE : GT_END_LOST;
+    lvl(P, Ls) = (uint32_t)c;
+    // descent: first the cell with the same index in the new universe as the
+    // history had at that level before, then the full search
+    int L = Ls;
+    while (fill < 0) {
+        const auto t = g.trans + 4 * (size_t)lvl(P, L);
+        qx = qx - t[0];
+        qy = qy - t[1];
+        qz = qz - t[2];
+        const uint32_t u = (uint32_t)(-fill - 1);
+        L++;
+        const Univ U = ldv<Univ>(g.univ + u);
+        const uint32_t loc = g.cell_local[lvl(P, L)];
+        int32_t d = -1;
+        if (loc < U.ncell && contains(g, U.cell0 + loc, qx, qy, qz, kNone, false, fill)) d = (int32_t)(U.cell0 + loc);
+        if (d < 0) d = search<PREC>(g, u, qx, qy, qz, kNone, false, -1, 0.0f, 0.0f, fill);
+        if (d < 0) {
+            P.depth = L;
+            return GT_END_LOST;
+        }
+        lvl(P, L) = (uint32_t)d;
+    }
+    P.depth = L + 1;
+    P.on_level = Ls;
+    P.on_surf = ss;
+    return GT_END_NONE;
 }
 
 // A history's end: its open tally sum, hash and outputs (as run_history).
@@ -112,6 +171,7 @@ __global__ void __launch_bounds__(kBlock) k_ev_birth(Dev g0, KParams p, KOut o, 
     if (i < p.n) {
         Particle P;
         P.cell = cells + threadIdx.x;
+        for (int L = 0; L < GT_MAX_LEVELS; L++) lvl(P, L) = 0;
         const uint64_t pid = p.first + i;
         uint32_t blk = 0;
         P.on_level = -1;
@@ -183,7 +243,8 @@ __global__ void __launch_bounds__(kBlock) k_ev_birth(Dev g0, KParams p, KOut o, 
     add_counts(cnt, o.counters);
 }
 
-// distance_to_surface over every level, with the leaf's Sigma and instance.
+// distance_to_surface over every level (as the persistent schedule takes it),
+// with the leaf's Sigma and instance.
 template <int PREC>
 __global__ void __launch_bounds__(kBlock) k_ev_distance(Dev g0, uint64_t n, EvBank b) {
     __shared__ uint32_t cells[GT_MAX_LEVELS * kBlock];
@@ -195,15 +256,14 @@ __global__ void __launch_bounds__(kBlock) k_ev_distance(Dev g0, uint64_t n, EvBa
     Particle P;
     P.cell = cells + threadIdx.x;
     ev_load(b, n, i, st, P);
-    int bl;
-    uint32_t bs, bk;
-    bool bpos;
-    b.t[i] = distance_all(g, P, bl, bs, bpos, bk);
-    const uint32_t lc = lvl(P, P.depth - 1);
-    b.sig[i] = g.sigma[g.cell[lc].fill];
-    b.inst[i] = leaf_instance(g, P);
-    b.surf[i] = bs;
-    b.st[i] = (st & ~(0xFu << 12 | 1u << 16)) | (uint32_t)bl << 12 | (uint32_t)bpos << 16;
+    Nearest nr;
+    nearest_surface(g, P, nr);
+    b.t[i] = nr.t;
+    b.sig[i] = g.sigma[nr.leaf_fill];
+    b.inst[i] = nr.inst;
+    b.surf[i] = nr.surf;
+    b.entry[i] = nr.entry;
+    b.st[i] = (st & ~(0xFu << 12 | 1u << 16)) | (uint32_t)nr.level << 12 | (uint32_t)nr.pos << 16;
 }
 
 // The segment: boundary or collision, move, tally, sequence, new direction.
@@ -307,7 +367,7 @@ __global__ void __launch_bounds__(kBlock) k_ev_cross(Dev g0, KParams p, KOut o, 
         ev_load(b, p.n, i, st, P);
         const int bl = (int)((st >> 12) & 15u);
         const bool bpos = (st >> 16) & 1u;
-        int end = cross<PREC>(g, P, bl, b.surf[i], bpos);
+        int end = cross_listed<PREC>(g, P, bl, b.surf[i], bpos, b.entry[i]);
         ev_store_geom(b, p.n, i, P);
         if (end == GT_END_NONE && b.segs[i] >= p.max_segs) end = GT_END_SEGCAP;
         const bool recovf = (st & kEvRecOvf) != 0;
