@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 # the tracker is compiled without contraction, so every add/mul/div/sqrt is
 # one operation).
 PEAK_FP64_OPS = 256 * 64 * 2.4e9
+PEAK_HBM = 8.0e12                     # bytes/s, MI355X HBM3E
 
 
 def parse():
@@ -339,6 +340,18 @@ def main():
                             "traffic": traffic_per_launch(),
                             "ops_per_segment": cb["ops_per_segment"], "kernel_ms": kernel_ms,
                             "kernel": "k_track_persistent<mixed, staged>"}
+        # the HBM side of the same kernel: algorithmic bytes (per-particle
+        # outputs; no sequences are recorded here, the tallies fit in the L2)
+        # and the measured bytes per launch from the committed counters
+        alg = 13.0 * n / head["segments"]
+        tr = line["roofline"]["traffic"]
+        line["hbm"] = {"algorithmic_bytes_per_segment": alg,
+                       "algorithmic_GBps": alg * seg_s / 1e9,
+                       "measured_bytes_per_launch": tr,
+                       "measured_GBps": (tr / (kernel_ms * 1e-3) / 1e9) if tr else None,
+                       "peak_GBps": PEAK_HBM / 1e9,
+                       "algorithmic_frac": alg * seg_s / PEAK_HBM,
+                       "measured_frac": (tr / (kernel_ms * 1e-3) / PEAK_HBM) if tr else None}
     print(json.dumps(line), flush=True)
 
 
