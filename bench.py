@@ -280,6 +280,17 @@ def main():
         res[name] = timed(gt, G, out, args, prec, hev, lane)
         print("# %s: %.3f ms/step, %d segments/step" % (name, sum(res[name]["ms"]) / args.steps,
                                                         res[name]["segments"]), file=sys.stderr, flush=True)
+    if args.only is None:
+        # the same workload with the lattice hints removed: no FP32 index
+        # guess, every full search through the hierarchy (the plain single
+        # tracker against its lattice-aware form)
+        fg2 = synth.make_config(2)
+        fg2.lattice_hint[:] = 0
+        G2 = gt.Geometry(fg2)
+        res["nohint"] = timed(gt, G2, gt.alloc_outputs(G2, n), args, gt.PREC_MIXED, hev, False)
+        print("# mixed without lattice hints: %.3f ms/step" % (sum(res["nohint"]["ms"]) / args.steps),
+              file=sys.stderr, flush=True)
+        G2.close()
     if args.only in (None, "event") and not args.no_event:
         res["event"] = timed_event(gt, G, args, hev)
         print("# event: %.3f ms/step, %d segments/step" % (sum(res["event"]["ms"]) / args.steps,
@@ -314,7 +325,7 @@ def main():
                    "launch_shape": head["shape"]},
     }
     for name, label in (("fp64", "fp64"), ("plain_fp64", "plain_fp64_lane_per_history"),
-                        ("event", "event_based_mixed")):
+                        ("event", "event_based_mixed"), ("nohint", "mixed_without_lattice_hints")):
         if name in res:
             f = res[name]
             fms = sum(f["ms"]) / len(f["ms"])
