@@ -947,7 +947,8 @@ struct ChunkQueue {
 // the buffer at its rank and read back by the lane of that rank, so fewer,
 // fuller waves carry the tail while the emptied ones wait at the barrier.  A
 // history's state moves as a whole, so its results do not depend on the lane
-// that finishes it.
+// that finishes it.  Optional (off by default): waves that wait for the tail
+// keep taking issue slots that finished waves would leave to working ones.
 constexpr int kTailFields = 16;   // 64-bit words per moved history
 constexpr uint32_t kTailRound = 8;
 
@@ -1330,8 +1331,6 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
     }
 }
 
-// Dynamic LDS of the persistent kernels: the level columns, the staged
-// tables at byte offset tables_at, then the tail buffer at tail_at.
 // Fold the replicas' limb counters of instance i into the 128-bit
 // fixed-point total (plus the previous total when accumulating), then convert
 // it to cm: high word * 2^-32 + low word * 2^-96.

@@ -632,9 +632,11 @@ int allow_dynamic_lds(const void *kernel, unsigned bytes) {
     return GT_OK;
 }
 
-// LDS of a persistent launch: the staged tables (if any), then the tail
-// buffer, as large as the workgroup's share of the compute unit's LDS allows
-// without lowering the number of resident workgroups.
+// LDS of a persistent launch: the level columns, the staged tables (if any),
+// the tally cache (up to kTallyCacheMax entries per lane), then the tail
+// buffer (with tail compaction), as large as the workgroup's share of the
+// compute unit's LDS allows without lowering the number of resident
+// workgroups.
 struct LdsPlan {
     unsigned dyn, tables_at, tail_at, tail_cap, cache_at, cache_k;
     int blocks;
