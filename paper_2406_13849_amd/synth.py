@@ -602,7 +602,7 @@ def box(half: Tuple[float, float, float] = (1.0, 1.0, 1.0), sigma: float = 1.0) 
     return b.build(root, [sigma], (-hx, -hy, -hz), (hx, hy, hz), "box")
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
+WORKLOADS = {1: config1, 2: config2, 3: config3, 4: config4}
 
 # particle counts of the workload table, and the seeds: geometry 1000+i,
 # particles 2000+i.
@@ -610,7 +610,7 @@ CONFIG_PARTICLES = {1: 10_000, 2: 1_000_000, 3: 10_000_000, 4: 10_000_000}
 
 
 def make_config(i: int) -> FlatGeometry:
-    return CONFIGS[i](1000 + i)
+    return WORKLOADS[i](1000 + i)
 
 
 def particle_seed(i: int) -> int:
