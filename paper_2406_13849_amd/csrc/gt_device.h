@@ -1331,6 +1331,315 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
     }
 }
 
+// ------------------------------------------------------------------ event-based schedule
+// The same histories as gt_track, with the state in a bank in device memory
+// and one kernel per operation over the whole bank per iteration:
+// distance_to_surface, then move / tally / collision, then cross_surface
+// (the organisation of an event-based tracker; kept for comparison).  Each
+// step below loads history i from the bank, takes its one step with the
+// device functions of the persistent schedule (slab pairs, candidate lists)
+// in the operation order of run_history, and stores it back.
+constexpr uint32_t kEvDone = 1u << 19, kEvPending = 1u << 17, kEvRecOvf = 1u << 18;
+
+__device__ __forceinline__ uint32_t ev_pack(int depth, int on_level, int end, int bl, bool bpos, bool pending,
+                                            bool recovf, bool done) {
+    return (uint32_t)depth | (uint32_t)(on_level + 1) << 4 | (uint32_t)end << 8 | (uint32_t)bl << 12 |
+           (uint32_t)bpos << 16 | (uint32_t)pending << 17 | (uint32_t)recovf << 18 | (uint32_t)done << 19;
+}
+
+__device__ __forceinline__ void ev_load(const EvBank &b, uint64_t n, uint64_t i, uint32_t st, Particle &P) {
+    P.x = b.x[i];
+    P.y = b.y[i];
+    P.z = b.z[i];
+    P.u = b.u[i];
+    P.v = b.v[i];
+    P.w = b.w[i];
+    P.tau = b.tau[i];
+    P.depth = (int)(st & 15u);
+    P.on_level = (int)((st >> 4) & 15u) - 1;
+    P.on_surf = b.on_surf[i];
+    // levels below the history's depth read as cell 0 (a descent's hint
+    // reads the previous cell of each level it enters)
+    for (int L = 0; L < GT_MAX_LEVELS; L++) lvl(P, L) = L < P.depth ? b.cell[(size_t)L * n + i] : 0u;
+}
+
+__device__ __forceinline__ void ev_store_geom(const EvBank &b, uint64_t n, uint64_t i, const Particle &P) {
+    for (int L = 0; L < P.depth; L++) b.cell[(size_t)L * n + i] = lvl(P, L);
+    b.on_surf[i] = P.on_surf;
+}
+
+// cross_surface as the persistent schedule takes it: the crossed
+// half-space's candidate list first, then the full search, then descent.
+template <int PREC, typename G>
+__device__ __forceinline__ int cross_listed(const G &g, Particle &P, int Ls, uint32_t ss, bool old_pos,
+                                            uint32_t entry) {
+    double qx = P.x, qy = P.y, qz = P.z;
+    uint32_t univ = g.root;
+    for (int L = 0; L < Ls; L++) {
+        const uint32_t c = lvl(P, L);
+        const auto t = g.trans + 4 * (size_t)c;
+        qx = qx - t[0];
+        qy = qy - t[1];
+        qz = qz - t[2];
+        univ = (uint32_t)(-g.cell[c].fill - 1);
+    }
+    const uint32_t old = lvl(P, Ls);
+    int32_t c = -1, fill = 0;
+    for (uint32_t k = g.adj_off[entry]; k < g.adj_off[entry + 1]; k++) {
+        const uint32_t d = g.adj[k];
+        if (contains(g, d, qx, qy, qz, ss, !old_pos, fill)) {
+            c = (int32_t)d;
+            break;
+        }
+    }
+    if (c < 0)
+        c = search<PREC>(g, univ, qx, qy, qz, ss, !old_pos, (int32_t)old, (float)P.u * 1e-3f, (float)P.v * 1e-3f,
+                         fill);
+    if (c < 0) return Ls == 0 ? GT_END_ESCAPE : GT_END_LOST;
+    lvl(P, Ls) = (uint32_t)c;
+    // descent: first the cell with the same index in the new universe as the
+    // history had at that level before, then the full search
+    int L = Ls;
+    while (fill < 0) {
+        const auto t = g.trans + 4 * (size_t)lvl(P, L);
+        qx = qx - t[0];
+        qy = qy - t[1];
+        qz = qz - t[2];
+        const uint32_t u = (uint32_t)(-fill - 1);
+        L++;
+        const Univ U = ldv<Univ>(g.univ + u);
+        const uint32_t loc = g.cell_local[lvl(P, L)];
+        int32_t d = -1;
+        if (loc < U.ncell && contains(g, U.cell0 + loc, qx, qy, qz, kNone, false, fill)) d = (int32_t)(U.cell0 + loc);
+        if (d < 0) d = search<PREC>(g, u, qx, qy, qz, kNone, false, -1, 0.0f, 0.0f, fill);
+        if (d < 0) {
+            P.depth = L;
+            return GT_END_LOST;
+        }
+        lvl(P, L) = (uint32_t)d;
+    }
+    P.depth = L + 1;
+    P.on_level = Ls;
+    P.on_surf = ss;
+    return GT_END_NONE;
+}
+
+// A history's end: its open tally sum, hash and outputs (as run_history).
+__device__ __forceinline__ void ev_finish(const EvBank &b, const KOut &o, uint64_t *rep, uint64_t i, int end,
+                                          bool recovf, Counts &cnt) {
+    TallyAcc acc;
+    acc.inst = b.acc_inst[i];
+    acc.lo = b.acc_lo[i];
+    acc.hi = b.acc_hi[i];
+    tally_flush(rep, acc);
+    b.acc_inst[i] = kNone;
+    const uint64_t h = b.h[i] ^ (uint64_t)end;
+    const uint32_t segs = b.segs[i];
+    if (o.seg_count) gstore(o.seg_count, i, segs);
+    if (o.seq_hash) gstore(o.seq_hash, i, h);
+    if (o.end_code) gstore(o.end_code, i, end);
+    count_end(cnt, end, segs, recovf);
+}
+
+// Birth of history i (as run_history), written to the bank.
+template <int PREC, typename G>
+__device__ __forceinline__ void ev_birth(const G &g, const KParams &p, const KOut &o, const EvBank &b, uint64_t *rep,
+                                         uint64_t i, uint32_t *cells, Counts &cnt) {
+    {
+        Particle P;
+        P.cell = cells;
+        for (int L = 0; L < GT_MAX_LEVELS; L++) lvl(P, L) = 0;
+        const uint64_t pid = p.first + i;
+        uint32_t blk = 0;
+        P.on_level = -1;
+        P.on_surf = kNone;
+        P.depth = 1;
+        P.u = P.v = P.w = P.tau = 0.0;
+        int end = GT_END_NONE;
+        double u0, u1, u2;
+        if (p.source == 1) {
+            const uint64_t n1 = p.ray_n1;
+            const uint64_t n2 = (p.n + n1 - 1) / n1;
+            const uint64_t j = pid % n1, k = pid / n1;
+            const double hy = (g.hi[1] - g.lo[1]) / (double)n1;
+            const double hz = (g.hi[2] - g.lo[2]) / (double)n2;
+            P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * 0x1p-30;
+            P.y = g.lo[1] + ((double)j + 0.5) * hy;
+            P.z = g.lo[2] + ((double)k + 0.5) * hz;
+            P.u = 1.0;
+            P.v = 0.0;
+            P.w = 0.0;
+            P.tau = 0.0;
+            int32_t rfill;
+            const int32_t c = search<PREC>(g, g.root, P.x, P.y, P.z, kNone, false, -1, 0.0f, 0.0f, rfill);
+            if (c < 0) {
+                end = GT_END_LOST;
+            } else {
+                lvl(P, 0) = (uint32_t)c;
+                if (!descend<PREC>(g, P, 0, P.x, P.y, P.z)) end = GT_END_LOST;
+            }
+        } else {
+            int32_t c = -1, rfill;
+            for (int a = 0; a < kMaxBirthAttempts && c < 0; a++) {
+                draw_block(p.seed, p.geom_id, pid, blk++, u0, u1, u2);
+                P.x = g.lo[0] + (g.hi[0] - g.lo[0]) * u0;
+                P.y = g.lo[1] + (g.hi[1] - g.lo[1]) * u1;
+                P.z = g.lo[2] + (g.hi[2] - g.lo[2]) * u2;
+                c = search<PREC>(g, g.root, P.x, P.y, P.z, kNone, false, -1, 0.0f, 0.0f, rfill);
+                if (c < 0) cnt.rejected++;
+            }
+            if (c < 0) {
+                end = GT_END_LOST;
+            } else {
+                lvl(P, 0) = (uint32_t)c;
+                if (!descend<PREC>(g, P, 0, P.x, P.y, P.z)) end = GT_END_LOST;
+                do draw_block(p.seed, p.geom_id, pid, blk++, u0, u1, u2);
+                while (!direction_from(u0, u1, P.u, P.v, P.w));
+                P.tau = -series_log(u2);
+            }
+        }
+        b.x[i] = P.x;
+        b.y[i] = P.y;
+        b.z[i] = P.z;
+        b.u[i] = P.u;
+        b.v[i] = P.v;
+        b.w[i] = P.w;
+        b.tau[i] = P.tau;
+        if (P.depth < 1) P.depth = 1;
+        ev_store_geom(b, p.n, i, P);
+        b.blk[i] = blk;
+        b.segs[i] = 0;
+        b.ncoll[i] = 0;
+        b.h[i] = kFnvOffset;
+        b.acc_inst[i] = kNone;
+        b.acc_lo[i] = 0;
+        b.acc_hi[i] = 0;
+        b.st[i] = ev_pack(P.depth, P.on_level, end, 0, false, false, false, end != GT_END_NONE);
+        if (end != GT_END_NONE) ev_finish(b, o, rep, i, end, false, cnt);
+    }
+}
+
+// distance_to_surface over every level (as the persistent schedule takes it),
+// with the leaf's Sigma and instance.
+template <typename G>
+__device__ __forceinline__ void ev_distance(const G &g, uint64_t n, const EvBank &b, uint64_t i, uint32_t *cells) {
+    const uint32_t st = b.st[i];
+    if (st & kEvDone) return;
+    Particle P;
+    P.cell = cells;
+    ev_load(b, n, i, st, P);
+    Nearest nr;
+    nearest_surface(g, P, nr);
+    b.t[i] = nr.t;
+    b.sig[i] = g.sigma[nr.leaf_fill];
+    b.inst[i] = nr.inst;
+    b.surf[i] = nr.surf;
+    b.entry[i] = nr.entry;
+    b.st[i] = (st & ~(0xFu << 12 | 1u << 16)) | (uint32_t)nr.level << 12 | (uint32_t)nr.pos << 16;
+}
+
+// The segment: boundary or collision, move, tally, sequence, new direction.
+__device__ __forceinline__ void ev_move(const KParams &p, const KOut &o, const EvBank &b, uint64_t *rep, uint64_t i,
+                                        Counts &cnt) {
+    const uint32_t st = b.st[i];
+    if (!(st & kEvDone)) {
+        const uint64_t local = i, pid = p.first + i;
+        double tau = b.tau[i];
+        const double t = b.t[i], sig = b.sig[i];
+        const uint32_t inst = b.inst[i];
+        bool recovf = (st & kEvRecOvf) != 0;
+        int end = GT_END_NONE;
+        const double sc = (p.source == 1) ? dinf() : tau / sig;
+        const bool boundary = t < sc;
+        if (!boundary && sc == dinf()) {
+            end = GT_END_LOST;
+            b.st[i] = st | kEvDone | (uint32_t)end << 8;
+            ev_finish(b, o, rep, i, end, recovf, cnt);
+        } else {
+            double l;
+            if (boundary) {
+                l = t;
+                if (p.source != 1) tau = tau - sig * t;
+            } else {
+                l = sc;
+            }
+            double u = b.u[i], v = b.v[i], w = b.w[i];
+            const double m0 = l * u, m1 = l * v, m2 = l * w;
+            b.x[i] = b.x[i] + m0;
+            b.y[i] = b.y[i] + m1;
+            b.z[i] = b.z[i] + m2;
+            TallyAcc acc;
+            acc.inst = b.acc_inst[i];
+            acc.lo = b.acc_lo[i];
+            acc.hi = b.acc_hi[i];
+            tally_add(rep, acc, inst, l);
+            b.acc_inst[i] = acc.inst;
+            b.acc_lo[i] = acc.lo;
+            b.acc_hi[i] = acc.hi;
+            b.h[i] = (b.h[i] ^ ((uint64_t)inst + 1)) * kFnvPrime;
+            uint32_t segs = b.segs[i];
+            if (local < p.rec_k) {
+                if (segs < p.rec_cap) gstore(o.rec, local * (uint64_t)p.rec_cap + segs, inst);
+                else recovf = true;
+            }
+            segs++;
+            b.segs[i] = segs;
+            uint32_t nst = st & ~(kEvRecOvf | kEvPending);
+            if (recovf) nst |= kEvRecOvf;
+            if (boundary) {
+                nst |= kEvPending;
+            } else {
+                // collision: off every surface, then CAP or a new direction and depth
+                nst = (nst & ~(0xFu << 4));
+                b.on_surf[i] = kNone;
+                const uint32_t ncoll = b.ncoll[i] + 1;
+                b.ncoll[i] = ncoll;
+                if (ncoll >= p.max_coll) {
+                    end = GT_END_CAP;
+                } else {
+                    uint32_t blk = b.blk[i];
+                    double u0, u1, u2;
+                    do draw_block(p.seed, p.geom_id, pid, blk++, u0, u1, u2);
+                    while (!direction_from(u0, u1, u, v, w));
+                    tau = -series_log(u2);
+                    b.blk[i] = blk;
+                    b.u[i] = u;
+                    b.v[i] = v;
+                    b.w[i] = w;
+                }
+                if (end == GT_END_NONE && segs >= p.max_segs) end = GT_END_SEGCAP;
+            }
+            b.tau[i] = tau;
+            if (end != GT_END_NONE) nst |= kEvDone | (uint32_t)end << 8;
+            b.st[i] = nst;
+            if (end != GT_END_NONE) ev_finish(b, o, rep, i, end, recovf, cnt);
+        }
+    }
+}
+
+// cross_surface for history i if its segment ended on a surface; true while
+// the history goes on.
+template <int PREC, typename G>
+__device__ __forceinline__ bool ev_cross(const G &g, const KParams &p, const KOut &o, const EvBank &b, uint64_t *rep,
+                                         uint64_t i, uint32_t *cells, Counts &cnt) {
+    uint32_t st = b.st[i];
+    if (!(st & kEvDone) && (st & kEvPending)) {
+        Particle P;
+        P.cell = cells;
+        ev_load(b, p.n, i, st, P);
+        const int bl = (int)((st >> 12) & 15u);
+        const bool bpos = (st >> 16) & 1u;
+        int end = cross_listed<PREC>(g, P, bl, b.surf[i], bpos, b.entry[i]);
+        ev_store_geom(b, p.n, i, P);
+        if (end == GT_END_NONE && b.segs[i] >= p.max_segs) end = GT_END_SEGCAP;
+        const bool recovf = (st & kEvRecOvf) != 0;
+        st = ev_pack(P.depth, P.on_level, end, bl, bpos, false, recovf, end != GT_END_NONE);
+        b.st[i] = st;
+        if (end != GT_END_NONE) ev_finish(b, o, rep, i, end, recovf, cnt);
+    }
+    return !(st & kEvDone);
+}
+
 // Fold the replicas' limb counters of instance i into the 128-bit
 // fixed-point total (plus the previous total when accumulating), then convert
 // it to cm: high word * 2^-32 + low word * 2^-96.

@@ -87,6 +87,53 @@ extern "C" int cpu_track(const gt_geometry *g, const gt_track_params *p, const g
     return GT_OK;
 }
 
+// gt_track_event on the CPU: the event-based schedule's steps (birth, then
+// per iteration distance, move and cross over every history of the bank)
+// run one history at a time in host memory, tables read in place.
+template <int PREC>
+static int cpu_event_t(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o) {
+    KParams kp;
+    KOut ko;
+    fill_kparams(p, g, kp, ko, o);
+    std::vector<unsigned char> mem(ev_layout(kp.n, nullptr, nullptr) + 256);
+    unsigned char *base = (unsigned char *)(((uintptr_t)mem.data() + 255) & ~(uintptr_t)255);
+    EvBank b;
+    ev_layout(kp.n, base, &b);
+    std::memset(g->tally_ws, 0, (size_t)8 * 4 * 8 * g->n_inst);
+    std::memset(o->counters, 0, 8 * sizeof(uint64_t));
+    if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
+    blockDim.x = 1;
+    threadIdx.x = 0;
+    const DevGlobal v = global_view(g->dev);
+    uint32_t cells[GT_MAX_LEVELS];
+    Counts cnt = {0, 0, 0, 0, 0, 0, 0};
+    uint64_t *rep = g->tally_ws;
+    for (uint64_t i = 0; i < kp.n; i++) ev_birth<PREC>(v, kp, ko, b, rep, i, cells, cnt);
+    for (uint64_t it = 0, alive = kp.n; alive; it++) {
+        if (it > (uint64_t)kp.max_segs + 1) return set_error("cpu_track_event: histories left"), GT_EHIP;
+        for (uint64_t i = 0; i < kp.n; i++) ev_distance(v, kp.n, b, i, cells);
+        for (uint64_t i = 0; i < kp.n; i++) ev_move(kp, ko, b, rep, i, cnt);
+        alive = 0;
+        for (uint64_t i = 0; i < kp.n; i++) alive += ev_cross<PREC>(v, kp, ko, b, rep, i, cells, cnt) ? 1 : 0;
+    }
+    uint64_t *c = o->counters;
+    c[GT_CNT_ESCAPED] += cnt.escaped;
+    c[GT_CNT_CAPPED] += cnt.capped;
+    c[GT_CNT_LOST] += cnt.lost;
+    c[GT_CNT_SEGCAP] += cnt.segcap;
+    c[GT_CNT_REC_OVERFLOW] += cnt.recovf;
+    c[GT_CNT_SEGMENTS] += cnt.segments;
+    c[GT_CNT_REJECTED] += cnt.rejected;
+    fold_all(g->tally_ws, o->tally_fx, o->tally, g->n_inst, (p->flags & GT_FLAG_ACCUMULATE) != 0);
+    return GT_OK;
+}
+
+extern "C" int cpu_track_event(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o) {
+    int rc = check_track_args(g, p, o);
+    if (rc) return rc;
+    return p->precision == GT_PREC_MIXED ? cpu_event_t<GT_PREC_MIXED>(g, p, o) : cpu_event_t<GT_PREC_FP64>(g, p, o);
+}
+
 // gt_track_batch on the CPU: gt_batch_create's descriptors (in host memory)
 // executed the way gt_batch_launch executes them -- the fill list, then the
 // chunk groups by staging kind (3, 2, 1, 0) each chunk through one lane with

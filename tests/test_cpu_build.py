@@ -130,6 +130,27 @@ def test_cpu_build_matches_oracle(host, what, k):
     host.L.gt_geometry_destroy(h)
 
 
+@pytest.mark.parametrize("what,k", [("cfg", 1), ("cfg", 2), ("cfg", 4), ("fn", "sphere"), ("batch", 41)],
+                         ids=["cfg1", "cfg2", "cfg4", "sphere", "batch41"])
+def test_cpu_event_schedule_matches_oracle(host, what, k):
+    """The event-based schedule's steps, run one history at a time over a
+    bank in host memory, give the oracle's histories and tallies (both
+    precisions)."""
+    fg, kw = make(what, k)
+    h, ni = host.geometry(fg)
+    n, rk, cap = 300, 25, 48
+    o = oracle.track(oracle.OracleGeometry(fg), oracle.TrackParams(n_particles=n, record_first_k=rk,
+                                                                    record_cap=cap, **kw), n_threads=4)
+    host.L.cpu_track_event.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    for prec in (gt.PREC_FP64, gt.PREC_MIXED):
+        out = Outs(ni, n, rk, cap)
+        prm = gt._params(kw["seed"], n, geometry_id=kw["geometry_id"], precision=prec, record_first_k=rk,
+                         record_cap=cap)
+        host.check(host.L.cpu_track_event(h, C.byref(prm), C.byref(out.struct())))
+        same(out.a, o, rk)
+    host.L.gt_geometry_destroy(h)
+
+
 def test_cpu_build_covers_every_staging_kind(host):
     kinds = set()
     for what, k in GEOMS:
@@ -175,8 +196,9 @@ def test_cpu_batch_descriptors(host, prec):
 
 
 def test_cpu_build_under_address_sanitizer():
-    """The same per-lane logic and batch planner with AddressSanitizer, in a
-    child process (the sanitizer runtime must be loaded first)."""
+    """The same per-lane logic, event-based steps and batch planner with
+    AddressSanitizer, in a child process (the sanitizer runtime must be
+    loaded first)."""
     try:
         lib = cpu_build.build(asan=True)
     except RuntimeError as e:
@@ -198,6 +220,11 @@ for what, k in [("cfg", 2), ("batch", 3), ("batch", 5), ("batch", 2)]:
             prm = t.gt._params(kw["seed"], 200, geometry_id=kw["geometry_id"], precision=prec, record_first_k=10,
                                record_cap=16)
             host.check(host.L.cpu_track(h, C.byref(prm), C.byref(out.struct()), kind))
+        out = t.Outs(ni, 150, 10, 16)
+        prm = t.gt._params(kw["seed"], 150, geometry_id=kw["geometry_id"], precision=prec, record_first_k=10,
+                           record_cap=16)
+        host.L.cpu_track_event.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        host.check(host.L.cpu_track_event(h, C.byref(prm), C.byref(out.struct())))
     host.L.gt_geometry_destroy(h)
 t.batch_run(host, [(57, 300, True), (5, 200, True), (41, 150, False)], 1, 64)
 print("asan clean")
