@@ -42,7 +42,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--particles", type=int, default=1_000_000)
+    ap.add_argument("--config", type=int, choices=[1, 2, 3, 4], default=2,
+                    help="workload: 1 one 3x3 pin lattice, 2 the 17x17 lattice (default, the headline), "
+                         "3 the three-level core, 4 the hexagonal core")
+    ap.add_argument("--particles", type=int, default=0, help="histories (0 = the workload's own count)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0, help="refill_min of the persistent schedule (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -118,7 +121,8 @@ def run_timed(gt, step, args, hev):
 
 
 def timed(gt, G, out, args, prec, hev, lane=False):
-    kw = dict(seed=2002, n_particles=args.particles, geometry_id=2, precision=prec, block_size=args.block, out=out,
+    kw = dict(seed=args.seed, n_particles=args.particles, geometry_id=args.config, precision=prec,
+              block_size=args.block, out=out,
               lane_per_history=lane, refill_min=0 if lane else args.refill, tail_compaction=args.tail)
     shape = None
     if not lane and args.autotune and not args.block and not args.refill:
@@ -139,7 +143,8 @@ def timed_event(gt, G, args, hev):
     n = args.particles
     out = gt.alloc_outputs(G, n)
     bank = torch.empty(gt.event_bank_bytes(n), dtype=torch.uint8, device="cuda")
-    r = run_timed(gt, lambda: gt.track_event(G, seed=2002, n_particles=n, geometry_id=2, precision=gt.PREC_MIXED,
+    r = run_timed(gt, lambda: gt.track_event(G, seed=args.seed, n_particles=n, geometry_id=args.config,
+                                             precision=gt.PREC_MIXED,
                                              out=out, bank=bank), args, hev)
     r["segments"] = out.counters_dict()["segments"]
     return r
@@ -181,7 +186,7 @@ def batched(gt, synth, args, hev):
     return out
 
 
-def cpu_baseline(fg, gpu_out, n):
+def cpu_baseline(fg, gpu_out, n, seed, gid):
     """Oracle on the host cores over the whole workload, and the parity
     gate of the GPU outputs against it."""
     import numpy as np
@@ -189,7 +194,7 @@ def cpu_baseline(fg, gpu_out, n):
     import oracle
     cores = min(16, os.cpu_count() or 1)
     og = oracle.OracleGeometry(fg)
-    p = oracle.TrackParams(seed=2002, n_particles=n, geometry_id=2)
+    p = oracle.TrackParams(seed=seed, n_particles=n, geometry_id=gid)
     t0 = time.perf_counter()
     o = oracle.track(og, p, n_threads=cores)
     dt = time.perf_counter() - t0
@@ -204,16 +209,20 @@ def cpu_baseline(fg, gpu_out, n):
     rel = float(np.max(np.abs(g_t[nz] - o.tally[nz]) / o.tally[nz])) if nz.any() else 0.0
     # one core on a 10^4-history slice
     t0 = time.perf_counter()
-    o1 = oracle.track(og, oracle.TrackParams(seed=2002, n_particles=min(n, 10_000), geometry_id=2), n_threads=1)
+    o1 = oracle.track(og, oracle.TrackParams(seed=seed, n_particles=min(n, 10_000), geometry_id=gid), n_threads=1)
     per_core = o1.counters["segments"] / (time.perf_counter() - t0)
     # algorithmic double-precision operations per segment (work meter over a sample)
-    ops, segs = oracle.count_work(og, oracle.TrackParams(seed=2002, n_particles=min(n, 20_000), geometry_id=2))
+    ops, segs = oracle.count_work(og, oracle.TrackParams(seed=seed, n_particles=min(n, 20_000), geometry_id=gid))
     return dict(value=o.counters["segments"] / dt, unit="segments/s", cores=cores, kind="oracle",
                 sample="the whole workload (%d histories, %d segments), %.1f s" % (n, o.counters["segments"], dt),
                 parity=parity, max_tally_rel_err=rel, ops_per_segment=ops / segs, per_core=per_core)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_track_persistent_17x17_1e6.md")
+WORKLOAD_NAMES = {1: "3x3 square lattice of one pin type (two levels)",
+                  2: "17x17 square lattice of 3 axially split pin types (two levels)",
+                  3: "15x15 core of 17x17 assemblies of 3 pin types in a cylinder (four levels)",
+                  4: "7-ring hexagonal core of 9-ring hexagonal assemblies, planes only (three levels)"}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2406_13849_amd", "csrc", f)
                   for f in ("gt_device.h", "gt_track.hip", "gt_internal.h", "gt_geometry.cpp")]
 
@@ -267,7 +276,10 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_bytes, "steps": args.steps}))
         return
     from paper_2406_13849_amd import gt, synth
-    fg = synth.make_config(2)
+    args.seed = synth.particle_seed(args.config)
+    if not args.particles:
+        args.particles = synth.CONFIG_PARTICLES[args.config]
+    fg = synth.make_config(args.config)
     G = gt.Geometry(fg)
     n = args.particles
     out = gt.alloc_outputs(G, n)
@@ -280,11 +292,11 @@ def main():
         res[name] = timed(gt, G, out, args, prec, hev, lane)
         print("# %s: %.3f ms/step, %d segments/step" % (name, sum(res[name]["ms"]) / args.steps,
                                                         res[name]["segments"]), file=sys.stderr, flush=True)
-    if args.only is None:
+    if args.only is None and synth.make_config(args.config).lattice_hint.any():
         # the same workload with the lattice hints removed: no FP32 index
         # guess, every full search through the hierarchy (the plain single
         # tracker against its lattice-aware form)
-        fg2 = synth.make_config(2)
+        fg2 = synth.make_config(args.config)
         fg2.lattice_hint[:] = 0
         G2 = gt.Geometry(fg2)
         res["nohint"] = timed(gt, G2, gt.alloc_outputs(G2, n), args, gt.PREC_MIXED, hev, False)
@@ -319,7 +331,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "17x17 square lattice of 3 axially split pin types (two levels), %d histories" % n,
+        "config": {"workload": "%s, %d histories" % (WORKLOAD_NAMES[args.config], n),
                    "histories": n, "segments_per_step": head["segments"],
                    "precision": "mixed" if "mixed" in res else "fp64", "parallelism": "none (1 GPU)",
                    "launch_shape": head["shape"]},
@@ -339,7 +351,7 @@ def main():
     if bat is not None:
         line["batched"] = bat
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(fg, out, n)
+        cb = cpu_baseline(fg, out, n, args.seed, args.config)
         line["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         line["parity"] = {"sequences_and_fixed_point_tallies_identical": cb["parity"],
                           "max_tally_rel_err": cb["max_tally_rel_err"]}
@@ -348,9 +360,9 @@ def main():
         achieved = cb["ops_per_segment"] * head["segments"] / (kernel_ms * 1e-3)
         line["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
                             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS,
-                            "traffic": traffic_per_launch(),
+                            "traffic": traffic_per_launch() if (args.config == 2 and n == 1_000_000) else None,
                             "ops_per_segment": cb["ops_per_segment"], "kernel_ms": kernel_ms,
-                            "kernel": "k_track_persistent<mixed, staged>"}
+                            "kernel": "k_track_persistent<mixed, staging kind %d>" % G.staging(gt.PREC_MIXED)[0]}
         # the HBM side of the same kernel: algorithmic bytes (per-particle
         # outputs; no sequences are recorded here, the tallies fit in the L2)
         # and the measured bytes per launch from the committed counters
