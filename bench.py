@@ -166,6 +166,25 @@ def batched(gt, synth, args, hev):
     b = gt.Batch(items, block_size=args.block, refill_min=args.refill, tuned=args.tune_batch)
     res = {"batched_mixed": run_timed(gt, b.launch, args, hev)}
     segs = sum(it.out.counters_dict()["segments"] for it in items)
+    # the same launch captured once into a HIP graph and replayed
+    import torch
+    s = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        b.launch(s)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, e in gev:
+        a.record()
+        graph.replay()
+        e.record()
+    torch.cuda.synchronize()
+    res["batched_mixed_graph_replay"] = {"ms": [a.elapsed_time(e) for a, e in gev]}
+    if sum(it.out.counters_dict()["segments"] for it in items) != segs:
+        raise RuntimeError("graph replay and eager segment counts differ")
+    del graph
     for name, prec in (("sequential_fp64", gt.PREC_FP64), ("sequential_mixed", gt.PREC_MIXED)):
         def step(prec=prec):
             for (G, n, j), it in zip(geoms, items):
