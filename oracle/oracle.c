@@ -210,7 +210,8 @@ int or_geometry_create(const or_flat *f, or_geom **out, char *err, int errlen) {
             for (uint32_t k2 = g->hs_off[c]; k2 < k; k2++)
                 if ((uint32_t)abs(g->hs[k2]) - 1 == s) { free(owner); FAIL("cell %u: surface %u repeated", c, s); }
             if (owner[s] >= 0 && owner[s] != (int64_t)g->cell_univ[c]) {
-                free(owner); FAIL("surface %u used by universes %lld and %u", s, (long long)owner[s], g->cell_univ[c]);
+                long long prev = (long long)owner[s];
+                free(owner); FAIL("surface %u used by universes %lld and %u", s, prev, g->cell_univ[c]);
             }
             owner[s] = g->cell_univ[c];
             g->nb_off[s + 1]++;

@@ -602,6 +602,23 @@ def box(half: Tuple[float, float, float] = (1.0, 1.0, 1.0), sigma: float = 1.0) 
     return b.build(root, [sigma], (-hx, -hy, -hz), (hx, hy, hz), "box")
 
 
+def nested_box(half: float = 1.0, sigma: float = 0.7) -> FlatGeometry:
+    """A box whose one cell holds a universe whose one cell is bounded by two
+    x-planes equal to the box's own (distinct surfaces, same coefficients):
+    every exit through x = +-half ties between the two levels at one
+    distance, which the top level must take (from the daughter there is no
+    neighbour)."""
+    b = GeomBuilder()
+    h = half
+    s = [b.surface(PX, -h), b.surface(PX, h), b.surface(PY, -h), b.surface(PY, h),
+         b.surface(PZ, -h), b.surface(PZ, h), b.surface(PX, -h), b.surface(PX, h)]
+    root = b.universe([([pos(s[0]), neg(s[1]), pos(s[2]), neg(s[3]), pos(s[4]), neg(s[5])],
+                        fill_universe(1), (0.0, 0.0, 0.0))])
+    inner = b.universe([([pos(s[6]), neg(s[7])], 0, (0.0, 0.0, 0.0))])
+    assert (root, inner) == (0, 1)
+    return b.build(root, [sigma], (-h, -h, -h), (h, h, h), "nested_box")
+
+
 WORKLOADS = {1: config1, 2: config2, 3: config3, 4: config4}
 
 # particle counts of the workload table, and the seeds: geometry 1000+i,

@@ -96,7 +96,7 @@ def host():
         pytest.skip(str(e))
 
 
-GEOMS = [("cfg", 1), ("cfg", 2), ("cfg", 4), ("fn", "sphere"), ("batch", 3), ("batch", 5), ("batch", 41),
+GEOMS = [("cfg", 1), ("cfg", 2), ("cfg", 4), ("fn", "sphere"), ("fn", "nested_box"), ("batch", 3), ("batch", 5), ("batch", 41),
          ("batch", 57), ("batch", 2), ("batch", 63)]
 
 
@@ -130,8 +130,9 @@ def test_cpu_build_matches_oracle(host, what, k):
     host.L.gt_geometry_destroy(h)
 
 
-@pytest.mark.parametrize("what,k", [("cfg", 1), ("cfg", 2), ("cfg", 4), ("fn", "sphere"), ("batch", 41)],
-                         ids=["cfg1", "cfg2", "cfg4", "sphere", "batch41"])
+@pytest.mark.parametrize("what,k", [("cfg", 1), ("cfg", 2), ("cfg", 4), ("fn", "sphere"), ("fn", "nested_box"),
+                                     ("batch", 41)],
+                         ids=["cfg1", "cfg2", "cfg4", "sphere", "nested_box", "batch41"])
 def test_cpu_event_schedule_matches_oracle(host, what, k):
     """The event-based schedule's steps, run one history at a time over a
     bank in host memory, give the oracle's histories and tallies (both

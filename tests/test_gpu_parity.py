@@ -129,6 +129,7 @@ CASES = [
     (3, dict(seed=2003, n_particles=4000, geometry_id=3), 1000, 1024),
     (4, dict(seed=2004, n_particles=4000, geometry_id=4), 1000, 1024),
     ("hex_pin_box", dict(seed=2104, n_particles=4000, geometry_id=11), 500, 256),
+    ("nested_box", dict(seed=2105, n_particles=20_000, geometry_id=12), 2000, 64),
 ]
 
 
@@ -540,7 +541,7 @@ def test_kernel_event_hook():
 
 
 # ---------------------------------------------------------------- event-based schedule
-EVENT_CASES = [c for c in CASES if c[0] in ("sphere", 1, 2, 3, 4, "hex_pin_box")]
+EVENT_CASES = [c for c in CASES if c[0] in ("sphere", 1, 2, 3, 4, "hex_pin_box", "nested_box")]
 
 
 @pytest.mark.parametrize("case", EVENT_CASES, ids=[str(c[0]) for c in EVENT_CASES])
