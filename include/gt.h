@@ -181,7 +181,17 @@ typedef struct {
                                  default 256); 0 = default                          */
     uint32_t refill_min;      /* persistent schedule: a wave starts new histories once at
                                  least this many of its lanes are idle (1..64; 0 = 8)   */
-    uint32_t reserved;        /* must be 0                                           */
+    uint32_t regroup_every;   /* persistent schedule: every this many loop trips the
+                                 waves of a workgroup meet and sort their lanes'
+                                 histories by key (the leaf universe of a history
+                                 about to take a segment, else its step; idle lanes
+                                 last) with a counting sort in LDS, moving each
+                                 history's state whole (regroup by universe, to cut
+                                 divergence; speed only).  0 = never (the default);
+                                 skipped where the LDS left over cannot hold one
+                                 64-bit word per lane or for workgroups of one wave;
+                                 must be 0 for GT_FLAG_LANE_PER_HISTORY and for
+                                 gt_track_event                                      */
 } gt_track_params;
 
 /* Outputs, all device memory owned by the caller.
@@ -251,6 +261,8 @@ typedef struct {
     uint32_t block_size;   /* threads per workgroup, multiple of 64 up to 1024; 0 = 1024      */
     uint32_t refill_min;   /* as gt_track_params.refill_min; 0 = 8                             */
     uint64_t chunk;        /* histories per work item taken from the device queue; 0 = 16384  */
+    uint32_t regroup_every;/* as gt_track_params.regroup_every; 0 = that of the first item    */
+    uint32_t reserved;     /* must be 0                                                        */
 } gt_tuning;               /* a NULL gt_tuning* means: the shape gt_autotune_batch found for
                               the same items in this process, else the defaults              */
 
@@ -284,9 +296,10 @@ void gt_batch_destroy(gt_batch *b);
  * the stream and overwrite the outputs they are given. */
 
 /* Time gt_track with every shape block_size in {256, 512, 640, 1024} x refill_min
- * in {1, 4, 8, 16} (one untimed and `reps` timed launches each) on the
- * given parameters; *best gets the fastest (chunk = 0) and *best_ms its mean
- * launch time (may be NULL).  The outputs end as those of one gt_track call
+ * in {1, 4, 8, 16} (one untimed and `reps` timed launches each), then the
+ * fastest of these with regroup_every in {16, 64, 256}, on the given
+ * parameters (regroup_every 0 in the first stage); *best gets the fastest
+ * (chunk = 0) and *best_ms its mean launch time (may be NULL).  The outputs end as those of one gt_track call
  * with the winning shape.  The winner is cached in the process under
  * (geometry, precision, staging and tail flags, histories rounded up to a
  * power of two): see gt_tuning_lookup.  Errors as gt_track, and GT_EINVAL
@@ -299,7 +312,8 @@ int gt_autotune_track(const gt_geometry *g, const gt_track_params *p, const gt_t
 int gt_tuning_lookup(const gt_geometry *g, const gt_track_params *p, gt_tuning *out);
 
 /* Time gt_batch_launch for block_size in {512, 640, 1024} x refill_min in
- * {1, 4, 8, 16} x chunk in {4096, 16384, 65536}; *best gets the fastest.  The
+ * {1, 4, 8, 16} x chunk in {4096, 16384, 65536}, then the fastest of these
+ * with regroup_every in {16, 64, 256}; *best gets the fastest.  The
  * winner is cached in the process for this list of (geometry, histories,
  * precision): gt_batch_create and gt_track_batch given a NULL tuning use it. */
 int gt_autotune_batch(const gt_batch_item *items, uint32_t n_items, uint32_t reps, void *stream, gt_tuning *best,
@@ -313,6 +327,21 @@ int gt_autotune_batch(const gt_batch_item *items, uint32_t n_items, uint32_t rep
  * The events stay the caller's; gt_set_kernel_events(NULL, NULL) turns the
  * hook off.  GT_EINVAL if exactly one handle is NULL. */
 int gt_set_kernel_events(void *start_event, void *stop_event);
+
+/* The plan of the calling thread's last persistent tracker launch (gt_track
+ * without GT_FLAG_LANE_PER_HISTORY, or the last staging-kind launch of
+ * gt_batch_launch), as chosen by the library from the launch shape and the
+ * LDS left over: workgroups launched, threads per workgroup, dynamic LDS
+ * bytes per workgroup, staging kind (0 tables in global memory ... 3 all
+ * in LDS), tally-cache entries per lane, tail-compaction capacity
+ * (histories; 0 = off) and regroup interval (loop trips; 0 = no regroup
+ * step).  For tests and tuning: 1 and *out filled, or 0 if this thread has
+ * made no such launch; GT_EINVAL for a NULL out. */
+typedef struct {
+    uint32_t workgroups, block_size, lds_bytes, staging_kind;
+    uint32_t tally_cache_entries, tail_capacity, regroup_every, reserved;
+} gt_launch_info;
+int gt_last_launch(gt_launch_info *out);
 
 /* One-shot form: create, launch, wait for the stream, destroy. */
 int gt_track_batch(const gt_batch_item *items, uint32_t n_items, const gt_tuning *tuning, void *stream);

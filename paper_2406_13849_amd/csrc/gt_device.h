@@ -940,29 +940,45 @@ struct ChunkQueue {
     }
 };
 
-// Tail compaction.  Once the queue is empty for every wave of the
-// workgroup, the histories still running are spread thinly over its waves.
-// Every `round` loop trips the waves meet at a barrier; when the live
-// histories fit in fewer waves (and in the LDS buffer), each is written to
-// the buffer at its rank and read back by the lane of that rank, so fewer,
-// fuller waves carry the tail while the emptied ones wait at the barrier.  A
-// history's state moves as a whole, so its results do not depend on the lane
-// that finishes it.  Optional (off by default): waves that wait for the tail
-// keep taking issue slots that finished waves would leave to working ones.
+// Meetings of the workgroup's waves.  The persistent loop runs per wave;
+// two optional, result-neutral steps make the waves meet at a barrier and
+// move histories between lanes through an LDS buffer.  A history's state
+// moves as a whole (kTailFields words: position, direction, optical depth,
+// id, hash, counters, search state, the cell of each level); the lane's
+// tally accumulator and cache stay with the lane, since the tallies are sums
+// over all histories.  So no result depends on the lane that finishes a
+// history.
+//  * Tail compaction: once the queue is empty for every wave, every `round`
+//    loop trips, when the live histories fit in fewer waves (and in the
+//    buffer), each is written at its rank and read back by the lane of that
+//    rank, so fewer, fuller waves carry the tail while the emptied ones wait
+//    at the barrier.  Off by default: waves that wait for the tail keep taking
+//    issue slots that finished waves would leave to working ones.
+//  * Regroup: every `regroup` loop trips (from the start), the lanes are sorted
+//    by a key -- the leaf universe of a history about to take a segment, else
+//    its step (birth position, direction, search), idle lanes last -- with a
+//    counting sort in LDS, so lanes that run the same code sit in the same
+//    waves.  The buffer holds one word per lane; the state moves a word per
+//    pass.
 constexpr int kTailFields = 16;   // 64-bit words per moved history
 constexpr uint32_t kTailRound = 8;
+constexpr uint32_t kRgBuckets = 64;   // regroup keys (one wave scans them)
+static_assert(13 + GT_MAX_LEVELS / 2 == kTailFields, "moved state: 13 words + the levels, two per word");
 
 struct TailCfg {
-    uint64_t *buf;   // LDS, kTailFields x cap words (field-major)
-    uint32_t *ctl;   // LDS: [0] waves whose queue is empty, [1 + w] live lanes of wave w
-    uint32_t cap;    // histories the buffer holds; 0 = no compaction
-    uint32_t round;  // loop trips between compactions
+    uint64_t *buf;     // LDS buffer of `words` 64-bit words
+    uint32_t *ctl;     // LDS: [0] waves whose queue is empty (compaction),
+                       // [1 + w] live lanes of wave w, bit 31: its queue is empty
+    uint32_t cap;      // compaction: histories the buffer holds field-major; 0 = off
+    uint32_t round;    // compaction: loop trips between meetings in the tail
+    uint32_t words;    // buffer size
+    uint32_t regroup;  // loop trips between regroups; 0 = off (needs words >= lanes)
 };
 
 // The persistent history loop of one lane (see above); returns when its
 // wave has drained the queue and every lane of the wave is idle (with tail
 // compaction: when no lane of the workgroup has a history left).
-template <int PREC, typename G, typename Queue>
+template <int PREC, bool RG = false, typename G, typename Queue>
 __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const KOut &o, uint64_t *rep,
                                            uint32_t *cells, const Queue &queue, Counts &cnt, const TailCfg &tc,
                                            const TallyCache &tcache) {
@@ -1001,106 +1017,177 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
     bool counted = false, in_tail = false;
     uint32_t titer = 0;
 
+    // (RG: the build with the regroup step; without it the step's code is left out)
+    const uint32_t regroup = RG && tc.words >= blockDim.x ? tc.regroup : 0u;
+    const bool meetings = tc.cap != 0 || regroup != 0;   // workgroup-uniform
+
+    // the moved state of a history, word by word (see TailCfg)
+    auto get_word = [&](int f) -> uint64_t {
+        switch (f) {
+        case 0: return (uint64_t)__double_as_longlong(P.x);
+        case 1: return (uint64_t)__double_as_longlong(P.y);
+        case 2: return (uint64_t)__double_as_longlong(P.z);
+        case 3: return (uint64_t)__double_as_longlong(P.u);
+        case 4: return (uint64_t)__double_as_longlong(P.v);
+        case 5: return (uint64_t)__double_as_longlong(P.w);
+        case 6: return (uint64_t)__double_as_longlong(P.tau);
+        case 7: return local;
+        case 8: return h;
+        case 9: return (uint64_t)blk | (uint64_t)segs << 32;
+        case 10: return (uint64_t)ncoll | (uint64_t)attempts << 32;
+        case 11: return (uint64_t)sforce | (uint64_t)sk << 32;
+        case 12: {
+            const uint32_t fl = (uint32_t)mode | (uint32_t)recovf << 3 | (uint32_t)birth << 4 | (uint32_t)sfpos << 5 |
+                                (uint32_t)P.depth << 8 | (uint32_t)(P.on_level + 1) << 12 | (uint32_t)sL << 16;
+            return (uint64_t)P.on_surf | (uint64_t)fl << 32;
+        }
+        default: {
+            const int L = 2 * (f - 13);
+            return (uint64_t)lvl(P, L) | (uint64_t)lvl(P, L + 1) << 32;
+        }
+        }
+    };
+    auto set_word = [&](int f, uint64_t v) {
+        switch (f) {
+        case 0: P.x = __longlong_as_double((long long)v); break;
+        case 1: P.y = __longlong_as_double((long long)v); break;
+        case 2: P.z = __longlong_as_double((long long)v); break;
+        case 3: P.u = __longlong_as_double((long long)v); break;
+        case 4: P.v = __longlong_as_double((long long)v); break;
+        case 5: P.w = __longlong_as_double((long long)v); break;
+        case 6: P.tau = __longlong_as_double((long long)v); break;
+        case 7: local = v; break;
+        case 8: h = v; break;
+        case 9: blk = (uint32_t)v; segs = (uint32_t)(v >> 32); break;
+        case 10: ncoll = (uint32_t)v; attempts = (uint32_t)(v >> 32); break;
+        case 11: sforce = (uint32_t)v; sk = (uint32_t)(v >> 32); break;
+        case 12: {
+            P.on_surf = (uint32_t)v;
+            const uint32_t fl = (uint32_t)(v >> 32);
+            mode = (int)(fl & 7u);
+            recovf = (fl >> 3) & 1u;
+            birth = (fl >> 4) & 1u;
+            sfpos = (fl >> 5) & 1u;
+            P.depth = (int)((fl >> 8) & 15u);
+            P.on_level = (int)((fl >> 12) & 15u) - 1;
+            sL = (int)((fl >> 16) & 15u);
+            break;
+        }
+        default: {
+            const int L = 2 * (f - 13);
+            lvl(P, L) = (uint32_t)v;
+            lvl(P, L + 1) = (uint32_t)(v >> 32);
+        }
+        }
+    };
+    // a lane without a history
+    auto clear_state = [&]() {
+        mode = M_IDLE;
+        P.x = P.y = P.z = P.u = P.v = P.w = P.tau = 0.0;
+        local = h = 0;
+        blk = segs = ncoll = attempts = sk = 0;
+        sforce = P.on_surf = kNone;
+        recovf = birth = sfpos = false;
+        P.depth = 1;
+        P.on_level = -1;
+        sL = 0;
+        end = GT_END_NONE;
+    };
+
     for (;;) {
-        if (tc.cap) {
-            if (drained && !counted) {
-                counted = true;
-                if (__lane_id() == 0) atomicAdd(&tc.ctl[0], 1u);
-            }
-            if (drained && !in_tail)
-                in_tail = __builtin_amdgcn_readfirstlane(__atomic_load_n(&tc.ctl[0], __ATOMIC_RELAXED)) == nwaves;
-            if (in_tail) {
-                const uint64_t act = __ballot(mode != M_IDLE);
-                if (act == 0 || ++titer >= tc.round) {
-                    titer = 0;
-                    if (__lane_id() == 0) tc.ctl[1 + wave] = (uint32_t)__popcll(act);
-                    __syncthreads();
-                    // (the counts are workgroup-uniform: read them as scalars)
-                    uint32_t A = 0, busy = 0, before = 0;
-                    for (uint32_t w = 0; w < nwaves; w++) {
-                        const uint32_t a = __builtin_amdgcn_readfirstlane(tc.ctl[1 + w]);
-                        A += a;
-                        busy += a ? 1u : 0u;
-                        before += w < wave ? a : 0u;
-                    }
-                    // every wave has read this round's counts before any wave
-                    // can write the next round's
-                    __syncthreads();
-                    if (A == 0) break;
-                    // pack the A live histories into lanes 0..A-1 of the workgroup
-                    // when that frees a wave and the buffer holds them all
-                    if (A <= tc.cap && (A + 63u) / 64u < busy) {
-                        const uint32_t C = tc.cap;
-                        if (mode != M_IDLE) {
-                            // (the tally accumulator and cache stay with the lane)
-                            uint64_t *b = tc.buf + before + lane_rank(act);
-                            b[0 * C] = __double_as_longlong(P.x);
-                            b[1 * C] = __double_as_longlong(P.y);
-                            b[2 * C] = __double_as_longlong(P.z);
-                            b[3 * C] = __double_as_longlong(P.u);
-                            b[4 * C] = __double_as_longlong(P.v);
-                            b[5 * C] = __double_as_longlong(P.w);
-                            b[6 * C] = __double_as_longlong(P.tau);
-                            b[7 * C] = local;
-                            b[8 * C] = h;
-                            b[9 * C] = (uint64_t)blk | (uint64_t)segs << 32;
-                            b[10 * C] = (uint64_t)ncoll | (uint64_t)attempts << 32;
-                            b[11 * C] = (uint64_t)sforce | (uint64_t)sk << 32;
-                            const uint32_t fl = (uint32_t)mode | (uint32_t)recovf << 3 | (uint32_t)birth << 4 |
-                                                (uint32_t)sfpos << 5 | (uint32_t)P.depth << 8 |
-                                                (uint32_t)(P.on_level + 1) << 12 | (uint32_t)sL << 16;
-                            b[12 * C] = (uint64_t)P.on_surf | (uint64_t)fl << 32;
-                            for (int L = 0; L < GT_MAX_LEVELS; L += 2)
-                                b[(13 + L / 2) * C] = (uint64_t)lvl(P, L) | (uint64_t)lvl(P, L + 1) << 32;
-                        }
-                        __syncthreads();
-                        if (threadIdx.x < A) {
-                            const uint64_t *b = tc.buf + threadIdx.x;
-                            P.x = __longlong_as_double(b[0 * C]);
-                            P.y = __longlong_as_double(b[1 * C]);
-                            P.z = __longlong_as_double(b[2 * C]);
-                            P.u = __longlong_as_double(b[3 * C]);
-                            P.v = __longlong_as_double(b[4 * C]);
-                            P.w = __longlong_as_double(b[5 * C]);
-                            P.tau = __longlong_as_double(b[6 * C]);
-                            local = b[7 * C];
-                            h = b[8 * C];
-                            blk = (uint32_t)b[9 * C];
-                            segs = (uint32_t)(b[9 * C] >> 32);
-                            ncoll = (uint32_t)b[10 * C];
-                            attempts = (uint32_t)(b[10 * C] >> 32);
-                            sforce = (uint32_t)b[11 * C];
-                            sk = (uint32_t)(b[11 * C] >> 32);
-                            P.on_surf = (uint32_t)b[12 * C];
-                            const uint32_t fl = (uint32_t)(b[12 * C] >> 32);
-                            mode = (int)(fl & 7u);
-                            recovf = (fl >> 3) & 1u;
-                            birth = (fl >> 4) & 1u;
-                            sfpos = (fl >> 5) & 1u;
-                            P.depth = (int)((fl >> 8) & 15u);
-                            P.on_level = (int)((fl >> 12) & 15u) - 1;
-                            sL = (int)((fl >> 16) & 15u);
-                            for (int L = 0; L < GT_MAX_LEVELS; L += 2) {
-                                const uint64_t v = b[(13 + L / 2) * C];
-                                lvl(P, L) = (uint32_t)v;
-                                lvl(P, L + 1) = (uint32_t)(v >> 32);
-                            }
-                        } else {
-                            // no history here any more (all of the old one is in the buffer)
-                            mode = M_IDLE;
-                            P.x = P.y = P.z = P.u = P.v = P.w = P.tau = 0.0;
-                            local = h = 0;
-                            blk = segs = ncoll = attempts = sk = 0;
-                            sforce = P.on_surf = kNone;
-                            recovf = birth = sfpos = false;
-                            P.depth = 1;
-                            P.on_level = -1;
-                            sL = 0;
-                        }
-                        end = GT_END_NONE;
-                    }
-                    continue;
+        if (meetings) {
+            const uint64_t act = __ballot(mode != M_IDLE);
+            bool meet;
+            if (RG && regroup) {
+                // every `regroup` trips; a wave with nothing left to do waits at once
+                meet = ++titer >= regroup || (drained && act == 0);
+            } else {
+                if (drained && !counted) {
+                    counted = true;
+                    if (__lane_id() == 0) atomicAdd(&tc.ctl[0], 1u);
                 }
+                if (drained && !in_tail)
+                    in_tail =
+                        __builtin_amdgcn_readfirstlane(__atomic_load_n(&tc.ctl[0], __ATOMIC_RELAXED)) == nwaves;
+                meet = in_tail && (act == 0 || ++titer >= tc.round);
+            }
+            if (meet) {
+                titer = 0;
+                if (__lane_id() == 0) tc.ctl[1 + wave] = (uint32_t)__popcll(act) | (drained ? 1u << 31 : 0u);
+                __syncthreads();
+                // (the counts are workgroup-uniform: read them as scalars)
+                uint32_t A = 0, busy = 0, before = 0, D = 0;
+                for (uint32_t w = 0; w < nwaves; w++) {
+                    const uint32_t cw = __builtin_amdgcn_readfirstlane(tc.ctl[1 + w]);
+                    const uint32_t a = cw & 0x7FFFFFFFu;
+                    A += a;
+                    busy += a ? 1u : 0u;
+                    before += w < wave ? a : 0u;
+                    D += cw >> 31;
+                }
+                // every wave has read this meeting's counts before any wave
+                // can write the next meeting's
+                __syncthreads();
+                if (A == 0 && D == nwaves) break;
+                if (tc.cap && D == nwaves && A <= tc.cap && (A + 63u) / 64u < busy) {
+                    // pack the A live histories into lanes 0..A-1 of the workgroup
+                    const uint32_t C = tc.cap;
+                    if (mode != M_IDLE) {
+                        uint64_t *b = tc.buf + before + lane_rank(act);
+#pragma unroll
+                        for (int f = 0; f < kTailFields; f++) b[f * C] = get_word(f);
+                    }
+                    __syncthreads();
+                    if (threadIdx.x < A) {
+                        const uint64_t *b = tc.buf + threadIdx.x;
+#pragma unroll
+                        for (int f = 0; f < kTailFields; f++) set_word(f, b[f * C]);
+                    } else {
+                        clear_state();   // (all of the old history is in the buffer)
+                    }
+                    end = GT_END_NONE;
+                } else if (RG && regroup) {
+                    // counting sort of the lanes by key: histogram, exclusive
+                    // scan by one wave, destination = bucket start + rank
+                    uint32_t key = kRgBuckets - 1;
+                    if (mode == M_TRACK) {
+                        const uint32_t u =
+                            P.depth > 1 ? (uint32_t)(-g.cell[lvl(P, P.depth - 2)].fill - 1) : g.root;
+                        key = u % (kRgBuckets - 4);
+                    } else if (mode != M_IDLE) {
+                        key = kRgBuckets - 4 + (uint32_t)mode - 1;   // birth position, direction, search
+                    }
+                    uint32_t *hist = (uint32_t *)tc.buf;
+                    if (threadIdx.x < kRgBuckets) hist[threadIdx.x] = 0;
+                    __syncthreads();
+                    const uint32_t rank = atomicAdd(&hist[key], 1u);
+                    __syncthreads();
+                    if (wave == 0) {
+                        const uint32_t n = hist[__lane_id()];
+                        uint32_t incl = n;
+                        for (int d = 1; d < 64; d <<= 1) {
+                            const uint32_t t = __shfl_up(incl, d);
+                            if ((int)__lane_id() >= d) incl += t;
+                        }
+                        hist[__lane_id()] = incl - n;
+                    }
+                    __syncthreads();
+                    const uint32_t dest = hist[key] + rank;   // a permutation of 0 .. lanes-1
+                    __syncthreads();
+                    // one word of the state per pass (no register holds more
+                    // than the word in flight)
+#pragma unroll
+                    for (int f = 0; f < kTailFields; f++) {
+                        tc.buf[dest] = get_word(f);
+                        __syncthreads();
+                        set_word(f, tc.buf[threadIdx.x]);
+                        __syncthreads();
+                    }
+                    end = GT_END_NONE;
+                }
+                // on into a loop trip: a wave with histories advances them
+                // before it can meet again (so any interval, down to one
+                // trip, makes progress)
             }
         }
         // ---- refill idle lanes
@@ -1138,18 +1225,10 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
             }
         }
         if (__ballot(mode != M_IDLE) == 0) {
-            if (!tc.cap) break;
-            // the queue is empty for this wave: wait for the workgroup's tail
-            // (no lane holds a history: the state is dead)
-            P.x = P.y = P.z = P.u = P.v = P.w = P.tau = 0.0;
-            local = h = 0;
-            blk = segs = ncoll = attempts = sk = 0;
-            sforce = P.on_surf = kNone;
-            recovf = birth = sfpos = false;
-            P.depth = 1;
-            P.on_level = -1;
-            sL = 0;
-            end = GT_END_NONE;
+            if (!meetings) break;
+            // the queue is empty for this wave: wait for the workgroup's next
+            // meeting (no lane holds a history: the state is dead)
+            clear_state();
             __builtin_amdgcn_s_sleep(2);
             continue;
         }

@@ -769,7 +769,8 @@ int gt::check_track_args(const gt_geometry *g, const gt_track_params *p, const g
     if (p->block_size && (p->block_size % 64 || p->block_size > 1024))
         return set_error("gt_track: block_size must be a multiple of 64 up to 1024"), GT_EINVAL;
     if (p->refill_min > 64) return set_error("gt_track: refill_min must be at most 64"), GT_EINVAL;
-    if (p->reserved) return set_error("gt_track: reserved must be 0"), GT_EINVAL;
+    if (p->regroup_every && (p->flags & GT_FLAG_LANE_PER_HISTORY))
+        return set_error("gt_track: regroup_every needs the persistent schedule"), GT_EINVAL;
     if (p->first_particle + p->n_particles < p->first_particle)
         return set_error("gt_track: particle id range overflows"), GT_EINVAL;
     if ((uint64_t)p->record_first_k * p->record_cap > (1ull << 40))
@@ -818,7 +819,8 @@ extern "C" int gt_track_event(const gt_geometry *g, const gt_track_params *p, co
     if (rc) return rc;
     if (p->flags & ~GT_FLAG_ACCUMULATE)
         return set_error("gt_track_event: only GT_FLAG_ACCUMULATE applies"), GT_EINVAL;
-    if (p->block_size || p->refill_min) return set_error("gt_track_event: no launch shape to set"), GT_EINVAL;
+    if (p->block_size || p->refill_min || p->regroup_every)
+        return set_error("gt_track_event: no launch shape to set"), GT_EINVAL;
     const uint64_t need = ev_layout(p->n_particles, nullptr, nullptr);
     if (p->n_particles && (!bank || bank_bytes < need))
         return set_error("gt_track_event: the bank needs %llu bytes", (unsigned long long)need), GT_EINVAL;
@@ -838,6 +840,9 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
     const uint64_t chunk = tuning && tuning->chunk ? tuning->chunk : 16384;
     if (block % 64 || block > 1024) return set_error("gt_batch_create: block_size must be a multiple of 64 up to 1024"), GT_EINVAL;
     if (refill > 64) return set_error("gt_batch_create: refill_min must be at most 64"), GT_EINVAL;
+    if (tuning && tuning->reserved) return set_error("gt_batch_create: tuning reserved must be 0"), GT_EINVAL;
+    const uint32_t regroup =
+        tuning && tuning->regroup_every ? tuning->regroup_every : items[0].params.regroup_every;
     try {
         const uint32_t prec = items[0].params.precision;
         const int dev = items[0].geometry ? items[0].geometry->device : 0;
@@ -940,6 +945,7 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
         b->d_queue = (unsigned long long *)(base + o_queue);
         for (int k = 0; k < 4; k++) b->lds_bytes[k] = lds[k];
         b->tail = (items[0].params.flags & GT_FLAG_TAIL_COMPACTION) != 0;
+        b->regroup = regroup;
         b->cache = !(items[0].params.flags & GT_FLAG_NO_TALLY_CACHE);
         b->side = nullptr;
         const int rcs = prepare_batch_streams(b);
@@ -954,6 +960,11 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
     } catch (...) {
         return set_error("unexpected exception in gt_batch_create"), GT_EINVAL;
     }
+}
+
+extern "C" int gt_last_launch(gt_launch_info *out) {
+    if (!out) return set_error("gt_last_launch: out is NULL"), GT_EINVAL;
+    return last_launch(out) ? 1 : 0;
 }
 
 extern "C" int gt_set_kernel_events(void *start_event, void *stop_event) {

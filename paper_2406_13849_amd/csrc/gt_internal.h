@@ -215,6 +215,7 @@ struct gt_batch {
     unsigned long long *d_queue;        // one counter per staging kind
     uint32_t lds_bytes[4];              // staged tables' LDS bytes per kind (largest item)
     bool tail;                          // tail compaction on
+    uint32_t regroup;                   // loop trips between regroups (0 = off)
     bool cache;                         // per-lane tally cache on
     void *side;                         // helper streams and events for the staging-kind launches
                                         // (made by gt_batch_create when there are several kinds)
@@ -226,6 +227,7 @@ int check_track_args(const gt_geometry *g, const gt_track_params *p, const gt_tr
 void fill_kparams(const gt_track_params *p, const gt_geometry *g, KParams &kp, KOut &ko, const gt_track_out *o);
 unsigned stage_budget();
 void set_kernel_events(void *start, void *stop);
+bool last_launch(gt_launch_info *out);
 bool cached_batch_tuning(const gt_batch_item *items, uint32_t n_items, gt_tuning *out);
 int launch_batch(gt_batch *b, void *stream);
 int prepare_batch_streams(gt_batch *b);

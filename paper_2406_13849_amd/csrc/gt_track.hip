@@ -100,10 +100,11 @@ __global__ void __launch_bounds__(kBlock) k_ev_cross(Dev g0, KParams p, KOut o, 
 // SIMD the register budget is cut for: 4 (up to 1024 lanes per workgroup,
 // 128 registers) or 5 (640 lanes, two workgroups per compute unit, 96
 // registers).
-template <int PREC, int KIND, int W>
+template <int PREC, int KIND, int W, bool RG>
 __global__ void __launch_bounds__(W == 5 ? 640 : kBlockP) __attribute__((amdgpu_waves_per_eu(W)))
 k_track_persistent(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict__ lr, uint32_t tables_at,
-                   uint32_t tail_at, uint32_t tail_cap, uint32_t tail_round, uint32_t cache_at, uint32_t cache_k) {
+                   uint32_t tail_at, uint32_t tail_cap, uint32_t tail_round, uint32_t tail_words, uint32_t regroup,
+                   uint32_t cache_at, uint32_t cache_k) {
     __shared__ uint32_t ctl[1 + kBlockP / 64];
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_dyn[];
     uint32_t *cells = (uint32_t *)lds_dyn;   // the cell of each level, one column per lane
@@ -117,9 +118,9 @@ k_track_persistent(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict_
     uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     const GlobalQueue q = {(unsigned long long *)&o.counters[7], p.n};
-    const TailCfg tc = {(uint64_t *)(lds_dyn + tail_at), ctl, tail_cap, tail_round};
+    const TailCfg tc = {(uint64_t *)(lds_dyn + tail_at), ctl, tail_cap, tail_round, tail_words, regroup};
     const TallyCache tcache = tally_cache(lds_dyn, cache_at, cache_k);
-    track_pool<PREC>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc, tcache);
+    track_pool<PREC, RG>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc, tcache);
     add_counts(cnt, o.counters);
 }
 
@@ -132,20 +133,21 @@ __global__ void k_put_launch(LaunchRec r, LaunchRec *dst) {
 // (item, range of particle indices) from a device queue, copies the item's
 // tables into LDS when the item changes (KIND), and runs the lanes' state
 // machine over the chunk with a workgroup-local id counter.
-template <int PREC, int KIND, int W>
+template <int PREC, int KIND, int W, bool RG>
 __global__ void __launch_bounds__(W == 5 ? 640 : kBlockP) __attribute__((amdgpu_waves_per_eu(W)))
 k_track_batch(const BatchItem *__restrict__ items,
                                                          const BatchChunk *__restrict__ chunks,
                                                          uint32_t n_chunks, unsigned long long *queue,
                                                          uint32_t tables_at, uint32_t tail_at, uint32_t tail_cap,
-                                                         uint32_t tail_round, uint32_t cache_at, uint32_t cache_k) {
+                                                         uint32_t tail_round, uint32_t tail_words, uint32_t regroup,
+                                                         uint32_t cache_at, uint32_t cache_k) {
     __shared__ uint32_t ctl[1 + kBlockP / 64];
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_dyn[];
     __shared__ uint32_t s_chunk;
     __shared__ unsigned long long s_pool;
     uint32_t *cells = (uint32_t *)lds_dyn;   // the cell of each level, one column per lane
     unsigned char *lds_tables = lds_dyn + tables_at;
-    const TailCfg tc = {(uint64_t *)(lds_dyn + tail_at), ctl, tail_cap, tail_round};
+    const TailCfg tc = {(uint64_t *)(lds_dyn + tail_at), ctl, tail_cap, tail_round, tail_words, regroup};
     const TallyCache tcache = tally_cache(lds_dyn, cache_at, cache_k);
     // the descriptors are read-only for the whole launch: their fields are
     // read where needed (scalar loads the compiler may repeat) rather than
@@ -171,7 +173,7 @@ k_track_batch(const BatchItem *__restrict__ items,
         uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
         Counts cnt = {0, 0, 0, 0, 0, 0, 0};
         const ChunkQueue q = {&s_pool, first, first + count};
-        track_pool<PREC>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc, tcache);
+        track_pool<PREC, RG>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc, tcache);
         add_counts(cnt, o.counters);
         __syncthreads();
     }
@@ -354,14 +356,20 @@ int allow_dynamic_lds(const void *kernel, unsigned bytes) {
 // compute unit's LDS allows without lowering the number of resident
 // workgroups.
 struct LdsPlan {
-    unsigned dyn, tables_at, tail_at, tail_cap, cache_at, cache_k;
+    unsigned dyn, tables_at, tail_at, tail_cap, tail_words, regroup, cache_at, cache_k;
     int blocks;
 };
 
 constexpr unsigned kLdsPerCU = 160 * 1024;
 
-int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail, bool cache, int device,
-                    LdsPlan &lp) {
+// Dynamic LDS of a persistent launch: level columns, staged tables, then --
+// within the workgroup's share of the compute unit's LDS that keeps the
+// resident workgroups -- the regroup buffer (one word per lane), the tally
+// cache, and the rest for the tail compaction buffer (which may reuse the
+// regroup buffer).  A regroup that finds no room is left out (it never
+// changes a result).
+int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail, bool cache, uint32_t regroup,
+                    int device, LdsPlan &lp) {
     hipFuncAttributes fa;
     int rc = hip_check(hipFuncGetAttributes(&fa, kern), "hipFuncGetAttributes");
     if (rc) return rc;
@@ -370,7 +378,6 @@ int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail
         return set_error("staged tables exceed the LDS"), GT_ECAPACITY;
     rc = allow_dynamic_lds(kern, kLdsPerCU - stat);
     if (rc) return rc;
-    // dynamic LDS: level columns, staged tables, tally cache, tail buffer
     const unsigned tables_at = (GT_MAX_LEVELS * 4u * block + 15u) & ~15u;
     const unsigned base = tables_at + ((tables + 15u) & ~15u);
     int blocks = 0;
@@ -380,26 +387,30 @@ int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail
     rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
     if (rc) return rc;
     const unsigned per = (unsigned)std::max(1, blocks / std::max(cus, 1));
-    // what is left of the workgroup's share of the compute unit's LDS (the
-    // share that keeps `per` workgroups resident)
     long avail = (long)(kLdsPerCU / per) - (long)stat - (long)base - 512;
+    long rg_bytes = 0;
+    if (regroup && block > 64 && avail >= 8L * block) rg_bytes = 8L * block;
+    else regroup = 0;
+    avail -= rg_bytes;
     unsigned ck = 0;
     if (cache && avail > 0) ck = std::min<unsigned>(kTallyCacheMax, (unsigned)(avail / (kTallyCacheEntry * block)));
     const unsigned cache_bytes = (ck * kTallyCacheEntry * block + 15u) & ~15u;
     avail -= (long)cache_bytes;
-    const unsigned tail_at = base + cache_bytes;
+    const long buf_bytes = rg_bytes + std::max(avail, 0L);   // the buffer may use all that is left
     unsigned cap = 0;
     if (tail && block > 64) {
-        if (avail > 0) cap = std::min<unsigned>((unsigned)(avail / (kTailFields * 8)), block);
+        cap = (unsigned)std::min<long>(buf_bytes / (kTailFields * 8), (long)block);
         if (cap < 64) cap = 0;
     }
-    unsigned dyn = tail_at + cap * kTailFields * 8;
+    unsigned words = std::max(cap * kTailFields, regroup ? block : 0u);
+    const unsigned tail_at = base + cache_bytes;
+    unsigned dyn = tail_at + words * 8u;
     if (dyn != base) {
         int b2 = 0;
         rc = persistent_grid(kern, block, dyn, device, &b2);
         if (rc) return rc;
         if (b2 < blocks) {   // cache and buffer would cost a resident workgroup: go without
-            ck = cap = 0;
+            ck = cap = words = regroup = 0;
             dyn = base;
         }
     }
@@ -409,6 +420,8 @@ int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail
     lp.cache_k = ck;
     lp.tail_at = ck ? tail_at : base;
     lp.tail_cap = cap;
+    lp.tail_words = words;
+    lp.regroup = regroup;
     lp.blocks = blocks;
     return GT_OK;
 }
@@ -418,48 +431,87 @@ int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail
 // (set by gt_set_kernel_events; both null = off).
 thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
 
+// The plan of this thread's last persistent launch (gt_last_launch).
+thread_local gt_launch_info t_last_launch;
+thread_local bool t_have_launch = false;
+
+void note_launch(const LdsPlan &lp, int blocks, unsigned block, int kind) {
+    t_last_launch = {(uint32_t)blocks, block, lp.dyn, (uint32_t)kind, lp.cache_k, lp.tail_cap, lp.regroup, 0};
+    t_have_launch = true;
+}
+
 inline void mark(hipEvent_t e, hipStream_t st) {
     if (e) (void)hipEventRecord(e, st);
 }
 
-// One persistent tracker launch for a geometry of staging kind KIND.
+// One persistent tracker launch for a geometry of staging kind KIND (the
+// build with the regroup step when one is asked for and finds room).
 template <int PREC, int KIND, int W>
-int launch_persistent_k(const gt_geometry *g, uint64_t n, unsigned block, bool tail, bool cache, hipStream_t st) {
-    const void *kern = (const void *)k_track_persistent<PREC, KIND, W>;
+int launch_persistent_k(const gt_geometry *g, uint64_t n, unsigned block, bool tail, bool cache, uint32_t regroup,
+                        hipStream_t st) {
+    const unsigned tables = KIND == SK_NONE ? 0 : g->stage[PREC].total;
+    const void *kern = (const void *)k_track_persistent<PREC, KIND, W, false>;
     LdsPlan lp;
-    int rc = plan_persistent(kern, block, KIND == SK_NONE ? 0 : g->stage[PREC].total, tail, cache, g->device, lp);
+    int rc = GT_OK;
+    if (regroup) {
+        const void *kr = (const void *)k_track_persistent<PREC, KIND, W, true>;
+        rc = plan_persistent(kr, block, tables, tail, cache, regroup, g->device, lp);
+        if (!rc && lp.regroup) kern = kr;
+    }
+    if (!rc && kern == (const void *)k_track_persistent<PREC, KIND, W, false>)
+        rc = plan_persistent(kern, block, tables, tail, cache, 0, g->device, lp);
     if (rc) return rc;
     int blocks = lp.blocks;
     const uint64_t need = (n + block - 1) / block;
     if ((uint64_t)blocks > need) blocks = (int)need;
-    hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W>), dim3(blocks), dim3(block), lp.dyn, st, g->desc,
-                       (const LaunchRec *)g->launch, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.cache_at,
-                       lp.cache_k);
+    note_launch(lp, blocks, block, KIND);
+    if (lp.regroup)
+        hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, true>), dim3(blocks), dim3(block), lp.dyn, st,
+                           g->desc, (const LaunchRec *)g->launch, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound,
+                           lp.tail_words, lp.regroup, lp.cache_at, lp.cache_k);
+    else
+        hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, false>), dim3(blocks), dim3(block), lp.dyn, st,
+                           g->desc, (const LaunchRec *)g->launch, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound,
+                           lp.tail_words, 0u, lp.cache_at, lp.cache_k);
     return GT_OK;
 }
 
 template <int PREC, int W>
 int launch_persistent(const gt_geometry *g, int kind, uint64_t n, unsigned block, bool tail, bool cache,
-                      hipStream_t st) {
+                      uint32_t regroup, hipStream_t st) {
     switch (kind) {
-    case SK_ALL: return launch_persistent_k<PREC, SK_ALL, W>(g, n, block, tail, cache, st);
-    case SK_LDS: return launch_persistent_k<PREC, SK_LDS, W>(g, n, block, tail, cache, st);
-    case SK_SPLIT: return launch_persistent_k<PREC, SK_SPLIT, W>(g, n, block, tail, cache, st);
-    default: return launch_persistent_k<PREC, SK_NONE, W>(g, n, block, tail, cache, st);
+    case SK_ALL: return launch_persistent_k<PREC, SK_ALL, W>(g, n, block, tail, cache, regroup, st);
+    case SK_LDS: return launch_persistent_k<PREC, SK_LDS, W>(g, n, block, tail, cache, regroup, st);
+    case SK_SPLIT: return launch_persistent_k<PREC, SK_SPLIT, W>(g, n, block, tail, cache, regroup, st);
+    default: return launch_persistent_k<PREC, SK_NONE, W>(g, n, block, tail, cache, regroup, st);
     }
 }
 
 // The chunks of one staging kind of a batch, in one launch.
 template <int PREC, int KIND, int W>
 int launch_batch_k(gt_batch *b, const BatchChunk *ch, uint32_t n, unsigned long long *q, hipStream_t st) {
-    const void *kern = (const void *)k_track_batch<PREC, KIND, W>;
+    const void *kern = (const void *)k_track_batch<PREC, KIND, W, false>;
     LdsPlan lp;
-    int rc = plan_persistent(kern, b->block, b->lds_bytes[KIND], b->tail, b->cache, b->device, lp);
+    int rc = GT_OK;
+    if (b->regroup) {
+        const void *kr = (const void *)k_track_batch<PREC, KIND, W, true>;
+        rc = plan_persistent(kr, b->block, b->lds_bytes[KIND], b->tail, b->cache, b->regroup, b->device, lp);
+        if (!rc && lp.regroup) kern = kr;
+    }
+    if (!rc && kern == (const void *)k_track_batch<PREC, KIND, W, false>)
+        rc = plan_persistent(kern, b->block, b->lds_bytes[KIND], b->tail, b->cache, 0, b->device, lp);
     if (rc) return rc;
     int blocks = lp.blocks;
     if ((uint32_t)blocks > n) blocks = (int)n;
-    hipLaunchKernelGGL((k_track_batch<PREC, KIND, W>), dim3(blocks), dim3(b->block), lp.dyn, st, b->d_items, ch, n, q,
-                       lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.cache_at, lp.cache_k);
+    note_launch(lp, blocks, b->block, KIND);
+    if (lp.regroup)
+        hipLaunchKernelGGL((k_track_batch<PREC, KIND, W, true>), dim3(blocks), dim3(b->block), lp.dyn, st,
+                           b->d_items, ch, n, q, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.tail_words,
+                           lp.regroup, lp.cache_at, lp.cache_k);
+    else
+        hipLaunchKernelGGL((k_track_batch<PREC, KIND, W, false>), dim3(blocks), dim3(b->block), lp.dyn, st,
+                           b->d_items, ch, n, q, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.tail_words,
+                           0u, lp.cache_at, lp.cache_k);
     return GT_OK;
 }
 
@@ -568,8 +620,9 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
             hipLaunchKernelGGL(k_put_launch, dim3(1), dim3(64), 0, st, rec, g->launch);
             const bool tail = (p->flags & GT_FLAG_TAIL_COMPACTION) != 0;
             const bool cache = !(p->flags & GT_FLAG_NO_TALLY_CACHE);
-            int rc = block == 640 ? launch_persistent<PREC, 5>(g, kind, kp.n, block, tail, cache, st)
-                                  : launch_persistent<PREC, 4>(g, kind, kp.n, block, tail, cache, st);
+            const uint32_t rg = p->regroup_every;
+            int rc = block == 640 ? launch_persistent<PREC, 5>(g, kind, kp.n, block, tail, cache, rg, st)
+                                  : launch_persistent<PREC, 4>(g, kind, kp.n, block, tail, cache, rg, st);
             if (rc) return rc;
         }
     }
@@ -646,6 +699,11 @@ int launch_batch_t(gt_batch *b, hipStream_t st) {
 void set_kernel_events(void *start, void *stop) {
     t_ev_start = (hipEvent_t)start;
     t_ev_stop = (hipEvent_t)stop;
+}
+
+bool last_launch(gt_launch_info *out) {
+    if (t_have_launch) *out = t_last_launch;
+    return t_have_launch;
 }
 
 int prepare_batch_streams(gt_batch *b) {

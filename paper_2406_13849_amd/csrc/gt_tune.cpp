@@ -68,6 +68,7 @@ int time_launches(F launch, uint32_t reps, hipStream_t st, float *ms) {
 const uint32_t kBlocks[] = {256, 512, 640, 1024};
 const uint32_t kRefills[] = {1, 4, 8, 16};
 const uint64_t kChunks[] = {4096, 16384, 65536};
+const uint32_t kRegroups[] = {16, 64, 256};   // second stage, at the fastest shape of the first
 
 }  // namespace
 
@@ -80,27 +81,34 @@ extern "C" int gt_autotune_track(const gt_geometry *g, const gt_track_params *p,
         return set_error("gt_autotune_track: the one-history-per-lane schedule has no shape to tune"), GT_EINVAL;
     if (reps < 1) reps = 1;
     const hipStream_t st = (hipStream_t)stream;
-    gt_tuning win = {0, 0, 0};
+    gt_tuning win = {0, 0, 0, 0, 0};
     float win_ms = 0;
     bool any = false;
-    for (uint32_t b : kBlocks)
-        for (uint32_t r : kRefills) {
-            gt_track_params q = *p;
-            q.block_size = b;
-            q.refill_min = r;
-            float ms = 0;
-            rc = time_launches([&] { return launch_track(g, &q, o, stream); }, reps, st, &ms);
-            if (rc) return rc;
-            if (!any || ms < win_ms) {
-                win = {b, r, 0};
-                win_ms = ms;
-                any = true;
-            }
+    auto trial = [&](const gt_tuning &t) {
+        gt_track_params q = *p;
+        q.block_size = t.block_size;
+        q.refill_min = t.refill_min;
+        q.regroup_every = t.regroup_every;
+        float ms = 0;
+        const int r = time_launches([&] { return launch_track(g, &q, o, stream); }, reps, st, &ms);
+        if (!r && (!any || ms < win_ms)) {
+            win = t;
+            win_ms = ms;
+            any = true;
         }
+        return r;
+    };
+    for (uint32_t b : kBlocks)
+        for (uint32_t r : kRefills)
+            if ((rc = trial({b, r, 0, 0, 0}))) return rc;
+    const gt_tuning shape = win;
+    for (uint32_t rg : kRegroups)
+        if ((rc = trial({shape.block_size, shape.refill_min, 0, rg, 0}))) return rc;
     // leave the outputs of the caller's own parameters with the chosen shape
     gt_track_params q = *p;
     q.block_size = win.block_size;
     q.refill_min = win.refill_min;
+    q.regroup_every = win.regroup_every;
     rc = launch_track(g, &q, o, stream);
     if (rc) return rc;
     *best = win;
@@ -124,28 +132,33 @@ extern "C" int gt_autotune_batch(const gt_batch_item *items, uint32_t n_items, u
     if (!best) return set_error("gt_autotune_batch: best is NULL"), GT_EINVAL;
     if (reps < 1) reps = 1;
     const hipStream_t st = (hipStream_t)stream;
-    gt_tuning win = {0, 0, 0};
+    gt_tuning win = {0, 0, 0, 0, 0};
     float win_ms = 0;
     bool any = false;
+    auto trial = [&](const gt_tuning &t) {
+        gt_batch *bt = nullptr;
+        int rc = gt_batch_create(items, n_items, &t, &bt);
+        if (rc) return rc;
+        float ms = 0;
+        rc = time_launches([&] { return gt_batch_launch(bt, stream); }, reps, st, &ms);
+        gt_batch_destroy(bt);
+        if (!rc && (!any || ms < win_ms)) {
+            win = t;
+            win_ms = ms;
+            any = true;
+        }
+        return rc;
+    };
+    // (the first stage keeps the items' own regroup setting)
     for (uint32_t b : kBlocks) {
         if (b < 512) continue;   // a batch runs one workgroup's chunk at a time: keep workgroups large
         for (uint32_t r : kRefills)
-            for (uint64_t c : kChunks) {
-                gt_tuning t = {b, r, c};
-                gt_batch *bt = nullptr;
-                int rc = gt_batch_create(items, n_items, &t, &bt);
-                if (rc) return rc;
-                float ms = 0;
-                rc = time_launches([&] { return gt_batch_launch(bt, stream); }, reps, st, &ms);
-                gt_batch_destroy(bt);
-                if (rc) return rc;
-                if (!any || ms < win_ms) {
-                    win = t;
-                    win_ms = ms;
-                    any = true;
-                }
-            }
+            for (uint64_t c : kChunks)
+                if (int rc = trial({b, r, c, 0, 0})) return rc;
     }
+    const gt_tuning shape = win;
+    for (uint32_t rg : kRegroups)
+        if (int rc = trial({shape.block_size, shape.refill_min, shape.chunk, rg, 0})) return rc;
     *best = win;
     if (best_ms) *best_ms = win_ms / (float)reps;
     std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -53,7 +53,7 @@ class _Params(C.Structure):
         ("geometry_id", C.c_uint32), ("max_collisions", C.c_uint32), ("source", C.c_uint32),
         ("ray_n1", C.c_uint32), ("max_segments", C.c_uint32), ("precision", C.c_uint32),
         ("record_first_k", C.c_uint32), ("record_cap", C.c_uint32), ("flags", C.c_uint32),
-        ("block_size", C.c_uint32), ("refill_min", C.c_uint32), ("reserved", C.c_uint32),
+        ("block_size", C.c_uint32), ("refill_min", C.c_uint32), ("regroup_every", C.c_uint32),
     ]
 
 
@@ -69,7 +69,13 @@ class _BatchItem(C.Structure):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("block_size", C.c_uint32), ("refill_min", C.c_uint32), ("chunk", C.c_uint64)]
+    _fields_ = [("block_size", C.c_uint32), ("refill_min", C.c_uint32), ("chunk", C.c_uint64),
+                ("regroup_every", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class _LaunchInfo(C.Structure):
+    _fields_ = [(n, C.c_uint32) for n in ("workgroups", "block_size", "lds_bytes", "staging_kind",
+                                          "tally_cache_entries", "tail_capacity", "regroup_every", "reserved")]
 
 
 _lib = None
@@ -103,6 +109,8 @@ def lib():
         L.gt_batch_launch.restype = i32
         L.gt_batch_destroy.argtypes = [vp]
         L.gt_batch_destroy.restype = None
+        L.gt_last_launch.argtypes = [C.POINTER(_LaunchInfo)]
+        L.gt_last_launch.restype = i32
         L.gt_track_batch.argtypes = [C.POINTER(_BatchItem), u32, C.POINTER(_Tuning), vp]
         L.gt_track_batch.restype = i32
         L.gt_autotune_track.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), u32, vp, C.POINTER(_Tuning),
@@ -233,19 +241,20 @@ def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 
           max_collisions: int = 20, source: int = 0, ray_n1: int = 0, max_segments: int = 100_000,
           precision: int = PREC_MIXED, record_first_k: int = 0, record_cap: int = 0, accumulate: bool = False,
           lane_per_history: bool = False, staging: bool = True, block_size: int = 0, refill_min: int = 0,
-          tail_compaction: bool = False, tally_cache: bool = True, out: Optional[TrackOutputs] = None,
-          stream=None) -> TrackOutputs:
+          tail_compaction: bool = False, tally_cache: bool = True, regroup_every: int = 0,
+          out: Optional[TrackOutputs] = None, stream=None) -> TrackOutputs:
     """gt_track: sample and track n_particles histories (asynchronous).
     lane_per_history selects the plain one-history-per-lane schedule instead
     of the persistent refilling one; staging=False keeps the geometry tables
     in global memory even when they fit in LDS; tail_compaction=True packs
     the histories left after the queue has drained into fewer waves; tally_cache=False
-    flushes a lane's tally sum at every change of instance."""
+    flushes a lane's tally sum at every change of instance; regroup_every=R
+    sorts a workgroup's histories by leaf universe every R loop trips."""
     if out is None:
         out = alloc_outputs(geom, n_particles, record_first_k, record_cap)
     prm = _params(seed, n_particles, first_particle, geometry_id, max_collisions, source, ray_n1, max_segments,
                   precision, record_first_k, record_cap, accumulate, lane_per_history, staging, block_size,
-                  refill_min, tail_compaction, tally_cache)
+                  refill_min, tail_compaction, tally_cache, regroup_every)
     o = _out_struct(out)
     _check(lib().gt_track(geom.h, C.byref(prm), C.byref(o), _stream(stream)))
     return out
@@ -278,14 +287,14 @@ def track_event(geom: Geometry, seed: int, n_particles: int, *, bank=None, out: 
 def _params(seed, n_particles, first_particle=0, geometry_id=0, max_collisions=20, source=0, ray_n1=0,
             max_segments=100_000, precision=PREC_MIXED, record_first_k=0, record_cap=0, accumulate=False,
             lane_per_history=False, staging=True, block_size=0, refill_min=0, tail_compaction=False,
-            tally_cache=True) -> _Params:
+            tally_cache=True, regroup_every=0) -> _Params:
     return _Params(seed=seed, first_particle=first_particle, n_particles=n_particles, geometry_id=geometry_id,
                    max_collisions=max_collisions, source=source, ray_n1=ray_n1, max_segments=max_segments,
                    precision=precision, record_first_k=record_first_k, record_cap=record_cap,
                    flags=(FLAG_ACCUMULATE if accumulate else 0) | (FLAG_LANE_PER_HISTORY if lane_per_history else 0)
                    | (0 if staging else FLAG_NO_STAGING) | (FLAG_TAIL_COMPACTION if tail_compaction else 0)
                    | (0 if tally_cache else FLAG_NO_TALLY_CACHE),
-                   block_size=block_size, refill_min=refill_min, reserved=0)
+                   block_size=block_size, refill_min=refill_min, regroup_every=regroup_every)
 
 
 def _out_struct(out: TrackOutputs) -> _Out:
@@ -310,12 +319,14 @@ class Batch:
     tracked by one persistent launch.  The descriptors hold the geometries'
     tables and the outputs' addresses, so both are kept alive here."""
 
-    def __init__(self, items, block_size: int = 0, refill_min: int = 0, chunk: int = 0, tuned: bool = False):
+    def __init__(self, items, block_size: int = 0, refill_min: int = 0, chunk: int = 0, regroup_every: int = 0,
+                 tuned: bool = False):
         """tuned=True passes no tuning: the shape gt_autotune_batch found for
         these items (else the defaults)."""
         self.items = list(items)
         arr = _batch_array(self.items)
-        tun = None if tuned else C.byref(_Tuning(block_size=block_size, refill_min=refill_min, chunk=chunk))
+        tun = None if tuned else C.byref(_Tuning(block_size=block_size, refill_min=refill_min, chunk=chunk,
+                                                 regroup_every=regroup_every))
         h = C.c_void_p()
         _check(lib().gt_batch_create(arr, len(self.items), tun, C.byref(h)))
         self.h = h.value
@@ -342,18 +353,19 @@ def batch_item(geom: Geometry, seed: int, n_particles: int, out: Optional[TrackO
     return BatchItem(geom, seed, n_particles, out, kwargs)
 
 
-def track_batch(items, block_size: int = 0, refill_min: int = 0, chunk: int = 0, tuned: bool = False,
-                stream=None):
+def track_batch(items, block_size: int = 0, refill_min: int = 0, chunk: int = 0, regroup_every: int = 0,
+                tuned: bool = False, stream=None):
     """gt_track_batch: one-shot batch (waits for the stream)."""
     arr = _batch_array(items)
-    tun = None if tuned else C.byref(_Tuning(block_size=block_size, refill_min=refill_min, chunk=chunk))
+    tun = None if tuned else C.byref(_Tuning(block_size=block_size, refill_min=refill_min, chunk=chunk,
+                                             regroup_every=regroup_every))
     _check(lib().gt_track_batch(arr, len(items), tun, _stream(stream)))
     return [it.out for it in items]
 
 
 def autotune_track(geom: Geometry, seed: int, n_particles: int, out: Optional[TrackOutputs] = None, reps: int = 3,
                    stream=None, **kwargs) -> dict:
-    """gt_autotune_track: the fastest (block_size, refill_min) for these
+    """gt_autotune_track: the fastest (block_size, refill_min, regroup_every) for these
     parameters (the outputs are overwritten and end as those of one launch
     with that shape); also cached in the library for gt_tuning_lookup."""
     if out is None:
@@ -363,7 +375,8 @@ def autotune_track(geom: Geometry, seed: int, n_particles: int, out: Optional[Tr
     ms = C.c_float()
     _check(lib().gt_autotune_track(geom.h, C.byref(prm), C.byref(_out_struct(out)), reps, _stream(stream),
                                    C.byref(best), C.byref(ms)))
-    return dict(block_size=best.block_size, refill_min=best.refill_min, ms=ms.value)
+    return dict(block_size=best.block_size, refill_min=best.refill_min, regroup_every=best.regroup_every,
+                ms=ms.value)
 
 
 def tuning_lookup(geom: Geometry, seed: int, n_particles: int, **kwargs) -> Optional[dict]:
@@ -373,7 +386,8 @@ def tuning_lookup(geom: Geometry, seed: int, n_particles: int, **kwargs) -> Opti
     rc = lib().gt_tuning_lookup(geom.h, C.byref(prm), C.byref(best))
     if rc < 0:
         _check(rc)
-    return dict(block_size=best.block_size, refill_min=best.refill_min) if rc == 1 else None
+    return (dict(block_size=best.block_size, refill_min=best.refill_min, regroup_every=best.regroup_every)
+            if rc == 1 else None)
 
 
 def _batch_array(items):
@@ -386,13 +400,25 @@ def _batch_array(items):
 
 
 def autotune_batch(items, reps: int = 1, stream=None) -> dict:
-    """gt_autotune_batch: the fastest (block_size, refill_min, chunk) for this
+    """gt_autotune_batch: the fastest (block_size, refill_min, chunk, regroup_every) for this
     list of items; Batch(items) and track_batch(items) then use it."""
     best = _Tuning()
     ms = C.c_float()
     _check(lib().gt_autotune_batch(_batch_array(items), len(items), reps, _stream(stream), C.byref(best),
                                    C.byref(ms)))
-    return dict(block_size=best.block_size, refill_min=best.refill_min, chunk=best.chunk, ms=ms.value)
+    return dict(block_size=best.block_size, refill_min=best.refill_min, chunk=best.chunk,
+                regroup_every=best.regroup_every, ms=ms.value)
+
+
+def last_launch() -> Optional[dict]:
+    """gt_last_launch: the plan of this thread's last persistent tracker
+    launch (workgroups, block size, LDS bytes, staging kind, tally-cache
+    entries, tail capacity, regroup interval), or None."""
+    info = _LaunchInfo()
+    rc = lib().gt_last_launch(C.byref(info))
+    if rc < 0:
+        _check(rc)
+    return {n: getattr(info, n) for n, _ in _LaunchInfo._fields_ if n != "reserved"} if rc == 1 else None
 
 
 def set_kernel_events(start: Optional[int], stop: Optional[int]):

@@ -29,7 +29,7 @@ void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut
     KParams p = p0;
     p.refill_min = 1;   // a one-lane wave refills as soon as its lane is idle
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
-    const TailCfg tc = {nullptr, ctl, 0, kTailRound};
+    const TailCfg tc = {nullptr, ctl, 0, kTailRound, 0, 0};
     const TallyCache tcache = {c_lo, c_hi, c_tag, g_cache_k, 1};
     track_pool<PREC>(v, p, o, o.tally_ws, cells, q, cnt, tc, tcache);
     counts[GT_CNT_ESCAPED] += cnt.escaped;

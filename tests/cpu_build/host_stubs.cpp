@@ -54,4 +54,5 @@ int launch_fp64_check(const double *, const double *, uint64_t, double *, double
     return GT_EHIP;
 }
 void set_kernel_events(void *, void *) {}
+bool last_launch(gt_launch_info *) { return false; }   // no device launches here
 }  // namespace gt

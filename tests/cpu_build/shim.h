@@ -36,6 +36,7 @@ static inline int __popcll(unsigned long long m) { return __builtin_popcountll(m
 static inline int __ffsll(unsigned long long m) { return __builtin_ffsll((long long)m); }
 static inline unsigned __lane_id() { return 0; }
 template <typename T> static inline T __shfl(T v, int) { return v; }
+template <typename T> static inline T __shfl_up(T v, unsigned) { return v; }   // no lane below lane 0
 static inline uint32_t __builtin_amdgcn_mbcnt_lo(uint32_t, uint32_t c) { return c; }
 static inline uint32_t __builtin_amdgcn_mbcnt_hi(uint32_t, uint32_t c) { return c; }
 template <typename T> static inline T __builtin_amdgcn_readfirstlane(T v) { return v; }

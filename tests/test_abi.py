@@ -85,3 +85,33 @@ def test_null_arguments():
     assert L.gt_track(None, None, None, None) == gt.GT_EINVAL
     assert L.gt_find_cell(None, None, 1, None, None, 0, None) == gt.GT_EINVAL
     assert L.gt_fp64_check(None, None, 5, None, None, None, None) == gt.GT_EINVAL
+
+
+def test_binding_struct_layouts_match_the_header(tmp_path):
+    """The ctypes structures of the binding have the header's sizes and
+    field offsets (a C program compiled against include/gt.h prints them)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"gt_track_params": gt._Params, "gt_track_out": gt._Out, "gt_batch_item": gt._BatchItem,
+               "gt_tuning": gt._Tuning, "gt_launch_info": gt._LaunchInfo, "gt_flat_geometry": gt._Flat}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gt.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, f, name, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        k, v = ln.rsplit(" ", 1)
+        got[k] = int(v)
+    for name, cls in structs.items():
+        assert got["%s size" % name] == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got["%s %s" % (name, f)] == getattr(cls, f).offset, (name, f)

@@ -220,6 +220,57 @@ def test_tally_cache_on_and_off(cfg, block, cache):
     assert_parity(g, o, where="tally cache %s cfg %s block %d" % (cache, cfg, block))
 
 
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, "hex_pin_box", "nested_box"])
+@pytest.mark.parametrize("block,every", [(1024, 1), (1024, 16), (640, 7), (128, 3)])
+def test_regroup_matches_oracle(cfg, block, every):
+    """Lanes sorted across the workgroup by leaf universe every few loop
+    trips, each history's state moved whole through LDS: same results, and
+    the launch did run the regroup build."""
+    fg, G, O = geoms(cfg)
+    gid = cfg if isinstance(cfg, int) else 13
+    kw = dict(seed=79, n_particles=6000, geometry_id=gid)
+    print("regroup", cfg, "block", block, "every", every, flush=True)
+    g = gpu_track(G, precision=gt.PREC_MIXED, block_size=block, regroup_every=every, record_first_k=50,
+                  record_cap=64, **kw)
+    info = gt.last_launch()
+    assert info["block_size"] == block, info
+    # the hexagonal core's tables at 640 lanes fill the LDS share of two
+    # workgroups per compute unit: no room for the buffer, the plain build runs
+    assert info["regroup_every"] == (0 if (cfg, block) == (4, 640) else every), info
+    o = oracle.track(O, oracle.TrackParams(record_first_k=50, record_cap=64, **kw), n_threads=NT)
+    assert_parity(g, o, where="regroup cfg %s block %d every %d" % (cfg, block, every))
+
+
+@pytest.mark.parametrize("prec,tail,staging", [(gt.PREC_FP64, False, True), (gt.PREC_MIXED, True, True),
+                                               (gt.PREC_MIXED, False, False)])
+def test_regroup_with_other_options(prec, tail, staging):
+    """Regroup in all-FP64, together with tail compaction, and with the
+    tables read from global memory."""
+    fg, G, O = geoms(2)
+    kw = dict(seed=80, n_particles=12_000, geometry_id=2)
+    print("regroup options", prec, tail, staging, flush=True)
+    g = gpu_track(G, precision=prec, regroup_every=8, tail_compaction=tail, staging=staging, record_first_k=40,
+                  record_cap=64, **kw)
+    info = gt.last_launch()
+    assert info["regroup_every"] == 8, info
+    assert (info["tail_capacity"] > 0) == tail, info
+    o = oracle.track(O, oracle.TrackParams(record_first_k=40, record_cap=64, **kw), n_threads=NT)
+    assert_parity(g, o, where="regroup options %s %s %s" % (prec, tail, staging))
+
+
+def test_regroup_arguments():
+    fg, G, O = geoms(1)
+    with pytest.raises(gt.GtError):
+        gt.track(G, seed=1, n_particles=10, regroup_every=4, lane_per_history=True)
+    with pytest.raises(gt.GtError):
+        gt.track_event(G, seed=1, n_particles=10, regroup_every=4)
+    # one wave per workgroup: nothing to sort across, the plain build runs
+    g = gpu_track(G, seed=81, n_particles=3000, geometry_id=1, block_size=64, regroup_every=4)
+    assert gt.last_launch()["regroup_every"] == 0
+    o = oracle.track(O, oracle.TrackParams(seed=81, n_particles=3000, geometry_id=1), n_threads=NT)
+    assert_parity(g, o, where="regroup, one wave")
+
+
 def test_accumulate_two_halves():
     import torch
     fg, G, O = geoms(1)
@@ -311,7 +362,8 @@ def test_batch_matches_oracle(prec, tail):
     """One batched launch over ten geometries (half of them forced to read
     their tables from global memory, so several staging-kind launches run on
     forked streams), with small chunks so every item is split into several
-    and ends ragged; with and without tail compaction."""
+    and ends ragged; with and without tail compaction (with it, also the
+    regroup step every 5 loop trips)."""
     import torch
     items, want = [], []
     for k, j in enumerate(BATCH_SUBSET):
@@ -324,8 +376,9 @@ def test_batch_matches_oracle(prec, tail):
                                                        geometry_id=synth.batch_geometry_id(j),
                                                        record_first_k=40, record_cap=64), n_threads=NT))
     print("batch of", len(items), "precision", prec, flush=True)
-    gt.track_batch(items, chunk=333)
+    gt.track_batch(items, chunk=333, regroup_every=5 if tail else 0)
     torch.cuda.synchronize()
+    assert gt.last_launch()["regroup_every"] == (5 if tail else 0)
     for j, it, o in zip(BATCH_SUBSET, items, want):
         assert_parity(_outs(it.out), o, where="batch item %d" % j)
 
@@ -462,8 +515,10 @@ def test_autotune_track_keeps_results():
     kw = dict(seed=515, n_particles=6000, geometry_id=2, record_first_k=30, record_cap=64)
     out = gt.alloc_outputs(G, 6000, 30, 64)
     shape = gt.autotune_track(G, out=out, reps=1, precision=gt.PREC_MIXED, **kw)
-    assert shape["block_size"] in (256, 512, 1024) and shape["refill_min"] in (1, 4, 8, 16)
-    assert gt.tuning_lookup(G, precision=gt.PREC_MIXED, **kw) == {k: shape[k] for k in ("block_size", "refill_min")}
+    assert shape["block_size"] in (256, 512, 640, 1024) and shape["refill_min"] in (1, 4, 8, 16)
+    assert shape["regroup_every"] in (0, 16, 64, 256)
+    assert gt.tuning_lookup(G, precision=gt.PREC_MIXED, **kw) == {
+        k: shape[k] for k in ("block_size", "refill_min", "regroup_every")}
     import torch
     torch.cuda.synchronize()
     o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT)
@@ -480,7 +535,8 @@ def test_autotune_batch_then_tuned_batch():
         want.append(oracle.track(O, oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=2500, **kw),
                                  n_threads=NT))
     shape = gt.autotune_batch(items, reps=1)
-    assert shape["block_size"] in (512, 1024) and shape["chunk"] in (4096, 16384, 65536)
+    assert shape["block_size"] in (512, 640, 1024) and shape["chunk"] in (4096, 16384, 65536)
+    assert shape["regroup_every"] in (0, 16, 64, 256)
     gt.track_batch(items, tuned=True)
     torch.cuda.synchronize()
     for it, o in zip(items, want):
