@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-geometry batched workload")
     ap.add_argument("--no-event", action="store_true", help="skip the event-based schedule leg")
     ap.add_argument("--tail", action="store_true", help="switch on tail compaction (comparison)")
+    ap.add_argument("--regroup", type=int, default=0,
+                    help="regroup the lanes by leaf universe every this many loop trips (comparison; 0 = off)")
+    ap.add_argument("--regroup-leg", type=int, default=64,
+                    help="interval of the extra leg timing the headline with regroup on (0 = no such leg)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the launch shape gt_autotune_track picks instead of the library default")
     ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)   # the default
@@ -120,18 +124,23 @@ def run_timed(gt, step, args, hev):
     return dict(ms=ms, kernel_ms=kms, wall=wall)
 
 
-def timed(gt, G, out, args, prec, hev, lane=False):
+def timed(gt, G, out, args, prec, hev, lane=False, regroup=None):
     kw = dict(seed=args.seed, n_particles=args.particles, geometry_id=args.config, precision=prec,
               block_size=args.block, out=out,
-              lane_per_history=lane, refill_min=0 if lane else args.refill, tail_compaction=args.tail)
+              lane_per_history=lane, refill_min=0 if lane else args.refill, tail_compaction=args.tail,
+              regroup_every=0 if lane else (args.regroup if regroup is None else regroup))
     shape = None
-    if not lane and args.autotune and not args.block and not args.refill:
-        shape = gt.autotune_track(G, reps=2, **{k: v for k, v in kw.items() if k not in ("block_size", "refill_min")})
+    if not lane and args.autotune and not args.block and not args.refill and regroup is None:
+        shape = gt.autotune_track(G, reps=2, **{k: v for k, v in kw.items()
+                                                if k not in ("block_size", "refill_min", "regroup_every")})
         kw["block_size"], kw["refill_min"] = shape["block_size"], shape["refill_min"]
+        kw["regroup_every"] = shape["regroup_every"]
     r = run_timed(gt, lambda: gt.track(G, **kw), args, hev)
     r["segments"] = out.counters_dict()["segments"]
     r["shape"] = {"block_size": kw["block_size"], "refill_min": kw["refill_min"],
-                  "autotuned": shape is not None}
+                  "regroup_every": kw["regroup_every"], "autotuned": shape is not None}
+    if not lane:
+        r["shape"]["plan"] = gt.last_launch()
     return r
 
 
@@ -322,6 +331,18 @@ def main():
         print("# mixed without lattice hints: %.3f ms/step" % (sum(res["nohint"]["ms"]) / args.steps),
               file=sys.stderr, flush=True)
         G2.close()
+    if args.only is None and args.regroup_leg:
+        # the headline with the regroup step on (lanes sorted by leaf universe)
+        out_rg = gt.alloc_outputs(G, n)
+        res["regroup"] = timed(gt, G, out_rg, args, gt.PREC_MIXED, hev, False, regroup=args.regroup_leg)
+        if "mixed" in res:   # result-neutral: the same sequences and tallies as the headline's
+            torch.cuda.synchronize()
+            res["regroup"]["identical"] = bool(torch.equal(out_rg.tally_fx, out.tally_fx) and
+                                               torch.equal(out_rg.seq_hash, out.seq_hash) and
+                                               torch.equal(out_rg.seg_count, out.seg_count))
+        print("# mixed with regroup every %d trips: %.3f ms/step" % (args.regroup_leg,
+                                                                     sum(res["regroup"]["ms"]) / args.steps),
+              file=sys.stderr, flush=True)
     if args.only in (None, "event") and not args.no_event:
         res["event"] = timed_event(gt, G, args, hev)
         print("# event: %.3f ms/step, %d segments/step" % (sum(res["event"]["ms"]) / args.steps,
@@ -356,11 +377,15 @@ def main():
                    "launch_shape": head["shape"]},
     }
     for name, label in (("fp64", "fp64"), ("plain_fp64", "plain_fp64_lane_per_history"),
-                        ("event", "event_based_mixed"), ("nohint", "mixed_without_lattice_hints")):
+                        ("event", "event_based_mixed"), ("nohint", "mixed_without_lattice_hints"),
+                        ("regroup", "mixed_with_regroup")):
         if name in res:
             f = res[name]
             fms = sum(f["ms"]) / len(f["ms"])
             line[label] = {"value": f["segments"] / (fms * 1e-3), "ms_per_step": fms}
+            if name == "regroup":
+                line[label]["regroup_every"] = f["shape"]["regroup_every"]
+                line[label]["identical_to_headline"] = f.get("identical")
     if "mixed" in res and "fp64" in res:
         line["mixed_over_fp64"] = line["value"] / line["fp64"]["value"]
     if "mixed" in res and "plain_fp64" in res:
