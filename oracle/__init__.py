@@ -66,7 +66,14 @@ class _Out(C.Structure):
     _fields_ = [
         ("tally_fx", C.c_void_p), ("tally", C.c_void_p), ("tally_fxd", C.c_void_p),
         ("seg_count", C.c_void_p), ("seq_hash", C.c_void_p), ("end_code", C.c_void_p),
-        ("rec", C.c_void_p), ("counters", C.c_void_p),
+        ("rec", C.c_void_p), ("counters", C.c_void_p), ("mesh", C.c_void_p),
+    ]
+
+
+class _Mesh(C.Structure):
+    _fields_ = [
+        ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("n", C.c_uint32 * 3), ("pad", C.c_uint32),
+        ("mesh_fx", C.c_void_p), ("mesh", C.c_void_p), ("mesh_fxd", C.c_void_p),
     ]
 
 
@@ -204,9 +211,15 @@ class TrackResult:
     end_code: np.ndarray
     rec: Optional[np.ndarray]         # [record_first_k, record_cap] i32, -1 padded
     counters: dict
+    mesh_fx: Optional[np.ndarray] = None    # [bins, 2] u64 (lo, hi) fixed point, quantum 2^-96
+    mesh: Optional[np.ndarray] = None       # [bins] Neumaier FP64 sums
+    mesh_fxd: Optional[np.ndarray] = None   # [bins] fixed point rounded to double
 
 
-def track(geom: OracleGeometry, p: TrackParams, n_threads: int = 0, tallies: bool = True) -> TrackResult:
+def track(geom: OracleGeometry, p: TrackParams, n_threads: int = 0, tallies: bool = True,
+          mesh=None) -> TrackResult:
+    """mesh = (lo[3], hi[3], n[3]) adds the superimposed mesh tally (bins
+    (iz * n[1] + iy) * n[0] + ix)."""
     if n_threads <= 0:
         n_threads = min(16, os.cpu_count() or 1)
     n = p.n_particles
@@ -221,11 +234,22 @@ def track(geom: OracleGeometry, p: TrackParams, n_threads: int = 0, tallies: boo
     cnt = np.zeros(8, np.uint64)
     out = _Out(tally_fx=_p(tfx), tally=_p(tally), tally_fxd=_p(tfxd), seg_count=_p(seg), seq_hash=_p(hsh),
                end_code=_p(end), rec=_p(rec), counters=_p(cnt))
+    m = mfx = msum = mfxd = None
+    if mesh is not None:
+        lo, hi, nm = mesh
+        nb = int(nm[0]) * int(nm[1]) * int(nm[2])
+        mfx, msum, mfxd = np.zeros((nb, 2), np.uint64), np.zeros(nb), np.zeros(nb)
+        m = _Mesh(mesh_fx=_p(mfx), mesh=_p(msum), mesh_fxd=_p(mfxd))
+        m.lo[:] = [float(v) for v in lo]
+        m.hi[:] = [float(v) for v in hi]
+        m.n[:] = [int(v) for v in nm]
+        out.mesh = C.cast(C.pointer(m), C.c_void_p)
     prm = p.c()
     rc = lib().or_track(geom.h, C.byref(prm), C.byref(out), int(n_threads))
     if rc != 0:
         raise RuntimeError("or_track failed (%d)" % rc)
-    return TrackResult(tally, tfx, tfxd, seg, hsh, end, rec, {k: int(v) for k, v in zip(COUNTERS, cnt)})
+    return TrackResult(tally, tfx, tfxd, seg, hsh, end, rec, {k: int(v) for k, v in zip(COUNTERS, cnt)},
+                       mfx, msum, mfxd)
 
 
 @dataclass

@@ -91,7 +91,21 @@ typedef struct {
     uint8_t *end_code;    /* [n_particles] */
     int32_t *rec;         /* [record_first_k * record_cap], -1 padded */
     uint64_t *counters;   /* [8] */
+    const struct or_mesh *mesh;   /* superimposed mesh tally, or NULL */
 } or_out;
+
+/* Superimposed mesh tally (the paper's active cycles add a regular mesh
+ * flux tally over the core): n[0] x n[1] x n[2] bins over the box [lo, hi],
+ * bin (ix, iy, iz) at index (iz * n[1] + iy) * n[0] + ix.  Outputs as the
+ * cell tally: 128-bit fixed point (quantum 2^-96), Neumaier sum, and the
+ * fixed point rounded to double; each may be NULL. */
+typedef struct or_mesh {
+    double lo[3], hi[3];
+    uint32_t n[3], pad;
+    uint64_t *mesh_fx;    /* [2 * bins] */
+    double *mesh;         /* [bins] */
+    double *mesh_fxd;     /* [bins] */
+} or_mesh;
 
 typedef struct {          /* per-segment record of one particle */
     uint32_t cap, n, n_flights, pad;
@@ -652,6 +666,10 @@ static double fx_to_double(u128 v) {
 typedef struct {
     double *sum, *comp;
     u128 *fx;
+    /* mesh tally (when mesh is not NULL): per bin, and a buffer of cuts */
+    const or_mesh *mesh;
+    double *msum, *mcomp, *cuts;
+    u128 *mfx;
 } tally_acc;
 
 static void neumaier_add(double *s, double *c, double x) {
@@ -659,6 +677,58 @@ static void neumaier_add(double *s, double *c, double x) {
     if (fabs(*s) >= fabs(x)) *c += (*s - t) + x;
     else *c += (x - t) + *s;
     *s = t;
+}
+
+/* ------------------------------------------------------------------ */
+/* mesh tally of one segment                                            */
+/* ------------------------------------------------------------------ */
+static uint64_t mesh_bins(const or_mesh *m) { return (uint64_t)m->n[0] * m->n[1] * m->n[2]; }
+
+static int cmp_double(const void *a, const void *b) {
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Track-length estimate of the segment p0 + t u, 0 <= t <= l, on the mesh.
+ * Plane k of axis a (k = 0 .. n[a]) sits at lo[a] + k w[a], w[a] = (hi[a] -
+ * lo[a]) / n[a]; the segment is cut at every t = (plane - p0[a]) / u[a] with
+ * 0 < t < l.  Each piece [t0, t1] between consecutive cuts (and the ends)
+ * adds t1 - t0 to the bin holding its midpoint p0 + ((t0 + t1) / 2) u, the
+ * bin index on axis a being floor((mid[a] - lo[a]) / w[a]); pieces whose
+ * midpoint is outside the mesh add nothing. */
+static void mesh_segment(tally_acc *acc, const double p0[3], const double u[3], double l) {
+    const or_mesh *m = acc->mesh;
+    double w[3];
+    for (int a = 0; a < 3; a++) w[a] = (m->hi[a] - m->lo[a]) / (double)m->n[a];
+    int nc = 0;
+    acc->cuts[nc++] = 0.0;
+    for (int a = 0; a < 3; a++) {
+        if (u[a] == 0.0) continue;
+        for (uint32_t k = 0; k <= m->n[a]; k++) {
+            double x = m->lo[a] + (double)k * w[a];
+            double t = (x - p0[a]) / u[a];
+            if (t > 0.0 && t < l) acc->cuts[nc++] = t;
+        }
+    }
+    acc->cuts[nc++] = l;
+    qsort(acc->cuts, (size_t)nc, sizeof(double), cmp_double);
+    for (int i = 0; i + 1 < nc; i++) {
+        double t0 = acc->cuts[i], t1 = acc->cuts[i + 1];
+        double tm = (t0 + t1) * 0.5;
+        uint64_t idx[3];
+        int inside = 1;
+        for (int a = 0; a < 3; a++) {
+            double mid = p0[a] + tm * u[a];
+            double f = floor((mid - m->lo[a]) / w[a]);
+            if (!(f >= 0.0 && f < (double)m->n[a])) { inside = 0; break; }
+            idx[a] = (uint64_t)f;
+        }
+        if (!inside) continue;
+        uint64_t b = (idx[2] * m->n[1] + idx[1]) * m->n[0] + idx[0];
+        double piece = t1 - t0;
+        neumaier_add(&acc->msum[b], &acc->mcomp[b], piece);
+        acc->mfx[b] += fx_of(piece);
+    }
 }
 
 /* ------------------------------------------------------------------ */
@@ -707,6 +777,7 @@ static void run_history(const or_geom *g, const or_params *pr, uint64_t local, t
             l = sc;
         }
         /* move_within_cell */
+        const double p0[3] = { t.p[0], t.p[1], t.p[2] };
         double m0 = l * t.u[0], m1 = l * t.u[1], m2 = l * t.u[2];
         t.p[0] = t.p[0] + m0; t.p[1] = t.p[1] + m1; t.p[2] = t.p[2] + m2;
         METER(6);
@@ -714,6 +785,7 @@ static void run_history(const or_geom *g, const or_params *pr, uint64_t local, t
         if (acc) {
             neumaier_add(&acc->sum[inst], &acc->comp[inst], l);
             acc->fx[inst] += fx_of(l);
+            if (acc->mesh) mesh_segment(acc, p0, t.u, l);
         }
         h = (h ^ (inst + 1)) * FNV_PRIME;
         if (rec) {
@@ -801,12 +873,30 @@ int or_track(const or_geom *g, const or_params *pr, const or_out *out, int n_thr
         jobs[k].g = g; jobs[k].pr = pr; jobs[k].out = out;
         jobs[k].i0 = n * (uint64_t)k / (uint64_t)n_threads;
         jobs[k].i1 = n * (uint64_t)(k + 1) / (uint64_t)n_threads;
-        if (want_tally) {
+        if (want_tally || out->mesh) {
             jobs[k].acc.sum = calloc(g->n_inst, sizeof(double));
             jobs[k].acc.comp = calloc(g->n_inst, sizeof(double));
             jobs[k].acc.fx = calloc(g->n_inst, sizeof(u128));
             if (!jobs[k].acc.sum || !jobs[k].acc.comp || !jobs[k].acc.fx) jobs[k].err = 1;
         }
+        if (out->mesh) {
+            const or_mesh *m = out->mesh;
+            uint64_t nb = mesh_bins(m);
+            jobs[k].acc.mesh = m;
+            jobs[k].acc.msum = calloc(nb, sizeof(double));
+            jobs[k].acc.mcomp = calloc(nb, sizeof(double));
+            jobs[k].acc.mfx = calloc(nb, sizeof(u128));
+            jobs[k].acc.cuts = malloc(sizeof(double) * ((size_t)m->n[0] + m->n[1] + m->n[2] + 5));
+            if (!jobs[k].acc.msum || !jobs[k].acc.mcomp || !jobs[k].acc.mfx || !jobs[k].acc.cuts) jobs[k].err = 1;
+        }
+    }
+    if (out->mesh) {
+        const or_mesh *m = out->mesh;
+        for (int a = 0; a < 3; a++)
+            if (m->n[a] < 1 || !(m->hi[a] > m->lo[a]) || !isfinite(m->lo[a]) || !isfinite(m->hi[a])) {
+                for (int k = 0; k < n_threads; k++) jobs[k].err = 1;
+                break;
+            }
     }
     int err = 0;
     for (int k = 0; k < n_threads; k++) err |= jobs[k].err;
@@ -832,8 +922,26 @@ int or_track(const or_geom *g, const or_params *pr, const or_out *out, int n_thr
                 if (out->tally_fxd) out->tally_fxd[i] = fx_to_double(fx);
             }
         }
+        if (out->mesh) {
+            const or_mesh *m = out->mesh;
+            for (uint64_t b = 0; b < mesh_bins(m); b++) {
+                double s = 0.0, c = 0.0;
+                u128 fx = 0;
+                for (int k = 0; k < n_threads; k++) {
+                    neumaier_add(&s, &c, jobs[k].acc.msum[b]);
+                    neumaier_add(&s, &c, jobs[k].acc.mcomp[b]);
+                    fx += jobs[k].acc.mfx[b];
+                }
+                if (m->mesh) m->mesh[b] = s + c;
+                if (m->mesh_fx) { m->mesh_fx[2 * b] = (uint64_t)fx; m->mesh_fx[2 * b + 1] = (uint64_t)(fx >> 64); }
+                if (m->mesh_fxd) m->mesh_fxd[b] = fx_to_double(fx);
+            }
+        }
     }
-    for (int k = 0; k < n_threads; k++) { free(jobs[k].acc.sum); free(jobs[k].acc.comp); free(jobs[k].acc.fx); }
+    for (int k = 0; k < n_threads; k++) {
+        free(jobs[k].acc.sum); free(jobs[k].acc.comp); free(jobs[k].acc.fx);
+        free(jobs[k].acc.msum); free(jobs[k].acc.mcomp); free(jobs[k].acc.mfx); free(jobs[k].acc.cuts);
+    }
     free(jobs);
     free(th);
     return err ? -3 : 0;
