@@ -61,6 +61,9 @@ def parse():
                     help="regroup the lanes by leaf universe every this many loop trips (comparison; 0 = off)")
     ap.add_argument("--regroup-leg", type=int, default=64,
                     help="interval of the extra leg timing the headline with regroup on (0 = no such leg)")
+    ap.add_argument("--mesh", type=int, nargs=3, default=[119, 119, 30], metavar=("NX", "NY", "NZ"),
+                    help="bins of the superimposed mesh tally leg over the domain (the paper's 119 x 119 x 30)")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the mesh tally leg")
     ap.add_argument("--autotune", action="store_true",
                     help="time the launch shape gt_autotune_track picks instead of the library default")
     ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)   # the default
@@ -343,6 +346,24 @@ def main():
         print("# mixed with regroup every %d trips: %.3f ms/step" % (args.regroup_leg,
                                                                      sum(res["regroup"]["ms"]) / args.steps),
               file=sys.stderr, flush=True)
+    if args.only is None and not args.no_mesh:
+        # the headline with the superimposed mesh tally (the paper's active cycles)
+        mb = tuple(args.mesh)
+        out_m, mesh_out = gt.alloc_outputs(G, n), gt.alloc_mesh(mb[0] * mb[1] * mb[2])
+        rm = run_timed(gt, lambda: gt.track_mesh(G, args.seed, n, fg.domain_lo, fg.domain_hi, mb,
+                                                 geometry_id=args.config, precision=gt.PREC_MIXED, out=out_m,
+                                                 mesh_out=mesh_out), args, hev)
+        rm["segments"] = out_m.counters_dict()["segments"]
+        torch.cuda.synchronize()
+        total = float(out_m.tally.sum().item())
+        rm["mesh"] = {"bins": list(mb), "track_length_cm": float(mesh_out.mesh.sum().item()),
+                      "cell_tally_track_length_cm": total,
+                      "identical_histories": bool(torch.equal(out_m.seq_hash, out.seq_hash) and
+                                                  torch.equal(out_m.tally_fx, out.tally_fx))
+                      if "mixed" in res else None}
+        res["mesh"] = rm
+        print("# mixed with the %dx%dx%d mesh tally: %.3f ms/step" % (mb + (sum(rm["ms"]) / args.steps,)),
+              file=sys.stderr, flush=True)
     if args.only in (None, "event") and not args.no_event:
         res["event"] = timed_event(gt, G, args, hev)
         print("# event: %.3f ms/step, %d segments/step" % (sum(res["event"]["ms"]) / args.steps,
@@ -378,7 +399,7 @@ def main():
     }
     for name, label in (("fp64", "fp64"), ("plain_fp64", "plain_fp64_lane_per_history"),
                         ("event", "event_based_mixed"), ("nohint", "mixed_without_lattice_hints"),
-                        ("regroup", "mixed_with_regroup")):
+                        ("regroup", "mixed_with_regroup"), ("mesh", "mixed_with_mesh_tally")):
         if name in res:
             f = res[name]
             fms = sum(f["ms"]) / len(f["ms"])
@@ -386,6 +407,10 @@ def main():
             if name == "regroup":
                 line[label]["regroup_every"] = f["shape"]["regroup_every"]
                 line[label]["identical_to_headline"] = f.get("identical")
+    if "mesh" in res:
+        line["mixed_with_mesh_tally"].update(res["mesh"]["mesh"])
+        line["mixed_with_mesh_tally"]["time_over_headline"] = \
+            line["mixed_with_mesh_tally"]["ms_per_step"] / ms_step
     if "mixed" in res and "fp64" in res:
         line["mixed_over_fp64"] = line["value"] / line["fp64"]["value"]
     if "mixed" in res and "plain_fp64" in res:

@@ -247,6 +247,41 @@ uint64_t gt_event_bank_bytes(uint64_t n_particles);   /* 0 above the particle li
 int gt_track_event(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *bank,
                    uint64_t bank_bytes, void *stream);
 
+/* ---- superimposed mesh tally --------------------------------------------
+ * The paper's active cycles add a regular mesh flux tally over the core
+ * (Section "NuScale SMR").  gt_track_mesh tracks exactly the histories of
+ * gt_track, with the same outputs, and also tallies track length on a mesh of
+ * n[0] x n[1] x n[2] bins over the box [lo, hi]; bin (ix, iy, iz) is entry
+ * (iz * n[1] + iy) * n[0] + ix.  Each segment p0 + t u, 0 <= t <= l, is cut at
+ * every mesh plane lo[a] + k w[a] (w[a] = (hi[a] - lo[a]) / n[a], k = 0..n[a])
+ * that it crosses at t = (plane - p0[a]) / u[a] with 0 < t < l, and each piece
+ * adds its length to the bin holding its midpoint (bin index floor((mid[a] -
+ * lo[a]) / w[a]) per axis); pieces outside the mesh add nothing.  Sums are
+ * fixed point as the cell tally's (each piece truncated to 2^-96 cm), so they
+ * do not depend on the order of the pieces.
+ *   mesh_fx:   [2 * bins] uint64 device, required ((low, high) words per bin);
+ *              overwritten, or added to with GT_FLAG_ACCUMULATE;
+ *   mesh:      [bins] double device or NULL: mesh_fx in cm;
+ *   workspace: caller-owned device memory of gt_mesh_workspace_bytes(bins)
+ *              bytes, 256-byte aligned, contents overwritten.
+ * Persistent schedule only (no GT_FLAG_LANE_PER_HISTORY, regroup_every 0).
+ * Errors as gt_track; GT_EINVAL for a bad mesh (n < 1, lo >= hi or not
+ * finite, reserved != 0), a missing mesh_fx, or a missing, short or
+ * misaligned workspace; GT_ECAPACITY above 2^31 bins.  Asynchronous; allocates
+ * nothing. */
+typedef struct {
+    double lo[3], hi[3];
+    uint32_t n[3];
+    uint32_t reserved;         /* must be 0 */
+    uint64_t *mesh_fx;
+    double *mesh;
+    void *workspace;
+    uint64_t workspace_bytes;
+} gt_mesh;
+uint64_t gt_mesh_workspace_bytes(uint64_t bins);   /* 0 for 0 or more than 2^31 bins */
+int gt_track_mesh(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, const gt_mesh *m,
+                  void *stream);
+
 /* ---- many geometries in one launch -------------------------------------- */
 typedef struct gt_batch gt_batch;   /* opaque: device descriptors of a batch */
 

@@ -615,6 +615,90 @@ __device__ __forceinline__ void tally_flush(uint64_t *rep, TallyAcc &a) {
     a.inst = kNone;
 }
 
+// ------------------------------------------------------------------ mesh tally
+// Track length of the segment p0 + t u (0 <= t <= l) on a regular mesh:
+// the segment is cut at every mesh plane lo[a] + k w[a] (k = 0..n[a]) that it
+// crosses at t = (plane - p0[a]) / u[a] with 0 < t < l, and each piece adds
+// its length to the bin holding its midpoint p0 + ((t0 + t1) / 2) u (bin
+// index floor((mid - lo) / w) per axis; nothing outside the mesh).  On each
+// axis t is monotone in k, so the planes crossed form one run of k, walked in
+// increasing t; merging the three runs lists the cuts in increasing order
+// (equal cuts give pieces of length 0, which add nothing).
+__device__ __forceinline__ double mesh_cut(const MeshDesc &m, int a, int k, double p0, double u) {
+    const double x = m.lo[a] + (double)k * m.w[a];
+    return (x - p0) / u;
+}
+
+__device__ __forceinline__ void mesh_segment(const MeshDesc &m, uint64_t *rep, const double p0[3],
+                                             const double u[3], double l) {
+    int k[3], step[3];
+    double tn[3];
+    for (int a = 0; a < 3; a++) {
+        tn[a] = dinf();
+        step[a] = 0;
+        k[a] = 0;
+        if (u[a] == 0.0) continue;
+        const int n = (int)m.n[a];
+        const double f = floor((p0[a] - m.lo[a]) / m.w[a]);
+        if (u[a] > 0.0) {
+            // first k with a cut ahead (t > 0): near floor(...) + 1, then exact
+            int kk = f < -1.0 ? 0 : (f > (double)n ? n + 1 : (int)f + 1);
+            while (kk > 0 && mesh_cut(m, a, kk - 1, p0[a], u[a]) > 0.0) kk--;
+            while (kk <= n && !(mesh_cut(m, a, kk, p0[a], u[a]) > 0.0)) kk++;
+            k[a] = kk;
+            step[a] = 1;
+            if (kk <= n) tn[a] = mesh_cut(m, a, kk, p0[a], u[a]);
+        } else {
+            // last k with a cut ahead, walking down
+            int kk = f < -1.0 ? -1 : (f > (double)n ? n : (int)f);
+            while (kk < n && mesh_cut(m, a, kk + 1, p0[a], u[a]) > 0.0) kk++;
+            while (kk >= 0 && !(mesh_cut(m, a, kk, p0[a], u[a]) > 0.0)) kk--;
+            k[a] = kk;
+            step[a] = -1;
+            if (kk >= 0) tn[a] = mesh_cut(m, a, kk, p0[a], u[a]);
+        }
+        if (!(tn[a] < l)) tn[a] = dinf();
+    }
+    double t0 = 0.0;
+    for (;;) {
+        double t1 = l;
+        int a1 = -1;
+        for (int a = 0; a < 3; a++)
+            if (tn[a] < t1) {
+                t1 = tn[a];
+                a1 = a;
+            }
+        // the piece [t0, t1]
+        const double tm = (t0 + t1) * 0.5;
+        uint32_t idx[3];
+        bool inside = true;
+        for (int a = 0; a < 3; a++) {
+            const double mid = p0[a] + tm * u[a];
+            const double f = floor((mid - m.lo[a]) / m.w[a]);
+            inside = inside && f >= 0.0 && f < (double)m.n[a];
+            idx[a] = inside ? (uint32_t)f : 0u;
+        }
+        if (inside) {
+            const double v = (t1 - t0) * 0x1p32;
+            const double fl = floor(v);
+            const double fr = v - fl;
+            const uint64_t hi = (uint64_t)fl, lo = (uint64_t)(fr * 0x1p64);
+            uint64_t *q = rep + 4 * (((uint64_t)idx[2] * m.n[1] + idx[1]) * m.n[0] + idx[0]);
+            add_limb(q + 0, lo & 0xFFFFFFFFull);
+            add_limb(q + 1, lo >> 32);
+            add_limb(q + 2, hi & 0xFFFFFFFFull);
+            add_limb(q + 3, hi >> 32);
+        }
+        if (a1 < 0) break;
+        t0 = t1;
+        const int kk = k[a1] + step[a1];
+        k[a1] = kk;
+        const bool ok = kk >= 0 && kk <= (int)m.n[a1];
+        const double t = ok ? mesh_cut(m, a1, kk, p0[a1], u[a1]) : dinf();
+        tn[a1] = t < l ? t : dinf();
+    }
+}
+
 __device__ __forceinline__ void tally_add(uint64_t *rep, TallyAcc &a, uint32_t inst, double l) {
     const double v = l * 0x1p32;
     const double fl = floor(v);
@@ -978,7 +1062,7 @@ struct TailCfg {
 // The persistent history loop of one lane (see above); returns when its
 // wave has drained the queue and every lane of the wave is idle (with tail
 // compaction: when no lane of the workgroup has a history left).
-template <int PREC, bool RG = false, typename G, typename Queue>
+template <int PREC, bool RG = false, bool MESH = false, typename G, typename Queue>
 __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const KOut &o, uint64_t *rep,
                                            uint32_t *cells, const Queue &queue, Counts &cnt, const TailCfg &tc,
                                            const TallyCache &tcache) {
@@ -1355,6 +1439,10 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
                     if (p.source != 1) P.tau = P.tau - sig * nr.t;
                 } else {
                     l = sc;
+                }
+                if constexpr (MESH) {
+                    const double p0[3] = {P.x, P.y, P.z}, uu[3] = {P.u, P.v, P.w};
+                    mesh_segment(o.mesh, o.mesh.ws + (size_t)xcc_id() * 4 * o.mesh.nb, p0, uu, l);
                 }
                 const double m0 = l * P.u, m1 = l * P.v, m2 = l * P.w;
                 P.x = P.x + m0;

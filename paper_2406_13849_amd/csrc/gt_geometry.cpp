@@ -743,6 +743,7 @@ void gt::fill_kparams(const gt_track_params *p, const gt_geometry *g, KParams &k
     kp.rec_k = (uint32_t)((uint64_t)p->record_first_k < p->n_particles ? p->record_first_k : p->n_particles);
     kp.rec_cap = p->record_cap;
     kp.refill_min = p->refill_min ? p->refill_min : kRefillMin;
+    ko.mesh = MeshDesc{};
     ko.tally_ws = g->tally_ws;
     ko.seg_count = o->seg_count;
     ko.seq_hash = o->seq_hash;
@@ -811,6 +812,39 @@ uint64_t ev_layout(uint64_t n, unsigned char *base, EvBank *b) {
 extern "C" uint64_t gt_event_bank_bytes(uint64_t n_particles) {
     if (n_particles > (uint64_t)0x7FFFFFFF * 64ull) return 0;
     return ev_layout(n_particles, nullptr, nullptr);
+}
+
+extern "C" uint64_t gt_mesh_workspace_bytes(uint64_t bins) {
+    if (bins == 0 || bins > (1ull << 31)) return 0;
+    return (uint64_t)8 * 4 * 8 * bins;   // per-XCD replicas x limbs x bytes, as the cell tally's workspace
+}
+
+extern "C" int gt_track_mesh(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o,
+                             const gt_mesh *m, void *stream) {
+    int rc = check_track_args(g, p, o);
+    if (rc) return rc;
+    if (!m) return set_error("gt_track_mesh: mesh is NULL"), GT_EINVAL;
+    if (p->flags & GT_FLAG_LANE_PER_HISTORY)
+        return set_error("gt_track_mesh: the mesh tally needs the persistent schedule"), GT_EINVAL;
+    if (p->regroup_every) return set_error("gt_track_mesh: regroup_every must be 0"), GT_EINVAL;
+    if (m->reserved) return set_error("gt_track_mesh: reserved must be 0"), GT_EINVAL;
+    uint64_t bins = 1;
+    for (int a = 0; a < 3; a++) {
+        if (m->n[a] < 1) return set_error("gt_track_mesh: n[%d] must be >= 1", a), GT_EINVAL;
+        if (!std::isfinite(m->lo[a]) || !std::isfinite(m->hi[a]) || !(m->hi[a] > m->lo[a]))
+            return set_error("gt_track_mesh: axis %d needs finite lo < hi", a), GT_EINVAL;
+        if (!(((m->hi[a] - m->lo[a]) / (double)m->n[a]) > 0.0))
+            return set_error("gt_track_mesh: axis %d bins have no width", a), GT_EINVAL;
+        bins *= m->n[a];
+        if (bins > (1ull << 31)) return set_error("gt_track_mesh: more than 2^31 bins"), GT_ECAPACITY;
+    }
+    if (!m->mesh_fx) return set_error("gt_track_mesh: mesh_fx is required"), GT_EINVAL;
+    const uint64_t need = gt_mesh_workspace_bytes(bins);
+    if (!m->workspace || m->workspace_bytes < need)
+        return set_error("gt_track_mesh: the workspace needs %llu bytes", (unsigned long long)need), GT_EINVAL;
+    if (((uintptr_t)m->workspace) & 255u)
+        return set_error("gt_track_mesh: the workspace must be 256-byte aligned"), GT_EINVAL;
+    return launch_track(g, p, o, stream, m);
 }
 
 extern "C" int gt_track_event(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *bank,

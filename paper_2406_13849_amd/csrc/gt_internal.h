@@ -117,7 +117,17 @@ struct KParams {
     uint32_t geom_id, max_coll, source, ray_n1, max_segs, rec_k, rec_cap, refill_min;
 };
 
+// A superimposed mesh: bins n[0] x n[1] x n[2] over lo + [0, n] w, with its
+// per-XCD replicas of per-bin limb counters (ws == nullptr: no mesh).
+struct MeshDesc {
+    double lo[3], w[3];
+    uint32_t n[3], pad;
+    uint64_t *ws;
+    uint64_t nb;
+};
+
 struct KOut {
+    MeshDesc mesh;
     uint64_t *tally_ws;     // per-XCD replicas of per-instance limb counters
     uint32_t *seg_count;
     uint64_t *seq_hash;
@@ -232,7 +242,8 @@ bool cached_batch_tuning(const gt_batch_item *items, uint32_t n_items, gt_tuning
 int launch_batch(gt_batch *b, void *stream);
 int prepare_batch_streams(gt_batch *b);
 void release_batch_streams(gt_batch *b);
-int launch_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream);
+int launch_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream,
+                 const gt_mesh *mesh = nullptr);
 int launch_find_cell(const gt_geometry *g, const double *pos, uint64_t n, int64_t *inst, int32_t *cells,
                      uint32_t precision, void *stream);
 int launch_distance(const gt_geometry *g, const double *pos, const double *dir, uint64_t n, double *dist,

@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(kBlock) k_ev_cross(Dev g0, KParams p, KOut o, 
 // SIMD the register budget is cut for: 4 (up to 1024 lanes per workgroup,
 // 128 registers) or 5 (640 lanes, two workgroups per compute unit, 96
 // registers).
-template <int PREC, int KIND, int W, bool RG>
+template <int PREC, int KIND, int W, bool RG, bool MESH>
 __global__ void __launch_bounds__(W == 5 ? 640 : kBlockP) __attribute__((amdgpu_waves_per_eu(W)))
 k_track_persistent(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict__ lr, uint32_t tables_at,
                    uint32_t tail_at, uint32_t tail_cap, uint32_t tail_round, uint32_t tail_words, uint32_t regroup,
@@ -120,7 +120,7 @@ k_track_persistent(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict_
     const GlobalQueue q = {(unsigned long long *)&o.counters[7], p.n};
     const TailCfg tc = {(uint64_t *)(lds_dyn + tail_at), ctl, tail_cap, tail_round, tail_words, regroup};
     const TallyCache tcache = tally_cache(lds_dyn, cache_at, cache_k);
-    track_pool<PREC, RG>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc, tcache);
+    track_pool<PREC, RG, MESH>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc, tcache);
     add_counts(cnt, o.counters);
 }
 
@@ -444,46 +444,53 @@ inline void mark(hipEvent_t e, hipStream_t st) {
     if (e) (void)hipEventRecord(e, st);
 }
 
-// One persistent tracker launch for a geometry of staging kind KIND (the
-// build with the regroup step when one is asked for and finds room).
+// One persistent tracker launch for a geometry of staging kind KIND: the
+// build with the mesh tally when there is a mesh, else the one with the
+// regroup step when one is asked for and finds room, else the plain one.
 template <int PREC, int KIND, int W>
 int launch_persistent_k(const gt_geometry *g, uint64_t n, unsigned block, bool tail, bool cache, uint32_t regroup,
-                        hipStream_t st) {
+                        bool mesh, hipStream_t st) {
     const unsigned tables = KIND == SK_NONE ? 0 : g->stage[PREC].total;
-    const void *kern = (const void *)k_track_persistent<PREC, KIND, W, false>;
+    const void *plain = (const void *)k_track_persistent<PREC, KIND, W, false, false>;
+    const void *kern = mesh ? (const void *)k_track_persistent<PREC, KIND, W, false, true> : plain;
     LdsPlan lp;
     int rc = GT_OK;
-    if (regroup) {
-        const void *kr = (const void *)k_track_persistent<PREC, KIND, W, true>;
+    if (regroup && !mesh) {
+        const void *kr = (const void *)k_track_persistent<PREC, KIND, W, true, false>;
         rc = plan_persistent(kr, block, tables, tail, cache, regroup, g->device, lp);
         if (!rc && lp.regroup) kern = kr;
     }
-    if (!rc && kern == (const void *)k_track_persistent<PREC, KIND, W, false>)
+    if (!rc && kern != (const void *)k_track_persistent<PREC, KIND, W, true, false>)
         rc = plan_persistent(kern, block, tables, tail, cache, 0, g->device, lp);
     if (rc) return rc;
     int blocks = lp.blocks;
     const uint64_t need = (n + block - 1) / block;
     if ((uint64_t)blocks > need) blocks = (int)need;
     note_launch(lp, blocks, block, KIND);
-    if (lp.regroup)
-        hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, true>), dim3(blocks), dim3(block), lp.dyn, st,
-                           g->desc, (const LaunchRec *)g->launch, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound,
-                           lp.tail_words, lp.regroup, lp.cache_at, lp.cache_k);
+    const LaunchRec *lr = (const LaunchRec *)g->launch;
+    if (mesh)
+        hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, false, true>), dim3(blocks), dim3(block), lp.dyn, st,
+                           g->desc, lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.tail_words, 0u,
+                           lp.cache_at, lp.cache_k);
+    else if (lp.regroup)
+        hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, true, false>), dim3(blocks), dim3(block), lp.dyn, st,
+                           g->desc, lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.tail_words, lp.regroup,
+                           lp.cache_at, lp.cache_k);
     else
-        hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, false>), dim3(blocks), dim3(block), lp.dyn, st,
-                           g->desc, (const LaunchRec *)g->launch, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound,
-                           lp.tail_words, 0u, lp.cache_at, lp.cache_k);
+        hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, false, false>), dim3(blocks), dim3(block), lp.dyn, st,
+                           g->desc, lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.tail_words, 0u,
+                           lp.cache_at, lp.cache_k);
     return GT_OK;
 }
 
 template <int PREC, int W>
 int launch_persistent(const gt_geometry *g, int kind, uint64_t n, unsigned block, bool tail, bool cache,
-                      uint32_t regroup, hipStream_t st) {
+                      uint32_t regroup, bool mesh, hipStream_t st) {
     switch (kind) {
-    case SK_ALL: return launch_persistent_k<PREC, SK_ALL, W>(g, n, block, tail, cache, regroup, st);
-    case SK_LDS: return launch_persistent_k<PREC, SK_LDS, W>(g, n, block, tail, cache, regroup, st);
-    case SK_SPLIT: return launch_persistent_k<PREC, SK_SPLIT, W>(g, n, block, tail, cache, regroup, st);
-    default: return launch_persistent_k<PREC, SK_NONE, W>(g, n, block, tail, cache, regroup, st);
+    case SK_ALL: return launch_persistent_k<PREC, SK_ALL, W>(g, n, block, tail, cache, regroup, mesh, st);
+    case SK_LDS: return launch_persistent_k<PREC, SK_LDS, W>(g, n, block, tail, cache, regroup, mesh, st);
+    case SK_SPLIT: return launch_persistent_k<PREC, SK_SPLIT, W>(g, n, block, tail, cache, regroup, mesh, st);
+    default: return launch_persistent_k<PREC, SK_NONE, W>(g, n, block, tail, cache, regroup, mesh, st);
     }
 }
 
@@ -594,12 +601,25 @@ int launch_batch_kinds(gt_batch *b, hipStream_t st) {
 }
 
 template <int PREC>
-int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, hipStream_t st) {
+int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, const gt_mesh *mesh,
+                   hipStream_t st) {
     KParams kp;
     KOut ko;
     fill_kparams(p, g, kp, ko, o);
     const uint64_t nws = (uint64_t)kReplicas * 4 * g->n_inst;
     hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(nws)), dim3(256), 0, st, g->tally_ws, nws, (uint64_t)0);
+    if (mesh) {
+        MeshDesc &m = ko.mesh;
+        for (int a = 0; a < 3; a++) {
+            m.lo[a] = mesh->lo[a];
+            m.w[a] = (mesh->hi[a] - mesh->lo[a]) / (double)mesh->n[a];
+            m.n[a] = mesh->n[a];
+        }
+        m.nb = (uint64_t)mesh->n[0] * mesh->n[1] * mesh->n[2];
+        m.ws = (uint64_t *)mesh->workspace;
+        const uint64_t mws = (uint64_t)kReplicas * 4 * m.nb;
+        hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(mws)), dim3(256), 0, st, m.ws, mws, (uint64_t)0);
+    }
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, o->counters, (uint64_t)8, (uint64_t)0);
     if (kp.rec_k) {
         const uint64_t nrec = (uint64_t)kp.rec_k * kp.rec_cap;
@@ -621,14 +641,18 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
             const bool tail = (p->flags & GT_FLAG_TAIL_COMPACTION) != 0;
             const bool cache = !(p->flags & GT_FLAG_NO_TALLY_CACHE);
             const uint32_t rg = p->regroup_every;
-            int rc = block == 640 ? launch_persistent<PREC, 5>(g, kind, kp.n, block, tail, cache, rg, st)
-                                  : launch_persistent<PREC, 4>(g, kind, kp.n, block, tail, cache, rg, st);
+            const bool ms = mesh != nullptr;
+            int rc = block == 640 ? launch_persistent<PREC, 5>(g, kind, kp.n, block, tail, cache, rg, ms, st)
+                                  : launch_persistent<PREC, 4>(g, kind, kp.n, block, tail, cache, rg, ms, st);
             if (rc) return rc;
         }
     }
     mark(t_ev_stop, st);
     hipLaunchKernelGGL(k_finalize, dim3(fill_grid(g->n_inst)), dim3(256), 0, st, (const uint64_t *)g->tally_ws,
                        o->tally_fx, o->tally, g->n_inst, (int)((p->flags & GT_FLAG_ACCUMULATE) != 0));
+    if (mesh)
+        hipLaunchKernelGGL(k_finalize, dim3(fill_grid(ko.mesh.nb)), dim3(256), 0, st, (const uint64_t *)ko.mesh.ws,
+                           mesh->mesh_fx, mesh->mesh, ko.mesh.nb, (int)((p->flags & GT_FLAG_ACCUMULATE) != 0));
     return hip_check(hipGetLastError(), "gt_track launch");
 }
 
@@ -738,13 +762,14 @@ int launch_event(const gt_geometry *g, const gt_track_params *p, const gt_track_
                                          : launch_event_t<GT_PREC_FP64>(g, p, o, bank, st);
 }
 
-int launch_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream) {
+int launch_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream,
+                 const gt_mesh *mesh) {
     hipStream_t st = (hipStream_t)stream;
     if ((p->flags & GT_FLAG_LANE_PER_HISTORY) && p->block_size > (uint32_t)kBlock)
         return set_error("gt_track: block_size must be at most %d with GT_FLAG_LANE_PER_HISTORY", kBlock), GT_EINVAL;
     if (p->n_particles > (uint64_t)0x7FFFFFFF * 64ull) return set_error("gt_track: too many particles"), GT_ECAPACITY;
-    return p->precision == GT_PREC_MIXED ? launch_track_t<GT_PREC_MIXED>(g, p, o, st)
-                                         : launch_track_t<GT_PREC_FP64>(g, p, o, st);
+    return p->precision == GT_PREC_MIXED ? launch_track_t<GT_PREC_MIXED>(g, p, o, mesh, st)
+                                         : launch_track_t<GT_PREC_FP64>(g, p, o, mesh, st);
 }
 
 int launch_find_cell(const gt_geometry *g, const double *pos, uint64_t n, int64_t *inst, int32_t *cells,

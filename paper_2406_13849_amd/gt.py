@@ -73,6 +73,12 @@ class _Tuning(C.Structure):
                 ("regroup_every", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+class _Mesh(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3), ("n", C.c_uint32 * 3), ("reserved", C.c_uint32),
+                ("mesh_fx", C.c_void_p), ("mesh", C.c_void_p), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_uint64)]
+
+
 class _LaunchInfo(C.Structure):
     _fields_ = [(n, C.c_uint32) for n in ("workgroups", "block_size", "lds_bytes", "staging_kind",
                                           "tally_cache_entries", "tail_capacity", "regroup_every", "reserved")]
@@ -111,6 +117,10 @@ def lib():
         L.gt_batch_destroy.restype = None
         L.gt_last_launch.argtypes = [C.POINTER(_LaunchInfo)]
         L.gt_last_launch.restype = i32
+        L.gt_mesh_workspace_bytes.argtypes = [u64]
+        L.gt_mesh_workspace_bytes.restype = u64
+        L.gt_track_mesh.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), C.POINTER(_Mesh), vp]
+        L.gt_track_mesh.restype = i32
         L.gt_track_batch.argtypes = [C.POINTER(_BatchItem), u32, C.POINTER(_Tuning), vp]
         L.gt_track_batch.restype = i32
         L.gt_autotune_track.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), u32, vp, C.POINTER(_Tuning),
@@ -258,6 +268,53 @@ def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 
     o = _out_struct(out)
     _check(lib().gt_track(geom.h, C.byref(prm), C.byref(o), _stream(stream)))
     return out
+
+
+@dataclass
+class MeshOutputs:
+    """Device outputs of a mesh tally: mesh_fx [bins, 2] int64 (the (low,
+    high) words of 128-bit fixed point, quantum 2^-96 cm), mesh [bins]
+    float64 (cm), and the caller-owned workspace."""
+    mesh_fx: object
+    mesh: object
+    workspace: object
+
+
+def mesh_workspace_bytes(bins: int) -> int:
+    """gt_mesh_workspace_bytes: device bytes of a mesh tally's workspace."""
+    return int(lib().gt_mesh_workspace_bytes(bins))
+
+
+def alloc_mesh(bins: int, device="cuda") -> MeshOutputs:
+    import torch
+    ws = mesh_workspace_bytes(bins)
+    if ws == 0:
+        raise GtError(GT_ECAPACITY, "mesh of %d bins" % bins)
+    return MeshOutputs(mesh_fx=torch.zeros((bins, 2), dtype=torch.int64, device=device),
+                       mesh=torch.zeros(bins, dtype=torch.float64, device=device),
+                       workspace=torch.empty(ws, dtype=torch.uint8, device=device))
+
+
+def track_mesh(geom: Geometry, seed: int, n_particles: int, mesh_lo, mesh_hi, mesh_n, *,
+               out: Optional[TrackOutputs] = None, mesh_out: Optional[MeshOutputs] = None, stream=None,
+               **kwargs):
+    """gt_track_mesh: the histories and outputs of track() plus a track-length
+    tally on a regular mesh of mesh_n = (nx, ny, nz) bins over [mesh_lo,
+    mesh_hi] (bin (ix, iy, iz) at (iz * ny + iy) * nx + ix).  kwargs as
+    track() (persistent schedule).  Returns (out, mesh_out)."""
+    if out is None:
+        out = alloc_outputs(geom, n_particles, kwargs.get("record_first_k", 0), kwargs.get("record_cap", 0))
+    bins = int(mesh_n[0]) * int(mesh_n[1]) * int(mesh_n[2])
+    if mesh_out is None:
+        mesh_out = alloc_mesh(bins)
+    m = _Mesh(mesh_fx=_ptr(mesh_out.mesh_fx), mesh=_ptr(mesh_out.mesh), workspace=_ptr(mesh_out.workspace),
+              workspace_bytes=mesh_out.workspace.numel())
+    m.lo[:] = [float(v) for v in mesh_lo]
+    m.hi[:] = [float(v) for v in mesh_hi]
+    m.n[:] = [int(v) for v in mesh_n]
+    prm = _params(seed, n_particles, **kwargs)
+    _check(lib().gt_track_mesh(geom.h, C.byref(prm), C.byref(_out_struct(out)), C.byref(m), _stream(stream)))
+    return out, mesh_out
 
 
 def event_bank_bytes(n_particles: int) -> int:

@@ -16,7 +16,7 @@ constexpr size_t kLdsEmuBytes = 160 * 1024;
 thread_local unsigned char g_lds[kLdsEmuBytes];
 thread_local uint32_t g_cache_k = kTallyCacheMax;   // tally-cache entries of the lane (0 = off)
 
-template <int PREC, int KIND, typename Queue>
+template <int PREC, int KIND, bool MESH, typename Queue>
 void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut &o, const Queue &q, uint64_t *counts) {
     static thread_local uint32_t cells[GT_MAX_LEVELS];
     static thread_local uint32_t ctl[1 + kBlockP / 64];
@@ -31,7 +31,7 @@ void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     const TailCfg tc = {nullptr, ctl, 0, kTailRound, 0, 0};
     const TallyCache tcache = {c_lo, c_hi, c_tag, g_cache_k, 1};
-    track_pool<PREC>(v, p, o, o.tally_ws, cells, q, cnt, tc, tcache);
+    track_pool<PREC, false, MESH>(v, p, o, o.tally_ws, cells, q, cnt, tc, tcache);
     counts[GT_CNT_ESCAPED] += cnt.escaped;
     counts[GT_CNT_CAPPED] += cnt.capped;
     counts[GT_CNT_LOST] += cnt.lost;
@@ -41,15 +41,15 @@ void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut
     counts[GT_CNT_REJECTED] += cnt.rejected;
 }
 
-template <int PREC, typename Queue>
+template <int PREC, bool MESH = false, typename Queue>
 int run_kind(int kind, const Dev &dev, const StagePlan &sp, const KParams &p, const KOut &o, const Queue &q,
              uint64_t *counts) {
     if (kind != SK_NONE && sp.total > sizeof(g_lds)) return GT_ECAPACITY;
     switch (kind) {
-    case SK_ALL: run_lane<PREC, SK_ALL>(dev, sp, p, o, q, counts); break;
-    case SK_LDS: run_lane<PREC, SK_LDS>(dev, sp, p, o, q, counts); break;
-    case SK_SPLIT: run_lane<PREC, SK_SPLIT>(dev, sp, p, o, q, counts); break;
-    default: run_lane<PREC, SK_NONE>(dev, sp, p, o, q, counts); break;
+    case SK_ALL: run_lane<PREC, SK_ALL, MESH>(dev, sp, p, o, q, counts); break;
+    case SK_LDS: run_lane<PREC, SK_LDS, MESH>(dev, sp, p, o, q, counts); break;
+    case SK_SPLIT: run_lane<PREC, SK_SPLIT, MESH>(dev, sp, p, o, q, counts); break;
+    default: run_lane<PREC, SK_NONE, MESH>(dev, sp, p, o, q, counts); break;
     }
     return GT_OK;
 }
@@ -84,6 +84,41 @@ extern "C" int cpu_track(const gt_geometry *g, const gt_track_params *p, const g
                                        : run_kind<GT_PREC_FP64>(kind, g->dev, sp, kp, ko, q, o->counters);
     if (rc) return rc;
     fold_all(g->tally_ws, o->tally_fx, o->tally, g->n_inst, (p->flags & GT_FLAG_ACCUMULATE) != 0);
+    return GT_OK;
+}
+
+// gt_track_mesh on the CPU: cpu_track with the mesh tally (the kernel's
+// mesh walk), host pointers throughout; the workspace holds the replicas.
+extern "C" int cpu_track_mesh(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o,
+                              const gt_mesh *m, int kind) {
+    int rc = check_track_args(g, p, o);
+    if (rc) return rc;
+    const StagePlan &sp = g->stage[p->precision];
+    if (kind != SK_NONE && kind != (int)sp.kind) return set_error("cpu_track_mesh: another staging kind"), GT_EINVAL;
+    KParams kp;
+    KOut ko;
+    fill_kparams(p, g, kp, ko, o);
+    MeshDesc &md = ko.mesh;
+    for (int a = 0; a < 3; a++) {
+        md.lo[a] = m->lo[a];
+        md.w[a] = (m->hi[a] - m->lo[a]) / (double)m->n[a];
+        md.n[a] = m->n[a];
+    }
+    md.nb = (uint64_t)m->n[0] * m->n[1] * m->n[2];
+    md.ws = (uint64_t *)m->workspace;
+    if (m->workspace_bytes < gt_mesh_workspace_bytes(md.nb)) return set_error("cpu_track_mesh: workspace"), GT_EINVAL;
+    std::memset(md.ws, 0, (size_t)8 * 4 * 8 * md.nb);
+    g_cache_k = kTallyCacheMax;
+    std::memset(g->tally_ws, 0, (size_t)8 * 4 * 8 * g->n_inst);
+    std::memset(o->counters, 0, 8 * sizeof(uint64_t));
+    if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
+    unsigned long long ctr = 0;
+    const GlobalQueue q = {&ctr, kp.n};
+    rc = p->precision == GT_PREC_MIXED ? run_kind<GT_PREC_MIXED, true>(kind, g->dev, sp, kp, ko, q, o->counters)
+                                       : run_kind<GT_PREC_FP64, true>(kind, g->dev, sp, kp, ko, q, o->counters);
+    if (rc) return rc;
+    fold_all(g->tally_ws, o->tally_fx, o->tally, g->n_inst, (p->flags & GT_FLAG_ACCUMULATE) != 0);
+    fold_all(md.ws, m->mesh_fx, m->mesh, md.nb, (p->flags & GT_FLAG_ACCUMULATE) != 0);
     return GT_OK;
 }
 

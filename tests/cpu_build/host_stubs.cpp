@@ -34,7 +34,7 @@ hipError_t hipEventElapsedTime(float *, hipEvent_t, hipEvent_t) { return hipSucc
 }
 
 namespace gt {
-int launch_track(const gt_geometry *, const gt_track_params *, const gt_track_out *, void *) {
+int launch_track(const gt_geometry *, const gt_track_params *, const gt_track_out *, void *, const gt_mesh *) {
     return set_error("host build: no kernels"), GT_EHIP;
 }
 int launch_batch(gt_batch *, void *) { return set_error("host build: no kernels"), GT_EHIP; }

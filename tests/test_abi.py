@@ -96,7 +96,8 @@ def test_binding_struct_layouts_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = {"gt_track_params": gt._Params, "gt_track_out": gt._Out, "gt_batch_item": gt._BatchItem,
-               "gt_tuning": gt._Tuning, "gt_launch_info": gt._LaunchInfo, "gt_flat_geometry": gt._Flat}
+               "gt_tuning": gt._Tuning, "gt_launch_info": gt._LaunchInfo, "gt_flat_geometry": gt._Flat,
+               "gt_mesh": gt._Mesh}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gt.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
