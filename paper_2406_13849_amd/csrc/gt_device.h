@@ -629,7 +629,7 @@ __device__ __forceinline__ double mesh_cut(const MeshDesc &m, int a, int k, doub
     return (x - p0) / u;
 }
 
-__device__ __forceinline__ void mesh_segment(const MeshDesc &m, uint64_t *rep, const double p0[3],
+__device__ __forceinline__ void mesh_segment(const MeshDesc &m, uint64_t *rep, TallyAcc &acc, const double p0[3],
                                              const double u[3], double l) {
     int k[3], step[3];
     double tn[3];
@@ -679,15 +679,23 @@ __device__ __forceinline__ void mesh_segment(const MeshDesc &m, uint64_t *rep, c
             idx[a] = inside ? (uint32_t)f : 0u;
         }
         if (inside) {
+            // into the lane's register accumulator while the bin stays the same
+            // (a segment's last piece and the next segment's first share one)
             const double v = (t1 - t0) * 0x1p32;
             const double fl = floor(v);
             const double fr = v - fl;
             const uint64_t hi = (uint64_t)fl, lo = (uint64_t)(fr * 0x1p64);
-            uint64_t *q = rep + 4 * (((uint64_t)idx[2] * m.n[1] + idx[1]) * m.n[0] + idx[0]);
-            add_limb(q + 0, lo & 0xFFFFFFFFull);
-            add_limb(q + 1, lo >> 32);
-            add_limb(q + 2, hi & 0xFFFFFFFFull);
-            add_limb(q + 3, hi >> 32);
+            const uint32_t b = (uint32_t)(((uint64_t)idx[2] * m.n[1] + idx[1]) * m.n[0] + idx[0]);
+            if (b == acc.inst) {
+                const uint64_t nlo = acc.lo + lo;
+                acc.hi += hi + (nlo < lo ? 1u : 0u);
+                acc.lo = nlo;
+            } else {
+                tally_flush(rep, acc);
+                acc.inst = b;
+                acc.lo = lo;
+                acc.hi = hi;
+            }
         }
         if (a1 < 0) break;
         t0 = t1;
@@ -1083,6 +1091,9 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
     TallyAcc acc;
     acc.inst = kNone;
     acc.lo = acc.hi = 0;
+    TallyAcc macc;   // the mesh tally's accumulator (MESH builds)
+    macc.inst = kNone;
+    macc.lo = macc.hi = 0;
     uint32_t rr = 0;   // next tally-cache entry to evict
     for (uint32_t e = 0; e < tcache.k; e++) tcache.tag[e * tcache.stride] = kNone;
     // pending search at level sL: after a crossing, surface sforce (sense
@@ -1442,7 +1453,7 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
                 }
                 if constexpr (MESH) {
                     const double p0[3] = {P.x, P.y, P.z}, uu[3] = {P.u, P.v, P.w};
-                    mesh_segment(o.mesh, o.mesh.ws + (size_t)xcc_id() * 4 * o.mesh.nb, p0, uu, l);
+                    mesh_segment(o.mesh, o.mesh.ws + (size_t)xcc_id() * 4 * o.mesh.nb, macc, p0, uu, l);
                 }
                 const double m0 = l * P.u, m1 = l * P.v, m2 = l * P.w;
                 P.x = P.x + m0;
@@ -1489,6 +1500,7 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
     }
     // the lane's partial tally sums
     tally_flush(rep, acc);
+    if constexpr (MESH) tally_flush(o.mesh.ws + (size_t)xcc_id() * 4 * o.mesh.nb, macc);
     for (uint32_t e = 0; e < tcache.k; e++) {
         TallyAcc c;
         c.inst = tcache.tag[e * tcache.stride];
