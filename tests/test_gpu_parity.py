@@ -303,8 +303,10 @@ def test_mesh_tally_matches_oracle(case, prec):
     kw = dict(seed=91, n_particles=n, geometry_id=gid, record_first_k=30, record_cap=64)
     lo, hi = _mesh_box(fg, cover)
     print("mesh", cfg, cover, bins, "precision", prec, flush=True)
-    out, m = gt.track_mesh(G, mesh_lo=lo, mesh_hi=hi, mesh_n=bins, precision=prec, **kw)
+    out, m = gt.track_mesh(G, mesh_lo=lo, mesh_hi=hi, mesh_n=bins, precision=prec,
+                           block_size=256 if cfg == 1 else 0, **kw)
     torch.cuda.synchronize()
+    assert gt.last_launch()["block_size"] == (256 if cfg == 1 else 768)
     o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT, mesh=(lo, hi, bins))
     assert_parity(_outs(out), o, where="mesh cfg %s" % cfg)
     mfx = m.mesh_fx.cpu().numpy().view(np.uint64)
@@ -324,7 +326,8 @@ def test_mesh_tally_accumulates_and_rejects_bad_meshes():
     o = oracle.track(O, oracle.TrackParams(seed=7, n_particles=8000, geometry_id=2), n_threads=NT,
                      mesh=(lo, hi, bins))
     assert np.array_equal(m.mesh_fx.cpu().numpy().view(np.uint64), o.mesh_fx)
-    bad = [dict(mesh_n=(0, 1, 1)), dict(mesh_lo=hi), dict(lane_per_history=True), dict(regroup_every=4)]
+    bad = [dict(mesh_n=(0, 1, 1)), dict(mesh_lo=hi), dict(lane_per_history=True), dict(regroup_every=4),
+           dict(block_size=1024)]
     for b in bad:
         kw = dict(mesh_lo=lo, mesh_hi=hi, mesh_n=bins)
         kw.update(b)
