@@ -233,6 +233,10 @@ for what, k in [("cfg", 2), ("batch", 3), ("batch", 5), ("batch", 2)]:
                            record_cap=16)
         host.L.cpu_track_event.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         host.check(host.L.cpu_track_event(h, C.byref(prm), C.byref(out.struct())))
+        if what == "cfg":   # the mesh walk, over a corner of the domain and over more than it
+            lo, hi = fg.domain_lo, fg.domain_hi
+            t.mesh_run(host, h, ni, kw, prec, lo + 0.3 * (hi - lo), lo + 0.8 * (hi - lo), (9, 4, 6), 150, 10, 16)
+            t.mesh_run(host, h, ni, kw, prec, lo - 1.0, hi + 2.0, (5, 7, 3), 150, 10, 16)
     host.L.gt_geometry_destroy(h)
 t.batch_run(host, [(57, 300, True), (5, 200, True), (41, 150, False)], 1, 64)
 print("asan clean")
@@ -254,6 +258,23 @@ def test_event_bank_layout(host):
         assert b % 256 == 0 and b >= prev and b >= 152 * n
         prev = b
     assert f(0x7FFFFFFF * 64 + 1) == 0
+
+
+def mesh_run(host, h, ni, kw, prec, lo, hi, bins, n, rk, cap):
+    """cpu_track_mesh in host memory: (outputs, mesh_fx, mesh)."""
+    nb = int(np.prod(bins))
+    out = Outs(ni, n, rk, cap)
+    mfx, msum = np.zeros((nb, 2), np.uint64), np.zeros(nb)
+    ws = np.zeros(int(host.L.gt_mesh_workspace_bytes(nb)) // 8, np.uint64)
+    m = gt._Mesh(mesh_fx=mfx.ctypes.data, mesh=msum.ctypes.data, workspace=ws.ctypes.data,
+                 workspace_bytes=ws.nbytes)
+    m.lo[:] = [float(v) for v in lo]
+    m.hi[:] = [float(v) for v in hi]
+    m.n[:] = list(bins)
+    prm = gt._params(kw["seed"], n, geometry_id=kw["geometry_id"], precision=prec, record_first_k=rk,
+                     record_cap=cap)
+    host.check(host.L.cpu_track_mesh(h, C.byref(prm), C.byref(out.struct()), C.byref(m), host.staging(h, prec)))
+    return out, mfx, msum
 
 
 MESH_CASES = [
@@ -281,20 +302,8 @@ def test_cpu_mesh_tally_matches_oracle(host, geom, cover, bins):
     o = oracle.track(oracle.OracleGeometry(fg), oracle.TrackParams(n_particles=n, record_first_k=rk,
                                                                     record_cap=cap, **kw),
                      n_threads=4, mesh=(lo, hi, bins))
-    nb = int(np.prod(bins))
     for prec in (gt.PREC_FP64, gt.PREC_MIXED):
-        out = Outs(ni, n, rk, cap)
-        mfx, msum = np.zeros((nb, 2), np.uint64), np.zeros(nb)
-        ws = np.zeros(int(host.L.gt_mesh_workspace_bytes(nb)) // 8, np.uint64)
-        m = gt._Mesh(mesh_fx=mfx.ctypes.data, mesh=msum.ctypes.data, workspace=ws.ctypes.data,
-                     workspace_bytes=ws.nbytes)
-        m.lo[:] = [float(v) for v in lo]
-        m.hi[:] = [float(v) for v in hi]
-        m.n[:] = list(bins)
-        prm = gt._params(kw["seed"], n, geometry_id=kw["geometry_id"], precision=prec, record_first_k=rk,
-                         record_cap=cap)
-        host.check(host.L.cpu_track_mesh(h, C.byref(prm), C.byref(out.struct()), C.byref(m),
-                                         host.staging(h, prec)))
+        out, mfx, msum = mesh_run(host, h, ni, kw, prec, lo, hi, bins, n, rk, cap)
         same(out.a, o, rk)
         assert np.array_equal(mfx, o.mesh_fx), (geom, cover, prec)
         assert np.array_equal(msum, o.mesh_fxd)
