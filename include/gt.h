@@ -268,7 +268,8 @@ int gt_track_event(const gt_geometry *g, const gt_track_params *p, const gt_trac
  * block_size up to 768 (default 768: the mesh build runs 3 waves per SIMD).
  * Errors as gt_track; GT_EINVAL for a bad mesh (n < 1, lo >= hi or not
  * finite, reserved != 0), block_size above 768, a missing mesh_fx, or a
- * missing, short or misaligned workspace; GT_ECAPACITY above 2^31 bins.  Asynchronous; allocates
+ * missing, short or misaligned workspace; GT_ECAPACITY above 2^24 bins on an
+ * axis or 2^31 in all.  Asynchronous; allocates
  * nothing. */
 typedef struct {
     double lo[3], hi[3];

@@ -833,6 +833,7 @@ extern "C" int gt_track_mesh(const gt_geometry *g, const gt_track_params *p, con
     uint64_t bins = 1;
     for (int a = 0; a < 3; a++) {
         if (m->n[a] < 1) return set_error("gt_track_mesh: n[%d] must be >= 1", a), GT_EINVAL;
+        if (m->n[a] > (1u << 24)) return set_error("gt_track_mesh: n[%d] above 2^24", a), GT_ECAPACITY;
         if (!std::isfinite(m->lo[a]) || !std::isfinite(m->hi[a]) || !(m->hi[a] > m->lo[a]))
             return set_error("gt_track_mesh: axis %d needs finite lo < hi", a), GT_EINVAL;
         if (!(((m->hi[a] - m->lo[a]) / (double)m->n[a]) > 0.0))
