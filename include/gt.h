@@ -297,7 +297,7 @@ typedef struct {
 typedef struct {
     uint32_t block_size;   /* threads per workgroup, multiple of 64 up to 1024; 0 = 1024      */
     uint32_t refill_min;   /* as gt_track_params.refill_min; 0 = 8                             */
-    uint64_t chunk;        /* histories per work item taken from the device queue; 0 = 16384  */
+    uint64_t chunk;        /* histories per work item taken from the device queue; 0 = 4096   */
     uint32_t regroup_every;/* as gt_track_params.regroup_every; 0 = that of the first item    */
     uint32_t reserved;     /* must be 0                                                        */
 } gt_tuning;               /* a NULL gt_tuning* means: the shape gt_autotune_batch found for
@@ -349,7 +349,7 @@ int gt_autotune_track(const gt_geometry *g, const gt_track_params *p, const gt_t
 int gt_tuning_lookup(const gt_geometry *g, const gt_track_params *p, gt_tuning *out);
 
 /* Time gt_batch_launch for block_size in {512, 640, 1024} x refill_min in
- * {1, 4, 8, 16} x chunk in {4096, 16384, 65536}, then the fastest of these
+ * {1, 4, 8, 16} x chunk in {1024, 2048, 4096, 16384, 65536}, then the fastest of these
  * with regroup_every in {16, 64, 256}; *best gets the fastest.  The
  * winner is cached in the process for this list of (geometry, histories,
  * precision): gt_batch_create and gt_track_batch given a NULL tuning use it. */

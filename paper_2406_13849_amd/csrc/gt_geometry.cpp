@@ -874,7 +874,7 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
     if (!tuning && cached_batch_tuning(items, n_items, &cached)) tuning = &cached;
     const uint32_t block = tuning && tuning->block_size ? tuning->block_size : 1024;
     const uint32_t refill = tuning && tuning->refill_min ? tuning->refill_min : 0;
-    const uint64_t chunk = tuning && tuning->chunk ? tuning->chunk : 16384;
+    const uint64_t chunk = tuning && tuning->chunk ? tuning->chunk : 4096;   // the tuner's choice on the 64-geometry batch
     if (block % 64 || block > 1024) return set_error("gt_batch_create: block_size must be a multiple of 64 up to 1024"), GT_EINVAL;
     if (refill > 64) return set_error("gt_batch_create: refill_min must be at most 64"), GT_EINVAL;
     if (tuning && tuning->reserved) return set_error("gt_batch_create: tuning reserved must be 0"), GT_EINVAL;

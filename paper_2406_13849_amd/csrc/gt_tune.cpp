@@ -67,7 +67,7 @@ int time_launches(F launch, uint32_t reps, hipStream_t st, float *ms) {
 
 const uint32_t kBlocks[] = {256, 512, 640, 1024};
 const uint32_t kRefills[] = {1, 4, 8, 16};
-const uint64_t kChunks[] = {4096, 16384, 65536};
+const uint64_t kChunks[] = {1024, 2048, 4096, 16384, 65536};
 const uint32_t kRegroups[] = {16, 64, 256};   // second stage, at the fastest shape of the first
 
 }  // namespace

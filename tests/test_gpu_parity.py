@@ -607,7 +607,7 @@ def test_autotune_batch_then_tuned_batch():
         want.append(oracle.track(O, oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=2500, **kw),
                                  n_threads=NT))
     shape = gt.autotune_batch(items, reps=1)
-    assert shape["block_size"] in (512, 640, 1024) and shape["chunk"] in (4096, 16384, 65536)
+    assert shape["block_size"] in (512, 640, 1024) and shape["chunk"] in (1024, 2048, 4096, 16384, 65536)
     assert shape["regroup_every"] in (0, 16, 64, 256)
     gt.track_batch(items, tuned=True)
     torch.cuda.synchronize()
