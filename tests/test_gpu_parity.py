@@ -315,6 +315,24 @@ def test_mesh_tally_matches_oracle(case, prec):
     assert (mfx[:, 1] > 0).sum() > 0
 
 
+def test_mesh_tally_full_size():
+    """The benchmark's mesh leg at full size, in its launch configuration:
+    the 17x17 workload's 1e6 histories (80.7 M segments) with the paper's
+    119 x 119 x 30 mesh over the domain, mixed precision, default shape; every
+    bin, every history and every cell tally against the oracle."""
+    import torch
+    fg, G, O = geoms(2)
+    kw = dict(seed=synth.particle_seed(2), n_particles=synth.CONFIG_PARTICLES[2], geometry_id=2)
+    bins = (119, 119, 30)
+    print("mesh full size", kw, bins, flush=True)
+    out, m = gt.track_mesh(G, mesh_lo=fg.domain_lo, mesh_hi=fg.domain_hi, mesh_n=bins, **kw)
+    torch.cuda.synchronize()
+    o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT, mesh=(fg.domain_lo, fg.domain_hi, bins))
+    assert_parity(_outs(out), o, where="mesh full size")
+    assert np.array_equal(m.mesh_fx.cpu().numpy().view(np.uint64), o.mesh_fx)
+    assert np.array_equal(m.mesh.cpu().numpy(), o.mesh_fxd)
+
+
 def test_mesh_tally_accumulates_and_rejects_bad_meshes():
     import torch
     fg, G, O = geoms(2)
