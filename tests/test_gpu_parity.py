@@ -395,13 +395,18 @@ def test_invalid_track_arguments():
 # ---------------------------------------------------------------- full size
 def test_full_size_cfg2_all_particles():
     """The benchmark workload (17x17 two-level lattice, 1e6 histories, mixed
-    precision, default launch): every particle and every tally."""
+    precision, default launch): every particle and every tally; then the
+    benchmark's regroup leg (every 64 loop trips), which must match too."""
     fg, G, O = geoms(2)
     kw = dict(seed=synth.particle_seed(2), n_particles=1_000_000, geometry_id=2)
     print("cfg2 full size", flush=True)
     g = gpu_track(G, precision=gt.PREC_MIXED, record_first_k=1000, record_cap=256, **kw)
     o = oracle.track(O, oracle.TrackParams(record_first_k=1000, record_cap=256, **kw), n_threads=NT)
     assert_parity(g, o, where="cfg2 full")
+    print("cfg2 full size, regroup every 64", flush=True)
+    g = gpu_track(G, precision=gt.PREC_MIXED, record_first_k=1000, record_cap=256, regroup_every=64, **kw)
+    assert gt.last_launch()["regroup_every"] == 64
+    assert_parity(g, o, where="cfg2 full, regroup")
 
 
 @pytest.mark.parametrize("cfg", [3, 4])
