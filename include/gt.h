@@ -264,12 +264,11 @@ int gt_track_event(const gt_geometry *g, const gt_track_params *p, const gt_trac
  *   mesh:      [bins] double device or NULL: mesh_fx in cm;
  *   workspace: caller-owned device memory of gt_mesh_workspace_bytes(bins)
  *              bytes, 256-byte aligned, contents overwritten.
- * Persistent schedule only (no GT_FLAG_LANE_PER_HISTORY, regroup_every 0),
- * block_size up to 768 (default 768: the mesh build runs 3 waves per SIMD).
+ * Persistent schedule only (no GT_FLAG_LANE_PER_HISTORY, regroup_every 0).
  * Errors as gt_track; GT_EINVAL for a bad mesh (n < 1, lo >= hi or not
- * finite, reserved != 0), block_size above 768, a missing mesh_fx, or a
- * missing, short or misaligned workspace; GT_ECAPACITY above 2^24 bins on an
- * axis or 2^31 in all.  Asynchronous; allocates
+ * finite, reserved != 0), a missing mesh_fx, or a missing, short or
+ * misaligned workspace; GT_ECAPACITY above 2^24 bins on an axis or 2^31 in
+ * all.  Asynchronous; allocates
  * nothing. */
 typedef struct {
     double lo[3], hi[3];

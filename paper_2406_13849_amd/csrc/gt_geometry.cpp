@@ -827,8 +827,6 @@ extern "C" int gt_track_mesh(const gt_geometry *g, const gt_track_params *p, con
     if (p->flags & GT_FLAG_LANE_PER_HISTORY)
         return set_error("gt_track_mesh: the mesh tally needs the persistent schedule"), GT_EINVAL;
     if (p->regroup_every) return set_error("gt_track_mesh: regroup_every must be 0"), GT_EINVAL;
-    if (p->block_size > (uint32_t)kBlockMesh)
-        return set_error("gt_track_mesh: block_size must be at most %d", kBlockMesh), GT_EINVAL;
     if (m->reserved) return set_error("gt_track_mesh: reserved must be 0"), GT_EINVAL;
     uint64_t bins = 1;
     for (int a = 0; a < 3; a++) {

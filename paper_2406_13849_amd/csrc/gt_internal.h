@@ -18,7 +18,6 @@ __host__ __device__ inline uint32_t hs_pack(uint32_t s, bool pos, uint32_t type)
 }
 
 constexpr int kBlockP = 1024;   // lanes per workgroup of the persistent trackers (launch bound)
-constexpr int kBlockMesh = 768; // the same with the mesh tally: 3 waves per SIMD, 168 registers
 // LDS left for staged geometry tables next to the persistent trackers'
 // per-lane level columns (160 KiB per compute unit on gfx950)
 constexpr unsigned kStageBudget = 160 * 1024 - GT_MAX_LEVELS * kBlockP * 4 - 1024;

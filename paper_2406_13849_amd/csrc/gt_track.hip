@@ -101,8 +101,7 @@ __global__ void __launch_bounds__(kBlock) k_ev_cross(Dev g0, KParams p, KOut o, 
 // 128 registers) or 5 (640 lanes, two workgroups per compute unit, 96
 // registers).
 template <int PREC, int KIND, int W, bool RG, bool MESH>
-__global__ void __launch_bounds__(MESH ? kBlockMesh : (W == 5 ? 640 : kBlockP))
-__attribute__((amdgpu_waves_per_eu(MESH ? 3 : W)))
+__global__ void __launch_bounds__(W == 5 ? 640 : kBlockP) __attribute__((amdgpu_waves_per_eu(W)))
 k_track_persistent(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict__ lr, uint32_t tables_at,
                    uint32_t tail_at, uint32_t tail_cap, uint32_t tail_round, uint32_t tail_words, uint32_t regroup,
                    uint32_t cache_at, uint32_t cache_k) {
@@ -632,7 +631,7 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
             const unsigned block = p->block_size ? p->block_size : kBlock;
             hipLaunchKernelGGL((k_track<PREC>), dim3(grid_for(kp.n, block)), dim3(block), 0, st, g->dev, kp, ko);
         } else {
-            const unsigned block = p->block_size ? p->block_size : (mesh ? kBlockMesh : kBlockP);
+            const unsigned block = p->block_size ? p->block_size : kBlockP;
             const StagePlan &sp = g->stage[PREC];
             const int kind = (p->flags & GT_FLAG_NO_STAGING) ? SK_NONE : (int)sp.kind;
             LaunchRec rec;
@@ -643,9 +642,8 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
             const bool cache = !(p->flags & GT_FLAG_NO_TALLY_CACHE);
             const uint32_t rg = p->regroup_every;
             const bool ms = mesh != nullptr;
-            // (the mesh build has its own register budget: one instantiation)
-            int rc = block == 640 && !ms ? launch_persistent<PREC, 5>(g, kind, kp.n, block, tail, cache, rg, ms, st)
-                                         : launch_persistent<PREC, 4>(g, kind, kp.n, block, tail, cache, rg, ms, st);
+            int rc = block == 640 ? launch_persistent<PREC, 5>(g, kind, kp.n, block, tail, cache, rg, ms, st)
+                                  : launch_persistent<PREC, 4>(g, kind, kp.n, block, tail, cache, rg, ms, st);
             if (rc) return rc;
         }
     }

@@ -306,7 +306,7 @@ def test_mesh_tally_matches_oracle(case, prec):
     out, m = gt.track_mesh(G, mesh_lo=lo, mesh_hi=hi, mesh_n=bins, precision=prec,
                            block_size=256 if cfg == 1 else 0, **kw)
     torch.cuda.synchronize()
-    assert gt.last_launch()["block_size"] == (256 if cfg == 1 else 768)
+    assert gt.last_launch()["block_size"] == (256 if cfg == 1 else 1024)
     o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT, mesh=(lo, hi, bins))
     assert_parity(_outs(out), o, where="mesh cfg %s" % cfg)
     mfx = m.mesh_fx.cpu().numpy().view(np.uint64)
@@ -345,7 +345,7 @@ def test_mesh_tally_accumulates_and_rejects_bad_meshes():
                      mesh=(lo, hi, bins))
     assert np.array_equal(m.mesh_fx.cpu().numpy().view(np.uint64), o.mesh_fx)
     bad = [dict(mesh_n=(0, 1, 1)), dict(mesh_lo=hi), dict(lane_per_history=True), dict(regroup_every=4),
-           dict(block_size=1024), dict(mesh_n=((1 << 24) + 1, 1, 1), mesh_out=gt.alloc_mesh(16))]
+           dict(mesh_n=((1 << 24) + 1, 1, 1), mesh_out=gt.alloc_mesh(16))]
     for b in bad:
         kw = dict(mesh_lo=lo, mesh_hi=hi, mesh_n=bins)
         kw.update(b)
