@@ -268,8 +268,7 @@ int gt_track_event(const gt_geometry *g, const gt_track_params *p, const gt_trac
  * Errors as gt_track; GT_EINVAL for a bad mesh (n < 1, lo >= hi or not
  * finite, reserved != 0), a missing mesh_fx, or a missing, short or
  * misaligned workspace; GT_ECAPACITY above 2^24 bins on an axis or 2^31 in
- * all.  Asynchronous; allocates
- * nothing. */
+ * all.  Asynchronous; allocates nothing. */
 typedef struct {
     double lo[3], hi[3];
     uint32_t n[3];
