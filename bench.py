@@ -13,6 +13,14 @@ resident in HBM before the timed region; a step is one gt_track call: zero
 the tallies, sample and track every history, write per-particle outputs,
 finalize the tallies.
 
+Further legs (each reported beside the headline, none of them is `value`):
+the same histories without lattice hints, with the regroup step
+(`mixed_with_regroup`, outputs compared with the headline's), with the
+119 x 119 x 30 superimposed mesh tally (`mixed_with_mesh_tally`, its total
+compared with the cell tallies' track length), by the event-based schedule,
+and the 64-geometry batched launch.  `--config N` runs another workload at
+its own size.
+
 The GPU results of the timed steps are checked against the CPU oracle
 (identical per-particle hashes, segment counts, end codes; bit-identical
 fixed-point tallies) in the cpu_baseline leg, which also times the oracle on
