@@ -333,6 +333,24 @@ def test_mesh_tally_full_size():
     assert np.array_equal(m.mesh.cpu().numpy(), o.mesh_fxd)
 
 
+@pytest.mark.parametrize("opts", [dict(tail_compaction=True), dict(staging=False), dict(block_size=640)],
+                         ids=["tail", "global-tables", "block640"])
+def test_mesh_tally_with_other_options(opts):
+    """The mesh build with tail compaction (the lane's mesh accumulator stays
+    with the lane while histories move), with the tables in global memory,
+    and in the five-wave build."""
+    import torch
+    fg, G, O = geoms(2)
+    kw = dict(seed=93, n_particles=15_000, geometry_id=2)
+    bins = (34, 17, 20)
+    print("mesh options", opts, flush=True)
+    out, m = gt.track_mesh(G, mesh_lo=fg.domain_lo, mesh_hi=fg.domain_hi, mesh_n=bins, **kw, **opts)
+    torch.cuda.synchronize()
+    o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT, mesh=(fg.domain_lo, fg.domain_hi, bins))
+    assert_parity(_outs(out), o, where="mesh %s" % opts)
+    assert np.array_equal(m.mesh_fx.cpu().numpy().view(np.uint64), o.mesh_fx)
+
+
 def test_mesh_tally_accumulates_and_rejects_bad_meshes():
     import torch
     fg, G, O = geoms(2)
