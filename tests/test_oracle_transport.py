@@ -214,6 +214,127 @@ def test_work_meter_hand_count():
     assert segs == 100 and ops == 1400
 
 
+def _box_planes(b, h):
+    return [b.surface(synth.PX, -h), b.surface(synth.PX, h), b.surface(synth.PY, -h),
+            b.surface(synth.PY, h), b.surface(synth.PZ, -h), b.surface(synth.PZ, h)]
+
+
+def _inside_box(s):
+    return [synth.pos(s[0]), synth.neg(s[1]), synth.pos(s[2]), synth.neg(s[3]), synth.pos(s[4]), synth.neg(s[5])]
+
+
+def _ray_grid(n1, n2, h):
+    """(y, z) of the stratified ray grid of ray mode over the face [-h, h]^2."""
+    return [(-h + (j + 0.5) * 2 * h / n1, -h + (k + 0.5) * 2 * h / n2) for k in range(n2) for j in range(n1)]
+
+
+def test_work_meter_hand_count_cylinder():
+    """Rays along +x through a z-cylinder (r = 1) inside a box [-2, 2]^3:
+    cell 0 is the inside of the cylinder (slab |z| <= 2), cell 1 the rest of
+    the box.  By hand, a ray that meets the cylinder costs:
+      birth, containment of cell 1: cylinder value 6 + six axis planes 6 = 12;
+      segment 1 (cell 1): cylinder root with a, b 8, c and discriminant 7,
+        sqrt, subtraction, division 3; the +x plane 2; move 6; crossing into
+        cell 0, its two z-planes checked 2 -> 28;
+      segment 2 (cell 0, on the cylinder): a, b 8, far root -2b/a 2; move 6;
+        crossing into cell 1, six axis planes 6 -> 22;
+      segment 3 (cell 1, on the cylinder, receding): a, b 8; +x plane 2;
+        move 6 -> 16 (then the ray escapes);
+    78 operations, 3 segments.  A ray that misses it: 12 + (8 + 7 + 2 + 6)
+    = 35 operations, 1 segment."""
+    b = synth.GeomBuilder()
+    cz = b.surface(synth.CZ, 0.0, 0.0, 1.0)
+    s = _box_planes(b, 2.0)
+    u = b.universe([([synth.neg(cz), synth.pos(s[4]), synth.neg(s[5])], 0, (0.0, 0.0, 0.0)),
+                    ([synth.pos(cz)] + _inside_box(s), 1, (0.0, 0.0, 0.0))])
+    og = oracle.OracleGeometry(b.build(u, [1.0, 1.0], (-2.0,) * 3, (2.0,) * 3))
+    n1, n2 = 8, 2
+    ops, segs = oracle.count_work(og, oracle.TrackParams(seed=0, n_particles=n1 * n2, source=1, ray_n1=n1))
+    hits = sum(abs(y) < 1.0 for y, z in _ray_grid(n1, n2, 2.0))
+    miss = n1 * n2 - hits
+    assert hits == 8
+    assert segs == 3 * hits + miss and ops == 78 * hits + 35 * miss
+
+
+def test_work_meter_hand_count_sphere():
+    """The same with a sphere (r = 1): cell 1's containment 9 + 6 = 15;
+    segment 1: a, b 13, c and discriminant 9, root 3, the +x plane 2, move 6
+    (cell 0 has no other surface to check) -> 33; segment 2 on the sphere:
+    13 + 2, move 6, six axis planes 6 -> 27; segment 3: 13 + 2 + 6 -> 21:
+    96 operations and 3 segments for a ray that meets it, 15 + (13 + 9 + 2
+    + 6) = 45 and 1 segment for one that does not."""
+    b = synth.GeomBuilder()
+    sp = b.surface(synth.SPH, 0.0, 0.0, 0.0, 1.0)
+    s = _box_planes(b, 2.0)
+    u = b.universe([([synth.neg(sp)], 0, (0.0, 0.0, 0.0)),
+                    ([synth.pos(sp)] + _inside_box(s), 1, (0.0, 0.0, 0.0))])
+    og = oracle.OracleGeometry(b.build(u, [1.0, 1.0], (-2.0,) * 3, (2.0,) * 3))
+    n1 = n2 = 8
+    ops, segs = oracle.count_work(og, oracle.TrackParams(seed=0, n_particles=n1 * n2, source=1, ray_n1=n1))
+    hits = sum(y * y + z * z < 1.0 for y, z in _ray_grid(n1, n2, 2.0))
+    miss = n1 * n2 - hits
+    assert hits == 12
+    assert segs == 3 * hits + miss and ops == 96 * hits + 45 * miss
+
+
+def test_work_meter_hand_count_general_plane():
+    """A general plane x + y = 0 splitting the box [-2, 2]^3: birth in
+    cell 0, containment 6 (plane value) + 6 = 12; segment 1: the plane's
+    denominator 5 and root 6 + 1, the +x plane 2, move 6, crossing into
+    cell 1 with its six axis planes 6 -> 26; segment 2 (on the plane): the
+    +x plane 2, move 6 -> 8; 46 operations and 2 segments per ray."""
+    b = synth.GeomBuilder()
+    pl = b.surface(synth.P, 1.0, 1.0, 0.0, 0.0)
+    s = _box_planes(b, 2.0)
+    u = b.universe([([synth.neg(pl)] + _inside_box(s), 0, (0.0, 0.0, 0.0)),
+                    ([synth.pos(pl)] + _inside_box(s), 1, (0.0, 0.0, 0.0))])
+    og = oracle.OracleGeometry(b.build(u, [1.0, 1.0], (-2.0,) * 3, (2.0,) * 3))
+    ops, segs = oracle.count_work(og, oracle.TrackParams(seed=0, n_particles=24, source=1, ray_n1=6))
+    assert segs == 2 * 24 and ops == 46 * 24
+
+
+def _philox_fields(seed, gid, pid, blk):
+    o = oracle.philox4x32_10([blk, pid & 0xFFFFFFFF, pid >> 32, gid], [seed & 0xFFFFFFFF, seed >> 32])
+    w0 = int(o[1]) << 32 | int(o[0])
+    w1 = int(o[3]) << 32 | int(o[2])
+    m42 = (1 << 42) - 1
+    return [w0 & m42, (w0 >> 42) | ((w1 & ((1 << 20) - 1)) << 22), (w1 >> 20) & m42]
+
+
+def test_work_meter_hand_count_birth():
+    """One birth and one collision in a box whose attenuation is so large
+    that the first flight always ends in a collision, with a cap of one
+    collision.  By hand: a position attempt is three uniforms (2 each) and
+    three scalings (3 each) = 15, never rejected (the box is the domain);
+    the box cell's containment 6; each direction attempt two uniforms (4),
+    2u - 1 twice (4) and s = v1^2 + v2^2 (3) = 11; the accepted direction
+    8 (square root of 1 - s, three scalings); the optical depth, one
+    uniform 2 and the series logarithm 32; then the segment: three axis
+    planes 6, tau / Sigma 1, move 6.  76 + 11 m operations for m direction
+    attempts, which follow from the Philox blocks 1, 2, ... (Marsaglia's
+    rejection of s >= 1)."""
+    seed, gid, n = 77, 9, 40
+    og = oracle.OracleGeometry(synth.box((1.0, 1.0, 1.0), sigma=1e12))
+    p = oracle.TrackParams(seed=seed, n_particles=n, geometry_id=gid, max_collisions=1)
+    ops, segs = oracle.count_work(og, p)
+    want = 0
+    for pid in range(n):
+        m, blk = 0, 1
+        while True:
+            f = _philox_fields(seed, gid, pid, blk)
+            v1 = 2.0 * ((f[0] + 0.5) * 2.0 ** -42) - 1.0
+            v2 = 2.0 * ((f[1] + 0.5) * 2.0 ** -42) - 1.0
+            m += 1
+            blk += 1
+            s = v1 * v1 + v2 * v2
+            if s < 1.0 and s != 0.0:
+                break
+        want += 76 + 11 * m
+    assert segs == n
+    assert ops == want
+    assert want != 87 * n   # some history needed a second direction attempt
+
+
 def test_ray_volumes_hex_pins():
     """Hexagonal pins (three plane families, flat-to-flat 1.3) filling a box:
     for every pin whose hexagon lies inside the box, stratified rays give
