@@ -84,7 +84,12 @@ class _Trace(C.Structure):
         ("seg_inst", C.c_void_p), ("seg_kind", C.c_void_p), ("flight_tau", C.c_void_p),
         ("birth_pos", C.c_double * 3), ("birth_dir", C.c_double * 3),
         ("end_code", C.c_uint8), ("pad2", C.c_uint8 * 7),
+        ("st_pos", C.c_void_p), ("st_dir", C.c_void_p), ("st_state", C.c_void_p),
     ]
+
+
+STATE_LEVELS = 6               # cells per tracking state (the library's level limit)
+STATE_W = STATE_LEVELS + 2     # + the level and surface the particle is on
 
 
 _lib = None
@@ -108,6 +113,7 @@ def lib():
         L.or_sample_births.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, vp]
         L.or_find_cell.argtypes = [vp, vp, u64, vp, vp]
         L.or_distance_to_surface.argtypes = [vp, vp, vp, u64, vp, vp, vp]
+        L.or_distance_to_surface_state.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp]
         L.or_neighbours.argtypes = [vp, u32, vp, u32]
         L.or_philox4x32_10.argtypes = [vp, vp, vp]
         L.or_u01.argtypes = [u64]
@@ -156,6 +162,19 @@ class OracleGeometry:
         if getattr(self, "h", None) and _lib is not None:
             _lib.or_geometry_destroy(self.h)
             self.h = None
+
+    def distance_to_surface_state(self, pos: np.ndarray, dirs: np.ndarray, state: np.ndarray):
+        """distance_to_surface from explicit states: per point the cell of
+        each level (-1 below the leaf) and the (level, surface) it is on."""
+        pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+        dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+        state = np.ascontiguousarray(state, np.int32).reshape(-1, STATE_W)
+        n = pos.shape[0]
+        d = np.empty(n, np.float64)
+        lev = np.empty(n, np.int32)
+        srf = np.empty(n, np.int32)
+        lib().or_distance_to_surface_state(self.h, _p(pos), _p(dirs), _p(state), n, _p(d), _p(lev), _p(srf))
+        return d, lev, srf
 
     def neighbours(self, s: int) -> np.ndarray:
         buf = np.zeros(1 << 16, np.uint32)
@@ -263,17 +282,25 @@ class Trace:
     birth_pos: np.ndarray
     birth_dir: np.ndarray
     end_code: int
+    st_pos: Optional[np.ndarray] = None     # state at the start of each segment (states=True)
+    st_dir: Optional[np.ndarray] = None
+    st_state: Optional[np.ndarray] = None   # [segments, STATE_W] int32
 
 
-def trace_particle(geom: OracleGeometry, p: TrackParams, local: int, cap: int = 100_000) -> Trace:
+def trace_particle(geom: OracleGeometry, p: TrackParams, local: int, cap: int = 100_000,
+                   states: bool = False) -> Trace:
     a = dict(seg_len=np.zeros(cap), seg_sigma=np.zeros(cap), seg_pos=np.zeros((cap, 3)),
              seg_inst=np.zeros(cap, np.int64), seg_kind=np.zeros(cap, np.uint8), flight_tau=np.zeros(cap))
+    if states:
+        a.update(st_pos=np.zeros((cap, 3)), st_dir=np.zeros((cap, 3)), st_state=np.zeros((cap, STATE_W), np.int32))
     t = _Trace(cap=cap, **{k: _p(v) for k, v in a.items()})
     prm = p.c()
     lib().or_trace_particle(geom.h, C.byref(prm), local, C.byref(t))
     n, nf = t.n, t.n_flights
+    extra = {k: a[k][:n] for k in ("st_pos", "st_dir", "st_state")} if states else {}
     return Trace(a["seg_len"][:n], a["seg_sigma"][:n], a["seg_pos"][:n], a["seg_inst"][:n], a["seg_kind"][:n],
-                 a["flight_tau"][:nf], np.array(t.birth_pos[:]), np.array(t.birth_dir[:]), int(t.end_code))
+                 a["flight_tau"][:nf], np.array(t.birth_pos[:]), np.array(t.birth_dir[:]), int(t.end_code),
+                 **extra)
 
 
 def sample_births(geom: OracleGeometry, p: TrackParams):

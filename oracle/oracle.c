@@ -115,7 +115,16 @@ typedef struct {          /* per-segment record of one particle */
     double *flight_tau;                      /* tau sampled at each flight start */
     double birth_pos[3], birth_dir[3];
     uint8_t end_code, pad2[7];
+    /* optional (NULL): the tracking state at the start of each segment --
+     * position and direction (3 each), and OR_STATE_W int32 words: the cell
+     * of levels 0..OR_STATE_LEVELS-1 (-1 below the leaf), then the level and
+     * surface the particle is on (-1, -1 when on none) */
+    double *st_pos, *st_dir;
+    int32_t *st_state;
 } or_trace;
+
+#define OR_STATE_LEVELS 6
+#define OR_STATE_W (OR_STATE_LEVELS + 2)
 
 /* ------------------------------------------------------------------ */
 /* geometry                                                            */
@@ -762,6 +771,15 @@ static void run_history(const or_geom *g, const or_params *pr, uint64_t local, t
     while (end == END_NONE) {
         int bl;
         int64_t bs;
+        if (tr && tr->st_state && tr->n < tr->cap) {
+            uint32_t n = tr->n;
+            memcpy(tr->st_pos + 3 * n, t.p, sizeof t.p);
+            memcpy(tr->st_dir + 3 * n, t.u, sizeof t.u);
+            int32_t *w = tr->st_state + (size_t)OR_STATE_W * n;
+            for (int L = 0; L < OR_STATE_LEVELS; L++) w[L] = L < t.depth ? (int32_t)t.cell[L] : -1;
+            w[OR_STATE_LEVELS] = t.on_level;
+            w[OR_STATE_LEVELS + 1] = t.on_level < 0 ? -1 : (int32_t)t.on_surf;
+        }
         double dist = distance_to_surface(g, &t, &bl, &bs);
         double sig = g->sigma[leaf_material(g, &t)];
         double sc = (pr->source == 1) ? INFINITY : t.tau / sig;
@@ -1038,6 +1056,48 @@ int or_distance_to_surface(const or_geom *g, const double *pos, const double *di
 }
 
 /* neighbour list of a surface (cells referencing it, ascending) */
+/* Table 1 distance_to_surface from explicit tracking states (the layout of
+ * or_trace.st_state): the cell of each level and the surface the particle
+ * is on, as cross_surface leaves them.  A state whose cells do not form a
+ * chain of fills from the root down to a material cell, or whose on-level
+ * is not one of its levels, gives NaN and -1. */
+int or_distance_to_surface_state(const or_geom *g, const double *pos, const double *dir, const int32_t *state,
+                                 uint64_t n, double *dist, int32_t *level, int32_t *surf) {
+    for (uint64_t i = 0; i < n; i++) {
+        const int32_t *w = state + (size_t)OR_STATE_W * i;
+        ptl t;
+        memset(&t, 0, sizeof t);
+        memcpy(t.p, pos + 3 * i, sizeof t.p);
+        memcpy(t.u, dir + 3 * i, sizeof t.u);
+        int ok = 1;
+        uint32_t u = g->root;
+        t.depth = 0;
+        for (int L = 0; L < OR_STATE_LEVELS && ok; L++) {
+            int32_t c = w[L];
+            if (c < 0) break;
+            if ((uint32_t)c >= g->nc || g->cell_univ[c] != u) { ok = 0; break; }
+            t.cell[L] = c;
+            t.depth = L + 1;
+            if (g->fill[c] >= 0) break;
+            u = (uint32_t)(-g->fill[c] - 1);
+        }
+        if (t.depth == 0 || g->fill[t.cell[t.depth - 1]] < 0) ok = 0;
+        for (int L = t.depth; ok && L < OR_STATE_LEVELS; L++)
+            if (w[L] != -1) ok = 0;
+        t.on_level = w[OR_STATE_LEVELS];
+        t.on_surf = w[OR_STATE_LEVELS + 1];
+        if (t.on_level < -1 || t.on_level >= t.depth) ok = 0;
+        if (t.on_level < 0) t.on_surf = -1;
+        if (!ok) { dist[i] = NAN; level[i] = -1; surf[i] = -1; continue; }
+        int bl;
+        int64_t bs;
+        dist[i] = distance_to_surface(g, &t, &bl, &bs);
+        level[i] = dist[i] == INFINITY ? -1 : bl;
+        surf[i] = dist[i] == INFINITY ? -1 : (int32_t)bs;
+    }
+    return 0;
+}
+
 int or_neighbours(const or_geom *g, uint32_t s, uint32_t *out, uint32_t cap) {
     uint32_t n = g->nb_off[s + 1] - g->nb_off[s];
     for (uint32_t k = 0; k < n && k < cap; k++) out[k] = g->nb[g->nb_off[s] + k];

@@ -283,6 +283,74 @@ def test_bruteforce_tracker_matches_oracle(name, n, kw):
     assert {k: v for k, v in tal.items() if v} == want
 
 
+def _states(og, seed, gid, n):
+    """Tracking states at the start of every segment of n histories (many of
+    them just after a crossing, so on a surface)."""
+    pos, dirs, st, lens, kinds = [], [], [], [], []
+    for i in range(n):
+        t = oracle.trace_particle(og, oracle.TrackParams(seed=seed, n_particles=n, geometry_id=gid), i,
+                                  cap=5000, states=True)
+        pos.append(t.st_pos)
+        dirs.append(t.st_dir)
+        st.append(t.st_state)
+        lens.append(t.seg_len)
+        kinds.append(t.seg_kind)
+    import numpy as np
+    return (np.concatenate(pos), np.concatenate(dirs), np.concatenate(st), np.concatenate(lens),
+            np.concatenate(kinds))
+
+
+@pytest.mark.parametrize("name,n", [("cfg1", 60), ("cfg2", 12), ("cfg3", 4), ("cfg4", 4), ("sphere", 60),
+                                    ("hex_pin_box", 10), ("nested_box", 60)])
+def test_distance_from_tracking_states_matches_bruteforce(name, n):
+    """distance_to_surface from explicit states (the cell of each level and
+    the surface the particle is on, as a crossing leaves them): the oracle's
+    distance, level and surface equal the brute-force minimum over every
+    half-space of every level, and for a boundary segment the distance is
+    the traced segment length."""
+    import numpy as np
+    fg, seed, gid = _geometry(name)
+    g = Geo(fg)
+    og = oracle.OracleGeometry(fg)
+    pos, dirs, st, lens, kinds = _states(og, seed, gid, n)
+    d, lev, srf = og.distance_to_surface_state(pos, dirs, st)
+    W = oracle.STATE_LEVELS
+    on = 0
+    for i in range(pos.shape[0]):
+        cells = [int(c) for c in st[i, :W] if c >= 0]
+        ol, os_ = int(st[i, W]), int(st[i, W + 1])
+        on += ol >= 0
+        r, L, s, _ = g.nearest(cells, tuple(pos[i]), tuple(dirs[i]), ol, os_)
+        assert (d[i], lev[i], srf[i]) == (r, -1 if L is None else L, -1 if s is None else s), (name, i)
+    assert np.array_equal(d[kinds == 0], lens[kinds == 0])
+    assert np.all(d[kinds == 1] >= lens[kinds == 1])
+    if name not in ("sphere", "nested_box"):   # (their crossings leave the geometry)
+        assert on > pos.shape[0] // 2
+
+
+def test_distance_from_invalid_states():
+    """States that are not a chain of fills from the root to a material
+    cell, or whose on-level is not one of their levels, give NaN and -1."""
+    import numpy as np
+    fg, seed, gid = _geometry("cfg2")
+    og = oracle.OracleGeometry(fg)
+    pos, dirs, st, _, _ = _states(og, seed, gid, 1)
+    good = st[0].copy()
+    W = oracle.STATE_LEVELS
+    bad = []
+    s = good.copy(); s[1] = -1; bad.append(s)                  # stops at a filled cell
+    s = good.copy(); s[0] = fg.n_cells; bad.append(s)          # no such cell
+    s = good.copy(); s[1] = good[0]; bad.append(s)             # level 1 not in the daughter universe
+    s = good.copy(); s[2] = good[1]; bad.append(s)             # a cell below the leaf
+    s = good.copy(); s[W] = 2; bad.append(s)                   # on a level below the leaf
+    s = good.copy(); s[W] = -2; bad.append(s)
+    states = np.stack([good] + bad)
+    d, lev, srf = og.distance_to_surface_state(np.repeat(pos[:1], len(states), 0),
+                                               np.repeat(dirs[:1], len(states), 0), states)
+    assert not np.isnan(d[0])
+    assert np.all(np.isnan(d[1:])) and np.all(lev[1:] == -1) and np.all(srf[1:] == -1)
+
+
 class _NoForcedSense(Geo):
     def find(self, u, q, force=None, exclude=None):
         return super().find(u, q, None, exclude)
