@@ -207,7 +207,15 @@ typedef struct {
  *             h ^= end_code.
  *   rec       [record_first_k * record_cap] int32 or NULL: leaf instance of
  *             each segment of the recorded particles, -1 padded.
- *   counters  [8] uint64, required; zeroed by the call (GT_CNT_*). */
+ *   counters  [8] uint64, required; zeroed by the call (GT_CNT_*).
+ *   workspace device scratch of at least workspace_bytes >=
+ *             gt_track_workspace_bytes(g) bytes, 256-byte aligned, for the
+ *             call's partial tally sums and launch record (overwritten; its
+ *             contents are meaningless after the call), or NULL: the call
+ *             then uses the geometry's own workspace, so calls on one
+ *             geometry that bring no workspace must be ordered (one stream,
+ *             or synchronised); calls with distinct workspaces may run
+ *             concurrently on different streams. */
 typedef struct {
     uint64_t *tally_fx;
     double *tally;
@@ -216,7 +224,12 @@ typedef struct {
     uint8_t *end_code;
     int32_t *rec;
     uint64_t *counters;
+    void *workspace;
+    uint64_t workspace_bytes;
 } gt_track_out;
+
+/* Bytes of the tally workspace a tracking call on g needs (0 for a NULL g). */
+uint64_t gt_track_workspace_bytes(const gt_geometry *g);
 
 /* Sample and track a batch of histories (Alg. 2 reduced to a toy
  * transport: uniform birth position rejected until a root cell contains
@@ -225,7 +238,8 @@ typedef struct {
  * geometry id); per segment distance_to_surface over every level, a
  * boundary crossing when it is strictly shorter than tau/Sigma of the leaf
  * material, else a collision with isotropic redirection; vacuum boundary).
- * Asynchronous on `stream`; allocates nothing. */
+ * Asynchronous on `stream`; allocates nothing.  GT_EINVAL also for a
+ * workspace that is short or not 256-byte aligned. */
 int gt_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream);
 
 /* ---- event-based schedule (for comparison) ------------------------------
@@ -388,12 +402,24 @@ int gt_track_batch(const gt_batch_item *items, uint32_t n_items, const gt_tuning
 int gt_find_cell(const gt_geometry *g, const double *pos, uint64_t n, int64_t *inst, int32_t *cells,
                  uint32_t precision, void *stream);
 
-/* Table 1 distance_to_surface for a batch (device pos[3n], dir[3n]); each
- * point is first located with find_cell and is not on a surface.  dist[n]
- * receives the distance (+inf if none, NaN if the point is in no cell),
- * level[n]/surf[n] the level and surface id hit (-1 if none). */
-int gt_distance_to_surface(const gt_geometry *g, const double *pos, const double *dir, uint64_t n,
-                           double *dist, int32_t *level, int32_t *surf, void *stream);
+/* Table 1 distance_to_surface for a batch (device pos[3n], dir[3n]): the
+ * distance along dir to the nearest surface of the cells the point is in at
+ * every level, ties going to the top-most level, then the lowest surface id
+ * (Alg. 8's surf_universe).
+ *   state: NULL -- each point is first located with find_cell and is on no
+ *          surface; or device int32 [n * (GT_MAX_LEVELS + 2)], per point the
+ *          cell id of levels 0..GT_MAX_LEVELS-1 (a chain of fills from the
+ *          root universe down to a material cell, -1 below it), then the
+ *          level and surface id the point is on (-1 -1 for none), as a
+ *          crossing leaves them: a plane the point is on is not hit again,
+ *          and a cylinder or sphere it is on gives only its far root.
+ * dist[n] receives the distance (+inf if none, NaN if the point is in no
+ * cell or its state is not such a chain or names a level below its leaf),
+ * level[n]/surf[n] the level and surface id hit (-1 if none).  Asynchronous;
+ * GT_EINVAL for a null geometry or, with n > 0, a null array other than
+ * state. */
+int gt_distance_to_surface(const gt_geometry *g, const double *pos, const double *dir, const int32_t *state,
+                           uint64_t n, double *dist, int32_t *level, int32_t *surf, void *stream);
 
 /* Floating-point contract check: for device arrays a[n], b[n] (b > 0)
  * writes a/b, sqrt(b) and the library's logarithm of b (the series used for

@@ -588,8 +588,6 @@ __device__ __forceinline__ int cross(const G &g, Particle &P, int Ls, uint32_t s
 // forwards these atomics to the memory side; the replicas keep the XCDs off
 // each other's addresses); the finalize kernel folds replicas and limbs into
 // the 128-bit total.
-constexpr int kReplicas = 8;
-
 __device__ __forceinline__ uint32_t xcc_id() {
     return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kReplicas - 1);   // HW_REG_XCC_ID[3:0]
 }

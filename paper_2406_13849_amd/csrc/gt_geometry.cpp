@@ -594,8 +594,6 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         if (hipGetDevice(&dev) != hipSuccess) return set_error("hipGetDevice failed"), GT_EHIP;
         const size_t desc_at = total;
         total = align_up(total + sizeof(GeomDesc));
-        const size_t launch_at = total;
-        total = align_up(total + sizeof(LaunchRec));
         void *blob = nullptr;
         hipError_t e = hipMalloc(&blob, total);
         if (e != hipSuccess) return set_error("hipMalloc(%zu): %s", total, hipGetErrorString(e)), GT_ENOMEM;
@@ -605,7 +603,7 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
             return set_error("hipMemcpy: %s", hipGetErrorString(e)), GT_EHIP;
         }
         void *ws = nullptr;
-        const size_t ws_bytes = (size_t)8 * 4 * 8 * (size_t)std::max<uint64_t>(B.ninst[F.root], 1);
+        const size_t ws_bytes = (size_t)track_ws_bytes(B.ninst[F.root]);
         e = hipMalloc(&ws, ws_bytes);
         if (e != hipSuccess) {
             (void)hipFree(blob);
@@ -688,10 +686,11 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
             return set_error("hipMemcpy: %s", hipGetErrorString(e)), GT_EHIP;
         }
         g->desc = (const GeomDesc *)(base + desc_at);
-        g->launch = (LaunchRec *)(base + launch_at);
         g->blob = blob;
         g->blob_bytes = total + ws_bytes;
-        g->tally_ws = (uint64_t *)ws;
+        g->ws = ws;
+        g->launch = (LaunchRec *)ws;
+        g->tally_ws = (uint64_t *)((unsigned char *)ws + kWsTallyAt);
         g->n_inst = B.ninst[F.root];
         g->max_depth = B.depth[F.root];
         g->device = dev;
@@ -726,7 +725,7 @@ extern "C" void gt_geometry_destroy(gt_geometry *g) {
     int cur = 0;
     bool switched = hipGetDevice(&cur) == hipSuccess && cur != g->device && hipSetDevice(g->device) == hipSuccess;
     (void)hipFree(g->blob);
-    (void)hipFree(g->tally_ws);
+    (void)hipFree(g->ws);
     if (switched) (void)hipSetDevice(cur);
     delete g;
 }
@@ -744,7 +743,8 @@ void gt::fill_kparams(const gt_track_params *p, const gt_geometry *g, KParams &k
     kp.rec_cap = p->record_cap;
     kp.refill_min = p->refill_min ? p->refill_min : kRefillMin;
     ko.mesh = MeshDesc{};
-    ko.tally_ws = g->tally_ws;
+    LaunchRec *lr;
+    workspace_of(g, o, &lr, &ko.tally_ws);
     ko.seg_count = o->seg_count;
     ko.seq_hash = o->seq_hash;
     ko.end_code = o->end_code;
@@ -752,11 +752,28 @@ void gt::fill_kparams(const gt_track_params *p, const gt_geometry *g, KParams &k
     ko.counters = o->counters;
 }
 
+void gt::workspace_of(const gt_geometry *g, const gt_track_out *o, LaunchRec **launch, uint64_t **tally) {
+    if (o && o->workspace) {
+        *launch = (LaunchRec *)o->workspace;
+        *tally = (uint64_t *)((unsigned char *)o->workspace + kWsTallyAt);
+    } else {
+        *launch = g->launch;
+        *tally = g->tally_ws;
+    }
+}
+
 unsigned gt::stage_budget() { return kStageBudget; }
+
+extern "C" uint64_t gt_track_workspace_bytes(const gt_geometry *g) {
+    return g ? track_ws_bytes(g->n_inst) : 0;
+}
 
 int gt::check_track_args(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o) {
     if (!g || !p || !o) return set_error("gt_track: null argument"), GT_EINVAL;
     if (!o->tally_fx || !o->counters) return set_error("gt_track: tally_fx and counters are required"), GT_EINVAL;
+    if (o->workspace && (o->workspace_bytes < track_ws_bytes(g->n_inst) || ((uintptr_t)o->workspace & 255u)))
+        return set_error("gt_track: the workspace needs %llu bytes, 256-byte aligned",
+                         (unsigned long long)track_ws_bytes(g->n_inst)), GT_EINVAL;
     if (p->max_collisions < 1) return set_error("gt_track: max_collisions must be >= 1"), GT_EINVAL;
     if (p->max_segments < 1) return set_error("gt_track: max_segments must be >= 1"), GT_EINVAL;
     if (p->precision > GT_PREC_MIXED) return set_error("gt_track: unknown precision %u", p->precision), GT_EINVAL;
@@ -816,7 +833,7 @@ extern "C" uint64_t gt_event_bank_bytes(uint64_t n_particles) {
 
 extern "C" uint64_t gt_mesh_workspace_bytes(uint64_t bins) {
     if (bins == 0 || bins > (1ull << 31)) return 0;
-    return (uint64_t)8 * 4 * 8 * bins;   // per-XCD replicas x limbs x bytes, as the cell tally's workspace
+    return (uint64_t)kReplicas * 4 * 8 * bins;   // per-XCD replicas x limbs x bytes, as the cell tally's workspace
 }
 
 extern "C" int gt_track_mesh(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o,
@@ -896,10 +913,12 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
             if (it.params.flags & GT_FLAG_LANE_PER_HISTORY)
                 return set_error("gt_batch_create: item %u: GT_FLAG_LANE_PER_HISTORY is not available in batches", i), GT_EINVAL;
             if (it.geometry->device != dev) return set_error("gt_batch_create: item %u: geometry on another device", i), GT_EINVAL;
-            for (uint32_t j = 0; j < i; j++)
-                if (items[j].geometry == it.geometry)
-                    return set_error("gt_batch_create: items %u and %u share a geometry", j, i), GT_EINVAL;
             const gt_geometry *g = it.geometry;
+            const void *wsi = it.out.workspace ? it.out.workspace : g->ws;
+            for (uint32_t j = 0; j < i; j++)
+                if ((items[j].out.workspace ? items[j].out.workspace : items[j].geometry->ws) == wsi)
+                    return set_error("gt_batch_create: items %u and %u share a tally workspace (the same geometry "
+                                     "without workspaces of their own)", j, i), GT_EINVAL;
             BatchItem &b = bi[i];
             b.dev = g->dev;
             b.plan = g->stage[prec];
@@ -908,10 +927,10 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
             fill_kparams(&p, g, b.p, b.o, &it.out);
             kind[i] = (it.params.flags & GT_FLAG_NO_STAGING) ? 0 : (uint8_t)b.plan.kind;
             lds[kind[i]] = std::max(lds[kind[i]], kind[i] ? b.plan.total : 0u);
-            fills.push_back({g->tally_ws, (uint64_t)8 * 4 * g->n_inst, 0, 8, 0});
+            fills.push_back({b.o.tally_ws, (uint64_t)kReplicas * 4 * g->n_inst, 0, 8, 0});
             fills.push_back({it.out.counters, 8, 0, 8, 0});
             if (b.p.rec_k) fills.push_back({it.out.rec, (uint64_t)b.p.rec_k * b.p.rec_cap, (uint64_t)(uint32_t)-1, 4, 0});
-            fin[i] = {g->tally_ws, it.out.tally_fx, it.out.tally, g->n_inst,
+            fin[i] = {b.o.tally_ws, it.out.tally_fx, it.out.tally, g->n_inst,
                       (uint32_t)((it.params.flags & GT_FLAG_ACCUMULATE) != 0), 0};
             max_inst = std::max(max_inst, g->n_inst);
             order.push_back({(double)it.params.n_particles * (double)g->max_depth, i});
@@ -934,6 +953,27 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
             n_kind[k] = (uint32_t)(chunks.size() - before);
         }
         if (chunks.size() > 0xFFFFFFF0u) return set_error("gt_batch_create: too many chunks"), GT_ECAPACITY;
+        // Before anything reaches the device: the chunk groups are ordered by
+        // kind (3 .. 0) and sized by n_kind, each chunk names an item of its
+        // group's kind and is non-empty and at most `chunk` long, and each
+        // item's chunks cover its histories [0, n) once, in order.
+        {
+            std::vector<uint64_t> covered(n_items, 0);
+            size_t at = 0;
+            for (int k = 3; k >= 0; k--)
+                for (uint32_t c = 0; c < n_kind[k]; c++, at++) {
+                    const BatchChunk &ch = chunks[at];
+                    if (ch.item >= n_items || kind[ch.item] != k || ch.count == 0 || ch.count > chunk ||
+                        ch.first != covered[ch.item])
+                        return set_error("gt_batch_create: chunk %zu is inconsistent", at), GT_EINVAL;
+                    covered[ch.item] += ch.count;
+                }
+            if (at != chunks.size()) return set_error("gt_batch_create: chunk groups do not add up"), GT_EINVAL;
+            for (uint32_t i = 0; i < n_items; i++)
+                if (covered[i] != items[i].params.n_particles)
+                    return set_error("gt_batch_create: item %u's histories are not covered by its chunks", i),
+                           GT_EINVAL;
+        }
         // one device allocation: items, chunks, fills, finalize items, four queue counters
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
         const size_t o_items = 0;
@@ -1043,11 +1083,12 @@ extern "C" int gt_find_cell(const gt_geometry *g, const double *pos, uint64_t n,
     return launch_find_cell(g, pos, n, inst, cells, precision, stream);
 }
 
-extern "C" int gt_distance_to_surface(const gt_geometry *g, const double *pos, const double *dir, uint64_t n,
-                                      double *dist, int32_t *level, int32_t *surf, void *stream) {
+extern "C" int gt_distance_to_surface(const gt_geometry *g, const double *pos, const double *dir,
+                                      const int32_t *state, uint64_t n, double *dist, int32_t *level, int32_t *surf,
+                                      void *stream) {
     if (!g || (n && (!pos || !dir || !dist || !level || !surf)))
         return set_error("gt_distance_to_surface: null argument"), GT_EINVAL;
-    return launch_distance(g, pos, dir, n, dist, level, surf, stream);
+    return launch_distance(g, pos, dir, state, n, dist, level, surf, stream);
 }
 
 extern "C" int gt_fp64_check(const double *a, const double *b, uint64_t n, double *quot, double *root, double *logb,

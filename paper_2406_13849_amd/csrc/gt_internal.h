@@ -27,6 +27,9 @@ constexpr unsigned kStageBudget = 160 * 1024 - GT_MAX_LEVELS * kBlockP * 4 - 102
 constexpr uint32_t kRefillMin = 8;
 
 constexpr uint32_t kLeafNone = 0xFFFFFFFFu;
+// int32 words of one tracking state given to gt_distance_to_surface: the
+// cell of each level, then the level and surface the particle is on
+constexpr int kStateWords = GT_MAX_LEVELS + 2;
 constexpr uint32_t kLeafMax = 4;       // cells per BVH leaf
 constexpr uint32_t kHintNone = 0, kHintSquare = 1;
 
@@ -149,6 +152,16 @@ struct LaunchRec {
     KOut o;
 };
 
+// Tally workspace of one tracking call (the geometry's own, or the caller's
+// through gt_track_out.workspace): the launch record, then kReplicas
+// replicas x n_inst x four 64-bit limb counters.  Replica r is used by the
+// waves of XCD r mod kReplicas.
+constexpr int kReplicas = 8;
+constexpr uint64_t kWsTallyAt = (sizeof(LaunchRec) + 255) & ~(uint64_t)255;
+inline uint64_t track_ws_bytes(uint64_t n_inst) {
+    return kWsTallyAt + (uint64_t)kReplicas * 4 * 8 * (n_inst ? n_inst : 1);
+}
+
 // One item of a batched launch (device copy).
 struct BatchItem {
     Dev dev;
@@ -199,10 +212,12 @@ struct gt_geometry {
     gt::Dev dev;
     gt::StagePlan stage[2];   // per precision mode (GT_PREC_FP64, GT_PREC_MIXED)
     const gt::GeomDesc *desc; // device copy of dev and stage (in the blob)
-    gt::LaunchRec *launch;    // device slot for the current launch's parameters (in the blob)
     void *blob;          // one device allocation holding every table
     uint64_t blob_bytes;
-    uint64_t *tally_ws;  // tally workspace: 8 replicas x n_inst x 4 limb counters
+    void *ws;            // the geometry's own tally workspace (track_ws_bytes(n_inst) bytes), used by
+                         // calls that bring none: its launch record ...
+    gt::LaunchRec *launch;
+    uint64_t *tally_ws;  // ... and its limb counters
     uint64_t n_inst;
     uint32_t max_depth;
     int device;
@@ -233,6 +248,8 @@ struct gt_batch {
 
 namespace gt {
 void set_error(const char *fmt, ...);
+// The workspace a call uses: the caller's (gt_track_out.workspace) or the geometry's.
+void workspace_of(const gt_geometry *g, const gt_track_out *o, LaunchRec **launch, uint64_t **tally);
 int check_track_args(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o);
 void fill_kparams(const gt_track_params *p, const gt_geometry *g, KParams &kp, KOut &ko, const gt_track_out *o);
 unsigned stage_budget();
@@ -246,8 +263,8 @@ int launch_track(const gt_geometry *g, const gt_track_params *p, const gt_track_
                  const gt_mesh *mesh = nullptr);
 int launch_find_cell(const gt_geometry *g, const double *pos, uint64_t n, int64_t *inst, int32_t *cells,
                      uint32_t precision, void *stream);
-int launch_distance(const gt_geometry *g, const double *pos, const double *dir, uint64_t n, double *dist,
-                    int32_t *level, int32_t *surf, void *stream);
+int launch_distance(const gt_geometry *g, const double *pos, const double *dir, const int32_t *state, uint64_t n,
+                    double *dist, int32_t *level, int32_t *surf, void *stream);
 int launch_fp64_check(const double *a, const double *b, uint64_t n, double *q, double *r, double *l,
                       void *stream);
 uint64_t ev_layout(uint64_t n, unsigned char *base, EvBank *b);

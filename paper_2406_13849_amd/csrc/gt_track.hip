@@ -237,8 +237,9 @@ __global__ void __launch_bounds__(kBlock) k_find_cell(Dev g0, const double *pos,
             cells[i * GT_MAX_LEVELS + L] = (c >= 0 && L < P.depth) ? (int32_t)lvl(P, L) : -1;
 }
 
-__global__ void __launch_bounds__(kBlock) k_distance(Dev g0, const double *pos, const double *dir, uint64_t n,
-                                                     double *dist, int32_t *level, int32_t *surf) {
+__global__ void __launch_bounds__(kBlock) k_distance(Dev g0, const double *pos, const double *dir,
+                                                     const int32_t *state, uint64_t n, double *dist,
+                                                     int32_t *level, int32_t *surf) {
     __shared__ uint32_t lc[GT_MAX_LEVELS * kBlock];
     const DevGlobal g = global_view(g0);
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -254,12 +255,37 @@ __global__ void __launch_bounds__(kBlock) k_distance(Dev g0, const double *pos, 
     P.on_level = -1;
     P.on_surf = kNone;
     P.depth = 0;
-    int32_t fill;
-    const int32_t c = search<GT_PREC_FP64>(g, g.root, P.x, P.y, P.z, kNone, false, -1, 0.0f, 0.0f, fill);
     bool ok = false;
-    if (c >= 0) {
-        lvl(P, 0) = (uint32_t)c;
-        ok = descend<GT_PREC_FP64>(g, P, 0, P.x, P.y, P.z);
+    if (state) {
+        // the caller's state: a chain of fills from the root universe down to
+        // a material cell, -1 below it, then the (level, surface) it is on
+        const int32_t *w = state + (size_t)kStateWords * i;
+        uint32_t u = g.root;
+        ok = true;
+        for (int L = 0; L < GT_MAX_LEVELS; L++) {
+            const int32_t c = w[L];
+            if (c < 0) break;
+            const Univ U = ldv<Univ>(g.univ + u);
+            if ((uint32_t)c < U.cell0 || (uint32_t)c - U.cell0 >= U.ncell) { ok = false; break; }
+            lvl(P, L) = (uint32_t)c;
+            P.depth = L + 1;
+            const int32_t f = g.cell[c].fill;
+            if (f >= 0) break;
+            u = (uint32_t)(-f - 1);
+        }
+        ok = ok && P.depth > 0 && g.cell[lvl(P, P.depth - 1)].fill >= 0;
+        for (int L = P.depth; ok && L < GT_MAX_LEVELS; L++) ok = w[L] == -1;
+        const int32_t ol = w[GT_MAX_LEVELS];
+        ok = ok && ol >= -1 && ol < P.depth;
+        P.on_level = ol;
+        P.on_surf = ol >= 0 ? (uint32_t)w[GT_MAX_LEVELS + 1] : kNone;
+    } else {
+        int32_t fill;
+        const int32_t c = search<GT_PREC_FP64>(g, g.root, P.x, P.y, P.z, kNone, false, -1, 0.0f, 0.0f, fill);
+        if (c >= 0) {
+            lvl(P, 0) = (uint32_t)c;
+            ok = descend<GT_PREC_FP64>(g, P, 0, P.x, P.y, P.z);
+        }
     }
     if (!ok) {
         dist[i] = __builtin_nan("");
@@ -448,8 +474,8 @@ inline void mark(hipEvent_t e, hipStream_t st) {
 // build with the mesh tally when there is a mesh, else the one with the
 // regroup step when one is asked for and finds room, else the plain one.
 template <int PREC, int KIND, int W>
-int launch_persistent_k(const gt_geometry *g, uint64_t n, unsigned block, bool tail, bool cache, uint32_t regroup,
-                        bool mesh, hipStream_t st) {
+int launch_persistent_k(const gt_geometry *g, const LaunchRec *lr, uint64_t n, unsigned block, bool tail, bool cache,
+                        uint32_t regroup, bool mesh, hipStream_t st) {
     const unsigned tables = KIND == SK_NONE ? 0 : g->stage[PREC].total;
     const void *plain = (const void *)k_track_persistent<PREC, KIND, W, false, false>;
     const void *kern = mesh ? (const void *)k_track_persistent<PREC, KIND, W, false, true> : plain;
@@ -467,7 +493,6 @@ int launch_persistent_k(const gt_geometry *g, uint64_t n, unsigned block, bool t
     const uint64_t need = (n + block - 1) / block;
     if ((uint64_t)blocks > need) blocks = (int)need;
     note_launch(lp, blocks, block, KIND);
-    const LaunchRec *lr = (const LaunchRec *)g->launch;
     if (mesh)
         hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, false, true>), dim3(blocks), dim3(block), lp.dyn, st,
                            g->desc, lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.tail_words, 0u,
@@ -484,13 +509,13 @@ int launch_persistent_k(const gt_geometry *g, uint64_t n, unsigned block, bool t
 }
 
 template <int PREC, int W>
-int launch_persistent(const gt_geometry *g, int kind, uint64_t n, unsigned block, bool tail, bool cache,
-                      uint32_t regroup, bool mesh, hipStream_t st) {
+int launch_persistent(const gt_geometry *g, const LaunchRec *lr, int kind, uint64_t n, unsigned block, bool tail,
+                      bool cache, uint32_t regroup, bool mesh, hipStream_t st) {
     switch (kind) {
-    case SK_ALL: return launch_persistent_k<PREC, SK_ALL, W>(g, n, block, tail, cache, regroup, mesh, st);
-    case SK_LDS: return launch_persistent_k<PREC, SK_LDS, W>(g, n, block, tail, cache, regroup, mesh, st);
-    case SK_SPLIT: return launch_persistent_k<PREC, SK_SPLIT, W>(g, n, block, tail, cache, regroup, mesh, st);
-    default: return launch_persistent_k<PREC, SK_NONE, W>(g, n, block, tail, cache, regroup, mesh, st);
+    case SK_ALL: return launch_persistent_k<PREC, SK_ALL, W>(g, lr, n, block, tail, cache, regroup, mesh, st);
+    case SK_LDS: return launch_persistent_k<PREC, SK_LDS, W>(g, lr, n, block, tail, cache, regroup, mesh, st);
+    case SK_SPLIT: return launch_persistent_k<PREC, SK_SPLIT, W>(g, lr, n, block, tail, cache, regroup, mesh, st);
+    default: return launch_persistent_k<PREC, SK_NONE, W>(g, lr, n, block, tail, cache, regroup, mesh, st);
     }
 }
 
@@ -561,7 +586,14 @@ int batch_streams(gt_batch *b, BatchStreams *&bs) {
 template <int PREC, int W>
 int launch_batch_kinds(gt_batch *b, hipStream_t st) {
     int kinds = 0;
-    for (int kind = 0; kind < 4; kind++) kinds += b->n_kind[kind] ? 1 : 0;
+    uint64_t listed = 0;
+    for (int kind = 0; kind < 4; kind++) {
+        kinds += b->n_kind[kind] ? 1 : 0;
+        listed += b->n_kind[kind];
+    }
+    // (gt_batch_create checked every chunk; the groups must still add up
+    // before any launch reads them)
+    if (listed != b->n_chunks) return set_error("gt_batch_launch: inconsistent chunk groups"), GT_EINVAL;
     BatchStreams *bs = nullptr;
     if (kinds > 1) {
         int rc = batch_streams(b, bs);
@@ -596,7 +628,6 @@ int launch_batch_kinds(gt_batch *b, hipStream_t st) {
         }
         lane++;
     }
-    if (first != b->n_chunks) return set_error("gt_batch_launch: inconsistent chunk groups"), GT_EINVAL;
     return GT_OK;
 }
 
@@ -607,7 +638,7 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
     KOut ko;
     fill_kparams(p, g, kp, ko, o);
     const uint64_t nws = (uint64_t)kReplicas * 4 * g->n_inst;
-    hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(nws)), dim3(256), 0, st, g->tally_ws, nws, (uint64_t)0);
+    hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(nws)), dim3(256), 0, st, ko.tally_ws, nws, (uint64_t)0);
     if (mesh) {
         MeshDesc &m = ko.mesh;
         for (int a = 0; a < 3; a++) {
@@ -637,18 +668,21 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
             LaunchRec rec;
             rec.p = kp;
             rec.o = ko;
-            hipLaunchKernelGGL(k_put_launch, dim3(1), dim3(64), 0, st, rec, g->launch);
+            LaunchRec *lrec;
+            uint64_t *tws;
+            workspace_of(g, o, &lrec, &tws);
+            hipLaunchKernelGGL(k_put_launch, dim3(1), dim3(64), 0, st, rec, lrec);
             const bool tail = (p->flags & GT_FLAG_TAIL_COMPACTION) != 0;
             const bool cache = !(p->flags & GT_FLAG_NO_TALLY_CACHE);
             const uint32_t rg = p->regroup_every;
             const bool ms = mesh != nullptr;
-            int rc = block == 640 ? launch_persistent<PREC, 5>(g, kind, kp.n, block, tail, cache, rg, ms, st)
-                                  : launch_persistent<PREC, 4>(g, kind, kp.n, block, tail, cache, rg, ms, st);
+            int rc = block == 640 ? launch_persistent<PREC, 5>(g, lrec, kind, kp.n, block, tail, cache, rg, ms, st)
+                                  : launch_persistent<PREC, 4>(g, lrec, kind, kp.n, block, tail, cache, rg, ms, st);
             if (rc) return rc;
         }
     }
     mark(t_ev_stop, st);
-    hipLaunchKernelGGL(k_finalize, dim3(fill_grid(g->n_inst)), dim3(256), 0, st, (const uint64_t *)g->tally_ws,
+    hipLaunchKernelGGL(k_finalize, dim3(fill_grid(g->n_inst)), dim3(256), 0, st, (const uint64_t *)ko.tally_ws,
                        o->tally_fx, o->tally, g->n_inst, (int)((p->flags & GT_FLAG_ACCUMULATE) != 0));
     if (mesh)
         hipLaunchKernelGGL(k_finalize, dim3(fill_grid(ko.mesh.nb)), dim3(256), 0, st, (const uint64_t *)ko.mesh.ws,
@@ -671,7 +705,7 @@ int launch_event_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
     EvBank b;
     ev_layout(kp.n, (unsigned char *)bank, &b);
     const uint64_t nws = (uint64_t)kReplicas * 4 * g->n_inst;
-    hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(nws)), dim3(256), 0, st, g->tally_ws, nws, (uint64_t)0);
+    hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(nws)), dim3(256), 0, st, ko.tally_ws, nws, (uint64_t)0);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, o->counters, (uint64_t)8, (uint64_t)0);
     if (kp.rec_k) {
         const uint64_t nrec = (uint64_t)kp.rec_k * kp.rec_cap;
@@ -699,7 +733,7 @@ int launch_event_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
         }
     }
     mark(t_ev_stop, st);
-    hipLaunchKernelGGL(k_finalize, dim3(fill_grid(g->n_inst)), dim3(256), 0, st, (const uint64_t *)g->tally_ws,
+    hipLaunchKernelGGL(k_finalize, dim3(fill_grid(g->n_inst)), dim3(256), 0, st, (const uint64_t *)ko.tally_ws,
                        o->tally_fx, o->tally, g->n_inst, (int)((p->flags & GT_FLAG_ACCUMULATE) != 0));
     return hip_check(hipGetLastError(), "gt_track_event launch");
 }
@@ -784,11 +818,11 @@ int launch_find_cell(const gt_geometry *g, const double *pos, uint64_t n, int64_
     return hip_check(hipGetLastError(), "gt_find_cell launch");
 }
 
-int launch_distance(const gt_geometry *g, const double *pos, const double *dir, uint64_t n, double *dist,
-                    int32_t *level, int32_t *surf, void *stream) {
+int launch_distance(const gt_geometry *g, const double *pos, const double *dir, const int32_t *state, uint64_t n,
+                    double *dist, int32_t *level, int32_t *surf, void *stream) {
     if (!n) return GT_OK;
-    hipLaunchKernelGGL(k_distance, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, (hipStream_t)stream, g->dev, pos, dir, n,
-                       dist, level, surf);
+    hipLaunchKernelGGL(k_distance, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, (hipStream_t)stream, g->dev, pos, dir,
+                       state, n, dist, level, surf);
     return hip_check(hipGetLastError(), "gt_distance_to_surface launch");
 }
 

@@ -61,6 +61,7 @@ class _Out(C.Structure):
     _fields_ = [
         ("tally_fx", C.c_void_p), ("tally", C.c_void_p), ("seg_count", C.c_void_p),
         ("seq_hash", C.c_void_p), ("end_code", C.c_void_p), ("rec", C.c_void_p), ("counters", C.c_void_p),
+        ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64),
     ]
 
 
@@ -105,6 +106,8 @@ def lib():
         L.gt_geometry_destroy.restype = None
         L.gt_track.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), vp]
         L.gt_track.restype = i32
+        L.gt_track_workspace_bytes.argtypes = [vp]
+        L.gt_track_workspace_bytes.restype = u64
         L.gt_event_bank_bytes.argtypes = [u64]
         L.gt_event_bank_bytes.restype = u64
         L.gt_track_event.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), vp, u64, vp]
@@ -135,7 +138,7 @@ def lib():
         L.gt_set_kernel_events.restype = i32
         L.gt_find_cell.argtypes = [vp, vp, u64, vp, vp, u32, vp]
         L.gt_find_cell.restype = i32
-        L.gt_distance_to_surface.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp]
+        L.gt_distance_to_surface.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp]
         L.gt_distance_to_surface.restype = i32
         L.gt_fp64_check.argtypes = [vp, vp, u64, vp, vp, vp, vp]
         L.gt_fp64_check.restype = i32
@@ -225,14 +228,22 @@ class TrackOutputs:
     end_code: "object"    # uint8 [n]
     rec: "object"         # int32 [k, cap] or None
     counters: "object"    # int64 [8]
+    workspace: "object" = None   # uint8 [gt_track_workspace_bytes] or None (the geometry's own)
 
     def counters_dict(self) -> dict:
         c = self.counters.cpu().numpy().view(np.uint64)
         return {k: int(v) for k, v in zip(COUNTERS, c)}
 
 
+def track_workspace_bytes(geom: Geometry) -> int:
+    """gt_track_workspace_bytes: device bytes of a tracking call's tally workspace."""
+    return int(lib().gt_track_workspace_bytes(geom.h))
+
+
 def alloc_outputs(geom: Geometry, n: int, record_first_k: int = 0, record_cap: int = 0, device="cuda",
-                  per_particle: bool = True) -> TrackOutputs:
+                  per_particle: bool = True, workspace: bool = False) -> TrackOutputs:
+    """Output tensors for n histories; workspace=True also gives the call a
+    tally workspace of its own (so calls on one geometry may overlap)."""
     import torch
     ni = geom.n_instances
     return TrackOutputs(
@@ -244,6 +255,7 @@ def alloc_outputs(geom: Geometry, n: int, record_first_k: int = 0, record_cap: i
         rec=torch.full((record_first_k, record_cap), -1, dtype=torch.int32, device=device)
         if record_first_k else None,
         counters=torch.zeros(8, dtype=torch.int64, device=device),
+        workspace=torch.empty(track_workspace_bytes(geom), dtype=torch.uint8, device=device) if workspace else None,
     )
 
 
@@ -355,9 +367,10 @@ def _params(seed, n_particles, first_particle=0, geometry_id=0, max_collisions=2
 
 
 def _out_struct(out: TrackOutputs) -> _Out:
+    ws = getattr(out, "workspace", None)
     return _Out(tally_fx=_ptr(out.tally_fx), tally=_ptr(out.tally), seg_count=_ptr(out.seg_count),
                 seq_hash=_ptr(out.seq_hash), end_code=_ptr(out.end_code), rec=_ptr(out.rec),
-                counters=_ptr(out.counters))
+                counters=_ptr(out.counters), workspace=_ptr(ws), workspace_bytes=0 if ws is None else ws.numel())
 
 
 @dataclass
@@ -493,15 +506,19 @@ def find_cell(geom: Geometry, pos, precision: int = PREC_MIXED, stream=None):
     return inst, cells
 
 
-def distance_to_surface(geom: Geometry, pos, dirs, stream=None):
-    """gt_distance_to_surface on device tensors pos, dirs [n, 3] float64."""
+def distance_to_surface(geom: Geometry, pos, dirs, state=None, stream=None):
+    """gt_distance_to_surface on device tensors pos, dirs [n, 3] float64;
+    state (optional) int32 [n, MAX_LEVELS + 2]: the cell of each level (-1
+    below the leaf) and the (level, surface) the point is on (-1, -1)."""
     import torch
     n = pos.shape[0]
+    if state is not None and tuple(state.shape) != (n, MAX_LEVELS + 2):
+        raise GtError(GT_EINVAL, "state must be [n, %d] int32" % (MAX_LEVELS + 2))
     dist = torch.empty(n, dtype=torch.float64, device=pos.device)
     lev = torch.empty(n, dtype=torch.int32, device=pos.device)
     srf = torch.empty(n, dtype=torch.int32, device=pos.device)
-    _check(lib().gt_distance_to_surface(geom.h, _ptr(pos), _ptr(dirs), n, _ptr(dist), _ptr(lev), _ptr(srf),
-                                        _stream(stream)))
+    _check(lib().gt_distance_to_surface(geom.h, _ptr(pos), _ptr(dirs), _ptr(state), n, _ptr(dist), _ptr(lev),
+                                        _ptr(srf), _stream(stream)))
     return dist, lev, srf
 
 

@@ -75,7 +75,7 @@ extern "C" int cpu_track(const gt_geometry *g, const gt_track_params *p, const g
     KOut ko;
     fill_kparams(p, g, kp, ko, o);
     g_cache_k = (p->flags & GT_FLAG_NO_TALLY_CACHE) ? 0 : kTallyCacheMax;
-    std::memset(g->tally_ws, 0, (size_t)8 * 4 * 8 * g->n_inst);
+    std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
     unsigned long long ctr = 0;
@@ -83,7 +83,7 @@ extern "C" int cpu_track(const gt_geometry *g, const gt_track_params *p, const g
     rc = p->precision == GT_PREC_MIXED ? run_kind<GT_PREC_MIXED>(kind, g->dev, sp, kp, ko, q, o->counters)
                                        : run_kind<GT_PREC_FP64>(kind, g->dev, sp, kp, ko, q, o->counters);
     if (rc) return rc;
-    fold_all(g->tally_ws, o->tally_fx, o->tally, g->n_inst, (p->flags & GT_FLAG_ACCUMULATE) != 0);
+    fold_all(ko.tally_ws, o->tally_fx, o->tally, g->n_inst, (p->flags & GT_FLAG_ACCUMULATE) != 0);
     return GT_OK;
 }
 
@@ -107,9 +107,9 @@ extern "C" int cpu_track_mesh(const gt_geometry *g, const gt_track_params *p, co
     md.nb = (uint64_t)m->n[0] * m->n[1] * m->n[2];
     md.ws = (uint64_t *)m->workspace;
     if (m->workspace_bytes < gt_mesh_workspace_bytes(md.nb)) return set_error("cpu_track_mesh: workspace"), GT_EINVAL;
-    std::memset(md.ws, 0, (size_t)8 * 4 * 8 * md.nb);
+    std::memset(md.ws, 0, (size_t)kReplicas * 4 * 8 * md.nb);
     g_cache_k = kTallyCacheMax;
-    std::memset(g->tally_ws, 0, (size_t)8 * 4 * 8 * g->n_inst);
+    std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
     unsigned long long ctr = 0;
@@ -117,7 +117,7 @@ extern "C" int cpu_track_mesh(const gt_geometry *g, const gt_track_params *p, co
     rc = p->precision == GT_PREC_MIXED ? run_kind<GT_PREC_MIXED, true>(kind, g->dev, sp, kp, ko, q, o->counters)
                                        : run_kind<GT_PREC_FP64, true>(kind, g->dev, sp, kp, ko, q, o->counters);
     if (rc) return rc;
-    fold_all(g->tally_ws, o->tally_fx, o->tally, g->n_inst, (p->flags & GT_FLAG_ACCUMULATE) != 0);
+    fold_all(ko.tally_ws, o->tally_fx, o->tally, g->n_inst, (p->flags & GT_FLAG_ACCUMULATE) != 0);
     fold_all(md.ws, m->mesh_fx, m->mesh, md.nb, (p->flags & GT_FLAG_ACCUMULATE) != 0);
     return GT_OK;
 }
@@ -134,7 +134,7 @@ static int cpu_event_t(const gt_geometry *g, const gt_track_params *p, const gt_
     unsigned char *base = (unsigned char *)(((uintptr_t)mem.data() + 255) & ~(uintptr_t)255);
     EvBank b;
     ev_layout(kp.n, base, &b);
-    std::memset(g->tally_ws, 0, (size_t)8 * 4 * 8 * g->n_inst);
+    std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
     blockDim.x = 1;
@@ -142,7 +142,7 @@ static int cpu_event_t(const gt_geometry *g, const gt_track_params *p, const gt_
     const DevGlobal v = global_view(g->dev);
     uint32_t cells[GT_MAX_LEVELS];
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
-    uint64_t *rep = g->tally_ws;
+    uint64_t *rep = ko.tally_ws;
     for (uint64_t i = 0; i < kp.n; i++) ev_birth<PREC>(v, kp, ko, b, rep, i, cells, cnt);
     for (uint64_t it = 0, alive = kp.n; alive; it++) {
         if (it > (uint64_t)kp.max_segs + 1) return set_error("cpu_track_event: histories left"), GT_EHIP;
@@ -159,7 +159,7 @@ static int cpu_event_t(const gt_geometry *g, const gt_track_params *p, const gt_
     c[GT_CNT_REC_OVERFLOW] += cnt.recovf;
     c[GT_CNT_SEGMENTS] += cnt.segments;
     c[GT_CNT_REJECTED] += cnt.rejected;
-    fold_all(g->tally_ws, o->tally_fx, o->tally, g->n_inst, (p->flags & GT_FLAG_ACCUMULATE) != 0);
+    fold_all(ko.tally_ws, o->tally_fx, o->tally, g->n_inst, (p->flags & GT_FLAG_ACCUMULATE) != 0);
     return GT_OK;
 }
 

@@ -46,8 +46,8 @@ void release_batch_streams(gt_batch *) {}
 int launch_find_cell(const gt_geometry *, const double *, uint64_t, int64_t *, int32_t *, uint32_t, void *) {
     return GT_EHIP;
 }
-int launch_distance(const gt_geometry *, const double *, const double *, uint64_t, double *, int32_t *, int32_t *,
-                    void *) {
+int launch_distance(const gt_geometry *, const double *, const double *, const int32_t *, uint64_t, double *,
+                    int32_t *, int32_t *, void *) {
     return GT_EHIP;
 }
 int launch_fp64_check(const double *, const double *, uint64_t, double *, double *, double *, void *) {

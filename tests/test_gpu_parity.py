@@ -121,6 +121,44 @@ def test_distance_parity(cfg):
 
 
 # ---------------------------------------------------------------- histories
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, "hex_pin_box", "nested_box"])
+def test_distance_from_tracking_states(cfg):
+    """distance_to_surface from the states the oracle's tracker passes
+    through (the cell of each level and the surface a crossing left the
+    particle on), plus invalid states: bit-identical distances, levels and
+    surfaces (NaN and -1 for the invalid ones)."""
+    import torch
+    fg, G, O = geoms(cfg)
+    seed, gid = (synth.particle_seed(cfg), cfg) if isinstance(cfg, int) else (4321, 17)
+    pos, dirs, st = [], [], []
+    for i in range(40 if isinstance(cfg, int) and cfg >= 3 else 150):
+        t = oracle.trace_particle(O, oracle.TrackParams(seed=seed, n_particles=1000, geometry_id=gid), i,
+                                  cap=5000, states=True)
+        pos.append(t.st_pos)
+        dirs.append(t.st_dir)
+        st.append(t.st_state)
+    pos, dirs, st = np.concatenate(pos), np.concatenate(dirs), np.concatenate(st)
+    W = oracle.STATE_LEVELS
+    bad = st[:6].copy()
+    bad[0, 0] = fg.n_cells
+    bad[1, W] = 5
+    bad[2, W] = -2
+    bad[3, 0] = -1
+    bad[4, W - 1] = 0
+    pos, dirs, st = np.concatenate([pos, pos[:6]]), np.concatenate([dirs, dirs[:6]]), np.concatenate([st, bad])
+    assert (st[:, W] >= 0).sum() > 0
+    dist, lev, srf = gt.distance_to_surface(G, torch.tensor(pos, device="cuda"), torch.tensor(dirs, device="cuda"),
+                                            torch.tensor(st, device="cuda"))
+    od, ol, os_ = O.distance_to_surface_state(pos, dirs, st)
+    gd = dist.cpu().numpy()
+    assert np.array_equal(np.isnan(gd), np.isnan(od))
+    assert np.isnan(od[-6:]).sum() >= 4
+    ok = ~np.isnan(od)
+    assert np.array_equal(gd[ok].view(np.int64), od[ok].view(np.int64))
+    assert np.array_equal(lev.cpu().numpy(), ol)
+    assert np.array_equal(srf.cpu().numpy(), os_)
+
+
 CASES = [
     ("sphere", dict(seed=31, n_particles=20_000, geometry_id=9, max_collisions=3), 20_000, 64),
     ("box", dict(seed=32, n_particles=20_000, geometry_id=8), 2000, 64),
@@ -410,6 +448,74 @@ def test_invalid_track_arguments():
         gt.track(G, seed=1, n_particles=10, source=1, ray_n1=0)
 
 
+# ---------------------------------------------------------------- workspaces and streams
+def test_concurrent_calls_on_two_streams():
+    """Two geometries on two streams at once (each its own workspace), and
+    one geometry tracked twice at once on two streams with a workspace per
+    call: every result equals the oracle's."""
+    import torch
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    fg1, G1, O1 = geoms(1)
+    fg2, G2, O2 = geoms(2)
+    jobs = [(G1, O1, dict(seed=71, n_particles=20_000, geometry_id=1), s1, False),
+            (G2, O2, dict(seed=72, n_particles=30_000, geometry_id=2), s2, False),
+            (G2, O2, dict(seed=73, n_particles=25_000, geometry_id=2), s1, True),
+            (G2, O2, dict(seed=74, n_particles=15_000, geometry_id=2, precision=gt.PREC_FP64), s2, True)]
+    outs = []
+    torch.cuda.synchronize()
+    for k, (G, O, kw, st, own) in enumerate(jobs[:2]):
+        outs.append(gt.track(G, out=gt.alloc_outputs(G, kw["n_particles"]), stream=st, **kw))
+    torch.cuda.synchronize()
+    for k, (G, O, kw, st, own) in enumerate(jobs[2:]):
+        outs.append(gt.track(G, out=gt.alloc_outputs(G, kw["n_particles"], workspace=True), stream=st,
+                             **kw))
+    torch.cuda.synchronize()
+    for (G, O, kw, st, own), out in zip(jobs, outs):
+        o = oracle.track(O, oracle.TrackParams(**{k: v for k, v in kw.items() if k != "precision"}), n_threads=NT)
+        assert_parity(_outs(out), o, where=str(kw))
+
+
+def test_workspace_arguments():
+    import torch
+    fg, G, O = geoms(1)
+    need = gt.track_workspace_bytes(G)
+    assert need >= 256 + 32 * 8 * G.n_instances
+    out = gt.alloc_outputs(G, 100)
+    out.workspace = torch.empty(need - 8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gt.GtError) as e:
+        gt.track(G, seed=1, n_particles=100, out=out)
+    assert e.value.code == gt.GT_EINVAL
+    big = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    out.workspace = big[8:8 + need]
+    with pytest.raises(gt.GtError) as e:
+        gt.track(G, seed=1, n_particles=100, out=out)
+    assert e.value.code == gt.GT_EINVAL
+    out.workspace = big[256:256 + need]
+    gt.track(G, seed=1, n_particles=100, geometry_id=1, out=out)
+    torch.cuda.synchronize()
+    o = oracle.track(O, oracle.TrackParams(seed=1, n_particles=100, geometry_id=1), n_threads=1)
+    assert_parity(_outs(out), o, where="workspace in a larger buffer")
+
+
+def test_batch_items_sharing_a_geometry_need_workspaces():
+    """Two batch items on one geometry: rejected while they would share the
+    geometry's workspace, tracked exactly once each has its own."""
+    import torch
+    fg, G, O = geoms(2)
+    a = dict(geometry_id=2)
+    with pytest.raises(gt.GtError) as e:
+        gt.track_batch([gt.batch_item(G, 81, 3000, **a), gt.batch_item(G, 82, 2000, **a)])
+    assert e.value.code == gt.GT_EINVAL
+    items = [gt.batch_item(G, 81, 3000, out=gt.alloc_outputs(G, 3000, workspace=True), **a),
+             gt.batch_item(G, 82, 2000, **a),
+             gt.batch_item(G, 83, 2500, out=gt.alloc_outputs(G, 2500, workspace=True), **a)]
+    gt.track_batch(items, chunk=700)
+    torch.cuda.synchronize()
+    for it in items:
+        o = oracle.track(O, oracle.TrackParams(seed=it.seed, n_particles=it.n_particles, geometry_id=2), n_threads=NT)
+        assert_parity(_outs(it.out), o, where="batch item seed %d" % it.seed)
+
+
 # ---------------------------------------------------------------- full size
 def test_full_size_cfg2_all_particles():
     """The benchmark workload (17x17 two-level lattice, 1e6 histories, mixed
@@ -427,26 +533,42 @@ def test_full_size_cfg2_all_particles():
     assert_parity(g, o, where="cfg2 full, regroup")
 
 
-@pytest.mark.parametrize("cfg", [3, 4])
-def test_full_size_sampled(cfg):
-    """Three-level square core (2.86M tallies) and hexagonal core (97k
-    tallies), 1e7 histories on the GPU; a random sample of particles is re-run
-    one by one in the oracle; counters add up."""
+_full_oracle = {}
+
+
+def full_oracle(cfg, n, rk, rc):
+    """One oracle run over every history of a full-size workload, shared by
+    the tests that compare a GPU schedule or precision with it."""
+    key = (cfg, n, rk, rc)
+    if key not in _full_oracle:
+        _full_oracle.clear()
+        fg, G, O = geoms(cfg)
+        print("oracle, cfg%d, %d histories" % (cfg, n), flush=True)
+        _full_oracle[key] = oracle.track(O, oracle.TrackParams(seed=synth.particle_seed(cfg), n_particles=n,
+                                                               geometry_id=cfg, record_first_k=rk, record_cap=rc),
+                                         n_threads=NT)
+    return _full_oracle[key]
+
+
+@pytest.mark.parametrize("cfg,prec,lane", [(3, gt.PREC_MIXED, False), (3, gt.PREC_FP64, False),
+                                           (3, gt.PREC_FP64, True), (4, gt.PREC_MIXED, False),
+                                           (4, gt.PREC_FP64, False)],
+                         ids=["core-mixed", "core-fp64", "core-fp64-lane", "hex-mixed", "hex-fp64"])
+def test_full_size_all_histories(cfg, prec, lane):
+    """The three-level square core (2.86M tallies) and the hexagonal core
+    (97k tallies) at full size, 1e7 histories, in the benchmark's launch
+    configuration (default persistent shape, the first 1e5 sequences
+    recorded; and the plain one-history-per-lane all-FP64 tracker): every
+    history's hash, segment count and end code, every recorded sequence,
+    every counter and every fixed-point tally against one oracle run."""
     fg, G, O = geoms(cfg)
-    n = 10_000_000
-    print("cfg%d full size" % cfg, flush=True)
-    g = gpu_track(G, precision=gt.PREC_MIXED, seed=synth.particle_seed(cfg), n_particles=n, geometry_id=cfg)
-    c = g["counters"]
-    assert c["escaped"] + c["capped"] + c["lost"] + c["segcap"] == n
-    assert c["segments"] == int(g["seg_count"].astype(np.int64).sum())
-    assert np.all(g["tally"] >= 0)
-    rng = np.random.default_rng(3)
-    ids = np.sort(rng.choice(n, size=300, replace=False))
-    for i in ids:
-        o = oracle.track(O, oracle.TrackParams(seed=synth.particle_seed(cfg), n_particles=1, first_particle=int(i),
-                                               geometry_id=cfg), n_threads=1, tallies=False)
-        assert g["seq_hash"][i] == o.seq_hash[0] and g["seg_count"][i] == o.seg_count[0], i
-        assert g["end_code"][i] == o.end_code[0]
+    n, rk, rc = 10_000_000, 100_000, 384
+    o = full_oracle(cfg, n, rk, rc)
+    print("cfg%d full size, precision %d, lane per history %s" % (cfg, prec, lane), flush=True)
+    g = gpu_track(G, precision=prec, seed=synth.particle_seed(cfg), n_particles=n, geometry_id=cfg,
+                  record_first_k=rk, record_cap=rc, lane_per_history=lane)
+    assert g["counters"]["rec_overflow"] == 0
+    assert_parity(g, o, where="cfg%d full" % cfg)
 
 
 # ---------------------------------------------------------------- batched launch
@@ -589,11 +711,10 @@ def test_batch_invalid_arguments():
     assert not g["tally_fx"].any() and sum(g["counters"].values()) == 0
 
 
-def test_batch_full_workload_sampled():
+def test_batch_full_workload_against_oracle():
     """The 64-geometry batched workload at full size (1.42e7 histories, mixed
-    precision, default tuning): counters add up per item, every item's
-    results equal its own gt_track launch, and sampled particles of every
-    item re-run one by one in the oracle."""
+    precision) in one batched launch at the default tuning: every history
+    and every tally of every item against the oracle."""
     import torch
     items = []
     for j in range(synth.BATCH_SIZE):
@@ -602,22 +723,12 @@ def test_batch_full_workload_sampled():
     print("batch full workload", flush=True)
     gt.track_batch(items)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(5)
     for j, it in enumerate(items):
         fg, n, G, O = batch_geoms(j)
         g = _outs(it.out)
-        c = g["counters"]
-        assert c["escaped"] + c["capped"] + c["lost"] + c["segcap"] == n, j
-        assert c["segments"] == int(g["seg_count"].astype(np.int64).sum()), j
-        single = gpu_track(G, precision=gt.PREC_MIXED, seed=synth.batch_particle_seed(j), n_particles=n,
-                           geometry_id=synth.batch_geometry_id(j))
-        for k in ("tally_fx", "seg_count", "seq_hash", "end_code"):
-            assert np.array_equal(g[k], single[k]), (j, k)
-        for i in np.sort(rng.choice(n, size=6, replace=False)):
-            o = oracle.track(O, oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=1,
-                                                   first_particle=int(i), geometry_id=synth.batch_geometry_id(j)),
-                             n_threads=1, tallies=False)
-            assert g["seq_hash"][i] == o.seq_hash[0] and g["seg_count"][i] == o.seg_count[0], (j, i)
+        o = oracle.track(O, oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=n,
+                                               geometry_id=synth.batch_geometry_id(j)), n_threads=NT)
+        assert_parity(g, o, where="batch item %d" % j)
 
 
 # ---------------------------------------------------------------- autotuning
