@@ -1,30 +1,37 @@
 #!/usr/bin/env python3
-"""Benchmark: track segments per second on one MI355X.
+"""Benchmark: track segments per second on one MI355X, mixed precision vs
+all-FP64, with every leg's outputs checked against the CPU oracle.
 
-Workload: the two-level 17x17 square lattice of axially split pins (three
-pin types, 12 materials, 12,716 leaf-instance tallies) with 1e6 toy-transport
-histories (uniform volume source, isotropic, at most 20 collisions), i.e.
-the second workload configuration.  Both precision modes are timed; `value`
-is the mixed-precision tracker (single-precision pruning, double-precision
-decisions), `fp64` the all-double tracker on the same persistent schedule,
-`plain_fp64_lane_per_history` the plain all-double tracker with one history
-per lane (the baseline the mixed tracker must beat).  Inputs (the geometry tables) are
-resident in HBM before the timed region; a step is one gt_track call: zero
-the tallies, sample and track every history, write per-particle outputs,
-finalize the tallies.
+Headline workload (the one the metric is quoted on): the three-level square
+core -- a root cell inside a z-cylinder of radius 140 cm, |z| <= 100, filled
+with a 15 x 15 core lattice of five seeded assembly types, each a 17 x 17
+lattice of three axially split pin types (2,861,100 leaf-instance tallies) --
+with 1e7 toy-transport histories (uniform volume source, isotropic, at most 20
+collisions) and the sequences of the first 1e5 histories recorded.  A step is
+one gt_track call: zero the tallies and counters, pad the record buffer, sample
+and track every history, write the per-particle outputs and recorded
+sequences, finalize the tallies.  Inputs (geometry tables) are resident in HBM
+before the timed region.  `value` is the mixed-precision persistent tracker
+(single-precision pruning, double-precision decisions); `fp64` the
+all-double tracker on the same schedule, the denominator of `mixed_over_fp64`.
 
-Further legs (each reported beside the headline, none of them is `value`):
-the same histories without lattice hints, with the regroup step
-(`mixed_with_regroup`, outputs compared with the headline's), with the
-119 x 119 x 30 superimposed mesh tally (`mixed_with_mesh_tally`, its total
-compared with the cell tallies' track length), by the event-based schedule,
-and the 64-geometry batched launch.  `--config N` runs another workload at
-its own size.
+Further legs on the same workload (each with its own output buffers, each
+checked against the oracle; none of them is `value`): the plain all-FP64
+tracker with one history per lane, the event-based schedule, the single
+tracker with the lattice hints removed (hierarchy searches only), the regroup
+step, and the paper's 119 x 119 x 30 superimposed mesh tally.  Beside it: the
+hexagonal core (7-ring core of 9-ring hexagonal assemblies, planes only, 1e7
+histories) mixed vs all-FP64, and the 64-geometry batch in one persistent
+launch at the shape gt_autotune_batch picks (eager and as a replayed HIP
+graph) against 64 sequential gt_track launches.
 
-The GPU results of the timed steps are checked against the CPU oracle
-(identical per-particle hashes, segment counts, end codes; bit-identical
-fixed-point tallies) in the cpu_baseline leg, which also times the oracle on
-the host cores.
+Parity gate: the oracle tracks every history of every workload on the host
+cores; each leg's per-particle hashes, segment counts and end codes, recorded
+sequences, counters and fixed-point tallies must be identical, and its
+finalized tallies within 1e-12 relative.  The JSON line carries a flag per
+leg; the script exits with status 1 when any leg differs.  The oracle run of
+the headline workload is also the `cpu_baseline` timing (all the host cores
+this process may use); one core on a 1e4-history slice gives the per-core rate.
 """
 
 import argparse
@@ -37,12 +44,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Peak FP64 rate for non-fused operations: 256 CUs x 64 FP64 lanes x 2.4 GHz
-# (the published 78.6 TFLOP/s counts a fused multiply-add as two operations;
-# the tracker is compiled without contraction, so every add/mul/div/sqrt is
-# one operation).
-PEAK_FP64_OPS = 256 * 64 * 2.4e9
-PEAK_HBM = 8.0e12                     # bytes/s, MI355X HBM3E
+# MI355X published peaks: FP64 vector 78.6 TFLOP/s (a fused multiply-add counts
+# two), i.e. 256 CUs x 64 FP64 lanes x 2.4 GHz = 39.3e12 instructions/s issue
+# of non-fused adds, multiplies, divides or square roots.
+PEAK_FP64_FLOPS = 78.6e12
+PEAK_FP64_NONFMA_OPS = 256 * 64 * 2.4e9
+PEAK_HBM = 8.0e12                     # bytes/s, HBM3E
+L2_BYTES_PER_XCD = 4 * 1024 * 1024
+
+# The paper's relative rates on Frontier (one MI250X GCD), quoted as context
+# only (full continuous-energy transport, not this toy; Table 3 and the
+# tracking-kernel times of Section "Performance results").
+PAPER_CONTEXT = {
+    "source": "arXiv 2406.13849, Table 3 and the tracking-kernel time ratios (MI250X GCD)",
+    "st_rate_over_rtk_inactive": 0.834, "st_rate_over_rtk_active": 0.910,
+    "sp_rate_over_rtk_inactive": 0.912, "dp_rate_over_rtk_inactive": 0.778,
+    "st_tracking_kernel_time_over_rtk": 2.02, "sp_tracking_kernel_time_over_rtk": 1.5,
+    "note": "full Shift k-eigenvalue transport on the NuScale SMR model; not comparable to these toy-transport "
+            "segment rates",
+}
+
+WORKLOAD_NAMES = {1: "3x3 square lattice of one pin type (two levels)",
+                  2: "17x17 square lattice of 3 axially split pin types (two levels)",
+                  3: "three-level square core: r=140 cylinder, 15x15 core of 5 assembly types, 17x17 pins of "
+                     "3 types (four levels)",
+                  4: "7-ring hexagonal core of 9-ring hexagonal assemblies, planes only (three levels)"}
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2406_13849_amd", "csrc", f)
+                  for f in ("gt_device.h", "gt_track.hip", "gt_internal.h", "gt_geometry.cpp")]
 
 
 def parse():
@@ -50,32 +78,35 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, choices=[1, 2, 3, 4], default=2,
-                    help="workload: 1 one 3x3 pin lattice, 2 the 17x17 lattice (default, the headline), "
-                         "3 the three-level core, 4 the hexagonal core")
+    ap.add_argument("--aux-steps", type=int, default=2,
+                    help="timed steps of the comparison legs that take most of a second per step "
+                         "(plain one-history-per-lane, event-based, mesh, regroup, no hints)")
+    ap.add_argument("--config", type=int, choices=[1, 2, 3, 4], default=3,
+                    help="headline workload: 1 one 3x3 pin lattice, 2 the 17x17 lattice, 3 the three-level "
+                         "core (default; the metric's workload), 4 the hexagonal core")
     ap.add_argument("--particles", type=int, default=0, help="histories (0 = the workload's own count)")
+    ap.add_argument("--record-k", type=int, default=100_000, help="histories whose sequences are recorded")
+    ap.add_argument("--record-cap", type=int, default=384, help="entries recorded per history")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0, help="refill_min of the persistent schedule (0 = default)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle (and so the parity gate): for profiling runs only")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of tracking, run a plain device copy of this many bytes --steps times "
                          "(reference kernel for scaling HBM counters)")
     ap.add_argument("--only", choices=["mixed", "fp64", "plain_fp64", "event", "batch"], default=None,
-                    help="time one mode only (profiling)")
+                    help="time one leg of the headline workload only (profiling; prints that leg's summary)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-geometry batched workload")
-    ap.add_argument("--no-event", action="store_true", help="skip the event-based schedule leg")
+    ap.add_argument("--no-hex", action="store_true", help="skip the hexagonal core")
+    ap.add_argument("--no-aux", action="store_true", help="skip the comparison legs of the headline workload")
     ap.add_argument("--tail", action="store_true", help="switch on tail compaction (comparison)")
-    ap.add_argument("--regroup", type=int, default=0,
-                    help="regroup the lanes by leaf universe every this many loop trips (comparison; 0 = off)")
     ap.add_argument("--regroup-leg", type=int, default=64,
-                    help="interval of the extra leg timing the headline with regroup on (0 = no such leg)")
+                    help="interval of the leg timing the headline with the regroup step (0 = no such leg)")
     ap.add_argument("--mesh", type=int, nargs=3, default=[119, 119, 30], metavar=("NX", "NY", "NZ"),
                     help="bins of the superimposed mesh tally leg over the domain (the paper's 119 x 119 x 30)")
-    ap.add_argument("--no-mesh", action="store_true", help="skip the mesh tally leg")
     ap.add_argument("--autotune", action="store_true",
-                    help="time the launch shape gt_autotune_track picks instead of the library default")
-    ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)   # the default
-    ap.add_argument("--tune-batch", action="store_true", help="autotune the batched launch shape first")
+                    help="time the headline at the launch shape gt_autotune_track picks")
+    ap.add_argument("--no-tune-batch", action="store_true", help="batched launch at the library defaults")
     return ap.parse_args()
 
 
@@ -109,16 +140,16 @@ class HipEvents:
         self.hip.hipEventDestroy(b)
 
 
-def run_timed(gt, step, args, hev):
-    """Warm up, then time args.steps calls of step(): torch events around
-    each whole step on the launch stream, HIP events (through the library's
-    hook) around its tracking kernels."""
+def run_timed(gt, step, steps, warmup, hev):
+    """Warm up, then time `steps` calls of step(): torch events around each
+    whole step on the launch stream, HIP events (through the library's hook)
+    around its tracking kernels."""
     import torch
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    kev = [hev.pair() for _ in range(args.steps)]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    kev = [hev.pair() for _ in range(steps)]
     t0 = time.perf_counter()
     for (a, b), (ka, kb) in zip(ev, kev):
         gt.set_kernel_events(ka, kb)
@@ -132,140 +163,70 @@ def run_timed(gt, step, args, hev):
     kms = [hev.elapsed_ms(ka, kb) for ka, kb in kev]
     for ka, kb in kev:
         hev.destroy(ka, kb)
-    return dict(ms=ms, kernel_ms=kms, wall=wall)
+    return dict(ms=ms, kernel_ms=kms, wall=wall, steps=steps)
 
 
-def timed(gt, G, out, args, prec, hev, lane=False, regroup=None):
-    kw = dict(seed=args.seed, n_particles=args.particles, geometry_id=args.config, precision=prec,
-              block_size=args.block, out=out,
-              lane_per_history=lane, refill_min=0 if lane else args.refill, tail_compaction=args.tail,
-              regroup_every=0 if lane else (args.regroup if regroup is None else regroup))
-    shape = None
-    if not lane and args.autotune and not args.block and not args.refill and regroup is None:
-        shape = gt.autotune_track(G, reps=2, **{k: v for k, v in kw.items()
-                                                if k not in ("block_size", "refill_min", "regroup_every")})
-        kw["block_size"], kw["refill_min"] = shape["block_size"], shape["refill_min"]
-        kw["regroup_every"] = shape["regroup_every"]
-    r = run_timed(gt, lambda: gt.track(G, **kw), args, hev)
-    r["segments"] = out.counters_dict()["segments"]
-    r["shape"] = {"block_size": kw["block_size"], "refill_min": kw["refill_min"],
-                  "regroup_every": kw["regroup_every"], "autotuned": shape is not None}
-    if not lane:
-        r["shape"]["plan"] = gt.last_launch()
-    return r
+def mean(v):
+    return sum(v) / len(v)
 
 
-def timed_event(gt, G, args, hev):
-    """The event-based schedule on the same workload (mixed precision): one
-    kernel per tracking operation per iteration over a particle bank in
-    device memory (its own outputs and bank)."""
-    import torch
-    n = args.particles
-    out = gt.alloc_outputs(G, n)
-    bank = torch.empty(gt.event_bank_bytes(n), dtype=torch.uint8, device="cuda")
-    r = run_timed(gt, lambda: gt.track_event(G, seed=args.seed, n_particles=n, geometry_id=args.config,
-                                             precision=gt.PREC_MIXED,
-                                             out=out, bank=bank), args, hev)
-    r["segments"] = out.counters_dict()["segments"]
-    return r
+def log(msg):
+    print("# " + msg, file=sys.stderr, flush=True)
 
 
-def batched(gt, synth, args, hev):
-    """The 64-geometry workload: one batched mixed-precision launch against
-    64 sequential gt_track launches (all-double, and mixed)."""
-    items, geoms = [], []
-    for j in range(synth.BATCH_SIZE):
-        fg, n = synth.batch_item(j)
-        G = gt.Geometry(fg)
-        geoms.append((G, n, j))
-        items.append(gt.batch_item(G, synth.batch_particle_seed(j), n, geometry_id=synth.batch_geometry_id(j),
-                                   precision=gt.PREC_MIXED, tail_compaction=args.tail))
-    tuned = None
-    if args.tune_batch:
-        tuned = gt.autotune_batch(items, reps=1)
-    b = gt.Batch(items, block_size=args.block, refill_min=args.refill, tuned=args.tune_batch)
-    res = {"batched_mixed": run_timed(gt, b.launch, args, hev)}
-    segs = sum(it.out.counters_dict()["segments"] for it in items)
-    # the same launch captured once into a HIP graph and replayed
-    import torch
-    s = torch.cuda.Stream()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph, stream=s):
-        b.launch(s)
-    for _ in range(args.warmup):
-        graph.replay()
-    torch.cuda.synchronize()
-    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    for a, e in gev:
-        a.record()
-        graph.replay()
-        e.record()
-    torch.cuda.synchronize()
-    res["batched_mixed_graph_replay"] = {"ms": [a.elapsed_time(e) for a, e in gev]}
-    if sum(it.out.counters_dict()["segments"] for it in items) != segs:
-        raise RuntimeError("graph replay and eager segment counts differ")
-    del graph
-    for name, prec in (("sequential_fp64", gt.PREC_FP64), ("sequential_mixed", gt.PREC_MIXED)):
-        def step(prec=prec):
-            for (G, n, j), it in zip(geoms, items):
-                gt.track(G, seed=synth.batch_particle_seed(j), n_particles=n, geometry_id=synth.batch_geometry_id(j),
-                         precision=prec, block_size=args.block, refill_min=args.refill, out=it.out,
-                         tail_compaction=args.tail)
-        res[name] = run_timed(gt, step, args, hev)
-        if sum(it.out.counters_dict()["segments"] for it in items) != segs:
-            raise RuntimeError("batched and sequential segment counts differ")
-    b.close()
-    out = {"workload": "64 seeded square/hexagonal geometries, 1-3 levels, %d histories" %
-           sum(n for _, n, _ in geoms), "segments_per_step": segs, "batch_shape": tuned}
-    for k, r in res.items():
-        ms = sum(r["ms"]) / len(r["ms"])
-        out[k] = {"value": segs / (ms * 1e-3), "ms_per_step": ms}
-    out["batched_over_sequential_fp64"] = out["batched_mixed"]["value"] / out["sequential_fp64"]["value"]
-    out["batched_over_sequential_mixed"] = out["batched_mixed"]["value"] / out["sequential_mixed"]["value"]
-    return out
-
-
-def cpu_baseline(fg, gpu_out, n, seed, gid):
-    """Oracle on the host cores over the whole workload, and the parity
-    gate of the GPU outputs against it."""
+# ---------------------------------------------------------------- parity
+def host_outputs(out):
+    """A leg's device outputs copied to host arrays."""
     import numpy as np
+    return dict(tally_fx=out.tally_fx.cpu().numpy().view(np.uint64), tally=out.tally.cpu().numpy(),
+                seg_count=out.seg_count.cpu().numpy().view(np.uint32),
+                seq_hash=out.seq_hash.cpu().numpy().view(np.uint64), end_code=out.end_code.cpu().numpy(),
+                rec=None if out.rec is None else out.rec.cpu().numpy(), counters=out.counters_dict())
 
-    import oracle
-    cores = min(16, os.cpu_count() or 1)
-    og = oracle.OracleGeometry(fg)
-    p = oracle.TrackParams(seed=seed, n_particles=n, geometry_id=gid)
-    t0 = time.perf_counter()
-    o = oracle.track(og, p, n_threads=cores)
-    dt = time.perf_counter() - t0
-    g_hash = gpu_out.seq_hash.cpu().numpy().view(np.uint64)
-    g_seg = gpu_out.seg_count.cpu().numpy().view(np.uint32)
-    g_end = gpu_out.end_code.cpu().numpy()
-    g_fx = gpu_out.tally_fx.cpu().numpy().view(np.uint64)
-    parity = bool(np.array_equal(g_hash, o.seq_hash) and np.array_equal(g_seg, o.seg_count)
-                  and np.array_equal(g_end, o.end_code) and np.array_equal(g_fx, o.tally_fx))
+
+def compare(g, o):
+    """Parity of one leg's host outputs g with the oracle's result o: the
+    per-particle hashes, segment counts and end codes, the recorded
+    sequences, the counters and the fixed-point tallies identical; finalized
+    tallies within 1e-12 relative (exactly 0 where the oracle's are 0)."""
+    import numpy as np
+    bad = []
+    for k in ("seq_hash", "seg_count", "end_code"):
+        if not np.array_equal(g[k], getattr(o, k)):
+            bad.append(k)
+    if (o.rec is None) != (g["rec"] is None) or (o.rec is not None and not np.array_equal(g["rec"], o.rec)):
+        bad.append("rec")
+    for k in ("escaped", "capped", "lost", "segcap", "rec_overflow", "segments", "rejected"):
+        if g["counters"][k] != o.counters[k]:
+            bad.append("counter " + k)
+    if not np.array_equal(g["tally_fx"], o.tally_fx):
+        bad.append("tally_fx")
     nz = o.tally != 0
-    g_t = gpu_out.tally.cpu().numpy()
-    rel = float(np.max(np.abs(g_t[nz] - o.tally[nz]) / o.tally[nz])) if nz.any() else 0.0
-    # one core on a 10^4-history slice
-    t0 = time.perf_counter()
-    o1 = oracle.track(og, oracle.TrackParams(seed=seed, n_particles=min(n, 10_000), geometry_id=gid), n_threads=1)
-    per_core = o1.counters["segments"] / (time.perf_counter() - t0)
-    # algorithmic double-precision operations per segment (work meter over a sample)
-    ops, segs = oracle.count_work(og, oracle.TrackParams(seed=seed, n_particles=min(n, 20_000), geometry_id=gid))
-    return dict(value=o.counters["segments"] / dt, unit="segments/s", cores=cores, kind="oracle",
-                sample="the whole workload (%d histories, %d segments), %.1f s" % (n, o.counters["segments"], dt),
-                parity=parity, max_tally_rel_err=rel, ops_per_segment=ops / segs, per_core=per_core)
+    rel = float(np.max(np.abs(g["tally"][nz] - o.tally[nz]) / o.tally[nz])) if nz.any() else 0.0
+    if rel > 1e-12 or np.any(g["tally"][~nz] != 0):
+        bad.append("tally")
+    return dict(identical=not bad, differs=bad, max_tally_rel_err=rel)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_track_persistent_17x17_1e6.md")
-WORKLOAD_NAMES = {1: "3x3 square lattice of one pin type (two levels)",
-                  2: "17x17 square lattice of 3 axially split pin types (two levels)",
-                  3: "15x15 core of 17x17 assemblies of 3 pin types in a cylinder (four levels)",
-                  4: "7-ring hexagonal core of 9-ring hexagonal assemblies, planes only (three levels)"}
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2406_13849_amd", "csrc", f)
-                  for f in ("gt_device.h", "gt_track.hip", "gt_internal.h", "gt_geometry.cpp")]
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ---------------------------------------------------------------- roofline inputs
 def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
@@ -275,34 +236,276 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def traffic_per_launch():
-    """HBM bytes per tracking launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by the
-    factor a plain device copy of known size gives), or None when the kernel
-    sources have changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
+def profile_fields(path):
+    """`- key: value` lines of a committed rocprofv3 summary."""
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    if not os.path.exists(path):
+        return kv
+    with open(path) as f:
         for line in f:
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 kv[k.strip()] = v.strip().strip("`")
+    return kv
+
+
+def counters_for(workload_tag):
+    """HBM bytes per tracking launch and the FP64 issue figures from the
+    committed counter summary of this workload's headline kernel, or None for
+    each when the kernel sources have changed since the counters were taken.
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are each scaled by what the
+    same counter reads for a device copy of known size."""
+    kv = profile_fields(os.path.join(ROOT, "profiles", "hbm_traffic_k_track_persistent_%s.md" % workload_tag))
+    if not kv or kv.get("kernel_source_sha256") != kernel_source_digest():
+        return None
     try:
-        if kv["kernel_source_sha256"] != kernel_source_digest():
-            return None
-        return (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
-                + float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])) * 1024.0
+        r = {"traffic": (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+                         + float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])) * 1024.0}
+        for k in ("fp64_valu_insts_per_dispatch", "valu_insts_per_dispatch", "valu_lane_utilisation",
+                  "lds_bank_conflict_over_lds_insts", "counter_kernel_us"):
+            if k in kv:
+                r[k] = float(kv[k])
+        return r
     except (KeyError, ValueError):
         return None
+
+
+# ---------------------------------------------------------------- legs
+def track_leg(gt, G, n, seed, gid, args, prec, steps, warmup, hev, rec=True, **kw):
+    """One gt_track leg with its own outputs: timing, launch plan, outputs."""
+    rk, rc = (args.record_k, args.record_cap) if rec else (0, 0)
+    rk = min(rk, n)
+    out = gt.alloc_outputs(G, n, rk, rc)
+    call = dict(seed=seed, n_particles=n, geometry_id=gid, precision=prec, record_first_k=rk, record_cap=rc,
+                out=out, tail_compaction=args.tail)
+    call.update(kw)
+    if not call.get("lane_per_history"):
+        call.setdefault("block_size", args.block)
+        call.setdefault("refill_min", args.refill)
+    r = run_timed(gt, lambda: gt.track(G, **call), steps, warmup, hev)
+    r["segments"] = out.counters_dict()["segments"]
+    r["out"] = out
+    if not call.get("lane_per_history"):
+        r["plan"] = gt.last_launch()
+    r["shape"] = {k: call.get(k, 0) for k in ("block_size", "refill_min", "regroup_every")}
+    return r
+
+
+def summary(r, extra=None):
+    ms = mean(r["ms"])
+    d = {"value": r["segments"] / (ms * 1e-3), "ms_per_step": ms, "kernel_ms": mean(r["kernel_ms"]),
+         "steps": r["steps"]}
+    if extra:
+        d.update(extra)
+    return d
+
+
+def workload_legs(gt, synth, cfg, n, args, hev, aux):
+    """The mixed and all-FP64 legs of one workload, and (aux) its comparison legs."""
+    import torch
+    seed = synth.particle_seed(cfg)
+    fg = synth.make_config(cfg)
+    G = gt.Geometry(fg)
+    legs = {}
+    shape_note = None
+    kw_mixed = {}
+    if args.autotune and cfg == args.config:
+        out = gt.alloc_outputs(G, n, min(args.record_k, n), args.record_cap)
+        shape_note = gt.autotune_track(G, seed=seed, n_particles=n, geometry_id=cfg, precision=gt.PREC_MIXED,
+                                       record_first_k=min(args.record_k, n), record_cap=args.record_cap, out=out,
+                                       reps=2)
+        kw_mixed = {k: shape_note[k] for k in ("block_size", "refill_min", "regroup_every")}
+        del out
+    for name, prec in (("mixed", gt.PREC_MIXED), ("fp64", gt.PREC_FP64)):
+        if args.only is None or args.only == name:
+            legs[name] = track_leg(gt, G, n, seed, cfg, args, prec, args.steps, args.warmup, hev,
+                                   **(kw_mixed if name == "mixed" else {}))
+            log("cfg%d %s: %.3f ms/step, %d segments" % (cfg, name, mean(legs[name]["ms"]), legs[name]["segments"]))
+    a_steps, a_warm = min(args.aux_steps, args.steps), min(args.warmup, 1)
+    if aux and args.only in (None, "plain_fp64"):
+        legs["plain_fp64"] = track_leg(gt, G, n, seed, cfg, args, gt.PREC_FP64, a_steps, a_warm, hev,
+                                       lane_per_history=True)
+        log("cfg%d plain fp64 (one history per lane): %.3f ms/step" % (cfg, mean(legs["plain_fp64"]["ms"])))
+    if aux and args.only in (None, "event"):
+        rk = min(args.record_k, n)
+        out = gt.alloc_outputs(G, n, rk, args.record_cap)
+        bank = torch.empty(gt.event_bank_bytes(n), dtype=torch.uint8, device="cuda")
+        r = run_timed(gt, lambda: gt.track_event(G, seed=seed, n_particles=n, geometry_id=cfg,
+                                                 precision=gt.PREC_MIXED, record_first_k=rk,
+                                                 record_cap=args.record_cap, out=out, bank=bank),
+                      a_steps, a_warm, hev)
+        r["segments"] = out.counters_dict()["segments"]
+        r["out"] = out
+        legs["event"] = r
+        del bank
+        log("cfg%d event-based: %.3f ms/step" % (cfg, mean(r["ms"])))
+    if aux and args.only is None:
+        if fg.lattice_hint.any():
+            # the single tracker with the lattice hints removed: no index
+            # guess, every full search through the hierarchy
+            fg2 = synth.make_config(cfg)
+            fg2.lattice_hint[:] = 0
+            G2 = gt.Geometry(fg2)
+            legs["nohint"] = track_leg(gt, G2, n, seed, cfg, args, gt.PREC_MIXED, a_steps, a_warm, hev)
+            legs["nohint"]["geometry"] = G2
+            log("cfg%d mixed without lattice hints: %.3f ms/step" % (cfg, mean(legs["nohint"]["ms"])))
+        if args.regroup_leg:
+            legs["regroup"] = track_leg(gt, G, n, seed, cfg, args, gt.PREC_MIXED, a_steps, a_warm, hev,
+                                        regroup_every=args.regroup_leg)
+            log("cfg%d mixed, regroup every %d: %.3f ms/step" % (cfg, args.regroup_leg,
+                                                                 mean(legs["regroup"]["ms"])))
+        mb = tuple(args.mesh)
+        out = gt.alloc_outputs(G, n, min(args.record_k, n), args.record_cap)
+        mesh_out = gt.alloc_mesh(mb[0] * mb[1] * mb[2])
+        r = run_timed(gt, lambda: gt.track_mesh(G, seed, n, fg.domain_lo, fg.domain_hi, mb, geometry_id=cfg,
+                                                precision=gt.PREC_MIXED, record_first_k=min(args.record_k, n),
+                                                record_cap=args.record_cap, out=out, mesh_out=mesh_out),
+                      a_steps, a_warm, hev)
+        r["segments"] = out.counters_dict()["segments"]
+        r["out"] = out
+        torch.cuda.synchronize()
+        r["mesh"] = {"bins": list(mb), "track_length_cm": float(mesh_out.mesh.sum().item()),
+                     "cell_tally_track_length_cm": float(out.tally.sum().item())}
+        legs["mesh"] = r
+        del mesh_out
+        log("cfg%d mixed with the %dx%dx%d mesh tally: %.3f ms/step" % ((cfg,) + mb + (mean(r["ms"]),)))
+    return fg, G, legs, shape_note
+
+
+def oracle_run(fg, n, seed, gid, args, threads, record=True):
+    import oracle
+    og = oracle.OracleGeometry(fg)
+    rk = min(args.record_k, n) if record else 0
+    p = oracle.TrackParams(seed=seed, n_particles=n, geometry_id=gid, record_first_k=rk,
+                           record_cap=args.record_cap if rk else 0)
+    t0 = time.perf_counter()
+    o = oracle.track(og, p, n_threads=threads)
+    return og, o, time.perf_counter() - t0
+
+
+def check_legs(legs, o, rec_legs):
+    """Parity of every leg against the oracle result o (legs without recorded
+    sequences are compared without them)."""
+    res = {}
+    for name, r in legs.items():
+        g = host_outputs(r["out"])
+        if name not in rec_legs:
+            g["rec"] = o.rec
+        res[name] = compare(g, o)
+        if name == "mesh":
+            m = r["mesh"]
+            ok = abs(m["track_length_cm"] - m["cell_tally_track_length_cm"]) <= 1e-9 * m["cell_tally_track_length_cm"]
+            res[name]["mesh_total_equals_cell_total"] = ok
+            if not ok:
+                res[name]["identical"] = False
+                res[name]["differs"].append("mesh total")
+        r["out"] = None
+    return res
+
+
+def batched(gt, synth, args, hev, threads):
+    """The 64-geometry workload: one batched mixed-precision launch (at the
+    autotuned shape) against 64 sequential gt_track launches (all-double, and
+    mixed); every item of every leg checked against the oracle."""
+    import torch
+    import oracle
+    items, geoms = [], []
+    for j in range(synth.BATCH_SIZE):
+        fg, n = synth.batch_item(j)
+        G = gt.Geometry(fg)
+        geoms.append((fg, G, n, j))
+        items.append(gt.batch_item(G, synth.batch_particle_seed(j), n, geometry_id=synth.batch_geometry_id(j),
+                                   precision=gt.PREC_MIXED, tail_compaction=args.tail))
+    tuned = None
+    if not args.no_tune_batch:
+        tuned = gt.autotune_batch(items, reps=1)
+        log("batch autotuned shape: %s" % tuned)
+    b = gt.Batch(items, tuned=not args.no_tune_batch)
+    res = {"batched_mixed": run_timed(gt, b.launch, args.steps, args.warmup, hev)}
+    segs = sum(it.out.counters_dict()["segments"] for it in items)
+    outs = {"batched_mixed": [host_outputs(it.out) for it in items]}
+    # the same launch captured once into a HIP graph and replayed
+    s = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        b.launch(s)
+    for it in items:
+        it.out.seq_hash.zero_()
+        it.out.tally_fx.zero_()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, e in gev:
+        a.record()
+        graph.replay()
+        e.record()
+    torch.cuda.synchronize()
+    res["batched_mixed_graph_replay"] = {"ms": [a.elapsed_time(e) for a, e in gev], "steps": args.steps}
+    outs["batched_mixed_graph_replay"] = [host_outputs(it.out) for it in items]
+    del graph
+    b.close()
+    for name, prec in (("sequential_fp64", gt.PREC_FP64), ("sequential_mixed", gt.PREC_MIXED)):
+        seq_out = [gt.alloc_outputs(G, n) for (_, G, n, _) in geoms]
+
+        def step(prec=prec, seq_out=seq_out):
+            for (fg, G, n, j), out in zip(geoms, seq_out):
+                gt.track(G, seed=synth.batch_particle_seed(j), n_particles=n, geometry_id=synth.batch_geometry_id(j),
+                         precision=prec, block_size=args.block, refill_min=args.refill, out=out,
+                         tail_compaction=args.tail)
+        res[name] = run_timed(gt, step, args.steps, args.warmup, hev)
+        outs[name] = [host_outputs(o) for o in seq_out]
+        del seq_out
+    log("batch legs timed; oracle over every item")
+    parity = {k: True for k in outs}
+    bad = []
+    t0 = time.perf_counter()
+    for (fg, G, n, j) in geoms:
+        o = oracle.track(oracle.OracleGeometry(fg),
+                         oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=n,
+                                            geometry_id=synth.batch_geometry_id(j)), n_threads=threads)
+        for k in outs:
+            g = outs[k][j]
+            g["rec"] = o.rec
+            c = compare(g, o)
+            if not c["identical"]:
+                parity[k] = False
+                bad.append((k, j, c["differs"]))
+    oracle_s = time.perf_counter() - t0
+    out = {"workload": "64 seeded square/hexagonal geometries, 1-3 levels, %d histories" %
+           sum(n for _, _, n, _ in geoms), "segments_per_step": segs, "batch_shape": tuned}
+    for k, r in res.items():
+        ms = mean(r["ms"])
+        out[k] = {"value": segs / (ms * 1e-3), "ms_per_step": ms, "steps": r["steps"],
+                  "every_item_identical_to_oracle": parity[k]}
+    out["batched_over_sequential_fp64"] = out["batched_mixed"]["value"] / out["sequential_fp64"]["value"]
+    out["batched_over_sequential_mixed"] = out["batched_mixed"]["value"] / out["sequential_mixed"]["value"]
+    out["oracle_s"] = oracle_s
+    if bad:
+        out["mismatches"] = [str(x) for x in bad[:10]]
+    for (_, G, _, _) in geoms:
+        G.close()
+    return out, all(parity.values())
+
+
+def alg_bytes_per_segment(n_inst, histories, segments, recorded_segments):
+    """Algorithmic HBM bytes per segment: 4 B per recorded sequence entry, a
+    16-byte tally read-modify-write for the share of uniformly spread tally
+    updates that miss a 4 MiB L2 (none when the tally array fits), and the
+    13 bytes of per-particle outputs per history."""
+    tally_bytes = 16.0 * n_inst
+    miss = max(0.0, 1.0 - L2_BYTES_PER_XCD / tally_bytes)
+    return (4.0 * recorded_segments + 16.0 * miss * segments + 13.0 * histories) / segments, miss
 
 
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the tracker has no multi-GPU path "
-              "(histories would shard across GPUs by particle-id range; only the one-GPU path is built)", file=sys.stderr)
+              "(histories would shard across GPUs by particle-id range; only the one-GPU path is built)",
+              file=sys.stderr)
         sys.exit(2)
+    import numpy as np
     import torch
     torch.cuda.set_device(0)
     if args.copy_bytes:
@@ -315,78 +518,84 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_bytes, "steps": args.steps}))
         return
     from paper_2406_13849_amd import gt, synth
-    args.seed = synth.particle_seed(args.config)
-    if not args.particles:
-        args.particles = synth.CONFIG_PARTICLES[args.config]
-    fg = synth.make_config(args.config)
-    G = gt.Geometry(fg)
-    n = args.particles
-    out = gt.alloc_outputs(G, n)
-    res = {}
-    modes = [("plain_fp64", gt.PREC_FP64, True), ("fp64", gt.PREC_FP64, False), ("mixed", gt.PREC_MIXED, False)]
-    if args.only:
-        modes = [m for m in modes if m[0] == args.only]
     hev = HipEvents()
-    for name, prec, lane in modes:
-        res[name] = timed(gt, G, out, args, prec, hev, lane)
-        print("# %s: %.3f ms/step, %d segments/step" % (name, sum(res[name]["ms"]) / args.steps,
-                                                        res[name]["segments"]), file=sys.stderr, flush=True)
-    if args.only is None and synth.make_config(args.config).lattice_hint.any():
-        # the same workload with the lattice hints removed: no FP32 index
-        # guess, every full search through the hierarchy (the plain single
-        # tracker against its lattice-aware form)
-        fg2 = synth.make_config(args.config)
-        fg2.lattice_hint[:] = 0
-        G2 = gt.Geometry(fg2)
-        res["nohint"] = timed(gt, G2, gt.alloc_outputs(G2, n), args, gt.PREC_MIXED, hev, False)
-        print("# mixed without lattice hints: %.3f ms/step" % (sum(res["nohint"]["ms"]) / args.steps),
-              file=sys.stderr, flush=True)
-        G2.close()
-    if args.only is None and args.regroup_leg:
-        # the headline with the regroup step on (lanes sorted by leaf universe)
-        out_rg = gt.alloc_outputs(G, n)
-        res["regroup"] = timed(gt, G, out_rg, args, gt.PREC_MIXED, hev, False, regroup=args.regroup_leg)
-        if "mixed" in res:   # result-neutral: the same sequences and tallies as the headline's
-            torch.cuda.synchronize()
-            res["regroup"]["identical"] = bool(torch.equal(out_rg.tally_fx, out.tally_fx) and
-                                               torch.equal(out_rg.seq_hash, out.seq_hash) and
-                                               torch.equal(out_rg.seg_count, out.seg_count))
-        print("# mixed with regroup every %d trips: %.3f ms/step" % (args.regroup_leg,
-                                                                     sum(res["regroup"]["ms"]) / args.steps),
-              file=sys.stderr, flush=True)
-    if args.only is None and not args.no_mesh:
-        # the headline with the superimposed mesh tally (the paper's active cycles)
-        mb = tuple(args.mesh)
-        out_m, mesh_out = gt.alloc_outputs(G, n), gt.alloc_mesh(mb[0] * mb[1] * mb[2])
-        rm = run_timed(gt, lambda: gt.track_mesh(G, args.seed, n, fg.domain_lo, fg.domain_hi, mb,
-                                                 geometry_id=args.config, precision=gt.PREC_MIXED, out=out_m,
-                                                 mesh_out=mesh_out), args, hev)
-        rm["segments"] = out_m.counters_dict()["segments"]
-        torch.cuda.synchronize()
-        total = float(out_m.tally.sum().item())
-        rm["mesh"] = {"bins": list(mb), "track_length_cm": float(mesh_out.mesh.sum().item()),
-                      "cell_tally_track_length_cm": total,
-                      "identical_histories": bool(torch.equal(out_m.seq_hash, out.seq_hash) and
-                                                  torch.equal(out_m.tally_fx, out.tally_fx))
-                      if "mixed" in res else None}
-        res["mesh"] = rm
-        print("# mixed with the %dx%dx%d mesh tally: %.3f ms/step" % (mb + (sum(rm["ms"]) / args.steps,)),
-              file=sys.stderr, flush=True)
-    if args.only in (None, "event") and not args.no_event:
-        res["event"] = timed_event(gt, G, args, hev)
-        print("# event: %.3f ms/step, %d segments/step" % (sum(res["event"]["ms"]) / args.steps,
-                                                           res["event"]["segments"]), file=sys.stderr, flush=True)
+    threads = host_cores()
+    cfg = args.config
+    n = args.particles or synth.CONFIG_PARTICLES[cfg]
+    seed = synth.particle_seed(cfg)
+
+    if args.only == "batch":
+        bat, ok = batched(gt, synth, args, hev, threads) if not args.no_cpu_baseline else (None, True)
+        print(json.dumps({"batched": bat}, default=str), flush=True)
+        sys.exit(0 if ok else 1)
+
+    fg, G, legs, tuned_shape = workload_legs(gt, synth, cfg, n, args, hev,
+                                             aux=not args.no_aux and args.only not in ("mixed", "fp64"))
+    if args.only is not None:
+        res = {k: summary(v) for k, v in legs.items()}
+        ok = True
+        if not args.no_cpu_baseline:
+            _, o, _ = oracle_run(fg, n, seed, cfg, args, host_cores())
+            par = check_legs(legs, o, rec_legs=set(legs))
+            for k in res:
+                res[k]["identical_to_oracle"] = par[k]["identical"]
+                ok = ok and par[k]["identical"]
+        print(json.dumps(res), flush=True)
+        sys.exit(0 if ok else 1)
+    hex_res = None
+    hex_legs = None
+    if cfg != 4 and not args.no_hex:
+        n4 = synth.CONFIG_PARTICLES[4]
+        fg4, G4, hex_legs, _ = workload_legs(gt, synth, 4, n4, args, hev, aux=False)
+
+    ok = True
+    parity = {}
+    cb = None
+    if not args.no_cpu_baseline:
+        log("oracle over the whole workload on %d host threads" % threads)
+        og, o, dt = oracle_run(fg, n, seed, cfg, args, threads)
+        parity = check_legs(legs, o, rec_legs=set(legs))
+        import oracle
+        # one core on a 10^4-history slice; the work meter over a sample
+        t0 = time.perf_counter()
+        o1 = oracle.track(og, oracle.TrackParams(seed=seed, n_particles=min(n, 10_000), geometry_id=cfg),
+                          n_threads=1)
+        per_core = o1.counters["segments"] / (time.perf_counter() - t0)
+        ops, msegs = oracle.count_work(og, oracle.TrackParams(seed=seed, n_particles=min(n, 20_000),
+                                                              geometry_id=cfg))
+        recorded = int((o.rec >= 0).sum()) if o.rec is not None else 0
+        cb = dict(value=o.counters["segments"] / dt, unit="segments/s", cores=threads, kind="oracle",
+                  sample="the whole workload (%d histories, %d segments, first %d sequences recorded), %.1f s"
+                         % (n, o.counters["segments"], min(args.record_k, n), dt),
+                  cpu_model=cpu_model(), per_core_value=per_core,
+                  per_core_sample="one thread, histories 0..%d" % (min(n, 10_000) - 1),
+                  ops_per_segment=ops / msegs, recorded_segments=recorded, n_inst=int(o.tally.shape[0]))
+        del o
+        if hex_legs is not None:
+            log("oracle over the hexagonal core")
+            _, o4, dt4 = oracle_run(fg4, synth.CONFIG_PARTICLES[4], synth.particle_seed(4), 4, args, threads)
+            hp = check_legs(hex_legs, o4, rec_legs=set(hex_legs))
+            hex_res = {"workload": "%s, %d histories" % (WORKLOAD_NAMES[4], synth.CONFIG_PARTICLES[4]),
+                       "segments_per_step": hex_legs["mixed"]["segments"],
+                       "oracle_segments_per_s": o4.counters["segments"] / dt4}
+            for k, r in hex_legs.items():
+                hex_res[k] = summary(r, {"identical_to_oracle": hp[k]["identical"]})
+                ok = ok and hp[k]["identical"]
+            hex_res["mixed_over_fp64"] = hex_res["mixed"]["value"] / hex_res["fp64"]["value"]
+            del o4
+    elif hex_legs is not None:
+        hex_res = {k: summary(r) for k, r in hex_legs.items()}
+
     bat = None
-    if (args.only in (None, "batch")) and not args.no_batch:
-        bat = batched(gt, synth, args, hev)
-        print("# batch: %s" % json.dumps(bat), file=sys.stderr, flush=True)
-    if not any(k in res for k in ("mixed", "fp64")):
-        print(json.dumps({"batched": bat, "event": res.get("event")}, default=str), flush=True)
-        return
-    head = res["mixed"] if "mixed" in res else res["fp64"]
-    ms_step = sum(head["ms"]) / len(head["ms"])
+    if args.only is None and not args.no_batch and not args.no_cpu_baseline:
+        bat, bok = batched(gt, synth, args, hev, threads)
+        ok = ok and bok
+        log("batch: %s" % json.dumps(bat))
+
+    head = legs["mixed"] if "mixed" in legs else legs["fp64"]
+    ms_step = mean(head["ms"])
     seg_s = head["segments"] / (ms_step * 1e-3)
-    kernel_ms = sum(head["kernel_ms"]) / len(head["kernel_ms"])
+    kernel_ms = mean(head["kernel_ms"])
     line = {
         "metric": "track segments/sec on 1 MI355X (mixed vs FP64), exact cell sequences",
         "value": seg_s,
@@ -400,59 +609,78 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "%s, %d histories" % (WORKLOAD_NAMES[args.config], n),
+        "config": {"workload": "%s, %d histories" % (WORKLOAD_NAMES[cfg], n),
                    "histories": n, "segments_per_step": head["segments"],
-                   "precision": "mixed" if "mixed" in res else "fp64", "parallelism": "none (1 GPU)",
-                   "launch_shape": head["shape"]},
+                   "recorded_sequences": [min(args.record_k, n), args.record_cap],
+                   "precision": "mixed" if "mixed" in legs else "fp64", "parallelism": "none (1 GPU)",
+                   "launch_shape": dict(head["shape"], plan=head.get("plan"), autotuned=tuned_shape is not None)},
     }
-    for name, label in (("fp64", "fp64"), ("plain_fp64", "plain_fp64_lane_per_history"),
-                        ("event", "event_based_mixed"), ("nohint", "mixed_without_lattice_hints"),
-                        ("regroup", "mixed_with_regroup"), ("mesh", "mixed_with_mesh_tally")):
-        if name in res:
-            f = res[name]
-            fms = sum(f["ms"]) / len(f["ms"])
-            line[label] = {"value": f["segments"] / (fms * 1e-3), "ms_per_step": fms}
+    labels = (("fp64", "fp64"), ("plain_fp64", "plain_fp64_lane_per_history"), ("event", "event_based_mixed"),
+              ("nohint", "mixed_without_lattice_hints"), ("regroup", "mixed_with_regroup"),
+              ("mesh", "mixed_with_mesh_tally"))
+    for name, label in labels:
+        if name in legs:
+            extra = {}
+            if name in parity:
+                extra["identical_to_oracle"] = parity[name]["identical"]
             if name == "regroup":
-                line[label]["regroup_every"] = f["shape"]["regroup_every"]
-                line[label]["identical_to_headline"] = f.get("identical")
-    if "mesh" in res:
-        line["mixed_with_mesh_tally"].update(res["mesh"]["mesh"])
-        line["mixed_with_mesh_tally"]["time_over_headline"] = \
-            line["mixed_with_mesh_tally"]["ms_per_step"] / ms_step
-    if "mixed" in res and "fp64" in res:
+                extra["regroup_every"] = args.regroup_leg
+            if name == "mesh":
+                extra.update(legs["mesh"]["mesh"])
+                extra["time_over_headline"] = mean(legs["mesh"]["ms"]) / ms_step
+            line[label] = summary(legs[name], extra)
+    if "mixed" in legs and "fp64" in legs:
         line["mixed_over_fp64"] = line["value"] / line["fp64"]["value"]
-    if "mixed" in res and "plain_fp64" in res:
+    if "mixed" in legs and "plain_fp64" in legs:
         line["mixed_over_plain_fp64"] = line["value"] / line["plain_fp64_lane_per_history"]["value"]
-    if "mixed" in res and "event" in res:
+    if "mixed" in legs and "event" in legs:
         line["persistent_over_event_based"] = line["value"] / line["event_based_mixed"]["value"]
+    if hex_res is not None:
+        line["hexagonal"] = hex_res
     if bat is not None:
         line["batched"] = bat
-    if not args.no_cpu_baseline:
-        cb = cpu_baseline(fg, out, n, args.seed, args.config)
-        line["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
-        line["parity"] = {"sequences_and_fixed_point_tallies_identical": cb["parity"],
-                          "max_tally_rel_err": cb["max_tally_rel_err"]}
-        line["cpu_baseline"]["per_core_value"] = cb["per_core"]
-        line["cpu_baseline"]["gpu_in_core_equivalents"] = seg_s / cb["per_core"]
+    line["paper_context"] = PAPER_CONTEXT
+    if cb is not None:
+        line["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "cpu_model",
+                                                   "per_core_value", "per_core_sample")}
+        line["cpu_baseline"]["gpu_in_core_equivalents"] = seg_s / cb["per_core_value"]
+        line["parity"] = {name: parity[name] for name in parity}
+        line["parity"]["all_legs_identical_to_oracle"] = all(p["identical"] for p in parity.values()) and ok
+        ok = ok and line["parity"]["all_legs_identical_to_oracle"]
         achieved = cb["ops_per_segment"] * head["segments"] / (kernel_ms * 1e-3)
-        line["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
-                            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS,
-                            "traffic": traffic_per_launch() if (args.config == 2 and n == 1_000_000) else None,
-                            "ops_per_segment": cb["ops_per_segment"], "kernel_ms": kernel_ms,
-                            "kernel": "k_track_persistent<mixed, staging kind %d>" % G.staging(gt.PREC_MIXED)[0]}
-        # the HBM side of the same kernel: algorithmic bytes (per-particle
-        # outputs; no sequences are recorded here, the tallies fit in the L2)
-        # and the measured bytes per launch from the committed counters
-        alg = 13.0 * n / head["segments"]
+        tag = {3: "core15x15_1e7", 2: "17x17_1e6", 4: "hex_core_1e7", 1: "3x3_1e4"}[cfg]
+        cnt = counters_for(tag) if n == synth.CONFIG_PARTICLES[cfg] else None
+        kind = G.staging(gt.PREC_MIXED)[0]
+        line["roofline"] = {
+            "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_FLOPS / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_FLOPS, "traffic": cnt["traffic"] if cnt else None,
+            "ops_per_segment": cb["ops_per_segment"], "kernel_ms": kernel_ms,
+            "kernel": "k_track_persistent<mixed, staging kind %d>" % kind,
+            "peak_nonfma_fp64_ops": PEAK_FP64_NONFMA_OPS / 1e12,
+            "frac_of_nonfma_issue": achieved / PEAK_FP64_NONFMA_OPS,
+        }
+        if cnt and "fp64_valu_insts_per_dispatch" in cnt:
+            # FP64 VALU wave instructions x 64 lanes over the FP64 lane-issue capacity of the kernel's time
+            line["roofline"]["fp64_valu_issue_frac"] = (cnt["fp64_valu_insts_per_dispatch"] * 64.0
+                                                        / (PEAK_FP64_NONFMA_OPS * kernel_ms * 1e-3))
+            for k in ("valu_lane_utilisation", "lds_bank_conflict_over_lds_insts"):
+                if k in cnt:
+                    line["roofline"][k] = cnt[k]
+        alg, miss = alg_bytes_per_segment(cb["n_inst"], n, head["segments"], cb["recorded_segments"])
         tr = line["roofline"]["traffic"]
-        line["hbm"] = {"algorithmic_bytes_per_segment": alg,
-                       "algorithmic_GBps": alg * seg_s / 1e9,
+        line["hbm"] = {"algorithmic_bytes_per_segment": alg, "tally_l2_miss_share": miss,
+                       "algorithmic_bytes_per_launch": alg * head["segments"],
+                       "algorithmic_GBps": alg * head["segments"] / (kernel_ms * 1e-3) / 1e9,
                        "measured_bytes_per_launch": tr,
+                       "measured_over_algorithmic": (tr / (alg * head["segments"])) if tr else None,
                        "measured_GBps": (tr / (kernel_ms * 1e-3) / 1e9) if tr else None,
                        "peak_GBps": PEAK_HBM / 1e9,
-                       "algorithmic_frac": alg * seg_s / PEAK_HBM,
+                       "algorithmic_frac": alg * head["segments"] / (kernel_ms * 1e-3) / PEAK_HBM,
                        "measured_frac": (tr / (kernel_ms * 1e-3) / PEAK_HBM) if tr else None}
-    print(json.dumps(line), flush=True)
+    print(json.dumps(line, default=str), flush=True)
+    if not ok:
+        log("PARITY FAILURE: a leg's outputs differ from the oracle's")
+        sys.exit(1)
 
 
 if __name__ == "__main__":
