@@ -242,6 +242,27 @@ uint64_t gt_track_workspace_bytes(const gt_geometry *g);
  * workspace that is short or not 256-byte aligned. */
 int gt_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream);
 
+/* ---- allocation-free tracking --------------------------------------------
+ * For callers that cannot allocate device memory during a call or bring a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): gt_track with its tally workspace and launch
+ * record taken from a fixed device array inside the library, of
+ * GT_NOALLOC_SCRATCH_BYTES bytes, one copy per GPU, held from the first
+ * such call on that GPU until the process ends.  The call allocates
+ * nothing (no hipMalloc, no library routine that allocates); inputs and
+ * outputs are the caller's, exactly as for gt_track, and the outputs are
+ * identical to gt_track's.
+ *   o->workspace must be NULL (GT_EINVAL otherwise).
+ *   The geometry's device must be the current device (GT_EINVAL).
+ *   GT_ECAPACITY when gt_track_workspace_bytes(g) exceeds
+ *   GT_NOALLOC_SCRATCH_BYTES (about 131,000 leaf instances).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind; each call clears what it needs.  Calls that may overlap on one GPU
+ * (different streams, or threads without ordering) race on the array and
+ * must be serialised by the caller. */
+#define GT_NOALLOC_SCRATCH_BYTES (32ull << 20)
+int gt_track_noalloc(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, void *stream);
+
 /* ---- event-based schedule (for comparison) ------------------------------
  * The histories and outputs of gt_track, computed the way an event-based GPU
  * tracker is organised (Section "GPU-based implementation in Shift"): the

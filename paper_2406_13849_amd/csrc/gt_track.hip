@@ -833,3 +833,60 @@ int launch_fp64_check(const double *a, const double *b, uint64_t n, double *q, d
 }
 
 }  // namespace gt
+
+// ------------------------------------------------------------------ allocation-free entry point
+// gt_track_noalloc's workspace (launch record, then the per-XCD limb
+// counters of the tallies) lives in this fixed array: every GPU the library
+// runs on holds its own copy until the process ends.  In host code the name
+// stands for the host-side shadow, not a device address, so the device
+// address is looked up once per device (with that device current) and only
+// that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[GT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_at[kMaxDevices];   // device address of `scratch` per device, once looked up
+}  // namespace
+
+extern "C" int gt_track_noalloc(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o,
+                                void *stream) {
+    using namespace gt;
+    if (o && o->workspace)
+        return set_error("gt_track_noalloc: workspace must be NULL (the library's fixed scratch array is used)"),
+               GT_EINVAL;
+    int rc = check_track_args(g, p, o);
+    if (rc) return rc;
+    const uint64_t need = track_ws_bytes(g->n_inst);
+    if (need > GT_NOALLOC_SCRATCH_BYTES)
+        return set_error("gt_track_noalloc: %llu leaf instances need %llu bytes of workspace, above the %llu of "
+                         "the fixed scratch array",
+                         (unsigned long long)g->n_inst, (unsigned long long)need,
+                         (unsigned long long)GT_NOALLOC_SCRATCH_BYTES),
+               GT_ECAPACITY;
+    int dev = -1;
+    rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (rc) return rc;
+    if (dev != g->device)
+        return set_error("gt_track_noalloc: the geometry lives on device %d but device %d is current", g->device,
+                         dev),
+               GT_EINVAL;
+    if (dev < 0 || dev >= kMaxDevices) return set_error("gt_track_noalloc: device %d out of range", dev), GT_EINVAL;
+    void *at;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_at[dev]) {
+            void *a = nullptr;
+            rc = hip_check(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+            if (rc) return rc;
+            if (!a || ((uintptr_t)a & 255u))
+                return set_error("gt_track_noalloc: scratch array at an unusable address %p", a), GT_EHIP;
+            g_scratch_at[dev] = a;
+        }
+        at = g_scratch_at[dev];
+    }
+    gt_track_out o2 = *o;
+    o2.workspace = at;
+    o2.workspace_bytes = GT_NOALLOC_SCRATCH_BYTES;
+    return launch_track(g, p, &o2, stream);
+}

@@ -106,6 +106,8 @@ def lib():
         L.gt_geometry_destroy.restype = None
         L.gt_track.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), vp]
         L.gt_track.restype = i32
+        L.gt_track_noalloc.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), vp]
+        L.gt_track_noalloc.restype = i32
         L.gt_track_workspace_bytes.argtypes = [vp]
         L.gt_track_workspace_bytes.restype = u64
         L.gt_event_bank_bytes.argtypes = [u64]
@@ -281,6 +283,23 @@ def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 
     _check(lib().gt_track(geom.h, C.byref(prm), C.byref(o), _stream(stream)))
     return out
 
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20   # GT_NOALLOC_SCRATCH_BYTES
+
+
+def track_noalloc(geom: Geometry, seed: int, n_particles: int, *, out: TrackOutputs, stream=None,
+                  **kwargs) -> TrackOutputs:
+    """gt_track_noalloc: gt_track with the tally workspace in the library's
+    fixed per-GPU scratch array (no device allocation in the call).  The
+    caller brings every output (`out`, without a workspace); the keyword
+    arguments are those of track()."""
+    if getattr(out, "workspace", None) is not None:
+        raise ValueError("track_noalloc: the outputs must not carry a workspace")
+    prm = _params(seed, n_particles, **kwargs)
+    o = _out_struct(out)
+    _check(lib().gt_track_noalloc(geom.h, C.byref(prm), C.byref(o), _stream(stream)))
+    return out
 
 @dataclass
 class MeshOutputs:
