@@ -16,7 +16,11 @@ before the timed region.  `value` is the mixed-precision persistent tracker
 all-double tracker on the same schedule, the denominator of `mixed_over_fp64`.
 
 Further legs on the same workload (each with its own output buffers, each
-checked against the oracle; none of them is `value`): the plain all-FP64
+checked against the oracle; none of them is `value`): the paper's two
+comparison trackers -- static polymorphism (`sp_tracker_mixed`: a switch on
+each level's universe kind, arrays by index) and the fixed-depth reactor
+tracker (`rtk_tracker`), with the ratios `st_over_rtk`, `sp_over_rtk` and
+`st_over_sp` beside the paper's own (context only) -- the plain all-FP64
 tracker with one history per lane, the event-based schedule, the single
 tracker with the lattice hints removed (hierarchy searches only), the regroup
 step, and the paper's 119 x 119 x 30 superimposed mesh tally.  Beside it: the
@@ -94,8 +98,10 @@ def parse():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of tracking, run a plain device copy of this many bytes --steps times "
                          "(reference kernel for scaling HBM counters)")
-    ap.add_argument("--only", choices=["mixed", "fp64", "plain_fp64", "event", "batch"], default=None,
+    ap.add_argument("--only", choices=["mixed", "fp64", "plain_fp64", "event", "batch", "sp", "rtk"], default=None,
                     help="time one leg of the headline workload only (profiling; prints that leg's summary)")
+    ap.add_argument("--no-trackers", action="store_true",
+                    help="skip the SP and RTK tracker legs of the headline workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-geometry batched workload")
     ap.add_argument("--no-hex", action="store_true", help="skip the hexagonal core")
     ap.add_argument("--no-aux", action="store_true", help="skip the comparison legs of the headline workload")
@@ -321,6 +327,15 @@ def workload_legs(gt, synth, cfg, n, args, hev, aux):
             legs[name] = track_leg(gt, G, n, seed, cfg, args, prec, args.steps, args.warmup, hev,
                                    **(kw_mixed if name == "mixed" else {}))
             log("cfg%d %s: %.3f ms/step, %d segments" % (cfg, name, mean(legs[name]["ms"]), legs[name]["segments"]))
+    # the paper's comparison trackers on the same workload: static
+    # polymorphism (arrays by index, mixed precision elsewhere) and the
+    # fixed-depth reactor tracker where the geometry has its shape
+    if args.only in (None, "sp") and not args.no_trackers:
+        legs["sp"] = track_leg(gt, G, n, seed, cfg, args, gt.PREC_MIXED, args.steps, args.warmup, hev, tracker="sp")
+        log("cfg%d SP tracker (mixed): %.3f ms/step" % (cfg, mean(legs["sp"]["ms"])))
+    if args.only in (None, "rtk") and not args.no_trackers and G.kinds()[2]:
+        legs["rtk"] = track_leg(gt, G, n, seed, cfg, args, gt.PREC_FP64, args.steps, args.warmup, hev, tracker="rtk")
+        log("cfg%d RTK tracker: %.3f ms/step" % (cfg, mean(legs["rtk"]["ms"])))
     a_steps, a_warm = min(args.aux_steps, args.steps), min(args.warmup, 1)
     if aux and args.only in (None, "plain_fp64"):
         legs["plain_fp64"] = track_leg(gt, G, n, seed, cfg, args, gt.PREC_FP64, a_steps, a_warm, hev,
@@ -615,7 +630,8 @@ def main():
                    "precision": "mixed" if "mixed" in legs else "fp64", "parallelism": "none (1 GPU)",
                    "launch_shape": dict(head["shape"], plan=head.get("plan"), autotuned=tuned_shape is not None)},
     }
-    labels = (("fp64", "fp64"), ("plain_fp64", "plain_fp64_lane_per_history"), ("event", "event_based_mixed"),
+    labels = (("fp64", "fp64"), ("sp", "sp_tracker_mixed"), ("rtk", "rtk_tracker"),
+              ("plain_fp64", "plain_fp64_lane_per_history"), ("event", "event_based_mixed"),
               ("nohint", "mixed_without_lattice_hints"), ("regroup", "mixed_with_regroup"),
               ("mesh", "mixed_with_mesh_tally"))
     for name, label in labels:
@@ -631,6 +647,13 @@ def main():
             line[label] = summary(legs[name], extra)
     if "mixed" in legs and "fp64" in legs:
         line["mixed_over_fp64"] = line["value"] / line["fp64"]["value"]
+    if "mixed" in legs and "rtk" in legs:
+        # the paper's Table 3 ratio (a tracking rate over the RTK rate) on this workload
+        line["st_over_rtk"] = line["value"] / line["rtk_tracker"]["value"]
+        if "sp" in legs:
+            line["sp_over_rtk"] = line["sp_tracker_mixed"]["value"] / line["rtk_tracker"]["value"]
+    if "mixed" in legs and "sp" in legs:
+        line["st_over_sp"] = line["value"] / line["sp_tracker_mixed"]["value"]
     if "mixed" in legs and "plain_fp64" in legs:
         line["mixed_over_plain_fp64"] = line["value"] / line["plain_fp64_lane_per_history"]["value"]
     if "mixed" in legs and "event" in legs:

@@ -97,6 +97,23 @@ extern "C" {
 #define GT_FLAG_NO_TALLY_CACHE 16u     /* persistent schedule: flush a lane's tally partial sum
                                           at every change of instance instead of keeping up
                                           to three more in an LDS cache (speed only)         */
+/* Tracker method of the persistent schedule (default: the single tracker, ST,
+ * of Section "Single tracker (ST) method": every universe is CSG, searched
+ * through its bounding-volume hierarchy).  The two others keep one tracker
+ * type per kind of universe, as the paper's comparison methods do; the
+ * kinds are recognised by gt_geometry_create from the cells themselves
+ * (gt_geometry_kinds).  All three give identical outputs. */
+#define GT_FLAG_TRACKER_SP 32u         /* static polymorphism (Section "Static polymorphism (SP)
+                                          method", Listing 1): a switch on each level's
+                                          universe kind; rectilinear arrays find a cell by
+                                          index and cross to the neighbour by index (Algs. 5
+                                          and 6), other universes use the CSG tracker       */
+#define GT_FLAG_TRACKER_RTK 64u        /* the fixed-depth reactor tracker (Section "RTK
+                                          tracking", Algs. 9 and 10): levels of known kind
+                                          (an optional one-cell root, one or two array
+                                          levels, pins of concentric cylinders and axial
+                                          planes), loops over levels unrolled; GT_EINVAL for
+                                          a geometry not of that shape                       */
 
 typedef struct gt_geometry gt_geometry;   /* opaque; owns its device tables */
 
@@ -155,6 +172,16 @@ int gt_geometry_info(const gt_geometry *g, uint64_t *n_instances, uint32_t *max_
  * the crossing tables (translations, candidate lists), 3 = every table; and
  * the LDS bytes copied per workgroup.  Either output may be NULL. */
 int gt_geometry_staging(const gt_geometry *g, uint32_t precision, uint32_t *kind, uint32_t *lds_bytes);
+
+/* Universe kinds the per-kind trackers see (GT_FLAG_TRACKER_SP / _RTK):
+ * the numbers of universes recognised as rectilinear arrays (nx x ny
+ * pseudo-arrays of cells bounded by x and y planes, local cell j*nx + i,
+ * with the same extra half-spaces in every cell) and as pins (concentric
+ * z-cylinders of one centre and z planes, local cell slab*(cylinders+1) +
+ * ring), and the fixed-depth shape: 0 when GT_FLAG_TRACKER_RTK cannot track
+ * the geometry, else 1 | (one-cell root above the arrays) << 1 | (two array
+ * levels) << 2.  Any output pointer may be NULL. */
+int gt_geometry_kinds(const gt_geometry *g, uint32_t *n_rect, uint32_t *n_pin, uint32_t *rtk_shape);
 
 void gt_geometry_destroy(gt_geometry *g);
 

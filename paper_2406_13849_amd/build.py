@@ -16,7 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgt.so")
-SOURCES = ["gt_geometry.cpp", "gt_tune.cpp", "gt_track.hip"]
+SOURCES = ["gt_geometry.cpp", "gt_tune.cpp", "gt_track.hip", "gt_kinds.hip"]
 ARCH = os.environ.get("GT_OFFLOAD_ARCH", "gfx950")
 
 
@@ -34,16 +34,33 @@ def flags() -> list:
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + flags() + ["-shared", "-x", "hip"] + srcs + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), file=sys.stderr)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libgt.so")
-    os.replace(tmp, LIB)
+    """Compile every source to an object (in parallel: the two kernel
+    translation units take most of the time), then link libgt.so."""
+    import tempfile
+    with tempfile.TemporaryDirectory(prefix="gt_build_") as tmpdir:
+        objs, procs = [], []
+        for s in SOURCES:
+            obj = os.path.join(tmpdir, s + ".o")
+            cmd = [hipcc()] + flags() + ["-c", "-x", "hip", os.path.join(CSRC, s), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), file=sys.stderr)
+            procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+            objs.append(obj)
+        failed = []
+        for s, pr in procs:
+            out, _ = pr.communicate()
+            if pr.returncode != 0:
+                sys.stderr.write(out)
+                failed.append(s)
+        if failed:
+            raise RuntimeError("hipcc failed on " + ", ".join(failed))
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed linking libgt.so")
+        os.replace(tmp, LIB)
     return LIB
 
 

@@ -51,6 +51,13 @@ struct DevT {
     cptr<A, Univ> univ;
     cptr<A, double> sigma;
     cptr<A, uint32_t> cell_local;
+    // universe-kind tables (read only by the trackers that switch on kind;
+    // staged with the per-segment tables in their plans)
+    cptr<A, UArr> uarr;
+    cptr<A, double> aval;
+    cptr<A, uint32_t> asurf;
+    cptr<A, uint32_t> ahs;
+    cptr<A, uint32_t> cell_ij;
     cptr<B, double> trans;
     cptr<B, uint32_t> adj_off;
     cptr<B, uint32_t> adj;
@@ -100,6 +107,11 @@ __device__ __forceinline__ DevGlobal global_view(const Dev &g) {
     d.univ = (cptr<1, Univ>)g.univ;
     d.sigma = (cptr<1, double>)g.sigma;
     d.cell_local = (cptr<1, uint32_t>)g.cell_local;
+    d.uarr = (cptr<1, UArr>)g.uarr;
+    d.aval = (cptr<1, double>)g.aval;
+    d.asurf = (cptr<1, uint32_t>)g.asurf;
+    d.ahs = (cptr<1, uint32_t>)g.ahs;
+    d.cell_ij = (cptr<1, uint32_t>)g.cell_ij;
     d.trans = (cptr<1, double>)g.trans;
     d.adj_off = (cptr<1, uint32_t>)g.adj_off;
     d.adj = (cptr<1, uint32_t>)g.adj;
@@ -272,6 +284,8 @@ __device__ __forceinline__ double plane_distance(uint32_t type, CP c, bool pos, 
 // Written without branches: every case's operands are formed, and the one
 // division takes those of the case that applies, so the quotient is the one
 // the case-by-case formula gives (lanes of a wave often take different cases).
+__device__ __forceinline__ double quad_root(double a, double b, double cc, bool pos, bool on);
+
 template <typename CP>
 __device__ __forceinline__ double quad_distance(uint32_t type, CP c, bool pos, double qx, double qy,
                                                 double qz, double u, double v, double w, bool on) {
@@ -282,6 +296,13 @@ __device__ __forceinline__ double quad_distance(uint32_t type, CP c, bool pos, d
     const double a = cyl ? a2 : a2 + w * w;
     const double b = cyl ? b2 : b2 + dz * w;
     const double cc = cyl ? r2 - c2 : (r2 + dz * dz) - c3;
+    return quad_root(a, b, cc, pos, on);
+}
+
+// The root step of quad_distance from the quadratic's a, b (half the linear
+// coefficient) and c = f(q); shared with the pin tracker, which forms a, b
+// and the squared radius once for all cylinders of a pin.
+__device__ __forceinline__ double quad_root(double a, double b, double cc, bool pos, bool on) {
     const double disc = b * b - a * cc;
     const double q = sqrt(disc > 0.0 ? disc : 0.0);
     double num, den;
@@ -578,6 +599,329 @@ __device__ __forceinline__ int cross(const G &g, Particle &P, int Ls, uint32_t s
     return GT_END_NONE;
 }
 
+// ------------------------------------------------------------------ per-kind trackers
+// The static-polymorphism method (Section "Static polymorphism (SP) method")
+// keeps one tracker type per kind of universe and switches on the kind of
+// each level's universe; the fixed-depth reactor tracker (Section "RTK
+// tracking") knows every level's kind at compile time: an optional one-cell
+// root, one or two levels of rectilinear arrays, then pins.  An array
+// tracker finds a cell by index and crosses to the neighbour by index
+// (Algs. 5 and 6); a pin tracker does the same over rings and axial slabs.
+// Both reach exactly the single tracker's cells: an index along an axis is
+// the number of grid boundaries the coordinate is strictly beyond, taken
+// with the double-precision difference of the half-space test itself, so it
+// names the one cell whose tests all pass.
+enum Tracker : int { TRK_ST = 0, TRK_SP = 1, TRK_RTK = 2 };
+// RTK shapes (the preprocessor's code): bit 1 a one-cell root above the
+// arrays, bit 2 two array levels instead of one
+constexpr int kRtkRootCsg = 2, kRtkTwoArrays = 4;
+__host__ __device__ constexpr int rtk_depth(int shape) {
+    return ((shape & kRtkRootCsg) ? 1 : 0) + ((shape & kRtkTwoArrays) ? 2 : 1) + 1;
+}
+// The kind of level L of the fixed-depth shape.
+__device__ __forceinline__ int rtk_kind(int shape, int L) {
+    const int root = (shape & kRtkRootCsg) ? 1 : 0;
+    const int arrays = (shape & kRtkTwoArrays) ? 2 : 1;
+    return L < root ? kKindCsg : (L < root + arrays ? kKindRect : kKindPin);
+}
+
+// Nearest.entry of a hit on a grid boundary: kArrHit | axis << 28 | p
+// (boundary p separates slabs p - 1 and p); kArrExtra: an extra half-space
+// of a rect universe (its crossing leaves every cell of the array).
+constexpr uint32_t kArrHit = 1u << 31, kArrExtra = kArrHit | (7u << 28);
+
+// Slab of coordinate x over boundaries B[0..n] (ascending, -inf / +inf where
+// absent), from the first guess i: the i in [0, n) with x - B[i] > 0 and not
+// x - B[i+1] > 0; -1 when x is not beyond B[0], n when it is beyond B[n]
+// (bounded ends only).
+template <typename VP>
+__device__ __forceinline__ int slab_of(VP B, int n, double x, int i) {
+    i = min(max(i, 0), n - 1);
+    while (i > 0 && !(x - B[i] > 0.0)) i--;
+    while (i < n - 1 && x - B[i + 1] > 0.0) i++;
+    if (!(x - B[i] > 0.0)) return -1;
+    if (x - B[i + 1] > 0.0) return n;
+    return i;
+}
+
+// The slab a crossing of boundary p leads to, the crossed boundary's sense
+// forced (fpos: beyond it) and every other boundary taken numerically
+// (i_num: the numeric slab of the moved point).  Beyond B_p the only cell
+// that uses B_p is slab p, which holds the point unless it is numerically
+// beyond B_{p+1}; short of B_p it is slab p - 1, unless the point is not
+// beyond B_{p-1}.  -1: no slab.
+__device__ __forceinline__ int forced_slab(int i_num, int p, bool fpos, int n) {
+    const int i = fpos ? (i_num <= p ? p : i_num) : (i_num >= p - 1 ? p - 1 : i_num);
+    return (i >= 0 && i < n) ? i : -1;
+}
+
+// The extra half-spaces every cell of a rect universe has (numeric senses,
+// or the forced sense on surface force_s).
+template <typename G>
+__device__ __forceinline__ bool rect_extras(const G &g, const UArr &A, double x, double y, double z,
+                                            uint32_t force_s, bool force_pos) {
+    for (uint32_t k = 0; k < A.nxhs; k++) {
+        const uint32_t h = g.ahs[A.xhs + k];
+        const uint32_t s = h >> 4, t = h & 7u;
+        const auto c = g.coef + 4 * (size_t)s;
+        const double f = t < ST_CZ ? plane_value(t, c, x, y, z) : quad_value(t, c, x, y, z);
+        const bool pos = s == force_s ? force_pos : f > 0.0;
+        if (pos != (bool)((h >> 3) & 1u)) return false;
+    }
+    return true;
+}
+
+// find_cell in a rect universe (Alg. 5 with the uniform-pitch first guess):
+// the cell (i, j) by index, then the extra half-spaces; -1 if none.
+template <typename G>
+__device__ __forceinline__ int32_t rect_locate(const G &g, const UArr &A, double x, double y, double z) {
+    const auto X = g.aval + A.arr;
+    const auto Y = X + (A.n0 + 1);
+    const int gi = (int)floorf(((float)x - A.x0) * A.inv_px), gj = (int)floorf(((float)y - A.y0) * A.inv_py);
+    const int i = slab_of(X, (int)A.n0, x, gi), j = slab_of(Y, (int)A.n1, y, gj);
+    if (i < 0 || i >= (int)A.n0 || j < 0 || j >= (int)A.n1) return -1;
+    if (A.nxhs && !rect_extras(g, A, x, y, z, kNone, false)) return -1;
+    return (int32_t)(A.cell0 + (uint32_t)j * A.n0 + (uint32_t)i);
+}
+
+// cross_surface in a rect universe (Alg. 6): from cell `old` across the grid
+// boundary named by `entry` (forced sense fpos) to the neighbour by index,
+// the other axis re-checked from the old index; -1 when the crossing leaves
+// the array.
+template <typename G>
+__device__ __forceinline__ int32_t rect_cross(const G &g, const UArr &A, uint32_t old, uint32_t entry, bool fpos,
+                                             double x, double y, double z) {
+    if ((entry & kArrExtra) == kArrExtra) return -1;
+    const auto X = g.aval + A.arr;
+    const auto Y = X + (A.n0 + 1);
+    const uint32_t ij = g.cell_ij[old];
+    int i = (int)(ij & 0xFFFFu), j = (int)(ij >> 16);
+    const int p = (int)(entry & 0x0FFFFFFFu);
+    if (((entry >> 28) & 7u) == 0) {
+        i = forced_slab(slab_of(X, (int)A.n0, x, i), p, fpos, (int)A.n0);
+        j = slab_of(Y, (int)A.n1, y, j);
+    } else {
+        j = forced_slab(slab_of(Y, (int)A.n1, y, j), p, fpos, (int)A.n1);
+        i = slab_of(X, (int)A.n0, x, i);
+    }
+    if (i < 0 || i >= (int)A.n0 || j < 0 || j >= (int)A.n1) return -1;
+    if (A.nxhs && !rect_extras(g, A, x, y, z, kNone, false)) return -1;
+    return (int32_t)(A.cell0 + (uint32_t)j * A.n0 + (uint32_t)i);
+}
+
+// Pin universe: ring and slab of a point.  The ring is the number of
+// cylinders the point is strictly outside, from the one squared radius
+// (x - cx)^2 + (y - cy)^2 every cylinder's test forms; the slab is the
+// number of z planes it is strictly above (binary search).
+template <typename G>
+__device__ __forceinline__ int pin_ring(const G &g, const UArr &A, double x, double y) {
+    const auto R = g.aval + A.arr;
+    const double dx = x - R[A.n0], dy = y - R[A.n0 + 1];
+    const double s2 = dx * dx + dy * dy;
+    int r = 0;
+    while (r < (int)A.n0 && s2 - R[r] > 0.0) r++;
+    return r;
+}
+
+template <typename G>
+__device__ __forceinline__ int pin_slab(const G &g, const UArr &A, double z) {
+    const auto Z = g.aval + A.arr + A.n0 + 2;
+    int lo = 0, hi = (int)A.n1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (z - Z[mid] > 0.0) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename G>
+__device__ __forceinline__ int32_t pin_locate(const G &g, const UArr &A, double x, double y, double z) {
+    return (int32_t)(A.cell0 + (uint32_t)pin_slab(g, A, z) * (A.n0 + 1) + (uint32_t)pin_ring(g, A, x, y));
+}
+
+// Crossing inside a pin: a cylinder (axis 0; boundary p = cylinder + 1) or a
+// z plane (axis 1; boundary p = plane + 1), the other coordinate numeric.
+template <typename G>
+__device__ __forceinline__ int32_t pin_cross(const G &g, const UArr &A, uint32_t entry, bool fpos, double x,
+                                            double y, double z) {
+    const int p = (int)(entry & 0x0FFFFFFFu);
+    int r = pin_ring(g, A, x, y), k = pin_slab(g, A, z);
+    if (((entry >> 28) & 7u) == 0) r = forced_slab(r, p, fpos, (int)A.n0 + 1);
+    else k = forced_slab(k, p, fpos, (int)A.n1 + 1);
+    if (r < 0 || k < 0) return -1;
+    return (int32_t)(A.cell0 + (uint32_t)k * (A.n0 + 1) + (uint32_t)r);
+}
+
+// The nearest-surface bookkeeping shared by the per-kind distance steps:
+// the lexicographic minimum of (distance, level, surface id).
+__device__ __forceinline__ bool nearer(Nearest &r, double d, int L, uint32_t s, bool pos, uint32_t entry) {
+    if (d < r.t || (d == r.t && d != dinf() && L == r.level && s < r.surf)) {
+        r.t = d;
+        r.level = L;
+        r.surf = s;
+        r.pos = pos;
+        r.entry = entry;
+        return true;
+    }
+    return false;
+}
+
+// distance_to_surface of one level that is a CSG cell (the single tracker's
+// loop over the cell's half-spaces: slab pairs, other planes, quadrics).
+template <typename G>
+__device__ __forceinline__ bool csg_level_distance(const G &g, const Particle &P, int L, const Cell &cc, double qx,
+                                                   double qy, double qz, Nearest &r) {
+    const auto hs = g.hs + cc.hs_off;
+    const uint32_t npl = cc.n_pl & kPlaneCountMask, npair2 = 2u * (cc.n_pl >> 12);
+    bool better = false;
+    for (uint32_t k = 0; k < npair2; k += 2) {
+        const uint32_t h0 = hs[k], h1 = hs[k + 1];
+        const double den = plane_den(h0 & 7u, g.coef + 4 * (size_t)(h0 >> 4), P.u, P.v, P.w);
+        const uint32_t kk = den > 0.0 ? k : k + 1;
+        const uint32_t h = den > 0.0 ? h0 : h1;
+        const uint32_t s = h >> 4;
+        const double t = (-plane_value(h & 7u, g.coef + 4 * (size_t)s, qx, qy, qz)) / den;
+        const bool skip = den == 0.0 || (P.on_level == L && P.on_surf == s);
+        const double d = skip ? dinf() : ((t > 0.0) ? t : 0.0);
+        better |= nearer(r, d, L, s, den < 0.0, cc.hs_off + kk);
+    }
+    for (uint32_t k = npair2; k < npl; k++) {
+        const uint32_t h = hs[k];
+        const uint32_t s = h >> 4;
+        const bool pos = (h >> 3) & 1u;
+        if (P.on_level == L && P.on_surf == s) continue;
+        const double d = plane_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w);
+        better |= nearer(r, d, L, s, pos, cc.hs_off + k);
+    }
+    for (uint32_t k = npl; k < cc.n_hs; k++) {
+        const uint32_t h = hs[k];
+        const uint32_t s = h >> 4;
+        const bool pos = (h >> 3) & 1u;
+        const bool on = (P.on_level == L) && (P.on_surf == s);
+        const double d = quad_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w, on);
+        better |= nearer(r, d, L, s, pos, cc.hs_off + k);
+    }
+    return better;
+}
+
+// distance_to_surface of one level that is a rect cell (i, j): the grid
+// plane ahead along x and along y (the same difference and quotient as the
+// plane's half-space), then the extra half-spaces.
+template <typename G>
+__device__ __forceinline__ bool rect_level_distance(const G &g, const Particle &P, int L, const UArr &A,
+                                                    uint32_t c, double qx, double qy, double qz, Nearest &r) {
+    const uint32_t ij = g.cell_ij[c];
+    const int i = (int)(ij & 0xFFFFu), j = (int)(ij >> 16);
+    bool better = false;
+    if (P.u != 0.0) {
+        const uint32_t p = (uint32_t)(P.u > 0.0 ? i + 1 : i);
+        const uint32_t s = g.asurf[A.arr + p];
+        if (s != kLeafNone && !(P.on_level == L && P.on_surf == s)) {
+            const double t = (-(qx - g.aval[A.arr + p])) / P.u;
+            better |= nearer(r, t > 0.0 ? t : 0.0, L, s, P.u < 0.0, kArrHit | p);
+        }
+    }
+    if (P.v != 0.0) {
+        const uint32_t p = (uint32_t)(P.v > 0.0 ? j + 1 : j);
+        const uint32_t at = A.arr + A.n0 + 1 + p;
+        const uint32_t s = g.asurf[at];
+        if (s != kLeafNone && !(P.on_level == L && P.on_surf == s)) {
+            const double t = (-(qy - g.aval[at])) / P.v;
+            better |= nearer(r, t > 0.0 ? t : 0.0, L, s, P.v < 0.0, kArrHit | 1u << 28 | p);
+        }
+    }
+    for (uint32_t k = 0; k < A.nxhs; k++) {
+        const uint32_t h = g.ahs[A.xhs + k];
+        const uint32_t s = h >> 4;
+        const bool pos = (h >> 3) & 1u;
+        const bool on = (P.on_level == L) && (P.on_surf == s);
+        const auto cf = g.coef + 4 * (size_t)s;
+        double d;
+        if ((h & 7u) < ST_CZ) d = on ? dinf() : plane_distance(h & 7u, cf, pos, qx, qy, qz, P.u, P.v, P.w);
+        else d = quad_distance(h & 7u, cf, pos, qx, qy, qz, P.u, P.v, P.w, on);
+        better |= nearer(r, d, L, s, pos, kArrExtra);
+    }
+    return better;
+}
+
+// distance_to_surface of one level that is a pin cell (ring, slab): the
+// bounding cylinders (a, b and the squared radius formed once) and the z
+// plane ahead.
+template <typename G>
+__device__ __forceinline__ bool pin_level_distance(const G &g, const Particle &P, int L, const UArr &A,
+                                                   uint32_t c, double qx, double qy, double qz, Nearest &r) {
+    const uint32_t rk = g.cell_ij[c];
+    const int ring = (int)(rk & 0xFFFFu), slab = (int)(rk >> 16);
+    const auto R = g.aval + A.arr;
+    const double dx = qx - R[A.n0], dy = qy - R[A.n0 + 1];
+    const double a2 = P.u * P.u + P.v * P.v, b2 = dx * P.u + dy * P.v, r2 = dx * dx + dy * dy;
+    bool better = false;
+    if (ring > 0) {
+        const uint32_t m = (uint32_t)ring - 1, s = g.asurf[A.arr + m];
+        const bool on = (P.on_level == L) && (P.on_surf == s);
+        better |= nearer(r, quad_root(a2, b2, r2 - R[m], true, on), L, s, true, kArrHit | (m + 1));
+    }
+    if (ring < (int)A.n0) {
+        const uint32_t m = (uint32_t)ring, s = g.asurf[A.arr + m];
+        const bool on = (P.on_level == L) && (P.on_surf == s);
+        better |= nearer(r, quad_root(a2, b2, r2 - R[m], false, on), L, s, false, kArrHit | (m + 1));
+    }
+    if (P.w != 0.0) {
+        const int p = P.w > 0.0 ? slab + 1 : slab;
+        if (p >= 1 && p <= (int)A.n1) {
+            const uint32_t at = A.arr + A.n0 + 2 + (uint32_t)p - 1;
+            const uint32_t s = g.asurf[at];
+            if (!(P.on_level == L && P.on_surf == s)) {
+                const double t = (-(qz - g.aval[at])) / P.w;
+                better |= nearer(r, t > 0.0 ? t : 0.0, L, s, P.w < 0.0, kArrHit | 1u << 28 | (uint32_t)p);
+            }
+        }
+    }
+    return better;
+}
+
+// distance_to_surface over every level for the trackers that switch on
+// universe kind (SP: the kind read per level; RTK: the shape's kind of the
+// level), with what the segment step needs (as nearest_surface).
+template <int TRK, int SHAPE, typename G>
+__device__ __forceinline__ void nearest_surface_kinds(const G &g, const Particle &P, Nearest &r) {
+    r.t = dinf();
+    r.level = GT_MAX_LEVELS;
+    r.surf = kNone;
+    r.entry = 0;
+    r.pos = false;
+    r.univ = g.root;
+    r.inst = 0;
+    double qx = P.x, qy = P.y, qz = P.z;
+    uint32_t univ = g.root;
+    int32_t fill = 0;
+    for (int L = 0; L < P.depth; L++) {
+        const uint32_t c = lvl(P, L);
+        if (L > 0) {
+            const auto t = g.trans + 4 * (size_t)lvl(P, L - 1);
+            qx = qx - t[0];
+            qy = qy - t[1];
+            qz = qz - t[2];
+            univ = (uint32_t)(-fill - 1);
+        }
+        const Cell cc = ldv<Cell>(g.cell + c);
+        fill = cc.fill;
+        r.inst += cc.inst_off;
+        const int kind = TRK == TRK_RTK ? rtk_kind(SHAPE, L) : g.uarr[univ].kind;
+        bool better;
+        if (kind == kKindRect) {
+            better = rect_level_distance(g, P, L, ldv<UArr>(g.uarr + univ), c, qx, qy, qz, r);
+        } else if (TRK == TRK_RTK && kind == kKindPin) {
+            better = pin_level_distance(g, P, L, ldv<UArr>(g.uarr + univ), c, qx, qy, qz, r);
+        } else {
+            better = csg_level_distance(g, P, L, cc, qx, qy, qz, r);
+        }
+        if (better) r.univ = univ;
+    }
+    r.leaf_fill = fill;
+}
+
 // ------------------------------------------------------------------ tallies
 // Segment lengths are summed as 128-bit integers in units of 2^-96 cm.  In
 // the kernel a contribution is split into four 32-bit limbs, each added to
@@ -597,10 +941,13 @@ struct TallyAcc {
     uint64_t lo, hi;   // 128-bit register accumulator for consecutive segments in one instance
 };
 
+// Agent scope: workgroups on every compute unit of the XCD add into one
+// replica (on gfx950 this is the same global_atomic_add_x2, with no cache
+// bits, as at workgroup scope).
 __device__ __forceinline__ void add_limb(uint64_t *p, uint64_t v) {
     if (v) __hip_atomic_fetch_add((GT_AS(1) unsigned long long *)p, (unsigned long long)v,
                                   __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+                                  __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void tally_flush(uint64_t *rep, TallyAcc &a) {
@@ -982,6 +1329,19 @@ __device__ __forceinline__ typename ViewOf<KIND>::type make_view(const Dev &g, c
         d.univ = (cptr<3, Univ>)lp(SEC_UNIV);
         d.sigma = (cptr<3, double>)lp(SEC_SIGMA);
         d.cell_local = (cptr<3, uint32_t>)lp(SEC_LOCAL);
+        if (sp.at[SEC_UARR] != 0xFFFFFFFFu) {
+            d.uarr = (cptr<3, UArr>)lp(SEC_UARR);
+            d.aval = (cptr<3, double>)lp(SEC_AVAL);
+            d.asurf = (cptr<3, uint32_t>)lp(SEC_ASURF);
+            d.ahs = (cptr<3, uint32_t>)lp(SEC_AHS);
+            d.cell_ij = (cptr<3, uint32_t>)lp(SEC_IJ);
+        } else {
+            // a plan without the universe-kind tables (the single tracker's):
+            // never read through these
+            d.uarr = nullptr;
+            d.aval = nullptr;
+            d.asurf = d.ahs = d.cell_ij = nullptr;
+        }
         if constexpr (KIND == SK_SPLIT) {
             d.trans = (cptr<1, double>)g.trans;
             d.adj_off = (cptr<1, uint32_t>)g.adj_off;
@@ -1068,7 +1428,8 @@ struct TailCfg {
 // The persistent history loop of one lane (see above); returns when its
 // wave has drained the queue and every lane of the wave is idle (with tail
 // compaction: when no lane of the workgroup has a history left).
-template <int PREC, bool RG = false, bool MESH = false, typename G, typename Queue>
+template <int PREC, bool RG = false, bool MESH = false, int TRK = TRK_ST, int SHAPE = 0, typename G,
+          typename Queue>
 __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const KOut &o, uint64_t *rep,
                                            uint32_t *cells, const Queue &queue, Counts &cnt, const TailCfg &tc,
                                            const TallyCache &tcache) {
@@ -1364,8 +1725,11 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
             }
         }
 
-        // ---- up to kSearchLevels levels of find_cell / cross_surface
-        for (int sn = 0; sn < kSearchLevels && mode == M_SEARCH && end == GT_END_NONE; sn++) {
+        // ---- up to kSearchLevels levels of find_cell / cross_surface (the
+        // fixed-depth tracker: every level, its loops over levels unrolled)
+        constexpr int kLevelsPerTrip = TRK == TRK_RTK ? rtk_depth(SHAPE) : kSearchLevels;
+#pragma unroll
+        for (int sn = 0; sn < kLevelsPerTrip && mode == M_SEARCH && end == GT_END_NONE; sn++) {
             // local position and universe at level sL (translations applied
             // level by level from the global position, as in the descent)
             double qx = P.x, qy = P.y, qz = P.z;
@@ -1378,33 +1742,56 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
                 qz = qz - t[2];
                 su = (uint32_t)(-g.cell[cl].fill - 1);
             }
-            // quick candidates first: after a crossing, the cells listed for the
-            // crossed half-space; in a descent, the cell with the same index in
-            // the new universe as the lane had at this level before
-            uint32_t k0, k1, hint = 0;
-            int32_t excl = -1;
-            if (sforce != kNone) {
-                k0 = g.adj_off[sk];
-                k1 = g.adj_off[sk + 1];
-                excl = (int32_t)lvl(P, sL);   // the cell being left
-            } else {
-                const uint32_t loc = g.cell_local[lvl(P, sL)];
-                const Univ U = ldv<Univ>(g.univ + su);
-                hint = U.cell0 + loc;
-                k0 = 0;
-                k1 = loc < U.ncell ? 1u : 0u;
-            }
             int32_t c = -1, fill = 0;
-            for (uint32_t k = k0; k < k1; k++) {
-                const uint32_t d = sforce != kNone ? g.adj[k] : hint;
-                if (contains(g, d, qx, qy, qz, sforce, sfpos, fill)) { c = (int32_t)d; break; }
+            bool by_kind = false;
+            if constexpr (TRK != TRK_ST) {
+                // the tracker of this level's kind: arrays and pins by index; the
+                // fixed-depth tracker's one-cell root by its containment test
+                // (a crossing of its boundary leaves the geometry)
+                const int kind = TRK == TRK_RTK ? rtk_kind(SHAPE, sL) : g.uarr[su].kind;
+                if (kind == kKindRect || (TRK == TRK_RTK && kind == kKindPin)) {
+                    by_kind = true;
+                    const UArr A = ldv<UArr>(g.uarr + su);
+                    if (kind == kKindRect)
+                        c = sforce != kNone ? rect_cross(g, A, lvl(P, sL), sk, sfpos, qx, qy, qz)
+                                            : rect_locate(g, A, qx, qy, qz);
+                    else
+                        c = sforce != kNone ? pin_cross(g, A, sk, sfpos, qx, qy, qz) : pin_locate(g, A, qx, qy, qz);
+                    if (c >= 0) fill = g.cell[c].fill;
+                } else if (TRK == TRK_RTK) {
+                    by_kind = true;
+                    const uint32_t c0 = g.uarr[su].cell0;
+                    if (sforce == kNone && contains(g, c0, qx, qy, qz, kNone, false, fill)) c = (int32_t)c0;
+                }
             }
-            // the full search; after a crossing its lattice guess is taken a
-            // little along the flight, so that it lands on the far side
-            if (c < 0) {
-                const float nu = sforce != kNone ? (float)P.u * 1e-3f : 0.0f;
-                const float nv = sforce != kNone ? (float)P.v * 1e-3f : 0.0f;
-                c = search<PREC>(g, su, qx, qy, qz, sforce, sfpos, excl, nu, nv, fill);
+            if (!by_kind) {
+                // quick candidates first: after a crossing, the cells listed for the
+                // crossed half-space; in a descent, the cell with the same index in
+                // the new universe as the lane had at this level before
+                uint32_t k0, k1, hint = 0;
+                int32_t excl = -1;
+                if (sforce != kNone) {
+                    k0 = g.adj_off[sk];
+                    k1 = g.adj_off[sk + 1];
+                    excl = (int32_t)lvl(P, sL);   // the cell being left
+                } else {
+                    const uint32_t loc = g.cell_local[lvl(P, sL)];
+                    const Univ U = ldv<Univ>(g.univ + su);
+                    hint = U.cell0 + loc;
+                    k0 = 0;
+                    k1 = loc < U.ncell ? 1u : 0u;
+                }
+                for (uint32_t k = k0; k < k1; k++) {
+                    const uint32_t d = sforce != kNone ? g.adj[k] : hint;
+                    if (contains(g, d, qx, qy, qz, sforce, sfpos, fill)) { c = (int32_t)d; break; }
+                }
+                // the full search; after a crossing its lattice guess is taken a
+                // little along the flight, so that it lands on the far side
+                if (c < 0) {
+                    const float nu = sforce != kNone ? (float)P.u * 1e-3f : 0.0f;
+                    const float nv = sforce != kNone ? (float)P.v * 1e-3f : 0.0f;
+                    c = search<PREC>(g, su, qx, qy, qz, sforce, sfpos, excl, nu, nv, fill);
+                }
             }
             if (c < 0) {
                 if (birth) {
@@ -1434,7 +1821,8 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
         // ---- one segment: distance_to_surface, move, tally, then crossing or collision
         if (mode == M_TRACK && end == GT_END_NONE) {
             Nearest nr;
-            nearest_surface(g, P, nr);
+            if constexpr (TRK == TRK_ST) nearest_surface(g, P, nr);
+            else nearest_surface_kinds<TRK, SHAPE>(g, P, nr);
             const double sig = g.sigma[nr.leaf_fill];
             const double sc = (p.source == 1) ? dinf() : P.tau / sig;
             const uint32_t inst = nr.inst;
@@ -1506,6 +1894,22 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
         c.hi = tcache.hi[e * tcache.stride];
         tally_flush(rep, c);
     }
+}
+
+// A workgroup's end counts, summed in LDS, then one atomic per counter.
+__device__ __forceinline__ void add_counts(const Counts &c, uint64_t *counters) {
+    __shared__ unsigned long long sh[7];
+    if (threadIdx.x < 7) sh[threadIdx.x] = 0;
+    __syncthreads();
+    if (c.escaped) atomicAdd(&sh[GT_CNT_ESCAPED], (unsigned long long)c.escaped);
+    if (c.capped) atomicAdd(&sh[GT_CNT_CAPPED], (unsigned long long)c.capped);
+    if (c.lost) atomicAdd(&sh[GT_CNT_LOST], (unsigned long long)c.lost);
+    if (c.segcap) atomicAdd(&sh[GT_CNT_SEGCAP], (unsigned long long)c.segcap);
+    if (c.recovf) atomicAdd(&sh[GT_CNT_REC_OVERFLOW], (unsigned long long)c.recovf);
+    if (c.segments) atomicAdd(&sh[GT_CNT_SEGMENTS], (unsigned long long)c.segments);
+    if (c.rejected) atomicAdd(&sh[GT_CNT_REJECTED], (unsigned long long)c.rejected);
+    __syncthreads();
+    if (threadIdx.x < 7 && sh[threadIdx.x]) atomicAdd((unsigned long long *)&counters[threadIdx.x], sh[threadIdx.x]);
 }
 
 // ------------------------------------------------------------------ event-based schedule

@@ -115,6 +115,12 @@ struct Builder {
     std::vector<uint32_t> leaf;
     std::vector<Univ> univ;
 
+    // universe kinds for the trackers that switch on them (see UArr)
+    std::vector<UArr> uarr;
+    std::vector<double> aval;
+    std::vector<uint32_t> asurf, ahs, cell_ij;
+    uint32_t rtk_shape = 0;
+
     uint32_t surf_of(int32_t h) const { return (uint32_t)(h < 0 ? -(int64_t)h : h) - 1; }
 
     int validate() {
@@ -379,6 +385,201 @@ struct Builder {
         return idx;
     }
 
+    // A square-hinted universe whose cells are exactly an nx x ny pseudo-array
+    // (see UArr): fills the rect entry and returns true.
+    bool detect_rect(uint32_t u) {
+        const gt_flat_geometry &F = *f;
+        if (!F.lattice_hint || F.lattice_hint[8 * (size_t)u] != 1) return false;
+        const uint32_t nx = (uint32_t)F.lattice_hint[8 * (size_t)u + 1], ny = (uint32_t)F.lattice_hint[8 * (size_t)u + 2];
+        const uint32_t c0 = F.univ_cell_off[u];
+        if (nx < 1 || ny < 1 || nx > 4096 || ny > 4096 || (uint64_t)nx * ny != F.univ_cell_off[u + 1] - c0) return false;
+        const int64_t kAbsent = -1;
+        std::vector<int64_t> lox(nx, -2), upx(nx, -2), loy(ny, -2), upy(ny, -2);
+        std::vector<int32_t> extra_ref;
+        for (uint32_t j = 0; j < ny; j++)
+            for (uint32_t i = 0; i < nx; i++) {
+                const uint32_t c = c0 + j * nx + i;
+                int64_t lx = kAbsent, ux = kAbsent, ly = kAbsent, uy = kAbsent;
+                std::vector<int32_t> extra;
+                for (uint32_t k = F.cell_hs_off[c]; k < F.cell_hs_off[c + 1]; k++) {
+                    const int32_t h = F.hs[k];
+                    const uint32_t sf = surf_of(h);
+                    const uint32_t t = F.surf_type[sf];
+                    int64_t *slot = nullptr;
+                    if (t == ST_PX) slot = h > 0 ? &lx : &ux;
+                    else if (t == ST_PY) slot = h > 0 ? &ly : &uy;
+                    if (!slot) { extra.push_back(h); continue; }
+                    if (*slot != kAbsent) return false;   // two planes bound one side
+                    *slot = sf;
+                }
+                std::sort(extra.begin(), extra.end());
+                if (c == c0) extra_ref = extra;
+                else if (extra != extra_ref) return false;
+                if ((j > 0 && (lox[i] != lx || upx[i] != ux)) || (i > 0 && (loy[j] != ly || upy[j] != uy))) return false;
+                lox[i] = lx; upx[i] = ux; loy[j] = ly; upy[j] = uy;
+            }
+        auto grid = [&](const std::vector<int64_t> &lo, const std::vector<int64_t> &up, uint32_t n,
+                        std::vector<double> &v, std::vector<uint32_t> &sid) {
+            for (uint32_t i = 0; i + 1 < n; i++)
+                if (up[i] == kAbsent || up[i] != lo[i + 1]) return false;
+            v.assign(n + 1, 0.0);
+            sid.assign(n + 1, kLeafNone);
+            for (uint32_t k = 0; k <= n; k++) {
+                const int64_t sf = k < n ? lo[k] : up[n - 1];
+                if (sf == kAbsent) {
+                    if (k != 0 && k != n) return false;
+                    v[k] = k == 0 ? -INFINITY : INFINITY;
+                } else {
+                    v[k] = F.surf_coef[8 * (size_t)sf];
+                    sid[k] = (uint32_t)sf;
+                }
+            }
+            for (uint32_t k = 0; k < n; k++)
+                if (!(v[k] < v[k + 1])) return false;
+            return true;
+        };
+        std::vector<double> vx, vy;
+        std::vector<uint32_t> sx, sy;
+        if (!grid(lox, upx, nx, vx, sx) || !grid(loy, upy, ny, vy, sy)) return false;
+        UArr &A = uarr[u];
+        A.kind = kKindRect;
+        A.x0 = (float)F.lattice_hint[8 * (size_t)u + 3];
+        A.y0 = (float)F.lattice_hint[8 * (size_t)u + 4];
+        A.inv_px = (float)(1.0 / F.lattice_hint[8 * (size_t)u + 5]);
+        A.inv_py = (float)(1.0 / F.lattice_hint[8 * (size_t)u + 6]);
+        A.arr = (uint32_t)aval.size();
+        A.n0 = nx;
+        A.n1 = ny;
+        aval.insert(aval.end(), vx.begin(), vx.end());
+        aval.insert(aval.end(), vy.begin(), vy.end());
+        asurf.insert(asurf.end(), sx.begin(), sx.end());
+        asurf.insert(asurf.end(), sy.begin(), sy.end());
+        A.xhs = (uint32_t)ahs.size();
+        A.nxhs = (uint32_t)extra_ref.size();
+        for (int32_t h : extra_ref) {
+            const uint32_t sf = surf_of(h);
+            ahs.push_back(hs_pack(sf, h > 0, F.surf_type[sf]));
+        }
+        for (uint32_t j = 0; j < ny; j++)
+            for (uint32_t i = 0; i < nx; i++) cell_ij[c0 + j * nx + i] = i | j << 16;
+        return true;
+    }
+
+    // A universe of concentric z-cylinders (one centre) and z planes whose
+    // cells are exactly the (slab, ring) regions in the order of UArr.
+    bool detect_pin(uint32_t u) {
+        const gt_flat_geometry &F = *f;
+        const uint32_t c0 = F.univ_cell_off[u], nc = F.univ_cell_off[u + 1] - c0;
+        std::vector<uint32_t> cyl, zp;
+        for (uint32_t c = c0; c < c0 + nc; c++)
+            for (uint32_t k = F.cell_hs_off[c]; k < F.cell_hs_off[c + 1]; k++) {
+                const uint32_t sf = surf_of(F.hs[k]);
+                const uint32_t t = F.surf_type[sf];
+                if (t == ST_CZ) cyl.push_back(sf);
+                else if (t == ST_PZ) zp.push_back(sf);
+                else return false;
+            }
+        std::sort(cyl.begin(), cyl.end());
+        cyl.erase(std::unique(cyl.begin(), cyl.end()), cyl.end());
+        std::sort(zp.begin(), zp.end());
+        zp.erase(std::unique(zp.begin(), zp.end()), zp.end());
+        if (cyl.empty() || cyl.size() > 64 || zp.size() > 4096) return false;
+        const double *q0 = F.surf_coef + 8 * (size_t)cyl[0];
+        for (uint32_t sf : cyl)
+            if (std::memcmp(F.surf_coef + 8 * (size_t)sf, q0, 2 * sizeof(double)) != 0) return false;
+        auto coef = [&](uint32_t sf, int k) { return F.surf_coef[8 * (size_t)sf + k]; };
+        std::sort(cyl.begin(), cyl.end(), [&](uint32_t a, uint32_t b) { return coef(a, 2) < coef(b, 2); });
+        std::sort(zp.begin(), zp.end(), [&](uint32_t a, uint32_t b) { return coef(a, 0) < coef(b, 0); });
+        for (size_t k = 0; k + 1 < cyl.size(); k++)
+            if (!(coef(cyl[k], 2) < coef(cyl[k + 1], 2))) return false;
+        for (size_t k = 0; k + 1 < zp.size(); k++)
+            if (!(coef(zp[k], 0) < coef(zp[k + 1], 0))) return false;
+        const uint32_t nr = (uint32_t)cyl.size() + 1, ns = (uint32_t)zp.size() + 1;
+        if ((uint64_t)nr * ns != nc) return false;
+        for (uint32_t k = 0; k < ns; k++)
+            for (uint32_t r = 0; r < nr; r++) {
+                const uint32_t c = c0 + k * nr + r;
+                std::vector<int32_t> want, have(F.hs + F.cell_hs_off[c], F.hs + F.cell_hs_off[c + 1]);
+                if (r > 0) want.push_back((int32_t)cyl[r - 1] + 1);
+                if (r + 1 < nr) want.push_back(-((int32_t)cyl[r] + 1));
+                if (k > 0) want.push_back((int32_t)zp[k - 1] + 1);
+                if (k + 1 < ns) want.push_back(-((int32_t)zp[k] + 1));
+                std::sort(want.begin(), want.end());
+                std::sort(have.begin(), have.end());
+                if (want != have) return false;
+            }
+        UArr &A = uarr[u];
+        A.kind = kKindPin;
+        A.arr = (uint32_t)aval.size();
+        A.n0 = (uint32_t)cyl.size();
+        A.n1 = (uint32_t)zp.size();
+        for (uint32_t sf : cyl) { aval.push_back(coef(sf, 2)); asurf.push_back(sf); }
+        aval.push_back(q0[0]);
+        aval.push_back(q0[1]);
+        asurf.push_back(kLeafNone);
+        asurf.push_back(kLeafNone);
+        for (uint32_t sf : zp) { aval.push_back(coef(sf, 0)); asurf.push_back(sf); }
+        for (uint32_t k = 0; k < ns; k++)
+            for (uint32_t r = 0; r < nr; r++) cell_ij[c0 + k * nr + r] = r | k << 16;
+        return true;
+    }
+
+    // The fixed-depth reactor shape (Section "RTK tracking"): an optional root
+    // of one cell filled with a rect universe, then one or two levels of rect
+    // universes every cell of which is filled, then pin universes of
+    // material cells.  Returns 1 | root_csg << 1 | (rect levels - 1) << 2,
+    // or 0 when the geometry is not of that shape.
+    uint32_t detect_rtk_shape() const {
+        const gt_flat_geometry &F = *f;
+        std::vector<uint32_t> level = {F.root};
+        uint32_t root_csg = 0, nrect = 0;
+        auto daughters = [&](const std::vector<uint32_t> &us, std::vector<uint32_t> &out) {
+            out.clear();
+            for (uint32_t u : us)
+                for (uint32_t c = F.univ_cell_off[u]; c < F.univ_cell_off[u + 1]; c++) {
+                    if (F.cell_fill[c] >= 0) return false;
+                    out.push_back((uint32_t)(-(int64_t)F.cell_fill[c] - 1));
+                }
+            std::sort(out.begin(), out.end());
+            out.erase(std::unique(out.begin(), out.end()), out.end());
+            return true;
+        };
+        std::vector<uint32_t> next;
+        if (uarr[F.root].kind == kKindCsg) {
+            if (F.univ_cell_off[F.root + 1] - F.univ_cell_off[F.root] != 1) return 0;
+            if (!daughters(level, next)) return 0;
+            level = next;
+            root_csg = 1;
+        }
+        for (;;) {
+            for (uint32_t u : level)
+                if (uarr[u].kind != kKindRect) goto leaf;
+            if (++nrect > 2) return 0;
+            if (!daughters(level, next)) return 0;
+            level = next;
+        }
+    leaf:
+        if (nrect == 0) return 0;
+        for (uint32_t u : level) {
+            if (uarr[u].kind != kKindPin) return 0;
+            for (uint32_t c = F.univ_cell_off[u]; c < F.univ_cell_off[u + 1]; c++)
+                if (F.cell_fill[c] < 0) return 0;
+        }
+        return 1u | root_csg << 1 | (nrect - 1) << 2;
+    }
+
+    void kinds() {
+        const gt_flat_geometry &F = *f;
+        uarr.assign(F.n_universes, UArr{});
+        cell_ij.assign(F.n_cells, 0);
+        for (uint32_t u = 0; u < F.n_universes; u++) {
+            uarr[u].kind = kKindCsg;
+            uarr[u].cell0 = F.univ_cell_off[u];
+            if (!detect_rect(u)) detect_pin(u);
+        }
+        rtk_shape = detect_rtk_shape();
+    }
+
     int hierarchies() {
         const gt_flat_geometry &F = *f;
         univ.assign(F.n_universes, Univ{});
@@ -445,6 +646,7 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         if (rc) return rc;
         rc = B.hierarchies();
         if (rc) return rc;
+        B.kinds();
         const gt_flat_geometry &F = *f;
         // host images of every table
         std::vector<double> coef(4 * (size_t)F.n_surfaces, 0.0);
@@ -582,12 +784,18 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         sz[SEC_ADJOFF] = adj_off.size() * 4;
         sz[SEC_ADJ] = adj.size() * 4;
         sz[SEC_LOCAL] = cell_local.size() * 4;
+        sz[SEC_UARR] = B.uarr.size() * sizeof(UArr);
+        sz[SEC_AVAL] = B.aval.size() * 8;
+        sz[SEC_ASURF] = B.asurf.size() * 4;
+        sz[SEC_AHS] = B.ahs.size() * 4;
+        sz[SEC_IJ] = B.cell_ij.size() * 4;
         size_t total = 0;
         for (int i = 0; i < SEC_COUNT; i++) { off[i] = total; total = align_up(total + std::max(sz[i], (size_t)16)); }
         std::vector<unsigned char> img(total, 0);
         const void *src[SEC_COUNT] = {coef.data(), hs.data(), cell.data(), trans.data(), B.univ.data(),
                                       B.n32.data(), B.n64.data(), B.leaf.data(), cb.data(), F.sigma_t,
-                                      adj_off.data(), adj.data(), cell_local.data()};
+                                      adj_off.data(), adj.data(), cell_local.data(), B.uarr.data(),
+                                      B.aval.data(), B.asurf.data(), B.ahs.data(), B.cell_ij.data()};
         for (int i = 0; i < SEC_COUNT; i++)
             if (sz[i]) std::memcpy(img.data() + off[i], src[i], sz[i]);
         int dev = 0;
@@ -624,6 +832,11 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         g->dev.adj_off = (const uint32_t *)(base + off[SEC_ADJOFF]);
         g->dev.adj = (const uint32_t *)(base + off[SEC_ADJ]);
         g->dev.cell_local = (const uint32_t *)(base + off[SEC_LOCAL]);
+        g->dev.uarr = (const UArr *)(base + off[SEC_UARR]);
+        g->dev.aval = (const double *)(base + off[SEC_AVAL]);
+        g->dev.asurf = (const uint32_t *)(base + off[SEC_ASURF]);
+        g->dev.ahs = (const uint32_t *)(base + off[SEC_AHS]);
+        g->dev.cell_ij = (const uint32_t *)(base + off[SEC_IJ]);
         g->dev.root = F.root;
         g->dev.n_inst = (uint32_t)B.ninst[F.root];
         g->dev.max_depth = B.depth[F.root];
@@ -634,11 +847,16 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         // fit, then the crossing tables (translations, candidate lists) if
         // those fit too, then as many hierarchy tables as fit; whatever is not
         // copied is read from global memory
-        static const int kTierA[] = {SEC_CELL, SEC_HS, SEC_COEF, SEC_UNIV, SEC_SIGMA, SEC_LOCAL};
+        // (the plans for the trackers that switch on universe kind count the
+        // universe-kind tables among the per-segment ones)
+        static const int kTierA[] = {SEC_CELL, SEC_HS, SEC_COEF, SEC_UNIV, SEC_SIGMA, SEC_LOCAL,
+                                     SEC_UARR, SEC_AVAL, SEC_ASURF, SEC_AHS, SEC_IJ};
         static const int kTierB[] = {SEC_TRANS, SEC_ADJOFF, SEC_ADJ};
         const uint64_t budget = stage_budget();
-        for (int prec = 0; prec < 2; prec++) {
-            StagePlan &P = g->stage[prec];
+        for (int plan = 0; plan < 4; plan++) {
+            const int prec = plan & 1;
+            const bool arr = plan >= 2;
+            StagePlan &P = arr ? g->stage_arr[prec] : g->stage[prec];
             std::memset(&P, 0, sizeof P);
             for (int i = 0; i < SEC_COUNT; i++) P.at[i] = 0xFFFFFFFFu;
             uint64_t at = 0;
@@ -651,11 +869,12 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
                 P.n++;
                 at += bytes(i);
             };
+            const int n_tier_a = arr ? 11 : 6;
             uint64_t need_a = 0, need_b = 0;
-            for (int i : kTierA) need_a += bytes(i);
+            for (int k = 0; k < n_tier_a; k++) need_a += bytes(kTierA[k]);
             for (int i : kTierB) need_b += bytes(i);
             if (need_a <= budget) {
-                for (int i : kTierA) add(i);
+                for (int k = 0; k < n_tier_a; k++) add(kTierA[k]);
                 P.kind = 1;
                 if (need_a + need_b <= budget) {
                     for (int i : kTierB) add(i);
@@ -678,6 +897,8 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         desc.dev = g->dev;
         desc.stage[0] = g->stage[0];
         desc.stage[1] = g->stage[1];
+        desc.stage_arr[0] = g->stage_arr[0];
+        desc.stage_arr[1] = g->stage_arr[1];
         e = hipMemcpy(base + desc_at, &desc, sizeof desc, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             (void)hipFree(blob);
@@ -694,6 +915,12 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         g->n_inst = B.ninst[F.root];
         g->max_depth = B.depth[F.root];
         g->device = dev;
+        g->rtk_shape = B.rtk_shape;
+        g->n_rect = g->n_pin = 0;
+        for (const UArr &A : B.uarr) {
+            g->n_rect += A.kind == kKindRect;
+            g->n_pin += A.kind == kKindPin;
+        }
         *out = g;
         return GT_OK;
     } catch (const std::bad_alloc &) {
@@ -717,6 +944,14 @@ extern "C" int gt_geometry_staging(const gt_geometry *g, uint32_t precision, uin
     if (precision > GT_PREC_MIXED) return set_error("gt_geometry_staging: unknown precision %u", precision), GT_EINVAL;
     if (kind) *kind = g->stage[precision].kind;
     if (lds_bytes) *lds_bytes = g->stage[precision].total;
+    return GT_OK;
+}
+
+extern "C" int gt_geometry_kinds(const gt_geometry *g, uint32_t *n_rect, uint32_t *n_pin, uint32_t *rtk_shape) {
+    if (!g) return set_error("gt_geometry_kinds: null geometry"), GT_EINVAL;
+    if (n_rect) *n_rect = g->n_rect;
+    if (n_pin) *n_pin = g->n_pin;
+    if (rtk_shape) *rtk_shape = g->rtk_shape;
     return GT_OK;
 }
 
@@ -782,8 +1017,19 @@ int gt::check_track_args(const gt_geometry *g, const gt_track_params *p, const g
     if (p->record_first_k && (!o->rec || p->record_cap < 1))
         return set_error("gt_track: recording needs rec and record_cap >= 1"), GT_EINVAL;
     if (p->flags & ~(GT_FLAG_ACCUMULATE | GT_FLAG_LANE_PER_HISTORY | GT_FLAG_NO_STAGING | GT_FLAG_TAIL_COMPACTION |
-                     GT_FLAG_NO_TALLY_CACHE))
+                     GT_FLAG_NO_TALLY_CACHE | GT_FLAG_TRACKER_SP | GT_FLAG_TRACKER_RTK))
         return set_error("gt_track: unknown flags 0x%x", p->flags), GT_EINVAL;
+    if (p->flags & (GT_FLAG_TRACKER_SP | GT_FLAG_TRACKER_RTK)) {
+        if ((p->flags & GT_FLAG_TRACKER_SP) && (p->flags & GT_FLAG_TRACKER_RTK))
+            return set_error("gt_track: GT_FLAG_TRACKER_SP and GT_FLAG_TRACKER_RTK exclude each other"), GT_EINVAL;
+        if (p->flags & GT_FLAG_LANE_PER_HISTORY)
+            return set_error("gt_track: the SP and RTK trackers run on the persistent schedule only"), GT_EINVAL;
+        if (p->regroup_every)
+            return set_error("gt_track: regroup_every is not available with the SP and RTK trackers"), GT_EINVAL;
+        if ((p->flags & GT_FLAG_TRACKER_RTK) && !g->rtk_shape)
+            return set_error("gt_track: the geometry is not of the fixed-depth reactor shape (GT_FLAG_TRACKER_RTK)"),
+                   GT_EINVAL;
+    }
     if (p->block_size && (p->block_size % 64 || p->block_size > 1024))
         return set_error("gt_track: block_size must be a multiple of 64 up to 1024"), GT_EINVAL;
     if (p->refill_min > 64) return set_error("gt_track: refill_min must be at most 64"), GT_EINVAL;
@@ -844,6 +1090,8 @@ extern "C" int gt_track_mesh(const gt_geometry *g, const gt_track_params *p, con
     if (p->flags & GT_FLAG_LANE_PER_HISTORY)
         return set_error("gt_track_mesh: the mesh tally needs the persistent schedule"), GT_EINVAL;
     if (p->regroup_every) return set_error("gt_track_mesh: regroup_every must be 0"), GT_EINVAL;
+    if (p->flags & (GT_FLAG_TRACKER_SP | GT_FLAG_TRACKER_RTK))
+        return set_error("gt_track_mesh: the mesh tally runs with the single tracker only"), GT_EINVAL;
     if (m->reserved) return set_error("gt_track_mesh: reserved must be 0"), GT_EINVAL;
     uint64_t bins = 1;
     for (int a = 0; a < 3; a++) {
@@ -912,6 +1160,8 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
             if (it.params.precision != prec) return set_error("gt_batch_create: item %u: precision differs", i), GT_EINVAL;
             if (it.params.flags & GT_FLAG_LANE_PER_HISTORY)
                 return set_error("gt_batch_create: item %u: GT_FLAG_LANE_PER_HISTORY is not available in batches", i), GT_EINVAL;
+            if (it.params.flags & (GT_FLAG_TRACKER_SP | GT_FLAG_TRACKER_RTK))
+                return set_error("gt_batch_create: item %u: batches run the single tracker only", i), GT_EINVAL;
             if (it.geometry->device != dev) return set_error("gt_batch_create: item %u: geometry on another device", i), GT_EINVAL;
             const gt_geometry *g = it.geometry;
             const void *wsi = it.out.workspace ? it.out.workspace : g->ws;

@@ -58,6 +58,36 @@ struct alignas(16) Univ {
     float x0, y0, inv_px, inv_py;   // lattice guess (single precision, advisory)
 };
 
+// Universe kinds for the trackers that keep one tracker type per kind of
+// universe (the static-polymorphism method and the fixed-depth reactor
+// tracker; Sections "Static polymorphism (SP) method" and "RTK tracking").
+// The preprocessor recognises them from the cells themselves; the single
+// tracker never reads them.
+//  * rect: an nx x ny pseudo-array whose cell (i, j) is local cell j*nx + i,
+//    bounded by x planes X_i < X_{i+1} and y planes Y_j < Y_{j+1} (the outer
+//    planes of the first and last row and column may be absent: unbounded),
+//    plus the same extra half-spaces in every cell;
+//  * pin: concentric z-cylinders of one centre and z planes; cell (slab k,
+//    ring r) is local cell k*(ncyl+1) + r, between cylinders r-1 and r and
+//    z planes k-1 and k (the innermost ring, the outermost ring and the end
+//    slabs unbounded on that side).
+constexpr int32_t kKindCsg = 0, kKindRect = 1, kKindPin = 2;
+
+// 48 bytes per universe.  Arrays (aval: values, asurf: surface ids):
+//  rect: X_0 .. X_nx, then Y_0 .. Y_ny (+-inf / kLeafNone where a plane is
+//        absent); extra half-spaces: nxhs packed entries at ahs[xhs];
+//  pin:  r^2 of the n0 cylinders (inner first), the centre (x, y), then the
+//        n1 z planes (ascending).
+struct alignas(16) UArr {
+    int32_t kind;
+    uint32_t cell0;
+    uint32_t arr;        // first entry in aval / asurf
+    uint32_t xhs;        // rect: first extra half-space in ahs
+    uint32_t n0, n1;     // rect: nx, ny; pin: cylinders, z planes
+    uint32_t nxhs, pad;
+    float x0, y0, inv_px, inv_py;   // rect: first-guess index (single precision; corrected exactly)
+};
+
 // BVH node with single-precision, outward-rounded bounds (32 bytes).  Nodes
 // are stored depth-first; an internal node's first child follows it, and
 // `escape` is the next node to visit when the point is outside the node
@@ -94,13 +124,19 @@ struct Dev {
     const uint32_t *adj;        // crossing candidates: cells using the surface with the other sense
                                 // whose widened boxes touch the cell's box, largest overlap first
     const uint32_t *cell_local; // index of each cell within its universe
+    const UArr *uarr;           // per universe: its kind and arrays (see UArr)
+    const double *aval;         // array values
+    const uint32_t *asurf;      // array surface ids
+    const uint32_t *ahs;        // extra half-spaces of rect universes (packed)
+    const uint32_t *cell_ij;    // rect cells: i | j << 16; pin cells: ring | slab << 16; others 0
     uint32_t root, n_inst, max_depth, n_cells;
     double lo[3], hi[3];
 };
 
 // Blob sections (all 256-byte aligned in one device allocation)
 enum Section { SEC_COEF, SEC_HS, SEC_CELL, SEC_TRANS, SEC_UNIV, SEC_NODE32, SEC_NODE64, SEC_LEAF, SEC_CBOX,
-               SEC_SIGMA, SEC_ADJOFF, SEC_ADJ, SEC_LOCAL, SEC_COUNT };
+               SEC_SIGMA, SEC_ADJOFF, SEC_ADJ, SEC_LOCAL, SEC_UARR, SEC_AVAL, SEC_ASURF, SEC_AHS, SEC_IJ,
+               SEC_COUNT };
 
 // Copy of a geometry's hot tables into LDS: sections of the device blob
 // (byte offsets, 16-byte multiples) and where each lands in LDS.
@@ -142,7 +178,9 @@ struct KOut {
 // Device copy of a geometry's descriptor (read-only for every launch).
 struct GeomDesc {
     Dev dev;
-    StagePlan stage[2];
+    StagePlan stage[2];       // per precision mode, for the single tracker
+    StagePlan stage_arr[2];   // the same with the universe-kind tables among the per-segment ones, for
+                              // the trackers that switch on universe kind
 };
 
 // Parameters of one tracking launch, written to device memory by a small
@@ -211,6 +249,9 @@ struct FinalizeItem {
 struct gt_geometry {
     gt::Dev dev;
     gt::StagePlan stage[2];   // per precision mode (GT_PREC_FP64, GT_PREC_MIXED)
+    gt::StagePlan stage_arr[2];   // ... for the trackers that switch on universe kind
+    uint32_t rtk_shape;       // 0: not of the fixed-depth reactor shape; else see gt_geometry_kinds
+    uint32_t n_rect, n_pin;   // universes recognised as rectilinear arrays and as pins
     const gt::GeomDesc *desc; // device copy of dev and stage (in the blob)
     void *blob;          // one device allocation holding every table
     uint64_t blob_bytes;

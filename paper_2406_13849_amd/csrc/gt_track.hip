@@ -21,24 +21,11 @@
 #include <new>
 
 #include "gt_device.h"
+#include "gt_launch.h"
 
 namespace gt {
 namespace {
 
-__device__ __forceinline__ void add_counts(const Counts &c, uint64_t *counters) {
-    __shared__ unsigned long long sh[7];
-    if (threadIdx.x < 7) sh[threadIdx.x] = 0;
-    __syncthreads();
-    if (c.escaped) atomicAdd(&sh[GT_CNT_ESCAPED], (unsigned long long)c.escaped);
-    if (c.capped) atomicAdd(&sh[GT_CNT_CAPPED], (unsigned long long)c.capped);
-    if (c.lost) atomicAdd(&sh[GT_CNT_LOST], (unsigned long long)c.lost);
-    if (c.segcap) atomicAdd(&sh[GT_CNT_SEGCAP], (unsigned long long)c.segcap);
-    if (c.recovf) atomicAdd(&sh[GT_CNT_REC_OVERFLOW], (unsigned long long)c.recovf);
-    if (c.segments) atomicAdd(&sh[GT_CNT_SEGMENTS], (unsigned long long)c.segments);
-    if (c.rejected) atomicAdd(&sh[GT_CNT_REJECTED], (unsigned long long)c.rejected);
-    __syncthreads();
-    if (threadIdx.x < 7 && sh[threadIdx.x]) atomicAdd((unsigned long long *)&counters[threadIdx.x], sh[threadIdx.x]);
-}
 
 template <int PREC>
 __global__ void __launch_bounds__(kBlock) k_track(Dev g0, KParams p, KOut o) {
@@ -311,21 +298,7 @@ __global__ void k_fp64_check(const double *a, const double *b, uint64_t n, doubl
 }
 
 // ------------------------------------------------------------------ launchers
-inline int hip_check(hipError_t e, const char *what) {
-    if (e == hipSuccess) return GT_OK;
-    set_error("%s: %s", what, hipGetErrorString(e));
-    return GT_EHIP;
-}
-
-inline unsigned grid_for(uint64_t n, unsigned block) {
-    uint64_t b = (n + block - 1) / block;
-    return (unsigned)(b < 1 ? 1 : (b > 0x7FFFFFFFull ? 0x7FFFFFFFull : b));
-}
-
-inline unsigned fill_grid(uint64_t n) {
-    uint64_t b = (n + 255) / 256;
-    return (unsigned)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
-}
+}  // namespace
 
 // Workgroups that fit on the device at once (all compute units, the
 // occupancy the kernel's resources allow), cached per device, kernel, block
@@ -365,14 +338,14 @@ int persistent_grid(const void *kernel, unsigned block, unsigned dyn, int device
 // Let a kernel use up to `bytes` of dynamic LDS (once per kernel).
 int allow_dynamic_lds(const void *kernel, unsigned bytes) {
     std::lock_guard<std::mutex> lk(g_launch_mu);
-    static const void *done[16];
+    static const void *done[64];
     static int used = 0;
     for (int i = 0; i < used; i++)
         if (done[i] == kernel) return GT_OK;
     int rc = hip_check(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes),
                        "hipFuncSetAttribute");
     if (rc) return rc;
-    if (used < 16) done[used++] = kernel;
+    if (used < 64) done[used++] = kernel;
     return GT_OK;
 }
 
@@ -381,13 +354,6 @@ int allow_dynamic_lds(const void *kernel, unsigned bytes) {
 // buffer (with tail compaction), as large as the workgroup's share of the
 // compute unit's LDS allows without lowering the number of resident
 // workgroups.
-struct LdsPlan {
-    unsigned dyn, tables_at, tail_at, tail_cap, tail_words, regroup, cache_at, cache_k;
-    int blocks;
-};
-
-constexpr unsigned kLdsPerCU = 160 * 1024;
-
 // Dynamic LDS of a persistent launch: level columns, staged tables, then --
 // within the workgroup's share of the compute unit's LDS that keeps the
 // resident workgroups -- the regroup buffer (one word per lane), the tally
@@ -466,9 +432,8 @@ void note_launch(const LdsPlan &lp, int blocks, unsigned block, int kind) {
     t_have_launch = true;
 }
 
-inline void mark(hipEvent_t e, hipStream_t st) {
-    if (e) (void)hipEventRecord(e, st);
-}
+
+namespace {
 
 // One persistent tracker launch for a geometry of staging kind KIND: the
 // build with the mesh tally when there is a mesh, else the one with the
@@ -676,8 +641,14 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
             const bool cache = !(p->flags & GT_FLAG_NO_TALLY_CACHE);
             const uint32_t rg = p->regroup_every;
             const bool ms = mesh != nullptr;
-            int rc = block == 640 ? launch_persistent<PREC, 5>(g, lrec, kind, kp.n, block, tail, cache, rg, ms, st)
+            int rc;
+            if (p->flags & (GT_FLAG_TRACKER_SP | GT_FLAG_TRACKER_RTK)) {
+                rc = launch_kinds(g, lrec, PREC, (p->flags & GT_FLAG_TRACKER_SP) ? TRK_SP : TRK_RTK, kp.n, block, tail,
+                                  cache, !(p->flags & GT_FLAG_NO_STAGING), st);
+            } else {
+                rc = block == 640 ? launch_persistent<PREC, 5>(g, lrec, kind, kp.n, block, tail, cache, rg, ms, st)
                                   : launch_persistent<PREC, 4>(g, lrec, kind, kp.n, block, tail, cache, rg, ms, st);
+            }
             if (rc) return rc;
         }
     }

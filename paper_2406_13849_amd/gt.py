@@ -26,6 +26,9 @@ FLAG_LANE_PER_HISTORY = 2
 FLAG_NO_STAGING = 4
 FLAG_TAIL_COMPACTION = 8
 FLAG_NO_TALLY_CACHE = 16
+FLAG_TRACKER_SP = 32
+FLAG_TRACKER_RTK = 64
+TRACKER_FLAGS = {"st": 0, "sp": FLAG_TRACKER_SP, "rtk": FLAG_TRACKER_RTK}
 END_NONE, END_ESCAPE, END_CAP, END_LOST, END_SEGCAP = 0, 1, 2, 3, 4
 COUNTERS = ("escaped", "capped", "lost", "segcap", "rec_overflow", "segments", "rejected", "spare")
 
@@ -102,6 +105,8 @@ def lib():
         L.gt_geometry_info.restype = i32
         L.gt_geometry_staging.argtypes = [vp, u32, C.POINTER(u32), C.POINTER(u32)]
         L.gt_geometry_staging.restype = i32
+        L.gt_geometry_kinds.argtypes = [vp, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]
+        L.gt_geometry_kinds.restype = i32
         L.gt_geometry_destroy.argtypes = [vp]
         L.gt_geometry_destroy.restype = None
         L.gt_track.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Out), vp]
@@ -211,6 +216,13 @@ class Geometry:
         _check(lib().gt_geometry_staging(self.h, precision, C.byref(k), C.byref(b)))
         return int(k.value), int(b.value)
 
+    def kinds(self):
+        """gt_geometry_kinds: (rectilinear arrays, pins, fixed-depth shape;
+        0 = not trackable with tracker="rtk")."""
+        r, p, s = C.c_uint32(), C.c_uint32(), C.c_uint32()
+        _check(lib().gt_geometry_kinds(self.h, C.byref(r), C.byref(p), C.byref(s)))
+        return int(r.value), int(p.value), int(s.value)
+
     def close(self):
         if getattr(self, "h", None) is not None and _lib is not None:
             _lib.gt_geometry_destroy(self.h)
@@ -265,7 +277,7 @@ def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 
           max_collisions: int = 20, source: int = 0, ray_n1: int = 0, max_segments: int = 100_000,
           precision: int = PREC_MIXED, record_first_k: int = 0, record_cap: int = 0, accumulate: bool = False,
           lane_per_history: bool = False, staging: bool = True, block_size: int = 0, refill_min: int = 0,
-          tail_compaction: bool = False, tally_cache: bool = True, regroup_every: int = 0,
+          tail_compaction: bool = False, tally_cache: bool = True, regroup_every: int = 0, tracker: str = "st",
           out: Optional[TrackOutputs] = None, stream=None) -> TrackOutputs:
     """gt_track: sample and track n_particles histories (asynchronous).
     lane_per_history selects the plain one-history-per-lane schedule instead
@@ -273,12 +285,15 @@ def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 
     in global memory even when they fit in LDS; tail_compaction=True packs
     the histories left after the queue has drained into fewer waves; tally_cache=False
     flushes a lane's tally sum at every change of instance; regroup_every=R
-    sorts a workgroup's histories by leaf universe every R loop trips."""
+    sorts a workgroup's histories by leaf universe every R loop trips;
+    tracker selects the tracker method: "st" the single tracker (default),
+    "sp" one tracker per universe kind switched per level, "rtk" the
+    fixed-depth reactor tracker (GT_FLAG_TRACKER_*)."""
     if out is None:
         out = alloc_outputs(geom, n_particles, record_first_k, record_cap)
     prm = _params(seed, n_particles, first_particle, geometry_id, max_collisions, source, ray_n1, max_segments,
                   precision, record_first_k, record_cap, accumulate, lane_per_history, staging, block_size,
-                  refill_min, tail_compaction, tally_cache, regroup_every)
+                  refill_min, tail_compaction, tally_cache, regroup_every, tracker)
     o = _out_struct(out)
     _check(lib().gt_track(geom.h, C.byref(prm), C.byref(o), _stream(stream)))
     return out
@@ -375,13 +390,15 @@ def track_event(geom: Geometry, seed: int, n_particles: int, *, bank=None, out: 
 def _params(seed, n_particles, first_particle=0, geometry_id=0, max_collisions=20, source=0, ray_n1=0,
             max_segments=100_000, precision=PREC_MIXED, record_first_k=0, record_cap=0, accumulate=False,
             lane_per_history=False, staging=True, block_size=0, refill_min=0, tail_compaction=False,
-            tally_cache=True, regroup_every=0) -> _Params:
+            tally_cache=True, regroup_every=0, tracker="st") -> _Params:
+    if tracker not in TRACKER_FLAGS:
+        raise ValueError("tracker must be one of %s" % sorted(TRACKER_FLAGS))
     return _Params(seed=seed, first_particle=first_particle, n_particles=n_particles, geometry_id=geometry_id,
                    max_collisions=max_collisions, source=source, ray_n1=ray_n1, max_segments=max_segments,
                    precision=precision, record_first_k=record_first_k, record_cap=record_cap,
                    flags=(FLAG_ACCUMULATE if accumulate else 0) | (FLAG_LANE_PER_HISTORY if lane_per_history else 0)
                    | (0 if staging else FLAG_NO_STAGING) | (FLAG_TAIL_COMPACTION if tail_compaction else 0)
-                   | (0 if tally_cache else FLAG_NO_TALLY_CACHE),
+                   | (0 if tally_cache else FLAG_NO_TALLY_CACHE) | TRACKER_FLAGS[tracker],
                    block_size=block_size, refill_min=refill_min, regroup_every=regroup_every)
 
 

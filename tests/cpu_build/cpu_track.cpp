@@ -16,7 +16,7 @@ constexpr size_t kLdsEmuBytes = 160 * 1024;
 thread_local unsigned char g_lds[kLdsEmuBytes];
 thread_local uint32_t g_cache_k = kTallyCacheMax;   // tally-cache entries of the lane (0 = off)
 
-template <int PREC, int KIND, bool MESH, typename Queue>
+template <int PREC, int KIND, bool MESH, typename Queue, int TRK = TRK_ST, int SHAPE = 0>
 void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut &o, const Queue &q, uint64_t *counts) {
     static thread_local uint32_t cells[GT_MAX_LEVELS];
     static thread_local uint32_t ctl[1 + kBlockP / 64];
@@ -31,7 +31,7 @@ void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     const TailCfg tc = {nullptr, ctl, 0, kTailRound, 0, 0};
     const TallyCache tcache = {c_lo, c_hi, c_tag, g_cache_k, 1};
-    track_pool<PREC, false, MESH>(v, p, o, o.tally_ws, cells, q, cnt, tc, tcache);
+    track_pool<PREC, false, MESH, TRK, SHAPE>(v, p, o, o.tally_ws, cells, q, cnt, tc, tcache);
     counts[GT_CNT_ESCAPED] += cnt.escaped;
     counts[GT_CNT_CAPPED] += cnt.capped;
     counts[GT_CNT_LOST] += cnt.lost;
@@ -50,6 +50,19 @@ int run_kind(int kind, const Dev &dev, const StagePlan &sp, const KParams &p, co
     case SK_LDS: run_lane<PREC, SK_LDS, MESH>(dev, sp, p, o, q, counts); break;
     case SK_SPLIT: run_lane<PREC, SK_SPLIT, MESH>(dev, sp, p, o, q, counts); break;
     default: run_lane<PREC, SK_NONE, MESH>(dev, sp, p, o, q, counts); break;
+    }
+    return GT_OK;
+}
+
+template <int PREC, int TRK, int SHAPE>
+int run_kind_trk(int kind, const Dev &dev, const StagePlan &sp, const KParams &p, const KOut &o,
+                 const GlobalQueue &q, uint64_t *counts) {
+    if (kind != SK_NONE && sp.total > sizeof(g_lds)) return GT_ECAPACITY;
+    switch (kind) {
+    case SK_ALL: run_lane<PREC, SK_ALL, false, GlobalQueue, TRK, SHAPE>(dev, sp, p, o, q, counts); break;
+    case SK_LDS: run_lane<PREC, SK_LDS, false, GlobalQueue, TRK, SHAPE>(dev, sp, p, o, q, counts); break;
+    case SK_SPLIT: run_lane<PREC, SK_SPLIT, false, GlobalQueue, TRK, SHAPE>(dev, sp, p, o, q, counts); break;
+    default: run_lane<PREC, SK_NONE, false, GlobalQueue, TRK, SHAPE>(dev, sp, p, o, q, counts); break;
     }
     return GT_OK;
 }
@@ -82,6 +95,42 @@ extern "C" int cpu_track(const gt_geometry *g, const gt_track_params *p, const g
     const GlobalQueue q = {&ctr, kp.n};
     rc = p->precision == GT_PREC_MIXED ? run_kind<GT_PREC_MIXED>(kind, g->dev, sp, kp, ko, q, o->counters)
                                        : run_kind<GT_PREC_FP64>(kind, g->dev, sp, kp, ko, q, o->counters);
+    if (rc) return rc;
+    fold_all(ko.tally_ws, o->tally_fx, o->tally, g->n_inst, (p->flags & GT_FLAG_ACCUMULATE) != 0);
+    return GT_OK;
+}
+
+// gt_track with GT_FLAG_TRACKER_SP or GT_FLAG_TRACKER_RTK on the CPU: the
+// per-kind trackers' state machine through one lane, tables held as the
+// plan with the universe-kind tables holds them (staging kind `kind`: that
+// plan's kind or 0).
+extern "C" int cpu_track_kinds(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o, int kind) {
+    int rc = check_track_args(g, p, o);
+    if (rc) return rc;
+    const bool rtk = (p->flags & GT_FLAG_TRACKER_RTK) != 0;
+    if (!rtk && !(p->flags & GT_FLAG_TRACKER_SP)) return set_error("cpu_track_kinds: no tracker flag"), GT_EINVAL;
+    const int prec = rtk ? GT_PREC_FP64 : (int)p->precision;
+    const StagePlan &sp = g->stage_arr[prec];
+    if (kind != SK_NONE && kind != (int)sp.kind) return set_error("cpu_track_kinds: another staging kind"), GT_EINVAL;
+    KParams kp;
+    KOut ko;
+    fill_kparams(p, g, kp, ko, o);
+    g_cache_k = (p->flags & GT_FLAG_NO_TALLY_CACHE) ? 0 : kTallyCacheMax;
+    std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
+    std::memset(o->counters, 0, 8 * sizeof(uint64_t));
+    if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
+    unsigned long long ctr = 0;
+    const GlobalQueue q = {&ctr, kp.n};
+    if (!rtk)
+        rc = prec == GT_PREC_MIXED ? run_kind_trk<GT_PREC_MIXED, TRK_SP, 0>(kind, g->dev, sp, kp, ko, q, o->counters)
+                                   : run_kind_trk<GT_PREC_FP64, TRK_SP, 0>(kind, g->dev, sp, kp, ko, q, o->counters);
+    else switch (g->rtk_shape) {
+        case 1: rc = run_kind_trk<GT_PREC_FP64, TRK_RTK, 1>(kind, g->dev, sp, kp, ko, q, o->counters); break;
+        case 3: rc = run_kind_trk<GT_PREC_FP64, TRK_RTK, 3>(kind, g->dev, sp, kp, ko, q, o->counters); break;
+        case 5: rc = run_kind_trk<GT_PREC_FP64, TRK_RTK, 5>(kind, g->dev, sp, kp, ko, q, o->counters); break;
+        case 7: rc = run_kind_trk<GT_PREC_FP64, TRK_RTK, 7>(kind, g->dev, sp, kp, ko, q, o->counters); break;
+        default: return set_error("cpu_track_kinds: not of the fixed-depth shape"), GT_EINVAL;
+        }
     if (rc) return rc;
     fold_all(ko.tally_ws, o->tally_fx, o->tally, g->n_inst, (p->flags & GT_FLAG_ACCUMULATE) != 0);
     return GT_OK;

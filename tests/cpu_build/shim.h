@@ -57,6 +57,8 @@ template <typename T, typename V> static inline T cpu_atomic_fetch_add(T *p, V v
 #define __hip_atomic_fetch_add cpu_atomic_fetch_add
 #undef __HIP_MEMORY_SCOPE_WORKGROUP
 #define __HIP_MEMORY_SCOPE_WORKGROUP 0
+#undef __HIP_MEMORY_SCOPE_AGENT
+#define __HIP_MEMORY_SCOPE_AGENT 0
 template <typename A, typename B> static inline A min(A a, B b) { return a < (A)b ? a : (A)b; }
 template <typename A, typename B> static inline A max(A a, B b) { return a > (A)b ? a : (A)b; }
 #define GT_AS(n)

@@ -550,23 +550,26 @@ def full_oracle(cfg, n, rk, rc):
     return _full_oracle[key]
 
 
-@pytest.mark.parametrize("cfg,prec,lane", [(3, gt.PREC_MIXED, False), (3, gt.PREC_FP64, False),
-                                           (3, gt.PREC_FP64, True), (4, gt.PREC_MIXED, False),
-                                           (4, gt.PREC_FP64, False)],
-                         ids=["core-mixed", "core-fp64", "core-fp64-lane", "hex-mixed", "hex-fp64"])
-def test_full_size_all_histories(cfg, prec, lane):
+@pytest.mark.parametrize("cfg,prec,lane,tracker", [(3, gt.PREC_MIXED, False, "st"), (3, gt.PREC_FP64, False, "st"),
+                                                   (3, gt.PREC_FP64, True, "st"), (3, gt.PREC_MIXED, False, "sp"),
+                                                   (3, gt.PREC_FP64, False, "rtk"), (4, gt.PREC_MIXED, False, "st"),
+                                                   (4, gt.PREC_FP64, False, "st")],
+                         ids=["core-mixed", "core-fp64", "core-fp64-lane", "core-sp-mixed", "core-rtk", "hex-mixed",
+                              "hex-fp64"])
+def test_full_size_all_histories(cfg, prec, lane, tracker):
     """The three-level square core (2.86M tallies) and the hexagonal core
     (97k tallies) at full size, 1e7 histories, in the benchmark's launch
     configuration (default persistent shape, the first 1e5 sequences
-    recorded; and the plain one-history-per-lane all-FP64 tracker): every
-    history's hash, segment count and end code, every recorded sequence,
-    every counter and every fixed-point tally against one oracle run."""
+    recorded; the plain one-history-per-lane all-FP64 tracker; the SP and
+    RTK trackers): every history's hash, segment count and end code, every
+    recorded sequence, every counter and every fixed-point tally against one
+    oracle run."""
     fg, G, O = geoms(cfg)
     n, rk, rc = 10_000_000, 100_000, 384
     o = full_oracle(cfg, n, rk, rc)
-    print("cfg%d full size, precision %d, lane per history %s" % (cfg, prec, lane), flush=True)
+    print("cfg%d full size, precision %d, lane per history %s, tracker %s" % (cfg, prec, lane, tracker), flush=True)
     g = gpu_track(G, precision=prec, seed=synth.particle_seed(cfg), n_particles=n, geometry_id=cfg,
-                  record_first_k=rk, record_cap=rc, lane_per_history=lane)
+                  record_first_k=rk, record_cap=rc, lane_per_history=lane, tracker=tracker)
     assert g["counters"]["rec_overflow"] == 0
     assert_parity(g, o, where="cfg%d full" % cfg)
 
@@ -877,3 +880,68 @@ def test_event_based_invalid_arguments():
     out = gt.track_event(G, seed=1, n_particles=0)
     torch.cuda.synchronize()
     assert int(out.counters.sum().item()) == 0
+
+
+# ---------------------------------------------------------------- per-kind trackers (SP, RTK)
+KIND_CASES = [(1, 10_000, 1), (2, 60_000, 1), (3, 40_000, 7), (4, 20_000, 0), ("nested_box", 3000, 0),
+              ("hex_pin_box", 4000, 0)]
+
+
+@pytest.mark.parametrize("case", KIND_CASES, ids=[str(c[0]) for c in KIND_CASES])
+@pytest.mark.parametrize("tracker,prec", [("sp", gt.PREC_FP64), ("sp", gt.PREC_MIXED), ("rtk", gt.PREC_FP64)],
+                         ids=["sp-fp64", "sp-mixed", "rtk"])
+@pytest.mark.parametrize("staging", [True, False], ids=["lds", "global"])
+def test_kind_trackers_parity(case, tracker, prec, staging):
+    """The static-polymorphism tracker (arrays by index, a switch on each
+    level's kind) in both precision modes and the fixed-depth reactor
+    tracker, tables in LDS and in global memory: identical to the oracle.
+    A geometry not of the reactor shape is refused by the RTK tracker."""
+    cfg, n, shape = case
+    fg, G, O = geoms(cfg)
+    assert G.kinds()[2] == shape
+    kw = dict(seed=synth.particle_seed(cfg) if isinstance(cfg, int) else 91, n_particles=n,
+              geometry_id=cfg if isinstance(cfg, int) else 5)
+    if tracker == "rtk" and not shape:
+        with pytest.raises(gt.GtError) as e:
+            gt.track(G, tracker="rtk", **kw)
+        assert e.value.code == gt.GT_EINVAL
+        return
+    print("tracker %s, case %s, precision %d, staging %s" % (tracker, cfg, prec, staging), flush=True)
+    g = gpu_track(G, precision=prec, record_first_k=500, record_cap=256, tracker=tracker, staging=staging, **kw)
+    o = oracle.track(O, oracle.TrackParams(record_first_k=500, record_cap=256, **kw), n_threads=NT)
+    assert_parity(g, o, where="%s %s" % (tracker, cfg))
+
+
+@pytest.mark.parametrize("tracker", ["sp", "rtk"])
+@pytest.mark.parametrize("opts", [dict(tail_compaction=True), dict(block_size=640), dict(block_size=256),
+                                  dict(tally_cache=False), dict(refill_min=1)],
+                         ids=["tail", "b640", "b256", "nocache", "refill1"])
+def test_kind_trackers_launch_shapes(tracker, opts):
+    """Launch shapes and options never change the per-kind trackers' outputs."""
+    fg, G, O = geoms(2)
+    kw = dict(seed=4242, n_particles=30_000, geometry_id=2)
+    print("tracker %s, options %s" % (tracker, opts), flush=True)
+    g = gpu_track(G, record_first_k=200, record_cap=256, tracker=tracker, **kw, **opts)
+    o = oracle.track(O, oracle.TrackParams(record_first_k=200, record_cap=256, **kw), n_threads=NT)
+    assert_parity(g, o, where="%s %s" % (tracker, opts))
+
+
+def test_kind_trackers_refused_where_not_built():
+    """The per-kind trackers run the persistent single-geometry schedule
+    only: one history per lane, the regroup step, the mesh tally and batches
+    refuse them; the two tracker flags exclude each other."""
+    fg, G, O = geoms(2)
+    kw = dict(seed=1, n_particles=100, geometry_id=2)
+    for bad in (dict(tracker="sp", lane_per_history=True), dict(tracker="rtk", regroup_every=16)):
+        with pytest.raises(gt.GtError) as e:
+            gt.track(G, **bad, **kw)
+        assert e.value.code == gt.GT_EINVAL
+    import ctypes as C
+    prm = gt._params(1, 100, geometry_id=2, tracker="sp")
+    prm.flags |= gt.FLAG_TRACKER_RTK
+    out = gt.alloc_outputs(G, 100)
+    assert gt.lib().gt_track(G.h, C.byref(prm), C.byref(gt._out_struct(out)), None) == gt.GT_EINVAL
+    with pytest.raises(gt.GtError):
+        gt.track_mesh(G, 1, 100, fg.domain_lo, fg.domain_hi, (4, 4, 4), geometry_id=2, tracker="sp")
+    with pytest.raises(gt.GtError):
+        gt.track_batch([gt.batch_item(G, 1, 100, geometry_id=2, tracker="sp")])
