@@ -74,7 +74,7 @@ WORKLOAD_NAMES = {1: "3x3 square lattice of one pin type (two levels)",
                      "3 types (four levels)",
                   4: "7-ring hexagonal core of 9-ring hexagonal assemblies, planes only (three levels)"}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2406_13849_amd", "csrc", f)
-                  for f in ("gt_device.h", "gt_track.hip", "gt_internal.h", "gt_geometry.cpp")]
+                  for f in ("gt_device.h", "gt_track.hip", "gt_internal.h", "gt_geometry.cpp", "gt_launch.h")]
 
 
 def parse():
@@ -293,7 +293,7 @@ def track_leg(gt, G, n, seed, gid, args, prec, steps, warmup, hev, rec=True, **k
     r["out"] = out
     if not call.get("lane_per_history"):
         r["plan"] = gt.last_launch()
-    r["shape"] = {k: call.get(k, 0) for k in ("block_size", "refill_min", "regroup_every")}
+    r["shape"] = {k: call.get(k, 0) for k in ("block_size", "refill_min", "regroup_every", "wave_histories")}
     return r
 
 
@@ -320,7 +320,7 @@ def workload_legs(gt, synth, cfg, n, args, hev, aux):
         shape_note = gt.autotune_track(G, seed=seed, n_particles=n, geometry_id=cfg, precision=gt.PREC_MIXED,
                                        record_first_k=min(args.record_k, n), record_cap=args.record_cap, out=out,
                                        reps=2)
-        kw_mixed = {k: shape_note[k] for k in ("block_size", "refill_min", "regroup_every")}
+        kw_mixed = {k: shape_note[k] for k in ("block_size", "refill_min", "regroup_every", "wave_histories")}
         del out
     for name, prec in (("mixed", gt.PREC_MIXED), ("fp64", gt.PREC_FP64)):
         if args.only is None or args.only == name:

@@ -219,6 +219,12 @@ typedef struct {
                                  64-bit word per lane or for workgroups of one wave;
                                  must be 0 for GT_FLAG_LANE_PER_HISTORY and for
                                  gt_track_event                                      */
+    uint32_t wave_histories;  /* persistent schedule: histories a wavefront claims
+                                 from the work queue at once and hands to its idle
+                                 lanes as they free up -- the particles per
+                                 wavefront of a claim: 64, 128, ..., 1024 (one to
+                                 sixteen per lane); 0 = 64.  Speed only.  Must be 0
+                                 for GT_FLAG_LANE_PER_HISTORY and gt_track_event     */
 } gt_track_params;
 
 /* Outputs, all device memory owned by the caller.
@@ -359,7 +365,7 @@ typedef struct {
     uint32_t refill_min;   /* as gt_track_params.refill_min; 0 = 8                             */
     uint64_t chunk;        /* histories per work item taken from the device queue; 0 = 4096   */
     uint32_t regroup_every;/* as gt_track_params.regroup_every; 0 = that of the first item    */
-    uint32_t reserved;     /* must be 0                                                        */
+    uint32_t wave_histories; /* as gt_track_params.wave_histories; 0 = each item's own          */
 } gt_tuning;               /* a NULL gt_tuning* means: the shape gt_autotune_batch found for
                               the same items in this process, else the defaults              */
 

@@ -657,11 +657,12 @@ __device__ __forceinline__ int forced_slab(int i_num, int p, bool fpos, int n) {
 
 // The extra half-spaces every cell of a rect universe has (numeric senses,
 // or the forced sense on surface force_s).
-template <typename G>
-__device__ __forceinline__ bool rect_extras(const G &g, const UArr &A, double x, double y, double z,
-                                            uint32_t force_s, bool force_pos) {
-    for (uint32_t k = 0; k < A.nxhs; k++) {
-        const uint32_t h = g.ahs[A.xhs + k];
+template <typename G, typename AP>
+__device__ __forceinline__ bool rect_extras(const G &g, AP A, double x, double y, double z, uint32_t force_s,
+                                            bool force_pos) {
+    const uint32_t n = A->nxhs, at = A->xhs;
+    for (uint32_t k = 0; k < n; k++) {
+        const uint32_t h = g.ahs[at + k];
         const uint32_t s = h >> 4, t = h & 7u;
         const auto c = g.coef + 4 * (size_t)s;
         const double f = t < ST_CZ ? plane_value(t, c, x, y, z) : quad_value(t, c, x, y, z);
@@ -673,60 +674,63 @@ __device__ __forceinline__ bool rect_extras(const G &g, const UArr &A, double x,
 
 // find_cell in a rect universe (Alg. 5 with the uniform-pitch first guess):
 // the cell (i, j) by index, then the extra half-spaces; -1 if none.
-template <typename G>
-__device__ __forceinline__ int32_t rect_locate(const G &g, const UArr &A, double x, double y, double z) {
-    const auto X = g.aval + A.arr;
-    const auto Y = X + (A.n0 + 1);
-    const int gi = (int)floorf(((float)x - A.x0) * A.inv_px), gj = (int)floorf(((float)y - A.y0) * A.inv_py);
-    const int i = slab_of(X, (int)A.n0, x, gi), j = slab_of(Y, (int)A.n1, y, gj);
-    if (i < 0 || i >= (int)A.n0 || j < 0 || j >= (int)A.n1) return -1;
-    if (A.nxhs && !rect_extras(g, A, x, y, z, kNone, false)) return -1;
-    return (int32_t)(A.cell0 + (uint32_t)j * A.n0 + (uint32_t)i);
+template <typename G, typename AP>
+__device__ __forceinline__ int32_t rect_locate(const G &g, AP A, double x, double y, double z) {
+    const uint32_t nx = A->n0, ny = A->n1;
+    const auto X = g.aval + A->arr;
+    const auto Y = X + (nx + 1);
+    const int gi = (int)floorf(((float)x - A->x0) * A->inv_px), gj = (int)floorf(((float)y - A->y0) * A->inv_py);
+    const int i = slab_of(X, (int)nx, x, gi), j = slab_of(Y, (int)ny, y, gj);
+    if (i < 0 || i >= (int)nx || j < 0 || j >= (int)ny) return -1;
+    if (A->nxhs && !rect_extras(g, A, x, y, z, kNone, false)) return -1;
+    return (int32_t)(A->cell0 + (uint32_t)j * nx + (uint32_t)i);
 }
 
 // cross_surface in a rect universe (Alg. 6): from cell `old` across the grid
 // boundary named by `entry` (forced sense fpos) to the neighbour by index,
 // the other axis re-checked from the old index; -1 when the crossing leaves
 // the array.
-template <typename G>
-__device__ __forceinline__ int32_t rect_cross(const G &g, const UArr &A, uint32_t old, uint32_t entry, bool fpos,
-                                             double x, double y, double z) {
+template <typename G, typename AP>
+__device__ __forceinline__ int32_t rect_cross(const G &g, AP A, uint32_t old, uint32_t entry, bool fpos, double x,
+                                             double y, double z) {
     if ((entry & kArrExtra) == kArrExtra) return -1;
-    const auto X = g.aval + A.arr;
-    const auto Y = X + (A.n0 + 1);
+    const int nx = (int)A->n0, ny = (int)A->n1;
+    const auto X = g.aval + A->arr;
+    const auto Y = X + (nx + 1);
     const uint32_t ij = g.cell_ij[old];
     int i = (int)(ij & 0xFFFFu), j = (int)(ij >> 16);
     const int p = (int)(entry & 0x0FFFFFFFu);
     if (((entry >> 28) & 7u) == 0) {
-        i = forced_slab(slab_of(X, (int)A.n0, x, i), p, fpos, (int)A.n0);
-        j = slab_of(Y, (int)A.n1, y, j);
+        i = forced_slab(slab_of(X, nx, x, i), p, fpos, nx);
+        j = slab_of(Y, ny, y, j);
     } else {
-        j = forced_slab(slab_of(Y, (int)A.n1, y, j), p, fpos, (int)A.n1);
-        i = slab_of(X, (int)A.n0, x, i);
+        j = forced_slab(slab_of(Y, ny, y, j), p, fpos, ny);
+        i = slab_of(X, nx, x, i);
     }
-    if (i < 0 || i >= (int)A.n0 || j < 0 || j >= (int)A.n1) return -1;
-    if (A.nxhs && !rect_extras(g, A, x, y, z, kNone, false)) return -1;
-    return (int32_t)(A.cell0 + (uint32_t)j * A.n0 + (uint32_t)i);
+    if (i < 0 || i >= nx || j < 0 || j >= ny) return -1;
+    if (A->nxhs && !rect_extras(g, A, x, y, z, kNone, false)) return -1;
+    return (int32_t)(A->cell0 + (uint32_t)j * (uint32_t)nx + (uint32_t)i);
 }
 
 // Pin universe: ring and slab of a point.  The ring is the number of
 // cylinders the point is strictly outside, from the one squared radius
 // (x - cx)^2 + (y - cy)^2 every cylinder's test forms; the slab is the
 // number of z planes it is strictly above (binary search).
-template <typename G>
-__device__ __forceinline__ int pin_ring(const G &g, const UArr &A, double x, double y) {
-    const auto R = g.aval + A.arr;
-    const double dx = x - R[A.n0], dy = y - R[A.n0 + 1];
+template <typename G, typename AP>
+__device__ __forceinline__ int pin_ring(const G &g, AP A, double x, double y) {
+    const int nc = (int)A->n0;
+    const auto R = g.aval + A->arr;
+    const double dx = x - R[nc], dy = y - R[nc + 1];
     const double s2 = dx * dx + dy * dy;
     int r = 0;
-    while (r < (int)A.n0 && s2 - R[r] > 0.0) r++;
+    while (r < nc && s2 - R[r] > 0.0) r++;
     return r;
 }
 
-template <typename G>
-__device__ __forceinline__ int pin_slab(const G &g, const UArr &A, double z) {
-    const auto Z = g.aval + A.arr + A.n0 + 2;
-    int lo = 0, hi = (int)A.n1;
+template <typename G, typename AP>
+__device__ __forceinline__ int pin_slab(const G &g, AP A, double z) {
+    const auto Z = g.aval + A->arr + A->n0 + 2;
+    int lo = 0, hi = (int)A->n1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (z - Z[mid] > 0.0) lo = mid + 1;
@@ -735,22 +739,22 @@ __device__ __forceinline__ int pin_slab(const G &g, const UArr &A, double z) {
     return lo;
 }
 
-template <typename G>
-__device__ __forceinline__ int32_t pin_locate(const G &g, const UArr &A, double x, double y, double z) {
-    return (int32_t)(A.cell0 + (uint32_t)pin_slab(g, A, z) * (A.n0 + 1) + (uint32_t)pin_ring(g, A, x, y));
+template <typename G, typename AP>
+__device__ __forceinline__ int32_t pin_locate(const G &g, AP A, double x, double y, double z) {
+    return (int32_t)(A->cell0 + (uint32_t)pin_slab(g, A, z) * (A->n0 + 1) + (uint32_t)pin_ring(g, A, x, y));
 }
 
 // Crossing inside a pin: a cylinder (axis 0; boundary p = cylinder + 1) or a
 // z plane (axis 1; boundary p = plane + 1), the other coordinate numeric.
-template <typename G>
-__device__ __forceinline__ int32_t pin_cross(const G &g, const UArr &A, uint32_t entry, bool fpos, double x,
-                                            double y, double z) {
+template <typename G, typename AP>
+__device__ __forceinline__ int32_t pin_cross(const G &g, AP A, uint32_t entry, bool fpos, double x, double y,
+                                            double z) {
     const int p = (int)(entry & 0x0FFFFFFFu);
     int r = pin_ring(g, A, x, y), k = pin_slab(g, A, z);
-    if (((entry >> 28) & 7u) == 0) r = forced_slab(r, p, fpos, (int)A.n0 + 1);
-    else k = forced_slab(k, p, fpos, (int)A.n1 + 1);
+    if (((entry >> 28) & 7u) == 0) r = forced_slab(r, p, fpos, (int)A->n0 + 1);
+    else k = forced_slab(k, p, fpos, (int)A->n1 + 1);
     if (r < 0 || k < 0) return -1;
-    return (int32_t)(A.cell0 + (uint32_t)k * (A.n0 + 1) + (uint32_t)r);
+    return (int32_t)(A->cell0 + (uint32_t)k * (A->n0 + 1) + (uint32_t)r);
 }
 
 // The nearest-surface bookkeeping shared by the per-kind distance steps:
@@ -808,31 +812,33 @@ __device__ __forceinline__ bool csg_level_distance(const G &g, const Particle &P
 // distance_to_surface of one level that is a rect cell (i, j): the grid
 // plane ahead along x and along y (the same difference and quotient as the
 // plane's half-space), then the extra half-spaces.
-template <typename G>
-__device__ __forceinline__ bool rect_level_distance(const G &g, const Particle &P, int L, const UArr &A,
-                                                    uint32_t c, double qx, double qy, double qz, Nearest &r) {
+template <typename G, typename AP>
+__device__ __forceinline__ bool rect_level_distance(const G &g, const Particle &P, int L, AP A, uint32_t c,
+                                                    double qx, double qy, double qz, Nearest &r) {
     const uint32_t ij = g.cell_ij[c];
     const int i = (int)(ij & 0xFFFFu), j = (int)(ij >> 16);
+    const uint32_t arr = A->arr;
     bool better = false;
     if (P.u != 0.0) {
         const uint32_t p = (uint32_t)(P.u > 0.0 ? i + 1 : i);
-        const uint32_t s = g.asurf[A.arr + p];
+        const uint32_t s = g.asurf[arr + p];
         if (s != kLeafNone && !(P.on_level == L && P.on_surf == s)) {
-            const double t = (-(qx - g.aval[A.arr + p])) / P.u;
+            const double t = (-(qx - g.aval[arr + p])) / P.u;
             better |= nearer(r, t > 0.0 ? t : 0.0, L, s, P.u < 0.0, kArrHit | p);
         }
     }
     if (P.v != 0.0) {
         const uint32_t p = (uint32_t)(P.v > 0.0 ? j + 1 : j);
-        const uint32_t at = A.arr + A.n0 + 1 + p;
+        const uint32_t at = arr + A->n0 + 1 + p;
         const uint32_t s = g.asurf[at];
         if (s != kLeafNone && !(P.on_level == L && P.on_surf == s)) {
             const double t = (-(qy - g.aval[at])) / P.v;
             better |= nearer(r, t > 0.0 ? t : 0.0, L, s, P.v < 0.0, kArrHit | 1u << 28 | p);
         }
     }
-    for (uint32_t k = 0; k < A.nxhs; k++) {
-        const uint32_t h = g.ahs[A.xhs + k];
+    const uint32_t nx = A->nxhs, xat = A->xhs;
+    for (uint32_t k = 0; k < nx; k++) {
+        const uint32_t h = g.ahs[xat + k];
         const uint32_t s = h >> 4;
         const bool pos = (h >> 3) & 1u;
         const bool on = (P.on_level == L) && (P.on_surf == s);
@@ -845,32 +851,44 @@ __device__ __forceinline__ bool rect_level_distance(const G &g, const Particle &
     return better;
 }
 
-// distance_to_surface of one level that is a pin cell (ring, slab): the
-// bounding cylinders (a, b and the squared radius formed once) and the z
-// plane ahead.
-template <typename G>
-__device__ __forceinline__ bool pin_level_distance(const G &g, const Particle &P, int L, const UArr &A,
-                                                   uint32_t c, double qx, double qy, double qz, Nearest &r) {
+// distance_to_surface of one level that is a pin cell (ring, slab): one
+// bounding cylinder (a, b and the squared radius formed once) and the z
+// plane ahead.  A flight that reaches the inner cylinder (moving inward,
+// positive discriminant) meets it before the outer one -- its near root is
+// below -b/a and the outer cylinder's far root, which the point inside it
+// can only meet, is above -b/a by at least as much -- so the outer
+// cylinder's root is formed only when the inner one is not reached: the
+// nearest of the two, as both half-space tests would give it.
+template <typename G, typename AP>
+__device__ __forceinline__ bool pin_level_distance(const G &g, const Particle &P, int L, AP A, uint32_t c,
+                                                   double qx, double qy, double qz, Nearest &r) {
     const uint32_t rk = g.cell_ij[c];
     const int ring = (int)(rk & 0xFFFFu), slab = (int)(rk >> 16);
-    const auto R = g.aval + A.arr;
-    const double dx = qx - R[A.n0], dy = qy - R[A.n0 + 1];
+    const uint32_t arr = A->arr, nc = A->n0;
+    const auto R = g.aval + arr;
+    const double dx = qx - R[nc], dy = qy - R[nc + 1];
     const double a2 = P.u * P.u + P.v * P.v, b2 = dx * P.u + dy * P.v, r2 = dx * dx + dy * dy;
     bool better = false;
-    if (ring > 0) {
-        const uint32_t m = (uint32_t)ring - 1, s = g.asurf[A.arr + m];
-        const bool on = (P.on_level == L) && (P.on_surf == s);
-        better |= nearer(r, quad_root(a2, b2, r2 - R[m], true, on), L, s, true, kArrHit | (m + 1));
-    }
-    if (ring < (int)A.n0) {
-        const uint32_t m = (uint32_t)ring, s = g.asurf[A.arr + m];
-        const bool on = (P.on_level == L) && (P.on_surf == s);
-        better |= nearer(r, quad_root(a2, b2, r2 - R[m], false, on), L, s, false, kArrHit | (m + 1));
+    {
+        // the inner cylinder when the flight reaches it (its hit comes before
+        // any hit of the outer one), else the outer cylinder: one root
+        const uint32_t mi = ring > 0 ? (uint32_t)ring - 1 : 0u;
+        const uint32_t si = g.asurf[arr + mi];
+        const double cci = r2 - R[mi];
+        const bool inner =
+            ring > 0 && !(P.on_level == L && P.on_surf == si) && b2 < 0.0 && b2 * b2 - a2 * cci > 0.0;
+        if (inner || ring < (int)nc) {
+            const uint32_t m = inner ? mi : (uint32_t)ring;
+            const uint32_t s = inner ? si : g.asurf[arr + m];
+            const bool on = !inner && (P.on_level == L) && (P.on_surf == s);
+            better |= nearer(r, quad_root(a2, b2, inner ? cci : r2 - R[m], inner, on), L, s, inner,
+                             kArrHit | (m + 1));
+        }
     }
     if (P.w != 0.0) {
         const int p = P.w > 0.0 ? slab + 1 : slab;
-        if (p >= 1 && p <= (int)A.n1) {
-            const uint32_t at = A.arr + A.n0 + 2 + (uint32_t)p - 1;
+        if (p >= 1 && p <= (int)A->n1) {
+            const uint32_t at = arr + nc + 2 + (uint32_t)p - 1;
             const uint32_t s = g.asurf[at];
             if (!(P.on_level == L && P.on_surf == s)) {
                 const double t = (-(qz - g.aval[at])) / P.w;
@@ -881,11 +899,50 @@ __device__ __forceinline__ bool pin_level_distance(const G &g, const Particle &P
     return better;
 }
 
-// distance_to_surface over every level for the trackers that switch on
-// universe kind (SP: the kind read per level; RTK: the shape's kind of the
-// level), with what the segment step needs (as nearest_surface).
-template <int TRK, int SHAPE, typename G>
-__device__ __forceinline__ void nearest_surface_kinds(const G &g, const Particle &P, Nearest &r) {
+// distance_to_surface of the fixed-depth reactor shape: the levels' kinds
+// are compile-time constants (the optional one-cell root, the array levels,
+// the pin), so the level loop unrolls into straight code.
+template <int SHAPE, typename G>
+__device__ __forceinline__ void nearest_surface_rtk(const G &g, const Particle &P, Nearest &r) {
+    constexpr int kRoot = (SHAPE & kRtkRootCsg) ? 1 : 0;
+    constexpr int kDepth = rtk_depth(SHAPE);
+    r.t = dinf();
+    r.level = GT_MAX_LEVELS;
+    r.surf = kNone;
+    r.entry = 0;
+    r.pos = false;
+    r.univ = g.root;
+    r.inst = 0;
+    double qx = P.x, qy = P.y, qz = P.z;
+    uint32_t univ = g.root;
+    int32_t fill = 0;
+#pragma unroll
+    for (int L = 0; L < kDepth; L++) {
+        const uint32_t c = lvl(P, L);
+        if (L > 0) {
+            const auto t = g.trans + 4 * (size_t)lvl(P, L - 1);
+            qx = qx - t[0];
+            qy = qy - t[1];
+            qz = qz - t[2];
+            univ = (uint32_t)(-fill - 1);
+        }
+        const Cell cc = ldv<Cell>(g.cell + c);
+        fill = cc.fill;
+        r.inst += cc.inst_off;
+        bool better;
+        if (L < kRoot) better = csg_level_distance(g, P, L, cc, qx, qy, qz, r);
+        else if (L < kDepth - 1) better = rect_level_distance(g, P, L, g.uarr + univ, c, qx, qy, qz, r);
+        else better = pin_level_distance(g, P, L, g.uarr + univ, c, qx, qy, qz, r);
+        if (better) r.univ = univ;
+    }
+    r.leaf_fill = fill;
+}
+
+// distance_to_surface over every level for the static-polymorphism
+// tracker: the kind read per level, arrays by index, every other universe
+// by its half-spaces (what the segment step needs, as nearest_surface).
+template <typename G>
+__device__ __forceinline__ void nearest_surface_sp(const G &g, const Particle &P, Nearest &r) {
     r.t = dinf();
     r.level = GT_MAX_LEVELS;
     r.surf = kNone;
@@ -908,15 +965,9 @@ __device__ __forceinline__ void nearest_surface_kinds(const G &g, const Particle
         const Cell cc = ldv<Cell>(g.cell + c);
         fill = cc.fill;
         r.inst += cc.inst_off;
-        const int kind = TRK == TRK_RTK ? rtk_kind(SHAPE, L) : g.uarr[univ].kind;
-        bool better;
-        if (kind == kKindRect) {
-            better = rect_level_distance(g, P, L, ldv<UArr>(g.uarr + univ), c, qx, qy, qz, r);
-        } else if (TRK == TRK_RTK && kind == kKindPin) {
-            better = pin_level_distance(g, P, L, ldv<UArr>(g.uarr + univ), c, qx, qy, qz, r);
-        } else {
-            better = csg_level_distance(g, P, L, cc, qx, qy, qz, r);
-        }
+        const bool better = g.uarr[univ].kind == kKindRect
+                                ? rect_level_distance(g, P, L, g.uarr + univ, c, qx, qy, qz, r)
+                                : csg_level_distance(g, P, L, cc, qx, qy, qz, r);
         if (better) r.univ = univ;
     }
     r.leaf_fill = fill;
@@ -1280,7 +1331,6 @@ __device__ void run_history(const G &g, const KParams &p, const KOut &o, uint64_
 // of their histories share one instruction stream per step.
 enum Mode : int { M_IDLE = 0, M_POS = 1, M_DIR = 2, M_SEARCH = 3, M_TRACK = 4 };
 
-constexpr uint32_t kChunk = 64;
 // Search levels a lane may take per loop trip: two lets a crossing of a
 // lattice cell and the descent into the pin below it finish in one trip, so
 // the lane still tracks a segment in that trip.
@@ -1652,11 +1702,11 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
                 if (pool_next == pool_end) {
                     const int leader = __ffsll((unsigned long long)idle) - 1;
                     unsigned long long base = 0;
-                    if ((int)__lane_id() == leader) base = queue.take(kChunk);
+                    if ((int)__lane_id() == leader) base = queue.take(p.wave_take);
                     base = __shfl(base, leader);
                     if (base >= queue.end) { drained = true; break; }
                     pool_next = base;
-                    pool_end = min((uint64_t)base + kChunk, queue.end);
+                    pool_end = min((uint64_t)base + p.wave_take, queue.end);
                 }
                 const uint64_t avail = pool_end - pool_next;
                 const uint32_t r = lane_rank(idle);
@@ -1726,9 +1776,9 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
         }
 
         // ---- up to kSearchLevels levels of find_cell / cross_surface (the
-        // fixed-depth tracker: every level, its loops over levels unrolled)
+        // fixed-depth tracker: every level below the crossing in this trip)
         constexpr int kLevelsPerTrip = TRK == TRK_RTK ? rtk_depth(SHAPE) : kSearchLevels;
-#pragma unroll
+#pragma unroll 1
         for (int sn = 0; sn < kLevelsPerTrip && mode == M_SEARCH && end == GT_END_NONE; sn++) {
             // local position and universe at level sL (translations applied
             // level by level from the global position, as in the descent)
@@ -1751,7 +1801,7 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
                 const int kind = TRK == TRK_RTK ? rtk_kind(SHAPE, sL) : g.uarr[su].kind;
                 if (kind == kKindRect || (TRK == TRK_RTK && kind == kKindPin)) {
                     by_kind = true;
-                    const UArr A = ldv<UArr>(g.uarr + su);
+                    const auto A = g.uarr + su;
                     if (kind == kKindRect)
                         c = sforce != kNone ? rect_cross(g, A, lvl(P, sL), sk, sfpos, qx, qy, qz)
                                             : rect_locate(g, A, qx, qy, qz);
@@ -1822,7 +1872,8 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
         if (mode == M_TRACK && end == GT_END_NONE) {
             Nearest nr;
             if constexpr (TRK == TRK_ST) nearest_surface(g, P, nr);
-            else nearest_surface_kinds<TRK, SHAPE>(g, P, nr);
+            else if constexpr (TRK == TRK_RTK) nearest_surface_rtk<SHAPE>(g, P, nr);
+            else nearest_surface_sp(g, P, nr);
             const double sig = g.sigma[nr.leaf_fill];
             const double sc = (p.source == 1) ? dinf() : P.tau / sig;
             const uint32_t inst = nr.inst;

@@ -977,6 +977,8 @@ void gt::fill_kparams(const gt_track_params *p, const gt_geometry *g, KParams &k
     kp.rec_k = (uint32_t)((uint64_t)p->record_first_k < p->n_particles ? p->record_first_k : p->n_particles);
     kp.rec_cap = p->record_cap;
     kp.refill_min = p->refill_min ? p->refill_min : kRefillMin;
+    kp.wave_take = p->wave_histories ? p->wave_histories : kWaveTake;
+    kp.pad = 0;
     ko.mesh = MeshDesc{};
     LaunchRec *lr;
     workspace_of(g, o, &lr, &ko.tally_ws);
@@ -1033,6 +1035,10 @@ int gt::check_track_args(const gt_geometry *g, const gt_track_params *p, const g
     if (p->block_size && (p->block_size % 64 || p->block_size > 1024))
         return set_error("gt_track: block_size must be a multiple of 64 up to 1024"), GT_EINVAL;
     if (p->refill_min > 64) return set_error("gt_track: refill_min must be at most 64"), GT_EINVAL;
+    if (p->wave_histories % 64 || p->wave_histories > 1024)
+        return set_error("gt_track: wave_histories must be a multiple of 64 up to 1024"), GT_EINVAL;
+    if (p->wave_histories && (p->flags & GT_FLAG_LANE_PER_HISTORY))
+        return set_error("gt_track: wave_histories needs the persistent schedule"), GT_EINVAL;
     if (p->regroup_every && (p->flags & GT_FLAG_LANE_PER_HISTORY))
         return set_error("gt_track: regroup_every needs the persistent schedule"), GT_EINVAL;
     if (p->first_particle + p->n_particles < p->first_particle)
@@ -1119,7 +1125,7 @@ extern "C" int gt_track_event(const gt_geometry *g, const gt_track_params *p, co
     if (rc) return rc;
     if (p->flags & ~GT_FLAG_ACCUMULATE)
         return set_error("gt_track_event: only GT_FLAG_ACCUMULATE applies"), GT_EINVAL;
-    if (p->block_size || p->refill_min || p->regroup_every)
+    if (p->block_size || p->refill_min || p->regroup_every || p->wave_histories)
         return set_error("gt_track_event: no launch shape to set"), GT_EINVAL;
     const uint64_t need = ev_layout(p->n_particles, nullptr, nullptr);
     if (p->n_particles && (!bank || bank_bytes < need))
@@ -1140,7 +1146,9 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
     const uint64_t chunk = tuning && tuning->chunk ? tuning->chunk : 4096;   // the tuner's choice on the 64-geometry batch
     if (block % 64 || block > 1024) return set_error("gt_batch_create: block_size must be a multiple of 64 up to 1024"), GT_EINVAL;
     if (refill > 64) return set_error("gt_batch_create: refill_min must be at most 64"), GT_EINVAL;
-    if (tuning && tuning->reserved) return set_error("gt_batch_create: tuning reserved must be 0"), GT_EINVAL;
+    const uint32_t wave = tuning ? tuning->wave_histories : 0;
+    if (wave % 64 || wave > 1024)
+        return set_error("gt_batch_create: wave_histories must be a multiple of 64 up to 1024"), GT_EINVAL;
     const uint32_t regroup =
         tuning && tuning->regroup_every ? tuning->regroup_every : items[0].params.regroup_every;
     try {
@@ -1174,6 +1182,7 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
             b.plan = g->stage[prec];
             gt_track_params p = it.params;
             p.refill_min = refill ? refill : p.refill_min;
+            p.wave_histories = wave ? wave : p.wave_histories;
             fill_kparams(&p, g, b.p, b.o, &it.out);
             kind[i] = (it.params.flags & GT_FLAG_NO_STAGING) ? 0 : (uint8_t)b.plan.kind;
             lds[kind[i]] = std::max(lds[kind[i]], kind[i] ? b.plan.total : 0u);

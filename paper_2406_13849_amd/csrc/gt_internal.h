@@ -25,6 +25,9 @@ constexpr unsigned kStageBudget = 160 * 1024 - GT_MAX_LEVELS * kBlockP * 4 - 102
 // new histories start together and their first searches (which rarely have
 // a good candidate) run once for several lanes.
 constexpr uint32_t kRefillMin = 8;
+// Histories a wave claims from the work queue at once by default (one per
+// lane): the pool it refills its lanes from.
+constexpr uint32_t kWaveTake = 64;
 
 constexpr uint32_t kLeafNone = 0xFFFFFFFFu;
 // int32 words of one tracking state given to gt_distance_to_surface: the
@@ -154,6 +157,7 @@ struct StagePlan {
 struct KParams {
     uint64_t seed, first, n;
     uint32_t geom_id, max_coll, source, ray_n1, max_segs, rec_k, rec_cap, refill_min;
+    uint32_t wave_take, pad;   // histories a wave claims from the queue at once (a multiple of 64)
 };
 
 // A superimposed mesh: bins n[0] x n[1] x n[2] over lo + [0, n] w, with its

@@ -1,6 +1,8 @@
 // Launch-shape autotuning for the persistent trackers.  The shape (threads
 // per workgroup, idle lanes before a wave refills, histories per batch
-// chunk) changes only the speed: every shape gives the same outputs.  The
+// chunk, the regroup interval, histories a wave claims at once -- the
+// particles per wavefront) changes only the speed: every shape gives the
+// same outputs.  The
 // tuner times the candidate shapes with HIP events on the caller's stream
 // and keeps the winner in a process-wide cache, which gt_batch_create reads
 // when it is given no tuning.
@@ -69,6 +71,8 @@ const uint32_t kBlocks[] = {256, 512, 640, 1024};
 const uint32_t kRefills[] = {1, 4, 8, 16};
 const uint64_t kChunks[] = {1024, 2048, 4096, 16384, 65536};
 const uint32_t kRegroups[] = {16, 64, 256};   // second stage, at the fastest shape of the first
+const uint32_t kWaveTakes[] = {128, 256};     // third stage: histories a wave claims at once (64 is the
+                                              // default the first two stages ran with)
 
 }  // namespace
 
@@ -89,6 +93,7 @@ extern "C" int gt_autotune_track(const gt_geometry *g, const gt_track_params *p,
         q.block_size = t.block_size;
         q.refill_min = t.refill_min;
         q.regroup_every = t.regroup_every;
+        q.wave_histories = t.wave_histories;
         float ms = 0;
         const int r = time_launches([&] { return launch_track(g, &q, o, stream); }, reps, st, &ms);
         if (!r && (!any || ms < win_ms)) {
@@ -104,11 +109,15 @@ extern "C" int gt_autotune_track(const gt_geometry *g, const gt_track_params *p,
     const gt_tuning shape = win;
     for (uint32_t rg : kRegroups)
         if ((rc = trial({shape.block_size, shape.refill_min, 0, rg, 0}))) return rc;
+    const gt_tuning shape2 = win;
+    for (uint32_t wt : kWaveTakes)
+        if ((rc = trial({shape2.block_size, shape2.refill_min, 0, shape2.regroup_every, wt}))) return rc;
     // leave the outputs of the caller's own parameters with the chosen shape
     gt_track_params q = *p;
     q.block_size = win.block_size;
     q.refill_min = win.refill_min;
     q.regroup_every = win.regroup_every;
+    q.wave_histories = win.wave_histories;
     rc = launch_track(g, &q, o, stream);
     if (rc) return rc;
     *best = win;
@@ -159,6 +168,9 @@ extern "C" int gt_autotune_batch(const gt_batch_item *items, uint32_t n_items, u
     const gt_tuning shape = win;
     for (uint32_t rg : kRegroups)
         if (int rc = trial({shape.block_size, shape.refill_min, shape.chunk, rg, 0})) return rc;
+    const gt_tuning shape2 = win;
+    for (uint32_t wt : kWaveTakes)
+        if (int rc = trial({shape2.block_size, shape2.refill_min, shape2.chunk, shape2.regroup_every, wt})) return rc;
     *best = win;
     if (best_ms) *best_ms = win_ms / (float)reps;
     std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -57,6 +57,7 @@ class _Params(C.Structure):
         ("ray_n1", C.c_uint32), ("max_segments", C.c_uint32), ("precision", C.c_uint32),
         ("record_first_k", C.c_uint32), ("record_cap", C.c_uint32), ("flags", C.c_uint32),
         ("block_size", C.c_uint32), ("refill_min", C.c_uint32), ("regroup_every", C.c_uint32),
+        ("wave_histories", C.c_uint32),
     ]
 
 
@@ -74,7 +75,7 @@ class _BatchItem(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("block_size", C.c_uint32), ("refill_min", C.c_uint32), ("chunk", C.c_uint64),
-                ("regroup_every", C.c_uint32), ("reserved", C.c_uint32)]
+                ("regroup_every", C.c_uint32), ("wave_histories", C.c_uint32)]
 
 
 class _Mesh(C.Structure):
@@ -278,7 +279,7 @@ def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 
           precision: int = PREC_MIXED, record_first_k: int = 0, record_cap: int = 0, accumulate: bool = False,
           lane_per_history: bool = False, staging: bool = True, block_size: int = 0, refill_min: int = 0,
           tail_compaction: bool = False, tally_cache: bool = True, regroup_every: int = 0, tracker: str = "st",
-          out: Optional[TrackOutputs] = None, stream=None) -> TrackOutputs:
+          wave_histories: int = 0, out: Optional[TrackOutputs] = None, stream=None) -> TrackOutputs:
     """gt_track: sample and track n_particles histories (asynchronous).
     lane_per_history selects the plain one-history-per-lane schedule instead
     of the persistent refilling one; staging=False keeps the geometry tables
@@ -288,12 +289,14 @@ def track(geom: Geometry, seed: int, n_particles: int, *, first_particle: int = 
     sorts a workgroup's histories by leaf universe every R loop trips;
     tracker selects the tracker method: "st" the single tracker (default),
     "sp" one tracker per universe kind switched per level, "rtk" the
-    fixed-depth reactor tracker (GT_FLAG_TRACKER_*)."""
+    fixed-depth reactor tracker (GT_FLAG_TRACKER_*); wave_histories is the
+    number of histories a wavefront claims from the queue at once (a
+    multiple of 64; 0 = 64)."""
     if out is None:
         out = alloc_outputs(geom, n_particles, record_first_k, record_cap)
     prm = _params(seed, n_particles, first_particle, geometry_id, max_collisions, source, ray_n1, max_segments,
                   precision, record_first_k, record_cap, accumulate, lane_per_history, staging, block_size,
-                  refill_min, tail_compaction, tally_cache, regroup_every, tracker)
+                  refill_min, tail_compaction, tally_cache, regroup_every, tracker, wave_histories)
     o = _out_struct(out)
     _check(lib().gt_track(geom.h, C.byref(prm), C.byref(o), _stream(stream)))
     return out
@@ -390,7 +393,7 @@ def track_event(geom: Geometry, seed: int, n_particles: int, *, bank=None, out: 
 def _params(seed, n_particles, first_particle=0, geometry_id=0, max_collisions=20, source=0, ray_n1=0,
             max_segments=100_000, precision=PREC_MIXED, record_first_k=0, record_cap=0, accumulate=False,
             lane_per_history=False, staging=True, block_size=0, refill_min=0, tail_compaction=False,
-            tally_cache=True, regroup_every=0, tracker="st") -> _Params:
+            tally_cache=True, regroup_every=0, tracker="st", wave_histories=0) -> _Params:
     if tracker not in TRACKER_FLAGS:
         raise ValueError("tracker must be one of %s" % sorted(TRACKER_FLAGS))
     return _Params(seed=seed, first_particle=first_particle, n_particles=n_particles, geometry_id=geometry_id,
@@ -399,7 +402,8 @@ def _params(seed, n_particles, first_particle=0, geometry_id=0, max_collisions=2
                    flags=(FLAG_ACCUMULATE if accumulate else 0) | (FLAG_LANE_PER_HISTORY if lane_per_history else 0)
                    | (0 if staging else FLAG_NO_STAGING) | (FLAG_TAIL_COMPACTION if tail_compaction else 0)
                    | (0 if tally_cache else FLAG_NO_TALLY_CACHE) | TRACKER_FLAGS[tracker],
-                   block_size=block_size, refill_min=refill_min, regroup_every=regroup_every)
+                   block_size=block_size, refill_min=refill_min, regroup_every=regroup_every,
+                   wave_histories=wave_histories)
 
 
 def _out_struct(out: TrackOutputs) -> _Out:
@@ -426,13 +430,13 @@ class Batch:
     tables and the outputs' addresses, so both are kept alive here."""
 
     def __init__(self, items, block_size: int = 0, refill_min: int = 0, chunk: int = 0, regroup_every: int = 0,
-                 tuned: bool = False):
+                 wave_histories: int = 0, tuned: bool = False):
         """tuned=True passes no tuning: the shape gt_autotune_batch found for
         these items (else the defaults)."""
         self.items = list(items)
         arr = _batch_array(self.items)
         tun = None if tuned else C.byref(_Tuning(block_size=block_size, refill_min=refill_min, chunk=chunk,
-                                                 regroup_every=regroup_every))
+                                                 regroup_every=regroup_every, wave_histories=wave_histories))
         h = C.c_void_p()
         _check(lib().gt_batch_create(arr, len(self.items), tun, C.byref(h)))
         self.h = h.value
@@ -460,18 +464,18 @@ def batch_item(geom: Geometry, seed: int, n_particles: int, out: Optional[TrackO
 
 
 def track_batch(items, block_size: int = 0, refill_min: int = 0, chunk: int = 0, regroup_every: int = 0,
-                tuned: bool = False, stream=None):
+                wave_histories: int = 0, tuned: bool = False, stream=None):
     """gt_track_batch: one-shot batch (waits for the stream)."""
     arr = _batch_array(items)
     tun = None if tuned else C.byref(_Tuning(block_size=block_size, refill_min=refill_min, chunk=chunk,
-                                             regroup_every=regroup_every))
+                                             regroup_every=regroup_every, wave_histories=wave_histories))
     _check(lib().gt_track_batch(arr, len(items), tun, _stream(stream)))
     return [it.out for it in items]
 
 
 def autotune_track(geom: Geometry, seed: int, n_particles: int, out: Optional[TrackOutputs] = None, reps: int = 3,
                    stream=None, **kwargs) -> dict:
-    """gt_autotune_track: the fastest (block_size, refill_min, regroup_every) for these
+    """gt_autotune_track: the fastest (block_size, refill_min, regroup_every, wave_histories) for these
     parameters (the outputs are overwritten and end as those of one launch
     with that shape); also cached in the library for gt_tuning_lookup."""
     if out is None:
@@ -482,7 +486,7 @@ def autotune_track(geom: Geometry, seed: int, n_particles: int, out: Optional[Tr
     _check(lib().gt_autotune_track(geom.h, C.byref(prm), C.byref(_out_struct(out)), reps, _stream(stream),
                                    C.byref(best), C.byref(ms)))
     return dict(block_size=best.block_size, refill_min=best.refill_min, regroup_every=best.regroup_every,
-                ms=ms.value)
+                wave_histories=best.wave_histories, ms=ms.value)
 
 
 def tuning_lookup(geom: Geometry, seed: int, n_particles: int, **kwargs) -> Optional[dict]:
@@ -492,8 +496,8 @@ def tuning_lookup(geom: Geometry, seed: int, n_particles: int, **kwargs) -> Opti
     rc = lib().gt_tuning_lookup(geom.h, C.byref(prm), C.byref(best))
     if rc < 0:
         _check(rc)
-    return (dict(block_size=best.block_size, refill_min=best.refill_min, regroup_every=best.regroup_every)
-            if rc == 1 else None)
+    return (dict(block_size=best.block_size, refill_min=best.refill_min, regroup_every=best.regroup_every,
+                 wave_histories=best.wave_histories) if rc == 1 else None)
 
 
 def _batch_array(items):
@@ -506,14 +510,14 @@ def _batch_array(items):
 
 
 def autotune_batch(items, reps: int = 1, stream=None) -> dict:
-    """gt_autotune_batch: the fastest (block_size, refill_min, chunk, regroup_every) for this
+    """gt_autotune_batch: the fastest (block_size, refill_min, chunk, regroup_every, wave_histories) for this
     list of items; Batch(items) and track_batch(items) then use it."""
     best = _Tuning()
     ms = C.c_float()
     _check(lib().gt_autotune_batch(_batch_array(items), len(items), reps, _stream(stream), C.byref(best),
                                    C.byref(ms)))
     return dict(block_size=best.block_size, refill_min=best.refill_min, chunk=best.chunk,
-                regroup_every=best.regroup_every, ms=ms.value)
+                regroup_every=best.regroup_every, wave_histories=best.wave_histories, ms=ms.value)
 
 
 def last_launch() -> Optional[dict]:

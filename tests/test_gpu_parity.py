@@ -233,6 +233,29 @@ def test_launch_shapes_do_not_change_results(block, lane, refill):
     assert_parity(g, o, where="block %d" % block)
 
 
+@pytest.mark.parametrize("wave", [64, 128, 256, 1024])
+@pytest.mark.parametrize("cfg,n", [(2, 20_000), (3, 30_000)])
+def test_histories_per_wave_claim(wave, cfg, n):
+    """The number of histories a wavefront claims from the queue at once
+    (the particles per wavefront of a claim) changes no output, also when it
+    does not divide the number of histories; batches take it from their
+    tuning."""
+    fg, G, O = geoms(cfg)
+    kw = dict(seed=808, n_particles=n + 17, geometry_id=cfg)
+    print("wave claim %d, cfg%d" % (wave, cfg), flush=True)
+    g = gpu_track(G, precision=gt.PREC_MIXED, wave_histories=wave, record_first_k=100, record_cap=256, **kw)
+    o = oracle.track(O, oracle.TrackParams(record_first_k=100, record_cap=256, **kw), n_threads=NT)
+    assert_parity(g, o, where="wave %d" % wave)
+    if cfg == 2:
+        it = gt.batch_item(G, kw["seed"], kw["n_particles"], geometry_id=cfg)
+        gt.track_batch([it], chunk=3000, wave_histories=wave)
+        o2 = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT)
+        assert_parity(_outs(it.out), o2, where="batch wave %d" % wave)
+    for bad in (32, 1088):
+        with pytest.raises(gt.GtError):
+            gt.track(G, wave_histories=bad, **kw)
+
+
 @pytest.mark.parametrize("cfg", [1, 2, 4])
 @pytest.mark.parametrize("block", [128, 640, 1024])
 def test_with_tail_compaction(cfg, block):
@@ -744,8 +767,9 @@ def test_autotune_track_keeps_results():
     shape = gt.autotune_track(G, out=out, reps=1, precision=gt.PREC_MIXED, **kw)
     assert shape["block_size"] in (256, 512, 640, 1024) and shape["refill_min"] in (1, 4, 8, 16)
     assert shape["regroup_every"] in (0, 16, 64, 256)
+    assert shape["wave_histories"] in (0, 128, 256)
     assert gt.tuning_lookup(G, precision=gt.PREC_MIXED, **kw) == {
-        k: shape[k] for k in ("block_size", "refill_min", "regroup_every")}
+        k: shape[k] for k in ("block_size", "refill_min", "regroup_every", "wave_histories")}
     import torch
     torch.cuda.synchronize()
     o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT)
