@@ -1025,6 +1025,26 @@ __device__ __forceinline__ double mesh_cut(const MeshDesc &m, int a, int k, doub
     return (x - p0) / u;
 }
 
+// floor(d / w), the bin index of a coordinate d past the mesh's low face,
+// as the definition forms it: from the product with the reciprocal when that
+// is clearly away from an integer (the two quotients are within a few ulps
+// of each other, so they then have the same floor), else from the division.
+__device__ __forceinline__ double mesh_floor(double d, double w, double iw) {
+    const double q = d * iw;
+    const double fq = floor(q);
+    const double r = q - fq;
+    const double tol = 0x1p-50 * fabs(q) + 0x1p-1000;
+    return (r > tol && r < 1.0 - tol) ? fq : floor(d / w);
+}
+
+// mesh_cut(k) > 0 without the division: a nonzero difference divided by
+// |u| <= 1 cannot round to zero, so the quotient is positive exactly when
+// the difference has the sign of u.
+__device__ __forceinline__ bool mesh_cut_ahead(const MeshDesc &m, int a, int k, double p0, double u) {
+    const double d = (m.lo[a] + (double)k * m.w[a]) - p0;
+    return u > 0.0 ? d > 0.0 : d < 0.0;
+}
+
 __device__ __forceinline__ void mesh_segment(const MeshDesc &m, uint64_t *rep, TallyAcc &acc, const double p0[3],
                                              const double u[3], double l) {
     int k[3], step[3];
@@ -1035,20 +1055,21 @@ __device__ __forceinline__ void mesh_segment(const MeshDesc &m, uint64_t *rep, T
         k[a] = 0;
         if (u[a] == 0.0) continue;
         const int n = (int)m.n[a];
-        const double f = floor((p0[a] - m.lo[a]) / m.w[a]);
+        // first guess of the plane index by the reciprocal, then exact steps
+        const double f = floor((p0[a] - m.lo[a]) * m.iw[a]);
         if (u[a] > 0.0) {
             // first k with a cut ahead (t > 0): near floor(...) + 1, then exact
             int kk = f < -1.0 ? 0 : (f > (double)n ? n + 1 : (int)f + 1);
-            while (kk > 0 && mesh_cut(m, a, kk - 1, p0[a], u[a]) > 0.0) kk--;
-            while (kk <= n && !(mesh_cut(m, a, kk, p0[a], u[a]) > 0.0)) kk++;
+            while (kk > 0 && mesh_cut_ahead(m, a, kk - 1, p0[a], u[a])) kk--;
+            while (kk <= n && !mesh_cut_ahead(m, a, kk, p0[a], u[a])) kk++;
             k[a] = kk;
             step[a] = 1;
             if (kk <= n) tn[a] = mesh_cut(m, a, kk, p0[a], u[a]);
         } else {
             // last k with a cut ahead, walking down
             int kk = f < -1.0 ? -1 : (f > (double)n ? n : (int)f);
-            while (kk < n && mesh_cut(m, a, kk + 1, p0[a], u[a]) > 0.0) kk++;
-            while (kk >= 0 && !(mesh_cut(m, a, kk, p0[a], u[a]) > 0.0)) kk--;
+            while (kk < n && mesh_cut_ahead(m, a, kk + 1, p0[a], u[a])) kk++;
+            while (kk >= 0 && !mesh_cut_ahead(m, a, kk, p0[a], u[a])) kk--;
             k[a] = kk;
             step[a] = -1;
             if (kk >= 0) tn[a] = mesh_cut(m, a, kk, p0[a], u[a]);
@@ -1070,7 +1091,7 @@ __device__ __forceinline__ void mesh_segment(const MeshDesc &m, uint64_t *rep, T
         bool inside = true;
         for (int a = 0; a < 3; a++) {
             const double mid = p0[a] + tm * u[a];
-            const double f = floor((mid - m.lo[a]) / m.w[a]);
+            const double f = mesh_floor(mid - m.lo[a], m.w[a], m.iw[a]);
             inside = inside && f >= 0.0 && f < (double)m.n[a];
             idx[a] = inside ? (uint32_t)f : 0u;
         }

@@ -164,6 +164,7 @@ struct KParams {
 // per-XCD replicas of per-bin limb counters (ws == nullptr: no mesh).
 struct MeshDesc {
     double lo[3], w[3];
+    double iw[3];       // 1 / w: only for the first guess of a plane index, corrected exactly
     uint32_t n[3], pad;
     uint64_t *ws;
     uint64_t nb;

@@ -609,6 +609,7 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
         for (int a = 0; a < 3; a++) {
             m.lo[a] = mesh->lo[a];
             m.w[a] = (mesh->hi[a] - mesh->lo[a]) / (double)mesh->n[a];
+            m.iw[a] = 1.0 / m.w[a];
             m.n[a] = mesh->n[a];
         }
         m.nb = (uint64_t)mesh->n[0] * mesh->n[1] * mesh->n[2];

@@ -136,6 +136,13 @@ extern "C" int cpu_track_kinds(const gt_geometry *g, const gt_track_params *p, c
     return GT_OK;
 }
 
+// The mesh walk's bin index (reciprocal fast path with the division as the
+// fallback) for n coordinates, for a test against floor(d / w).
+extern "C" void cpu_mesh_floor(const double *d, uint64_t n, double w, double *out) {
+    const double iw = 1.0 / w;
+    for (uint64_t i = 0; i < n; i++) out[i] = mesh_floor(d[i], w, iw);
+}
+
 // gt_track_mesh on the CPU: cpu_track with the mesh tally (the kernel's
 // mesh walk), host pointers throughout; the workspace holds the replicas.
 extern "C" int cpu_track_mesh(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o,
@@ -151,6 +158,7 @@ extern "C" int cpu_track_mesh(const gt_geometry *g, const gt_track_params *p, co
     for (int a = 0; a < 3; a++) {
         md.lo[a] = m->lo[a];
         md.w[a] = (m->hi[a] - m->lo[a]) / (double)m->n[a];
+        md.iw[a] = 1.0 / md.w[a];
         md.n[a] = m->n[a];
     }
     md.nb = (uint64_t)m->n[0] * m->n[1] * m->n[2];

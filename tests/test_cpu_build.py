@@ -309,3 +309,25 @@ def test_cpu_mesh_tally_matches_oracle(host, geom, cover, bins):
         assert np.array_equal(msum, o.mesh_fxd)
         assert (mfx[:, 1] > 0).sum() > 0
     host.L.gt_geometry_destroy(h)
+
+
+def test_mesh_floor_matches_division(host):
+    """The mesh walk's bin index from the reciprocal (with the division as
+    the fallback near integers) equals floor(d / w) for coordinates on, next
+    to and between the planes of meshes of the benchmark's and odd widths."""
+    rng = np.random.default_rng(11)
+    host.L.cpu_mesh_floor.argtypes = [C.c_void_p, C.c_uint64, C.c_double, C.c_void_p]
+    host.L.cpu_mesh_floor.restype = None
+    for lo, hi, n in ((-140.0, 140.0, 119), (-100.0, 100.0, 30), (-10.625, 10.625, 17), (0.0, 1.0, 3),
+                      (-1.875, 1.875, 7), (-3.3, 7.1, 113)):
+        w = (hi - lo) / n
+        k = rng.integers(-2, n + 3, size=20000).astype(np.float64)
+        planes = lo + k * w
+        near = np.concatenate([planes, np.nextafter(planes, np.inf), np.nextafter(planes, -np.inf),
+                               np.nextafter(np.nextafter(planes, np.inf), np.inf),
+                               planes + rng.uniform(-1e-12, 1e-12, planes.size),
+                               rng.uniform(lo - w, hi + w, 40000)])
+        d = near - lo
+        out = np.empty_like(d)
+        host.L.cpu_mesh_floor(d.ctypes.data, d.size, w, out.ctypes.data)
+        assert np.array_equal(out, np.floor(d / w)), (lo, hi, n)
