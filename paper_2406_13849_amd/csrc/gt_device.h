@@ -218,6 +218,23 @@ __device__ __forceinline__ double plane_value(uint32_t type, CP c, double x, dou
     }
 }
 
+// plane_value split as linear part minus offset (the same operations):
+// the coordinate, or ((a x + b y) + c z); then d.
+template <typename CP>
+__device__ __forceinline__ double plane_linear(uint32_t type, CP c, double x, double y, double z) {
+    switch (type) {
+    case ST_PX: return x;
+    case ST_PY: return y;
+    case ST_PZ: return z;
+    default: return (c[0] * x + c[1] * y) + c[2] * z;
+    }
+}
+
+template <typename CP>
+__device__ __forceinline__ double plane_offset(uint32_t type, CP c) {
+    return type == ST_P ? c[3] : c[0];
+}
+
 template <typename CP>
 __device__ __forceinline__ double quad_value(uint32_t type, CP c, double x, double y, double z) {
     const double dx = x - c[0], dy = y - c[1];
@@ -234,8 +251,20 @@ __device__ __forceinline__ bool contains(const G &g, uint32_t c, double x, doubl
     const Cell cc = ldv<Cell>(g.cell + c);
     fill = cc.fill;
     const auto hs = g.hs + cc.hs_off;
-    const uint32_t npl = cc.n_pl & kPlaneCountMask;
-    for (uint32_t k = 0; k < npl; k++) {
+    const uint32_t npl = cc.n_pl & kPlaneCountMask, npair2 = 2u * (cc.n_pl >> 12);
+    for (uint32_t k = 0; k < npair2; k += 2) {
+        // a slab pair: one plane family, so both planes' values take the same
+        // coordinate, or the same dot product with their bitwise-identical
+        // normal, minus their own offsets (the arithmetic of plane_value)
+        const uint32_t h0 = hs[k], h1 = hs[k + 1];
+        const uint32_t s0 = h0 >> 4, s1 = h1 >> 4, t = h0 & 7u;
+        const auto c0 = g.coef + 4 * (size_t)s0, c1 = g.coef + 4 * (size_t)s1;
+        const double lin = plane_linear(t, c0, x, y, z);
+        const bool p0 = (s0 == force_s) ? force_pos : (lin - plane_offset(t, c0) > 0.0);
+        const bool p1 = (s1 == force_s) ? force_pos : (lin - plane_offset(t, c1) > 0.0);
+        if (p0 != (bool)((h0 >> 3) & 1u) || p1 != (bool)((h1 >> 3) & 1u)) return false;
+    }
+    for (uint32_t k = npair2; k < npl; k++) {
         const uint32_t h = hs[k];
         const uint32_t s = h >> 4;
         const bool pos = (s == force_s) ? force_pos : (plane_value(h & 7u, g.coef + 4 * (size_t)s, x, y, z) > 0.0);
@@ -521,11 +550,14 @@ __device__ __forceinline__ void nearest_surface(const G &g, const Particle &P, N
             // would give no hit.  No branches: a plane that cannot be hit, or was
             // just crossed, gets +inf.
             const uint32_t h0 = hs[k], h1 = hs[k + 1];
-            const double den = plane_den(h0 & 7u, g.coef + 4 * (size_t)(h0 >> 4), P.u, P.v, P.w);
+            const auto c0 = g.coef + 4 * (size_t)(h0 >> 4);
+            const double den = plane_den(h0 & 7u, c0, P.u, P.v, P.w);
             const uint32_t kk = den > 0.0 ? k : k + 1;
             const uint32_t h = den > 0.0 ? h0 : h1;
             const uint32_t s = h >> 4;
-            const double t = (-plane_value(h & 7u, g.coef + 4 * (size_t)s, qx, qy, qz)) / den;
+            // the pair shares its normal: the linear part from h0's record, the
+            // offset from the reached plane's (the operations of plane_value)
+            const double t = (-(plane_linear(h0 & 7u, c0, qx, qy, qz) - plane_offset(h & 7u, g.coef + 4 * (size_t)s))) / den;
             const bool skip = den == 0.0 || (P.on_level == L && P.on_surf == s);
             const double d = skip ? dinf() : ((t > 0.0) ? t : 0.0);
             if (d < r.t || (d == r.t && d != dinf() && L == r.level && s < r.surf)) {
@@ -781,11 +813,14 @@ __device__ __forceinline__ bool csg_level_distance(const G &g, const Particle &P
     bool better = false;
     for (uint32_t k = 0; k < npair2; k += 2) {
         const uint32_t h0 = hs[k], h1 = hs[k + 1];
-        const double den = plane_den(h0 & 7u, g.coef + 4 * (size_t)(h0 >> 4), P.u, P.v, P.w);
+        const auto c0 = g.coef + 4 * (size_t)(h0 >> 4);
+        const double den = plane_den(h0 & 7u, c0, P.u, P.v, P.w);
         const uint32_t kk = den > 0.0 ? k : k + 1;
         const uint32_t h = den > 0.0 ? h0 : h1;
         const uint32_t s = h >> 4;
-        const double t = (-plane_value(h & 7u, g.coef + 4 * (size_t)s, qx, qy, qz)) / den;
+        // the pair shares its normal: the linear part from h0's record, the
+        // offset from the reached plane's (the operations of plane_value)
+        const double t = (-(plane_linear(h0 & 7u, c0, qx, qy, qz) - plane_offset(h & 7u, g.coef + 4 * (size_t)s))) / den;
         const bool skip = den == 0.0 || (P.on_level == L && P.on_surf == s);
         const double d = skip ? dinf() : ((t > 0.0) ? t : 0.0);
         better |= nearer(r, d, L, s, den < 0.0, cc.hs_off + kk);
