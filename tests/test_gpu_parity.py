@@ -969,3 +969,35 @@ def test_kind_trackers_refused_where_not_built():
         gt.track_mesh(G, 1, 100, fg.domain_lo, fg.domain_hi, (4, 4, 4), geometry_id=2, tracker="sp")
     with pytest.raises(gt.GtError):
         gt.track_batch([gt.batch_item(G, 1, 100, geometry_id=2, tracker="sp")])
+
+
+@pytest.mark.parametrize("tracker", ["sp", "rtk"])
+def test_kind_trackers_edge_cases(tracker):
+    """The per-kind trackers on the edge cases of the single tracker: segment
+    and collision caps, 40-bit particle ids, one and 65 histories, ray mode
+    (parallel rays through the lattice: every boundary crossed by index),
+    accumulation into existing tallies, an empty launch."""
+    fg, G, O = geoms(2)
+    base = dict(seed=7, n_particles=3000, geometry_id=2)
+    for extra in (dict(max_segments=5), dict(max_collisions=1), dict(first_particle=123_456_789_012),
+                  dict(n_particles=1), dict(n_particles=65), dict(max_segments=1),
+                  dict(n_particles=1700 * 22, source=1, ray_n1=1700, max_collisions=1)):
+        kw = dict(base, **extra)
+        print("tracker %s, %s" % (tracker, extra), flush=True)
+        g = gpu_track(G, record_first_k=70, record_cap=4, tracker=tracker, **kw)
+        o = oracle.track(O, oracle.TrackParams(record_first_k=70, record_cap=4, **kw), n_threads=NT)
+        assert_parity(g, o, where="%s %s" % (tracker, extra))
+    # two halves accumulated give the tallies of the whole
+    import torch
+    out = gt.alloc_outputs(G, 2000)
+    gt.track(G, seed=99, n_particles=1000, geometry_id=2, tracker=tracker, out=out)
+    first = out.tally_fx.clone()
+    out2 = gt.alloc_outputs(G, 1000)
+    out2.tally_fx.copy_(first)
+    gt.track(G, seed=99, first_particle=1000, n_particles=1000, geometry_id=2, tracker=tracker, accumulate=True,
+             out=out2)
+    torch.cuda.synchronize()
+    o = oracle.track(O, oracle.TrackParams(seed=99, n_particles=2000, geometry_id=2), n_threads=NT)
+    assert np.array_equal(out2.tally_fx.cpu().numpy().view(np.uint64), o.tally_fx)
+    g = gpu_track(G, seed=1, n_particles=0, tracker=tracker)
+    assert not g["tally_fx"].any() and sum(g["counters"].values()) == 0
