@@ -363,16 +363,25 @@ typedef struct {
 typedef struct {
     uint32_t block_size;   /* threads per workgroup, multiple of 64 up to 1024; 0 = 1024      */
     uint32_t refill_min;   /* as gt_track_params.refill_min; 0 = 8                             */
-    uint64_t chunk;        /* histories per work item taken from the device queue; 0 = 4096   */
+    uint64_t chunk;        /* histories per work item taken from the device queue; 0 = whole
+                              items: a workgroup joins an item and claims its histories
+                              until none is left (see gt_batch_create)                       */
     uint32_t regroup_every;/* as gt_track_params.regroup_every; 0 = that of the first item    */
     uint32_t wave_histories; /* as gt_track_params.wave_histories; 0 = each item's own          */
 } gt_tuning;               /* a NULL gt_tuning* means: the shape gt_autotune_batch found for
                               the same items in this process, else the defaults              */
 
 /* Validate a batch and upload its descriptors: per item the geometry
- * tables, parameters and output pointers; a work list of (item, particle
- * range) chunks, largest items first.  The histories are exactly those each
- * item's gt_track call would track, with identical outputs. */
+ * tables, parameters and output pointers, and the work list, largest items
+ * first (estimated work: histories x nesting depth).  With chunk > 0 the
+ * work list holds (item, particle range) chunks that workgroups take one at
+ * a time, their waves meeting at the end of each.  With chunk = 0 (whole
+ * items) it lists the items: workgroups first spread over the items in
+ * proportion to their estimated work, each workgroup's waves then claim
+ * their item's histories from its counter (shared by the workgroups on the
+ * item) until none is left, and the workgroup then joins the item with the
+ * most estimated work left per workgroup on it.  The histories are exactly
+ * those each item's gt_track call would track, with identical outputs. */
 int gt_batch_create(const gt_batch_item *items, uint32_t n_items, const gt_tuning *tuning, gt_batch **out);
 /* Errors: GT_EINVAL for an empty batch, a rejected item (the message names
  * it), mixed precisions, GT_FLAG_LANE_PER_HISTORY, a geometry used twice or
@@ -415,7 +424,7 @@ int gt_autotune_track(const gt_geometry *g, const gt_track_params *p, const gt_t
 int gt_tuning_lookup(const gt_geometry *g, const gt_track_params *p, gt_tuning *out);
 
 /* Time gt_batch_launch for block_size in {512, 640, 1024} x refill_min in
- * {1, 4, 8, 16} x chunk in {1024, 2048, 4096, 16384, 65536}, then the fastest of these
+ * {1, 4, 8, 16} x chunk in {0 (whole items), 1024, 4096, 16384}, then the fastest of these
  * with regroup_every in {16, 64, 256}; *best gets the fastest.  The
  * winner is cached in the process for this list of (geometry, histories,
  * precision): gt_batch_create and gt_track_batch given a NULL tuning use it. */

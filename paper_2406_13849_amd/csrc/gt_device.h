@@ -1480,8 +1480,10 @@ __device__ __forceinline__ typename ViewOf<KIND>::type make_view(const Dev &g, c
 }
 
 // Particle-id sources for the state machine below: a global counter over
-// [0, end) for one geometry, or a workgroup (LDS) counter over one chunk of
-// a batch item.  take() is called by one lane and returns the first of k ids.
+// [0, end) for one geometry, or, in a batch, a counter over one chunk of an
+// item (in LDS) or over all of an item's histories (in device memory, shared
+// by the workgroups on the item).  take() is called by one lane and returns
+// the first of k ids.
 struct GlobalQueue {
     unsigned long long *ctr;
     uint64_t end;
@@ -1489,12 +1491,86 @@ struct GlobalQueue {
 };
 
 struct ChunkQueue {
-    unsigned long long *ctr;   // LDS
+    unsigned long long *ctr;   // LDS or device memory
     uint64_t first, end;
     __device__ __forceinline__ uint64_t take(uint64_t k) const {
         return first + atomicAdd(ctr, (unsigned long long)k);
     }
 };
+
+// Which item of a batch launch a workgroup works on next, when workgroups
+// join whole items.  Every lane of the workgroup calls it; lane 0 stores the
+// item (kNoItem once every item's histories are claimed) in *pick and counts
+// the workgroup in workers[item]; the caller's barrier publishes it.
+//  * first call: the workgroups are spread over the slots in proportion to
+//    their estimated work (n x weight): workgroup b takes the slot whose
+//    running sum first exceeds (b + 1/2) / grid of the total;
+//  * later calls: the item with the most estimated work left per workgroup
+//    on it, counting the one joining -- (n - claimed) x weight / (workers + 1).
+// Only the order in which histories run depends on this choice, never a
+// result.  The counters are read with agent-scope atomic loads after the
+// barrier that ends a visit, so a workgroup that has seen an item's counter
+// reach n never chooses that item again: a visit that claims nothing finds
+// its item exhausted, each workgroup makes at most (its claims + the number
+// of items) visits, and the loop over visits ends.  red_s, red_i: LDS, one
+// entry per wave.
+__device__ __forceinline__ void pick_item(const BatchSlot *slots, uint32_t n_slots, unsigned long long *claimed,
+                                          unsigned long long *workers, bool first, float *red_s, uint32_t *red_i,
+                                          uint32_t *pick) {
+    if (first) {
+        if (threadIdx.x == 0) {
+            const double total = slots[n_slots - 1].cum;
+            const double at = ((double)blockIdx.x + 0.5) / (double)gridDim.x * total;
+            uint32_t lo = 0, hi = n_slots - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) / 2;
+                if (slots[mid].cum > at) hi = mid;
+                else lo = mid + 1;
+            }
+            const uint32_t it = slots[lo].item;
+            atomicAdd(&workers[it], 1ull);
+            *pick = it;
+        }
+        return;
+    }
+    float best = 0.0f;
+    uint32_t bi = kNoItem;
+    for (uint32_t s = threadIdx.x; s < n_slots; s += blockDim.x) {
+        const BatchSlot sl = slots[s];
+        const uint64_t c = __hip_atomic_load(&claimed[sl.item], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (c >= sl.n) continue;
+        const uint64_t w = __hip_atomic_load(&workers[sl.item], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const float score = (float)(sl.n - c) * sl.weight / (float)(w + 1);
+        if (bi == kNoItem || score > best) {
+            best = score;
+            bi = sl.item;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {   // the wave's best (lowest item among equal scores)
+        const float bs = __shfl_xor(best, o);
+        const uint32_t bo = __shfl_xor(bi, o);
+        if (bo != kNoItem && (bi == kNoItem || bs > best || (bs == best && bo < bi))) {
+            best = bs;
+            bi = bo;
+        }
+    }
+    if (__lane_id() == 0) {
+        red_s[threadIdx.x / 64] = best;
+        red_i[threadIdx.x / 64] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float b = 0.0f;
+        uint32_t it = kNoItem;
+        for (uint32_t w = 0; w < (blockDim.x + 63) / 64; w++)
+            if (red_i[w] != kNoItem && (it == kNoItem || red_s[w] > b || (red_s[w] == b && red_i[w] < it))) {
+                b = red_s[w];
+                it = red_i[w];
+            }
+        if (it != kNoItem) atomicAdd(&workers[it], 1ull);
+        *pick = it;
+    }
+}
 
 // Meetings of the workgroup's waves.  The persistent loop runs per wave;
 // two optional, result-neutral steps make the waves meet at a barrier and

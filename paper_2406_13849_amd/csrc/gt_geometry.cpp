@@ -1143,7 +1143,9 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
     if (!tuning && cached_batch_tuning(items, n_items, &cached)) tuning = &cached;
     const uint32_t block = tuning && tuning->block_size ? tuning->block_size : 1024;
     const uint32_t refill = tuning && tuning->refill_min ? tuning->refill_min : 0;
-    const uint64_t chunk = tuning && tuning->chunk ? tuning->chunk : 4096;   // the tuner's choice on the 64-geometry batch
+    // 0: workgroups join whole items (the default); else histories per chunk
+    const uint64_t chunk = tuning ? tuning->chunk : 0;
+    const bool by_item = chunk == 0;
     if (block % 64 || block > 1024) return set_error("gt_batch_create: block_size must be a multiple of 64 up to 1024"), GT_EINVAL;
     if (refill > 64) return set_error("gt_batch_create: refill_min must be at most 64"), GT_EINVAL;
     const uint32_t wave = tuning ? tuning->wave_histories : 0;
@@ -1200,22 +1202,36 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
                              return a.first > b.first;
                          });
         std::vector<BatchChunk> chunks;
-        uint32_t n_kind[4] = {0, 0, 0, 0};
+        std::vector<BatchSlot> slots;
+        uint32_t n_kind[4] = {0, 0, 0, 0}, n_slot_kind[4] = {0, 0, 0, 0};
+        uint64_t n_hist_kind[4] = {0, 0, 0, 0};
         for (int k = 3; k >= 0; k--) {
-            const size_t before = chunks.size();
+            const size_t before = chunks.size(), before_s = slots.size();
+            double cum = 0.0;
             for (const auto &o : order) {
                 const uint32_t i = o.second;
                 if (kind[i] != k) continue;
                 const uint64_t n = items[i].params.n_particles;
-                for (uint64_t f = 0; f < n; f += chunk) chunks.push_back({i, 0, f, std::min(chunk, n - f)});
+                if (n == 0) continue;
+                n_hist_kind[k] += n;
+                if (by_item) {
+                    const float w = (float)items[i].geometry->max_depth;
+                    cum += (double)n * w;
+                    slots.push_back({i, w, n, cum});
+                } else {
+                    for (uint64_t f = 0; f < n; f += chunk) chunks.push_back({i, 0, f, std::min(chunk, n - f)});
+                }
             }
             n_kind[k] = (uint32_t)(chunks.size() - before);
+            n_slot_kind[k] = (uint32_t)(slots.size() - before_s);
         }
         if (chunks.size() > 0xFFFFFFF0u) return set_error("gt_batch_create: too many chunks"), GT_ECAPACITY;
         // Before anything reaches the device: the chunk groups are ordered by
         // kind (3 .. 0) and sized by n_kind, each chunk names an item of its
         // group's kind and is non-empty and at most `chunk` long, and each
-        // item's chunks cover its histories [0, n) once, in order.
+        // item's chunks cover its histories [0, n) once, in order; or, with
+        // whole items, every item with histories has one slot, in its kind's
+        // group, with its n, a positive weight and a rising running sum.
         {
             std::vector<uint64_t> covered(n_items, 0);
             size_t at = 0;
@@ -1228,17 +1244,35 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
                     covered[ch.item] += ch.count;
                 }
             if (at != chunks.size()) return set_error("gt_batch_create: chunk groups do not add up"), GT_EINVAL;
+            at = 0;
+            for (int k = 3; k >= 0; k--) {
+                double prev = 0.0;
+                for (uint32_t c = 0; c < n_slot_kind[k]; c++, at++) {
+                    const BatchSlot &sl = slots[at];
+                    if (sl.item >= n_items || kind[sl.item] != k || sl.n == 0 || covered[sl.item] != 0 ||
+                        sl.n != items[sl.item].params.n_particles || !(sl.weight > 0.0f) || !(sl.cum > prev))
+                        return set_error("gt_batch_create: item slot %zu is inconsistent", at), GT_EINVAL;
+                    covered[sl.item] = sl.n;
+                    prev = sl.cum;
+                }
+            }
+            if (at != slots.size()) return set_error("gt_batch_create: item groups do not add up"), GT_EINVAL;
             for (uint32_t i = 0; i < n_items; i++)
                 if (covered[i] != items[i].params.n_particles)
-                    return set_error("gt_batch_create: item %u's histories are not covered by its chunks", i),
+                    return set_error("gt_batch_create: item %u's histories are not covered by its %s", i,
+                                     by_item ? "slot" : "chunks"),
                            GT_EINVAL;
         }
-        // one device allocation: items, chunks, fills, finalize items, four queue counters
+        // one device allocation: items, chunks, item slots, fills, finalize
+        // items, then the counters: four queue counters (one per staging
+        // kind), each item's claim counter and each item's workgroup count
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        const size_t n_ctr = 4 + 2 * (size_t)n_items;
         const size_t o_items = 0;
         const size_t o_chunks = al(o_items + bi.size() * sizeof(BatchItem));
-        const size_t o_queue = al(o_chunks + std::max<size_t>(chunks.size(), 1) * sizeof(BatchChunk));
-        const size_t o_fill = al(o_queue + 4 * sizeof(unsigned long long));
+        const size_t o_slots = al(o_chunks + std::max<size_t>(chunks.size(), 1) * sizeof(BatchChunk));
+        const size_t o_queue = al(o_slots + std::max<size_t>(slots.size(), 1) * sizeof(BatchSlot));
+        const size_t o_fill = al(o_queue + n_ctr * sizeof(unsigned long long));
         const size_t o_fin = al(o_fill + (fills.size() + 1) * sizeof(FillRange));
         const size_t total = al(o_fin + fin.size() * sizeof(FinalizeItem));
         int cur = 0;
@@ -1248,11 +1282,12 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
         hipError_t e = hipMalloc(&dm, total);
         if (e != hipSuccess) return set_error("hipMalloc(%zu): %s", total, hipGetErrorString(e)), GT_ENOMEM;
         unsigned char *base = (unsigned char *)dm;
-        fills.push_back({base + o_queue, 4, 0, 8, 0});
+        fills.push_back({base + o_queue, n_ctr, 0, 8, 0});
         for (const FillRange &f : fills) max_fill = std::max(max_fill, f.count);
         std::vector<unsigned char> img(total, 0);
         std::memcpy(img.data() + o_items, bi.data(), bi.size() * sizeof(BatchItem));
         if (!chunks.empty()) std::memcpy(img.data() + o_chunks, chunks.data(), chunks.size() * sizeof(BatchChunk));
+        if (!slots.empty()) std::memcpy(img.data() + o_slots, slots.data(), slots.size() * sizeof(BatchSlot));
         std::memcpy(img.data() + o_fill, fills.data(), fills.size() * sizeof(FillRange));
         std::memcpy(img.data() + o_fin, fin.data(), fin.size() * sizeof(FinalizeItem));
         e = hipMemcpy(dm, img.data(), total, hipMemcpyHostToDevice);
@@ -1277,6 +1312,15 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
         b->d_fin = (FinalizeItem *)(base + o_fin);
         b->max_inst = max_inst;
         b->d_queue = (unsigned long long *)(base + o_queue);
+        b->by_item = by_item;
+        b->d_slots = (BatchSlot *)(base + o_slots);
+        b->n_slots = (uint32_t)slots.size();
+        for (int k = 0; k < 4; k++) {
+            b->n_slot_kind[k] = n_slot_kind[k];
+            b->n_hist_kind[k] = n_hist_kind[k];
+        }
+        b->d_claimed = b->d_queue + 4;
+        b->d_workers = b->d_queue + 4 + n_items;
         for (int k = 0; k < 4; k++) b->lds_bytes[k] = lds[k];
         b->tail = (items[0].params.flags & GT_FLAG_TAIL_COMPACTION) != 0;
         b->regroup = regroup;

@@ -219,6 +219,17 @@ struct BatchChunk {
     uint64_t first, count;
 };
 
+// One item of a batch launch whose workgroups join whole items (chunk = 0):
+// its histories, the estimated cost of one of them, and the running sum of
+// n * weight over the launch's slots up to and including this one.
+struct BatchSlot {
+    uint32_t item;
+    float weight;
+    uint64_t n;
+    double cum;
+};
+constexpr uint32_t kNoItem = 0xFFFFFFFFu;
+
 // Particle bank of the event-based schedule: structure of arrays in device
 // memory, n entries each (the caller's buffer, laid out by ev_layout).
 struct EvBank {
@@ -278,6 +289,15 @@ struct gt_batch {
     gt::BatchChunk *d_chunks;           // chunks by staging kind: kind 3, then 2, 1, 0
     uint32_t n_chunks;
     uint32_t n_kind[4];
+    // workgroups join whole items (chunk = 0): the items with histories, by
+    // staging kind (3, 2, 1, 0), and per item its claim counter and the
+    // number of workgroups on it
+    bool by_item;
+    gt::BatchSlot *d_slots;
+    uint32_t n_slots;
+    uint32_t n_slot_kind[4];
+    uint64_t n_hist_kind[4];
+    unsigned long long *d_claimed, *d_workers;
     gt::FillRange *d_fill;
     uint32_t n_fill;
     uint64_t max_fill;

@@ -116,41 +116,52 @@ __global__ void k_put_launch(LaunchRec r, LaunchRec *dst) {
     if (threadIdx.x == 0) *dst = r;
 }
 
-// Many geometries in one persistent launch: each workgroup takes chunks
-// (item, range of particle indices) from a device queue, copies the item's
-// tables into LDS when the item changes (KIND), and runs the lanes' state
-// machine over the chunk with a workgroup-local id counter.
+// Many geometries in one persistent launch, in one of two ways:
+//  * chunks (n_slots == 0): each workgroup takes chunks (item, range of
+//    particle indices) from a device queue and runs the lanes' state machine
+//    over the chunk with a workgroup-local id counter, its waves meeting at
+//    the end of every chunk;
+//  * whole items (n_slots > 0): each workgroup joins an item (pick_item) and
+//    its waves claim the item's histories from the item's counter in device
+//    memory, which the workgroups on the item share, until none is left;
+//    the waves meet only when the workgroup moves to another item.
+// Either way the item's tables are copied into LDS when the item changes
+// (KIND).
 template <int PREC, int KIND, int W, bool RG>
 __global__ void __launch_bounds__(W == 5 ? 640 : kBlockP) __attribute__((amdgpu_waves_per_eu(W)))
-k_track_batch(const BatchItem *__restrict__ items,
-                                                         const BatchChunk *__restrict__ chunks,
-                                                         uint32_t n_chunks, unsigned long long *queue,
-                                                         uint32_t tables_at, uint32_t tail_at, uint32_t tail_cap,
-                                                         uint32_t tail_round, uint32_t tail_words, uint32_t regroup,
-                                                         uint32_t cache_at, uint32_t cache_k) {
+k_track_batch(const BatchItem *__restrict__ items, const BatchChunk *__restrict__ chunks, uint32_t n_chunks,
+              unsigned long long *queue, const BatchSlot *__restrict__ slots, uint32_t n_slots,
+              unsigned long long *claimed, unsigned long long *workers, uint32_t tables_at, uint32_t tail_at,
+              uint32_t tail_cap, uint32_t tail_round, uint32_t tail_words, uint32_t regroup, uint32_t cache_at,
+              uint32_t cache_k) {
     __shared__ uint32_t ctl[1 + kBlockP / 64];
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_dyn[];
     __shared__ uint32_t s_chunk;
     __shared__ unsigned long long s_pool;
+    __shared__ float red_s[kBlockP / 64];
+    __shared__ uint32_t red_i[kBlockP / 64];
     uint32_t *cells = (uint32_t *)lds_dyn;   // the cell of each level, one column per lane
     unsigned char *lds_tables = lds_dyn + tables_at;
     const TailCfg tc = {(uint64_t *)(lds_dyn + tail_at), ctl, tail_cap, tail_round, tail_words, regroup};
     const TallyCache tcache = tally_cache(lds_dyn, cache_at, cache_k);
+    const bool by_item = n_slots != 0;
     // the descriptors are read-only for the whole launch: their fields are
     // read where needed (scalar loads the compiler may repeat) rather than
     // carried from chunk to chunk in registers
     uint32_t cur = 0xFFFFFFFFu;
-    for (;;) {
-        if (threadIdx.x == 0) {
+    for (bool first_visit = true;; first_visit = false) {
+        if (by_item) {
+            pick_item(slots, n_slots, claimed, workers, first_visit, red_s, red_i, &s_chunk);
+            if (threadIdx.x == 0) ctl[0] = 0;
+        } else if (threadIdx.x == 0) {
             s_chunk = (uint32_t)atomicAdd(queue, 1ull);
             s_pool = 0;
             ctl[0] = 0;
         }
         __syncthreads();
         const uint32_t c = __builtin_amdgcn_readfirstlane(s_chunk);
-        if (c >= n_chunks) break;
-        const uint32_t item = chunks[c].item;
-        const uint64_t first = chunks[c].first, count = chunks[c].count;
+        if (by_item ? c == kNoItem : c >= n_chunks) break;
+        const uint32_t item = by_item ? c : chunks[c].item;
         const BatchItem &it = items[item];
         if (KIND != SK_NONE && item != cur) stage_copy(it.plan, (const unsigned char *)it.dev.coef, lds_tables);
         cur = item;
@@ -159,10 +170,12 @@ k_track_batch(const BatchItem *__restrict__ items,
         const KOut &o = it.o;
         uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
         Counts cnt = {0, 0, 0, 0, 0, 0, 0};
-        const ChunkQueue q = {&s_pool, first, first + count};
+        const ChunkQueue q = by_item ? ChunkQueue{&claimed[item], 0, p.n}
+                                     : ChunkQueue{&s_pool, chunks[c].first, chunks[c].first + chunks[c].count};
         track_pool<PREC, RG>(g, p, o, rep, cells + threadIdx.x, q, cnt, tc, tcache);
         add_counts(cnt, o.counters);
         __syncthreads();
+        if (by_item && threadIdx.x == 0) atomicAdd(&workers[item], ~0ull);   // leaves the item
     }
 }
 
@@ -484,9 +497,11 @@ int launch_persistent(const gt_geometry *g, const LaunchRec *lr, int kind, uint6
     }
 }
 
-// The chunks of one staging kind of a batch, in one launch.
+// The work of one staging kind of a batch, in one launch: n chunks at ch,
+// or (ns > 0) the ns items at sl with nh histories in all.
 template <int PREC, int KIND, int W>
-int launch_batch_k(gt_batch *b, const BatchChunk *ch, uint32_t n, unsigned long long *q, hipStream_t st) {
+int launch_batch_k(gt_batch *b, const BatchChunk *ch, uint32_t n, unsigned long long *q, const BatchSlot *sl,
+                   uint32_t ns, uint64_t nh, hipStream_t st) {
     const void *kern = (const void *)k_track_batch<PREC, KIND, W, false>;
     LdsPlan lp;
     int rc = GT_OK;
@@ -499,16 +514,18 @@ int launch_batch_k(gt_batch *b, const BatchChunk *ch, uint32_t n, unsigned long 
         rc = plan_persistent(kern, b->block, b->lds_bytes[KIND], b->tail, b->cache, 0, b->device, lp);
     if (rc) return rc;
     int blocks = lp.blocks;
-    if ((uint32_t)blocks > n) blocks = (int)n;
+    // no more workgroups than chunks, or than whole workgroups of histories
+    const uint64_t cap = ns ? (nh + b->block - 1) / b->block : n;
+    if ((uint64_t)blocks > cap) blocks = (int)cap;
     note_launch(lp, blocks, b->block, KIND);
     if (lp.regroup)
         hipLaunchKernelGGL((k_track_batch<PREC, KIND, W, true>), dim3(blocks), dim3(b->block), lp.dyn, st,
-                           b->d_items, ch, n, q, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.tail_words,
-                           lp.regroup, lp.cache_at, lp.cache_k);
+                           b->d_items, ch, n, q, sl, ns, b->d_claimed, b->d_workers, lp.tables_at, lp.tail_at,
+                           lp.tail_cap, kTailRound, lp.tail_words, lp.regroup, lp.cache_at, lp.cache_k);
     else
         hipLaunchKernelGGL((k_track_batch<PREC, KIND, W, false>), dim3(blocks), dim3(b->block), lp.dyn, st,
-                           b->d_items, ch, n, q, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.tail_words,
-                           0u, lp.cache_at, lp.cache_k);
+                           b->d_items, ch, n, q, sl, ns, b->d_claimed, b->d_workers, lp.tables_at, lp.tail_at,
+                           lp.tail_cap, kTailRound, lp.tail_words, 0u, lp.cache_at, lp.cache_k);
     return GT_OK;
 }
 
@@ -551,14 +568,16 @@ int batch_streams(gt_batch *b, BatchStreams *&bs) {
 template <int PREC, int W>
 int launch_batch_kinds(gt_batch *b, hipStream_t st) {
     int kinds = 0;
-    uint64_t listed = 0;
+    uint64_t listed = 0, slotted = 0;
     for (int kind = 0; kind < 4; kind++) {
-        kinds += b->n_kind[kind] ? 1 : 0;
+        kinds += (b->by_item ? b->n_slot_kind[kind] : b->n_kind[kind]) ? 1 : 0;
         listed += b->n_kind[kind];
+        slotted += b->n_slot_kind[kind];
     }
-    // (gt_batch_create checked every chunk; the groups must still add up
-    // before any launch reads them)
-    if (listed != b->n_chunks) return set_error("gt_batch_launch: inconsistent chunk groups"), GT_EINVAL;
+    // (gt_batch_create checked every chunk and slot; the groups must still
+    // add up before any launch reads them)
+    if (listed != b->n_chunks || slotted != b->n_slots || (b->by_item ? b->n_chunks : b->n_slots) != 0)
+        return set_error("gt_batch_launch: inconsistent chunk or item groups"), GT_EINVAL;
     BatchStreams *bs = nullptr;
     if (kinds > 1) {
         int rc = batch_streams(b, bs);
@@ -566,24 +585,27 @@ int launch_batch_kinds(gt_batch *b, hipStream_t st) {
         rc = hip_check(hipEventRecord(bs->fork, st), "hipEventRecord");
         if (rc) return rc;
     }
-    uint32_t first = 0;
+    uint32_t first = 0, first_slot = 0;
     int lane = 0;
-    for (int kind = 3; kind >= 0; kind--) {   // chunk groups in the order gt_batch_create wrote them
-        const uint32_t n = b->n_kind[kind];
+    for (int kind = 3; kind >= 0; kind--) {   // groups in the order gt_batch_create wrote them
+        const uint32_t n = b->n_kind[kind], ns = b->n_slot_kind[kind];
         const BatchChunk *ch = b->d_chunks + first;
+        const BatchSlot *sl = b->d_slots + first_slot;
+        const uint64_t nh = b->n_hist_kind[kind];
         unsigned long long *q = b->d_queue + kind;
         first += n;
-        if (!n) continue;
+        first_slot += ns;
+        if (b->by_item ? !ns : !n) continue;
         hipStream_t s = st;
         if (lane > 0) {
             s = bs->s[lane - 1];
             int rc = hip_check(hipStreamWaitEvent(s, bs->fork, 0), "hipStreamWaitEvent");
             if (rc) return rc;
         }
-        int rc = kind == SK_ALL     ? launch_batch_k<PREC, SK_ALL, W>(b, ch, n, q, s)
-                 : kind == SK_LDS   ? launch_batch_k<PREC, SK_LDS, W>(b, ch, n, q, s)
-                 : kind == SK_SPLIT ? launch_batch_k<PREC, SK_SPLIT, W>(b, ch, n, q, s)
-                                    : launch_batch_k<PREC, SK_NONE, W>(b, ch, n, q, s);
+        int rc = kind == SK_ALL     ? launch_batch_k<PREC, SK_ALL, W>(b, ch, n, q, sl, ns, nh, s)
+                 : kind == SK_LDS   ? launch_batch_k<PREC, SK_LDS, W>(b, ch, n, q, sl, ns, nh, s)
+                 : kind == SK_SPLIT ? launch_batch_k<PREC, SK_SPLIT, W>(b, ch, n, q, sl, ns, nh, s)
+                                    : launch_batch_k<PREC, SK_NONE, W>(b, ch, n, q, sl, ns, nh, s);
         if (rc) return rc;
         if (lane > 0) {
             rc = hip_check(hipEventRecord(bs->join[lane - 1], s), "hipEventRecord");
@@ -738,7 +760,7 @@ bool last_launch(gt_launch_info *out) {
 
 int prepare_batch_streams(gt_batch *b) {
     int kinds = 0;
-    for (int kind = 0; kind < 4; kind++) kinds += b->n_kind[kind] ? 1 : 0;
+    for (int kind = 0; kind < 4; kind++) kinds += (b->by_item ? b->n_slot_kind[kind] : b->n_kind[kind]) ? 1 : 0;
     BatchStreams *bs = nullptr;
     return kinds > 1 ? batch_streams(b, bs) : GT_OK;
 }

@@ -69,7 +69,7 @@ int time_launches(F launch, uint32_t reps, hipStream_t st, float *ms) {
 
 const uint32_t kBlocks[] = {256, 512, 640, 1024};
 const uint32_t kRefills[] = {1, 4, 8, 16};
-const uint64_t kChunks[] = {1024, 2048, 4096, 16384, 65536};
+const uint64_t kChunks[] = {0, 1024, 4096, 16384};   // 0: workgroups join whole items
 const uint32_t kRegroups[] = {16, 64, 256};   // second stage, at the fastest shape of the first
 const uint32_t kWaveTakes[] = {128, 256};     // third stage: histories a wave claims at once (64 is the
                                               // default the first two stages ran with)
@@ -160,7 +160,7 @@ extern "C" int gt_autotune_batch(const gt_batch_item *items, uint32_t n_items, u
     };
     // (the first stage keeps the items' own regroup setting)
     for (uint32_t b : kBlocks) {
-        if (b < 512) continue;   // a batch runs one workgroup's chunk at a time: keep workgroups large
+        if (b < 512) continue;   // a workgroup runs one item at a time: keep workgroups large
         for (uint32_t r : kRefills)
             for (uint64_t c : kChunks)
                 if (int rc = trial({b, r, c, 0, 0})) return rc;

@@ -230,9 +230,13 @@ extern "C" int cpu_track_event(const gt_geometry *g, const gt_track_params *p, c
 // executed the way gt_batch_launch executes them -- the fill list, then the
 // chunk groups by staging kind (3, 2, 1, 0) each chunk through one lane with
 // its item's tables, then the finalize list.  *n_chunks gets the number of
-// chunks run.
+// chunks run.  With whole items (chunk = 0) each kind's item group is run
+// by `groups` one-lane workgroups: all of them make their first choice
+// (pick_item), then each in turn runs visits (draining its item's counter)
+// and chooses again until no item has histories left; *n_chunks then gets
+// the number of visits.
 extern "C" int cpu_track_batch(const gt_batch_item *items, uint32_t n_items, const gt_tuning *tuning,
-                               uint32_t *n_chunks) {
+                               uint32_t *n_chunks, uint32_t groups) {
     gt_batch *b = nullptr;
     int rc = gt_batch_create(items, n_items, tuning, &b);
     if (rc) return rc;
@@ -245,7 +249,59 @@ extern "C" int cpu_track_batch(const gt_batch_item *items, uint32_t n_items, con
     }
     g_cache_k = b->cache ? kTallyCacheMax : 0;
     uint32_t first = 0, ran = 0;
-    for (int kind = 3; kind >= 0 && !rc; kind--) {
+    if (b->by_item) {
+        if (groups == 0) {
+            set_error("cpu_track_batch: no workgroups");
+            gt_batch_destroy(b);
+            return GT_EINVAL;
+        }
+        uint32_t first_slot = 0;
+        std::vector<uint32_t> pick(groups);
+        float rs[1];
+        uint32_t ri[1];
+        for (int kind = 3; kind >= 0 && !rc; kind--) {
+            const uint32_t ns = b->n_slot_kind[kind];
+            const BatchSlot *sl = b->d_slots + first_slot;
+            first_slot += ns;
+            if (!ns) continue;
+            gridDim.x = groups;
+            for (uint32_t w = 0; w < groups; w++) {
+                blockIdx.x = w;
+                pick_item(sl, ns, b->d_claimed, b->d_workers, true, rs, ri, &pick[w]);
+            }
+            for (uint32_t w = 0; w < groups && !rc; w++) {
+                blockIdx.x = w;
+                while (pick[w] != kNoItem && !rc) {
+                    const uint32_t item = pick[w];
+                    if (item >= b->n_items) {
+                        set_error("cpu_track_batch: a choice names item %u", item);
+                        rc = GT_EINVAL;
+                        break;
+                    }
+                    const BatchItem &it = b->d_items[item];
+                    const ChunkQueue q = {&b->d_claimed[item], 0, it.p.n};
+                    rc = b->precision == GT_PREC_MIXED
+                             ? run_kind<GT_PREC_MIXED>(kind, it.dev, it.plan, it.p, it.o, q, it.o.counters)
+                             : run_kind<GT_PREC_FP64>(kind, it.dev, it.plan, it.p, it.o, q, it.o.counters);
+                    b->d_workers[item] -= 1;
+                    ran++;
+                    pick_item(sl, ns, b->d_claimed, b->d_workers, false, rs, ri, &pick[w]);
+                }
+            }
+            blockIdx.x = 0;
+            gridDim.x = 1;
+            for (uint32_t s = 0; s < ns && !rc; s++)
+                if (b->d_workers[sl[s].item] != 0 || b->d_claimed[sl[s].item] < sl[s].n) {
+                    set_error("cpu_track_batch: item %u left with workers or unclaimed histories", sl[s].item);
+                    rc = GT_EINVAL;
+                }
+        }
+        if (!rc && first_slot != b->n_slots) {
+            set_error("cpu_track_batch: item groups do not cover the items");
+            rc = GT_EINVAL;
+        }
+    }
+    for (int kind = 3; kind >= 0 && !rc && !b->by_item; kind--) {
         for (uint32_t c = first; c < first + b->n_kind[kind] && !rc; c++) {
             const BatchChunk &ch = b->d_chunks[c];
             if (ch.item >= b->n_items) {
@@ -262,7 +318,7 @@ extern "C" int cpu_track_batch(const gt_batch_item *items, uint32_t n_items, con
         }
         first += b->n_kind[kind];
     }
-    if (!rc && (first != b->n_chunks || ran != b->n_chunks)) {
+    if (!rc && !b->by_item && (first != b->n_chunks || ran != b->n_chunks)) {
         set_error("cpu_track_batch: chunk groups do not cover the chunks");
         rc = GT_EINVAL;
     }

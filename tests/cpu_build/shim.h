@@ -37,6 +37,7 @@ static inline int __ffsll(unsigned long long m) { return __builtin_ffsll((long l
 static inline unsigned __lane_id() { return 0; }
 template <typename T> static inline T __shfl(T v, int) { return v; }
 template <typename T> static inline T __shfl_up(T v, unsigned) { return v; }   // no lane below lane 0
+template <typename T> static inline T __shfl_xor(T v, int) { return v; }
 static inline uint32_t __builtin_amdgcn_mbcnt_lo(uint32_t, uint32_t c) { return c; }
 static inline uint32_t __builtin_amdgcn_mbcnt_hi(uint32_t, uint32_t c) { return c; }
 template <typename T> static inline T __builtin_amdgcn_readfirstlane(T v) { return v; }
@@ -55,6 +56,8 @@ template <typename T, typename V> static inline T cpu_atomic_fetch_add(T *p, V v
     return o;
 }
 #define __hip_atomic_fetch_add cpu_atomic_fetch_add
+template <typename T> static inline T cpu_atomic_load(T *p, int, int) { return *p; }
+#define __hip_atomic_load cpu_atomic_load
 #undef __HIP_MEMORY_SCOPE_WORKGROUP
 #define __HIP_MEMORY_SCOPE_WORKGROUP 0
 #undef __HIP_MEMORY_SCOPE_AGENT

@@ -39,7 +39,7 @@ class HostLib:
         L.gt_last_error.restype = C.c_char_p
         L.cpu_track.argtypes = [vp, C.POINTER(gt._Params), C.POINTER(gt._Out), C.c_int]
         L.cpu_track_batch.argtypes = [C.POINTER(gt._BatchItem), C.c_uint32, C.POINTER(gt._Tuning),
-                                      C.POINTER(C.c_uint32)]
+                                      C.POINTER(C.c_uint32), C.c_uint32]
         L.cpu_track_mesh.argtypes = [vp, C.POINTER(gt._Params), C.POINTER(gt._Out), C.POINTER(gt._Mesh), C.c_int]
         L.gt_mesh_workspace_bytes.argtypes = [C.c_uint64]
         L.gt_mesh_workspace_bytes.restype = C.c_uint64
@@ -167,7 +167,7 @@ def test_cpu_build_covers_every_staging_kind(host):
     assert kinds == {0, 1, 2, 3}
 
 
-def batch_run(host, items_spec, prec, chunk):
+def batch_run(host, items_spec, prec, chunk, groups=1):
     arr = (gt._BatchItem * len(items_spec))()
     outs, want, hs = [], [], []
     for i, (j, n, staging) in enumerate(items_spec):
@@ -183,7 +183,7 @@ def batch_run(host, items_spec, prec, chunk):
         want.append(oracle.track(oracle.OracleGeometry(fg), oracle.TrackParams(n_particles=n, record_first_k=20,
                                                                                  record_cap=32, **kw), n_threads=4))
     ran = C.c_uint32()
-    host.check(host.L.cpu_track_batch(arr, len(items_spec), C.byref(gt._Tuning(0, 0, chunk)), C.byref(ran)))
+    host.check(host.L.cpu_track_batch(arr, len(items_spec), C.byref(gt._Tuning(0, 0, chunk)), C.byref(ran), groups))
     for out, o in zip(outs, want):
         same(out.a, o, 20)
     for h in hs:
@@ -199,6 +199,23 @@ def test_cpu_batch_descriptors(host, prec):
     spec = [(57, 700, True), (3, 500, True), (5, 450, True), (2, 380, True), (41, 333, False), (63, 300, True)]
     ran = batch_run(host, spec, prec, 97)
     assert ran == sum((n + 96) // 97 for _, n, _ in spec)
+
+
+@pytest.mark.parametrize("prec", [gt.PREC_FP64, gt.PREC_MIXED])
+@pytest.mark.parametrize("groups", [1, 3, 40])
+def test_cpu_batch_whole_items(host, prec, groups):
+    """Whole items (chunk = 0): the item groups by staging kind, the first
+    choice of every workgroup, the later choices and the shared claim
+    counters cover every item's histories exactly once, every workgroup
+    leaves its items (the driver checks the counters), and every item's
+    outputs equal the oracle's; one item with no histories and more
+    workgroups than items included."""
+    spec = [(57, 700, True), (3, 500, True), (5, 450, True), (2, 0, True), (41, 333, False), (63, 300, True)]
+    ran = batch_run(host, spec, prec, 0, groups)
+    busy = sum(1 for _, n, _ in spec if n)
+    # each item drained in one visit; at most one empty visit per workgroup and kind
+    # (several workgroups: some first choices land on items drained before them)
+    assert busy <= ran <= busy + 4 * groups and (groups == 1 or ran > busy)
 
 
 def test_cpu_build_under_address_sanitizer():
@@ -239,6 +256,7 @@ for what, k in [("cfg", 2), ("batch", 3), ("batch", 5), ("batch", 2)]:
             t.mesh_run(host, h, ni, kw, prec, lo - 1.0, hi + 2.0, (5, 7, 3), 150, 10, 16)
     host.L.gt_geometry_destroy(h)
 t.batch_run(host, [(57, 300, True), (5, 200, True), (41, 150, False)], 1, 64)
+t.batch_run(host, [(57, 300, True), (5, 200, True), (41, 150, False)], 1, 0, 3)
 print("asan clean")
 """ % (os.path.dirname(HERE), HERE, lib)
     env = dict(os.environ, LD_PRELOAD=rt, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")

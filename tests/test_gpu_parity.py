@@ -618,13 +618,15 @@ def _outs(out):
 BATCH_SUBSET = [0, 2, 3, 5, 7, 10, 25, 41, 57, 63]
 
 
+@pytest.mark.parametrize("chunk", [333, 0])
 @pytest.mark.parametrize("prec,tail", [(gt.PREC_FP64, False), (gt.PREC_MIXED, False), (gt.PREC_MIXED, True)])
-def test_batch_matches_oracle(prec, tail):
+def test_batch_matches_oracle(prec, tail, chunk):
     """One batched launch over ten geometries (half of them forced to read
     their tables from global memory, so several staging-kind launches run on
     forked streams), with small chunks so every item is split into several
-    and ends ragged; with and without tail compaction (with it, also the
-    regroup step every 5 loop trips)."""
+    and ends ragged, or with workgroups joining whole items (chunk 0); with
+    and without tail compaction (with it, also the regroup step every 5 loop
+    trips)."""
     import torch
     items, want = [], []
     for k, j in enumerate(BATCH_SUBSET):
@@ -636,8 +638,8 @@ def test_batch_matches_oracle(prec, tail):
         want.append(oracle.track(O, oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=n,
                                                        geometry_id=synth.batch_geometry_id(j),
                                                        record_first_k=40, record_cap=64), n_threads=NT))
-    print("batch of", len(items), "precision", prec, flush=True)
-    gt.track_batch(items, chunk=333, regroup_every=5 if tail else 0)
+    print("batch of", len(items), "precision", prec, "chunk", chunk, flush=True)
+    gt.track_batch(items, chunk=chunk, regroup_every=5 if tail else 0)
     torch.cuda.synchronize()
     assert gt.last_launch()["regroup_every"] == (5 if tail else 0)
     for j, it, o in zip(BATCH_SUBSET, items, want):
@@ -673,17 +675,20 @@ def test_every_staging_kind_is_tracked_exactly():
             assert_parity(g, o, where="staging kind %d (%s %s) prec %d" % (kind, what, k, prec))
 
 
-def test_batch_graph_replays_match_eager():
+@pytest.mark.parametrize("chunk", [700, 0])
+def test_batch_graph_replays_match_eager(chunk):
     """gt_batch_launch captured into a HIP graph: every replay (with other
     device work and host synchronisation in between) reproduces the eager
-    launch exactly, including the zeroing of tallies and counters."""
+    launch exactly, including the zeroing of tallies and counters (with
+    whole items, also of the items' claim and workgroup counters)."""
     import torch
     items = []
     for j in (3, 10, 41):
         fg, n, G, O = batch_geoms(j)
         items.append(gt.batch_item(G, synth.batch_particle_seed(j), 3000, geometry_id=synth.batch_geometry_id(j),
                                    record_first_k=20, record_cap=32))
-    b = gt.Batch(items, chunk=700)
+    print("graph replay, chunk", chunk, flush=True)
+    b = gt.Batch(items, chunk=chunk)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         b.launch(s)
@@ -786,7 +791,7 @@ def test_autotune_batch_then_tuned_batch():
         want.append(oracle.track(O, oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=2500, **kw),
                                  n_threads=NT))
     shape = gt.autotune_batch(items, reps=1)
-    assert shape["block_size"] in (512, 640, 1024) and shape["chunk"] in (1024, 2048, 4096, 16384, 65536)
+    assert shape["block_size"] in (512, 640, 1024) and shape["chunk"] in (0, 1024, 4096, 16384)
     assert shape["regroup_every"] in (0, 16, 64, 256)
     gt.track_batch(items, tuned=True)
     torch.cuda.synchronize()
@@ -794,7 +799,8 @@ def test_autotune_batch_then_tuned_batch():
         assert_parity(_outs(it.out), o, where="tuned batch")
 
 
-def test_batch_of_one_staging_kind_matches_oracle():
+@pytest.mark.parametrize("chunk", [500, 0])
+def test_batch_of_one_staging_kind_matches_oracle(chunk):
     """Every item forced to read its tables from global memory: one kind,
     one launch on the caller's stream (no helper streams)."""
     import torch
@@ -807,10 +813,44 @@ def test_batch_of_one_staging_kind_matches_oracle():
         want.append(oracle.track(O, oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=n,
                                                        geometry_id=synth.batch_geometry_id(j),
                                                        record_first_k=16, record_cap=64), n_threads=NT))
-    gt.track_batch(items, chunk=500)
+    print("one-kind batch, chunk", chunk, flush=True)
+    gt.track_batch(items, chunk=chunk)
     torch.cuda.synchronize()
     for j, it, o in zip(BATCH_SUBSET, items, want):
         assert_parity(_outs(it.out), o, where="one-kind batch item %d" % j)
+
+
+@pytest.mark.parametrize("prec", [gt.PREC_FP64, gt.PREC_MIXED])
+def test_batch_whole_items_small_and_uneven(prec):
+    """Workgroups joining whole items when items are many and small: all 64
+    geometries with 1 to a few hundred histories each (fewer histories than
+    lanes in most items, one item with none), every kind of staging; each
+    item's outputs against the oracle, and the same items with 512-lane
+    workgroups."""
+    import torch
+    items, want, ns = [], [], []
+    for j in range(synth.BATCH_SIZE):
+        fg, n, G, O = batch_geoms(j)
+        n = 0 if j == 7 else min(n, 1 + (j * 37) % 400)
+        ns.append(n)
+        items.append(gt.batch_item(G, synth.batch_particle_seed(j), n, geometry_id=synth.batch_geometry_id(j),
+                                   record_first_k=8, record_cap=64, precision=prec))
+        want.append(oracle.track(O, oracle.TrackParams(seed=synth.batch_particle_seed(j), n_particles=n,
+                                                       geometry_id=synth.batch_geometry_id(j),
+                                                       record_first_k=8, record_cap=64), n_threads=NT)
+                    if n else None)
+    for block in (1024, 512):
+        print("whole items, small, block", block, "precision", prec, flush=True)
+        for it in items:
+            it.out.tally_fx.fill_(9)
+        gt.track_batch(items, chunk=0, block_size=block)
+        torch.cuda.synchronize()
+        for j, it, o in zip(range(synth.BATCH_SIZE), items, want):
+            g = _outs(it.out)
+            if o is None:
+                assert not g["tally_fx"].any() and sum(g["counters"].values()) == 0
+            else:
+                assert_parity(g, o, where="small batch item %d (block %d)" % (j, block))
 
 
 def test_kernel_event_hook():
