@@ -268,7 +268,7 @@ def counters_for(workload_tag):
         r = {"traffic": (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
                          + float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])) * 1024.0}
         for k in ("fp64_valu_insts_per_dispatch", "valu_insts_per_dispatch", "valu_lane_utilisation",
-                  "lds_bank_conflict_over_lds_insts", "counter_kernel_us"):
+                  "lds_bank_conflict_over_lds_insts", "valu_busy_frac", "counter_kernel_us"):
             if k in kv:
                 r[k] = float(kv[k])
         return r
@@ -686,7 +686,7 @@ def main():
             # FP64 VALU wave instructions x 64 lanes over the FP64 lane-issue capacity of the kernel's time
             line["roofline"]["fp64_valu_issue_frac"] = (cnt["fp64_valu_insts_per_dispatch"] * 64.0
                                                         / (PEAK_FP64_NONFMA_OPS * kernel_ms * 1e-3))
-            for k in ("valu_lane_utilisation", "lds_bank_conflict_over_lds_insts"):
+            for k in ("valu_lane_utilisation", "valu_busy_frac", "lds_bank_conflict_over_lds_insts"):
                 if k in cnt:
                     line["roofline"][k] = cnt[k]
         alg, miss = alg_bytes_per_segment(cb["n_inst"], n, head["segments"], cb["recorded_segments"])
