@@ -247,10 +247,11 @@ def test_histories_per_wave_claim(wave, cfg, n):
     o = oracle.track(O, oracle.TrackParams(record_first_k=100, record_cap=256, **kw), n_threads=NT)
     assert_parity(g, o, where="wave %d" % wave)
     if cfg == 2:
-        it = gt.batch_item(G, kw["seed"], kw["n_particles"], geometry_id=cfg)
-        gt.track_batch([it], chunk=3000, wave_histories=wave)
         o2 = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT)
-        assert_parity(_outs(it.out), o2, where="batch wave %d" % wave)
+        for chunk in (3000, 0):   # chunks, and workgroups joining the whole item
+            it = gt.batch_item(G, kw["seed"], kw["n_particles"], geometry_id=cfg)
+            gt.track_batch([it], chunk=chunk, wave_histories=wave)
+            assert_parity(_outs(it.out), o2, where="batch wave %d chunk %d" % (wave, chunk))
     for bad in (32, 1088):
         with pytest.raises(gt.GtError):
             gt.track(G, wave_histories=bad, **kw)
