@@ -451,7 +451,8 @@ int gt_set_kernel_events(void *start_event, void *stop_event);
  * made no such launch; GT_EINVAL for a NULL out. */
 typedef struct {
     uint32_t workgroups, block_size, lds_bytes, staging_kind;
-    uint32_t tally_cache_entries, tail_capacity, regroup_every, reserved;
+    uint32_t tally_cache_entries, tail_capacity, regroup_every;
+    uint32_t surface_set;   /* 1: the build for axis planes and z-cylinders only; 0: every surface type */
 } gt_launch_info;
 int gt_last_launch(gt_launch_info *out);
 

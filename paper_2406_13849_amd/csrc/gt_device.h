@@ -41,10 +41,14 @@ __device__ __forceinline__ double dinf() { return __builtin_huge_val(); }
 // tables (cells, half-spaces, surfaces, universes, materials, local indices)
 // in address space A, the crossing tables (translations, candidate lists) in
 // B and the hierarchy (nodes, leaves, cell boxes) in C; 3 = LDS, 1 = global.
+// S is the set of surface types the code handles (SF_ALL, or SF_AXCZ when
+// the geometry has only axis planes and z-cylinders): the surface
+// functions below are compiled for that set alone.
 template <int AS, typename T> using cptr = const GT_AS(AS) T *;
 
-template <int A, int B, int C>
+template <int A, int B, int C, int S = SF_ALL>
 struct DevT {
+    static constexpr int kSurf = S;
     cptr<A, double> coef;
     cptr<A, uint32_t> hs;
     cptr<A, Cell> cell;
@@ -87,8 +91,8 @@ __device__ __forceinline__ T ldv(P p) {
     return *(const T *)p;
 }
 
-template <int A, int B, int C>
-__device__ __forceinline__ void view_scalars(DevT<A, B, C> &d, const Dev &g) {
+template <int A, int B, int C, int S>
+__device__ __forceinline__ void view_scalars(DevT<A, B, C, S> &d, const Dev &g) {
     d.root = g.root;
     d.n_inst = g.n_inst;
     d.max_depth = g.max_depth;
@@ -99,8 +103,9 @@ __device__ __forceinline__ void view_scalars(DevT<A, B, C> &d, const Dev &g) {
     }
 }
 
-__device__ __forceinline__ DevGlobal global_view(const Dev &g) {
-    DevGlobal d;
+template <int S = SF_ALL>
+__device__ __forceinline__ DevT<1, 1, 1, S> global_view(const Dev &g) {
+    DevT<1, 1, 1, S> d;
     d.coef = (cptr<1, double>)g.coef;
     d.hs = (cptr<1, uint32_t>)g.hs;
     d.cell = (cptr<1, Cell>)g.cell;
@@ -208,37 +213,54 @@ __device__ __forceinline__ bool direction_from(double u0, double u1, double &u, 
 // ------------------------------------------------------------------ surfaces
 // Half-spaces of a cell are stored planes first (types PX, PY, PZ, P), then
 // quadrics (CZ, SPH), so each loop below runs one surface family.
-template <typename CP>
+template <int SF, typename CP>
 __device__ __forceinline__ double plane_value(uint32_t type, CP c, double x, double y, double z) {
-    switch (type) {
-    case ST_PX: return x - c[0];
-    case ST_PY: return y - c[0];
-    case ST_PZ: return z - c[0];
-    default: return ((c[0] * x + c[1] * y) + c[2] * z) - c[3];
+    if constexpr (SF == SF_AXCZ) {
+        switch (type) {
+        case ST_PX: return x - c[0];
+        case ST_PY: return y - c[0];
+        default: return z - c[0];
+        }
+    } else {
+        switch (type) {
+        case ST_PX: return x - c[0];
+        case ST_PY: return y - c[0];
+        case ST_PZ: return z - c[0];
+        default: return ((c[0] * x + c[1] * y) + c[2] * z) - c[3];
+        }
     }
 }
 
 // plane_value split as linear part minus offset (the same operations):
 // the coordinate, or ((a x + b y) + c z); then d.
-template <typename CP>
+template <int SF, typename CP>
 __device__ __forceinline__ double plane_linear(uint32_t type, CP c, double x, double y, double z) {
-    switch (type) {
-    case ST_PX: return x;
-    case ST_PY: return y;
-    case ST_PZ: return z;
-    default: return (c[0] * x + c[1] * y) + c[2] * z;
+    if constexpr (SF == SF_AXCZ) {
+        switch (type) {
+        case ST_PX: return x;
+        case ST_PY: return y;
+        default: return z;
+        }
+    } else {
+        switch (type) {
+        case ST_PX: return x;
+        case ST_PY: return y;
+        case ST_PZ: return z;
+        default: return (c[0] * x + c[1] * y) + c[2] * z;
+        }
     }
 }
 
-template <typename CP>
+template <int SF, typename CP>
 __device__ __forceinline__ double plane_offset(uint32_t type, CP c) {
-    return type == ST_P ? c[3] : c[0];
+    if constexpr (SF == SF_AXCZ) return c[0];
+    else return type == ST_P ? c[3] : c[0];
 }
 
-template <typename CP>
+template <int SF, typename CP>
 __device__ __forceinline__ double quad_value(uint32_t type, CP c, double x, double y, double z) {
     const double dx = x - c[0], dy = y - c[1];
-    if (type == ST_CZ) return (dx * dx + dy * dy) - c[2];
+    if (SF == SF_AXCZ || type == ST_CZ) return (dx * dx + dy * dy) - c[2];
     const double dz = z - c[2];
     return ((dx * dx + dy * dy) + dz * dz) - c[3];
 }
@@ -259,21 +281,21 @@ __device__ __forceinline__ bool contains(const G &g, uint32_t c, double x, doubl
         const uint32_t h0 = hs[k], h1 = hs[k + 1];
         const uint32_t s0 = h0 >> 4, s1 = h1 >> 4, t = h0 & 7u;
         const auto c0 = g.coef + 4 * (size_t)s0, c1 = g.coef + 4 * (size_t)s1;
-        const double lin = plane_linear(t, c0, x, y, z);
-        const bool p0 = (s0 == force_s) ? force_pos : (lin - plane_offset(t, c0) > 0.0);
-        const bool p1 = (s1 == force_s) ? force_pos : (lin - plane_offset(t, c1) > 0.0);
+        const double lin = plane_linear<G::kSurf>(t, c0, x, y, z);
+        const bool p0 = (s0 == force_s) ? force_pos : (lin - plane_offset<G::kSurf>(t, c0) > 0.0);
+        const bool p1 = (s1 == force_s) ? force_pos : (lin - plane_offset<G::kSurf>(t, c1) > 0.0);
         if (p0 != (bool)((h0 >> 3) & 1u) || p1 != (bool)((h1 >> 3) & 1u)) return false;
     }
     for (uint32_t k = npair2; k < npl; k++) {
         const uint32_t h = hs[k];
         const uint32_t s = h >> 4;
-        const bool pos = (s == force_s) ? force_pos : (plane_value(h & 7u, g.coef + 4 * (size_t)s, x, y, z) > 0.0);
+        const bool pos = (s == force_s) ? force_pos : (plane_value<G::kSurf>(h & 7u, g.coef + 4 * (size_t)s, x, y, z) > 0.0);
         if (pos != (bool)((h >> 3) & 1u)) return false;
     }
     for (uint32_t k = npl; k < cc.n_hs; k++) {
         const uint32_t h = hs[k];
         const uint32_t s = h >> 4;
-        const bool pos = (s == force_s) ? force_pos : (quad_value(h & 7u, g.coef + 4 * (size_t)s, x, y, z) > 0.0);
+        const bool pos = (s == force_s) ? force_pos : (quad_value<G::kSurf>(h & 7u, g.coef + 4 * (size_t)s, x, y, z) > 0.0);
         if (pos != (bool)((h >> 3) & 1u)) return false;
     }
     return true;
@@ -288,23 +310,31 @@ __device__ __forceinline__ bool contains(const G &g, uint32_t c, double x, doubl
 
 // Distance along (u,v,w) from q to the point where a plane's sense leaves
 // the cell's required side `pos`; +inf if it does not (Table 1).
-template <typename CP>
+template <int SF, typename CP>
 __device__ __forceinline__ double plane_den(uint32_t type, CP c, double u, double v, double w) {
-    switch (type) {
-    case ST_PX: return u;
-    case ST_PY: return v;
-    case ST_PZ: return w;
-    default: return (c[0] * u + c[1] * v) + c[2] * w;
+    if constexpr (SF == SF_AXCZ) {
+        switch (type) {
+        case ST_PX: return u;
+        case ST_PY: return v;
+        default: return w;
+        }
+    } else {
+        switch (type) {
+        case ST_PX: return u;
+        case ST_PY: return v;
+        case ST_PZ: return w;
+        default: return (c[0] * u + c[1] * v) + c[2] * w;
+        }
     }
 }
 
-template <typename CP>
+template <int SF, typename CP>
 __device__ __forceinline__ double plane_distance(uint32_t type, CP c, bool pos, double qx, double qy,
                                                  double qz, double u, double v, double w) {
-    const double den = plane_den(type, c, u, v, w);
+    const double den = plane_den<SF>(type, c, u, v, w);
     if (den == 0.0) return dinf();
     if (!((!pos && den > 0.0) || (pos && den < 0.0))) return dinf();
-    const double t = (-plane_value(type, c, qx, qy, qz)) / den;
+    const double t = (-plane_value<SF>(type, c, qx, qy, qz)) / den;
     return (t > 0.0) ? t : 0.0;
 }
 
@@ -315,10 +345,10 @@ __device__ __forceinline__ double plane_distance(uint32_t type, CP c, bool pos, 
 // the case-by-case formula gives (lanes of a wave often take different cases).
 __device__ __forceinline__ double quad_root(double a, double b, double cc, bool pos, bool on);
 
-template <typename CP>
+template <int SF, typename CP>
 __device__ __forceinline__ double quad_distance(uint32_t type, CP c, bool pos, double qx, double qy,
                                                 double qz, double u, double v, double w, bool on) {
-    const bool cyl = type == ST_CZ;
+    const bool cyl = SF == SF_AXCZ || type == ST_CZ;
     const double c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
     const double dx = qx - c0, dy = qy - c1, dz = qz - c2;
     const double a2 = u * u + v * v, b2 = dx * u + dy * v, r2 = dx * dx + dy * dy;
@@ -479,7 +509,7 @@ __device__ __forceinline__ double distance_all(const G &g, const Particle &P, in
             const uint32_t s = h >> 4;
             const bool pos = (h >> 3) & 1u;
             if (P.on_level == L && P.on_surf == s) continue;   // a plane just crossed is not hit again
-            const double d = plane_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w);
+            const double d = plane_distance<G::kSurf>(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w);
             if (d < bt || (d == bt && d != dinf() && L == bl && s < bs)) {
                 bt = d;
                 bl = L;
@@ -493,7 +523,7 @@ __device__ __forceinline__ double distance_all(const G &g, const Particle &P, in
             const uint32_t s = h >> 4;
             const bool pos = (h >> 3) & 1u;
             const bool on = (P.on_level == L) && (P.on_surf == s);
-            const double d = quad_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w, on);
+            const double d = quad_distance<G::kSurf>(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w, on);
             if (d < bt || (d == bt && d != dinf() && L == bl && s < bs)) {
                 bt = d;
                 bl = L;
@@ -551,13 +581,13 @@ __device__ __forceinline__ void nearest_surface(const G &g, const Particle &P, N
             // just crossed, gets +inf.
             const uint32_t h0 = hs[k], h1 = hs[k + 1];
             const auto c0 = g.coef + 4 * (size_t)(h0 >> 4);
-            const double den = plane_den(h0 & 7u, c0, P.u, P.v, P.w);
+            const double den = plane_den<G::kSurf>(h0 & 7u, c0, P.u, P.v, P.w);
             const uint32_t kk = den > 0.0 ? k : k + 1;
             const uint32_t h = den > 0.0 ? h0 : h1;
             const uint32_t s = h >> 4;
             // the pair shares its normal: the linear part from h0's record, the
             // offset from the reached plane's (the operations of plane_value)
-            const double t = (-(plane_linear(h0 & 7u, c0, qx, qy, qz) - plane_offset(h & 7u, g.coef + 4 * (size_t)s))) / den;
+            const double t = (-(plane_linear<G::kSurf>(h0 & 7u, c0, qx, qy, qz) - plane_offset<G::kSurf>(h & 7u, g.coef + 4 * (size_t)s))) / den;
             const bool skip = den == 0.0 || (P.on_level == L && P.on_surf == s);
             const double d = skip ? dinf() : ((t > 0.0) ? t : 0.0);
             if (d < r.t || (d == r.t && d != dinf() && L == r.level && s < r.surf)) {
@@ -574,7 +604,7 @@ __device__ __forceinline__ void nearest_surface(const G &g, const Particle &P, N
             const uint32_t s = h >> 4;
             const bool pos = (h >> 3) & 1u;
             if (P.on_level == L && P.on_surf == s) continue;   // a plane just crossed is not hit again
-            const double d = plane_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w);
+            const double d = plane_distance<G::kSurf>(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w);
             if (d < r.t || (d == r.t && d != dinf() && L == r.level && s < r.surf)) {
                 r.t = d;
                 r.level = L;
@@ -589,7 +619,7 @@ __device__ __forceinline__ void nearest_surface(const G &g, const Particle &P, N
             const uint32_t s = h >> 4;
             const bool pos = (h >> 3) & 1u;
             const bool on = (P.on_level == L) && (P.on_surf == s);
-            const double d = quad_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w, on);
+            const double d = quad_distance<G::kSurf>(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w, on);
             if (d < r.t || (d == r.t && d != dinf() && L == r.level && s < r.surf)) {
                 r.t = d;
                 r.level = L;
@@ -697,7 +727,7 @@ __device__ __forceinline__ bool rect_extras(const G &g, AP A, double x, double y
         const uint32_t h = g.ahs[at + k];
         const uint32_t s = h >> 4, t = h & 7u;
         const auto c = g.coef + 4 * (size_t)s;
-        const double f = t < ST_CZ ? plane_value(t, c, x, y, z) : quad_value(t, c, x, y, z);
+        const double f = t < ST_CZ ? plane_value<G::kSurf>(t, c, x, y, z) : quad_value<G::kSurf>(t, c, x, y, z);
         const bool pos = s == force_s ? force_pos : f > 0.0;
         if (pos != (bool)((h >> 3) & 1u)) return false;
     }
@@ -814,13 +844,13 @@ __device__ __forceinline__ bool csg_level_distance(const G &g, const Particle &P
     for (uint32_t k = 0; k < npair2; k += 2) {
         const uint32_t h0 = hs[k], h1 = hs[k + 1];
         const auto c0 = g.coef + 4 * (size_t)(h0 >> 4);
-        const double den = plane_den(h0 & 7u, c0, P.u, P.v, P.w);
+        const double den = plane_den<G::kSurf>(h0 & 7u, c0, P.u, P.v, P.w);
         const uint32_t kk = den > 0.0 ? k : k + 1;
         const uint32_t h = den > 0.0 ? h0 : h1;
         const uint32_t s = h >> 4;
         // the pair shares its normal: the linear part from h0's record, the
         // offset from the reached plane's (the operations of plane_value)
-        const double t = (-(plane_linear(h0 & 7u, c0, qx, qy, qz) - plane_offset(h & 7u, g.coef + 4 * (size_t)s))) / den;
+        const double t = (-(plane_linear<G::kSurf>(h0 & 7u, c0, qx, qy, qz) - plane_offset<G::kSurf>(h & 7u, g.coef + 4 * (size_t)s))) / den;
         const bool skip = den == 0.0 || (P.on_level == L && P.on_surf == s);
         const double d = skip ? dinf() : ((t > 0.0) ? t : 0.0);
         better |= nearer(r, d, L, s, den < 0.0, cc.hs_off + kk);
@@ -830,7 +860,7 @@ __device__ __forceinline__ bool csg_level_distance(const G &g, const Particle &P
         const uint32_t s = h >> 4;
         const bool pos = (h >> 3) & 1u;
         if (P.on_level == L && P.on_surf == s) continue;
-        const double d = plane_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w);
+        const double d = plane_distance<G::kSurf>(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w);
         better |= nearer(r, d, L, s, pos, cc.hs_off + k);
     }
     for (uint32_t k = npl; k < cc.n_hs; k++) {
@@ -838,7 +868,7 @@ __device__ __forceinline__ bool csg_level_distance(const G &g, const Particle &P
         const uint32_t s = h >> 4;
         const bool pos = (h >> 3) & 1u;
         const bool on = (P.on_level == L) && (P.on_surf == s);
-        const double d = quad_distance(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w, on);
+        const double d = quad_distance<G::kSurf>(h & 7u, g.coef + 4 * (size_t)s, pos, qx, qy, qz, P.u, P.v, P.w, on);
         better |= nearer(r, d, L, s, pos, cc.hs_off + k);
     }
     return better;
@@ -879,8 +909,8 @@ __device__ __forceinline__ bool rect_level_distance(const G &g, const Particle &
         const bool on = (P.on_level == L) && (P.on_surf == s);
         const auto cf = g.coef + 4 * (size_t)s;
         double d;
-        if ((h & 7u) < ST_CZ) d = on ? dinf() : plane_distance(h & 7u, cf, pos, qx, qy, qz, P.u, P.v, P.w);
-        else d = quad_distance(h & 7u, cf, pos, qx, qy, qz, P.u, P.v, P.w, on);
+        if ((h & 7u) < ST_CZ) d = on ? dinf() : plane_distance<G::kSurf>(h & 7u, cf, pos, qx, qy, qz, P.u, P.v, P.w);
+        else d = quad_distance<G::kSurf>(h & 7u, cf, pos, qx, qy, qz, P.u, P.v, P.w, on);
         better |= nearer(r, d, L, s, pos, kArrExtra);
     }
     return better;
@@ -1412,20 +1442,20 @@ __device__ __forceinline__ void stage_copy(const StagePlan &sp, const unsigned c
 // (signed, so that loops counting down over the kinds end)
 enum StageKind : int { SK_NONE = 0, SK_SPLIT = 1, SK_LDS = 2, SK_ALL = 3 };
 
-template <int KIND> struct ViewOf;
-template <> struct ViewOf<SK_NONE> { typedef DevGlobal type; };
-template <> struct ViewOf<SK_SPLIT> { typedef DevSplit type; };
-template <> struct ViewOf<SK_LDS> { typedef DevLds type; };
-template <> struct ViewOf<SK_ALL> { typedef DevAll type; };
+template <int KIND, int S> struct ViewOf;
+template <int S> struct ViewOf<SK_NONE, S> { typedef DevT<1, 1, 1, S> type; };
+template <int S> struct ViewOf<SK_SPLIT, S> { typedef DevT<3, 1, 1, S> type; };
+template <int S> struct ViewOf<SK_LDS, S> { typedef DevT<3, 3, 1, S> type; };
+template <int S> struct ViewOf<SK_ALL, S> { typedef DevT<3, 3, 3, S> type; };
 
 // The view of a geometry for a kernel of staging kind KIND: staged tables at
 // their LDS copies (`lds`, a workgroup-shared address), the others global.
-template <int KIND>
-__device__ __forceinline__ typename ViewOf<KIND>::type make_view(const Dev &g, const StagePlan &sp,
-                                                                 unsigned char *lds) {
-    typedef typename ViewOf<KIND>::type V;
+template <int KIND, int S = SF_ALL>
+__device__ __forceinline__ typename ViewOf<KIND, S>::type make_view(const Dev &g, const StagePlan &sp,
+                                                                    unsigned char *lds) {
+    typedef typename ViewOf<KIND, S>::type V;
     if constexpr (KIND == SK_NONE) {
-        return global_view(g);
+        return global_view<S>(g);
     } else {
         V d;
         auto lp = [&](int sec) { return lds + sp.at[sec]; };

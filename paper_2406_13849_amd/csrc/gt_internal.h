@@ -12,6 +12,11 @@ namespace gt {
 
 enum SurfType : uint32_t { ST_PX = 0, ST_PY = 1, ST_PZ = 2, ST_P = 3, ST_CZ = 4, ST_SPH = 5 };
 
+// Surface sets the tracker code is compiled for: every type, or only axis
+// planes and z-cylinders (the square lattices of pins).  The host picks the
+// build from the geometry's surface types; both give identical results.
+constexpr int SF_ALL = 0, SF_AXCZ = 1;
+
 // packed half-space: surface id << 4 | positive-side bit << 3 | surface type
 __host__ __device__ inline uint32_t hs_pack(uint32_t s, bool pos, uint32_t type) {
     return (s << 4) | ((pos ? 1u : 0u) << 3) | type;
@@ -268,6 +273,7 @@ struct gt_geometry {
     gt::StagePlan stage_arr[2];   // ... for the trackers that switch on universe kind
     uint32_t rtk_shape;       // 0: not of the fixed-depth reactor shape; else see gt_geometry_kinds
     uint32_t n_rect, n_pin;   // universes recognised as rectilinear arrays and as pins
+    uint32_t surf_set;        // SF_AXCZ when every surface is an axis plane or a z-cylinder, else SF_ALL
     const gt::GeomDesc *desc; // device copy of dev and stage (in the blob)
     void *blob;          // one device allocation holding every table
     uint64_t blob_bytes;

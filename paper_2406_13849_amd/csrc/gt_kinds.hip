@@ -24,8 +24,9 @@ namespace gt {
 namespace {
 
 // KIND = staging kind of the geometry's plan with the universe-kind tables
-// (stage_arr); TRK = TRK_SP or TRK_RTK; SHAPE = the fixed-depth shape (RTK).
-template <int PREC, int KIND, int TRK, int SHAPE>
+// (stage_arr); TRK = TRK_SP or TRK_RTK; SHAPE = the fixed-depth shape (RTK);
+// SF = the surface set the code handles.
+template <int PREC, int KIND, int TRK, int SHAPE, int SF>
 __global__ void __launch_bounds__(kBlockP) __attribute__((amdgpu_waves_per_eu(4)))
 k_track_kinds(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict__ lr, uint32_t tables_at,
               uint32_t tail_at, uint32_t tail_cap, uint32_t tail_round, uint32_t tail_words, uint32_t cache_at,
@@ -37,7 +38,7 @@ k_track_kinds(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict__ lr,
     if (threadIdx.x == 0) ctl[0] = 0;
     if (KIND != SK_NONE) stage_copy(gd->stage_arr[PREC], (const unsigned char *)gd->dev.coef, lds_tables);
     else __syncthreads();
-    const auto g = make_view<KIND>(gd->dev, gd->stage_arr[PREC], lds_tables);
+    const auto g = make_view<KIND, SF>(gd->dev, gd->stage_arr[PREC], lds_tables);
     const KParams &p = lr->p;
     const KOut &o = lr->o;
     uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
@@ -49,32 +50,40 @@ k_track_kinds(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict__ lr,
     add_counts(cnt, o.counters);
 }
 
-template <int PREC, int KIND, int TRK, int SHAPE>
+template <int PREC, int KIND, int TRK, int SHAPE, int SF>
 int launch_kinds_k(const gt_geometry *g, const LaunchRec *lr, uint64_t n, unsigned block, bool tail, bool cache,
                    hipStream_t st) {
     const unsigned tables = KIND == SK_NONE ? 0 : g->stage_arr[PREC].total;
-    const void *kern = (const void *)k_track_kinds<PREC, KIND, TRK, SHAPE>;
+    const void *kern = (const void *)k_track_kinds<PREC, KIND, TRK, SHAPE, SF>;
     LdsPlan lp;
     int rc = plan_persistent(kern, block, tables, tail, cache, 0, g->device, lp);
     if (rc) return rc;
     int blocks = lp.blocks;
     const uint64_t need = (n + block - 1) / block;
     if ((uint64_t)blocks > need) blocks = (int)need;
-    note_launch(lp, blocks, block, KIND);
-    hipLaunchKernelGGL((k_track_kinds<PREC, KIND, TRK, SHAPE>), dim3(blocks), dim3(block), lp.dyn, st, g->desc, lr,
+    note_launch(lp, blocks, block, KIND, SF);
+    hipLaunchKernelGGL((k_track_kinds<PREC, KIND, TRK, SHAPE, SF>), dim3(blocks), dim3(block), lp.dyn, st, g->desc, lr,
                        lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.tail_words, lp.cache_at, lp.cache_k);
     return GT_OK;
 }
 
+template <int PREC, int TRK, int SHAPE, int SF>
+int launch_kinds_s(const gt_geometry *g, const LaunchRec *lr, int kind, uint64_t n, unsigned block, bool tail,
+                   bool cache, hipStream_t st) {
+    switch (kind) {
+    case SK_ALL: return launch_kinds_k<PREC, SK_ALL, TRK, SHAPE, SF>(g, lr, n, block, tail, cache, st);
+    case SK_LDS: return launch_kinds_k<PREC, SK_LDS, TRK, SHAPE, SF>(g, lr, n, block, tail, cache, st);
+    case SK_SPLIT: return launch_kinds_k<PREC, SK_SPLIT, TRK, SHAPE, SF>(g, lr, n, block, tail, cache, st);
+    default: return launch_kinds_k<PREC, SK_NONE, TRK, SHAPE, SF>(g, lr, n, block, tail, cache, st);
+    }
+}
+
+// The build for the geometry's surface set.
 template <int PREC, int TRK, int SHAPE>
 int launch_kinds_t(const gt_geometry *g, const LaunchRec *lr, int kind, uint64_t n, unsigned block, bool tail,
                    bool cache, hipStream_t st) {
-    switch (kind) {
-    case SK_ALL: return launch_kinds_k<PREC, SK_ALL, TRK, SHAPE>(g, lr, n, block, tail, cache, st);
-    case SK_LDS: return launch_kinds_k<PREC, SK_LDS, TRK, SHAPE>(g, lr, n, block, tail, cache, st);
-    case SK_SPLIT: return launch_kinds_k<PREC, SK_SPLIT, TRK, SHAPE>(g, lr, n, block, tail, cache, st);
-    default: return launch_kinds_k<PREC, SK_NONE, TRK, SHAPE>(g, lr, n, block, tail, cache, st);
-    }
+    return g->surf_set == SF_AXCZ ? launch_kinds_s<PREC, TRK, SHAPE, SF_AXCZ>(g, lr, kind, n, block, tail, cache, st)
+                                  : launch_kinds_s<PREC, TRK, SHAPE, SF_ALL>(g, lr, kind, n, block, tail, cache, st);
 }
 
 }  // namespace

@@ -41,7 +41,7 @@ int persistent_grid(const void *kernel, unsigned block, unsigned dyn, int device
 int allow_dynamic_lds(const void *kernel, unsigned bytes);
 int plan_persistent(const void *kern, unsigned block, unsigned tables, bool tail, bool cache, uint32_t regroup,
                     int device, LdsPlan &lp);
-void note_launch(const LdsPlan &lp, int blocks, unsigned block, int kind);
+void note_launch(const LdsPlan &lp, int blocks, unsigned block, int kind, int surf);
 
 // Events recorded around the tracking kernels of this thread's next launches
 // (set by gt_set_kernel_events; both null = off).

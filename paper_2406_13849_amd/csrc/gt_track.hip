@@ -86,8 +86,9 @@ __global__ void __launch_bounds__(kBlock) k_ev_cross(Dev g0, KParams p, KOut o, 
 // KIND = staging kind of the geometry's plan (see make_view); W = waves per
 // SIMD the register budget is cut for: 4 (up to 1024 lanes per workgroup,
 // 128 registers) or 5 (640 lanes, two workgroups per compute unit, 96
-// registers).
-template <int PREC, int KIND, int W, bool RG, bool MESH>
+// registers); SF = the surface set the code handles (SF_AXCZ for
+// geometries of axis planes and z-cylinders only, else SF_ALL).
+template <int PREC, int KIND, int W, bool RG, bool MESH, int SF>
 __global__ void __launch_bounds__(W == 5 ? 640 : kBlockP) __attribute__((amdgpu_waves_per_eu(W)))
 k_track_persistent(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict__ lr, uint32_t tables_at,
                    uint32_t tail_at, uint32_t tail_cap, uint32_t tail_round, uint32_t tail_words, uint32_t regroup,
@@ -99,7 +100,7 @@ k_track_persistent(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict_
     if (threadIdx.x == 0) ctl[0] = 0;
     if (KIND != SK_NONE) stage_copy(gd->stage[PREC], (const unsigned char *)gd->dev.coef, lds_tables);
     else __syncthreads();
-    const auto g = make_view<KIND>(gd->dev, gd->stage[PREC], lds_tables);
+    const auto g = make_view<KIND, SF>(gd->dev, gd->stage[PREC], lds_tables);
     const KParams &p = lr->p;
     const KOut &o = lr->o;
     uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
@@ -440,8 +441,9 @@ thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
 thread_local gt_launch_info t_last_launch;
 thread_local bool t_have_launch = false;
 
-void note_launch(const LdsPlan &lp, int blocks, unsigned block, int kind) {
-    t_last_launch = {(uint32_t)blocks, block, lp.dyn, (uint32_t)kind, lp.cache_k, lp.tail_cap, lp.regroup, 0};
+void note_launch(const LdsPlan &lp, int blocks, unsigned block, int kind, int surf) {
+    t_last_launch = {(uint32_t)blocks, block, lp.dyn, (uint32_t)kind, lp.cache_k, lp.tail_cap, lp.regroup,
+                     (uint32_t)surf};
     t_have_launch = true;
 }
 
@@ -451,50 +453,59 @@ namespace {
 // One persistent tracker launch for a geometry of staging kind KIND: the
 // build with the mesh tally when there is a mesh, else the one with the
 // regroup step when one is asked for and finds room, else the plain one.
-template <int PREC, int KIND, int W>
+template <int PREC, int KIND, int W, int SF>
 int launch_persistent_k(const gt_geometry *g, const LaunchRec *lr, uint64_t n, unsigned block, bool tail, bool cache,
                         uint32_t regroup, bool mesh, hipStream_t st) {
     const unsigned tables = KIND == SK_NONE ? 0 : g->stage[PREC].total;
-    const void *plain = (const void *)k_track_persistent<PREC, KIND, W, false, false>;
-    const void *kern = mesh ? (const void *)k_track_persistent<PREC, KIND, W, false, true> : plain;
+    const void *plain = (const void *)k_track_persistent<PREC, KIND, W, false, false, SF>;
+    const void *kern = mesh ? (const void *)k_track_persistent<PREC, KIND, W, false, true, SF> : plain;
     LdsPlan lp;
     int rc = GT_OK;
     if (regroup && !mesh) {
-        const void *kr = (const void *)k_track_persistent<PREC, KIND, W, true, false>;
+        const void *kr = (const void *)k_track_persistent<PREC, KIND, W, true, false, SF>;
         rc = plan_persistent(kr, block, tables, tail, cache, regroup, g->device, lp);
         if (!rc && lp.regroup) kern = kr;
     }
-    if (!rc && kern != (const void *)k_track_persistent<PREC, KIND, W, true, false>)
+    if (!rc && kern != (const void *)k_track_persistent<PREC, KIND, W, true, false, SF>)
         rc = plan_persistent(kern, block, tables, tail, cache, 0, g->device, lp);
     if (rc) return rc;
     int blocks = lp.blocks;
     const uint64_t need = (n + block - 1) / block;
     if ((uint64_t)blocks > need) blocks = (int)need;
-    note_launch(lp, blocks, block, KIND);
+    note_launch(lp, blocks, block, KIND, SF);
     if (mesh)
-        hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, false, true>), dim3(blocks), dim3(block), lp.dyn, st,
+        hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, false, true, SF>), dim3(blocks), dim3(block), lp.dyn, st,
                            g->desc, lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.tail_words, 0u,
                            lp.cache_at, lp.cache_k);
     else if (lp.regroup)
-        hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, true, false>), dim3(blocks), dim3(block), lp.dyn, st,
+        hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, true, false, SF>), dim3(blocks), dim3(block), lp.dyn, st,
                            g->desc, lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.tail_words, lp.regroup,
                            lp.cache_at, lp.cache_k);
     else
-        hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, false, false>), dim3(blocks), dim3(block), lp.dyn, st,
+        hipLaunchKernelGGL((k_track_persistent<PREC, KIND, W, false, false, SF>), dim3(blocks), dim3(block), lp.dyn, st,
                            g->desc, lr, lp.tables_at, lp.tail_at, lp.tail_cap, kTailRound, lp.tail_words, 0u,
                            lp.cache_at, lp.cache_k);
     return GT_OK;
 }
 
+template <int PREC, int W, int SF>
+int launch_persistent_s(const gt_geometry *g, const LaunchRec *lr, int kind, uint64_t n, unsigned block, bool tail,
+                        bool cache, uint32_t regroup, bool mesh, hipStream_t st) {
+    switch (kind) {
+    case SK_ALL: return launch_persistent_k<PREC, SK_ALL, W, SF>(g, lr, n, block, tail, cache, regroup, mesh, st);
+    case SK_LDS: return launch_persistent_k<PREC, SK_LDS, W, SF>(g, lr, n, block, tail, cache, regroup, mesh, st);
+    case SK_SPLIT: return launch_persistent_k<PREC, SK_SPLIT, W, SF>(g, lr, n, block, tail, cache, regroup, mesh, st);
+    default: return launch_persistent_k<PREC, SK_NONE, W, SF>(g, lr, n, block, tail, cache, regroup, mesh, st);
+    }
+}
+
+// The build for the geometry's surface set.
 template <int PREC, int W>
 int launch_persistent(const gt_geometry *g, const LaunchRec *lr, int kind, uint64_t n, unsigned block, bool tail,
                       bool cache, uint32_t regroup, bool mesh, hipStream_t st) {
-    switch (kind) {
-    case SK_ALL: return launch_persistent_k<PREC, SK_ALL, W>(g, lr, n, block, tail, cache, regroup, mesh, st);
-    case SK_LDS: return launch_persistent_k<PREC, SK_LDS, W>(g, lr, n, block, tail, cache, regroup, mesh, st);
-    case SK_SPLIT: return launch_persistent_k<PREC, SK_SPLIT, W>(g, lr, n, block, tail, cache, regroup, mesh, st);
-    default: return launch_persistent_k<PREC, SK_NONE, W>(g, lr, n, block, tail, cache, regroup, mesh, st);
-    }
+    return g->surf_set == SF_AXCZ
+               ? launch_persistent_s<PREC, W, SF_AXCZ>(g, lr, kind, n, block, tail, cache, regroup, mesh, st)
+               : launch_persistent_s<PREC, W, SF_ALL>(g, lr, kind, n, block, tail, cache, regroup, mesh, st);
 }
 
 // The work of one staging kind of a batch, in one launch: n chunks at ch,
@@ -517,7 +528,7 @@ int launch_batch_k(gt_batch *b, const BatchChunk *ch, uint32_t n, unsigned long 
     // no more workgroups than chunks, or than whole workgroups of histories
     const uint64_t cap = ns ? (nh + b->block - 1) / b->block : n;
     if ((uint64_t)blocks > cap) blocks = (int)cap;
-    note_launch(lp, blocks, b->block, KIND);
+    note_launch(lp, blocks, b->block, KIND, SF_ALL);
     if (lp.regroup)
         hipLaunchKernelGGL((k_track_batch<PREC, KIND, W, true>), dim3(blocks), dim3(b->block), lp.dyn, st,
                            b->d_items, ch, n, q, sl, ns, b->d_claimed, b->d_workers, lp.tables_at, lp.tail_at,

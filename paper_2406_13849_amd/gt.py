@@ -86,7 +86,7 @@ class _Mesh(C.Structure):
 
 class _LaunchInfo(C.Structure):
     _fields_ = [(n, C.c_uint32) for n in ("workgroups", "block_size", "lds_bytes", "staging_kind",
-                                          "tally_cache_entries", "tail_capacity", "regroup_every", "reserved")]
+                                          "tally_cache_entries", "tail_capacity", "regroup_every", "surface_set")]
 
 
 _lib = None
@@ -528,7 +528,7 @@ def last_launch() -> Optional[dict]:
     rc = lib().gt_last_launch(C.byref(info))
     if rc < 0:
         _check(rc)
-    return {n: getattr(info, n) for n, _ in _LaunchInfo._fields_ if n != "reserved"} if rc == 1 else None
+    return {n: getattr(info, n) for n, _ in _LaunchInfo._fields_} if rc == 1 else None
 
 
 def set_kernel_events(start: Optional[int], stop: Optional[int]):

@@ -15,9 +15,14 @@ namespace {
 constexpr size_t kLdsEmuBytes = 160 * 1024;
 thread_local unsigned char g_lds[kLdsEmuBytes];
 thread_local uint32_t g_cache_k = kTallyCacheMax;   // tally-cache entries of the lane (0 = off)
+// The surface set the lane's code is compiled for: the geometry's own (as the
+// library picks it), unless a test forces the build for every type.
+thread_local int g_surf = SF_ALL;
+thread_local int g_force_surf = -1;
 
-template <int PREC, int KIND, bool MESH, typename Queue, int TRK = TRK_ST, int SHAPE = 0>
-void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut &o, const Queue &q, uint64_t *counts) {
+template <int PREC, int KIND, bool MESH, typename Queue, int TRK, int SHAPE, int SF>
+void run_lane_s(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut &o, const Queue &q,
+                uint64_t *counts) {
     static thread_local uint32_t cells[GT_MAX_LEVELS];
     static thread_local uint32_t ctl[1 + kBlockP / 64];
     static thread_local uint64_t c_lo[kTallyCacheMax], c_hi[kTallyCacheMax];
@@ -25,7 +30,7 @@ void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut
     blockDim.x = 1;
     threadIdx.x = 0;
     if (KIND != SK_NONE) stage_copy(sp, (const unsigned char *)dev.coef, g_lds);
-    const auto v = make_view<KIND>(dev, sp, g_lds);
+    const auto v = make_view<KIND, SF>(dev, sp, g_lds);
     KParams p = p0;
     p.refill_min = 1;   // a one-lane wave refills as soon as its lane is idle
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
@@ -40,6 +45,14 @@ void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut
     counts[GT_CNT_SEGMENTS] += cnt.segments;
     counts[GT_CNT_REJECTED] += cnt.rejected;
 }
+
+template <int PREC, int KIND, bool MESH, typename Queue, int TRK = TRK_ST, int SHAPE = 0>
+void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut &o, const Queue &q, uint64_t *counts) {
+    if (g_surf == SF_AXCZ) run_lane_s<PREC, KIND, MESH, Queue, TRK, SHAPE, SF_AXCZ>(dev, sp, p0, o, q, counts);
+    else run_lane_s<PREC, KIND, MESH, Queue, TRK, SHAPE, SF_ALL>(dev, sp, p0, o, q, counts);
+}
+
+int surf_of(const gt_geometry *g) { return g_force_surf >= 0 ? g_force_surf : (int)g->surf_set; }
 
 template <int PREC, bool MESH = false, typename Queue>
 int run_kind(int kind, const Dev &dev, const StagePlan &sp, const KParams &p, const KOut &o, const Queue &q,
@@ -88,6 +101,7 @@ extern "C" int cpu_track(const gt_geometry *g, const gt_track_params *p, const g
     KOut ko;
     fill_kparams(p, g, kp, ko, o);
     g_cache_k = (p->flags & GT_FLAG_NO_TALLY_CACHE) ? 0 : kTallyCacheMax;
+    g_surf = surf_of(g);
     std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
@@ -116,6 +130,7 @@ extern "C" int cpu_track_kinds(const gt_geometry *g, const gt_track_params *p, c
     KOut ko;
     fill_kparams(p, g, kp, ko, o);
     g_cache_k = (p->flags & GT_FLAG_NO_TALLY_CACHE) ? 0 : kTallyCacheMax;
+    g_surf = surf_of(g);
     std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
@@ -166,6 +181,7 @@ extern "C" int cpu_track_mesh(const gt_geometry *g, const gt_track_params *p, co
     if (m->workspace_bytes < gt_mesh_workspace_bytes(md.nb)) return set_error("cpu_track_mesh: workspace"), GT_EINVAL;
     std::memset(md.ws, 0, (size_t)kReplicas * 4 * 8 * md.nb);
     g_cache_k = kTallyCacheMax;
+    g_surf = surf_of(g);
     std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
@@ -226,6 +242,10 @@ extern "C" int cpu_track_event(const gt_geometry *g, const gt_track_params *p, c
     return p->precision == GT_PREC_MIXED ? cpu_event_t<GT_PREC_MIXED>(g, p, o) : cpu_event_t<GT_PREC_FP64>(g, p, o);
 }
 
+// The surface set of the lane's code for later calls: -1 (the default) the
+// geometry's own, as the library picks it; 0 or 1 forces SF_ALL or SF_AXCZ.
+extern "C" void cpu_force_surface_set(int sf) { g_force_surf = sf; }
+
 // gt_track_batch on the CPU: gt_batch_create's descriptors (in host memory)
 // executed the way gt_batch_launch executes them -- the fill list, then the
 // chunk groups by staging kind (3, 2, 1, 0) each chunk through one lane with
@@ -248,6 +268,7 @@ extern "C" int cpu_track_batch(const gt_batch_item *items, uint32_t n_items, con
         }
     }
     g_cache_k = b->cache ? kTallyCacheMax : 0;
+    g_surf = SF_ALL;   // batches run the build for every surface type
     uint32_t first = 0, ran = 0;
     if (b->by_item) {
         if (groups == 0) {

@@ -38,6 +38,8 @@ class HostLib:
         L.gt_geometry_destroy.restype = None
         L.gt_last_error.restype = C.c_char_p
         L.cpu_track.argtypes = [vp, C.POINTER(gt._Params), C.POINTER(gt._Out), C.c_int]
+        L.cpu_force_surface_set.argtypes = [C.c_int]
+        L.cpu_force_surface_set.restype = None
         L.cpu_track_batch.argtypes = [C.POINTER(gt._BatchItem), C.c_uint32, C.POINTER(gt._Tuning),
                                       C.POINTER(C.c_uint32), C.c_uint32]
         L.cpu_track_mesh.argtypes = [vp, C.POINTER(gt._Params), C.POINTER(gt._Out), C.POINTER(gt._Mesh), C.c_int]
@@ -118,20 +120,26 @@ def make(what, k):
 def test_cpu_build_matches_oracle(host, what, k):
     """Every staging kind the geometry can be held in (its own and all
     global), both precisions, with and without the lane's tally cache, 400
-    histories with recorded sequences."""
+    histories with recorded sequences; the code built for the geometry's own
+    surface set and the code built for every surface type."""
     fg, kw = make(what, k)
     h, ni = host.geometry(fg)
     n, rk, cap = 400, 30, 48
     o = oracle.track(oracle.OracleGeometry(fg), oracle.TrackParams(n_particles=n, record_first_k=rk,
                                                                     record_cap=cap, **kw), n_threads=4)
-    for prec in (gt.PREC_FP64, gt.PREC_MIXED):
-        for kind in sorted({0, host.staging(h, prec)}):
-            for cache in ((True, False) if kind else (True,)):
-                out = Outs(ni, n, rk, cap)
-                prm = gt._params(kw["seed"], n, geometry_id=kw["geometry_id"], precision=prec, record_first_k=rk,
-                                 record_cap=cap, tally_cache=cache)
-                host.check(host.L.cpu_track(h, C.byref(prm), C.byref(out.struct()), kind))
-                same(out.a, o, rk)
+    try:
+        for sf in (-1, 0):
+            host.L.cpu_force_surface_set(sf)
+            for prec in (gt.PREC_FP64, gt.PREC_MIXED):
+                for kind in sorted({0, host.staging(h, prec)}):
+                    for cache in ((True, False) if kind else (True,)):
+                        out = Outs(ni, n, rk, cap)
+                        prm = gt._params(kw["seed"], n, geometry_id=kw["geometry_id"], precision=prec,
+                                         record_first_k=rk, record_cap=cap, tally_cache=cache)
+                        host.check(host.L.cpu_track(h, C.byref(prm), C.byref(out.struct()), kind))
+                        same(out.a, o, rk)
+    finally:
+        host.L.cpu_force_surface_set(-1)
     host.L.gt_geometry_destroy(h)
 
 

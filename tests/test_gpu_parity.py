@@ -233,6 +233,33 @@ def test_launch_shapes_do_not_change_results(block, lane, refill):
     assert_parity(g, o, where="block %d" % block)
 
 
+def test_surface_set_build_chosen():
+    """The tracker code built for axis planes and z-cylinders runs exactly
+    for the geometries made of those only (the 3x3, 17x17 and three-level
+    square workloads), the build for every surface type for the hexagonal
+    core and the sphere; single tracker, SP and RTK alike, and each against
+    the oracle."""
+    import torch
+    cases = [(("cfg", 1), 1), (("cfg", 2), 1), (("cfg", 3), 1), (("cfg", 4), 0), (("fn", "sphere"), 0)]
+    for (what, k), want in cases:
+        if what == "cfg":
+            fg, G, O = geoms(k)
+            kw = dict(seed=31, n_particles=3000, geometry_id=k)
+        else:
+            fg = getattr(synth, k)()
+            G, O = gt.Geometry(fg), oracle.OracleGeometry(fg)
+            kw = dict(seed=31, n_particles=3000, geometry_id=9)
+        trackers = ["st", "sp"] + (["rtk"] if G.kinds()[2] else [])
+        for trk in trackers:
+            print("surface set", what, k, trk, flush=True)
+            extra = {} if trk == "st" else dict(tracker=trk)
+            g = gpu_track(G, precision=gt.PREC_FP64 if trk == "rtk" else gt.PREC_MIXED, **extra, **kw)
+            torch.cuda.synchronize()
+            assert gt.last_launch()["surface_set"] == want, (what, k, trk)
+            o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT)
+            assert_parity(g, o, where="surface set %s%s %s" % (what, k, trk))
+
+
 @pytest.mark.parametrize("wave", [64, 128, 256, 1024])
 @pytest.mark.parametrize("cfg,n", [(2, 20_000), (3, 30_000)])
 def test_histories_per_wave_claim(wave, cfg, n):
