@@ -2,18 +2,24 @@
 // through nested CSG universes with one CSG tracker and per-universe
 // bounding-volume hierarchies (Section "Single tracker (ST) method").
 //
-// Two schedules share every device function:
-//   - k_track_persistent (default): one workgroup per compute unit; each
-//     wave loops until the particle pool is drained, refilling finished
-//     lanes from a wave-local pool of particle ids, and every lane runs a
-//     small state machine whose steps (draw random numbers, search one
-//     level, one segment) each have a single call site;
-//   - k_track (GT_FLAG_LANE_PER_HISTORY): one history per lane.
+// Three schedules share every device function:
+//   - persistent (default): one workgroup per compute unit; each wave loops
+//     until the particle pool is drained, refilling finished lanes from a
+//     wave-local pool of particle ids, and every lane runs a small state
+//     machine whose steps (draw random numbers, search one level, one
+//     segment) each have a single call site -- k_track_persistent for one
+//     geometry, k_track_batch for many in one launch;
+//   - k_track (GT_FLAG_LANE_PER_HISTORY): one history per lane;
+//   - event-based (gt_track_event): one kernel per operation per iteration
+//     over a particle bank in device memory.
 // A particle's state lives in registers; the cell of each level lives in
-// LDS (one column per lane) so level loops index it without spilling.
+// LDS (one column per lane) so level loops index it without spilling.  The
+// persistent single-geometry trackers are built twice: for geometries of
+// axis planes and z-cylinders only, and for every surface type.
 //
 // The device functions are in gt_device.h; this file holds the kernels and
-// their host-side launchers.
+// their host-side launchers (the trackers that switch on universe kind are
+// in gt_kinds.hip).
 #pragma clang fp contract(off)
 
 #include <algorithm>
