@@ -74,7 +74,8 @@ WORKLOAD_NAMES = {1: "3x3 square lattice of one pin type (two levels)",
                      "3 types (four levels)",
                   4: "7-ring hexagonal core of 9-ring hexagonal assemblies, planes only (three levels)"}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2406_13849_amd", "csrc", f)
-                  for f in ("gt_device.h", "gt_track.hip", "gt_internal.h", "gt_geometry.cpp", "gt_launch.h")]
+                  for f in ("gt_device.h", "gt_track.hip", "gt_internal.h", "gt_geometry.cpp", "gt_launch.h",
+                            "gt_persistent.h", "gt_track_axcz.hip", "gt_track_vert.hip")]
 
 
 def parse():

@@ -16,7 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgt.so")
-SOURCES = ["gt_geometry.cpp", "gt_tune.cpp", "gt_track.hip", "gt_kinds.hip"]
+SOURCES = ["gt_geometry.cpp", "gt_tune.cpp", "gt_track.hip", "gt_track_axcz.hip", "gt_track_vert.hip", "gt_kinds.hip"]
 ARCH = os.environ.get("GT_OFFLOAD_ARCH", "gfx950")
 
 

@@ -41,9 +41,9 @@ __device__ __forceinline__ double dinf() { return __builtin_huge_val(); }
 // tables (cells, half-spaces, surfaces, universes, materials, local indices)
 // in address space A, the crossing tables (translations, candidate lists) in
 // B and the hierarchy (nodes, leaves, cell boxes) in C; 3 = LDS, 1 = global.
-// S is the set of surface types the code handles (SF_ALL, or SF_AXCZ when
-// the geometry has only axis planes and z-cylinders): the surface
-// functions below are compiled for that set alone.
+// S is the set of surface types the code handles (SF_ALL, SF_AXCZ or
+// SF_VERT; see gt_internal.h): the surface functions below are compiled for
+// that set alone.
 template <int AS, typename T> using cptr = const GT_AS(AS) T *;
 
 template <int A, int B, int C, int S = SF_ALL>
@@ -221,6 +221,13 @@ __device__ __forceinline__ double plane_value(uint32_t type, CP c, double x, dou
         case ST_PY: return y - c[0];
         default: return z - c[0];
         }
+    } else if constexpr (SF == SF_VERT) {
+        switch (type) {
+        case ST_PX: return x - c[0];
+        case ST_PY: return y - c[0];
+        case ST_PZ: return z - c[0];
+        default: return (c[0] * x + c[1] * y) - c[3];
+        }
     } else {
         switch (type) {
         case ST_PX: return x - c[0];
@@ -241,6 +248,13 @@ __device__ __forceinline__ double plane_linear(uint32_t type, CP c, double x, do
         case ST_PY: return y;
         default: return z;
         }
+    } else if constexpr (SF == SF_VERT) {
+        switch (type) {
+        case ST_PX: return x;
+        case ST_PY: return y;
+        case ST_PZ: return z;
+        default: return c[0] * x + c[1] * y;
+        }
     } else {
         switch (type) {
         case ST_PX: return x;
@@ -260,7 +274,7 @@ __device__ __forceinline__ double plane_offset(uint32_t type, CP c) {
 template <int SF, typename CP>
 __device__ __forceinline__ double quad_value(uint32_t type, CP c, double x, double y, double z) {
     const double dx = x - c[0], dy = y - c[1];
-    if (SF == SF_AXCZ || type == ST_CZ) return (dx * dx + dy * dy) - c[2];
+    if (SF != SF_ALL || type == ST_CZ) return (dx * dx + dy * dy) - c[2];
     const double dz = z - c[2];
     return ((dx * dx + dy * dy) + dz * dz) - c[3];
 }
@@ -318,6 +332,13 @@ __device__ __forceinline__ double plane_den(uint32_t type, CP c, double u, doubl
         case ST_PY: return v;
         default: return w;
         }
+    } else if constexpr (SF == SF_VERT) {
+        switch (type) {
+        case ST_PX: return u;
+        case ST_PY: return v;
+        case ST_PZ: return w;
+        default: return c[0] * u + c[1] * v;
+        }
     } else {
         switch (type) {
         case ST_PX: return u;
@@ -348,7 +369,7 @@ __device__ __forceinline__ double quad_root(double a, double b, double cc, bool 
 template <int SF, typename CP>
 __device__ __forceinline__ double quad_distance(uint32_t type, CP c, bool pos, double qx, double qy,
                                                 double qz, double u, double v, double w, bool on) {
-    const bool cyl = SF == SF_AXCZ || type == ST_CZ;
+    const bool cyl = SF != SF_ALL || type == ST_CZ;
     const double c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
     const double dx = qx - c0, dy = qy - c1, dz = qz - c2;
     const double a2 = u * u + v * v, b2 = dx * u + dy * v, r2 = dx * dx + dy * dy;

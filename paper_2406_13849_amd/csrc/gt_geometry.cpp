@@ -841,9 +841,13 @@ extern "C" int gt_geometry_create(const gt_flat_geometry *f, gt_geometry **out) 
         g->dev.n_inst = (uint32_t)B.ninst[F.root];
         g->dev.max_depth = B.depth[F.root];
         g->dev.n_cells = F.n_cells;
-        g->surf_set = SF_AXCZ;
-        for (uint32_t s = 0; s < F.n_surfaces; s++)
-            if (F.surf_type[s] == ST_P || F.surf_type[s] == ST_SPH) g->surf_set = SF_ALL;
+        // the smallest surface set of the tracker builds that holds every surface
+        bool general = false, vertical = false;
+        for (uint32_t s = 0; s < F.n_surfaces; s++) {
+            if (F.surf_type[s] == ST_SPH) general = true;
+            if (F.surf_type[s] == ST_P) (F.surf_coef[8 * (size_t)s + 2] == 0.0 ? vertical : general) = true;
+        }
+        g->surf_set = general ? SF_ALL : vertical ? SF_VERT : SF_AXCZ;
         for (int k = 0; k < 3; k++) { g->dev.lo[k] = F.domain_lo[k]; g->dev.hi[k] = F.domain_hi[k]; }
         // LDS staging plans per precision mode: the per-segment tables (cells,
         // half-spaces, surfaces, universes, materials, local indices) if they

@@ -12,10 +12,14 @@ namespace gt {
 
 enum SurfType : uint32_t { ST_PX = 0, ST_PY = 1, ST_PZ = 2, ST_P = 3, ST_CZ = 4, ST_SPH = 5 };
 
-// Surface sets the tracker code is compiled for: every type, or only axis
-// planes and z-cylinders (the square lattices of pins).  The host picks the
-// build from the geometry's surface types; both give identical results.
-constexpr int SF_ALL = 0, SF_AXCZ = 1;
+// Surface sets the tracker code is compiled for: every type; only axis
+// planes and z-cylinders (square lattices of pins); or those and general
+// planes parallel to the z axis (zero z coefficient: hexagonal lattices),
+// whose value and denominator then leave out the z term -- a signed zero,
+// which can change only the sign of a zero result, on which no decision
+// depends.  The host picks the build from the geometry's surfaces; every
+// build gives identical results.
+constexpr int SF_ALL = 0, SF_AXCZ = 1, SF_VERT = 2;
 
 // packed half-space: surface id << 4 | positive-side bit << 3 | surface type
 __host__ __device__ inline uint32_t hs_pack(uint32_t s, bool pos, uint32_t type) {
@@ -273,7 +277,7 @@ struct gt_geometry {
     gt::StagePlan stage_arr[2];   // ... for the trackers that switch on universe kind
     uint32_t rtk_shape;       // 0: not of the fixed-depth reactor shape; else see gt_geometry_kinds
     uint32_t n_rect, n_pin;   // universes recognised as rectilinear arrays and as pins
-    uint32_t surf_set;        // SF_AXCZ when every surface is an axis plane or a z-cylinder, else SF_ALL
+    uint32_t surf_set;        // SF_AXCZ, SF_VERT or SF_ALL (the smallest set that holds every surface)
     const gt::GeomDesc *desc; // device copy of dev and stage (in the blob)
     void *blob;          // one device allocation holding every table
     uint64_t blob_bytes;

@@ -82,8 +82,11 @@ int launch_kinds_s(const gt_geometry *g, const LaunchRec *lr, int kind, uint64_t
 template <int PREC, int TRK, int SHAPE>
 int launch_kinds_t(const gt_geometry *g, const LaunchRec *lr, int kind, uint64_t n, unsigned block, bool tail,
                    bool cache, hipStream_t st) {
-    return g->surf_set == SF_AXCZ ? launch_kinds_s<PREC, TRK, SHAPE, SF_AXCZ>(g, lr, kind, n, block, tail, cache, st)
-                                  : launch_kinds_s<PREC, TRK, SHAPE, SF_ALL>(g, lr, kind, n, block, tail, cache, st);
+    switch (g->surf_set) {
+    case SF_AXCZ: return launch_kinds_s<PREC, TRK, SHAPE, SF_AXCZ>(g, lr, kind, n, block, tail, cache, st);
+    case SF_VERT: return launch_kinds_s<PREC, TRK, SHAPE, SF_VERT>(g, lr, kind, n, block, tail, cache, st);
+    default: return launch_kinds_s<PREC, TRK, SHAPE, SF_ALL>(g, lr, kind, n, block, tail, cache, st);
+    }
 }
 
 }  // namespace

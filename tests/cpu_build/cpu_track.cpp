@@ -49,6 +49,7 @@ void run_lane_s(const Dev &dev, const StagePlan &sp, const KParams &p0, const KO
 template <int PREC, int KIND, bool MESH, typename Queue, int TRK = TRK_ST, int SHAPE = 0>
 void run_lane(const Dev &dev, const StagePlan &sp, const KParams &p0, const KOut &o, const Queue &q, uint64_t *counts) {
     if (g_surf == SF_AXCZ) run_lane_s<PREC, KIND, MESH, Queue, TRK, SHAPE, SF_AXCZ>(dev, sp, p0, o, q, counts);
+    else if (g_surf == SF_VERT) run_lane_s<PREC, KIND, MESH, Queue, TRK, SHAPE, SF_VERT>(dev, sp, p0, o, q, counts);
     else run_lane_s<PREC, KIND, MESH, Queue, TRK, SHAPE, SF_ALL>(dev, sp, p0, o, q, counts);
 }
 
@@ -243,7 +244,8 @@ extern "C" int cpu_track_event(const gt_geometry *g, const gt_track_params *p, c
 }
 
 // The surface set of the lane's code for later calls: -1 (the default) the
-// geometry's own, as the library picks it; 0 or 1 forces SF_ALL or SF_AXCZ.
+// geometry's own, as the library picks it; 0, 1 or 2 forces SF_ALL, SF_AXCZ or
+// SF_VERT.
 extern "C" void cpu_force_surface_set(int sf) { g_force_surf = sf; }
 
 // gt_track_batch on the CPU: gt_batch_create's descriptors (in host memory)
