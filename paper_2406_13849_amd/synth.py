@@ -619,6 +619,33 @@ def nested_box(half: float = 1.0, sigma: float = 0.7) -> FlatGeometry:
     return b.build(root, [sigma], (-h, -h, -h), (h, h, h), "nested_box")
 
 
+def deep_slabs(levels: int = 6, sigma: float = 0.5) -> FlatGeometry:
+    """The deepest nesting the library takes: a root box |x|, |y|, |z| < 2
+    filled with universe 1, and each universe k = 1 .. levels-2 split along
+    x into a left slab, a middle slab filled with universe k+1 (translated a
+    little in x and y) and a right slab, the slabs narrowing with k; the
+    last universe is a z-cylinder of radius 0.3 and what lies outside it.
+    Materials differ by level, so tallies tell the levels apart."""
+    if not 2 <= levels <= 6:
+        raise ValueError("levels must be 2..6")
+    b = GeomBuilder()
+    box = [b.surface(PX, -2.0), b.surface(PX, 2.0), b.surface(PY, -2.0), b.surface(PY, 2.0),
+           b.surface(PZ, -2.0), b.surface(PZ, 2.0)]
+    root = b.universe([([pos(box[0]), neg(box[1]), pos(box[2]), neg(box[3]), pos(box[4]), neg(box[5])],
+                        fill_universe(1), (0.1, -0.05, 0.0))])
+    for k in range(1, levels - 1):
+        a = 1.8 - 0.3 * k
+        sl, sr = b.surface(PX, -a), b.surface(PX, a)
+        u = b.universe([([neg(sl)], k % 3, (0.0, 0.0, 0.0)),
+                        ([pos(sl), neg(sr)], fill_universe(k + 1), (0.03 * k, 0.02, 0.0)),
+                        ([pos(sr)], (k + 1) % 3, (0.0, 0.0, 0.0))])
+        assert u == k
+    cyl = b.surface(CZ, 0.0, 0.0, 0.09)
+    last = b.universe([([neg(cyl)], 1, (0.0, 0.0, 0.0)), ([pos(cyl)], 2, (0.0, 0.0, 0.0))])
+    assert last == levels - 1 and root == 0
+    return b.build(root, [sigma, 0.8 * sigma, 1.3 * sigma], (-2.0, -2.0, -2.0), (2.0, 2.0, 2.0), "deep_slabs")
+
+
 WORKLOADS = {1: config1, 2: config2, 3: config3, 4: config4}
 
 # particle counts of the workload table, and the seeds: geometry 1000+i,

@@ -103,8 +103,8 @@ def host():
         raise   # a build that fails is a failure, not a skip
 
 
-GEOMS = [("cfg", 1), ("cfg", 2), ("cfg", 4), ("fn", "sphere"), ("fn", "nested_box"), ("batch", 3), ("batch", 5), ("batch", 41),
-         ("batch", 57), ("batch", 2), ("batch", 63)]
+GEOMS = [("cfg", 1), ("cfg", 2), ("cfg", 4), ("fn", "sphere"), ("fn", "nested_box"), ("fn", "deep_slabs"), ("batch", 3),
+         ("batch", 5), ("batch", 41), ("batch", 57), ("batch", 2), ("batch", 63)]
 
 
 def make(what, k):

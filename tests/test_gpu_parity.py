@@ -241,7 +241,7 @@ def test_surface_set_build_chosen():
     tracker, SP and RTK alike, and each against the oracle."""
     import torch
     cases = [(("cfg", 1), 1), (("cfg", 2), 1), (("cfg", 3), 1), (("cfg", 4), 2), (("fn", "sphere"), 0),
-             (("fn", "nested_box"), None)]
+             (("fn", "nested_box"), None), (("fn", "deep_slabs"), 1)]
     for (what, k), want in cases:
         if what == "cfg":
             fg, G, O = geoms(k)
