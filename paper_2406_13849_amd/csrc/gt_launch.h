@@ -1,6 +1,8 @@
 // Host-side launch helpers shared by the kernel translation units of libgt
-// (gt_track.hip: the single tracker, batches, event schedule; gt_kinds.hip:
-// the trackers that switch on universe kind).  Not part of the public ABI.
+// (gt_track.hip: the single tracker, batches, event schedule;
+// gt_track_axcz.hip and gt_track_vert.hip: the single tracker's builds for
+// smaller surface sets; gt_kinds.hip: the trackers that switch on universe
+// kind).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -328,22 +328,18 @@ int persistent_grid(const void *kernel, unsigned block, unsigned dyn, int device
 // Let a kernel use up to `bytes` of dynamic LDS (once per kernel).
 int allow_dynamic_lds(const void *kernel, unsigned bytes) {
     std::lock_guard<std::mutex> lk(g_launch_mu);
-    static const void *done[64];
+    constexpr int kDone = 256;   // kernels remembered (beyond that the attribute is set on every launch)
+    static const void *done[kDone];
     static int used = 0;
     for (int i = 0; i < used; i++)
         if (done[i] == kernel) return GT_OK;
     int rc = hip_check(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes),
                        "hipFuncSetAttribute");
     if (rc) return rc;
-    if (used < 64) done[used++] = kernel;
+    if (used < kDone) done[used++] = kernel;
     return GT_OK;
 }
 
-// LDS of a persistent launch: the level columns, the staged tables (if any),
-// the tally cache (up to kTallyCacheMax entries per lane), then the tail
-// buffer (with tail compaction), as large as the workgroup's share of the
-// compute unit's LDS allows without lowering the number of resident
-// workgroups.
 // Dynamic LDS of a persistent launch: level columns, staged tables, then --
 // within the workgroup's share of the compute unit's LDS that keeps the
 // resident workgroups -- the regroup buffer (one word per lane), the tally

@@ -423,12 +423,14 @@ def test_mesh_tally_full_size():
     assert np.array_equal(m.mesh.cpu().numpy(), o.mesh_fxd)
 
 
-@pytest.mark.parametrize("opts", [dict(tail_compaction=True), dict(staging=False), dict(block_size=640)],
-                         ids=["tail", "global-tables", "block640"])
+@pytest.mark.parametrize("opts", [dict(tail_compaction=True), dict(staging=False), dict(block_size=640),
+                                  dict(tally_cache=False)],
+                         ids=["tail", "global-tables", "block640", "no-cache"])
 def test_mesh_tally_with_other_options(opts):
-    """The mesh build with tail compaction (the lane's mesh accumulator stays
-    with the lane while histories move), with the tables in global memory,
-    and in the five-wave build."""
+    """The mesh build with tail compaction (the lane's mesh accumulator and
+    its cache of recent bins stay with the lane while histories move), with
+    the tables in global memory, in the five-wave build, and without the
+    lane's LDS cache (the register accumulator alone)."""
     import torch
     fg, G, O = geoms(2)
     kw = dict(seed=93, n_particles=15_000, geometry_id=2)
