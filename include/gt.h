@@ -453,7 +453,8 @@ typedef struct {
     uint32_t workgroups, block_size, lds_bytes, staging_kind;
     uint32_t tally_cache_entries, tail_capacity, regroup_every;
     uint32_t surface_set;   /* the build's surface set: 1 axis planes and z-cylinders only, 2 those and
-                               planes parallel to the z axis, 0 every surface type */
+                               planes parallel to the z axis, 0 every surface type (also every
+                               launch with the parallel-ray source) */
 } gt_launch_info;
 int gt_last_launch(gt_launch_info *out);
 

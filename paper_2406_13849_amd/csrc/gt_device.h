@@ -1666,6 +1666,9 @@ template <int PREC, bool RG = false, bool MESH = false, int TRK = TRK_ST, int SH
 __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const KOut &o, uint64_t *rep,
                                            uint32_t *cells, const Queue &queue, Counts &cnt, const TailCfg &tc,
                                            const TallyCache &tcache) {
+    // the parallel-ray source exists in the builds for every surface type only
+    // (the host sends ray launches there); the smaller builds drop its code
+    const bool ray = G::kSurf == SF_ALL && p.source == 1;
     Particle P;
     P.cell = cells;
     for (int L = 0; L < GT_MAX_LEVELS; L++) lvl(P, L) = 0;   // hints below read earlier levels
@@ -1922,7 +1925,7 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
 
         // ---- draw: a birth-position attempt, or a direction attempt and its optical depth
         if (mode == M_POS || mode == M_DIR) {
-            if (mode == M_POS && p.source == 1) {
+            if (mode == M_POS && ray) {
                 const uint64_t n1 = p.ray_n1;
                 const uint64_t n2 = (p.n + n1 - 1) / n1;
                 const uint64_t pid = p.first + local;
@@ -2028,7 +2031,7 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
             }
             if (c < 0) {
                 if (birth) {
-                    if (sL == 0 && p.source != 1) { cnt.rejected++; mode = M_POS; }
+                    if (sL == 0 && !ray) { cnt.rejected++; mode = M_POS; }
                     else end = GT_END_LOST;
                 } else {
                     end = (sforce != kNone && sL == 0) ? GT_END_ESCAPE : GT_END_LOST;
@@ -2042,7 +2045,7 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
                     P.depth = sL + 1;
                     if (birth) {
                         birth = false;
-                        mode = p.source == 1 ? M_TRACK : M_DIR;
+                        mode = ray ? M_TRACK : M_DIR;
                     } else {
                         if (segs >= p.max_segs) end = GT_END_SEGCAP;
                         mode = M_TRACK;
@@ -2058,7 +2061,7 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
             else if constexpr (TRK == TRK_RTK) nearest_surface_rtk<SHAPE>(g, P, nr);
             else nearest_surface_sp(g, P, nr);
             const double sig = g.sigma[nr.leaf_fill];
-            const double sc = (p.source == 1) ? dinf() : P.tau / sig;
+            const double sc = ray ? dinf() : P.tau / sig;
             const uint32_t inst = nr.inst;
             const bool boundary = nr.t < sc;
             if (!boundary && sc == dinf()) {
@@ -2067,7 +2070,7 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
                 double l;
                 if (boundary) {
                     l = nr.t;
-                    if (p.source != 1) P.tau = P.tau - sig * nr.t;
+                    if (!ray) P.tau = P.tau - sig * nr.t;
                 } else {
                     l = sc;
                 }

@@ -81,8 +81,8 @@ int launch_kinds_s(const gt_geometry *g, const LaunchRec *lr, int kind, uint64_t
 // The build for the geometry's surface set.
 template <int PREC, int TRK, int SHAPE>
 int launch_kinds_t(const gt_geometry *g, const LaunchRec *lr, int kind, uint64_t n, unsigned block, bool tail,
-                   bool cache, hipStream_t st) {
-    switch (g->surf_set) {
+                   bool cache, bool ray, hipStream_t st) {
+    switch (ray ? SF_ALL : (int)g->surf_set) {   // the ray source only in the general build
     case SF_AXCZ: return launch_kinds_s<PREC, TRK, SHAPE, SF_AXCZ>(g, lr, kind, n, block, tail, cache, st);
     case SF_VERT: return launch_kinds_s<PREC, TRK, SHAPE, SF_VERT>(g, lr, kind, n, block, tail, cache, st);
     default: return launch_kinds_s<PREC, TRK, SHAPE, SF_ALL>(g, lr, kind, n, block, tail, cache, st);
@@ -92,19 +92,19 @@ int launch_kinds_t(const gt_geometry *g, const LaunchRec *lr, int kind, uint64_t
 }  // namespace
 
 int launch_kinds(const gt_geometry *g, const LaunchRec *lr, int prec, int trk, uint64_t n, unsigned block, bool tail,
-                 bool cache, bool staging, hipStream_t st) {
+                 bool cache, bool staging, bool ray, hipStream_t st) {
     if (trk == TRK_RTK) prec = GT_PREC_FP64;
     const int kind = staging ? (int)g->stage_arr[prec].kind : SK_NONE;
     if (trk == TRK_SP)
-        return prec == GT_PREC_MIXED ? launch_kinds_t<GT_PREC_MIXED, TRK_SP, 0>(g, lr, kind, n, block, tail, cache, st)
-                                     : launch_kinds_t<GT_PREC_FP64, TRK_SP, 0>(g, lr, kind, n, block, tail, cache, st);
+        return prec == GT_PREC_MIXED ? launch_kinds_t<GT_PREC_MIXED, TRK_SP, 0>(g, lr, kind, n, block, tail, cache, ray, st)
+                                     : launch_kinds_t<GT_PREC_FP64, TRK_SP, 0>(g, lr, kind, n, block, tail, cache, ray, st);
     // the fixed-depth tracker takes every decision by index or by the one
     // root cell's test in double precision: no precision mode applies
     switch (g->rtk_shape) {
-    case 1: return launch_kinds_t<GT_PREC_FP64, TRK_RTK, 1>(g, lr, kind, n, block, tail, cache, st);
-    case 3: return launch_kinds_t<GT_PREC_FP64, TRK_RTK, 3>(g, lr, kind, n, block, tail, cache, st);
-    case 5: return launch_kinds_t<GT_PREC_FP64, TRK_RTK, 5>(g, lr, kind, n, block, tail, cache, st);
-    case 7: return launch_kinds_t<GT_PREC_FP64, TRK_RTK, 7>(g, lr, kind, n, block, tail, cache, st);
+    case 1: return launch_kinds_t<GT_PREC_FP64, TRK_RTK, 1>(g, lr, kind, n, block, tail, cache, ray, st);
+    case 3: return launch_kinds_t<GT_PREC_FP64, TRK_RTK, 3>(g, lr, kind, n, block, tail, cache, ray, st);
+    case 5: return launch_kinds_t<GT_PREC_FP64, TRK_RTK, 5>(g, lr, kind, n, block, tail, cache, ray, st);
+    case 7: return launch_kinds_t<GT_PREC_FP64, TRK_RTK, 7>(g, lr, kind, n, block, tail, cache, ray, st);
     default: return set_error("gt_track: the geometry is not of the fixed-depth reactor shape"), GT_EINVAL;
     }
 }

@@ -56,6 +56,6 @@ inline void mark(hipEvent_t e, hipStream_t st) {
 // The persistent tracker of a per-kind method (GT_FLAG_TRACKER_SP or
 // GT_FLAG_TRACKER_RTK) for a geometry whose launch record is at lr.
 int launch_kinds(const gt_geometry *g, const LaunchRec *lr, int prec, int trk, uint64_t n, unsigned block,
-                 bool tail, bool cache, bool staging, hipStream_t st);
+                 bool tail, bool cache, bool staging, bool ray, hipStream_t st);
 
 }  // namespace gt

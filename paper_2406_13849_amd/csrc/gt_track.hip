@@ -422,10 +422,11 @@ void note_launch(const LdsPlan &lp, int blocks, unsigned block, int kind, int su
 
 namespace {
 
-// The build for the geometry's surface set.
+// The build for the geometry's surface set (the general build for the
+// parallel-ray source, whose code the smaller builds leave out).
 int launch_persistent(const gt_geometry *g, const LaunchRec *lr, int prec, int w, int kind, uint64_t n, unsigned block,
-                      bool tail, bool cache, uint32_t regroup, bool mesh, hipStream_t st) {
-    switch (g->surf_set) {
+                      bool tail, bool cache, uint32_t regroup, bool mesh, bool ray, hipStream_t st) {
+    switch (ray ? SF_ALL : (int)g->surf_set) {
     case SF_AXCZ: return launch_persistent_axcz(g, lr, prec, w, kind, n, block, tail, cache, regroup, mesh, st);
     case SF_VERT: return launch_persistent_vert(g, lr, prec, w, kind, n, block, tail, cache, regroup, mesh, st);
     default: return launch_persistent_all(g, lr, prec, w, kind, n, block, tail, cache, regroup, mesh, st);
@@ -602,9 +603,10 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
             int rc;
             if (p->flags & (GT_FLAG_TRACKER_SP | GT_FLAG_TRACKER_RTK)) {
                 rc = launch_kinds(g, lrec, PREC, (p->flags & GT_FLAG_TRACKER_SP) ? TRK_SP : TRK_RTK, kp.n, block, tail,
-                                  cache, !(p->flags & GT_FLAG_NO_STAGING), st);
+                                  cache, !(p->flags & GT_FLAG_NO_STAGING), p->source == 1, st);
             } else {
-                rc = launch_persistent(g, lrec, PREC, block == 640 ? 5 : 4, kind, kp.n, block, tail, cache, rg, ms, st);
+                rc = launch_persistent(g, lrec, PREC, block == 640 ? 5 : 4, kind, kp.n, block, tail, cache, rg, ms,
+                                       p->source == 1, st);
             }
             if (rc) return rc;
         }

@@ -102,7 +102,7 @@ extern "C" int cpu_track(const gt_geometry *g, const gt_track_params *p, const g
     KOut ko;
     fill_kparams(p, g, kp, ko, o);
     g_cache_k = (p->flags & GT_FLAG_NO_TALLY_CACHE) ? 0 : kTallyCacheMax;
-    g_surf = surf_of(g);
+    g_surf = p->source == 1 ? SF_ALL : surf_of(g);   // the ray source: the general build only
     std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
@@ -131,7 +131,7 @@ extern "C" int cpu_track_kinds(const gt_geometry *g, const gt_track_params *p, c
     KOut ko;
     fill_kparams(p, g, kp, ko, o);
     g_cache_k = (p->flags & GT_FLAG_NO_TALLY_CACHE) ? 0 : kTallyCacheMax;
-    g_surf = surf_of(g);
+    g_surf = p->source == 1 ? SF_ALL : surf_of(g);   // the ray source: the general build only
     std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
@@ -182,7 +182,7 @@ extern "C" int cpu_track_mesh(const gt_geometry *g, const gt_track_params *p, co
     if (m->workspace_bytes < gt_mesh_workspace_bytes(md.nb)) return set_error("cpu_track_mesh: workspace"), GT_EINVAL;
     std::memset(md.ws, 0, (size_t)kReplicas * 4 * 8 * md.nb);
     g_cache_k = kTallyCacheMax;
-    g_surf = surf_of(g);
+    g_surf = p->source == 1 ? SF_ALL : surf_of(g);   // the ray source: the general build only
     std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;

@@ -143,6 +143,27 @@ def test_cpu_build_matches_oracle(host, what, k):
     host.L.gt_geometry_destroy(h)
 
 
+@pytest.mark.parametrize("what,k", [("cfg", 1), ("cfg", 2), ("cfg", 4)])
+def test_cpu_ray_source_matches_oracle(host, what, k):
+    """The parallel-ray source (no collisions) through the lane's state
+    machine, which runs it in the build for every surface type: the oracle's
+    histories and tallies, both precisions."""
+    fg, kw = make(what, k)
+    h, ni = host.geometry(fg)
+    n1 = 600
+    n, rk, cap = 3 * n1, 20, 48
+    kw = dict(seed=0, geometry_id=kw["geometry_id"], source=1, ray_n1=n1, max_collisions=1)
+    o = oracle.track(oracle.OracleGeometry(fg), oracle.TrackParams(n_particles=n, record_first_k=rk, record_cap=cap,
+                                                                    **kw), n_threads=4)
+    for prec in (gt.PREC_FP64, gt.PREC_MIXED):
+        out = Outs(ni, n, rk, cap)
+        prm = gt._params(0, n, geometry_id=kw["geometry_id"], precision=prec, record_first_k=rk, record_cap=cap,
+                         source=1, ray_n1=n1, max_collisions=1)
+        host.check(host.L.cpu_track(h, C.byref(prm), C.byref(out.struct()), host.staging(h, prec)))
+        same(out.a, o, rk)
+    host.L.gt_geometry_destroy(h)
+
+
 @pytest.mark.parametrize("what,k", [("cfg", 1), ("cfg", 2), ("cfg", 4), ("fn", "sphere"), ("fn", "nested_box"),
                                      ("batch", 41)],
                          ids=["cfg1", "cfg2", "cfg4", "sphere", "nested_box", "batch41"])

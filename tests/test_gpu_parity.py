@@ -203,6 +203,7 @@ def test_ray_mode_parity(cfg, n1, n2):
     kw = dict(seed=0, n_particles=n1 * n2, source=1, ray_n1=n1, max_collisions=1)
     for prec in (gt.PREC_FP64, gt.PREC_MIXED):
         g = gpu_track(G, precision=prec, **kw)
+        assert gt.last_launch()["surface_set"] == 0   # the ray source runs in the general build
         o = oracle.track(O, oracle.TrackParams(**kw), n_threads=NT)
         assert_parity(g, o, where="rays cfg %s" % cfg)
         assert g["counters"]["escaped"] == n1 * n2
