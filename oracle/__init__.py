@@ -123,6 +123,7 @@ def lib():
         L.or_mc_log_batch.argtypes = [vp, u64, vp]
         L.or_fx_quantise.argtypes = [vp, u64, vp]
         L.or_count_work.argtypes = [vp, C.POINTER(_Params), vp]
+        L.or_mesh_segments.argtypes = [C.POINTER(_Mesh), u64, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -341,6 +342,27 @@ def count_work(geom: OracleGeometry, p: TrackParams):
     prm = p.c()
     lib().or_count_work(geom.h, C.byref(prm), _p(out))
     return int(out[0]), int(out[1])
+
+
+def mesh_segments(mesh, p0, u, l) -> np.ndarray:
+    """The superimposed mesh tally (fixed point, [bins, 2] u64) of the given
+    segments, each cut and binned as a tracking segment is; mesh = (lo[3],
+    hi[3], n[3])."""
+    lo, hi, nm = mesh
+    p0 = np.ascontiguousarray(p0, np.float64).reshape(-1, 3)
+    u = np.ascontiguousarray(u, np.float64).reshape(-1, 3)
+    l = np.ascontiguousarray(l, np.float64).ravel()
+    assert p0.shape == u.shape and p0.shape[0] == l.shape[0]
+    nb = int(nm[0]) * int(nm[1]) * int(nm[2])
+    mfx = np.zeros((nb, 2), np.uint64)
+    m = _Mesh(mesh_fx=_p(mfx))
+    m.lo[:] = [float(v) for v in lo]
+    m.hi[:] = [float(v) for v in hi]
+    m.n[:] = [int(v) for v in nm]
+    rc = lib().or_mesh_segments(C.byref(m), l.shape[0], _p(p0), _p(u), _p(l))
+    if rc != 0:
+        raise RuntimeError("or_mesh_segments failed (%d)" % rc)
+    return mfx
 
 
 def fx_quantise(lengths) -> np.ndarray:

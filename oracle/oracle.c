@@ -1111,3 +1111,30 @@ void or_fx_quantise(const double *l, uint64_t n, uint64_t *lohi) {
         lohi[2 * i + 1] = (uint64_t)(v >> 64);
     }
 }
+
+/* Test entry: the superimposed mesh tally of n_seg given segments, segment
+ * i running from p0[3i..3i+2] along the unit direction u[3i..3i+2] for the
+ * length l[i], each added as a tracking segment is (mesh_segment above).
+ * Outputs as or_track's mesh outputs; -1 for an invalid mesh. */
+int or_mesh_segments(const or_mesh *m, uint64_t n_seg, const double *p0, const double *u, const double *l) {
+    for (int a = 0; a < 3; a++)
+        if (m->n[a] < 1 || !(m->hi[a] > m->lo[a]) || !isfinite(m->lo[a]) || !isfinite(m->hi[a])) return -1;
+    uint64_t nb = mesh_bins(m);
+    tally_acc acc;
+    memset(&acc, 0, sizeof acc);
+    acc.mesh = m;
+    acc.msum = calloc(nb, sizeof(double));
+    acc.mcomp = calloc(nb, sizeof(double));
+    acc.mfx = calloc(nb, sizeof(u128));
+    acc.cuts = malloc(sizeof(double) * ((size_t)m->n[0] + m->n[1] + m->n[2] + 5));
+    int rc = 0;
+    if (!acc.msum || !acc.mcomp || !acc.mfx || !acc.cuts) rc = -2;
+    for (uint64_t i = 0; !rc && i < n_seg; i++) mesh_segment(&acc, p0 + 3 * i, u + 3 * i, l[i]);
+    for (uint64_t b = 0; !rc && b < nb; b++) {
+        if (m->mesh) m->mesh[b] = acc.msum[b] + acc.mcomp[b];
+        if (m->mesh_fx) { m->mesh_fx[2 * b] = (uint64_t)acc.mfx[b]; m->mesh_fx[2 * b + 1] = (uint64_t)(acc.mfx[b] >> 64); }
+        if (m->mesh_fxd) m->mesh_fxd[b] = fx_to_double(acc.mfx[b]);
+    }
+    free(acc.msum); free(acc.mcomp); free(acc.mfx); free(acc.cuts);
+    return rc;
+}

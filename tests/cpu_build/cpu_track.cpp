@@ -159,6 +159,31 @@ extern "C" void cpu_mesh_floor(const double *d, uint64_t n, double w, double *ou
     for (uint64_t i = 0; i < n; i++) out[i] = mesh_floor(d[i], w, iw);
 }
 
+// The kernel's mesh walk over n_seg given segments (p0, u and l as in
+// tracking, 3 doubles a point or direction), through one lane's register
+// accumulator into one replica of the limb counters, folded into mesh_fx
+// ([bins, 2] u64); for a test against the oracle's mesh tally.
+extern "C" int cpu_mesh_segments(const double *lo, const double *hi, const uint32_t *n, uint64_t n_seg,
+                                 const double *p0, const double *u, const double *l, uint64_t *mesh_fx) {
+    MeshDesc md;
+    for (int a = 0; a < 3; a++) {
+        if (n[a] < 1) return GT_EINVAL;
+        md.lo[a] = lo[a];
+        md.w[a] = (hi[a] - lo[a]) / (double)n[a];
+        md.iw[a] = 1.0 / md.w[a];
+        md.n[a] = n[a];
+    }
+    md.nb = (uint64_t)n[0] * n[1] * n[2];
+    std::vector<uint64_t> ws((size_t)kReplicas * 4 * md.nb, 0);
+    md.ws = ws.data();
+    TallyAcc acc = {kNone, 0, 0};
+    for (uint64_t i = 0; i < n_seg; i++) mesh_segment(md, md.ws, acc, p0 + 3 * i, u + 3 * i, l[i]);
+    tally_flush(md.ws, acc);
+    std::vector<double> sums(md.nb);
+    fold_all(md.ws, mesh_fx, sums.data(), md.nb, false);
+    return GT_OK;
+}
+
 // gt_track_mesh on the CPU: cpu_track with the mesh tally (the kernel's
 // mesh walk), host pointers throughout; the workspace holds the replicas.
 extern "C" int cpu_track_mesh(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o,

@@ -358,6 +358,63 @@ def test_cpu_mesh_tally_matches_oracle(host, geom, cover, bins):
     host.L.gt_geometry_destroy(h)
 
 
+def _mesh_segment_cases(rng, lo, hi, n, count):
+    """Segments whose ends fall exactly on a mesh plane's cut, one ulp to
+    either side of it, or anywhere; directions with zero, tiny and subnormal
+    components as well as random ones."""
+    lo, hi, n = np.asarray(lo, float), np.asarray(hi, float), np.asarray(n)
+    w = (hi - lo) / n
+    p0 = rng.uniform(lo - 0.2 * w, hi + 0.2 * w, size=(count, 3))
+    u = rng.normal(size=(count, 3))
+    kinds = rng.integers(0, 6, size=count)
+    u[kinds == 1, rng.integers(0, 3)] = 0.0                      # one axis not moving
+    u[kinds == 2, 2] = 1e-300                                   # a component far below the rest
+    u[kinds == 3, 1] = 4e-320                                   # a subnormal component
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    l = rng.uniform(0.0, 3.0, size=count) * w.max()
+    # end the segment on the cut of a plane it crosses (as the walk computes
+    # it), or one ulp short of or past that cut
+    a = rng.integers(0, 3, size=count)
+    ua = u[np.arange(count), a]
+    pa = p0[np.arange(count), a]
+    k = np.floor((pa - lo[a]) / w[a]) + np.where(ua > 0, 1 + rng.integers(0, 3, size=count),
+                                                    -rng.integers(0, 3, size=count))
+    with np.errstate(over="ignore"):
+        t = ((lo[a] + k * w[a]) - pa) / np.where(ua == 0.0, 1.0, ua)
+    on = (kinds >= 4) & (ua != 0.0) & (t > 0)
+    nudge = rng.integers(-1, 2, size=count)
+    tt = np.where(nudge < 0, np.nextafter(t, -np.inf), np.where(nudge > 0, np.nextafter(t, np.inf), t))
+    l = np.where(on, tt, l)
+    l[rng.integers(0, count, size=count // 50)] = 0.0            # empty segments
+    return p0, u, l
+
+
+def test_mesh_walk_matches_oracle_on_plane_edges(host):
+    """The kernel's mesh walk (the first cut ahead per axis found without
+    dividing, divisions skipped for cuts certainly past the segment's end)
+    gives the oracle's mesh tally bit for bit on segments that end exactly on
+    a plane's cut or one ulp from it, that run along an axis, or whose
+    direction has a tiny or subnormal component, on meshes of the
+    benchmark's and of odd widths."""
+    rng = np.random.default_rng(23)
+    fn = host.L.cpu_mesh_segments
+    fn.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p,
+                   C.c_void_p]
+    fn.restype = C.c_int
+    for lo, hi, n in (((-140.0, -140.0, -183.0), (140.0, 140.0, 183.0), (119, 119, 30)),
+                      ((-10.625, -10.625, -1.0), (10.625, 10.625, 1.0), (17, 17, 3)),
+                      ((-3.3, 0.0, -2.5), (7.1, 1.0, 9.25), (13, 3, 7))):
+        p0, u, l = _mesh_segment_cases(rng, lo, hi, n, 40000)
+        want = oracle.mesh_segments((lo, hi, n), p0, u, l)
+        got = np.zeros_like(want)
+        lo_a, hi_a = np.array(lo, float), np.array(hi, float)
+        n_a = np.array(n, np.uint32)
+        assert fn(lo_a.ctypes.data, hi_a.ctypes.data, n_a.ctypes.data, l.size, p0.ctypes.data, u.ctypes.data,
+                  l.ctypes.data, got.ctypes.data) == 0
+        assert np.array_equal(got, want), (lo, hi, n)
+        assert (want[:, 1] > 0).sum() > 100
+
+
 def test_mesh_floor_matches_division(host):
     """The mesh walk's bin index from the reciprocal (with the division as
     the fallback near integers) equals floor(d / w) for coordinates on, next
