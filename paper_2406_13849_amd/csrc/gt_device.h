@@ -1131,36 +1131,58 @@ __device__ __forceinline__ bool mesh_cut_ahead(const MeshDesc &m, int a, int k, 
     return u > 0.0 ? d > 0.0 : d < 0.0;
 }
 
+// An axis's cut that lies ahead, at plane offset d = (lo + k w) - p0 of u's
+// sign, is certainly at t >= l when |d| > reach, reach = (l |u|)(1 + 2^-50):
+// the two roundings leave reach above the exact l |u|, so |d / u| > l
+// exactly and the rounded quotient is not below l.  Without that certainty
+// (reach of no use when l |u| is tiny or zero) the quotient is formed.
+__device__ __forceinline__ double mesh_reach(double l, double u) {
+    const double lu = l * fabs(u);
+    return lu > 0x1p-1000 ? lu * (1.0 + 0x1p-50) : -1.0;
+}
+
+__device__ __forceinline__ bool mesh_cut_beyond(const MeshDesc &m, int a, int k, double p0, double reach) {
+    return reach >= 0.0 && fabs((m.lo[a] + (double)k * m.w[a]) - p0) > reach;
+}
+
 __device__ __forceinline__ void mesh_segment(const MeshDesc &m, uint64_t *rep, TallyAcc &acc, const double p0[3],
                                              const double u[3], double l) {
     int k[3], step[3];
-    double tn[3];
+    double tn[3], reach[3];
+    uint32_t pend = 0;   // axes whose first cut ahead may lie within the segment
     for (int a = 0; a < 3; a++) {
         tn[a] = dinf();
         step[a] = 0;
         k[a] = 0;
+        reach[a] = mesh_reach(l, u[a]);
         if (u[a] == 0.0) continue;
         const int n = (int)m.n[a];
         // first guess of the plane index by the reciprocal, then exact steps
         const double f = floor((p0[a] - m.lo[a]) * m.iw[a]);
+        int kk;
         if (u[a] > 0.0) {
             // first k with a cut ahead (t > 0): near floor(...) + 1, then exact
-            int kk = f < -1.0 ? 0 : (f > (double)n ? n + 1 : (int)f + 1);
+            kk = f < -1.0 ? 0 : (f > (double)n ? n + 1 : (int)f + 1);
             while (kk > 0 && mesh_cut_ahead(m, a, kk - 1, p0[a], u[a])) kk--;
             while (kk <= n && !mesh_cut_ahead(m, a, kk, p0[a], u[a])) kk++;
-            k[a] = kk;
             step[a] = 1;
-            if (kk <= n) tn[a] = mesh_cut(m, a, kk, p0[a], u[a]);
         } else {
             // last k with a cut ahead, walking down
-            int kk = f < -1.0 ? -1 : (f > (double)n ? n : (int)f);
+            kk = f < -1.0 ? -1 : (f > (double)n ? n : (int)f);
             while (kk < n && mesh_cut_ahead(m, a, kk + 1, p0[a], u[a])) kk++;
             while (kk >= 0 && !mesh_cut_ahead(m, a, kk, p0[a], u[a])) kk--;
-            k[a] = kk;
             step[a] = -1;
-            if (kk >= 0) tn[a] = mesh_cut(m, a, kk, p0[a], u[a]);
         }
-        if (!(tn[a] < l)) tn[a] = dinf();
+        k[a] = kk;
+        if (kk >= 0 && kk <= n && !mesh_cut_beyond(m, a, kk, p0[a], reach[a])) pend |= 1u << a;
+    }
+    // one division site for the axes that need their cut (most segments
+    // cross no plane, and a lane's divergent branches would each be issued)
+    while (pend) {
+        const int a = __builtin_ctz(pend);
+        pend &= pend - 1;
+        const double t = mesh_cut(m, a, k[a], p0[a], u[a]);
+        tn[a] = t < l ? t : dinf();
     }
     double t0 = 0.0;
     for (;;) {
@@ -1204,7 +1226,7 @@ __device__ __forceinline__ void mesh_segment(const MeshDesc &m, uint64_t *rep, T
         t0 = t1;
         const int kk = k[a1] + step[a1];
         k[a1] = kk;
-        const bool ok = kk >= 0 && kk <= (int)m.n[a1];
+        const bool ok = kk >= 0 && kk <= (int)m.n[a1] && !mesh_cut_beyond(m, a1, kk, p0[a1], reach[a1]);
         const double t = ok ? mesh_cut(m, a1, kk, p0[a1], u[a1]) : dinf();
         tn[a1] = t < l ? t : dinf();
     }
