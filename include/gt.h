@@ -288,7 +288,8 @@ int gt_track(const gt_geometry *g, const gt_track_params *p, const gt_track_out 
  *   o->workspace must be NULL (GT_EINVAL otherwise).
  *   The geometry's device must be the current device (GT_EINVAL).
  *   GT_ECAPACITY when gt_track_workspace_bytes(g) exceeds
- *   GT_NOALLOC_SCRATCH_BYTES (about 131,000 leaf instances).
+ *   GT_NOALLOC_SCRATCH_BYTES (every geometry of up to 131,000 leaf
+ *   instances fits).
  * Every call on one GPU shares that GPU's array and leaves its contents
  * behind; each call clears what it needs.  Calls that may overlap on one GPU
  * (different streams, or threads without ordering) race on the array and

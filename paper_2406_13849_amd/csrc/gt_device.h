@@ -1064,13 +1064,14 @@ __device__ __forceinline__ void nearest_surface_sp(const G &g, const Particle &P
 // the kernel a contribution is split into four 32-bit limbs, each added to
 // its own 64-bit counter with an atomic whose result is not used, so no
 // carry has to travel back to the lane; the counters are exact for up to
-// 2^32 contributions per instance and launch.  Each XCD adds into its own
-// replica of the counters (on device memory of the default type the L2
-// forwards these atomics to the memory side; the replicas keep the XCDs off
-// each other's addresses); the finalize kernel folds replicas and limbs into
-// the 128-bit total.
-__device__ __forceinline__ uint32_t xcc_id() {
-    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kReplicas - 1);   // HW_REG_XCC_ID[3:0]
+// 2^32 contributions per instance and launch.  Each XCD adds into the
+// replica of the counters its id selects (on device memory of the default
+// type the L2 forwards these atomics to the memory side; the replicas halve
+// the XCDs sharing an address); the finalize kernel folds replicas and limbs
+// into the 128-bit total.
+// (nrep: the replica count of the array, a power of two)
+__device__ __forceinline__ uint32_t replica_id(uint32_t nrep) {
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (nrep - 1);   // HW_REG_XCC_ID[3:0]
 }
 
 struct TallyAcc {
@@ -1078,7 +1079,7 @@ struct TallyAcc {
     uint64_t lo, hi;   // 128-bit register accumulator for consecutive segments in one instance
 };
 
-// Agent scope: workgroups on every compute unit of the XCD add into one
+// Agent scope: workgroups on the compute units of several XCDs add into one
 // replica (on gfx950 this is the same global_atomic_add_x2, with no cache
 // bits, as at workgroup scope).
 __device__ __forceinline__ void add_limb(uint64_t *p, uint64_t v) {
@@ -2098,7 +2099,7 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
                 }
                 if constexpr (MESH) {
                     const double p0[3] = {P.x, P.y, P.z}, uu[3] = {P.u, P.v, P.w};
-                    mesh_segment(o.mesh, o.mesh.ws + (size_t)xcc_id() * 4 * o.mesh.nb, macc, p0, uu, l);
+                    mesh_segment(o.mesh, o.mesh.ws + (size_t)replica_id(tally_replicas(o.mesh.nb)) * 4 * o.mesh.nb, macc, p0, uu, l);
                 }
                 const double m0 = l * P.u, m1 = l * P.v, m2 = l * P.w;
                 P.x = P.x + m0;
@@ -2145,7 +2146,7 @@ __device__ __forceinline__ void track_pool(const G &g, const KParams &p, const K
     }
     // the lane's partial tally sums
     tally_flush(rep, acc);
-    if constexpr (MESH) tally_flush(o.mesh.ws + (size_t)xcc_id() * 4 * o.mesh.nb, macc);
+    if constexpr (MESH) tally_flush(o.mesh.ws + (size_t)replica_id(tally_replicas(o.mesh.nb)) * 4 * o.mesh.nb, macc);
     for (uint32_t e = 0; e < tcache.k; e++) {
         TallyAcc c;
         c.inst = tcache.tag[e * tcache.stride];
@@ -2486,7 +2487,8 @@ __device__ __forceinline__ bool ev_cross(const G &g, const KParams &p, const KOu
 __device__ __forceinline__ void fold_tally(const uint64_t *ws, uint64_t *tfx, double *tally, uint64_t n, uint64_t i,
                                            bool accumulate) {
     uint64_t lo = accumulate ? tfx[2 * i] : 0, hi = accumulate ? tfx[2 * i + 1] : 0;
-    for (int r = 0; r < kReplicas; r++) {
+    const uint32_t nrep = tally_replicas(n);
+    for (uint32_t r = 0; r < nrep; r++) {
         const uint64_t *L = ws + ((size_t)r * n + i) * 4;
         for (int k = 0; k < 4; k++) {
             // add L[k] * 2^(32 k) to (hi, lo) modulo 2^128

@@ -1092,7 +1092,7 @@ extern "C" uint64_t gt_event_bank_bytes(uint64_t n_particles) {
 
 extern "C" uint64_t gt_mesh_workspace_bytes(uint64_t bins) {
     if (bins == 0 || bins > (1ull << 31)) return 0;
-    return (uint64_t)kReplicas * 4 * 8 * bins;   // per-XCD replicas x limbs x bytes, as the cell tally's workspace
+    return (uint64_t)tally_replicas(bins) * 4 * 8 * bins;   // replicas x limbs x bytes, as the cell tally's workspace
 }
 
 extern "C" int gt_track_mesh(const gt_geometry *g, const gt_track_params *p, const gt_track_out *o,
@@ -1195,7 +1195,7 @@ extern "C" int gt_batch_create(const gt_batch_item *items, uint32_t n_items, con
             fill_kparams(&p, g, b.p, b.o, &it.out);
             kind[i] = (it.params.flags & GT_FLAG_NO_STAGING) ? 0 : (uint8_t)b.plan.kind;
             lds[kind[i]] = std::max(lds[kind[i]], kind[i] ? b.plan.total : 0u);
-            fills.push_back({b.o.tally_ws, (uint64_t)kReplicas * 4 * g->n_inst, 0, 8, 0});
+            fills.push_back({b.o.tally_ws, (uint64_t)tally_replicas(g->n_inst) * 4 * g->n_inst, 0, 8, 0});
             fills.push_back({it.out.counters, 8, 0, 8, 0});
             if (b.p.rec_k) fills.push_back({it.out.rec, (uint64_t)b.p.rec_k * b.p.rec_cap, (uint64_t)(uint32_t)-1, 4, 0});
             fin[i] = {b.o.tally_ws, it.out.tally_fx, it.out.tally, g->n_inst,

@@ -170,7 +170,7 @@ struct KParams {
 };
 
 // A superimposed mesh: bins n[0] x n[1] x n[2] over lo + [0, n] w, with its
-// per-XCD replicas of per-bin limb counters (ws == nullptr: no mesh).
+// replicas of per-bin limb counters (ws == nullptr: no mesh).
 struct MeshDesc {
     double lo[3], w[3];
     double iw[3];       // 1 / w: only for the first guess of a plane index, corrected exactly
@@ -181,7 +181,7 @@ struct MeshDesc {
 
 struct KOut {
     MeshDesc mesh;
-    uint64_t *tally_ws;     // per-XCD replicas of per-instance limb counters
+    uint64_t *tally_ws;     // replicas of per-instance limb counters
     uint32_t *seg_count;
     uint64_t *seq_hash;
     uint8_t *end_code;
@@ -204,14 +204,27 @@ struct LaunchRec {
     KOut o;
 };
 
+// Replicas of an array of n sets of four 64-bit limb counters (one set per
+// leaf instance, or per mesh bin): one per XCD while the eight copies take at
+// most kReplicaBudget bytes, else two.  Replica r is used by the waves of the
+// XCDs whose id is r mod the replica count.  Few, hot entries need the XCDs
+// kept apart (two replicas slow the small geometries of a batch); many entries
+// are touched rarely, and the memory-side atomics run faster on the smaller
+// array (the three-level core's 2.86 M instances take 183 MB of counters with
+// two replicas instead of 732 MB with eight).
+constexpr int kReplicas = 8;   // the most: one per XCD
+constexpr uint64_t kReplicaBudget = 64ull << 20;
+__host__ __device__ inline uint32_t tally_replicas(uint64_t n) {
+    return (uint64_t)kReplicas * 32 * n <= kReplicaBudget ? (uint32_t)kReplicas : 2u;
+}
+
 // Tally workspace of one tracking call (the geometry's own, or the caller's
-// through gt_track_out.workspace): the launch record, then kReplicas
-// replicas x n_inst x four 64-bit limb counters.  Replica r is used by the
-// waves of XCD r mod kReplicas.
-constexpr int kReplicas = 8;
+// through gt_track_out.workspace): the launch record, then the replicas of
+// n_inst x four 64-bit limb counters.
 constexpr uint64_t kWsTallyAt = (sizeof(LaunchRec) + 255) & ~(uint64_t)255;
 inline uint64_t track_ws_bytes(uint64_t n_inst) {
-    return kWsTallyAt + (uint64_t)kReplicas * 4 * 8 * (n_inst ? n_inst : 1);
+    const uint64_t n = n_inst ? n_inst : 1;
+    return kWsTallyAt + (uint64_t)tally_replicas(n) * 4 * 8 * n;
 }
 
 // One item of a batched launch (device copy).

@@ -31,7 +31,7 @@ k_track_persistent(const GeomDesc *__restrict__ gd, const LaunchRec *__restrict_
     const auto g = make_view<KIND, SF>(gd->dev, gd->stage[PREC], lds_tables);
     const KParams &p = lr->p;
     const KOut &o = lr->o;
-    uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
+    uint64_t *rep = o.tally_ws + (size_t)replica_id(tally_replicas(g.n_inst)) * 4 * g.n_inst;
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     const GlobalQueue q = {(unsigned long long *)&o.counters[7], p.n};
     const TailCfg tc = {(uint64_t *)(lds_dyn + tail_at), ctl, tail_cap, tail_round, tail_words, regroup};

@@ -36,7 +36,7 @@ template <int PREC>
 __global__ void __launch_bounds__(kBlock) k_track(Dev g0, KParams p, KOut o) {
     __shared__ uint32_t cells[GT_MAX_LEVELS * kBlock];
     const DevGlobal g = global_view(g0);
-    uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
+    uint64_t *rep = o.tally_ws + (size_t)replica_id(tally_replicas(g.n_inst)) * 4 * g.n_inst;
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     const uint64_t local = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (local < p.n) run_history<PREC>(g, p, o, rep, local, cells + threadIdx.x, cnt);
@@ -49,7 +49,7 @@ template <int PREC>
 __global__ void __launch_bounds__(kBlock) k_ev_birth(Dev g0, KParams p, KOut o, EvBank b) {
     __shared__ uint32_t cells[GT_MAX_LEVELS * kBlock];
     const DevGlobal g = global_view(g0);
-    uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
+    uint64_t *rep = o.tally_ws + (size_t)replica_id(tally_replicas(g.n_inst)) * 4 * g.n_inst;
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < p.n) ev_birth<PREC>(g, p, o, b, rep, i, cells + threadIdx.x, cnt);
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(kBlock) k_ev_distance(Dev g0, uint64_t n, EvBa
 
 template <int PREC>
 __global__ void __launch_bounds__(kBlock) k_ev_move(Dev g0, KParams p, KOut o, EvBank b) {
-    uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g0.n_inst;
+    uint64_t *rep = o.tally_ws + (size_t)replica_id(tally_replicas(g0.n_inst)) * 4 * g0.n_inst;
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < p.n) ev_move(p, o, b, rep, i, cnt);
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(kBlock) k_ev_cross(Dev g0, KParams p, KOut o, 
                                                       unsigned long long *alive) {
     __shared__ uint32_t cells[GT_MAX_LEVELS * kBlock];
     const DevGlobal g = global_view(g0);
-    uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
+    uint64_t *rep = o.tally_ws + (size_t)replica_id(tally_replicas(g.n_inst)) * 4 * g.n_inst;
     Counts cnt = {0, 0, 0, 0, 0, 0, 0};
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = i < p.n && ev_cross<PREC>(g, p, o, b, rep, i, cells + threadIdx.x, cnt);
@@ -145,7 +145,7 @@ k_track_batch(const BatchItem *__restrict__ items, const BatchChunk *__restrict_
         const auto g = make_view<KIND>(it.dev, it.plan, lds_tables);
         const KParams &p = it.p;
         const KOut &o = it.o;
-        uint64_t *rep = o.tally_ws + (size_t)xcc_id() * 4 * g.n_inst;
+        uint64_t *rep = o.tally_ws + (size_t)replica_id(tally_replicas(g.n_inst)) * 4 * g.n_inst;
         Counts cnt = {0, 0, 0, 0, 0, 0, 0};
         const ChunkQueue q = by_item ? ChunkQueue{&claimed[item], 0, p.n}
                                      : ChunkQueue{&s_pool, chunks[c].first, chunks[c].first + chunks[c].count};
@@ -560,7 +560,7 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
     KParams kp;
     KOut ko;
     fill_kparams(p, g, kp, ko, o);
-    const uint64_t nws = (uint64_t)kReplicas * 4 * g->n_inst;
+    const uint64_t nws = (uint64_t)tally_replicas(g->n_inst) * 4 * g->n_inst;
     hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(nws)), dim3(256), 0, st, ko.tally_ws, nws, (uint64_t)0);
     if (mesh) {
         MeshDesc &m = ko.mesh;
@@ -572,7 +572,7 @@ int launch_track_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
         }
         m.nb = (uint64_t)mesh->n[0] * mesh->n[1] * mesh->n[2];
         m.ws = (uint64_t *)mesh->workspace;
-        const uint64_t mws = (uint64_t)kReplicas * 4 * m.nb;
+        const uint64_t mws = (uint64_t)tally_replicas(m.nb) * 4 * m.nb;
         hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(mws)), dim3(256), 0, st, m.ws, mws, (uint64_t)0);
     }
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, o->counters, (uint64_t)8, (uint64_t)0);
@@ -634,7 +634,7 @@ int launch_event_t(const gt_geometry *g, const gt_track_params *p, const gt_trac
     fill_kparams(p, g, kp, ko, o);
     EvBank b;
     ev_layout(kp.n, (unsigned char *)bank, &b);
-    const uint64_t nws = (uint64_t)kReplicas * 4 * g->n_inst;
+    const uint64_t nws = (uint64_t)tally_replicas(g->n_inst) * 4 * g->n_inst;
     hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(nws)), dim3(256), 0, st, ko.tally_ws, nws, (uint64_t)0);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, o->counters, (uint64_t)8, (uint64_t)0);
     if (kp.rec_k) {

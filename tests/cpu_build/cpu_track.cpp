@@ -103,7 +103,7 @@ extern "C" int cpu_track(const gt_geometry *g, const gt_track_params *p, const g
     fill_kparams(p, g, kp, ko, o);
     g_cache_k = (p->flags & GT_FLAG_NO_TALLY_CACHE) ? 0 : kTallyCacheMax;
     g_surf = p->source == 1 ? SF_ALL : surf_of(g);   // the ray source: the general build only
-    std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
+    std::memset(ko.tally_ws, 0, (size_t)tally_replicas(g->n_inst) * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
     unsigned long long ctr = 0;
@@ -132,7 +132,7 @@ extern "C" int cpu_track_kinds(const gt_geometry *g, const gt_track_params *p, c
     fill_kparams(p, g, kp, ko, o);
     g_cache_k = (p->flags & GT_FLAG_NO_TALLY_CACHE) ? 0 : kTallyCacheMax;
     g_surf = p->source == 1 ? SF_ALL : surf_of(g);   // the ray source: the general build only
-    std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
+    std::memset(ko.tally_ws, 0, (size_t)tally_replicas(g->n_inst) * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
     unsigned long long ctr = 0;
@@ -174,7 +174,7 @@ extern "C" int cpu_mesh_segments(const double *lo, const double *hi, const uint3
         md.n[a] = n[a];
     }
     md.nb = (uint64_t)n[0] * n[1] * n[2];
-    std::vector<uint64_t> ws((size_t)kReplicas * 4 * md.nb, 0);
+    std::vector<uint64_t> ws((size_t)tally_replicas(md.nb) * 4 * md.nb, 0);
     md.ws = ws.data();
     TallyAcc acc = {kNone, 0, 0};
     for (uint64_t i = 0; i < n_seg; i++) mesh_segment(md, md.ws, acc, p0 + 3 * i, u + 3 * i, l[i]);
@@ -205,10 +205,10 @@ extern "C" int cpu_track_mesh(const gt_geometry *g, const gt_track_params *p, co
     md.nb = (uint64_t)m->n[0] * m->n[1] * m->n[2];
     md.ws = (uint64_t *)m->workspace;
     if (m->workspace_bytes < gt_mesh_workspace_bytes(md.nb)) return set_error("cpu_track_mesh: workspace"), GT_EINVAL;
-    std::memset(md.ws, 0, (size_t)kReplicas * 4 * 8 * md.nb);
+    std::memset(md.ws, 0, (size_t)tally_replicas(md.nb) * 4 * 8 * md.nb);
     g_cache_k = kTallyCacheMax;
     g_surf = p->source == 1 ? SF_ALL : surf_of(g);   // the ray source: the general build only
-    std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
+    std::memset(ko.tally_ws, 0, (size_t)tally_replicas(g->n_inst) * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
     unsigned long long ctr = 0;
@@ -233,7 +233,7 @@ static int cpu_event_t(const gt_geometry *g, const gt_track_params *p, const gt_
     unsigned char *base = (unsigned char *)(((uintptr_t)mem.data() + 255) & ~(uintptr_t)255);
     EvBank b;
     ev_layout(kp.n, base, &b);
-    std::memset(ko.tally_ws, 0, (size_t)kReplicas * 4 * 8 * g->n_inst);
+    std::memset(ko.tally_ws, 0, (size_t)tally_replicas(g->n_inst) * 4 * 8 * g->n_inst);
     std::memset(o->counters, 0, 8 * sizeof(uint64_t));
     if (o->rec) for (uint64_t i = 0; i < (uint64_t)kp.rec_k * kp.rec_cap; i++) o->rec[i] = -1;
     blockDim.x = 1;

@@ -534,7 +534,7 @@ def test_workspace_arguments():
     import torch
     fg, G, O = geoms(1)
     need = gt.track_workspace_bytes(G)
-    assert need >= 256 + 32 * 8 * G.n_instances
+    assert need >= 256 + 32 * 8 * G.n_instances   # the launch record, then 8 replicas (a small geometry) x 4 limbs x 8 B
     out = gt.alloc_outputs(G, 100)
     out.workspace = torch.empty(need - 8, dtype=torch.uint8, device="cuda")
     with pytest.raises(gt.GtError) as e:
