@@ -1066,10 +1066,10 @@ __device__ __forceinline__ void nearest_surface_sp(const G &g, const Particle &P
 // carry has to travel back to the lane; the counters are exact for up to
 // 2^32 contributions per instance and launch.  Each XCD adds into the
 // replica of the counters its id selects (on device memory of the default
-// type the L2 forwards these atomics to the memory side; the replicas halve
-// the XCDs sharing an address); the finalize kernel folds replicas and limbs
-// into the 128-bit total.
-// (nrep: the replica count of the array, a power of two)
+// type the L2 forwards these atomics to the memory side; replicas keep the
+// XCDs off each other's addresses where few entries are hot); the finalize
+// kernel folds replicas and limbs into the 128-bit total.
+// (nrep: the replica count of the array, 1 or 8)
 __device__ __forceinline__ uint32_t replica_id(uint32_t nrep) {
     return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (nrep - 1);   // HW_REG_XCC_ID[3:0]
 }
@@ -1079,8 +1079,8 @@ struct TallyAcc {
     uint64_t lo, hi;   // 128-bit register accumulator for consecutive segments in one instance
 };
 
-// Agent scope: workgroups on the compute units of several XCDs add into one
-// replica (on gfx950 this is the same global_atomic_add_x2, with no cache
+// Agent scope: workgroups on the compute units of one XCD, or of all, add
+// into one replica (on gfx950 this is the same global_atomic_add_x2, with no cache
 // bits, as at workgroup scope).
 __device__ __forceinline__ void add_limb(uint64_t *p, uint64_t v) {
     if (v) __hip_atomic_fetch_add((GT_AS(1) unsigned long long *)p, (unsigned long long)v,

@@ -206,16 +206,16 @@ struct LaunchRec {
 
 // Replicas of an array of n sets of four 64-bit limb counters (one set per
 // leaf instance, or per mesh bin): one per XCD while the eight copies take at
-// most kReplicaBudget bytes, else two.  Replica r is used by the waves of the
-// XCDs whose id is r mod the replica count.  Few, hot entries need the XCDs
-// kept apart (two replicas slow the small geometries of a batch); many entries
-// are touched rarely, and the memory-side atomics run faster on the smaller
-// array (the three-level core's 2.86 M instances take 183 MB of counters with
-// two replicas instead of 732 MB with eight).
+// most kReplicaBudget bytes, else a single one.  Replica r is used by the
+// waves of the XCDs whose id is r mod the replica count.  Few, hot entries
+// need the XCDs kept apart (fewer replicas slow the small geometries of a
+// batch); many entries are touched rarely, and the memory-side atomics run
+// faster on the smaller array (the three-level core's 2.86 M instances take
+// 92 MB of counters in one replica instead of 732 MB in eight).
 constexpr int kReplicas = 8;   // the most: one per XCD
 constexpr uint64_t kReplicaBudget = 64ull << 20;
 __host__ __device__ inline uint32_t tally_replicas(uint64_t n) {
-    return (uint64_t)kReplicas * 32 * n <= kReplicaBudget ? (uint32_t)kReplicas : 2u;
+    return (uint64_t)kReplicas * 32 * n <= kReplicaBudget ? (uint32_t)kReplicas : 1u;
 }
 
 // Tally workspace of one tracking call (the geometry's own, or the caller's

@@ -121,7 +121,7 @@ def test_binding_struct_layouts_match_the_header(tmp_path):
 def test_mesh_workspace_bytes_follows_the_replica_rule():
     """A mesh workspace holds four 64-bit limb counters per bin in each
     replica: one replica per XCD (eight) while those take at most 64 MB,
-    two above that; 0 for no bins or more than 2^31."""
+    a single one above that; 0 for no bins or more than 2^31."""
     L = gt.lib()
     L.gt_mesh_workspace_bytes.argtypes = [C.c_uint64]
     L.gt_mesh_workspace_bytes.restype = C.c_uint64
@@ -130,4 +130,4 @@ def test_mesh_workspace_bytes_follows_the_replica_rule():
     for bins in (1, 1000, 262_144):
         assert L.gt_mesh_workspace_bytes(bins) == 8 * 32 * bins
     for bins in (262_145, 119 * 119 * 30, 1 << 31):
-        assert L.gt_mesh_workspace_bytes(bins) == 2 * 32 * bins
+        assert L.gt_mesh_workspace_bytes(bins) == 32 * bins
