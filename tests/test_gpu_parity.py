@@ -530,6 +530,19 @@ def test_concurrent_calls_on_two_streams():
         assert_parity(_outs(out), o, where=str(kw))
 
 
+def test_workspace_bytes_follow_the_replica_rule():
+    """The tally workspace is the launch record plus four 64-bit limb
+    counters per leaf instance in each replica: one replica per XCD (eight)
+    for the 3x3 pins, whose eight copies fit 64 MB, a single one for the
+    three-level core's 2.86 M instances."""
+    fg1, G1, O1 = geoms(1)
+    fg3, G3, O3 = geoms(3)
+    assert G3.n_instances > 262_144 >= G1.n_instances
+    rec1 = gt.track_workspace_bytes(G1) - 8 * 32 * G1.n_instances
+    rec3 = gt.track_workspace_bytes(G3) - 1 * 32 * G3.n_instances
+    assert rec1 == rec3 and 256 <= rec1 <= 4096 and rec1 % 256 == 0
+
+
 def test_workspace_arguments():
     import torch
     fg, G, O = geoms(1)
