@@ -99,7 +99,8 @@ def parse():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of tracking, run a plain device copy of this many bytes --steps times "
                          "(reference kernel for scaling HBM counters)")
-    ap.add_argument("--only", choices=["mixed", "fp64", "plain_fp64", "event", "batch", "sp", "rtk"], default=None,
+    ap.add_argument("--only", choices=["mixed", "fp64", "plain_fp64", "event", "batch", "sp", "rtk", "mesh"],
+                    default=None,
                     help="time one leg of the headline workload only (profiling; prints that leg's summary)")
     ap.add_argument("--no-trackers", action="store_true",
                     help="skip the SP and RTK tracker legs of the headline workload")
@@ -370,6 +371,7 @@ def workload_legs(gt, synth, cfg, n, args, hev, aux):
                                         regroup_every=args.regroup_leg)
             log("cfg%d mixed, regroup every %d: %.3f ms/step" % (cfg, args.regroup_leg,
                                                                  mean(legs["regroup"]["ms"])))
+    if aux and args.only in (None, "mesh"):
         mb = tuple(args.mesh)
         out = gt.alloc_outputs(G, n, min(args.record_k, n), args.record_cap)
         mesh_out = gt.alloc_mesh(mb[0] * mb[1] * mb[2])
